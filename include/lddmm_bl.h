@@ -1,0 +1,181 @@
+/*
+ * lddmm_bl.h - C ABI of the MI355X (gfx950) band-limited PDE-LDDMM library.
+ *
+ * The library computes the hot path of band-limited Gauss-Newton-Krylov
+ * PDE-constrained LDDMM with semi-Lagrangian Runge-Kutta (SL-RK2) integration
+ * (M. Hernandez, arXiv 2006.06823):
+ *   - the truncated Fourier maps pi (grid -> band) and iota (band -> grid) of
+ *     Section 2.2, done as separable dense contractions on the matrix cores;
+ *   - the SL-RK2 solves of Table 1 (Section 3.3) for the state, adjoint,
+ *     incremental state and incremental adjoint of two variants:
+ *       LDDMM_BL_IMAGE_TRANSPORT   original BL PDE-LDDMM (Section 2.3.1),
+ *       LDDMM_BL_DEFORMATION_STATE BL PDE-LDDMM based on the deformation state
+ *                                  equation (Section 2.3.3);
+ *   - the gradient, the Gauss-Newton Hessian-vector product and the
+ *     Gauss-Newton-Krylov driver with PCG preconditioned by L~^{-1}
+ *     (Section 2.2, eqs. BLNewton and BLKKT).
+ *
+ * Conventions (the paper leaves them open; these are the readings used):
+ *   - The image domain is the periodic unit torus [0,1)^d with nodes
+ *     x = i / N_j.  The L^2 inner product is the grid mean.
+ *   - Grid scalars are [N1][N2](..[N3]) in C order (last axis contiguous);
+ *     vector fields are component-major [d][N1][N2](..[N3]).
+ *   - Band-limited (BL) arrays are [ncomp][K1][K2](..[K3]) coefficients of the
+ *     real orthonormal tensor basis: per axis, slot 0 = 1, slots 2k-1 / 2k =
+ *     sqrt(2) cos(2 pi k x) / sqrt(2) sin(2 pi k x) for k = 1 .. K_j/2 - 1, and
+ *     slot K_j - 1 an always-zero pad.  K_j must be even, K_j - 1 <= N_j, and
+ *     N_j >= 3 (K_j/2 - 1) + 1 for alias-free truncated products.
+ *   - The energy is 1/2 <L~ v~, v~> + (1/sigma^2) mean((m(1) - I1)^2) with
+ *     L~ = (1 + alpha (2 pi)^2 |k|^2)^s (eq. BLEnergy); the velocity is
+ *     stationary; time integrals use the trapezoid rule over Nt steps.
+ *   - Element type of every device buffer: double for LDDMM_BL_FP64, float
+ *     otherwise.  Reductions (objective, dot products, norms, Jacobian) are
+ *     accumulated in double on the device.
+ *
+ * Ownership and ordering: the caller owns every buffer it passes; device
+ * buffers are borrowed for the duration of the call.  The context owns its
+ * workspaces (trajectories, departure points, scratch).  Every call runs in
+ * order on the stream given at creation; calls that return host scalars
+ * synchronise that stream.  No exception or abort crosses the ABI.
+ *
+ * Errors: negative status = error (the result is not valid), positive =
+ * warning with a valid result.  lddmm_bl_last_error() gives the text of the
+ * last error of a context.
+ */
+#ifndef LDDMM_BL_H
+#define LDDMM_BL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lddmm_bl_ctx lddmm_bl_ctx;
+
+typedef enum {
+  LDDMM_BL_OK = 0,
+  LDDMM_BL_E_ARG = -1,        /* invalid argument or size */
+  LDDMM_BL_E_OOM = -2,        /* device allocation failed */
+  LDDMM_BL_E_HIP = -3,        /* HIP runtime error */
+  LDDMM_BL_E_NONFINITE = -4,  /* NaN/Inf in an objective, norm or dot product */
+  LDDMM_BL_E_STATE = -5,      /* call order: e.g. adjoint before a state solve at this velocity */
+  LDDMM_BL_W_MAXITER = 1,     /* iteration cap reached before the gradient tolerance */
+  LDDMM_BL_W_LINESEARCH = 2,  /* Armijo backtracking failed; velocity left unchanged */
+  LDDMM_BL_W_NEGCURV = 3      /* PCG met non-positive curvature and was truncated */
+} lddmm_bl_status;
+
+typedef enum {
+  LDDMM_BL_IMAGE_TRANSPORT = 1,   /* original BL PDE-LDDMM, Section 2.3.1 */
+  LDDMM_BL_DEFORMATION_STATE = 3  /* deformation state equation, Section 2.3.3 */
+} lddmm_bl_variant;
+
+typedef enum {
+  LDDMM_BL_FP64 = 0,   /* every buffer and kernel in double */
+  LDDMM_BL_FP32 = 1,   /* float buffers, float contractions, double reductions */
+  LDDMM_BL_BF16_DFT = 2 /* float buffers; truncated-DFT contractions on bf16 matrix cores
+                          with float accumulation (hi/lo split operands) */
+} lddmm_bl_precision;
+
+typedef struct {
+  int32_t dim;            /* 2 or 3 */
+  int32_t n[3];           /* grid N1..Nd (unused entries ignored) */
+  int32_t k[3];           /* band K1..Kd, even */
+  int32_t nt;             /* SL-RK2 time steps, dt = 1/nt */
+  int32_t variant;        /* lddmm_bl_variant */
+  double alpha;           /* L = (Id - alpha Laplacian)^s, Section 2.1 */
+  int32_t s;
+  double sigma2;          /* data weight 1/sigma^2, eq. BLEnergy */
+  int32_t precision;      /* lddmm_bl_precision */
+} lddmm_bl_params;
+
+typedef struct {
+  int32_t max_gn;         /* Gauss-Newton iteration cap (Section 4.3: 10) */
+  int32_t max_pcg;        /* PCG iteration cap per GN iteration (Section 4.3: 5) */
+  double grad_rtol;       /* stop when ||g||_inf <= grad_rtol * reference */
+  double grad_ref_inf;    /* reference ||g||_inf; 0 => ||g||_inf at the initial velocity */
+  int32_t fixed_iters;    /* 1 => run every cap to the end (no tolerance exits) */
+} lddmm_bl_gn_opts;
+
+typedef struct {
+  int32_t gn_iters, pcg_iters_total, backtracks, hess_matvecs;
+  double E0, E;           /* energy at the start and at the end */
+  double mse_rel;         /* ||m(1) - I1||^2 / ||I0 - I1||^2 (Section 5.1.1) */
+  double grad_inf_rel;    /* final ||g||_inf / reference */
+  double seconds;         /* wall time of the call */
+} lddmm_bl_gn_report;
+
+/* Create a context for one registration problem.  hip_stream: a hipStream_t
+ * (NULL = the default stream).  Allocates every workspace the variant needs. */
+lddmm_bl_status lddmm_bl_create(const lddmm_bl_params* params, void* hip_stream, lddmm_bl_ctx** out);
+lddmm_bl_status lddmm_bl_destroy(lddmm_bl_ctx* ctx);
+const char* lddmm_bl_last_error(const lddmm_bl_ctx* ctx);
+
+/* Source I0 and target I1 (device, grid layout), copied into the context. */
+lddmm_bl_status lddmm_bl_set_images(lddmm_bl_ctx* ctx, const void* I0, const void* I1);
+
+/* State solve at velocity v_bl (device, BL [d][K..]): characteristics
+ * (Section 3.1), then the state equation (Table 1 row 1 or 3).  Writes the
+ * deformed source m(1) (device grid) when m1_or_null is not NULL and
+ * {E, regulariser, data term} to E_reg_data (host, may be NULL). */
+lddmm_bl_status lddmm_bl_state_solve(lddmm_bl_ctx* ctx, const void* v_bl, void* m1_or_null,
+                                     double* E_reg_data);
+
+/* Adjoint solve (Table 1 row 2 or 4) at the velocity of the last state solve
+ * and the gradient L~v~ + int (adjoint term) dt (Section 2.3.1 / 2.3.3).
+ * grad_bl: device BL [d][K..]; grad_inf (host, may be NULL) = max over grid
+ * nodes and components of |iota(g)|.  E_STATE without a prior state solve. */
+lddmm_bl_status lddmm_bl_adjoint_solve(lddmm_bl_ctx* ctx, void* grad_bl, double* grad_inf);
+
+/* Gauss-Newton Hessian-vector product at the velocity of the last state solve:
+ * incremental state (Table 1 row 5 or 7), final coupling, incremental adjoint
+ * (row 6 or 8) and the time integral of the Hessian term.  dv_bl, hdv_bl:
+ * device BL [d][K..] (may not alias).  E_STATE without a prior state solve. */
+lddmm_bl_status lddmm_bl_hess_matvec(lddmm_bl_ctx* ctx, const void* dv_bl, void* hdv_bl);
+
+/* Gauss-Newton-Krylov registration (eqs. BLNewton, BLKKT) starting from
+ * v_bl_inout (device BL [d][K..]), which receives the result.  PCG uses
+ * L~^{-1}; when precond_Z_or_null is a device array of r BL directions
+ * [r][d][K..], the two-level preconditioner L~^{-1} + Z (Z^T H Z)^{-1} Z^T is
+ * used instead.  report (host) may be NULL. */
+lddmm_bl_status lddmm_bl_gn_solve(lddmm_bl_ctx* ctx, const lddmm_bl_gn_opts* opts, void* v_bl_inout,
+                                  const void* precond_Z_or_null, int32_t r, lddmm_bl_gn_report* report);
+
+/* Jacobian determinant det(I - D iota(u~(1))) of phi(1) = id - iota(u~(1))
+ * (Sections 2.3.2-2.3.3) at the velocity of the last state solve, evaluated
+ * in double.  detmap_or_null: device double grid; minmax: host double[2]. */
+lddmm_bl_status lddmm_bl_jacobian(lddmm_bl_ctx* ctx, void* detmap_or_null, double* minmax);
+
+/* Truncated Fourier maps of Section 2.2 on ncomp stacked fields:
+ * project: device grid [ncomp][N..] -> device BL [ncomp][K..] (pi);
+ * include: device BL [ncomp][K..] -> device grid [ncomp][N..] (iota). */
+lddmm_bl_status lddmm_bl_project(lddmm_bl_ctx* ctx, const void* grid, void* bl, int32_t ncomp);
+lddmm_bl_status lddmm_bl_include(lddmm_bl_ctx* ctx, const void* bl, void* grid, int32_t ncomp);
+
+/* Internal fields of the last solves, for inspection and parity checks.
+ * Copies field `which` at time node `index` into dst (device) and returns the
+ * number of elements through count (host).  With dst = NULL only the count is
+ * returned.  Grid fields use the grid layout, BL fields the BL layout. */
+typedef enum {
+  LDDMM_BL_FIELD_VELOCITY = 0,     /* iota(v~) [d][N..] */
+  LDDMM_BL_FIELD_DEP_BACKWARD = 1, /* departure displacement X - x for forward-in-time equations, grid units [d][N..] */
+  LDDMM_BL_FIELD_DEP_FORWARD = 2,  /* departure displacement for backward-in-time equations [d][N..] */
+  LDDMM_BL_FIELD_DIV_V = 3,        /* iota(div~ v~) [N..] */
+  LDDMM_BL_FIELD_STATE = 4,        /* image-transport: m at node index [N..]; deformation-state: u~ at node index [d][K..] */
+  LDDMM_BL_FIELD_M1 = 5,           /* m(1) [N..] */
+  LDDMM_BL_FIELD_ADJOINT0 = 6,     /* image-transport: lambda(0) [N..]; deformation-state: rho~(0) [d][K..] */
+  LDDMM_BL_FIELD_INC_STATE = 7,    /* dm~ [K..] or du~ [d][K..] at node index, from the last matvec */
+  LDDMM_BL_FIELD_INC_ADJOINT = 8   /* dlambda~ [K..] or drho~ [d][K..] at node index, from the last matvec */
+} lddmm_bl_field;
+lddmm_bl_status lddmm_bl_get_field(lddmm_bl_ctx* ctx, int32_t which, int32_t index, void* dst, int64_t* count);
+
+/* Device-side FP64 reductions used by PCG, exposed for checks:
+ * dot = sum a_i b_i over n elements of the context's element type. */
+lddmm_bl_status lddmm_bl_dot(lddmm_bl_ctx* ctx, const void* a, const void* b, int64_t n, double* dot);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LDDMM_BL_H */

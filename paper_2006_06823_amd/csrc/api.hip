@@ -1,0 +1,162 @@
+// extern "C" entry points of the library (declared in include/lddmm_bl.h).
+// Every call catches its own exceptions and turns them into status codes; the
+// text of the last error is kept per context.
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "solver.h"
+
+struct lddmm_bl_ctx {
+  std::unique_ptr<lddmm::SolverBase> solver;
+  std::string err;
+};
+
+namespace {
+
+template <typename F>
+lddmm_bl_status guarded(lddmm_bl_ctx* ctx, F&& f) {
+  if (!ctx || !ctx->solver) return LDDMM_BL_E_ARG;
+  try {
+    return static_cast<lddmm_bl_status>(f());
+  } catch (const lddmm::ArgError& e) {
+    ctx->err = e.what();
+    return LDDMM_BL_E_ARG;
+  } catch (const lddmm::StateError& e) {
+    ctx->err = e.what();
+    return LDDMM_BL_E_STATE;
+  } catch (const lddmm::NonFiniteError& e) {
+    ctx->err = e.what();
+    return LDDMM_BL_E_NONFINITE;
+  } catch (const lddmm::HipError& e) {
+    ctx->err = e.what();
+    return LDDMM_BL_E_HIP;
+  } catch (const std::bad_alloc&) {
+    ctx->err = "device allocation failed";
+    return LDDMM_BL_E_OOM;
+  } catch (const std::exception& e) {
+    ctx->err = e.what();
+    return LDDMM_BL_E_HIP;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+lddmm_bl_status lddmm_bl_create(const lddmm_bl_params* params, void* hip_stream, lddmm_bl_ctx** out) {
+  if (!params || !out) return LDDMM_BL_E_ARG;
+  *out = nullptr;
+  auto* ctx = new (std::nothrow) lddmm_bl_ctx();
+  if (!ctx) return LDDMM_BL_E_OOM;
+  try {
+    ctx->solver = lddmm::make_solver(*params, static_cast<hipStream_t>(hip_stream));
+  } catch (const lddmm::ArgError&) {
+    delete ctx;
+    return LDDMM_BL_E_ARG;
+  } catch (const std::bad_alloc&) {
+    delete ctx;
+    return LDDMM_BL_E_OOM;
+  } catch (...) {
+    delete ctx;
+    return LDDMM_BL_E_HIP;
+  }
+  *out = ctx;
+  return LDDMM_BL_OK;
+}
+
+lddmm_bl_status lddmm_bl_destroy(lddmm_bl_ctx* ctx) {
+  if (!ctx) return LDDMM_BL_E_ARG;
+  try {
+    delete ctx;
+  } catch (...) {
+    return LDDMM_BL_E_HIP;
+  }
+  return LDDMM_BL_OK;
+}
+
+const char* lddmm_bl_last_error(const lddmm_bl_ctx* ctx) {
+  if (!ctx) return "null context";
+  return ctx->err.c_str();
+}
+
+lddmm_bl_status lddmm_bl_set_images(lddmm_bl_ctx* ctx, const void* I0, const void* I1) {
+  return guarded(ctx, [&] {
+    if (!I0 || !I1) throw lddmm::ArgError("null image");
+    ctx->solver->set_images(I0, I1);
+    return 0;
+  });
+}
+
+lddmm_bl_status lddmm_bl_state_solve(lddmm_bl_ctx* ctx, const void* v_bl, void* m1_or_null, double* E) {
+  return guarded(ctx, [&] {
+    if (!v_bl) throw lddmm::ArgError("null velocity");
+    ctx->solver->state_solve(v_bl, m1_or_null, E);
+    return 0;
+  });
+}
+
+lddmm_bl_status lddmm_bl_adjoint_solve(lddmm_bl_ctx* ctx, void* grad_bl, double* grad_inf) {
+  return guarded(ctx, [&] {
+    ctx->solver->adjoint_solve(grad_bl, grad_inf);
+    return 0;
+  });
+}
+
+lddmm_bl_status lddmm_bl_hess_matvec(lddmm_bl_ctx* ctx, const void* dv_bl, void* hdv_bl) {
+  return guarded(ctx, [&] {
+    if (!dv_bl || !hdv_bl) throw lddmm::ArgError("null vector");
+    if (dv_bl == hdv_bl) throw lddmm::ArgError("dv and hdv may not alias");
+    ctx->solver->hess_matvec(dv_bl, hdv_bl);
+    return 0;
+  });
+}
+
+lddmm_bl_status lddmm_bl_gn_solve(lddmm_bl_ctx* ctx, const lddmm_bl_gn_opts* opts, void* v_bl_inout,
+                                  const void* precond_Z_or_null, int32_t r, lddmm_bl_gn_report* report) {
+  return guarded(ctx, [&] {
+    if (!opts || !v_bl_inout) throw lddmm::ArgError("null options or velocity");
+    return ctx->solver->gn_solve(*opts, v_bl_inout, precond_Z_or_null, r, report);
+  });
+}
+
+lddmm_bl_status lddmm_bl_jacobian(lddmm_bl_ctx* ctx, void* detmap_or_null, double* minmax) {
+  return guarded(ctx, [&] {
+    ctx->solver->jacobian(static_cast<double*>(detmap_or_null), minmax);
+    return 0;
+  });
+}
+
+lddmm_bl_status lddmm_bl_project(lddmm_bl_ctx* ctx, const void* grid, void* bl, int32_t ncomp) {
+  return guarded(ctx, [&] {
+    if (!grid || !bl) throw lddmm::ArgError("null buffer");
+    ctx->solver->project(grid, bl, ncomp);
+    return 0;
+  });
+}
+
+lddmm_bl_status lddmm_bl_include(lddmm_bl_ctx* ctx, const void* bl, void* grid, int32_t ncomp) {
+  return guarded(ctx, [&] {
+    if (!grid || !bl) throw lddmm::ArgError("null buffer");
+    ctx->solver->include(bl, grid, ncomp);
+    return 0;
+  });
+}
+
+lddmm_bl_status lddmm_bl_get_field(lddmm_bl_ctx* ctx, int32_t which, int32_t index, void* dst, int64_t* count) {
+  return guarded(ctx, [&] {
+    const int64_t c = ctx->solver->get_field(which, index, dst);
+    if (count) *count = c;
+    return 0;
+  });
+}
+
+lddmm_bl_status lddmm_bl_dot(lddmm_bl_ctx* ctx, const void* a, const void* b, int64_t n, double* dot) {
+  return guarded(ctx, [&] {
+    if (!a || !b || !dot || n < 0) throw lddmm::ArgError("bad dot arguments");
+    *dot = ctx->solver->dot(a, b, n);
+    return 0;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,205 @@
+// Separable truncated DFT contractions (iota / pi of Section 2.2) on gfx950.
+//
+// A 3D truncated transform is three one-axis contractions with small dense
+// per-axis basis matrices (<= 192 x 48).  Two kernel shapes cover all stages:
+//   left : out[b][m][c] = sum_l W[m][l] in[b][l][c]   (contract a non-last axis;
+//          rows l of the input are contiguous in c, so loads are coalesced)
+//   right: out[r][m]    = sum_l in[r][l] W[m][l]      (contract the last axis)
+// In float the products run on the matrix cores (v_mfma_f32_32x32x2f32: each
+// wave owns a 32 x 32 output block); in double the same tiling runs on the
+// vector FMA units.  Tiles of W and of the input are staged through LDS.
+#include "kernels.h"
+
+namespace lddmm {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+namespace {
+
+constexpr int LC = 32;  // contraction chunk staged in LDS
+
+// Row (within the wave's 32 x 32 block) held by accumulator register r of a lane,
+// for the 32x32 output layout of the matrix-core instruction.
+__device__ __forceinline__ int acc_row(int r, int lane) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
+
+template <typename T>
+struct Acc16 {
+  T v[16];
+};
+
+// One LC-deep chunk of a 32x32 block product: acc[i][j] += sum_k A[i][k] B[k][j],
+// A read as As[(arow0 + i) * lda + k], B as Bs[k * ldb + bcol0 + j].
+__device__ __forceinline__ void chunk_mma(f32x16& acc, const float* As, int lda, const float* Bs, int ldb,
+                                          int lane) {
+  const int i = lane & 31, kh = lane >> 5;
+#pragma unroll
+  for (int kk = 0; kk < LC; kk += 2) {
+    const float a = As[i * lda + kk + kh];
+    const float b = Bs[(kk + kh) * ldb + i];
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, acc, 0, 0, 0);
+  }
+}
+
+__device__ __forceinline__ void chunk_mma(Acc16<double>& acc, const double* As, int lda, const double* Bs,
+                                          int ldb, int lane) {
+  const int j = lane & 31;
+#pragma unroll 4
+  for (int kk = 0; kk < LC; ++kk) {
+    const double b = Bs[kk * ldb + j];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc.v[r] += As[acc_row(r, lane) * lda + kk] * b;
+  }
+}
+
+template <typename T>
+struct AccOf;
+template <>
+struct AccOf<float> {
+  using type = f32x16;
+  static __device__ __forceinline__ float get(const f32x16& a, int r) { return a[r]; }
+  static __device__ __forceinline__ void zero(f32x16& a) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) a[r] = 0.f;
+  }
+};
+template <>
+struct AccOf<double> {
+  using type = Acc16<double>;
+  static __device__ __forceinline__ double get(const Acc16<double>& a, int r) { return a.v[r]; }
+  static __device__ __forceinline__ void zero(Acc16<double>& a) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) a.v[r] = 0.0;
+  }
+};
+
+// out[b][m][c] = sum_l W[m][l] in[b][l][c]; block tile (32 WM) x (32 WC), one wave per 32x32 block.
+template <typename T, int WM, int WC>
+__global__ __launch_bounds__(64 * WM * WC) void dft_left_kernel(const T* __restrict__ in, T* __restrict__ out,
+                                                                FieldMats<T> mats, int bpf, int M, int L,
+                                                                int C, int64_t sIb, int64_t sOb) {
+  constexpr int TM = 32 * WM, TC = 32 * WC, NT = 64 * WM * WC;
+  constexpr int LDA = LC + 1;
+  __shared__ T Ws[TM * LDA];
+  __shared__ T Xs[LC * TC];
+  const int b = blockIdx.z;
+  const T* __restrict__ W = mats.w[b / bpf];
+  const int m0 = blockIdx.y * TM, c0 = blockIdx.x * TC;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WC, wc = wave % WC;
+  in += b * sIb;
+  out += b * sOb;
+  typename AccOf<T>::type acc;
+  AccOf<T>::zero(acc);
+  for (int l0 = 0; l0 < L; l0 += LC) {
+    for (int e = tid; e < TM * LC; e += NT) {
+      const int mm = e / LC, ll = e - mm * LC;
+      const int m = m0 + mm, l = l0 + ll;
+      Ws[mm * LDA + ll] = (m < M && l < L) ? W[(int64_t)m * L + l] : T(0);
+    }
+    for (int e = tid; e < LC * TC; e += NT) {
+      const int ll = e / TC, cc = e - ll * TC;
+      const int l = l0 + ll, c = c0 + cc;
+      Xs[ll * TC + cc] = (l < L && c < C) ? in[(int64_t)l * C + c] : T(0);
+    }
+    __syncthreads();
+    chunk_mma(acc, Ws + wm * 32 * LDA, LDA, Xs + wc * 32, TC, lane);
+    __syncthreads();
+  }
+  const int c = c0 + wc * 32 + (lane & 31);
+  if (c < C) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int m = m0 + wm * 32 + acc_row(r, lane);
+      if (m < M) out[(int64_t)m * C + c] = AccOf<T>::get(acc, r);
+    }
+  }
+}
+
+// out[f][r][m] = sum_l in[f][r][l] W_f[m][l]; block tile rows (32 WR) x outputs (32 WM).
+template <typename T, int WR, int WM>
+__global__ __launch_bounds__(64 * WR * WM) void dft_right_kernel(const T* __restrict__ in, T* __restrict__ out,
+                                                                 FieldMats<T> mats, int R, int L, int Mo) {
+  constexpr int TR = 32 * WR, TMo = 32 * WM, NT = 64 * WR * WM;
+  constexpr int LDA = LC + 1;
+  __shared__ T Xs[TR * LDA];
+  __shared__ T Ws[LC * TMo];
+  const int f = blockIdx.z;
+  const T* __restrict__ W = mats.w[f];
+  in += (int64_t)f * R * L;
+  out += (int64_t)f * R * Mo;
+  const int r0 = blockIdx.y * TR, m0 = blockIdx.x * TMo;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave / WM, wm = wave % WM;
+  typename AccOf<T>::type acc;
+  AccOf<T>::zero(acc);
+  for (int l0 = 0; l0 < L; l0 += LC) {
+    for (int e = tid; e < TR * LC; e += NT) {
+      const int rr = e / LC, ll = e - rr * LC;
+      const int r = r0 + rr, l = l0 + ll;
+      Xs[rr * LDA + ll] = (r < R && l < L) ? in[(int64_t)r * L + l] : T(0);
+    }
+    // W staged transposed, [l][m], so the B operand is read contiguously
+    for (int e = tid; e < TMo * LC; e += NT) {
+      const int mm = e / LC, ll = e - mm * LC;
+      const int m = m0 + mm, l = l0 + ll;
+      Ws[ll * TMo + mm] = (m < Mo && l < L) ? W[(int64_t)m * L + l] : T(0);
+    }
+    __syncthreads();
+    chunk_mma(acc, Xs + wr * 32 * LDA, LDA, Ws + wm * 32, TMo, lane);
+    __syncthreads();
+  }
+  const int m = m0 + wm * 32 + (lane & 31);
+  if (m < Mo) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int r = r0 + wr * 32 + acc_row(q, lane);
+      if (r < R) out[(int64_t)r * Mo + m] = AccOf<T>::get(acc, q);
+    }
+  }
+}
+
+}  // namespace
+
+template <typename T>
+void dft_left(const T* in, T* out, const FieldMats<T>& W, int nb, int bpf, int M, int L, int C, int64_t sIb,
+              int64_t sOb, hipStream_t s) {
+  if (nb <= 0 || M <= 0 || C <= 0) return;
+  if (nb > 65535) throw ArgError("dft_left: batch too large");
+  if (M > 64) {
+    dim3 g(ceil_div(C, 32), ceil_div(M, 128), nb);
+    dft_left_kernel<T, 4, 1><<<g, 256, 0, s>>>(in, out, W, bpf, M, L, C, sIb, sOb);
+  } else if (M > 32) {
+    dim3 g(ceil_div(C, 64), ceil_div(M, 64), nb);
+    dft_left_kernel<T, 2, 2><<<g, 256, 0, s>>>(in, out, W, bpf, M, L, C, sIb, sOb);
+  } else {
+    dim3 g(ceil_div(C, 128), ceil_div(M, 32), nb);
+    dft_left_kernel<T, 1, 4><<<g, 256, 0, s>>>(in, out, W, bpf, M, L, C, sIb, sOb);
+  }
+  LDDMM_LAUNCH_CHECK();
+}
+
+template <typename T>
+void dft_right(const T* in, T* out, const FieldMats<T>& W, int nf, int R, int L, int Mo, hipStream_t s) {
+  if (nf <= 0 || R <= 0 || Mo <= 0) return;
+  if (Mo > 64) {
+    dim3 g(ceil_div(Mo, 128), ceil_div(R, 32), nf);
+    dft_right_kernel<T, 1, 4><<<g, 256, 0, s>>>(in, out, W, R, L, Mo);
+  } else if (Mo > 32) {
+    dim3 g(ceil_div(Mo, 64), ceil_div(R, 64), nf);
+    dft_right_kernel<T, 2, 2><<<g, 256, 0, s>>>(in, out, W, R, L, Mo);
+  } else {
+    dim3 g(ceil_div(Mo, 32), ceil_div(R, 128), nf);
+    dft_right_kernel<T, 4, 1><<<g, 256, 0, s>>>(in, out, W, R, L, Mo);
+  }
+  LDDMM_LAUNCH_CHECK();
+}
+
+template void dft_left<float>(const float*, float*, const FieldMats<float>&, int, int, int, int, int, int64_t,
+                              int64_t, hipStream_t);
+template void dft_left<double>(const double*, double*, const FieldMats<double>&, int, int, int, int, int,
+                               int64_t, int64_t, hipStream_t);
+template void dft_right<float>(const float*, float*, const FieldMats<float>&, int, int, int, int, hipStream_t);
+template void dft_right<double>(const double*, double*, const FieldMats<double>&, int, int, int, int,
+                                hipStream_t);
+
+}  // namespace lddmm

@@ -1,0 +1,112 @@
+// Launchers of the gfx950 kernels (HIP device code lives in the .hip files).
+#pragma once
+
+#include "common.h"
+
+namespace lddmm {
+
+// ---- separable truncated DFT contractions (dft.hip) -------------------------
+// left:  out[b][m][c] = sum_l W_f[m][l] in[b][l][c],   f = b / bpf, b < nb
+// right: out[f][r][m] = sum_l in[f][r][l] W_f[m][l],   r < R, f < nf
+template <typename T>
+void dft_left(const T* in, T* out, const FieldMats<T>& W, int nb, int bpf, int M, int L, int C,
+              int64_t sIb, int64_t sOb, hipStream_t s);
+template <typename T>
+void dft_right(const T* in, T* out, const FieldMats<T>& W, int nf, int R, int L, int Mo, hipStream_t s);
+
+// bf16 hi/lo split variants (float in/out, bf16 matrix-core products, float accumulation)
+void dft_left_bf16(const float* in, float* out, const FieldMats<float>& W, int nb, int bpf, int M, int L,
+                   int C, int64_t sIb, int64_t sOb, hipStream_t s);
+void dft_right_bf16(const float* in, float* out, const FieldMats<float>& W, int nf, int R, int L, int Mo,
+                    hipStream_t s);
+
+// ---- band-limited coefficient kernels (grid.hip) ----------------------------
+// out = a x + b y (n elements; y may be null when b == 0)
+template <typename T>
+void bl_axpby(T* out, T a, const T* x, T b, const T* y, int64_t n, hipStream_t s);
+// out = x * sym (+ y), sym a per-coefficient symbol (double), repeated over ncomp components
+template <typename T>
+void bl_scale_sym(T* out, const T* x, const double* sym, int ncomp, int64_t Q, const T* y_or_null,
+                  hipStream_t s);
+// out[Q] = sum_j d_j v[j]  (spectral divergence in the real basis)
+template <typename T>
+void bl_div(T* out, const T* v, const Dims& d, hipStream_t s);
+
+// ---- grid kernels (grid.hip) ------------------------------------------------
+// departure displacements (grid units) of the characteristic scheme:
+// X = x + dir dt/2 (v + v o (x + dir dt v)), v given in unit-torus units
+template <typename T>
+void characteristics(T* disp, const T* v, const T* cv, const Dims& d, T dt, int dir, hipStream_t s);
+// out_f = P(c_f) o X, X = x + disp, for nf <= 3 coefficient fields
+template <typename T>
+void interp(T* out, const T* coef, int nf, const T* disp, const Dims& d, hipStream_t s);
+// periodic cubic B-spline prefilter of nf fields, in place
+template <typename T>
+void prefilter(T* f, int nf, const Dims& d, hipStream_t s);
+// variant-1 adjoint Heun step on the grid:
+//   a = c1 o X, b = c2 o X, out = a + dt/2 (b + (a + dt b) divv)
+template <typename T>
+void adjoint_grid_step(T* out, const T* c1, const T* c2, const T* disp, const T* divv, const Dims& d, T dt,
+                       hipStream_t s);
+// band-limited adjoint Heun step for nf components:
+//   out_f = cA_f o X + dt/2 divv (cB_f o X), cA = P(x + dt/2 f), cB = P(x + dt f)
+template <typename T>
+void bl_adjoint_step(T* out, const T* cA, const T* cB, int nf, const T* disp, const T* divv, const Dims& d,
+                     T dt, hipStream_t s);
+// variant-1 incremental state step: out0 = c o X, out1 = -G . dv
+template <typename T>
+void inc_state_v1(T* out, const T* c, const T* disp, const T* G, const T* dv, const Dims& d, hipStream_t s);
+// variant-3 incremental state step: out[0..2] = c_f o X, out[3..5] = dv - Du dv
+template <typename T>
+void inc_state_v3(T* out, const T* c, const T* disp, const T* Du, const T* dv, const Dims& d,
+                  hipStream_t s);
+// variant-3 state source at node n: out = dv - Du dv  (3 comps)
+template <typename T>
+void v3_source(T* out, const T* Du, const T* dv, const Dims& d, hipStream_t s);
+// variant-1 source at node n: out = -G . dv
+template <typename T>
+void v1_source(T* out, const T* G, const T* dv, const Dims& d, hipStream_t s);
+// products for the variant-1 backward sweeps: out = [e divv, e G0, e G1, e G2]
+template <typename T>
+void v1_products(T* out, const T* e, const T* divv, const T* G, const Dims& d, hipStream_t s);
+// products for the variant-3 backward sweeps: out = [e_i divv (3), (Du)^T e (3)]
+template <typename T>
+void v3_products(T* out, const T* e, const T* divv, const T* Du, const Dims& d, hipStream_t s);
+// variant-3 final warp: m1 = P(I0) o (x - u n), g1 = grad P(I0) o (.) in unit-torus units
+template <typename T>
+void final_warp(T* m1, T* g1, const T* cI0, const T* u, const Dims& d, hipStream_t s);
+// out = a * (x - y)
+template <typename T>
+void scaled_diff(T* out, T a, const T* x, const T* y, int64_t n, hipStream_t s);
+// out_i = a * r * g1_i  (3 comps), r = x - y
+template <typename T>
+void residual_times_grad(T* out, T a, const T* x, const T* y, const T* g1, const Dims& d, hipStream_t s);
+// out_i = a * (g1 . w) * g1_i
+template <typename T>
+void coupling_v3(T* out, T a, const T* g1, const T* w, const Dims& d, hipStream_t s);
+// out = x * y (elementwise, n)
+template <typename T>
+void mul(T* out, const T* x, const T* y, int64_t n, hipStream_t s);
+// det(I - Du) in double from 9 derivative fields (T)
+template <typename T>
+void jacobian_det(double* out, const T* Du, int dim, int64_t P, hipStream_t s);
+// copy with conversion for components (used for d = 2 staging): dst[c] = src[c] over n elems
+template <typename T>
+void zero(T* p, int64_t n, hipStream_t s);
+
+// ---- FP64 reductions (reduce.hip) -------------------------------------------
+// partial results go to `work` (device, >= reduce_work_size doubles); result to host
+int64_t reduce_work_size();
+template <typename T>
+double dot(const T* a, const T* b, int64_t n, double* work, double* host_pinned, hipStream_t s);
+template <typename T>
+double sqdiff(const T* a, const T* b, int64_t n, double* work, double* host_pinned, hipStream_t s);
+template <typename T>
+double maxabs(const T* a, int64_t n, double* work, double* host_pinned, hipStream_t s);
+// sum_i sym_i x_i y_i over ncomp components of length Q (sym double)
+template <typename T>
+double sym_dot(const T* x, const T* y, const double* sym, int ncomp, int64_t Q, double* work,
+               double* host_pinned, hipStream_t s);
+void minmax_f64(const double* a, int64_t n, double* work, double* host_pinned2, hipStream_t s);
+
+}  // namespace lddmm

@@ -1,0 +1,146 @@
+// FP64 reductions on the device: PCG inner products and norms, the data term
+// of the objective, the regulariser, the gradient infinity norm and the
+// Jacobian extrema.  Two passes with a fixed block count keep the summation
+// order deterministic: each block reduces a strided slice to one double (wave
+// shuffles, then LDS across the block's waves), a single block adds the partials.
+#include "kernels.h"
+
+namespace lddmm {
+
+namespace {
+
+constexpr int kRBlocks = 512;
+constexpr int kRThreads = 256;
+
+enum class Op { Sum, Max, Min };
+
+template <Op op>
+__device__ __forceinline__ double combine(double a, double b) {
+  if constexpr (op == Op::Sum) return a + b;
+  if constexpr (op == Op::Max) return a > b ? a : b;
+  return a < b ? a : b;
+}
+
+template <Op op>
+__device__ __forceinline__ double identity() {
+  if constexpr (op == Op::Sum) return 0.0;
+  if constexpr (op == Op::Max) return -1.0 / 0.0;
+  return 1.0 / 0.0;
+}
+
+template <Op op>
+__device__ double block_reduce(double v) {
+  __shared__ double part[kRThreads / 64];
+  for (int off = 32; off > 0; off >>= 1) v = combine<op>(v, __shfl_down(v, off, 64));
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) part[wave] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = part[0];
+    for (int w = 1; w < kRThreads / 64; ++w) r = combine<op>(r, part[w]);
+    v = r;
+  }
+  return v;
+}
+
+enum class Kind { Dot, SqDiff, MaxAbs, SymDot, Max, Min };
+
+template <typename T, Kind kind>
+__global__ __launch_bounds__(kRThreads) void k_reduce_pass1(const T* a, const T* b, const double* sym,
+                                                            int64_t Q, int64_t n, double* work) {
+  constexpr Op op = (kind == Kind::MaxAbs || kind == Kind::Max) ? Op::Max : (kind == Kind::Min ? Op::Min : Op::Sum);
+  double acc = identity<op>();
+  for (int64_t i = blockIdx.x * (int64_t)kRThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kRThreads) {
+    double x;
+    if constexpr (kind == Kind::Dot) {
+      x = static_cast<double>(a[i]) * static_cast<double>(b[i]);
+    } else if constexpr (kind == Kind::SqDiff) {
+      const double dd = static_cast<double>(a[i]) - static_cast<double>(b[i]);
+      x = dd * dd;
+    } else if constexpr (kind == Kind::MaxAbs) {
+      x = fabs(static_cast<double>(a[i]));
+    } else if constexpr (kind == Kind::SymDot) {
+      x = sym[i % Q] * static_cast<double>(a[i]) * static_cast<double>(b[i]);
+    } else {
+      x = static_cast<double>(a[i]);
+    }
+    acc = combine<op>(acc, x);
+  }
+  acc = block_reduce<op>(acc);
+  if (threadIdx.x == 0) work[blockIdx.x] = acc;
+}
+
+template <Op op>
+__global__ __launch_bounds__(kRThreads) void k_reduce_pass2(double* work, int nparts, int slot) {
+  double acc = identity<op>();
+  for (int i = threadIdx.x; i < nparts; i += kRThreads) acc = combine<op>(acc, work[i]);
+  acc = block_reduce<op>(acc);
+  if (threadIdx.x == 0) work[kRBlocks + slot] = acc;
+}
+
+template <typename T, Kind kind>
+void launch(const T* a, const T* b, const double* sym, int64_t Q, int64_t n, double* work, hipStream_t s,
+            int slot) {
+  constexpr Op op = (kind == Kind::MaxAbs || kind == Kind::Max) ? Op::Max : (kind == Kind::Min ? Op::Min : Op::Sum);
+  int blocks = ceil_div(n, kRThreads);
+  if (blocks > kRBlocks) blocks = kRBlocks;
+  if (blocks < 1) blocks = 1;
+  k_reduce_pass1<T, kind><<<blocks, kRThreads, 0, s>>>(a, b, sym, Q, n, work);
+  LDDMM_LAUNCH_CHECK();
+  k_reduce_pass2<op><<<1, kRThreads, 0, s>>>(work, blocks, slot);
+  LDDMM_LAUNCH_CHECK();
+}
+
+double fetch(double* work, double* host, int count, hipStream_t s) {
+  LDDMM_HIP(hipMemcpyAsync(host, work + kRBlocks, count * sizeof(double), hipMemcpyDeviceToHost, s));
+  LDDMM_HIP(hipStreamSynchronize(s));
+  return host[0];
+}
+
+}  // namespace
+
+int64_t reduce_work_size() { return kRBlocks + 8; }
+
+template <typename T>
+double dot(const T* a, const T* b, int64_t n, double* work, double* host, hipStream_t s) {
+  launch<T, Kind::Dot>(a, b, nullptr, 1, n, work, s, 0);
+  return fetch(work, host, 1, s);
+}
+
+template <typename T>
+double sqdiff(const T* a, const T* b, int64_t n, double* work, double* host, hipStream_t s) {
+  launch<T, Kind::SqDiff>(a, b, nullptr, 1, n, work, s, 0);
+  return fetch(work, host, 1, s);
+}
+
+template <typename T>
+double maxabs(const T* a, int64_t n, double* work, double* host, hipStream_t s) {
+  launch<T, Kind::MaxAbs>(a, nullptr, nullptr, 1, n, work, s, 0);
+  return fetch(work, host, 1, s);
+}
+
+template <typename T>
+double sym_dot(const T* x, const T* y, const double* sym, int ncomp, int64_t Q, double* work, double* host,
+               hipStream_t s) {
+  launch<T, Kind::SymDot>(x, y, sym, Q, Q * ncomp, work, s, 0);
+  return fetch(work, host, 1, s);
+}
+
+void minmax_f64(const double* a, int64_t n, double* work, double* host2, hipStream_t s) {
+  launch<double, Kind::Min>(a, nullptr, nullptr, 1, n, work, s, 0);
+  launch<double, Kind::Max>(a, nullptr, nullptr, 1, n, work, s, 1);
+  fetch(work, host2, 2, s);
+}
+
+template double dot<float>(const float*, const float*, int64_t, double*, double*, hipStream_t);
+template double dot<double>(const double*, const double*, int64_t, double*, double*, hipStream_t);
+template double sqdiff<float>(const float*, const float*, int64_t, double*, double*, hipStream_t);
+template double sqdiff<double>(const double*, const double*, int64_t, double*, double*, hipStream_t);
+template double maxabs<float>(const float*, int64_t, double*, double*, hipStream_t);
+template double maxabs<double>(const double*, int64_t, double*, double*, hipStream_t);
+template double sym_dot<float>(const float*, const float*, const double*, int, int64_t, double*, double*,
+                               hipStream_t);
+template double sym_dot<double>(const double*, const double*, const double*, int, int64_t, double*, double*,
+                                hipStream_t);
+
+}  // namespace lddmm

@@ -1,0 +1,854 @@
+// Band-limited PDE-LDDMM with SL-RK2 integration: the sweeps of Table 1 for the
+// image-transport variant (Section 2.3.1) and the deformation-state variant
+// (Section 2.3.3), their gradient and Gauss-Newton Hessian-vector product, and
+// the Gauss-Newton-Krylov driver (Section 2.2, eqs. BLNewton / BLKKT).
+//
+// Readings of the paper used throughout (it leaves them open):
+//  - unit periodic torus, grid-mean L^2 product, real orthonormal band basis with
+//    a zero pad slot per axis, L~ = (1 + alpha (2 pi)^2 |k|^2)^s;
+//  - characteristics X = x -/+ dt/2 (v + v o (x -/+ dt v)) (Section 3.1), one pair
+//    per velocity since v is stationary;
+//  - RK along the characteristic = Heun; a source that does not depend on the
+//    unknown reduces it to the trapezoid rule;
+//  - each band-limited unknown is projected once per step: the stage-1 source is
+//    the exact truncated product of the band-limited snapshot, the predictor stays
+//    a grid field and the stage-2 source is projected with the step result;
+//  - the B-spline interpolant of a band-limited field c has coefficients
+//    iota(S c) with S(k) = prod_j 3 / (2 + cos(2 pi k_j / N_j)): the prefilter is
+//    folded into the inclusion matrices;
+//  - time integrals of the gradient and Hessian terms: trapezoid rule;
+//  - deformation-state gradient term (Du)^T rho, Gauss-Newton Hessian term
+//    (Du)^T drho, final conditions with g1 = (grad P(I0)) o phi(1).
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "solver.h"
+
+namespace lddmm {
+
+namespace {
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+enum MatKind { kPlain = 0, kPref = 1, kDeriv = 2, kProj = 3 };
+
+inline int slot_freq(int a, int K) {
+  if (a == 0) return 0;
+  if (K % 2 == 0 && a == K - 1) return -1;  // pad
+  return (a + 1) / 2;
+}
+
+// value (or derivative) of the real basis function of slot a at x in [0,1)
+inline double basis(int a, int K, double x, bool deriv) {
+  const int k = slot_freq(a, K);
+  if (k < 0) return 0.0;
+  if (k == 0) return deriv ? 0.0 : 1.0;
+  const double th = kTwoPi * k * x, r2 = std::sqrt(2.0);
+  if (a & 1) return deriv ? -kTwoPi * k * r2 * std::sin(th) : r2 * std::cos(th);
+  return deriv ? kTwoPi * k * r2 * std::cos(th) : r2 * std::sin(th);
+}
+
+}  // namespace
+
+template <typename T>
+class Solver final : public SolverBase {
+ public:
+  Solver(const lddmm_bl_params& p, hipStream_t s) : st_(s) {
+    dim_ = p.dim;
+    if (dim_ != 2 && dim_ != 3) throw ArgError("dim must be 2 or 3");
+    if (p.nt < 1) throw ArgError("nt must be >= 1");
+    if (p.variant != LDDMM_BL_IMAGE_TRANSPORT && p.variant != LDDMM_BL_DEFORMATION_STATE)
+      throw ArgError("unknown variant");
+    if (!(p.alpha > 0) || p.s < 1 || !(p.sigma2 > 0)) throw ArgError("alpha, s, sigma2 must be positive");
+    const int off = 3 - dim_;
+    d_.n[0] = d_.n[1] = d_.n[2] = 1;
+    d_.k[0] = d_.k[1] = d_.k[2] = 1;
+    for (int j = 0; j < dim_; ++j) {
+      const int n = p.n[j], k = p.k[j];
+      if (k < 2 || (k % 2) || n < 3 * (k / 2 - 1) + 1 || k - 1 > n || n > 4096)
+        throw ArgError("band must be even with N >= 3 (K/2 - 1) + 1 on every axis");
+      d_.n[off + j] = n;
+      d_.k[off + j] = k;
+    }
+    d_.P = (int64_t)d_.n[0] * d_.n[1] * d_.n[2];
+    d_.Q = (int64_t)d_.k[0] * d_.k[1] * d_.k[2];
+    nt_ = p.nt;
+    dt_ = T(1.0 / p.nt);
+    variant_ = p.variant;
+    alpha_ = p.alpha;
+    s_ = p.s;
+    sigma2_ = p.sigma2;
+    build_matrices();
+    allocate();
+  }
+
+  // ---------------------------------------------------------------- API ops
+  void set_images(const void* I0, const void* I1) override {
+    copy(I0_.get(), static_cast<const T*>(I0), d_.P);
+    copy(I1_.get(), static_cast<const T*>(I1), d_.P);
+    copy(cI0_.get(), I0_.get(), d_.P);
+    prefilter(cI0_.get(), 1, d_, st_);
+    have_images_ = true;
+    state_valid_ = false;
+  }
+
+  void state_solve(const void* v, void* m1, double* E3) override {
+    if (!have_images_) throw StateError("set_images must precede state_solve");
+    to_internal(vbl_.get(), static_cast<const T*>(v), 3);
+    double e[3];
+    run_state(e);
+    if (m1) copy(static_cast<T*>(m1), m1_ptr(), d_.P);
+    if (E3) std::memcpy(E3, e, sizeof(e));
+    sync();
+  }
+
+  void adjoint_solve(void* grad, double* ginf) override {
+    require_state();
+    run_adjoint(gbl_.get());
+    if (grad) from_internal(static_cast<T*>(grad), gbl_.get(), 3);
+    if (ginf) *ginf = grad_inf(gbl_.get());
+    sync();
+  }
+
+  void hess_matvec(const void* dv, void* hdv) override {
+    require_state();
+    to_internal(dvbl_.get(), static_cast<const T*>(dv), 3);
+    run_matvec(dvbl_.get(), hbl_.get());
+    from_internal(static_cast<T*>(hdv), hbl_.get(), 3);
+    sync();
+  }
+
+  int gn_solve(const lddmm_bl_gn_opts& o, void* v, const void* Z, int r, lddmm_bl_gn_report* rep) override;
+
+  void jacobian(double* detmap, double* minmax) override {
+    require_state();
+    // u~(1): the deformation state (variant 3 holds it; variant 1 integrates it here)
+    const T* u1;
+    if (variant_ == LDDMM_BL_DEFORMATION_STATE) {
+      u1 = ubl_.get() + (int64_t)nt_ * 3 * d_.Q;
+    } else {
+      displacement_only(tmpbl_.get());
+      u1 = tmpbl_.get();
+    }
+    stack_deriv9(u1, stk_.get());
+    iota9_deriv(stk_.get(), S9());
+    DevBuf<double> det(d_.P);
+    jacobian_det(det.get(), S9(), dim_, d_.P, st_);
+    minmax_f64(det.get(), d_.P, work_.get(), host_.get(), st_);
+    if (minmax) {
+      minmax[0] = host_.get()[0];
+      minmax[1] = host_.get()[1];
+    }
+    if (detmap) LDDMM_HIP(hipMemcpyAsync(detmap, det.get(), d_.P * sizeof(double), hipMemcpyDeviceToDevice, st_));
+    sync();
+  }
+
+  void project(const void* grid, void* bl, int ncomp) override {
+    check_ncomp(ncomp);
+    pi(static_cast<const T*>(grid), static_cast<T*>(bl), ncomp);
+    sync();
+  }
+
+  void include(const void* bl, void* grid, int ncomp) override {
+    check_ncomp(ncomp);
+    int kinds[kMaxFields][3] = {};
+    iota(static_cast<const T*>(bl), static_cast<T*>(grid), ncomp, kinds);
+    sync();
+  }
+
+  int64_t get_field(int which, int index, void* dst) override;
+
+  double dot(const void* a, const void* b, int64_t n) override {
+    return lddmm::dot<T>(static_cast<const T*>(a), static_cast<const T*>(b), n, work_.get(), host_.get(), st_);
+  }
+
+ private:
+  // ------------------------------------------------------------ set-up
+  void build_matrices() {
+    // per axis: B [n][k], Bs [n][k], Bd [n][k], P [k][n]
+    int64_t total = 0;
+    for (int a = 0; a < 3; ++a) total += 4LL * d_.n[a] * d_.k[a];
+    std::vector<T> h(total);
+    int64_t o = 0;
+    for (int a = 0; a < 3; ++a) {
+      const int n = d_.n[a], k = d_.k[a];
+      for (int m = 0; m < 4; ++m) mat_off_[a][m] = o + (int64_t)m * n * k;
+      for (int x = 0; x < n; ++x) {
+        const double xx = double(x) / n;
+        for (int s = 0; s < k; ++s) {
+          const double b = basis(s, k, xx, false);
+          const int f = slot_freq(s, k);
+          const double sc = f < 0 ? 0.0 : 3.0 / (2.0 + std::cos(kTwoPi * f / n));
+          h[mat_off_[a][kPlain] + (int64_t)x * k + s] = static_cast<T>(b);
+          h[mat_off_[a][kPref] + (int64_t)x * k + s] = static_cast<T>(b * sc);
+          h[mat_off_[a][kDeriv] + (int64_t)x * k + s] = static_cast<T>(basis(s, k, xx, true));
+          h[mat_off_[a][kProj] + (int64_t)s * n + x] = static_cast<T>(b / n);
+        }
+      }
+      o += 4LL * n * k;
+    }
+    mats_.alloc(total);
+    LDDMM_HIP(hipMemcpy(mats_.get(), h.data(), total * sizeof(T), hipMemcpyHostToDevice));
+    // L~ symbol and its inverse; zero on pad slots
+    std::vector<double> L(d_.Q), Li(d_.Q);
+    for (int a0 = 0; a0 < d_.k[0]; ++a0)
+      for (int a1 = 0; a1 < d_.k[1]; ++a1)
+        for (int a2 = 0; a2 < d_.k[2]; ++a2) {
+          const int f0 = slot_freq(a0, d_.k[0]), f1 = slot_freq(a1, d_.k[1]), f2 = slot_freq(a2, d_.k[2]);
+          const int64_t q = ((int64_t)a0 * d_.k[1] + a1) * d_.k[2] + a2;
+          if (f0 < 0 || f1 < 0 || f2 < 0) {
+            L[q] = Li[q] = 0.0;
+            continue;
+          }
+          const double k2 = double(f0) * f0 + double(f1) * f1 + double(f2) * f2;
+          L[q] = std::pow(1.0 + alpha_ * kTwoPi * kTwoPi * k2, s_);
+          Li[q] = 1.0 / L[q];
+        }
+    Lsym_.alloc(d_.Q);
+    Linv_.alloc(d_.Q);
+    LDDMM_HIP(hipMemcpy(Lsym_.get(), L.data(), d_.Q * sizeof(double), hipMemcpyHostToDevice));
+    LDDMM_HIP(hipMemcpy(Linv_.get(), Li.data(), d_.Q * sizeof(double), hipMemcpyHostToDevice));
+  }
+
+  void allocate() {
+    const int64_t P = d_.P, Q = d_.Q, nn = nt_ + 1;
+    const int64_t t_sz = (int64_t)kMaxFields * std::max<int64_t>((int64_t)d_.k[0] * d_.n[1] * d_.n[2],
+                                                                 (int64_t)d_.k[0] * d_.k[1] * d_.n[2]);
+    t1_.alloc(t_sz);
+    t2_.alloc(t_sz);
+    I0_.alloc(P);
+    I1_.alloc(P);
+    cI0_.alloc(P);
+    vbl_.alloc(3 * Q);
+    dvbl_.alloc(3 * Q);
+    gbl_.alloc(3 * Q);
+    hbl_.alloc(3 * Q);
+    tmpbl_.alloc(3 * Q);
+    stk_.alloc(kMaxFields * Q);
+    blA_.alloc(kMaxFields * Q);
+    blB_.alloc(kMaxFields * Q);
+    acc_.alloc(3 * Q);
+    vg_.alloc(3 * P);
+    divv_.alloc(P);
+    Xb_.alloc(3 * P);
+    Xf_.alloc(3 * P);
+    dvg_.alloc(3 * P);
+    scratch_.alloc(13 * P);  // 9P-field transforms + 4P staging
+    inc_.alloc(nn * 3 * Q);
+    incadj_.alloc(nn * 3 * Q);
+    if (variant_ == LDDMM_BL_IMAGE_TRANSPORT) {
+      G_.alloc(nn * 3 * P);
+      m_.alloc(nn * P);
+      lam0_.alloc(P);
+    } else {
+      ubl_.alloc(nn * 3 * Q);
+      Du_.alloc(nn * 9 * P);
+      m1_.alloc(P);
+      g1_.alloc(3 * P);
+      rho_.alloc(nn * 3 * Q);
+    }
+    work_.alloc(reduce_work_size());
+    double* hp = nullptr;
+    LDDMM_HIP(hipHostMalloc(reinterpret_cast<void**>(&hp), 8 * sizeof(double), hipHostMallocDefault));
+    host_.reset(hp);
+  }
+
+  struct PinnedFree {
+    void operator()(double* p) const { (void)hipHostFree(p); }
+  };
+
+  // --------------------------------------------------------- small helpers
+  const T* mat(int axis, int kind) const { return mats_.get() + mat_off_[axis][kind]; }
+  void copy(T* dst, const T* src, int64_t n) {
+    LDDMM_HIP(hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyDeviceToDevice, st_));
+  }
+  void sync() { LDDMM_HIP(hipStreamSynchronize(st_)); }
+  void check_ncomp(int ncomp) const {
+    if (ncomp < 1 || ncomp > kMaxFields) throw ArgError("ncomp must be in 1..12");
+  }
+  void require_state() const {
+    if (!state_valid_) throw StateError("no state solve at the current velocity");
+  }
+  T* S(int i) { return scratch_.get() + (int64_t)i * d_.P; }
+  T* S9() { return scratch_.get(); }
+  const T* m1_ptr() const {
+    return variant_ == LDDMM_BL_IMAGE_TRANSPORT ? m_.get() + (int64_t)nt_ * d_.P : m1_.get();
+  }
+
+  // user [dim][..] <-> internal [3][..] for ncomp-vector arrays of length Q
+  void to_internal(T* dst, const T* src, int ncomp) {
+    const int64_t Q = d_.Q;
+    if (dim_ == 3) {
+      copy(dst, src, ncomp * Q);
+    } else {
+      zero(dst, Q, st_);
+      copy(dst + Q, src, 2 * Q);
+    }
+  }
+  void from_internal(T* dst, const T* src, int ncomp) {
+    const int64_t Q = d_.Q;
+    if (dim_ == 3)
+      copy(dst, src, ncomp * Q);
+    else
+      copy(dst, src + Q, 2 * Q);
+  }
+
+  // ------------------------------------------------ truncated DFT (Section 2.2)
+  // iota of nf stacked BL fields; kinds[f][axis] picks plain / prefiltered / derivative matrices
+  void iota(const T* bl, T* out, int nf, const int kinds[][3]) {
+    const int n0 = d_.n[0], n1 = d_.n[1], n2 = d_.n[2], k0 = d_.k[0], k1 = d_.k[1], k2 = d_.k[2];
+    FieldMats<T> W{};
+    for (int f = 0; f < nf; ++f) W.w[f] = mat(2, kinds[f][2]);
+    dft_right(bl, t1_.get(), W, nf, k0 * k1, k2, n2, st_);
+    const bool skip0 = (n0 == 1 && k0 == 1);
+    T* dstB = skip0 ? out : t2_.get();
+    for (int f = 0; f < nf; ++f) W.w[f] = mat(1, kinds[f][1]);
+    dft_left(t1_.get(), dstB, W, nf * k0, k0, n1, k1, n2, (int64_t)k1 * n2, (int64_t)n1 * n2, st_);
+    if (!skip0) {
+      for (int f = 0; f < nf; ++f) W.w[f] = mat(0, kinds[f][0]);
+      dft_left(t2_.get(), out, W, nf, 1, n0, k0, n1 * n2, (int64_t)k0 * n1 * n2, d_.P, st_);
+    }
+  }
+  void iota_kind(const T* bl, T* out, int nf, int kind) {
+    int kinds[kMaxFields][3];
+    for (int f = 0; f < nf; ++f) kinds[f][0] = kinds[f][1] = kinds[f][2] = kind;
+    iota(bl, out, nf, kinds);
+  }
+  // pi of nf stacked grid fields
+  void pi(const T* grid, T* bl, int nf) {
+    const int n0 = d_.n[0], n1 = d_.n[1], n2 = d_.n[2], k0 = d_.k[0], k1 = d_.k[1], k2 = d_.k[2];
+    FieldMats<T> W{};
+    const T* srcB = grid;
+    if (!(n0 == 1 && k0 == 1)) {
+      for (int f = 0; f < nf; ++f) W.w[f] = mat(0, kProj);
+      dft_left(grid, t1_.get(), W, nf, 1, k0, n0, n1 * n2, d_.P, (int64_t)k0 * n1 * n2, st_);
+      srcB = t1_.get();
+    }
+    for (int f = 0; f < nf; ++f) W.w[f] = mat(1, kProj);
+    dft_left(srcB, t2_.get(), W, nf * k0, k0, k1, n1, n2, (int64_t)n1 * n2, (int64_t)k1 * n2, st_);
+    for (int f = 0; f < nf; ++f) W.w[f] = mat(2, kProj);
+    dft_right(t2_.get(), bl, W, nf, k0 * k1, n2, k2, st_);
+  }
+  // 9 derivative fields d_j u_i from a BL vector u (stacked as [u0,u0,u0,u1,u1,u1,u2,u2,u2])
+  void stack_deriv9(const T* u, T* stk) {
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) copy(stk + (int64_t)(3 * i + j) * d_.Q, u + (int64_t)i * d_.Q, d_.Q);
+  }
+  void iota9_deriv(const T* stk, T* out) {
+    int kinds[kMaxFields][3] = {};
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        for (int a = 0; a < 3; ++a) kinds[3 * i + j][a] = (a == j) ? kDeriv : kPlain;
+    iota(stk, out, 9, kinds);
+  }
+  void axpby(T* out, T a, const T* x, T b, const T* y, int64_t n) { bl_axpby<T>(out, a, x, b, y, n, st_); }
+
+  double grad_inf(const T* g) {
+    iota_kind(g, S(0), 3, kPlain);
+    return maxabs<T>(S(0), 3 * d_.P, work_.get(), host_.get(), st_);
+  }
+
+  // ---------------------------------------------- per-velocity set-up (Section 3.1)
+  void setup_velocity() {
+    const int64_t Q = d_.Q, P = d_.P;
+    // velocity samples and the B-spline coefficients of the velocity in one 6-field transform
+    copy(stk_.get(), vbl_.get(), 3 * Q);
+    copy(stk_.get() + 3 * Q, vbl_.get(), 3 * Q);
+    int kinds[kMaxFields][3] = {};
+    for (int f = 3; f < 6; ++f) kinds[f][0] = kinds[f][1] = kinds[f][2] = kPref;
+    iota(stk_.get(), S(0), 6, kinds);
+    copy(vg_.get(), S(0), 3 * P);
+    const T* cv = S(3);
+    characteristics<T>(Xb_.get(), vg_.get(), cv, d_, dt_, -1, st_);
+    characteristics<T>(Xf_.get(), vg_.get(), cv, d_, dt_, +1, st_);
+    bl_div<T>(tmpbl_.get(), vbl_.get(), d_, st_);
+    iota_kind(tmpbl_.get(), divv_.get(), 1, kPlain);
+  }
+
+  double regulariser() {
+    return 0.5 * sym_dot<T>(vbl_.get(), vbl_.get(), Lsym_.get(), 3, d_.Q, work_.get(), host_.get(), st_);
+  }
+
+  void finish_objective(double e[3]) {
+    const double data = sqdiff<T>(m1_ptr(), I1_.get(), d_.P, work_.get(), host_.get(), st_) / d_.P / sigma2_;
+    const double reg = regulariser();
+    e[0] = reg + data;
+    e[1] = reg;
+    e[2] = data;
+    if (!std::isfinite(e[0])) throw NonFiniteError("objective is not finite");
+  }
+
+  void run_state(double e[3]) {
+    state_valid_ = false;
+    setup_velocity();
+    if (variant_ == LDDMM_BL_IMAGE_TRANSPORT)
+      state_v1();
+    else
+      state_v3();
+    finish_objective(e);
+    state_valid_ = true;
+  }
+
+  // ------------------------------------ image transport: state (Table 1 row 1)
+  void state_v1() {
+    const int64_t P = d_.P, Q = d_.Q;
+    copy(m_.get(), I0_.get(), P);
+    for (int n = 0; n <= nt_; ++n) {
+      T* mn = m_.get() + n * P;
+      // G_n = iota(grad~ pi(m_n)): derivative folded into the axis matrices
+      pi(mn, tmpbl_.get(), 1);
+      for (int j = 0; j < 3; ++j) copy(stk_.get() + j * Q, tmpbl_.get(), Q);
+      int kinds[kMaxFields][3] = {};
+      for (int j = 0; j < 3; ++j) kinds[j][j] = kDeriv;
+      iota(stk_.get(), G_.get() + n * 3 * P, 3, kinds);
+      if (n < nt_) {
+        copy(S(0), mn, P);
+        prefilter(S(0), 1, d_, st_);
+        interp<T>(mn + P, S(0), 1, Xb_.get(), d_, st_);
+      }
+    }
+  }
+
+  // ------------------------------ deformation state: state (Table 1 row 3)
+  void state_v3() {
+    const int64_t P = d_.P, Q = d_.Q;
+    const T hdt = T(0.5) * dt_;
+    zero(ubl_.get(), 3 * Q, st_);
+    for (int n = 0; n < nt_; ++n) {
+      const T* un = ubl_.get() + n * 3 * Q;
+      T* un1 = ubl_.get() + (n + 1) * 3 * Q;
+      axpby(tmpbl_.get(), T(1), un, hdt, vbl_.get(), 3 * Q);
+      iota_kind(tmpbl_.get(), S(0), 3, kPref);
+      interp<T>(S(3), S(0), 3, Xb_.get(), d_, st_);
+      pi(S(3), blA_.get(), 3);
+      axpby(un1, T(1), blA_.get(), hdt, vbl_.get(), 3 * Q);
+    }
+    for (int n = 0; n <= nt_; ++n) {
+      stack_deriv9(ubl_.get() + n * 3 * Q, stk_.get());
+      iota9_deriv(stk_.get(), Du_.get() + n * 9 * P);
+    }
+    iota_kind(ubl_.get() + (int64_t)nt_ * 3 * Q, S(0), 3, kPlain);
+    final_warp<T>(m1_.get(), g1_.get(), cI0_.get(), S(0), d_, st_);
+  }
+
+  // u~(1) only, for the Jacobian of the image-transport variant
+  void displacement_only(T* u) {
+    const int64_t Q = d_.Q;
+    const T hdt = T(0.5) * dt_;
+    zero(u, 3 * Q, st_);
+    for (int n = 0; n < nt_; ++n) {
+      axpby(blB_.get(), T(1), u, hdt, vbl_.get(), 3 * Q);
+      iota_kind(blB_.get(), S(0), 3, kPref);
+      interp<T>(S(3), S(0), 3, Xb_.get(), d_, st_);
+      pi(S(3), blA_.get(), 3);
+      axpby(u, T(1), blA_.get(), hdt, vbl_.get(), 3 * Q);
+    }
+  }
+
+  T trap_w(int n) const { return (n == 0 || n == nt_) ? T(0.5) * dt_ : dt_; }
+
+  // ------------------------------------------ adjoint + gradient (rows 2 / 4)
+  void run_adjoint(T* g) {
+    if (variant_ == LDDMM_BL_IMAGE_TRANSPORT)
+      adjoint_v1();
+    else
+      adjoint_v3();
+    bl_scale_sym<T>(g, vbl_.get(), Lsym_.get(), 3, d_.Q, acc_.get(), st_);
+  }
+
+  void adjoint_v1() {
+    const int64_t P = d_.P, Q = d_.Q;
+    T* lam = S(9);
+    T* lam_next = S(10);
+    scaled_diff<T>(lam, T(-2.0 / sigma2_), m1_ptr(), I1_.get(), P, st_);
+    zero(acc_.get(), 3 * Q, st_);
+    for (int n = nt_; n >= 0; --n) {
+      // gradient term w_n pi(iota(pi lambda_n) G_n)
+      pi(lam, tmpbl_.get(), 1);
+      iota_kind(tmpbl_.get(), S(0), 1, kPlain);
+      v1_products<T>(S(1), S(0), divv_.get(), G_.get() + n * 3 * P, d_, st_);
+      pi(S(2), blA_.get(), 3);
+      axpby(acc_.get(), T(1), acc_.get(), trap_w(n), blA_.get(), 3 * Q);
+      if (n == 0) break;
+      copy(S(5), lam, P);
+      mul<T>(S(6), lam, divv_.get(), P, st_);
+      prefilter(S(5), 2, d_, st_);
+      adjoint_grid_step<T>(lam_next, S(5), S(6), Xf_.get(), divv_.get(), d_, dt_, st_);
+      std::swap(lam, lam_next);
+    }
+    copy(lam0_.get(), lam, P);
+  }
+
+  // band-limited backward sweep with source (.) star div~ v~ (rows 4, 6, 8), ncomp 1 or 3,
+  // accumulating the Hessian / gradient term: variant 1 pi(e G_n), variant 3 -pi((Du_n)^T e)
+  void bl_backward(T* traj, int ncomp, T* acc) {
+    const int64_t P = d_.P, Q = d_.Q;
+    const int64_t stride = (int64_t)ncomp * Q;
+    const T hdt = T(0.5) * dt_;
+    zero(acc, 3 * Q, st_);
+    for (int n = nt_; n >= 0; --n) {
+      T* xn = traj + n * stride;
+      iota_kind(xn, S(0), ncomp, kPlain);  // e = iota(x_n)
+      if (variant_ == LDDMM_BL_IMAGE_TRANSPORT) {
+        v1_products<T>(S(1), S(0), divv_.get(), G_.get() + n * 3 * P, d_, st_);
+        pi(S(1), blA_.get(), 4);  // [fl, e G0, e G1, e G2]
+        axpby(acc, T(1), acc, trap_w(n), blA_.get() + Q, 3 * Q);
+      } else {
+        v3_products<T>(S(3), S(0), divv_.get(), Du_.get() + n * 9 * P, d_, st_);
+        pi(S(3), blA_.get(), 6);  // [fl (3), (Du)^T e (3)]
+        axpby(acc, T(1), acc, trap_w(n), xn, 3 * Q);
+        axpby(acc, T(1), acc, -trap_w(n), blA_.get() + 3 * Q, 3 * Q);
+      }
+      if (n == 0) break;
+      const T* fl = blA_.get();
+      // cA = P(x + dt/2 fl), cB = P(x + dt fl), stacked
+      axpby(blB_.get(), T(1), xn, hdt, fl, stride);
+      axpby(blB_.get() + stride, T(1), xn, dt_, fl, stride);
+      iota_kind(blB_.get(), S(3), 2 * ncomp, kPref);
+      bl_adjoint_step<T>(S(9), S(3), S(3 + ncomp), ncomp, Xf_.get(), divv_.get(), d_, dt_, st_);
+      pi(S(9), traj + (n - 1) * stride, ncomp);
+    }
+  }
+
+  void adjoint_v3() {
+    const int64_t Q = d_.Q;
+    residual_times_grad<T>(S(0), T(-2.0 / sigma2_), m1_.get(), I1_.get(), g1_.get(), d_, st_);
+    pi(S(0), rho_.get() + (int64_t)nt_ * 3 * Q, 3);
+    bl_backward(rho_.get(), 3, acc_.get());
+  }
+
+  // ----------------------------------- Hessian matvec (rows 5-8, Section 2.3)
+  void run_matvec(const T* dv, T* h) {
+    const int64_t P = d_.P, Q = d_.Q;
+    const T hdt = T(0.5) * dt_;
+    iota_kind(dv, dvg_.get(), 3, kPlain);
+    if (variant_ == LDDMM_BL_IMAGE_TRANSPORT) {
+      T* dm = inc_.get();  // [nt+1][Q]
+      T* f = blB_.get();   // source projection at node n
+      v1_source<T>(S(0), G_.get(), dvg_.get(), d_, st_);
+      pi(S(0), f, 1);
+      zero(dm, Q, st_);
+      for (int n = 0; n < nt_; ++n) {
+        axpby(tmpbl_.get(), T(1), dm + n * Q, hdt, f, Q);
+        iota_kind(tmpbl_.get(), S(0), 1, kPref);
+        inc_state_v1<T>(S(1), S(0), Xb_.get(), G_.get() + (n + 1) * 3 * P, dvg_.get(), d_, st_);
+        pi(S(1), blA_.get(), 2);
+        copy(f, blA_.get() + Q, Q);
+        axpby(dm + (n + 1) * Q, T(1), blA_.get(), hdt, f, Q);
+      }
+      T* dl = incadj_.get();
+      axpby(dl + (int64_t)nt_ * Q, T(-2.0 / sigma2_), dm + (int64_t)nt_ * Q, T(0), nullptr, Q);
+      bl_backward(dl, 1, acc_.get());
+    } else {
+      T* du = inc_.get();  // [nt+1][3][Q]
+      T* f = blB_.get();
+      v3_source<T>(S(0), Du_.get(), dvg_.get(), d_, st_);
+      pi(S(0), f, 3);
+      zero(du, 3 * Q, st_);
+      for (int n = 0; n < nt_; ++n) {
+        axpby(tmpbl_.get(), T(1), du + n * 3 * Q, hdt, f, 3 * Q);
+        iota_kind(tmpbl_.get(), S(0), 3, kPref);
+        inc_state_v3<T>(S(3), S(0), Xb_.get(), Du_.get() + (n + 1) * 9 * P, dvg_.get(), d_, st_);
+        pi(S(3), blA_.get(), 6);
+        copy(f, blA_.get() + 3 * Q, 3 * Q);
+        axpby(du + (n + 1) * 3 * Q, T(1), blA_.get(), hdt, f, 3 * Q);
+      }
+      // t = 1 coupling: drho~(1) = pi((2/sigma^2) (g1 . iota(du~(1))) g1)
+      iota_kind(du + (int64_t)nt_ * 3 * Q, S(0), 3, kPlain);
+      coupling_v3<T>(S(3), T(2.0 / sigma2_), g1_.get(), S(0), d_, st_);
+      T* dr = incadj_.get();
+      pi(S(3), dr + (int64_t)nt_ * 3 * Q, 3);
+      bl_backward(dr, 3, acc_.get());
+    }
+    bl_scale_sym<T>(h, dv, Lsym_.get(), 3, Q, acc_.get(), st_);
+  }
+
+  // ------------------------------------------------------------------ state
+  hipStream_t st_;
+  Dims d_{};
+  int dim_ = 3, nt_ = 1, variant_ = 1, s_ = 2;
+  T dt_ = T(1);
+  double alpha_ = 0, sigma2_ = 1;
+  bool have_images_ = false, state_valid_ = false;
+  int64_t mat_off_[3][4] = {};
+  DevBuf<T> mats_;
+  DevBuf<double> Lsym_, Linv_, work_;
+  std::unique_ptr<double, PinnedFree> host_;
+  DevBuf<T> t1_, t2_, I0_, I1_, cI0_;
+  DevBuf<T> vbl_, dvbl_, gbl_, hbl_, tmpbl_, stk_, blA_, blB_, acc_;
+  DevBuf<T> vg_, divv_, Xb_, Xf_, dvg_, scratch_;
+  DevBuf<T> inc_, incadj_;
+  DevBuf<T> G_, m_, lam0_;               // image transport
+  DevBuf<T> ubl_, Du_, m1_, g1_, rho_;   // deformation state
+
+ public:
+  // accessors used by the Gauss-Newton driver
+  int64_t vec_len() const { return 3 * d_.Q; }
+  void set_velocity_internal(const T* v) { copy(vbl_.get(), v, 3 * d_.Q); }
+  void state_internal(double e[3]) { run_state(e); }
+  void adjoint_internal(T* g) { run_adjoint(g); }
+  void matvec_internal(const T* x, T* y) { run_matvec(x, y); }
+  void precond_internal(const T* r, T* z) { bl_scale_sym<T>(z, r, Linv_.get(), 3, d_.Q, nullptr, st_); }
+  double dot_internal(const T* a, const T* b) {
+    return lddmm::dot<T>(a, b, 3 * d_.Q, work_.get(), host_.get(), st_);
+  }
+  double grad_inf_internal(const T* g) { return grad_inf(g); }
+  void axpby_internal(T* out, T a, const T* x, T b, const T* y) { axpby(out, a, x, b, y, 3 * d_.Q); }
+  void copy_internal(T* dst, const T* src) { copy(dst, src, 3 * d_.Q); }
+  void user_to_internal(T* dst, const T* src) { to_internal(dst, src, 3); }
+  void internal_to_user(T* dst, const T* src) { from_internal(dst, src, 3); }
+  double mse_rel() {
+    const double num = sqdiff<T>(m1_ptr(), I1_.get(), d_.P, work_.get(), host_.get(), st_);
+    const double den = sqdiff<T>(I0_.get(), I1_.get(), d_.P, work_.get(), host_.get(), st_);
+    return den > 0 ? num / den : 0.0;
+  }
+  hipStream_t stream() const { return st_; }
+  void synchronize() { sync(); }
+};
+
+// ---------------------------------------------------------------- field access
+template <typename T>
+int64_t Solver<T>::get_field(int which, int index, void* dst_v) {
+  T* dst = static_cast<T*>(dst_v);
+  const int64_t P = d_.P, Q = d_.Q;
+  const int off = 3 - dim_;
+  auto grid_vec = [&](const T* src) -> int64_t {
+    if (dst) copy(dst, src + off * P, dim_ * P);
+    return dim_ * P;
+  };
+  auto bl_vec = [&](const T* src) -> int64_t {
+    if (dst) copy(dst, src + off * Q, dim_ * Q);
+    return dim_ * Q;
+  };
+  auto check_index = [&]() {
+    if (index < 0 || index > nt_) throw ArgError("time index out of range");
+  };
+  int64_t count = 0;
+  const bool v1 = variant_ == LDDMM_BL_IMAGE_TRANSPORT;
+  if (which != LDDMM_BL_FIELD_INC_STATE && which != LDDMM_BL_FIELD_INC_ADJOINT) require_state();
+  switch (which) {
+    case LDDMM_BL_FIELD_VELOCITY:
+      count = grid_vec(vg_.get());
+      break;
+    case LDDMM_BL_FIELD_DEP_BACKWARD:
+      count = grid_vec(Xb_.get());
+      break;
+    case LDDMM_BL_FIELD_DEP_FORWARD:
+      count = grid_vec(Xf_.get());
+      break;
+    case LDDMM_BL_FIELD_DIV_V:
+      if (dst) copy(dst, divv_.get(), P);
+      count = P;
+      break;
+    case LDDMM_BL_FIELD_STATE:
+      check_index();
+      if (v1) {
+        if (dst) copy(dst, m_.get() + index * P, P);
+        count = P;
+      } else {
+        count = bl_vec(ubl_.get() + index * 3 * Q);
+      }
+      break;
+    case LDDMM_BL_FIELD_M1:
+      if (dst) copy(dst, m1_ptr(), P);
+      count = P;
+      break;
+    case LDDMM_BL_FIELD_ADJOINT0:
+      if (v1) {
+        if (dst) copy(dst, lam0_.get(), P);
+        count = P;
+      } else {
+        count = bl_vec(rho_.get());
+      }
+      break;
+    case LDDMM_BL_FIELD_INC_STATE:
+    case LDDMM_BL_FIELD_INC_ADJOINT: {
+      check_index();
+      const T* base = which == LDDMM_BL_FIELD_INC_STATE ? inc_.get() : incadj_.get();
+      if (v1) {
+        if (dst) copy(dst, base + index * Q, Q);
+        count = Q;
+      } else {
+        count = bl_vec(base + index * 3 * Q);
+      }
+      break;
+    }
+    default:
+      throw ArgError("unknown field");
+  }
+  sync();
+  return count;
+}
+
+// ------------------------------------------------------- Gauss-Newton-Krylov
+// PCG on H dv = -g from dv = 0 with L~^{-1} (or the two-level preconditioner),
+// stopped at ||r|| <= eta ||g||, eta = min(0.5, sqrt(||g_k|| / ||g_0||)), the cap, or
+// non-positive curvature; Armijo backtracking from eps = 1 (<= 10 halvings,
+// c = 1e-4); stop at ||g||_inf <= rtol * reference.
+template <typename T>
+int Solver<T>::gn_solve(const lddmm_bl_gn_opts& o, void* v_user, const void* Zu, int r, lddmm_bl_gn_report* rep) {
+  if (!have_images_) throw StateError("set_images must precede gn_solve");
+  if (o.max_gn < 0 || o.max_pcg < 1) throw ArgError("max_gn >= 0 and max_pcg >= 1 required");
+  if (Zu && (r < 1 || r > 16)) throw ArgError("preconditioner rank must be 1..16");
+  const auto t0 = std::chrono::steady_clock::now();
+  const int64_t n = vec_len();
+  DevBuf<T> v(n), g(n), x(n), rr(n), z(n), p(n), Ap(n), vt(n), Z, HZ;
+  std::vector<double> ZHZinv;
+  int status = LDDMM_BL_OK;
+  lddmm_bl_gn_report R{};
+  user_to_internal(v.get(), static_cast<T*>(v_user));
+  set_velocity_internal(v.get());
+  double e[3];
+  state_internal(e);
+  double E = e[0];
+  R.E0 = E;
+  adjoint_internal(g.get());
+  double ginf = grad_inf_internal(g.get());
+  const double ref = o.grad_ref_inf > 0 ? o.grad_ref_inf : ginf;
+  const double gnorm0 = std::sqrt(dot_internal(g.get(), g.get()));
+  const bool fixed = o.fixed_iters != 0;
+  // two-level preconditioner: M^-1 r = L^-1 r + Z (Z^T H Z)^-1 Z^T r, Z recomputed per GN iteration
+  const bool twolevel = Zu != nullptr;
+  if (twolevel) {
+    Z.alloc(r * n);
+    HZ.alloc(r * n);
+    for (int i = 0; i < r; ++i)
+      user_to_internal(Z.get() + i * n, static_cast<const T*>(Zu) + (int64_t)i * (n / 3) * dim_);
+    ZHZinv.assign(r * r, 0.0);
+  }
+  auto precond = [&](const T* rin, T* zout) {
+    precond_internal(rin, zout);
+    if (!twolevel) return;
+    std::vector<double> c(r), y(r, 0.0);
+    for (int i = 0; i < r; ++i) c[i] = dot_internal(Z.get() + i * n, rin);
+    for (int i = 0; i < r; ++i)
+      for (int j = 0; j < r; ++j) y[i] += ZHZinv[i * r + j] * c[j];
+    for (int i = 0; i < r; ++i) axpby_internal(zout, T(1), zout, T(y[i]), Z.get() + i * n);
+  };
+  int k = 0;
+  for (k = 0; k < o.max_gn; ++k) {
+    if (!fixed && ginf <= o.grad_rtol * ref) break;
+    if (twolevel) {
+      // Z^T H Z at the current velocity (r extra matvecs), inverted by Gauss-Jordan in double
+      std::vector<double> A(r * r);
+      for (int i = 0; i < r; ++i) {
+        matvec_internal(Z.get() + i * n, HZ.get() + i * n);
+        ++R.hess_matvecs;
+      }
+      for (int i = 0; i < r; ++i)
+        for (int j = 0; j < r; ++j) A[i * r + j] = dot_internal(Z.get() + i * n, HZ.get() + j * n);
+      for (int i = 0; i < r; ++i)
+        for (int j = 0; j < i; ++j) A[i * r + j] = A[j * r + i] = 0.5 * (A[i * r + j] + A[j * r + i]);
+      std::vector<double> Inv(r * r, 0.0);
+      for (int i = 0; i < r; ++i) Inv[i * r + i] = 1.0;
+      bool ok = true;
+      for (int c = 0; c < r && ok; ++c) {
+        int piv = c;
+        for (int i = c + 1; i < r; ++i)
+          if (std::fabs(A[i * r + c]) > std::fabs(A[piv * r + c])) piv = i;
+        if (!(std::fabs(A[piv * r + c]) > 1e-300)) {
+          ok = false;
+          break;
+        }
+        for (int j = 0; j < r; ++j) {
+          std::swap(A[c * r + j], A[piv * r + j]);
+          std::swap(Inv[c * r + j], Inv[piv * r + j]);
+        }
+        const double dv = A[c * r + c];
+        for (int j = 0; j < r; ++j) {
+          A[c * r + j] /= dv;
+          Inv[c * r + j] /= dv;
+        }
+        for (int i = 0; i < r; ++i) {
+          if (i == c) continue;
+          const double f = A[i * r + c];
+          for (int j = 0; j < r; ++j) {
+            A[i * r + j] -= f * A[c * r + j];
+            Inv[i * r + j] -= f * Inv[c * r + j];
+          }
+        }
+      }
+      if (ok)
+        ZHZinv = Inv;
+      else
+        std::fill(ZHZinv.begin(), ZHZinv.end(), 0.0);
+    }
+    const double gnorm = std::sqrt(dot_internal(g.get(), g.get()));
+    const double eta = gnorm0 > 0 ? std::min(0.5, std::sqrt(gnorm / gnorm0)) : 0.5;
+    const double tol = eta * gnorm;
+    // PCG
+    zero(x.get(), n, stream());
+    axpby_internal(rr.get(), T(-1), g.get(), T(0), nullptr);
+    precond(rr.get(), z.get());
+    copy_internal(p.get(), z.get());
+    double rz = dot_internal(rr.get(), z.get());
+    int its = 0;
+    for (its = 0; its < o.max_pcg; ++its) {
+      const double rn = std::sqrt(dot_internal(rr.get(), rr.get()));
+      if (!fixed && rn <= tol) break;
+      matvec_internal(p.get(), Ap.get());
+      ++R.hess_matvecs;
+      const double pAp = dot_internal(p.get(), Ap.get());
+      if (!std::isfinite(pAp)) throw NonFiniteError("non-finite curvature in PCG");
+      if (pAp <= 0.0) {
+        status = LDDMM_BL_W_NEGCURV;
+        if (its == 0) copy_internal(x.get(), p.get());
+        break;
+      }
+      const double a = rz / pAp;
+      axpby_internal(x.get(), T(1), x.get(), T(a), p.get());
+      axpby_internal(rr.get(), T(1), rr.get(), T(-a), Ap.get());
+      precond(rr.get(), z.get());
+      const double rz_new = dot_internal(rr.get(), z.get());
+      axpby_internal(p.get(), T(1), z.get(), T(rz_new / rz), p.get());
+      rz = rz_new;
+    }
+    R.pcg_iters_total += its;
+    // Armijo line search on the objective
+    const double gd = dot_internal(g.get(), x.get());
+    double eps = 1.0;
+    bool accepted = false;
+    double Et = E;
+    for (int bt = 0; bt <= 10; ++bt) {
+      axpby_internal(vt.get(), T(1), v.get(), T(eps), x.get());
+      set_velocity_internal(vt.get());
+      state_internal(e);
+      Et = e[0];
+      if (Et <= E + 1e-4 * eps * gd) {
+        accepted = true;
+        break;
+      }
+      ++R.backtracks;
+      eps *= 0.5;
+    }
+    if (!accepted) {
+      set_velocity_internal(v.get());
+      state_internal(e);
+      status = LDDMM_BL_W_LINESEARCH;
+      break;
+    }
+    copy_internal(v.get(), vt.get());
+    E = Et;
+    adjoint_internal(g.get());
+    ginf = grad_inf_internal(g.get());
+    R.gn_iters = k + 1;
+  }
+  if (status == LDDMM_BL_OK && !fixed && k == o.max_gn && ginf > o.grad_rtol * ref) status = LDDMM_BL_W_MAXITER;
+  internal_to_user(static_cast<T*>(v_user), v.get());
+  R.E = E;
+  R.grad_inf_rel = ref > 0 ? ginf / ref : 0.0;
+  R.mse_rel = mse_rel();
+  synchronize();
+  R.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (rep) *rep = R;
+  return status;
+}
+
+std::unique_ptr<SolverBase> make_solver(const lddmm_bl_params& p, hipStream_t s) {
+  if (p.precision == LDDMM_BL_FP64) return std::make_unique<Solver<double>>(p, s);
+  if (p.precision == LDDMM_BL_FP32) return std::make_unique<Solver<float>>(p, s);
+  throw ArgError("unsupported precision");
+}
+
+}  // namespace lddmm

@@ -1,0 +1,260 @@
+"""Python binding of the gfx950 band-limited PDE-LDDMM library (ctypes).
+
+Argument marshalling only: every step of the method runs in the HIP library
+(liblddmm_bl.so, C ABI in include/lddmm_bl.h).  PyTorch provides device
+memory and the stream; tensors must live on a ROCm device, be contiguous and
+have the context's element type (float64 for FP64, float32 otherwise).
+Loading fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence, Tuple
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblddmm_bl.so")
+
+IMAGE_TRANSPORT = 1
+DEFORMATION_STATE = 3
+FP64, FP32, BF16_DFT = 0, 1, 2
+
+FIELD_VELOCITY, FIELD_DEP_BACKWARD, FIELD_DEP_FORWARD, FIELD_DIV_V = 0, 1, 2, 3
+FIELD_STATE, FIELD_M1, FIELD_ADJOINT0, FIELD_INC_STATE, FIELD_INC_ADJOINT = 4, 5, 6, 7, 8
+
+STATUS = {
+    0: "OK", -1: "E_ARG", -2: "E_OOM", -3: "E_HIP", -4: "E_NONFINITE", -5: "E_STATE",
+    1: "W_MAXITER", 2: "W_LINESEARCH", 3: "W_NEGCURV",
+}
+
+EXPORTS = [
+    "lddmm_bl_create", "lddmm_bl_destroy", "lddmm_bl_last_error", "lddmm_bl_set_images",
+    "lddmm_bl_state_solve", "lddmm_bl_adjoint_solve", "lddmm_bl_hess_matvec", "lddmm_bl_gn_solve",
+    "lddmm_bl_jacobian", "lddmm_bl_project", "lddmm_bl_include", "lddmm_bl_get_field", "lddmm_bl_dot",
+]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int32), ("n", ctypes.c_int32 * 3), ("k", ctypes.c_int32 * 3),
+        ("nt", ctypes.c_int32), ("variant", ctypes.c_int32), ("alpha", ctypes.c_double),
+        ("s", ctypes.c_int32), ("sigma2", ctypes.c_double), ("precision", ctypes.c_int32),
+    ]
+
+
+class GNOpts(ctypes.Structure):
+    _fields_ = [
+        ("max_gn", ctypes.c_int32), ("max_pcg", ctypes.c_int32), ("grad_rtol", ctypes.c_double),
+        ("grad_ref_inf", ctypes.c_double), ("fixed_iters", ctypes.c_int32),
+    ]
+
+
+class GNReport(ctypes.Structure):
+    _fields_ = [
+        ("gn_iters", ctypes.c_int32), ("pcg_iters_total", ctypes.c_int32), ("backtracks", ctypes.c_int32),
+        ("hess_matvecs", ctypes.c_int32), ("E0", ctypes.c_double), ("E", ctypes.c_double),
+        ("mse_rel", ctypes.c_double), ("grad_inf_rel", ctypes.c_double), ("seconds", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load liblddmm_bl.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library not built: {path} is missing (run python -m paper_2006_06823_amd.build)")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)
+    sig = {
+        "lddmm_bl_create": [ctypes.POINTER(Params), vp, ctypes.POINTER(vp)],
+        "lddmm_bl_destroy": [vp],
+        "lddmm_bl_set_images": [vp, vp, vp],
+        "lddmm_bl_state_solve": [vp, vp, vp, dp],
+        "lddmm_bl_adjoint_solve": [vp, vp, dp],
+        "lddmm_bl_hess_matvec": [vp, vp, vp],
+        "lddmm_bl_gn_solve": [vp, ctypes.POINTER(GNOpts), vp, vp, i32, ctypes.POINTER(GNReport)],
+        "lddmm_bl_jacobian": [vp, vp, dp],
+        "lddmm_bl_project": [vp, vp, vp, i32],
+        "lddmm_bl_include": [vp, vp, vp, i32],
+        "lddmm_bl_get_field": [vp, i32, i32, vp, ctypes.POINTER(i64)],
+        "lddmm_bl_dot": [vp, vp, vp, i64, dp],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.lddmm_bl_last_error.argtypes = [vp]
+    lib.lddmm_bl_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+class LddmmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+@dataclass
+class Problem:
+    """Problem description; n and k are per-axis grid and band sizes (d = len(n))."""
+    n: Sequence[int]
+    k: Sequence[int]
+    nt: int = 10
+    variant: int = IMAGE_TRANSPORT
+    alpha: float = 0.0025
+    s: int = 2
+    sigma2: float = 1.0
+    precision: int = FP32
+
+
+class Context:
+    """One registration problem on the current ROCm device and stream."""
+
+    def __init__(self, prob: Problem, device: Optional[torch.device] = None, stream=None):
+        self.lib = load_library()
+        self.prob = prob
+        self.dim = len(prob.n)
+        self.n = tuple(int(x) for x in prob.n)
+        self.k = tuple(int(x) for x in prob.k)
+        self.dtype = torch.float64 if prob.precision == FP64 else torch.float32
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        p = Params()
+        p.dim = self.dim
+        for j in range(3):
+            p.n[j] = self.n[j] if j < self.dim else 1
+            p.k[j] = self.k[j] if j < self.dim else 1
+        p.nt, p.variant, p.alpha, p.s, p.sigma2, p.precision = (
+            prob.nt, prob.variant, prob.alpha, prob.s, prob.sigma2, prob.precision)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            st = self.lib.lddmm_bl_create(ctypes.byref(p), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if st != 0:
+            raise LddmmError(st, "lddmm_bl_create failed")
+        self.h = h
+
+    # -- helpers -----------------------------------------------------------
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.lddmm_bl_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st, allow_warn=False):
+        if st < 0 or (st > 0 and not allow_warn):
+            raise LddmmError(st, self.lib.lddmm_bl_last_error(self.h).decode())
+        return st
+
+    def _grid_shape(self, ncomp=None):
+        return self.n if ncomp is None else (ncomp,) + self.n
+
+    def _bl_shape(self, ncomp=None):
+        return self.k if ncomp is None else (ncomp,) + self.k
+
+    def _arg(self, t: torch.Tensor, shape, name):
+        if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+            raise TypeError(f"{name} must be a ROCm device tensor")
+        if t.dtype != self.dtype:
+            raise TypeError(f"{name} must be {self.dtype}")
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        return t
+
+    def empty_grid(self, ncomp=None):
+        return torch.empty(self._grid_shape(ncomp), dtype=self.dtype, device=self.device)
+
+    def empty_bl(self, ncomp=None):
+        return torch.empty(self._bl_shape(ncomp), dtype=self.dtype, device=self.device)
+
+    # -- C ABI calls -----------------------------------------------------------
+    def set_images(self, I0: torch.Tensor, I1: torch.Tensor):
+        self._arg(I0, self.n, "I0")
+        self._arg(I1, self.n, "I1")
+        self._check(self.lib.lddmm_bl_set_images(self.h, _ptr(I0), _ptr(I1)))
+
+    def state_solve(self, v: torch.Tensor, want_m1: bool = False) -> Tuple[Tuple[float, float, float], Optional[torch.Tensor]]:
+        self._arg(v, self._bl_shape(self.dim), "v")
+        m1 = self.empty_grid() if want_m1 else None
+        E = (ctypes.c_double * 3)()
+        self._check(self.lib.lddmm_bl_state_solve(self.h, _ptr(v), _ptr(m1), E))
+        return (E[0], E[1], E[2]), m1
+
+    def adjoint_solve(self) -> Tuple[torch.Tensor, float]:
+        g = self.empty_bl(self.dim)
+        ginf = ctypes.c_double()
+        self._check(self.lib.lddmm_bl_adjoint_solve(self.h, _ptr(g), ctypes.byref(ginf)))
+        return g, ginf.value
+
+    def hess_matvec(self, dv: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        self._arg(dv, self._bl_shape(self.dim), "dv")
+        out = self.empty_bl(self.dim) if out is None else self._arg(out, self._bl_shape(self.dim), "out")
+        self._check(self.lib.lddmm_bl_hess_matvec(self.h, _ptr(dv), _ptr(out)))
+        return out
+
+    def gn_solve(self, v: torch.Tensor, max_gn=10, max_pcg=5, grad_rtol=1e-3, grad_ref_inf=0.0,
+                 fixed_iters=False, Z: Optional[torch.Tensor] = None):
+        """Gauss-Newton-Krylov in place on v; returns (status, report dict)."""
+        self._arg(v, self._bl_shape(self.dim), "v")
+        o = GNOpts(max_gn, max_pcg, grad_rtol, grad_ref_inf, 1 if fixed_iters else 0)
+        rep = GNReport()
+        r = 0
+        if Z is not None:
+            r = Z.shape[0]
+            self._arg(Z, (r, self.dim) + self.k, "Z")
+        st = self.lib.lddmm_bl_gn_solve(self.h, ctypes.byref(o), _ptr(v), _ptr(Z), r, ctypes.byref(rep))
+        self._check(st, allow_warn=True)
+        return st, rep.as_dict()
+
+    def jacobian(self, want_map: bool = False):
+        det = torch.empty(self.n, dtype=torch.float64, device=self.device) if want_map else None
+        mm = (ctypes.c_double * 2)()
+        self._check(self.lib.lddmm_bl_jacobian(self.h, _ptr(det), mm))
+        return (mm[0], mm[1]), det
+
+    def project(self, grid: torch.Tensor, ncomp: int = 1) -> torch.Tensor:
+        self._arg(grid, self._grid_shape(ncomp if ncomp > 1 else None), "grid")
+        out = self.empty_bl(ncomp if ncomp > 1 else None)
+        self._check(self.lib.lddmm_bl_project(self.h, _ptr(grid), _ptr(out), ncomp))
+        return out
+
+    def include(self, bl: torch.Tensor, ncomp: int = 1) -> torch.Tensor:
+        self._arg(bl, self._bl_shape(ncomp if ncomp > 1 else None), "bl")
+        out = self.empty_grid(ncomp if ncomp > 1 else None)
+        self._check(self.lib.lddmm_bl_include(self.h, _ptr(bl), _ptr(out), ncomp))
+        return out
+
+    def get_field(self, which: int, index: int = 0) -> torch.Tensor:
+        cnt = ctypes.c_int64()
+        self._check(self.lib.lddmm_bl_get_field(self.h, which, index, None, ctypes.byref(cnt)))
+        out = torch.empty(cnt.value, dtype=self.dtype, device=self.device)
+        self._check(self.lib.lddmm_bl_get_field(self.h, which, index, _ptr(out), ctypes.byref(cnt)))
+        return out
+
+    def dot(self, a: torch.Tensor, b: torch.Tensor) -> float:
+        if a.numel() != b.numel() or a.dtype != self.dtype or b.dtype != self.dtype:
+            raise ValueError("dot: size or dtype mismatch")
+        r = ctypes.c_double()
+        self._check(self.lib.lddmm_bl_dot(self.h, _ptr(a), _ptr(b), a.numel(), ctypes.byref(r)))
+        return r.value

@@ -1,0 +1,44 @@
+"""Shared set-up of the GPU parity tests: seeded inputs fed to both the HIP library and the oracle."""
+import numpy as np
+import torch
+
+from oracle import spectral as sp
+from oracle.problem import Problem as OProblem
+from oracle.variant1 import Variant1
+from oracle.variant3 import Variant3
+from paper_2006_06823_amd import synthetic as syn
+
+
+def rel_l2(a, b):
+    a = torch.as_tensor(a).double().cpu().reshape(-1)
+    b = torch.as_tensor(b).double().cpu().reshape(-1)
+    return float((a - b).norm() / b.norm().clamp_min(1e-300))
+
+
+def images(N, seed):
+    """Source/target pair: 2D Gaussian blobs or 3D brain-like phantom (float64 arrays)."""
+    if len(N) == 2:
+        if N[0] == N[1]:
+            I0, I1 = syn.blob_pair_2d(N[0], seed, max_disp_vox=N[0] / 16)
+        else:
+            n = max(N)
+            I0, I1 = syn.blob_pair_2d(n, seed, max_disp_vox=n / 16)
+            I0, I1 = I0[:N[0], :N[1]], I1[:N[0], :N[1]]
+        return np.ascontiguousarray(I0), np.ascontiguousarray(I1)
+    I0, I1 = syn.phantom_pair_3d(tuple(N), seed, max_disp_vox=min(N) / 16)
+    return I0.astype(np.float64), I1.astype(np.float64)
+
+
+def velocity(N, K, Nt, seed, cfl_vox=0.8):
+    """Random BL velocity scaled so that max_x |v_j| dt N_j = cfl_vox voxels per step (oracle iota)."""
+    d = len(N)
+    v = torch.tensor(syn.random_bl_coefficients(d, K, seed))
+    vg = sp.include(v, N)
+    scale = torch.tensor([float(n) for n in N], dtype=torch.float64).reshape((-1,) + (1,) * d)
+    vmax = float((vg * scale).abs().max()) / Nt
+    return (v * (cfl_vox / vmax)).numpy()
+
+
+def oracle_model(variant, N, K, Nt, I0, I1):
+    prob = OProblem(tuple(N), tuple(K), Nt=Nt)
+    return (Variant1 if variant == 1 else Variant3)(prob, I0, I1)

@@ -1,0 +1,129 @@
+"""GPU-vs-oracle parity of the HIP library, called through its C ABI.
+
+Tolerances: FP32 truncated DFT rel-L2 <= 1e-6; FP32 trajectories, gradients
+and Hessian-vector products rel-L2 <= 1e-5; FP64 (the 2D configuration)
+<= 1e-10.  Sizes span several 32-wide tiles with ragged tails.
+"""
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import images, oracle_model, rel_l2, velocity
+from oracle import spectral as sp
+from paper_2006_06823_amd import lddmm_bl as L
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    # (dim, N, K, Nt, precision)
+    (3, (40, 36, 44), (12, 10, 14), 4, L.FP32),
+    (2, (64, 64), (16, 16), 10, L.FP64),
+    (2, (48, 40), (14, 12), 5, L.FP32),
+]
+
+
+def tol(precision, kind="traj"):
+    if precision == L.FP64:
+        return 1e-10
+    return 1e-6 if kind == "dft" else 1e-5
+
+
+def dev(x, ctx):
+    return torch.tensor(np.ascontiguousarray(x), dtype=ctx.dtype, device=ctx.device)
+
+
+def make(variant, dim, N, K, Nt, precision, seed=0):
+    I0, I1 = images(N, seed)
+    ctx = L.Context(L.Problem(N, K, nt=Nt, variant=variant, precision=precision))
+    ctx.set_images(dev(I0, ctx), dev(I1, ctx))
+    v = velocity(N, K, Nt, seed + 1)
+    om = oracle_model(variant, N, K, Nt, I0, I1)
+    return ctx, om, v
+
+
+@pytest.mark.parametrize("dim,N,K,Nt,precision", CASES)
+def test_truncated_dft_parity(dim, N, K, Nt, precision):
+    ctx = L.Context(L.Problem(N, K, nt=Nt, precision=precision))
+    rng = np.random.default_rng(5)
+    for nf in (1, 3, 7):
+        f = rng.standard_normal((nf,) + tuple(N))
+        got = ctx.project(dev(f, ctx).reshape((nf,) + tuple(N)) if nf > 1 else dev(f[0], ctx), nf)
+        ref = sp.project(torch.tensor(f), K)
+        assert rel_l2(got.reshape(ref.shape), ref) <= tol(precision, "dft")
+        c = np.stack([np.random.default_rng(s).standard_normal(K) for s in range(nf)])
+        for j, k in enumerate(K):
+            sl = [slice(None)] * (dim + 1)
+            sl[j + 1] = k - 1
+            c[tuple(sl)] = 0.0
+        got = ctx.include(dev(c, ctx) if nf > 1 else dev(c[0], ctx), nf)
+        ref = sp.include(torch.tensor(c), N)
+        assert rel_l2(got.reshape(ref.shape), ref) <= tol(precision, "dft")
+
+
+@pytest.mark.parametrize("variant", [1, 3])
+@pytest.mark.parametrize("dim,N,K,Nt,precision", CASES)
+def test_state_adjoint_gradient_parity(variant, dim, N, K, Nt, precision):
+    ctx, om, v = make(variant, dim, N, K, Nt, precision)
+    E, m1 = ctx.state_solve(dev(v, ctx), want_m1=True)
+    om.setup(v)
+    om.state()
+    Eo = [float(x) for x in om.objective()]
+    # characteristics and divergence
+    assert rel_l2(ctx.get_field(L.FIELD_DEP_BACKWARD).reshape(om.Xb.shape), om.Xb) <= tol(precision)
+    assert rel_l2(ctx.get_field(L.FIELD_DEP_FORWARD).reshape(om.Xf.shape), om.Xf) <= tol(precision)
+    assert rel_l2(ctx.get_field(L.FIELD_DIV_V).reshape(om.divv.shape), om.divv) <= tol(precision)
+    # state trajectory
+    if variant == 1:
+        for n in range(Nt + 1):
+            assert rel_l2(ctx.get_field(L.FIELD_STATE, n).reshape(om.m[n].shape), om.m[n]) <= tol(precision)
+        m1o = om.m[-1]
+    else:
+        for n in range(1, Nt + 1):
+            assert rel_l2(ctx.get_field(L.FIELD_STATE, n).reshape(om.u[n].shape), om.u[n]) <= tol(precision)
+        m1o = om.m1
+    assert rel_l2(m1, m1o) <= tol(precision)
+    for a, b in zip(E, Eo):
+        assert abs(a - b) <= tol(precision) * abs(b) * 10
+    # adjoint and gradient
+    g, ginf = ctx.adjoint_solve()
+    om.adjoint()
+    go = om.gradient()
+    if variant == 1:
+        assert rel_l2(ctx.get_field(L.FIELD_ADJOINT0).reshape(om.lam[0].shape), om.lam[0]) <= tol(precision)
+    else:
+        assert rel_l2(ctx.get_field(L.FIELD_ADJOINT0).reshape(om.rho[0].shape), om.rho[0]) <= tol(precision)
+    assert rel_l2(g, go) <= tol(precision)
+    ginf_o = float(sp.include(go, N).abs().max())
+    assert abs(ginf - ginf_o) <= tol(precision) * ginf_o * 10
+
+
+@pytest.mark.parametrize("variant", [1, 3])
+@pytest.mark.parametrize("dim,N,K,Nt,precision", CASES)
+def test_hess_matvec_parity(variant, dim, N, K, Nt, precision):
+    ctx, om, v = make(variant, dim, N, K, Nt, precision)
+    ctx.state_solve(dev(v, ctx))
+    om.setup(v)
+    om.state()
+    from paper_2006_06823_amd import synthetic as syn
+    dv = syn.random_bl_coefficients(dim, K, 11)
+    h = ctx.hess_matvec(dev(dv, ctx))
+    ho = om.hess_matvec(dv)
+    assert rel_l2(h, ho) <= tol(precision)
+    dm, dl = om.last_inc
+    for n in (1, Nt // 2, Nt):
+        got = ctx.get_field(L.FIELD_INC_STATE, n).reshape(dm[n].shape)
+        assert rel_l2(got, dm[n]) <= tol(precision)
+    for n in (0, Nt // 2, Nt):
+        got = ctx.get_field(L.FIELD_INC_ADJOINT, n).reshape(dl[n].shape)
+        assert rel_l2(got, dl[n]) <= tol(precision)
+
+
+def test_dot_fp64_reduction():
+    """Device FP64 reductions over FP32 data equal the sum computed in double on the host (1e-12)."""
+    ctx = L.Context(L.Problem((32, 32, 32), (8, 8, 8), precision=L.FP32))
+    rng = np.random.default_rng(3)
+    a = rng.standard_normal(1_000_003).astype(np.float32)
+    b = rng.standard_normal(1_000_003).astype(np.float32)
+    got = ctx.dot(torch.tensor(a, device="cuda"), torch.tensor(b, device="cuda"))
+    ref = float(np.dot(a.astype(np.float64), b.astype(np.float64)))
+    assert abs(got - ref) <= 1e-12 * np.sqrt(len(a)) * max(1.0, abs(ref))
