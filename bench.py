@@ -1,0 +1,189 @@
+#!/usr/bin/env python
+"""Benchmark: Gauss-Newton Hessian-vector products per second on one MI355X.
+
+Workload (default): the image-transport variant of band-limited PDE-LDDMM
+(original BL PDE-LDDMM, Section 2.3.1 of the paper) on a 128^3 grid with a
+32^3 x 3 band-limited velocity, Nt = 10 SL-RK2 steps, alpha = 0.0025, s = 2,
+sigma^2 = 1, FP32 fields with FP64 reductions.  One step = one full Hessian
+matvec (incremental state sweep, t = 1 coupling, incremental adjoint sweep
+with the Hessian time integral, L~ term), after a state solve at a fixed
+velocity (not timed).  Inputs are synthetic: a brain-like phantom pair and a
+random band-limited velocity of 8 voxels maximum displacement per unit time,
+resident on the GPU before timing starts.
+
+Prints one JSON line with the throughput, the roofline figures of the
+dominant kernel (per-launch algorithmic bytes over its event-timed average
+duration) and the CPU oracle timed on the host as a baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
+FP32_PEAK_TFLOPS = 157.3     # MI355X dense FP32 (matrix and vector)
+
+# variant-1 Hessian matvec kernels that move data (HBM roofline); DFT kernels also report MFMA use
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_dominant_kernel.json")
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--variant", type=int, default=1, choices=(1, 3))
+    ap.add_argument("--size", type=int, nargs=3, default=(128, 128, 128))
+    ap.add_argument("--band", type=int, nargs=3, default=(32, 32, 32))
+    ap.add_argument("--nt", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported (the build targets a single "
+              f"MI355X; see DESIGN.md for how the path would shard).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2006_06823_amd import lddmm_bl as L
+    from paper_2006_06823_amd import synthetic as syn
+
+    N, K, Nt = tuple(args.size), tuple(args.band), args.nt
+    variant = L.IMAGE_TRANSPORT if args.variant == 1 else L.DEFORMATION_STATE
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+
+    I0, I1 = syn.phantom_pair_3d(N, seed=1, max_disp_vox=8.0)
+    ctx = L.Context(L.Problem(N, K, nt=Nt, variant=variant, precision=L.FP32))
+    g = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device=dev)
+    ctx.set_images(g(I0), g(I1))
+    # random band-limited velocity scaled to 8 voxels maximum displacement per unit time
+    vc = syn.random_bl_coefficients(3, K, seed=2)
+    vg = ctx.include(g(vc), 3).double()
+    scale = torch.tensor([float(n) for n in N], dtype=torch.float64, device=dev).reshape(3, 1, 1, 1)
+    vmax = float((vg * scale).abs().max())
+    v = g(vc * (8.0 / vmax))
+    dv = g(syn.random_bl_coefficients(3, K, seed=3))
+    E, _ = ctx.state_solve(v)
+    out = torch.empty_like(dv)
+    stream = torch.cuda.current_stream(dev)
+
+    for _ in range(args.warmup):
+        ctx.hess_matvec(dv, out)
+    torch.cuda.synchronize()
+
+    # timed region: K matvecs
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t_start.record(stream)
+    for _ in range(args.steps):
+        ctx.hess_matvec(dv, out)
+    t_stop.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms_total = t_start.elapsed_time(t_stop)
+    ms_per_step = ms_total / args.steps
+    value = 1000.0 / ms_per_step
+
+    # same region again with per-kernel HIP events inside the library (roofline of the dominant kernel)
+    L.profile_enable(True)
+    for _ in range(args.steps):
+        ctx.hess_matvec(dv, out)
+    torch.cuda.synchronize()
+    stats = L.profile_read()
+    L.profile_enable(False)
+    dom_name, dom = max(stats.items(), key=lambda kv: kv[1]["ms"])
+    kernel_ms = sum(s["ms"] for s in stats.values())
+    avg_ms = dom["ms"] / dom["count"]
+    bytes_per_launch = dom["bytes"] / dom["count"]
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        try:
+            tr = json.load(open(TRAFFIC_FILE))
+            if tr.get("kernel") == dom_name and tr.get("workload") == list(N) + list(K):
+                traffic = tr.get("bytes_per_launch")
+        except Exception:
+            traffic = None
+    roofline = {
+        "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+        "kernel": dom_name, "launches_per_step": dom["count"] / args.steps,
+        "avg_launch_us": round(avg_ms * 1e3, 2), "algorithmic_bytes_per_launch": bytes_per_launch,
+    }
+    dft = [s for n, s in stats.items() if n.startswith("dft_")]
+    dft_flops = sum(s["flops"] for s in dft)
+    dft_ms = sum(s["ms"] for s in dft)
+    kernels = {n: {"launches_per_step": s["count"] / args.steps, "ms_per_step": round(s["ms"] / args.steps, 4),
+                   "GBps": round(s["bytes"] / (s["ms"] * 1e-3) / 1e9, 1) if s["ms"] > 0 else None}
+               for n, s in sorted(stats.items(), key=lambda kv: -kv[1]["ms"])}
+
+    # extra timings of the other solves at this velocity (not the metric)
+    t0 = time.perf_counter()
+    ctx.state_solve(v)
+    state_ms = (time.perf_counter() - t0) * 1e3
+    t0 = time.perf_counter()
+    ctx.adjoint_solve()
+    adjoint_ms = (time.perf_counter() - t0) * 1e3
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(variant, N, K, Nt, I0, I1, (vc * (8.0 / vmax)), syn.random_bl_coefficients(3, K, seed=3))
+
+    line = {
+        "metric": "Hessian-matvecs/s at 128^3" if N == (128, 128, 128) else f"Hessian-matvecs/s at {N}",
+        "value": round(value, 2), "unit": "matvec/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{'image-transport' if args.variant == 1 else 'deformation-state'} BL PDE-LDDMM "
+                               f"Gauss-Newton Hessian matvec, grid {N[0]}x{N[1]}x{N[2]}, band {K[0]}x{K[1]}x{K[2]}x3, "
+                               f"Nt={Nt}, SL-RK2, FP32 with FP64 reductions",
+                   "grid": list(N), "band": list(K), "nt": Nt, "variant": args.variant,
+                   "alpha": 0.0025, "s": 2, "sigma2": 1.0},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "extra": {"wall_s_timed": round(wall, 4), "kernel_ms_per_step": round(kernel_ms / args.steps, 4),
+                  "dft_mfma_tflops": round(dft_flops / (dft_ms * 1e-3) / 1e12, 2) if dft_ms > 0 else None,
+                  "dft_mfma_frac_fp32": round(dft_flops / (dft_ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 4)
+                  if dft_ms > 0 else None,
+                  "state_solve_ms": round(state_ms, 3), "adjoint_solve_ms": round(adjoint_ms, 3),
+                  "objective": E, "kernels": kernels},
+    }
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline(variant, N, K, Nt, I0, I1, v, dv):
+    """The FP64 CPU oracle on the host cores: one full Hessian matvec at the same workload."""
+    import numpy as np
+    import torch
+
+    from oracle.problem import Problem as OP
+    from oracle.variant1 import Variant1
+    from oracle.variant3 import Variant3
+
+    model = (Variant1 if variant == 1 else Variant3)(OP(N, K, Nt=Nt), I0.astype(np.float64), I1.astype(np.float64))
+    model.setup(v)
+    model.state()
+    t0 = time.perf_counter()
+    model.hess_matvec(dv)
+    dt = time.perf_counter() - t0
+    return {"value": round(1.0 / dt, 5), "unit": "matvec/s", "cores": torch.get_num_threads(), "kind": "oracle",
+            "sample": f"one full Hessian matvec of the same workload in the FP64 oracle (torch CPU), "
+                      f"{dt:.1f} s; set-up and state solve excluded"}
+
+
+if __name__ == "__main__":
+    main()

@@ -174,6 +174,16 @@ lddmm_bl_status lddmm_bl_get_field(lddmm_bl_ctx* ctx, int32_t which, int32_t ind
  * dot = sum a_i b_i over n elements of the context's element type. */
 lddmm_bl_status lddmm_bl_dot(lddmm_bl_ctx* ctx, const void* a, const void* b, int64_t n, double* dot);
 
+/* Per-kernel timing for measurement tools (process-wide).  While enabled,
+ * every kernel launch of the library is bracketed with HIP events on its
+ * stream and its algorithmic bytes and flops are recorded (enabling clears
+ * old records).  lddmm_bl_profile_read(NULL, 0) collects the records into a
+ * text table, one line per kernel: name, launches, total ms, algorithmic
+ * bytes, flops (tab separated), and returns the buffer size it needs;
+ * lddmm_bl_profile_read(buf, len) then copies the table into buf. */
+lddmm_bl_status lddmm_bl_profile_enable(int32_t on);
+int64_t lddmm_bl_profile_read(char* buf, int64_t len);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,10 +1,12 @@
 // extern "C" entry points of the library (declared in include/lddmm_bl.h).
 // Every call catches its own exceptions and turns them into status codes; the
 // text of the last error is kept per context.
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <string>
 
+#include "prof.h"
 #include "solver.h"
 
 struct lddmm_bl_ctx {
@@ -157,6 +159,28 @@ lddmm_bl_status lddmm_bl_dot(lddmm_bl_ctx* ctx, const void* a, const void* b, in
     *dot = ctx->solver->dot(a, b, n);
     return 0;
   });
+}
+
+lddmm_bl_status lddmm_bl_profile_enable(int32_t on) {
+  try {
+    if (on) lddmm::prof::collect();  // drop stale records
+    lddmm::prof::set_enabled(on != 0);
+  } catch (...) {
+    return LDDMM_BL_E_HIP;
+  }
+  return LDDMM_BL_OK;
+}
+
+int64_t lddmm_bl_profile_read(char* buf, int64_t len) {
+  static std::string last;
+  if (buf == nullptr || len <= 0) {
+    last = lddmm::prof::collect();
+    return static_cast<int64_t>(last.size()) + 1;
+  }
+  const int64_t n = std::min<int64_t>(len - 1, static_cast<int64_t>(last.size()));
+  std::memcpy(buf, last.data(), n);
+  buf[n] = 0;
+  return n + 1;
 }
 
 }  // extern "C"

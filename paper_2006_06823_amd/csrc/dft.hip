@@ -9,6 +9,7 @@
 // wave owns a 32 x 32 output block); in double the same tiling runs on the
 // vector FMA units.  Tiles of W and of the input are staged through LDS.
 #include "kernels.h"
+#include "prof.h"
 
 namespace lddmm {
 
@@ -165,6 +166,10 @@ void dft_left(const T* in, T* out, const FieldMats<T>& W, int nb, int bpf, int M
               int64_t sOb, hipStream_t s) {
   if (nb <= 0 || M <= 0 || C <= 0) return;
   if (nb > 65535) throw ArgError("dft_left: batch too large");
+  const int wm = M > 64 ? 4 : (M > 32 ? 2 : 1);
+  prof::Scope ps_(s, std::string("dft_left_kernel<") + prof::tname<T>() + "," + std::to_string(wm) + "," +
+                         std::to_string(4 / wm) + ">",
+                  double(sizeof(T)) * ((double)nb * L * C + (double)nb * M * C), 2.0 * nb * M * (double)L * C);
   if (M > 64) {
     dim3 g(ceil_div(C, 32), ceil_div(M, 128), nb);
     dft_left_kernel<T, 4, 1><<<g, 256, 0, s>>>(in, out, W, bpf, M, L, C, sIb, sOb);
@@ -181,6 +186,10 @@ void dft_left(const T* in, T* out, const FieldMats<T>& W, int nb, int bpf, int M
 template <typename T>
 void dft_right(const T* in, T* out, const FieldMats<T>& W, int nf, int R, int L, int Mo, hipStream_t s) {
   if (nf <= 0 || R <= 0 || Mo <= 0) return;
+  const int wm = Mo > 64 ? 4 : (Mo > 32 ? 2 : 1);
+  prof::Scope ps_(s, std::string("dft_right_kernel<") + prof::tname<T>() + "," + std::to_string(4 / wm) + "," +
+                         std::to_string(wm) + ">",
+                  double(sizeof(T)) * ((double)nf * R * L + (double)nf * R * Mo), 2.0 * nf * R * (double)L * Mo);
   if (Mo > 64) {
     dim3 g(ceil_div(Mo, 128), ceil_div(R, 32), nf);
     dft_right_kernel<T, 1, 4><<<g, 256, 0, s>>>(in, out, W, R, L, Mo);

@@ -6,6 +6,7 @@
 // Every grid kernel maps one thread to one node; fields are component-major
 // [c][n0][n1][n2], n2 contiguous, so neighbouring lanes touch neighbouring nodes.
 #include "kernels.h"
+#include "prof.h"
 
 namespace lddmm {
 
@@ -467,12 +468,14 @@ void bl_div(T* out, const T* v, const Dims& d, hipStream_t s) {
 
 template <typename T>
 void characteristics(T* disp, const T* v, const T* cv, const Dims& d, T dt, int dir, hipStream_t s) {
+  prof::Scope ps_(s, "k_characteristics<" + std::string(prof::tname<T>()) + ">", 9.0 * d.P * sizeof(T), 0.0);
   k_characteristics<T><<<grid_for(d.P), kBlock, 0, s>>>(disp, v, cv, d.n[0], d.n[1], d.n[2], dt, dir);
   LDDMM_LAUNCH_CHECK();
 }
 
 template <typename T>
 void interp(T* out, const T* coef, int nf, const T* disp, const Dims& d, hipStream_t s) {
+  prof::Scope ps_(s, "k_interp<" + std::string(prof::tname<T>()) + "," + std::to_string(nf) + ">", (3.0 + 2.0 * nf) * d.P * sizeof(T), 0.0);
   switch (nf) {
     case 1:
       k_interp<T, 1><<<grid_for(d.P), kBlock, 0, s>>>(out, coef, disp, d.n[0], d.n[1], d.n[2]);
@@ -491,6 +494,7 @@ void interp(T* out, const T* coef, int nf, const T* disp, const Dims& d, hipStre
 
 template <typename T>
 void prefilter(T* f, int nf, const Dims& d, hipStream_t s) {
+  prof::Scope ps_(s, "prefilter<" + std::string(prof::tname<T>()) + ">", 6.0 * nf * d.P * sizeof(T), 0.0);
   const int n0 = d.n[0], n1 = d.n[1], n2 = d.n[2];
   if (n2 > 1) {
     const int64_t rows = (int64_t)nf * n0 * n1;
@@ -516,6 +520,7 @@ void prefilter(T* f, int nf, const Dims& d, hipStream_t s) {
 template <typename T>
 void adjoint_grid_step(T* out, const T* c1, const T* c2, const T* disp, const T* divv, const Dims& d, T dt,
                        hipStream_t s) {
+  prof::Scope ps_(s, "k_adjoint_grid_step<" + std::string(prof::tname<T>()) + ">", 7.0 * d.P * sizeof(T), 0.0);
   k_adjoint_grid_step<T><<<grid_for(d.P), kBlock, 0, s>>>(out, c1, c2, disp, divv, d.n[0], d.n[1], d.n[2], dt);
   LDDMM_LAUNCH_CHECK();
 }
@@ -523,6 +528,7 @@ void adjoint_grid_step(T* out, const T* c1, const T* c2, const T* disp, const T*
 template <typename T>
 void bl_adjoint_step(T* out, const T* cA, const T* cB, int nf, const T* disp, const T* divv, const Dims& d, T dt,
                      hipStream_t s) {
+  prof::Scope ps_(s, "k_bl_adjoint_step<" + std::string(prof::tname<T>()) + "," + std::to_string(nf) + ">", (4.0 + 3.0 * nf) * d.P * sizeof(T), 0.0);
   if (nf == 1)
     k_bl_adjoint_step<T, 1><<<grid_for(d.P), kBlock, 0, s>>>(out, cA, cB, disp, divv, d.n[0], d.n[1], d.n[2], dt);
   else if (nf == 3)
@@ -534,42 +540,49 @@ void bl_adjoint_step(T* out, const T* cA, const T* cB, int nf, const T* disp, co
 
 template <typename T>
 void inc_state_v1(T* out, const T* c, const T* disp, const T* G, const T* dv, const Dims& d, hipStream_t s) {
+  prof::Scope ps_(s, "k_inc_state_v1<" + std::string(prof::tname<T>()) + ">", 12.0 * d.P * sizeof(T), 0.0);
   k_inc_state_v1<T><<<grid_for(d.P), kBlock, 0, s>>>(out, c, disp, G, dv, d.n[0], d.n[1], d.n[2]);
   LDDMM_LAUNCH_CHECK();
 }
 
 template <typename T>
 void inc_state_v3(T* out, const T* c, const T* disp, const T* Du, const T* dv, const Dims& d, hipStream_t s) {
+  prof::Scope ps_(s, "k_inc_state_v3<" + std::string(prof::tname<T>()) + ">", 24.0 * d.P * sizeof(T), 0.0);
   k_inc_state_v3<T><<<grid_for(d.P), kBlock, 0, s>>>(out, c, disp, Du, dv, d.n[0], d.n[1], d.n[2]);
   LDDMM_LAUNCH_CHECK();
 }
 
 template <typename T>
 void v3_source(T* out, const T* Du, const T* dv, const Dims& d, hipStream_t s) {
+  prof::Scope ps_(s, "k_v3_source<" + std::string(prof::tname<T>()) + ">", 15.0 * d.P * sizeof(T), 0.0);
   k_v3_source<T><<<grid_for(d.P), kBlock, 0, s>>>(out, Du, dv, d.P);
   LDDMM_LAUNCH_CHECK();
 }
 
 template <typename T>
 void v1_source(T* out, const T* G, const T* dv, const Dims& d, hipStream_t s) {
+  prof::Scope ps_(s, "k_v1_source<" + std::string(prof::tname<T>()) + ">", 7.0 * d.P * sizeof(T), 0.0);
   k_v1_source<T><<<grid_for(d.P), kBlock, 0, s>>>(out, G, dv, d.P);
   LDDMM_LAUNCH_CHECK();
 }
 
 template <typename T>
 void v1_products(T* out, const T* e, const T* divv, const T* G, const Dims& d, hipStream_t s) {
+  prof::Scope ps_(s, "k_v1_products<" + std::string(prof::tname<T>()) + ">", 9.0 * d.P * sizeof(T), 0.0);
   k_v1_products<T><<<grid_for(d.P), kBlock, 0, s>>>(out, e, divv, G, d.P);
   LDDMM_LAUNCH_CHECK();
 }
 
 template <typename T>
 void v3_products(T* out, const T* e, const T* divv, const T* Du, const Dims& d, hipStream_t s) {
+  prof::Scope ps_(s, "k_v3_products<" + std::string(prof::tname<T>()) + ">", 19.0 * d.P * sizeof(T), 0.0);
   k_v3_products<T><<<grid_for(d.P), kBlock, 0, s>>>(out, e, divv, Du, d.P);
   LDDMM_LAUNCH_CHECK();
 }
 
 template <typename T>
 void final_warp(T* m1, T* g1, const T* cI0, const T* u, const Dims& d, hipStream_t s) {
+  prof::Scope ps_(s, "k_final_warp<" + std::string(prof::tname<T>()) + ">", 8.0 * d.P * sizeof(T), 0.0);
   k_final_warp<T><<<grid_for(d.P), kBlock, 0, s>>>(m1, g1, cI0, u, d.n[0], d.n[1], d.n[2]);
   LDDMM_LAUNCH_CHECK();
 }

@@ -34,6 +34,7 @@ EXPORTS = [
     "lddmm_bl_create", "lddmm_bl_destroy", "lddmm_bl_last_error", "lddmm_bl_set_images",
     "lddmm_bl_state_solve", "lddmm_bl_adjoint_solve", "lddmm_bl_hess_matvec", "lddmm_bl_gn_solve",
     "lddmm_bl_jacobian", "lddmm_bl_project", "lddmm_bl_include", "lddmm_bl_get_field", "lddmm_bl_dot",
+    "lddmm_bl_profile_enable", "lddmm_bl_profile_read",
 ]
 
 
@@ -93,6 +94,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = ctypes.c_int
+    lib.lddmm_bl_profile_enable.argtypes = [i32]
+    lib.lddmm_bl_profile_enable.restype = ctypes.c_int
+    lib.lddmm_bl_profile_read.argtypes = [ctypes.c_char_p, i64]
+    lib.lddmm_bl_profile_read.restype = i64
     lib.lddmm_bl_last_error.argtypes = [vp]
     lib.lddmm_bl_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -258,3 +263,21 @@ class Context:
         r = ctypes.c_double()
         self._check(self.lib.lddmm_bl_dot(self.h, _ptr(a), _ptr(b), a.numel(), ctypes.byref(r)))
         return r.value
+
+
+def profile_enable(on: bool = True) -> None:
+    """Start (clearing old records) or stop per-kernel event timing in the library."""
+    load_library().lddmm_bl_profile_enable(1 if on else 0)
+
+
+def profile_read():
+    """Collect per-kernel timings: {name: dict(count, ms, bytes, flops)}."""
+    lib = load_library()
+    need = lib.lddmm_bl_profile_read(None, 0)
+    buf = ctypes.create_string_buffer(int(need))
+    lib.lddmm_bl_profile_read(buf, need)
+    out = {}
+    for line in buf.value.decode().splitlines():
+        name, count, ms, nbytes, flops = line.split("\t")
+        out[name] = dict(count=int(count), ms=float(ms), bytes=float(nbytes), flops=float(flops))
+    return out
