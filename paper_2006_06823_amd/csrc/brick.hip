@@ -1,0 +1,371 @@
+// Tricubic B-spline interpolation at SL departure points through LDS bricks
+// (float, 3D grids).
+//
+// A workgroup owns an 8 x 8 x 32 tile of output nodes.  Per coefficient field
+// it stages the tile plus a 2-node halo on every side (12 x 12 x 36 floats,
+// 20.7 KB) into LDS with coalesced, periodically wrapped loads, then evaluates
+// the 64-tap tensor B-spline for each of its nodes from LDS.  A departure
+// point whose 4 x 4 x 4 stencil leaves the brick (displacement of a voxel or
+// more) falls back to a gather from global memory, so any displacement is
+// handled; at the SL step sizes of the configurations (about 0.8 voxel) every
+// stencil lies in the brick.  The epilogue functor consumes the interpolated
+// values of a node together with its other pointwise operands, fusing the
+// SL-RK2 step update of each equation into the same pass.
+#include "kernels.h"
+#include "prof.h"
+
+namespace lddmm {
+
+namespace {
+
+constexpr int TX0 = 8, TX1 = 8, TX2 = 32, HALO = 2;
+constexpr int B0 = TX0 + 2 * HALO, B1 = TX1 + 2 * HALO, B2 = TX2 + 2 * HALO;
+constexpr int VOL = B0 * B1 * B2;
+constexpr int NTHR = 512;
+constexpr int PPT = TX0 * TX1 * TX2 / NTHR;  // nodes per thread
+
+struct Grid3 {
+  int n0, n1, n2;
+  int64_t P;
+};
+
+__device__ __forceinline__ int wrapi(int i, int n) {
+  i %= n;
+  return i < 0 ? i + n : i;
+}
+
+// 64-tap evaluation from the LDS brick; s* are brick-relative first-tap indices
+__device__ __forceinline__ float eval_brick(const float* __restrict__ br, int s0, int s1, int s2, const float w0[4],
+                                            const float w1[4], const float w2[4]) {
+  float acc = 0.f;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    float sa = 0.f;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const float* row = br + ((s0 + a) * B1 + (s1 + b)) * B2 + s2;
+      sa += w1[b] * (w2[0] * row[0] + w2[1] * row[1] + w2[2] * row[2] + w2[3] * row[3]);
+    }
+    acc += w0[a] * sa;
+  }
+  return acc;
+}
+
+__device__ __noinline__ float eval_global(const float* __restrict__ c, float x0, float x1, float x2,
+                                             const Grid3& g) {
+  int i0[4], i1[4], i2[4];
+  float w0[4], w1[4], w2[4];
+  bspline_weights(tap_indices(x0, g.n0, i0), w0);
+  bspline_weights(tap_indices(x1, g.n1, i1), w1);
+  bspline_weights(tap_indices(x2, g.n2, i2), w2);
+  float acc = 0.f;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    float sa = 0.f;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const float* row = c + (static_cast<int64_t>(i0[a]) * g.n1 + i1[b]) * g.n2;
+      sa += w1[b] * (w2[0] * row[i2[0]] + w2[1] * row[i2[1]] + w2[2] * row[i2[2]] + w2[3] * row[i2[3]]);
+    }
+    acc += w0[a] * sa;
+  }
+  return acc;
+}
+
+// Generic brick kernel.  Epi provides:
+//   static constexpr int NF      coefficient fields, stacked with stride P in `coef`;
+//   struct State                 per-node accumulator;
+//   pos(p, i0, i1, i2, x[3])     departure point of node p (grid units);
+//   init(p, State&)              loads the node's pointwise operands;
+//   accum(State&, f, value)      folds the interpolated value of field f in;
+//   emit(p, const State&)        writes the node's results.
+template <class Epi>
+__global__ __launch_bounds__(NTHR) void k_brick(Epi epi, const float* __restrict__ coef, Grid3 g) {
+  constexpr int NF = Epi::NF;
+  __shared__ float br[VOL];
+  const int t0 = blockIdx.z * TX0, t1 = blockIdx.y * TX1, t2 = blockIdx.x * TX2;
+  const int o0 = t0 - HALO, o1 = t1 - HALO, o2 = t2 - HALO;
+  const int tid = threadIdx.x;
+  float x[PPT][3];
+  int pidx[PPT];  // node index (grids stay below 2^31 nodes)
+  bool live[PPT];
+  typename Epi::State st[PPT];
+#pragma unroll
+  for (int j = 0; j < PPT; ++j) {
+    const int q = tid + NTHR * j;
+    const int l2 = q % TX2, l1 = (q / TX2) % TX1, l0 = q / (TX1 * TX2);
+    const int i0 = t0 + l0, i1 = t1 + l1, i2 = t2 + l2;
+    live[j] = (i0 < g.n0) && (i1 < g.n1) && (i2 < g.n2);
+    pidx[j] = (i0 * g.n1 + i1) * g.n2 + i2;
+    if (live[j]) {
+      epi.pos(pidx[j], i0, i1, i2, x[j]);
+      epi.init(pidx[j], st[j]);
+    } else {
+      x[j][0] = x[j][1] = x[j][2] = 0.f;
+    }
+  }
+  // one field at a time (not unrolled: keeps the register footprint independent of NF)
+#pragma unroll 1
+  for (int f = 0; f < NF; ++f) {
+    const float* __restrict__ c = coef + f * g.P;
+    __syncthreads();
+    for (int e = tid; e < VOL; e += NTHR) {
+      const int b2 = e % B2, b1 = (e / B2) % B1, b0 = e / (B1 * B2);
+      const int gi0 = wrapi(o0 + b0, g.n0), gi1 = wrapi(o1 + b1, g.n1), gi2 = wrapi(o2 + b2, g.n2);
+      br[e] = c[(static_cast<int64_t>(gi0) * g.n1 + gi1) * g.n2 + gi2];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      if (!live[j]) continue;
+      const float f0 = floorf(x[j][0]), f1 = floorf(x[j][1]), f2 = floorf(x[j][2]);
+      const int s0 = static_cast<int>(f0) - 1 - o0, s1 = static_cast<int>(f1) - 1 - o1,
+                s2 = static_cast<int>(f2) - 1 - o2;
+      const bool inb = s0 >= 0 && s0 + 3 < B0 && s1 >= 0 && s1 + 3 < B1 && s2 >= 0 && s2 + 3 < B2;
+      float value;
+      if (inb) {
+        float w0[4], w1[4], w2[4];
+        bspline_weights(x[j][0] - f0, w0);
+        bspline_weights(x[j][1] - f1, w1);
+        bspline_weights(x[j][2] - f2, w2);
+        value = eval_brick(br, s0, s1, s2, w0, w1, w2);
+      } else {
+        value = eval_global(c, x[j][0], x[j][1], x[j][2], g);
+      }
+      epi.accum(st[j], f, value);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < PPT; ++j)
+    if (live[j]) epi.emit(pidx[j], st[j]);
+}
+
+// ---- epilogues ---------------------------------------------------------------------
+
+// nodes displaced by a stored departure displacement field (grid units)
+struct DispPos {
+  const float* __restrict__ disp;
+  int64_t P;
+  __device__ __forceinline__ void pos(int64_t p, int i0, int i1, int i2, float x[3]) const {
+    x[0] = i0 + disp[p];
+    x[1] = i1 + disp[P + p];
+    x[2] = i2 + disp[2 * P + p];
+  }
+};
+
+template <int NFv>
+struct EpiInterp : DispPos {
+  static constexpr int NF = NFv;
+  struct State {
+    float o[NF];
+  };
+  float* __restrict__ out;
+  __device__ __forceinline__ void init(int64_t, State&) const {}
+  __device__ __forceinline__ void accum(State& s, int f, float v) const {
+#pragma unroll
+    for (int i = 0; i < NF; ++i) s.o[i] = (f == i) ? v : s.o[i];
+  }
+  __device__ __forceinline__ void emit(int64_t p, const State& s) const {
+#pragma unroll
+    for (int f = 0; f < NF; ++f) out[f * P + p] = s.o[f];
+  }
+};
+
+// band-limited adjoint Heun step: out_f = cA_f o X + dt/2 divv (cB_f o X)
+template <int NC>
+struct EpiBLAdjoint : DispPos {
+  static constexpr int NF = 2 * NC;
+  struct State {
+    float hd, o[NC];
+  };
+  float* __restrict__ out;
+  const float* __restrict__ divv;
+  float dt;
+  __device__ __forceinline__ void init(int64_t p, State& s) const {
+    s.hd = 0.5f * dt * divv[p];
+#pragma unroll
+    for (int i = 0; i < NC; ++i) s.o[i] = 0.f;
+  }
+  __device__ __forceinline__ void accum(State& s, int f, float v) const {
+    const float w = f < NC ? v : s.hd * v;
+    const int i0 = f < NC ? f : f - NC;
+#pragma unroll
+    for (int i = 0; i < NC; ++i) s.o[i] += (i0 == i) ? w : 0.f;
+  }
+  __device__ __forceinline__ void emit(int64_t p, const State& s) const {
+#pragma unroll
+    for (int f = 0; f < NC; ++f) out[f * P + p] = s.o[f];
+  }
+};
+
+// image-transport adjoint on the grid: a = c1 o X, b = c2 o X,
+// out = a + dt/2 (b + (a + dt b) divv) = (1 + dt/2 divv) a + dt/2 (1 + dt divv) b
+struct EpiAdjointGrid : DispPos {
+  static constexpr int NF = 2;
+  struct State {
+    float ca, cb, o;
+  };
+  float* __restrict__ out;
+  const float* __restrict__ divv;
+  float dt;
+  __device__ __forceinline__ void init(int64_t p, State& s) const {
+    const float dv = divv[p];
+    s.ca = 1.f + 0.5f * dt * dv;
+    s.cb = 0.5f * dt * (1.f + dt * dv);
+    s.o = 0.f;
+  }
+  __device__ __forceinline__ void accum(State& s, int f, float v) const { s.o += (f == 0 ? s.ca : s.cb) * v; }
+  __device__ __forceinline__ void emit(int64_t p, const State& s) const { out[p] = s.o; }
+};
+
+// image-transport incremental state: out0 = c o X, out1 = -G . dv
+struct EpiIncStateV1 : DispPos {
+  static constexpr int NF = 1;
+  struct State {
+    float o;
+  };
+  float* __restrict__ out;
+  const float* __restrict__ G;
+  const float* __restrict__ dv;
+  __device__ __forceinline__ void init(int64_t, State&) const {}
+  __device__ __forceinline__ void accum(State& s, int, float v) const { s.o = v; }
+  __device__ __forceinline__ void emit(int64_t p, const State& s) const {
+    out[p] = s.o;
+    out[P + p] = -(G[p] * dv[p] + G[P + p] * dv[P + p] + G[2 * P + p] * dv[2 * P + p]);
+  }
+};
+
+// deformation-state incremental state: out[0..2] = c_f o X, out[3..5] = dv - Du dv
+struct EpiIncStateV3 : DispPos {
+  static constexpr int NF = 3;
+  struct State {
+    float o[3];
+  };
+  float* __restrict__ out;
+  const float* __restrict__ Du;
+  const float* __restrict__ dv;
+  __device__ __forceinline__ void init(int64_t, State&) const {}
+  __device__ __forceinline__ void accum(State& s, int f, float v) const {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) s.o[i] = (f == i) ? v : s.o[i];
+  }
+  __device__ __forceinline__ void emit(int64_t p, const State& s) const {
+    const float w0 = dv[p], w1 = dv[P + p], w2 = dv[2 * P + p];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      out[i * P + p] = s.o[i];
+      const float* D = Du + (int64_t)(3 * i) * P;
+      const float wi = i == 0 ? w0 : (i == 1 ? w1 : w2);
+      out[(3 + i) * P + p] = wi - (D[p] * w0 + D[P + p] * w1 + D[2 * P + p] * w2);
+    }
+  }
+};
+
+// characteristics: X* = x + sdt v, X - x = sdt/2 (v + v o X*) (grid units)
+struct EpiCharacteristics {
+  static constexpr int NF = 3;
+  struct State {
+    float o[3];
+  };
+  const float* __restrict__ v;
+  float* __restrict__ disp;
+  int64_t P;
+  float sdt, s0, s1, s2;  // signed dt and per-axis grid sizes
+  __device__ __forceinline__ void pos(int64_t p, int i0, int i1, int i2, float x[3]) const {
+    x[0] = i0 + sdt * v[p] * s0;
+    x[1] = i1 + sdt * v[P + p] * s1;
+    x[2] = i2 + sdt * v[2 * P + p] * s2;
+  }
+  __device__ __forceinline__ void init(int64_t, State&) const {}
+  __device__ __forceinline__ void accum(State& s, int f, float val) const {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) s.o[i] = (f == i) ? val : s.o[i];
+  }
+  __device__ __forceinline__ void emit(int64_t p, const State& s) const {
+    const float h = 0.5f * sdt;
+    disp[p] = h * (v[p] * s0 + s.o[0] * s0);
+    disp[P + p] = h * (v[P + p] * s1 + s.o[1] * s1);
+    disp[2 * P + p] = h * (v[2 * P + p] * s2 + s.o[2] * s2);
+  }
+};
+
+template <class Epi>
+void launch(const Epi& epi, const float* coef, const Dims& d, hipStream_t s) {
+  const Grid3 g{d.n[0], d.n[1], d.n[2], d.P};
+  dim3 grid(ceil_div(d.n[2], TX2), ceil_div(d.n[1], TX1), ceil_div(d.n[0], TX0));
+  k_brick<Epi><<<grid, NTHR, 0, s>>>(epi, coef, g);
+  LDDMM_LAUNCH_CHECK();
+}
+
+std::string nm(const char* base) { return std::string(base) + "<brick>"; }
+
+}  // namespace
+
+bool brick_ok(const Dims& d) { return d.n[0] > 1; }
+
+void brick_interp(float* out, const float* coef, int nf, const float* disp, const Dims& d, hipStream_t s) {
+  prof::Scope ps_(s, nm("k_interp") + std::to_string(nf), (3.0 + 2.0 * nf) * d.P * 4, 0.0);
+  if (nf == 1) {
+    EpiInterp<1> e;
+    e.disp = disp, e.P = d.P, e.out = out;
+    launch(e, coef, d, s);
+  } else if (nf == 3) {
+    EpiInterp<3> e;
+    e.disp = disp, e.P = d.P, e.out = out;
+    launch(e, coef, d, s);
+  } else {
+    throw ArgError("brick_interp: nf must be 1 or 3");
+  }
+}
+
+void brick_bl_adjoint_step(float* out, const float* cAB, int nc, const float* disp, const float* divv,
+                           const Dims& d, float dt, hipStream_t s) {
+  prof::Scope ps_(s, nm("k_bl_adjoint_step") + std::to_string(nc), (4.0 + 3.0 * nc) * d.P * 4, 0.0);
+  if (nc == 1) {
+    EpiBLAdjoint<1> e;
+    e.disp = disp, e.P = d.P, e.out = out, e.divv = divv, e.dt = dt;
+    launch(e, cAB, d, s);
+  } else if (nc == 3) {
+    EpiBLAdjoint<3> e;
+    e.disp = disp, e.P = d.P, e.out = out, e.divv = divv, e.dt = dt;
+    launch(e, cAB, d, s);
+  } else {
+    throw ArgError("brick_bl_adjoint_step: nc must be 1 or 3");
+  }
+}
+
+void brick_adjoint_grid_step(float* out, const float* c12, const float* disp, const float* divv, const Dims& d,
+                             float dt, hipStream_t s) {
+  prof::Scope ps_(s, nm("k_adjoint_grid_step"), 7.0 * d.P * 4, 0.0);
+  EpiAdjointGrid e;
+  e.disp = disp, e.P = d.P, e.out = out, e.divv = divv, e.dt = dt;
+  launch(e, c12, d, s);
+}
+
+void brick_inc_state_v1(float* out, const float* c, const float* disp, const float* G, const float* dv,
+                        const Dims& d, hipStream_t s) {
+  prof::Scope ps_(s, nm("k_inc_state_v1"), 12.0 * d.P * 4, 0.0);
+  EpiIncStateV1 e;
+  e.disp = disp, e.P = d.P, e.out = out, e.G = G, e.dv = dv;
+  launch(e, c, d, s);
+}
+
+void brick_inc_state_v3(float* out, const float* c, const float* disp, const float* Du, const float* dv,
+                        const Dims& d, hipStream_t s) {
+  prof::Scope ps_(s, nm("k_inc_state_v3"), 24.0 * d.P * 4, 0.0);
+  EpiIncStateV3 e;
+  e.disp = disp, e.P = d.P, e.out = out, e.Du = Du, e.dv = dv;
+  launch(e, c, d, s);
+}
+
+void brick_characteristics(float* disp, const float* v, const float* cv, const Dims& d, float dt, int dir,
+                           hipStream_t s) {
+  prof::Scope ps_(s, nm("k_characteristics"), 9.0 * d.P * 4, 0.0);
+  EpiCharacteristics e;
+  e.v = v, e.disp = disp, e.P = d.P;
+  e.sdt = dir > 0 ? dt : -dt;
+  e.s0 = float(d.n[0]), e.s1 = float(d.n[1]), e.s2 = float(d.n[2]);
+  launch(e, cv, d, s);
+}
+
+}  // namespace lddmm

@@ -8,6 +8,8 @@
 #include "kernels.h"
 #include "prof.h"
 
+#include <type_traits>
+
 namespace lddmm {
 
 namespace {
@@ -338,6 +340,12 @@ __global__ void k_mul(T* out, const T* x, const T* y, int64_t n) {
 }
 
 template <typename T>
+__global__ void k_copy(T* __restrict__ dst, const T* __restrict__ src, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+template <typename T>
 __global__ void k_zero(T* p, int64_t n) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < n) p[i] = T(0);
@@ -468,6 +476,9 @@ void bl_div(T* out, const T* v, const Dims& d, hipStream_t s) {
 
 template <typename T>
 void characteristics(T* disp, const T* v, const T* cv, const Dims& d, T dt, int dir, hipStream_t s) {
+  if constexpr (std::is_same_v<T, float>) {
+    if (brick_ok(d)) return brick_characteristics(disp, v, cv, d, dt, dir, s);
+  }
   prof::Scope ps_(s, "k_characteristics<" + std::string(prof::tname<T>()) + ">", 9.0 * d.P * sizeof(T), 0.0);
   k_characteristics<T><<<grid_for(d.P), kBlock, 0, s>>>(disp, v, cv, d.n[0], d.n[1], d.n[2], dt, dir);
   LDDMM_LAUNCH_CHECK();
@@ -475,6 +486,9 @@ void characteristics(T* disp, const T* v, const T* cv, const Dims& d, T dt, int 
 
 template <typename T>
 void interp(T* out, const T* coef, int nf, const T* disp, const Dims& d, hipStream_t s) {
+  if constexpr (std::is_same_v<T, float>) {
+    if (brick_ok(d) && (nf == 1 || nf == 3)) return brick_interp(out, coef, nf, disp, d, s);
+  }
   prof::Scope ps_(s, "k_interp<" + std::string(prof::tname<T>()) + "," + std::to_string(nf) + ">", (3.0 + 2.0 * nf) * d.P * sizeof(T), 0.0);
   switch (nf) {
     case 1:
@@ -520,6 +534,9 @@ void prefilter(T* f, int nf, const Dims& d, hipStream_t s) {
 template <typename T>
 void adjoint_grid_step(T* out, const T* c1, const T* c2, const T* disp, const T* divv, const Dims& d, T dt,
                        hipStream_t s) {
+  if constexpr (std::is_same_v<T, float>) {
+    if (brick_ok(d) && c2 == c1 + d.P) return brick_adjoint_grid_step(out, c1, disp, divv, d, dt, s);
+  }
   prof::Scope ps_(s, "k_adjoint_grid_step<" + std::string(prof::tname<T>()) + ">", 7.0 * d.P * sizeof(T), 0.0);
   k_adjoint_grid_step<T><<<grid_for(d.P), kBlock, 0, s>>>(out, c1, c2, disp, divv, d.n[0], d.n[1], d.n[2], dt);
   LDDMM_LAUNCH_CHECK();
@@ -528,6 +545,9 @@ void adjoint_grid_step(T* out, const T* c1, const T* c2, const T* disp, const T*
 template <typename T>
 void bl_adjoint_step(T* out, const T* cA, const T* cB, int nf, const T* disp, const T* divv, const Dims& d, T dt,
                      hipStream_t s) {
+  if constexpr (std::is_same_v<T, float>) {
+    if (brick_ok(d) && cB == cA + nf * d.P) return brick_bl_adjoint_step(out, cA, nf, disp, divv, d, dt, s);
+  }
   prof::Scope ps_(s, "k_bl_adjoint_step<" + std::string(prof::tname<T>()) + "," + std::to_string(nf) + ">", (4.0 + 3.0 * nf) * d.P * sizeof(T), 0.0);
   if (nf == 1)
     k_bl_adjoint_step<T, 1><<<grid_for(d.P), kBlock, 0, s>>>(out, cA, cB, disp, divv, d.n[0], d.n[1], d.n[2], dt);
@@ -540,6 +560,9 @@ void bl_adjoint_step(T* out, const T* cA, const T* cB, int nf, const T* disp, co
 
 template <typename T>
 void inc_state_v1(T* out, const T* c, const T* disp, const T* G, const T* dv, const Dims& d, hipStream_t s) {
+  if constexpr (std::is_same_v<T, float>) {
+    if (brick_ok(d)) return brick_inc_state_v1(out, c, disp, G, dv, d, s);
+  }
   prof::Scope ps_(s, "k_inc_state_v1<" + std::string(prof::tname<T>()) + ">", 12.0 * d.P * sizeof(T), 0.0);
   k_inc_state_v1<T><<<grid_for(d.P), kBlock, 0, s>>>(out, c, disp, G, dv, d.n[0], d.n[1], d.n[2]);
   LDDMM_LAUNCH_CHECK();
@@ -547,6 +570,9 @@ void inc_state_v1(T* out, const T* c, const T* disp, const T* G, const T* dv, co
 
 template <typename T>
 void inc_state_v3(T* out, const T* c, const T* disp, const T* Du, const T* dv, const Dims& d, hipStream_t s) {
+  if constexpr (std::is_same_v<T, float>) {
+    if (brick_ok(d)) return brick_inc_state_v3(out, c, disp, Du, dv, d, s);
+  }
   prof::Scope ps_(s, "k_inc_state_v3<" + std::string(prof::tname<T>()) + ">", 24.0 * d.P * sizeof(T), 0.0);
   k_inc_state_v3<T><<<grid_for(d.P), kBlock, 0, s>>>(out, c, disp, Du, dv, d.n[0], d.n[1], d.n[2]);
   LDDMM_LAUNCH_CHECK();
@@ -619,6 +645,13 @@ void jacobian_det(double* out, const T* Du, int dim, int64_t P, hipStream_t s) {
 }
 
 template <typename T>
+void copy_dev(T* dst, const T* src, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  k_copy<T><<<grid_for(n), kBlock, 0, s>>>(dst, src, n);
+  LDDMM_LAUNCH_CHECK();
+}
+
+template <typename T>
 void zero(T* p, int64_t n, hipStream_t s) {
   if (n <= 0) return;
   k_zero<T><<<grid_for(n), kBlock, 0, s>>>(p, n);
@@ -648,7 +681,8 @@ void zero(T* p, int64_t n, hipStream_t s) {
   template void coupling_v3<T>(T*, T, const T*, const T*, const Dims&, hipStream_t);                    \
   template void mul<T>(T*, const T*, const T*, int64_t, hipStream_t);                                   \
   template void jacobian_det<T>(double*, const T*, int, int64_t, hipStream_t);                          \
-  template void zero<T>(T*, int64_t, hipStream_t);
+  template void zero<T>(T*, int64_t, hipStream_t);                                                     \
+  template void copy_dev<T>(T*, const T*, int64_t, hipStream_t);
 
 LDDMM_INST(float)
 LDDMM_INST(double)

@@ -90,9 +90,25 @@ void mul(T* out, const T* x, const T* y, int64_t n, hipStream_t s);
 // det(I - Du) in double from 9 derivative fields (T)
 template <typename T>
 void jacobian_det(double* out, const T* Du, int dim, int64_t P, hipStream_t s);
-// copy with conversion for components (used for d = 2 staging): dst[c] = src[c] over n elems
+// p[0..n) = 0 and dst[0..n) = src[0..n) as kernels (safe inside captured graphs)
 template <typename T>
 void zero(T* p, int64_t n, hipStream_t s);
+template <typename T>
+void copy_dev(T* dst, const T* src, int64_t n, hipStream_t s);
+
+// ---- LDS-brick interpolation, float 3D grids (brick.hip) ---------------------
+bool brick_ok(const Dims& d);
+void brick_interp(float* out, const float* coef, int nf, const float* disp, const Dims& d, hipStream_t s);
+void brick_bl_adjoint_step(float* out, const float* cAB, int nc, const float* disp, const float* divv,
+                           const Dims& d, float dt, hipStream_t s);
+void brick_adjoint_grid_step(float* out, const float* c12, const float* disp, const float* divv, const Dims& d,
+                             float dt, hipStream_t s);
+void brick_inc_state_v1(float* out, const float* c, const float* disp, const float* G, const float* dv,
+                        const Dims& d, hipStream_t s);
+void brick_inc_state_v3(float* out, const float* c, const float* disp, const float* Du, const float* dv,
+                        const Dims& d, hipStream_t s);
+void brick_characteristics(float* disp, const float* v, const float* cv, const Dims& d, float dt, int dir,
+                           hipStream_t s);
 
 // ---- FP64 reductions (reduce.hip) -------------------------------------------
 // partial results go to `work` (device, >= reduce_work_size doubles); result to host

@@ -21,8 +21,10 @@
 //    (Du)^T drho, final conditions with g1 = (grad P(I0)) o phi(1).
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 
+#include "prof.h"
 #include "solver.h"
 
 namespace lddmm {
@@ -114,9 +116,18 @@ class Solver final : public SolverBase {
   void hess_matvec(const void* dv, void* hdv) override {
     require_state();
     to_internal(dvbl_.get(), static_cast<const T*>(dv), 3);
-    run_matvec(dvbl_.get(), hbl_.get());
+    if (use_graphs()) {
+      if (!mv_exec_) capture_matvec();
+      LDDMM_HIP(hipGraphLaunch(mv_exec_, st_));
+    } else {
+      run_matvec(dvbl_.get(), hbl_.get());
+    }
     from_internal(static_cast<T*>(hdv), hbl_.get(), 3);
     sync();
+  }
+
+  ~Solver() override {
+    if (mv_exec_) (void)hipGraphExecDestroy(mv_exec_);
   }
 
   int gn_solve(const lddmm_bl_gn_opts& o, void* v, const void* Z, int r, lddmm_bl_gn_report* rep) override;
@@ -258,11 +269,34 @@ class Solver final : public SolverBase {
     void operator()(double* p) const { (void)hipHostFree(p); }
   };
 
+  // ------------------------------------------------------ graph capture
+  // The Hessian matvec has no host synchronisation inside: its whole launch
+  // sequence (about 300 kernels for Nt = 10) is captured once into a HIP graph
+  // over the context's fixed buffers and replayed.  Needs a non-default stream;
+  // not used while per-kernel profiling is on.
+  bool use_graphs() const { return st_ != nullptr && graphs_enabled_ && !prof::enabled(); }
+  void capture_matvec() {
+    hipGraph_t g = nullptr;
+    LDDMM_HIP(hipStreamBeginCapture(st_, hipStreamCaptureModeThreadLocal));
+    try {
+      run_matvec(dvbl_.get(), hbl_.get());
+    } catch (...) {
+      (void)hipStreamEndCapture(st_, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    LDDMM_HIP(hipStreamEndCapture(st_, &g));
+    const hipError_t e = hipGraphInstantiate(&mv_exec_, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      mv_exec_ = nullptr;
+      throw HipError(std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+  }
+
   // --------------------------------------------------------- small helpers
   const T* mat(int axis, int kind) const { return mats_.get() + mat_off_[axis][kind]; }
-  void copy(T* dst, const T* src, int64_t n) {
-    LDDMM_HIP(hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyDeviceToDevice, st_));
-  }
+  void copy(T* dst, const T* src, int64_t n) { copy_dev<T>(dst, src, n, st_); }
   void sync() { LDDMM_HIP(hipStreamSynchronize(st_)); }
   void check_ncomp(int ncomp) const {
     if (ncomp < 1 || ncomp > kMaxFields) throw ArgError("ncomp must be in 1..12");
@@ -571,6 +605,8 @@ class Solver final : public SolverBase {
   T dt_ = T(1);
   double alpha_ = 0, sigma2_ = 1;
   bool have_images_ = false, state_valid_ = false;
+  bool graphs_enabled_ = std::getenv("LDDMM_BL_NO_GRAPH") == nullptr;
+  hipGraphExec_t mv_exec_ = nullptr;
   int64_t mat_off_[3][4] = {};
   DevBuf<T> mats_;
   DevBuf<double> Lsym_, Linv_, work_;

@@ -138,7 +138,8 @@ class Context:
         self.k = tuple(int(x) for x in prob.k)
         self.dtype = torch.float64 if prob.precision == FP64 else torch.float32
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        # a dedicated non-default stream: the library captures its Hessian matvec into a HIP graph on it
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
         p = Params()
         p.dim = self.dim
         for j in range(3):
@@ -164,6 +165,12 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def _order(self):
+        """Make the library's stream wait for work queued on the caller's current stream."""
+        cur = torch.cuda.current_stream(self.device)
+        if cur != self.stream:
+            self.stream.wait_stream(cur)
 
     def _check(self, st, allow_warn=False):
         if st < 0 or (st > 0 and not allow_warn):
@@ -197,24 +204,28 @@ class Context:
     def set_images(self, I0: torch.Tensor, I1: torch.Tensor):
         self._arg(I0, self.n, "I0")
         self._arg(I1, self.n, "I1")
+        self._order()
         self._check(self.lib.lddmm_bl_set_images(self.h, _ptr(I0), _ptr(I1)))
 
     def state_solve(self, v: torch.Tensor, want_m1: bool = False) -> Tuple[Tuple[float, float, float], Optional[torch.Tensor]]:
         self._arg(v, self._bl_shape(self.dim), "v")
         m1 = self.empty_grid() if want_m1 else None
         E = (ctypes.c_double * 3)()
+        self._order()
         self._check(self.lib.lddmm_bl_state_solve(self.h, _ptr(v), _ptr(m1), E))
         return (E[0], E[1], E[2]), m1
 
     def adjoint_solve(self) -> Tuple[torch.Tensor, float]:
         g = self.empty_bl(self.dim)
         ginf = ctypes.c_double()
+        self._order()
         self._check(self.lib.lddmm_bl_adjoint_solve(self.h, _ptr(g), ctypes.byref(ginf)))
         return g, ginf.value
 
     def hess_matvec(self, dv: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
         self._arg(dv, self._bl_shape(self.dim), "dv")
         out = self.empty_bl(self.dim) if out is None else self._arg(out, self._bl_shape(self.dim), "out")
+        self._order()
         self._check(self.lib.lddmm_bl_hess_matvec(self.h, _ptr(dv), _ptr(out)))
         return out
 
@@ -228,6 +239,7 @@ class Context:
         if Z is not None:
             r = Z.shape[0]
             self._arg(Z, (r, self.dim) + self.k, "Z")
+        self._order()
         st = self.lib.lddmm_bl_gn_solve(self.h, ctypes.byref(o), _ptr(v), _ptr(Z), r, ctypes.byref(rep))
         self._check(st, allow_warn=True)
         return st, rep.as_dict()
@@ -235,18 +247,21 @@ class Context:
     def jacobian(self, want_map: bool = False):
         det = torch.empty(self.n, dtype=torch.float64, device=self.device) if want_map else None
         mm = (ctypes.c_double * 2)()
+        self._order()
         self._check(self.lib.lddmm_bl_jacobian(self.h, _ptr(det), mm))
         return (mm[0], mm[1]), det
 
     def project(self, grid: torch.Tensor, ncomp: int = 1) -> torch.Tensor:
         self._arg(grid, self._grid_shape(ncomp if ncomp > 1 else None), "grid")
         out = self.empty_bl(ncomp if ncomp > 1 else None)
+        self._order()
         self._check(self.lib.lddmm_bl_project(self.h, _ptr(grid), _ptr(out), ncomp))
         return out
 
     def include(self, bl: torch.Tensor, ncomp: int = 1) -> torch.Tensor:
         self._arg(bl, self._bl_shape(ncomp if ncomp > 1 else None), "bl")
         out = self.empty_grid(ncomp if ncomp > 1 else None)
+        self._order()
         self._check(self.lib.lddmm_bl_include(self.h, _ptr(bl), _ptr(out), ncomp))
         return out
 
@@ -261,6 +276,7 @@ class Context:
         if a.numel() != b.numel() or a.dtype != self.dtype or b.dtype != self.dtype:
             raise ValueError("dot: size or dtype mismatch")
         r = ctypes.c_double()
+        self._order()
         self._check(self.lib.lddmm_bl_dot(self.h, _ptr(a), _ptr(b), a.numel(), ctypes.byref(r)))
         return r.value
 
