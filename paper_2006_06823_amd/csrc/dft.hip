@@ -11,6 +11,9 @@
 #include "kernels.h"
 #include "prof.h"
 
+#include <algorithm>
+#include <type_traits>
+
 namespace lddmm {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
@@ -159,6 +162,113 @@ __global__ __launch_bounds__(64 * WR * WM) void dft_right_kernel(const T* __rest
   }
 }
 
+// ---- streaming float kernels for the large stages ----------------------------------
+// The B operand (input rows, contiguous in c) is read straight from global memory
+// into the matrix-core operand registers, 32 consecutive floats per half-wave, so
+// the input streams through once without LDS staging; only W sits in LDS.
+//
+// contract mode (M <= 64, L large): the four waves of a block share 32 columns and
+// split the contraction range; partial 32x32 blocks are summed through LDS.
+template <int MB>
+__global__ __launch_bounds__(256) void dft_left_contract(const float* __restrict__ in, float* __restrict__ out,
+                                                         FieldMats<float> mats, int bpf, int M, int L, int C,
+                                                         int64_t sIb, int64_t sOb) {
+  extern __shared__ float smem[];
+  const int ldw = L + 1;
+  float* Ws = smem;   // [32 MB][L + 1]
+  float* red = smem;  // [4][MB][16][64], reuses the W tile after the contraction
+  const int b = blockIdx.z;
+  const float* __restrict__ W = mats.w[b / bpf];
+  in += b * sIb;
+  out += b * sOb;
+  const int c0 = blockIdx.x * 32;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int e = tid; e < 32 * MB * L; e += 256) {
+    const int m = e / L, l = e - m * L;
+    Ws[m * ldw + l] = m < M ? W[(int64_t)m * L + l] : 0.f;
+  }
+  __syncthreads();
+  // this wave's contraction range (even length, so each k-step pairs two rows)
+  const int seg = ((L + 7) / 8) * 2;
+  const int lb = wave * seg, le = min(L, lb + seg);
+  const int c = c0 + (lane & 31);
+  const bool cok = c < C;
+  const int kh = lane >> 5;
+  f32x16 acc[MB];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[mb][r] = 0.f;
+#pragma unroll 8
+  for (int kk = lb; kk < le; kk += 2) {
+    const int l = kk + kh;
+    const float bv = (cok && l < le) ? in[(int64_t)l * C + c] : 0.f;
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+      const float av = l < le ? Ws[(mb * 32 + (lane & 31)) * ldw + l] : 0.f;
+      acc[mb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc[mb], 0, 0, 0);
+    }
+  }
+  __syncthreads();  // every wave is done reading W
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) red[((wave * MB + mb) * 16 + r) * 64 + lane] = acc[mb][r];
+  __syncthreads();
+  for (int e = tid; e < MB * 16 * 64; e += 256) {
+    const int ln = e & 63, r = (e >> 6) & 15, mb = e >> 10;
+    float sum = 0.f;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) sum += red[((w * MB + mb) * 16 + r) * 64 + ln];
+    const int m = mb * 32 + acc_row(r, ln), cc = c0 + (ln & 31);
+    if (m < M && cc < C) out[(int64_t)m * C + cc] = sum;
+  }
+}
+
+// expand mode (L <= 64): each wave owns one 32-row block of a 128-row block tile and
+// the block's 32 columns, over the whole (short) contraction.
+__global__ __launch_bounds__(256) void dft_left_expand(const float* __restrict__ in, float* __restrict__ out,
+                                                       FieldMats<float> mats, int bpf, int M, int L, int C,
+                                                       int64_t sIb, int64_t sOb) {
+  extern __shared__ float smem[];
+  const int ldw = L + 1;
+  float* Ws = smem;  // [128][L + 1]
+  const int b = blockIdx.z;
+  const float* __restrict__ W = mats.w[b / bpf];
+  in += b * sIb;
+  out += b * sOb;
+  const int c0 = blockIdx.x * 32, m0 = blockIdx.y * 128;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int e = tid; e < 128 * L; e += 256) {
+    const int mm = e / L, l = e - mm * L;
+    Ws[mm * ldw + l] = (m0 + mm) < M ? W[(int64_t)(m0 + mm) * L + l] : 0.f;
+  }
+  __syncthreads();
+  const int mw = m0 + wave * 32;
+  if (mw >= M) return;
+  const int c = c0 + (lane & 31);
+  const bool cok = c < C;
+  const int kh = lane >> 5;
+  f32x16 acc;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+  const float* Wr = Ws + (wave * 32 + (lane & 31)) * ldw;
+#pragma unroll 8
+  for (int kk = 0; kk < L; kk += 2) {
+    const int l = kk + kh;
+    const float bv = (cok && l < L) ? in[(int64_t)l * C + c] : 0.f;
+    const float av = l < L ? Wr[l] : 0.f;
+    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
+  }
+  if (cok) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int m = mw + acc_row(r, lane);
+      if (m < M) out[(int64_t)m * C + c] = acc[r];
+    }
+  }
+}
+
 }  // namespace
 
 template <typename T>
@@ -166,10 +276,34 @@ void dft_left(const T* in, T* out, const FieldMats<T>& W, int nb, int bpf, int M
               int64_t sOb, hipStream_t s) {
   if (nb <= 0 || M <= 0 || C <= 0) return;
   if (nb > 65535) throw ArgError("dft_left: batch too large");
+  const double bytes = double(sizeof(T)) * ((double)nb * L * C + (double)nb * M * C);
+  const double flops = 2.0 * nb * M * (double)L * C;
+  if constexpr (std::is_same_v<T, float>) {
+    if (M <= 64 && L > 64 && L <= 192) {
+      prof::Scope ps_(s, M > 32 ? "dft_left_contract<2>" : "dft_left_contract<1>", bytes, flops);
+      const int MB = M > 32 ? 2 : 1;
+      const size_t sm = (size_t)std::max(32 * MB * (L + 1), 4 * MB * 16 * 64) * sizeof(float);
+      dim3 g(ceil_div(C, 32), 1, nb);
+      if (MB == 2)
+        dft_left_contract<2><<<g, 256, sm, s>>>(in, out, W, bpf, M, L, C, sIb, sOb);
+      else
+        dft_left_contract<1><<<g, 256, sm, s>>>(in, out, W, bpf, M, L, C, sIb, sOb);
+      LDDMM_LAUNCH_CHECK();
+      return;
+    }
+    if (L <= 64) {
+      prof::Scope ps_(s, "dft_left_expand", bytes, flops);
+      const size_t sm = (size_t)128 * (L + 1) * sizeof(float);
+      dim3 g(ceil_div(C, 32), ceil_div(M, 128), nb);
+      dft_left_expand<<<g, 256, sm, s>>>(in, out, W, bpf, M, L, C, sIb, sOb);
+      LDDMM_LAUNCH_CHECK();
+      return;
+    }
+  }
   const int wm = M > 64 ? 4 : (M > 32 ? 2 : 1);
   prof::Scope ps_(s, std::string("dft_left_kernel<") + prof::tname<T>() + "," + std::to_string(wm) + "," +
                          std::to_string(4 / wm) + ">",
-                  double(sizeof(T)) * ((double)nb * L * C + (double)nb * M * C), 2.0 * nb * M * (double)L * C);
+                  bytes, flops);
   if (M > 64) {
     dim3 g(ceil_div(C, 32), ceil_div(M, 128), nb);
     dft_left_kernel<T, 4, 1><<<g, 256, 0, s>>>(in, out, W, bpf, M, L, C, sIb, sOb);
@@ -187,18 +321,17 @@ template <typename T>
 void dft_right(const T* in, T* out, const FieldMats<T>& W, int nf, int R, int L, int Mo, hipStream_t s) {
   if (nf <= 0 || R <= 0 || Mo <= 0) return;
   const int wm = Mo > 64 ? 4 : (Mo > 32 ? 2 : 1);
-  prof::Scope ps_(s, std::string("dft_right_kernel<") + prof::tname<T>() + "," + std::to_string(4 / wm) + "," +
-                         std::to_string(wm) + ">",
+  prof::Scope ps_(s, std::string("dft_right_kernel<") + prof::tname<T>() + ",1," + std::to_string(wm) + ">",
                   double(sizeof(T)) * ((double)nf * R * L + (double)nf * R * Mo), 2.0 * nf * R * (double)L * Mo);
   if (Mo > 64) {
     dim3 g(ceil_div(Mo, 128), ceil_div(R, 32), nf);
     dft_right_kernel<T, 1, 4><<<g, 256, 0, s>>>(in, out, W, R, L, Mo);
   } else if (Mo > 32) {
-    dim3 g(ceil_div(Mo, 64), ceil_div(R, 64), nf);
-    dft_right_kernel<T, 2, 2><<<g, 256, 0, s>>>(in, out, W, R, L, Mo);
+    dim3 g(ceil_div(Mo, 64), ceil_div(R, 32), nf);
+    dft_right_kernel<T, 1, 2><<<g, 128, 0, s>>>(in, out, W, R, L, Mo);
   } else {
-    dim3 g(ceil_div(Mo, 32), ceil_div(R, 128), nf);
-    dft_right_kernel<T, 4, 1><<<g, 256, 0, s>>>(in, out, W, R, L, Mo);
+    dim3 g(ceil_div(Mo, 32), ceil_div(R, 32), nf);
+    dft_right_kernel<T, 1, 1><<<g, 64, 0, s>>>(in, out, W, R, L, Mo);
   }
   LDDMM_LAUNCH_CHECK();
 }
