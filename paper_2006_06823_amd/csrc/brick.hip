@@ -1,9 +1,10 @@
 // Tricubic B-spline interpolation at SL departure points through LDS bricks
 // (float, 3D grids).
 //
-// A workgroup owns an 8 x 8 x 32 tile of output nodes.  Per coefficient field
-// it stages the tile plus a 2-node halo on every side (12 x 12 x 36 floats,
-// 20.7 KB) into LDS with coalesced, periodically wrapped loads, then evaluates
+// A workgroup owns a 4 x 8 x 32 tile of output nodes.  Per coefficient field
+// it stages the tile plus a 2-node halo on every side (8 x 12 x 36 floats,
+// 13.8 KB) into LDS with coalesced, periodically wrapped loads (the wrapped row
+// offsets and columns are tabulated once per workgroup), then evaluates
 // the 64-tap tensor B-spline for each of its nodes from LDS.  A departure
 // point whose 4 x 4 x 4 stencil leaves the brick (displacement of a voxel or
 // more) falls back to a gather from global memory, so any displacement is
@@ -18,10 +19,10 @@ namespace lddmm {
 
 namespace {
 
-constexpr int TX0 = 8, TX1 = 8, TX2 = 32, HALO = 2;
+constexpr int TX0 = 4, TX1 = 8, TX2 = 32, HALO = 2;
 constexpr int B0 = TX0 + 2 * HALO, B1 = TX1 + 2 * HALO, B2 = TX2 + 2 * HALO;
 constexpr int VOL = B0 * B1 * B2;
-constexpr int NTHR = 512;
+constexpr int NTHR = 256;
 constexpr int PPT = TX0 * TX1 * TX2 / NTHR;  // nodes per thread
 
 struct Grid3 {
@@ -73,19 +74,29 @@ __device__ __noinline__ float eval_global(const float* __restrict__ c, float x0,
 }
 
 // Generic brick kernel.  Epi provides:
-//   static constexpr int NF      coefficient fields, stacked with stride P in `coef`;
+//   NF, GROUPS, GSIZE and field(g, k): the NF coefficient fields (stacked with
+//       stride P in `coef`) are staged GSIZE at a time, GROUPS times;
 //   struct State                 per-node accumulator;
 //   pos(p, i0, i1, i2, x[3])     departure point of node p (grid units);
 //   init(p, State&)              loads the node's pointwise operands;
 //   accum(State&, f, value)      folds the interpolated value of field f in;
 //   emit(p, const State&)        writes the node's results.
+// The B-spline weights of a node are computed once per group and shared by the
+// group's fields.
 template <class Epi>
 __global__ __launch_bounds__(NTHR) void k_brick(Epi epi, const float* __restrict__ coef, Grid3 g) {
-  constexpr int NF = Epi::NF;
-  __shared__ float br[VOL];
+  constexpr int GS = Epi::GSIZE;
+  __shared__ float br[GS * VOL];
+  __shared__ int rowoff[B0 * B1];  // wrapped (i0, i1) row offsets of the brick
+  __shared__ int colidx[B2];       // wrapped i2 of the brick columns
   const int t0 = blockIdx.z * TX0, t1 = blockIdx.y * TX1, t2 = blockIdx.x * TX2;
   const int o0 = t0 - HALO, o1 = t1 - HALO, o2 = t2 - HALO;
   const int tid = threadIdx.x;
+  for (int e = tid; e < B0 * B1; e += NTHR) {
+    const int b0 = e / B1, b1 = e - b0 * B1;
+    rowoff[e] = (wrapi(o0 + b0, g.n0) * g.n1 + wrapi(o1 + b1, g.n1)) * g.n2;
+  }
+  for (int e = tid; e < B2; e += NTHR) colidx[e] = wrapi(o2 + e, g.n2);
   float x[PPT][3];
   int pidx[PPT];  // node index (grids stay below 2^31 nodes)
   bool live[PPT];
@@ -104,15 +115,14 @@ __global__ __launch_bounds__(NTHR) void k_brick(Epi epi, const float* __restrict
       x[j][0] = x[j][1] = x[j][2] = 0.f;
     }
   }
-  // one field at a time (not unrolled: keeps the register footprint independent of NF)
 #pragma unroll 1
-  for (int f = 0; f < NF; ++f) {
-    const float* __restrict__ c = coef + f * g.P;
+  for (int grp = 0; grp < Epi::GROUPS; ++grp) {
     __syncthreads();
     for (int e = tid; e < VOL; e += NTHR) {
-      const int b2 = e % B2, b1 = (e / B2) % B1, b0 = e / (B1 * B2);
-      const int gi0 = wrapi(o0 + b0, g.n0), gi1 = wrapi(o1 + b1, g.n1), gi2 = wrapi(o2 + b2, g.n2);
-      br[e] = c[(static_cast<int64_t>(gi0) * g.n1 + gi1) * g.n2 + gi2];
+      const int row = e / B2, b2 = e - row * B2;
+      const int off = rowoff[row] + colidx[b2];
+#pragma unroll
+      for (int k = 0; k < GS; ++k) br[k * VOL + e] = coef[Epi::field(grp, k) * g.P + off];
     }
     __syncthreads();
 #pragma unroll
@@ -122,23 +132,34 @@ __global__ __launch_bounds__(NTHR) void k_brick(Epi epi, const float* __restrict
       const int s0 = static_cast<int>(f0) - 1 - o0, s1 = static_cast<int>(f1) - 1 - o1,
                 s2 = static_cast<int>(f2) - 1 - o2;
       const bool inb = s0 >= 0 && s0 + 3 < B0 && s1 >= 0 && s1 + 3 < B1 && s2 >= 0 && s2 + 3 < B2;
-      float value;
       if (inb) {
         float w0[4], w1[4], w2[4];
         bspline_weights(x[j][0] - f0, w0);
         bspline_weights(x[j][1] - f1, w1);
         bspline_weights(x[j][2] - f2, w2);
-        value = eval_brick(br, s0, s1, s2, w0, w1, w2);
+#pragma unroll
+        for (int k = 0; k < GS; ++k)
+          epi.accum(st[j], Epi::field(grp, k), eval_brick(br + k * VOL, s0, s1, s2, w0, w1, w2));
       } else {
-        value = eval_global(c, x[j][0], x[j][1], x[j][2], g);
+#pragma unroll
+        for (int k = 0; k < GS; ++k) {
+          const int f = Epi::field(grp, k);
+          epi.accum(st[j], f, eval_global(coef + f * g.P, x[j][0], x[j][1], x[j][2], g));
+        }
       }
-      epi.accum(st[j], f, value);
     }
   }
 #pragma unroll
   for (int j = 0; j < PPT; ++j)
     if (live[j]) epi.emit(pidx[j], st[j]);
 }
+
+// default field staging: all fields in one group
+template <int NFv>
+struct OneGroup {
+  static constexpr int NF = NFv, GROUPS = 1, GSIZE = NFv;
+  __device__ static int field(int, int k) { return k; }
+};
 
 // ---- epilogues ---------------------------------------------------------------------
 
@@ -154,7 +175,7 @@ struct DispPos {
 };
 
 template <int NFv>
-struct EpiInterp : DispPos {
+struct EpiInterp : DispPos, OneGroup<NFv> {
   static constexpr int NF = NFv;
   struct State {
     float o[NF];
@@ -174,7 +195,9 @@ struct EpiInterp : DispPos {
 // band-limited adjoint Heun step: out_f = cA_f o X + dt/2 divv (cB_f o X)
 template <int NC>
 struct EpiBLAdjoint : DispPos {
-  static constexpr int NF = 2 * NC;
+  // fields [cA_0..cA_{NC-1}, cB_0..cB_{NC-1}], staged as the pairs (cA_i, cB_i)
+  static constexpr int NF = 2 * NC, GROUPS = NC, GSIZE = 2;
+  __device__ static int field(int g, int k) { return g + k * NC; }
   struct State {
     float hd, o[NC];
   };
@@ -200,7 +223,7 @@ struct EpiBLAdjoint : DispPos {
 
 // image-transport adjoint on the grid: a = c1 o X, b = c2 o X,
 // out = a + dt/2 (b + (a + dt b) divv) = (1 + dt/2 divv) a + dt/2 (1 + dt divv) b
-struct EpiAdjointGrid : DispPos {
+struct EpiAdjointGrid : DispPos, OneGroup<2> {
   static constexpr int NF = 2;
   struct State {
     float ca, cb, o;
@@ -219,7 +242,7 @@ struct EpiAdjointGrid : DispPos {
 };
 
 // image-transport incremental state: out0 = c o X, out1 = -G . dv
-struct EpiIncStateV1 : DispPos {
+struct EpiIncStateV1 : DispPos, OneGroup<1> {
   static constexpr int NF = 1;
   struct State {
     float o;
@@ -236,7 +259,7 @@ struct EpiIncStateV1 : DispPos {
 };
 
 // deformation-state incremental state: out[0..2] = c_f o X, out[3..5] = dv - Du dv
-struct EpiIncStateV3 : DispPos {
+struct EpiIncStateV3 : DispPos, OneGroup<3> {
   static constexpr int NF = 3;
   struct State {
     float o[3];
@@ -262,7 +285,7 @@ struct EpiIncStateV3 : DispPos {
 };
 
 // characteristics: X* = x + sdt v, X - x = sdt/2 (v + v o X*) (grid units)
-struct EpiCharacteristics {
+struct EpiCharacteristics : OneGroup<3> {
   static constexpr int NF = 3;
   struct State {
     float o[3];
@@ -290,29 +313,31 @@ struct EpiCharacteristics {
 };
 
 template <class Epi>
-void launch(const Epi& epi, const float* coef, const Dims& d, hipStream_t s) {
+void launch(const std::string& name, double bytes, const Epi& epi, const float* coef, const Dims& d,
+            hipStream_t s) {
   const Grid3 g{d.n[0], d.n[1], d.n[2], d.P};
   dim3 grid(ceil_div(d.n[2], TX2), ceil_div(d.n[1], TX1), ceil_div(d.n[0], TX0));
-  k_brick<Epi><<<grid, NTHR, 0, s>>>(epi, coef, g);
+  prof::launch(name, bytes, 0.0, k_brick<Epi>, grid, dim3(NTHR), 0, s, epi, coef, g);
   LDDMM_LAUNCH_CHECK();
 }
 
-std::string nm(const char* base) { return std::string(base) + "<brick>"; }
+std::string nm(const char* base) { return std::string("k_brick<") + base + ">"; }
 
 }  // namespace
 
 bool brick_ok(const Dims& d) { return d.n[0] > 1; }
 
 void brick_interp(float* out, const float* coef, int nf, const float* disp, const Dims& d, hipStream_t s) {
-  prof::Scope ps_(s, nm("k_interp") + std::to_string(nf), (3.0 + 2.0 * nf) * d.P * 4, 0.0);
+  const std::string name_ = nm("k_interp") + std::to_string(nf);
+  const double bytes_ = (3.0 + 2.0 * nf) * d.P * 4;
   if (nf == 1) {
     EpiInterp<1> e;
     e.disp = disp, e.P = d.P, e.out = out;
-    launch(e, coef, d, s);
+    launch(name_, bytes_, e, coef, d, s);
   } else if (nf == 3) {
     EpiInterp<3> e;
     e.disp = disp, e.P = d.P, e.out = out;
-    launch(e, coef, d, s);
+    launch(name_, bytes_, e, coef, d, s);
   } else {
     throw ArgError("brick_interp: nf must be 1 or 3");
   }
@@ -320,15 +345,16 @@ void brick_interp(float* out, const float* coef, int nf, const float* disp, cons
 
 void brick_bl_adjoint_step(float* out, const float* cAB, int nc, const float* disp, const float* divv,
                            const Dims& d, float dt, hipStream_t s) {
-  prof::Scope ps_(s, nm("k_bl_adjoint_step") + std::to_string(nc), (4.0 + 3.0 * nc) * d.P * 4, 0.0);
+  const std::string name_ = nm("k_bl_adjoint_step") + std::to_string(nc);
+  const double bytes_ = (4.0 + 3.0 * nc) * d.P * 4;
   if (nc == 1) {
     EpiBLAdjoint<1> e;
     e.disp = disp, e.P = d.P, e.out = out, e.divv = divv, e.dt = dt;
-    launch(e, cAB, d, s);
+    launch(name_, bytes_, e, cAB, d, s);
   } else if (nc == 3) {
     EpiBLAdjoint<3> e;
     e.disp = disp, e.P = d.P, e.out = out, e.divv = divv, e.dt = dt;
-    launch(e, cAB, d, s);
+    launch(name_, bytes_, e, cAB, d, s);
   } else {
     throw ArgError("brick_bl_adjoint_step: nc must be 1 or 3");
   }
@@ -336,36 +362,40 @@ void brick_bl_adjoint_step(float* out, const float* cAB, int nc, const float* di
 
 void brick_adjoint_grid_step(float* out, const float* c12, const float* disp, const float* divv, const Dims& d,
                              float dt, hipStream_t s) {
-  prof::Scope ps_(s, nm("k_adjoint_grid_step"), 7.0 * d.P * 4, 0.0);
+  const std::string name_ = nm("k_adjoint_grid_step");
+  const double bytes_ = 7.0 * d.P * 4;
   EpiAdjointGrid e;
   e.disp = disp, e.P = d.P, e.out = out, e.divv = divv, e.dt = dt;
-  launch(e, c12, d, s);
+  launch(name_, bytes_, e, c12, d, s);
 }
 
 void brick_inc_state_v1(float* out, const float* c, const float* disp, const float* G, const float* dv,
                         const Dims& d, hipStream_t s) {
-  prof::Scope ps_(s, nm("k_inc_state_v1"), 12.0 * d.P * 4, 0.0);
+  const std::string name_ = nm("k_inc_state_v1");
+  const double bytes_ = 12.0 * d.P * 4;
   EpiIncStateV1 e;
   e.disp = disp, e.P = d.P, e.out = out, e.G = G, e.dv = dv;
-  launch(e, c, d, s);
+  launch(name_, bytes_, e, c, d, s);
 }
 
 void brick_inc_state_v3(float* out, const float* c, const float* disp, const float* Du, const float* dv,
                         const Dims& d, hipStream_t s) {
-  prof::Scope ps_(s, nm("k_inc_state_v3"), 24.0 * d.P * 4, 0.0);
+  const std::string name_ = nm("k_inc_state_v3");
+  const double bytes_ = 24.0 * d.P * 4;
   EpiIncStateV3 e;
   e.disp = disp, e.P = d.P, e.out = out, e.Du = Du, e.dv = dv;
-  launch(e, c, d, s);
+  launch(name_, bytes_, e, c, d, s);
 }
 
 void brick_characteristics(float* disp, const float* v, const float* cv, const Dims& d, float dt, int dir,
                            hipStream_t s) {
-  prof::Scope ps_(s, nm("k_characteristics"), 9.0 * d.P * 4, 0.0);
+  const std::string name_ = nm("k_characteristics");
+  const double bytes_ = 9.0 * d.P * 4;
   EpiCharacteristics e;
   e.v = v, e.disp = disp, e.P = d.P;
   e.sdt = dir > 0 ? dt : -dt;
   e.s0 = float(d.n[0]), e.s1 = float(d.n[1]), e.s2 = float(d.n[2]);
-  launch(e, cv, d, s);
+  launch(name_, bytes_, e, cv, d, s);
 }
 
 }  // namespace lddmm

@@ -280,39 +280,37 @@ void dft_left(const T* in, T* out, const FieldMats<T>& W, int nb, int bpf, int M
   const double flops = 2.0 * nb * M * (double)L * C;
   if constexpr (std::is_same_v<T, float>) {
     if (M <= 64 && L > 64 && L <= 192) {
-      prof::Scope ps_(s, M > 32 ? "dft_left_contract<2>" : "dft_left_contract<1>", bytes, flops);
       const int MB = M > 32 ? 2 : 1;
-      const size_t sm = (size_t)std::max(32 * MB * (L + 1), 4 * MB * 16 * 64) * sizeof(float);
+      const uint32_t sm = (uint32_t)std::max(32 * MB * (L + 1), 4 * MB * 16 * 64) * sizeof(float);
       dim3 g(ceil_div(C, 32), 1, nb);
       if (MB == 2)
-        dft_left_contract<2><<<g, 256, sm, s>>>(in, out, W, bpf, M, L, C, sIb, sOb);
+        prof::launch("dft_left_contract<2>", bytes, flops, dft_left_contract<2>, g, dim3(256), sm, s, in, out, W, bpf,
+                     M, L, C, sIb, sOb);
       else
-        dft_left_contract<1><<<g, 256, sm, s>>>(in, out, W, bpf, M, L, C, sIb, sOb);
+        prof::launch("dft_left_contract<1>", bytes, flops, dft_left_contract<1>, g, dim3(256), sm, s, in, out, W, bpf,
+                     M, L, C, sIb, sOb);
       LDDMM_LAUNCH_CHECK();
       return;
     }
     if (L <= 64) {
-      prof::Scope ps_(s, "dft_left_expand", bytes, flops);
-      const size_t sm = (size_t)128 * (L + 1) * sizeof(float);
+      const uint32_t sm = (uint32_t)128 * (L + 1) * sizeof(float);
       dim3 g(ceil_div(C, 32), ceil_div(M, 128), nb);
-      dft_left_expand<<<g, 256, sm, s>>>(in, out, W, bpf, M, L, C, sIb, sOb);
+      prof::launch("dft_left_expand", bytes, flops, dft_left_expand, g, dim3(256), sm, s, in, out, W, bpf, M, L, C,
+                   sIb, sOb);
       LDDMM_LAUNCH_CHECK();
       return;
     }
   }
-  const int wm = M > 64 ? 4 : (M > 32 ? 2 : 1);
-  prof::Scope ps_(s, std::string("dft_left_kernel<") + prof::tname<T>() + "," + std::to_string(wm) + "," +
-                         std::to_string(4 / wm) + ">",
-                  bytes, flops);
+  const std::string nm = std::string("dft_left_kernel<") + prof::tname<T>() + ">";
   if (M > 64) {
     dim3 g(ceil_div(C, 32), ceil_div(M, 128), nb);
-    dft_left_kernel<T, 4, 1><<<g, 256, 0, s>>>(in, out, W, bpf, M, L, C, sIb, sOb);
+    prof::launch(nm, bytes, flops, dft_left_kernel<T, 4, 1>, g, dim3(256), 0, s, in, out, W, bpf, M, L, C, sIb, sOb);
   } else if (M > 32) {
     dim3 g(ceil_div(C, 64), ceil_div(M, 64), nb);
-    dft_left_kernel<T, 2, 2><<<g, 256, 0, s>>>(in, out, W, bpf, M, L, C, sIb, sOb);
+    prof::launch(nm, bytes, flops, dft_left_kernel<T, 2, 2>, g, dim3(256), 0, s, in, out, W, bpf, M, L, C, sIb, sOb);
   } else {
     dim3 g(ceil_div(C, 128), ceil_div(M, 32), nb);
-    dft_left_kernel<T, 1, 4><<<g, 256, 0, s>>>(in, out, W, bpf, M, L, C, sIb, sOb);
+    prof::launch(nm, bytes, flops, dft_left_kernel<T, 1, 4>, g, dim3(256), 0, s, in, out, W, bpf, M, L, C, sIb, sOb);
   }
   LDDMM_LAUNCH_CHECK();
 }
@@ -320,18 +318,18 @@ void dft_left(const T* in, T* out, const FieldMats<T>& W, int nb, int bpf, int M
 template <typename T>
 void dft_right(const T* in, T* out, const FieldMats<T>& W, int nf, int R, int L, int Mo, hipStream_t s) {
   if (nf <= 0 || R <= 0 || Mo <= 0) return;
-  const int wm = Mo > 64 ? 4 : (Mo > 32 ? 2 : 1);
-  prof::Scope ps_(s, std::string("dft_right_kernel<") + prof::tname<T>() + ",1," + std::to_string(wm) + ">",
-                  double(sizeof(T)) * ((double)nf * R * L + (double)nf * R * Mo), 2.0 * nf * R * (double)L * Mo);
+  const std::string nm = std::string("dft_right_kernel<") + prof::tname<T>() + ">";
+  const double bytes = double(sizeof(T)) * ((double)nf * R * L + (double)nf * R * Mo);
+  const double flops = 2.0 * nf * R * (double)L * Mo;
   if (Mo > 64) {
     dim3 g(ceil_div(Mo, 128), ceil_div(R, 32), nf);
-    dft_right_kernel<T, 1, 4><<<g, 256, 0, s>>>(in, out, W, R, L, Mo);
+    prof::launch(nm, bytes, flops, dft_right_kernel<T, 1, 4>, g, dim3(256), 0, s, in, out, W, R, L, Mo);
   } else if (Mo > 32) {
     dim3 g(ceil_div(Mo, 64), ceil_div(R, 32), nf);
-    dft_right_kernel<T, 1, 2><<<g, 128, 0, s>>>(in, out, W, R, L, Mo);
+    prof::launch(nm, bytes, flops, dft_right_kernel<T, 1, 2>, g, dim3(128), 0, s, in, out, W, R, L, Mo);
   } else {
     dim3 g(ceil_div(Mo, 32), ceil_div(R, 32), nf);
-    dft_right_kernel<T, 1, 1><<<g, 64, 0, s>>>(in, out, W, R, L, Mo);
+    prof::launch(nm, bytes, flops, dft_right_kernel<T, 1, 1>, g, dim3(64), 0, s, in, out, W, R, L, Mo);
   }
   LDDMM_LAUNCH_CHECK();
 }

@@ -458,19 +458,19 @@ inline dim3 grid_for(int64_t n) { return dim3(ceil_div(n, kBlock)); }
 
 template <typename T>
 void bl_axpby(T* out, T a, const T* x, T b, const T* y, int64_t n, hipStream_t s) {
-  k_axpby<T><<<grid_for(n), kBlock, 0, s>>>(out, a, x, b, y, n);
+  prof::launch(std::string("k_axpby<") + prof::tname<T>() + ">", (y ? 3.0 : 2.0) * n * sizeof(T), 0.0, k_axpby<T>, grid_for(n), dim3(kBlock), 0, s, out, a, x, b, y, n);
   LDDMM_LAUNCH_CHECK();
 }
 
 template <typename T>
 void bl_scale_sym(T* out, const T* x, const double* sym, int ncomp, int64_t Q, const T* y, hipStream_t s) {
-  k_scale_sym<T><<<grid_for(Q * ncomp), kBlock, 0, s>>>(out, x, sym, ncomp, Q, y);
+  prof::launch(std::string("k_scale_sym<") + prof::tname<T>() + ">", 3.0 * Q * ncomp * sizeof(T), 0.0, k_scale_sym<T>, grid_for(Q * ncomp), dim3(kBlock), 0, s, out, x, sym, ncomp, Q, y);
   LDDMM_LAUNCH_CHECK();
 }
 
 template <typename T>
 void bl_div(T* out, const T* v, const Dims& d, hipStream_t s) {
-  k_bl_div<T><<<grid_for(d.Q), kBlock, 0, s>>>(out, v, d.k[0], d.k[1], d.k[2]);
+  prof::launch(std::string("k_bl_div<") + prof::tname<T>() + ">", 4.0 * d.Q * sizeof(T), 0.0, k_bl_div<T>, grid_for(d.Q), dim3(kBlock), 0, s, out, v, d.k[0], d.k[1], d.k[2]);
   LDDMM_LAUNCH_CHECK();
 }
 
@@ -479,8 +479,7 @@ void characteristics(T* disp, const T* v, const T* cv, const Dims& d, T dt, int 
   if constexpr (std::is_same_v<T, float>) {
     if (brick_ok(d)) return brick_characteristics(disp, v, cv, d, dt, dir, s);
   }
-  prof::Scope ps_(s, "k_characteristics<" + std::string(prof::tname<T>()) + ">", 9.0 * d.P * sizeof(T), 0.0);
-  k_characteristics<T><<<grid_for(d.P), kBlock, 0, s>>>(disp, v, cv, d.n[0], d.n[1], d.n[2], dt, dir);
+  prof::launch("k_characteristics<" + std::string(prof::tname<T>()) + ">", 9.0 * d.P * sizeof(T), 0.0, k_characteristics<T>, grid_for(d.P), dim3(kBlock), 0, s, disp, v, cv, d.n[0], d.n[1], d.n[2], dt, dir);
   LDDMM_LAUNCH_CHECK();
 }
 
@@ -489,16 +488,15 @@ void interp(T* out, const T* coef, int nf, const T* disp, const Dims& d, hipStre
   if constexpr (std::is_same_v<T, float>) {
     if (brick_ok(d) && (nf == 1 || nf == 3)) return brick_interp(out, coef, nf, disp, d, s);
   }
-  prof::Scope ps_(s, "k_interp<" + std::string(prof::tname<T>()) + "," + std::to_string(nf) + ">", (3.0 + 2.0 * nf) * d.P * sizeof(T), 0.0);
   switch (nf) {
     case 1:
-      k_interp<T, 1><<<grid_for(d.P), kBlock, 0, s>>>(out, coef, disp, d.n[0], d.n[1], d.n[2]);
+      prof::launch("k_interp<" + std::string(prof::tname<T>()) + "," + std::to_string(nf) + ">", (3.0 + 2.0 * nf) * d.P * sizeof(T), 0.0, k_interp<T, 1>, grid_for(d.P), dim3(kBlock), 0, s, out, coef, disp, d.n[0], d.n[1], d.n[2]);
       break;
     case 2:
-      k_interp<T, 2><<<grid_for(d.P), kBlock, 0, s>>>(out, coef, disp, d.n[0], d.n[1], d.n[2]);
+      prof::launch("k_interp<" + std::string(prof::tname<T>()) + "," + std::to_string(nf) + ">", (3.0 + 2.0 * nf) * d.P * sizeof(T), 0.0, k_interp<T, 2>, grid_for(d.P), dim3(kBlock), 0, s, out, coef, disp, d.n[0], d.n[1], d.n[2]);
       break;
     case 3:
-      k_interp<T, 3><<<grid_for(d.P), kBlock, 0, s>>>(out, coef, disp, d.n[0], d.n[1], d.n[2]);
+      prof::launch("k_interp<" + std::string(prof::tname<T>()) + "," + std::to_string(nf) + ">", (3.0 + 2.0 * nf) * d.P * sizeof(T), 0.0, k_interp<T, 3>, grid_for(d.P), dim3(kBlock), 0, s, out, coef, disp, d.n[0], d.n[1], d.n[2]);
       break;
     default:
       throw ArgError("interp: nf must be 1..3");
@@ -508,7 +506,6 @@ void interp(T* out, const T* coef, int nf, const T* disp, const Dims& d, hipStre
 
 template <typename T>
 void prefilter(T* f, int nf, const Dims& d, hipStream_t s) {
-  prof::Scope ps_(s, "prefilter<" + std::string(prof::tname<T>()) + ">", 6.0 * nf * d.P * sizeof(T), 0.0);
   const int n0 = d.n[0], n1 = d.n[1], n2 = d.n[2];
   if (n2 > 1) {
     const int64_t rows = (int64_t)nf * n0 * n1;
@@ -516,17 +513,20 @@ void prefilter(T* f, int nf, const Dims& d, hipStream_t s) {
     rpb = rpb > 64 ? 64 : rpb;
     if (rpb < 1) throw ArgError("prefilter: grid line too long");
     const size_t sm = (size_t)rpb * (n2 + 1) * sizeof(T);
-    k_prefilter_inner<T><<<dim3(ceil_div(rows, rpb)), 64, sm, s>>>(f, n2, rows, rpb);
+    prof::launch(std::string("k_prefilter_inner<") + prof::tname<T>() + ">", 2.0 * rows * n2 * sizeof(T), 0.0,
+                 k_prefilter_inner<T>, dim3(ceil_div(rows, rpb)), dim3(64), (uint32_t)sm, s, f, n2, rows, rpb);
     LDDMM_LAUNCH_CHECK();
   }
   if (n1 > 1) {
     const int64_t lines = (int64_t)n0 * n2;
-    k_prefilter_outer<T><<<grid_for(lines * nf), kBlock, 0, s>>>(f, n0, n1, n2, 1, lines, d.P, nf);
+    prof::launch(std::string("k_prefilter_outer<") + prof::tname<T>() + ">", 2.0 * nf * d.P * sizeof(T), 0.0,
+                 k_prefilter_outer<T>, grid_for(lines * nf), dim3(kBlock), 0, s, f, n0, n1, n2, 1, lines, d.P, nf);
     LDDMM_LAUNCH_CHECK();
   }
   if (n0 > 1) {
     const int64_t lines = (int64_t)n1 * n2;
-    k_prefilter_outer<T><<<grid_for(lines * nf), kBlock, 0, s>>>(f, n0, n1, n2, 0, lines, d.P, nf);
+    prof::launch(std::string("k_prefilter_outer<") + prof::tname<T>() + ">", 2.0 * nf * d.P * sizeof(T), 0.0,
+                 k_prefilter_outer<T>, grid_for(lines * nf), dim3(kBlock), 0, s, f, n0, n1, n2, 0, lines, d.P, nf);
     LDDMM_LAUNCH_CHECK();
   }
 }
@@ -537,8 +537,7 @@ void adjoint_grid_step(T* out, const T* c1, const T* c2, const T* disp, const T*
   if constexpr (std::is_same_v<T, float>) {
     if (brick_ok(d) && c2 == c1 + d.P) return brick_adjoint_grid_step(out, c1, disp, divv, d, dt, s);
   }
-  prof::Scope ps_(s, "k_adjoint_grid_step<" + std::string(prof::tname<T>()) + ">", 7.0 * d.P * sizeof(T), 0.0);
-  k_adjoint_grid_step<T><<<grid_for(d.P), kBlock, 0, s>>>(out, c1, c2, disp, divv, d.n[0], d.n[1], d.n[2], dt);
+  prof::launch("k_adjoint_grid_step<" + std::string(prof::tname<T>()) + ">", 7.0 * d.P * sizeof(T), 0.0, k_adjoint_grid_step<T>, grid_for(d.P), dim3(kBlock), 0, s, out, c1, c2, disp, divv, d.n[0], d.n[1], d.n[2], dt);
   LDDMM_LAUNCH_CHECK();
 }
 
@@ -548,11 +547,10 @@ void bl_adjoint_step(T* out, const T* cA, const T* cB, int nf, const T* disp, co
   if constexpr (std::is_same_v<T, float>) {
     if (brick_ok(d) && cB == cA + nf * d.P) return brick_bl_adjoint_step(out, cA, nf, disp, divv, d, dt, s);
   }
-  prof::Scope ps_(s, "k_bl_adjoint_step<" + std::string(prof::tname<T>()) + "," + std::to_string(nf) + ">", (4.0 + 3.0 * nf) * d.P * sizeof(T), 0.0);
   if (nf == 1)
-    k_bl_adjoint_step<T, 1><<<grid_for(d.P), kBlock, 0, s>>>(out, cA, cB, disp, divv, d.n[0], d.n[1], d.n[2], dt);
+    prof::launch("k_bl_adjoint_step<" + std::string(prof::tname<T>()) + "," + std::to_string(nf) + ">", (4.0 + 3.0 * nf) * d.P * sizeof(T), 0.0, k_bl_adjoint_step<T, 1>, grid_for(d.P), dim3(kBlock), 0, s, out, cA, cB, disp, divv, d.n[0], d.n[1], d.n[2], dt);
   else if (nf == 3)
-    k_bl_adjoint_step<T, 3><<<grid_for(d.P), kBlock, 0, s>>>(out, cA, cB, disp, divv, d.n[0], d.n[1], d.n[2], dt);
+    prof::launch("k_bl_adjoint_step<" + std::string(prof::tname<T>()) + "," + std::to_string(nf) + ">", (4.0 + 3.0 * nf) * d.P * sizeof(T), 0.0, k_bl_adjoint_step<T, 3>, grid_for(d.P), dim3(kBlock), 0, s, out, cA, cB, disp, divv, d.n[0], d.n[1], d.n[2], dt);
   else
     throw ArgError("bl_adjoint_step: nf must be 1 or 3");
   LDDMM_LAUNCH_CHECK();
@@ -563,8 +561,7 @@ void inc_state_v1(T* out, const T* c, const T* disp, const T* G, const T* dv, co
   if constexpr (std::is_same_v<T, float>) {
     if (brick_ok(d)) return brick_inc_state_v1(out, c, disp, G, dv, d, s);
   }
-  prof::Scope ps_(s, "k_inc_state_v1<" + std::string(prof::tname<T>()) + ">", 12.0 * d.P * sizeof(T), 0.0);
-  k_inc_state_v1<T><<<grid_for(d.P), kBlock, 0, s>>>(out, c, disp, G, dv, d.n[0], d.n[1], d.n[2]);
+  prof::launch("k_inc_state_v1<" + std::string(prof::tname<T>()) + ">", 12.0 * d.P * sizeof(T), 0.0, k_inc_state_v1<T>, grid_for(d.P), dim3(kBlock), 0, s, out, c, disp, G, dv, d.n[0], d.n[1], d.n[2]);
   LDDMM_LAUNCH_CHECK();
 }
 
@@ -573,88 +570,82 @@ void inc_state_v3(T* out, const T* c, const T* disp, const T* Du, const T* dv, c
   if constexpr (std::is_same_v<T, float>) {
     if (brick_ok(d)) return brick_inc_state_v3(out, c, disp, Du, dv, d, s);
   }
-  prof::Scope ps_(s, "k_inc_state_v3<" + std::string(prof::tname<T>()) + ">", 24.0 * d.P * sizeof(T), 0.0);
-  k_inc_state_v3<T><<<grid_for(d.P), kBlock, 0, s>>>(out, c, disp, Du, dv, d.n[0], d.n[1], d.n[2]);
+  prof::launch("k_inc_state_v3<" + std::string(prof::tname<T>()) + ">", 24.0 * d.P * sizeof(T), 0.0, k_inc_state_v3<T>, grid_for(d.P), dim3(kBlock), 0, s, out, c, disp, Du, dv, d.n[0], d.n[1], d.n[2]);
   LDDMM_LAUNCH_CHECK();
 }
 
 template <typename T>
 void v3_source(T* out, const T* Du, const T* dv, const Dims& d, hipStream_t s) {
-  prof::Scope ps_(s, "k_v3_source<" + std::string(prof::tname<T>()) + ">", 15.0 * d.P * sizeof(T), 0.0);
-  k_v3_source<T><<<grid_for(d.P), kBlock, 0, s>>>(out, Du, dv, d.P);
+  prof::launch("k_v3_source<" + std::string(prof::tname<T>()) + ">", 15.0 * d.P * sizeof(T), 0.0, k_v3_source<T>, grid_for(d.P), dim3(kBlock), 0, s, out, Du, dv, d.P);
   LDDMM_LAUNCH_CHECK();
 }
 
 template <typename T>
 void v1_source(T* out, const T* G, const T* dv, const Dims& d, hipStream_t s) {
-  prof::Scope ps_(s, "k_v1_source<" + std::string(prof::tname<T>()) + ">", 7.0 * d.P * sizeof(T), 0.0);
-  k_v1_source<T><<<grid_for(d.P), kBlock, 0, s>>>(out, G, dv, d.P);
+  prof::launch("k_v1_source<" + std::string(prof::tname<T>()) + ">", 7.0 * d.P * sizeof(T), 0.0, k_v1_source<T>, grid_for(d.P), dim3(kBlock), 0, s, out, G, dv, d.P);
   LDDMM_LAUNCH_CHECK();
 }
 
 template <typename T>
 void v1_products(T* out, const T* e, const T* divv, const T* G, const Dims& d, hipStream_t s) {
-  prof::Scope ps_(s, "k_v1_products<" + std::string(prof::tname<T>()) + ">", 9.0 * d.P * sizeof(T), 0.0);
-  k_v1_products<T><<<grid_for(d.P), kBlock, 0, s>>>(out, e, divv, G, d.P);
+  prof::launch("k_v1_products<" + std::string(prof::tname<T>()) + ">", 9.0 * d.P * sizeof(T), 0.0, k_v1_products<T>, grid_for(d.P), dim3(kBlock), 0, s, out, e, divv, G, d.P);
   LDDMM_LAUNCH_CHECK();
 }
 
 template <typename T>
 void v3_products(T* out, const T* e, const T* divv, const T* Du, const Dims& d, hipStream_t s) {
-  prof::Scope ps_(s, "k_v3_products<" + std::string(prof::tname<T>()) + ">", 19.0 * d.P * sizeof(T), 0.0);
-  k_v3_products<T><<<grid_for(d.P), kBlock, 0, s>>>(out, e, divv, Du, d.P);
+  prof::launch("k_v3_products<" + std::string(prof::tname<T>()) + ">", 19.0 * d.P * sizeof(T), 0.0, k_v3_products<T>, grid_for(d.P), dim3(kBlock), 0, s, out, e, divv, Du, d.P);
   LDDMM_LAUNCH_CHECK();
 }
 
 template <typename T>
 void final_warp(T* m1, T* g1, const T* cI0, const T* u, const Dims& d, hipStream_t s) {
-  prof::Scope ps_(s, "k_final_warp<" + std::string(prof::tname<T>()) + ">", 8.0 * d.P * sizeof(T), 0.0);
-  k_final_warp<T><<<grid_for(d.P), kBlock, 0, s>>>(m1, g1, cI0, u, d.n[0], d.n[1], d.n[2]);
+  prof::launch("k_final_warp<" + std::string(prof::tname<T>()) + ">", 8.0 * d.P * sizeof(T), 0.0, k_final_warp<T>, grid_for(d.P), dim3(kBlock), 0, s, m1, g1, cI0, u, d.n[0], d.n[1], d.n[2]);
   LDDMM_LAUNCH_CHECK();
 }
 
 template <typename T>
 void scaled_diff(T* out, T a, const T* x, const T* y, int64_t n, hipStream_t s) {
-  k_scaled_diff<T><<<grid_for(n), kBlock, 0, s>>>(out, a, x, y, n);
+  prof::launch(std::string("k_scaled_diff<") + prof::tname<T>() + ">", 3.0 * n * sizeof(T), 0.0, k_scaled_diff<T>, grid_for(n), dim3(kBlock), 0, s, out, a, x, y, n);
   LDDMM_LAUNCH_CHECK();
 }
 
 template <typename T>
 void residual_times_grad(T* out, T a, const T* x, const T* y, const T* g1, const Dims& d, hipStream_t s) {
-  k_residual_times_grad<T><<<grid_for(d.P), kBlock, 0, s>>>(out, a, x, y, g1, d.P);
+  prof::launch(std::string("k_residual_times_grad<") + prof::tname<T>() + ">", 6.0 * d.P * sizeof(T), 0.0, k_residual_times_grad<T>, grid_for(d.P), dim3(kBlock), 0, s, out, a, x, y, g1, d.P);
   LDDMM_LAUNCH_CHECK();
 }
 
 template <typename T>
 void coupling_v3(T* out, T a, const T* g1, const T* w, const Dims& d, hipStream_t s) {
-  k_coupling_v3<T><<<grid_for(d.P), kBlock, 0, s>>>(out, a, g1, w, d.P);
+  prof::launch(std::string("k_coupling_v3<") + prof::tname<T>() + ">", 9.0 * d.P * sizeof(T), 0.0, k_coupling_v3<T>, grid_for(d.P), dim3(kBlock), 0, s, out, a, g1, w, d.P);
   LDDMM_LAUNCH_CHECK();
 }
 
 template <typename T>
 void mul(T* out, const T* x, const T* y, int64_t n, hipStream_t s) {
-  k_mul<T><<<grid_for(n), kBlock, 0, s>>>(out, x, y, n);
+  prof::launch(std::string("k_mul<") + prof::tname<T>() + ">", 3.0 * n * sizeof(T), 0.0, k_mul<T>, grid_for(n), dim3(kBlock), 0, s, out, x, y, n);
   LDDMM_LAUNCH_CHECK();
 }
 
 template <typename T>
 void jacobian_det(double* out, const T* Du, int dim, int64_t P, hipStream_t s) {
   (void)dim;
-  k_jacobian<T><<<grid_for(P), kBlock, 0, s>>>(out, Du, P);
+  prof::launch(std::string("k_jacobian<") + prof::tname<T>() + ">", 9.0 * P * sizeof(T) + 8.0 * P, 0.0, k_jacobian<T>, grid_for(P), dim3(kBlock), 0, s, out, Du, P);
   LDDMM_LAUNCH_CHECK();
 }
 
 template <typename T>
 void copy_dev(T* dst, const T* src, int64_t n, hipStream_t s) {
   if (n <= 0) return;
-  k_copy<T><<<grid_for(n), kBlock, 0, s>>>(dst, src, n);
+  prof::launch(std::string("k_copy<") + prof::tname<T>() + ">", 2.0 * n * sizeof(T), 0.0, k_copy<T>, grid_for(n), dim3(kBlock), 0, s, dst, src, n);
   LDDMM_LAUNCH_CHECK();
 }
 
 template <typename T>
 void zero(T* p, int64_t n, hipStream_t s) {
   if (n <= 0) return;
-  k_zero<T><<<grid_for(n), kBlock, 0, s>>>(p, n);
+  prof::launch(std::string("k_zero<") + prof::tname<T>() + ">", 1.0 * n * sizeof(T), 0.0, k_zero<T>, grid_for(n), dim3(kBlock), 0, s, p, n);
   LDDMM_LAUNCH_CHECK();
 }
 

@@ -36,6 +36,18 @@ hipEvent_t take_event() {
 
 bool enabled() { return g_on; }
 
+bool take_events(hipEvent_t* start, hipEvent_t* stop) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  *start = take_event();
+  *stop = take_event();
+  return *start != nullptr && *stop != nullptr;
+}
+
+void record(const std::string& name, double bytes, double flops, hipEvent_t start, hipEvent_t stop) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_rec.push_back(Record{name, bytes, flops, start, stop});
+}
+
 void set_enabled(bool on) {
   std::lock_guard<std::mutex> lk(g_mu);
   g_on = on;

@@ -1,0 +1,61 @@
+"""Parity at the benchmark sizes, in the launch configuration bench.py times.
+
+* Image-transport variant at 128^3 / band 32^3 / Nt = 10 (the Hessian-matvec benchmark): state,
+  gradient and Hessian matvec against the full oracle (rel-L2 <= 1e-5).
+* Deformation-state variant at 160 x 192 x 160 / band 40 x 48 x 40: at v = 0 the Hessian and the
+  gradient have closed forms the oracle evaluates cheaply (L~ x + (2/sigma^2) pi(g1 (g1 . iota x)) and
+  pi(-(2/sigma^2)(I0 - I1) g1), g1 = grad P(I0)); checked element-wise at full size.
+"""
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import oracle_model, rel_l2
+from oracle import bspline, spectral as sp
+from paper_2006_06823_amd import lddmm_bl as L
+from paper_2006_06823_amd import synthetic as syn
+
+pytestmark = pytest.mark.gpu
+
+
+def test_variant1_128_full_oracle():
+    N, K, Nt = (128, 128, 128), (32, 32, 32), 10
+    I0, I1 = syn.phantom_pair_3d(N, seed=1, max_disp_vox=8.0)
+    ctx = L.Context(L.Problem(N, K, nt=Nt, variant=L.IMAGE_TRANSPORT, precision=L.FP32))
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda")
+    ctx.set_images(t(I0), t(I1))
+    vc = syn.random_bl_coefficients(3, K, seed=2)
+    vg = sp.include(torch.tensor(vc), N)
+    scale = torch.tensor([128.0] * 3, dtype=torch.float64).reshape(3, 1, 1, 1)
+    v = vc * (8.0 / float((vg * scale).abs().max()))
+    dv = syn.random_bl_coefficients(3, K, seed=3)
+    E, m1 = ctx.state_solve(t(v), want_m1=True)
+    g, _ = ctx.adjoint_solve()
+    h = ctx.hess_matvec(t(dv))
+    om = oracle_model(1, N, K, Nt, I0.astype(np.float64), I1.astype(np.float64))
+    om.setup(v)
+    om.state()
+    assert rel_l2(m1, om.m[-1]) <= 1e-5
+    om.adjoint()
+    assert rel_l2(g, om.gradient()) <= 1e-5
+    assert rel_l2(h, om.hess_matvec(dv)) <= 1e-5
+
+
+def test_variant3_c3_size_zero_velocity_closed_forms():
+    N, K, Nt = (160, 192, 160), (40, 48, 40), 10
+    I0, I1 = syn.phantom_pair_3d(N, seed=2, max_disp_vox=8.0)
+    ctx = L.Context(L.Problem(N, K, nt=Nt, variant=L.DEFORMATION_STATE, precision=L.FP32))
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda")
+    ctx.set_images(t(I0), t(I1))
+    ctx.state_solve(torch.zeros((3,) + K, dtype=torch.float32, device="cuda"))
+    g, _ = ctx.adjoint_solve()
+    x = syn.random_bl_coefficients(3, K, seed=4)
+    h = ctx.hess_matvec(t(x))
+    I0d = torch.tensor(I0.astype(np.float64))
+    _, gi = bspline.evaluate(bspline.prefilter(I0d, 3), bspline.grid_index(N), grad=True)
+    g1 = gi * torch.tensor([float(n) for n in N], dtype=torch.float64).reshape(3, 1, 1, 1)
+    g_ref = sp.project(-2.0 * (I0d - torch.tensor(I1.astype(np.float64))) * g1, K)
+    assert rel_l2(g, g_ref) <= 1e-5
+    xg = sp.include(torch.tensor(x), N)
+    h_ref = sp.apply_L(torch.tensor(x), 3, 0.0025, 2) + 2.0 * sp.project(g1 * (g1 * xg).sum(0), K)
+    assert rel_l2(h, h_ref) <= 1e-5

@@ -1,0 +1,52 @@
+"""Gauss-Newton-Krylov on the GPU against the oracle's driver: the 2D configuration (64^2, band 16^2,
+Nt = 10, FP64, 10 GN x 5 PCG with fixed iteration counts), both variants.
+
+Parity target: final velocity rel-L2 <= 1e-3 (the FP64 runs agree far closer, checked at 1e-8),
+identical iteration and backtracking counts, monotone energy.
+"""
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import oracle_model, rel_l2
+from oracle.gauss_newton import gauss_newton
+from paper_2006_06823_amd import lddmm_bl as L
+from paper_2006_06823_amd import synthetic as syn
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("variant", [1, 3])
+def test_gn_2d_fp64_matches_oracle(variant):
+    N, K, Nt = (64, 64), (16, 16), 10
+    I0, I1 = syn.blob_pair_2d(64, 0, 4.0)
+    ctx = L.Context(L.Problem(N, K, nt=Nt, variant=variant, precision=L.FP64))
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+    ctx.set_images(t(I0), t(I1))
+    v = torch.zeros((2,) + K, dtype=torch.float64, device="cuda")
+    st, rep = ctx.gn_solve(v, max_gn=10, max_pcg=5, fixed_iters=True)
+    om = oracle_model(variant, N, K, Nt, I0, I1)
+    vo, ro = gauss_newton(om, np.zeros((2,) + K), max_gn=10, max_pcg=5, fixed_iters=True)
+    assert rep["gn_iters"] == ro.gn_iters
+    assert rep["pcg_iters_total"] == ro.pcg_iters_total
+    assert rep["backtracks"] == ro.backtracks
+    assert rel_l2(v, vo) <= 1e-8
+    assert abs(rep["E"] - ro.E) <= 1e-8 * abs(ro.E)
+    assert rep["E"] < rep["E0"] and rep["mse_rel"] < 0.5
+    (dmin, dmax), _ = ctx.jacobian()
+    assert 0.0 < dmin <= 1.0 <= dmax
+
+
+def test_gn_3d_fp32_small_matches_oracle():
+    """FP32 3D GN (fixed 3 GN x 3 PCG) ends within rel-L2 1e-3 of the FP64 oracle's velocity."""
+    N, K, Nt = (32, 32, 32), (8, 8, 8), 5
+    I0, I1 = syn.phantom_pair_3d(N, 5, max_disp_vox=2.0)
+    ctx = L.Context(L.Problem(N, K, nt=Nt, variant=L.DEFORMATION_STATE, precision=L.FP32))
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda")
+    ctx.set_images(t(I0), t(I1))
+    v = torch.zeros((3,) + K, dtype=torch.float32, device="cuda")
+    st, rep = ctx.gn_solve(v, max_gn=3, max_pcg=3, fixed_iters=True)
+    om = oracle_model(3, N, K, Nt, I0.astype(np.float64), I1.astype(np.float64))
+    vo, ro = gauss_newton(om, np.zeros((3,) + K), max_gn=3, max_pcg=3, fixed_iters=True)
+    assert rep["backtracks"] == ro.backtracks
+    assert rel_l2(v, vo) <= 1e-3
