@@ -20,6 +20,42 @@ void dft_left_bf16(const float* in, float* out, const FieldMats<float>& W, int n
 void dft_right_bf16(const float* in, float* out, const FieldMats<float>& W, int nf, int R, int L, int Mo,
                     hipStream_t s);
 
+// fused inner-axis stages (dft_fused.hip), float
+struct IotaABArgs {
+  const float* x[kMaxFields];  // per-field band input [k0][k1][k2]
+  const float* y[kMaxFields];  // optional second input (null: none); slab = x + alpha y
+  float alpha[kMaxFields];
+  const float* w1[kMaxFields];  // [n1][k1]
+  const float* w2[kMaxFields];  // [n2][k2]
+  float* out;                   // [nf][k0][n1][n2]
+  int k0, k1, k2, n1, n2;
+};
+struct PiBAArgs {
+  const float* in;  // [nf][k0][n1][n2]
+  const float* p1;  // [k1][n1]
+  const float* p2;  // [k2][n2]
+  float* out[kMaxFields];  // per-field band output [k0][k1][k2]: out = beta out + alpha r
+  float alpha[kMaxFields];
+  float beta[kMaxFields];
+  int k0, k1, k2, n1, n2;
+};
+bool fused_dft_ok(int n1, int n2, int k1, int k2);
+void iota_ab(const IotaABArgs& a, int nf, hipStream_t s);
+void pi_ba(const PiBAArgs& a, int nf, hipStream_t s);
+
+// fused image-transport backward grid pass (fused_back.hip), float
+struct BackV1Args {
+  const float* t2;    // [k0][C] inner-axis slab of iota(dl~), C = n1 n2
+  const float* divv;  // [n0][C]
+  const float* G;     // [3][n0][C]
+  const float* B0;    // [n0][k0] axis-0 basis
+  float* out;         // [4][k0][C] axis-0 projections of e divv, e G_0, e G_1, e G_2
+  int n0, k0, C;
+  float inv_n0;
+};
+bool back_v1_ok(int n0, int k0);
+void back_v1(const BackV1Args& a, hipStream_t s);
+
 // ---- band-limited coefficient kernels (grid.hip) ----------------------------
 // out = a x + b y (n elements; y may be null when b == 0)
 template <typename T>

@@ -23,6 +23,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <type_traits>
 
 #include "prof.h"
 #include "solver.h"
@@ -239,6 +240,7 @@ class Solver final : public SolverBase {
     stk_.alloc(kMaxFields * Q);
     blA_.alloc(kMaxFields * Q);
     blB_.alloc(kMaxFields * Q);
+    blC_.alloc(kMaxFields * Q);
     acc_.alloc(3 * Q);
     vg_.alloc(3 * P);
     divv_.alloc(P);
@@ -332,6 +334,13 @@ class Solver final : public SolverBase {
   // iota of nf stacked BL fields; kinds[f][axis] picks plain / prefiltered / derivative matrices
   void iota(const T* bl, T* out, int nf, const int kinds[][3]) {
     const int n0 = d_.n[0], n1 = d_.n[1], n2 = d_.n[2], k0 = d_.k[0], k1 = d_.k[1], k2 = d_.k[2];
+    if constexpr (std::is_same_v<T, float>) {
+      if (fused_dft_ok(n1, n2, k1, k2)) {
+        const T* xs[kMaxFields];
+        for (int f = 0; f < nf; ++f) xs[f] = bl + f * d_.Q;
+        return iota_comb(xs, nullptr, nullptr, out, nf, kinds);
+      }
+    }
     FieldMats<T> W{};
     for (int f = 0; f < nf; ++f) W.w[f] = mat(2, kinds[f][2]);
     dft_right(bl, t1_.get(), W, nf, k0 * k1, k2, n2, st_);
@@ -344,13 +353,131 @@ class Solver final : public SolverBase {
       dft_left(t2_.get(), out, W, nf, 1, n0, k0, n1 * n2, (int64_t)k0 * n1 * n2, d_.P, st_);
     }
   }
+  // iota of per-field combinations x_f + alpha_f y_f (y_f may be null)
+  void iota_comb(const T* const* xs, const T* const* ys, const T* al, T* out, int nf, const int kinds[][3]) {
+    const int n0 = d_.n[0], n1 = d_.n[1], n2 = d_.n[2], k0 = d_.k[0], k1 = d_.k[1], k2 = d_.k[2];
+    const bool skip0 = (n0 == 1 && k0 == 1);
+    if constexpr (std::is_same_v<T, float>) {
+      if (fused_dft_ok(n1, n2, k1, k2)) {
+        IotaABArgs a{};
+        for (int f = 0; f < nf; ++f) {
+          a.x[f] = xs[f];
+          a.y[f] = ys ? ys[f] : nullptr;
+          a.alpha[f] = al ? al[f] : 0.f;
+          a.w1[f] = mat(1, kinds[f][1]);
+          a.w2[f] = mat(2, kinds[f][2]);
+        }
+        a.out = skip0 ? out : t2_.get();
+        a.k0 = k0, a.k1 = k1, a.k2 = k2, a.n1 = n1, a.n2 = n2;
+        iota_ab(a, nf, st_);
+        if (!skip0) {
+          FieldMats<T> W{};
+          for (int f = 0; f < nf; ++f) W.w[f] = mat(0, kinds[f][0]);
+          dft_left(t2_.get(), out, W, nf, 1, n0, k0, n1 * n2, (int64_t)k0 * n1 * n2, d_.P, st_);
+        }
+        return;
+      }
+    }
+    // generic path: stack the combinations, then the separable stages
+    for (int f = 0; f < nf; ++f) {
+      if (ys && ys[f])
+        axpby(stk_.get() + f * d_.Q, T(1), xs[f], al[f], ys[f], d_.Q);
+      else
+        copy(stk_.get() + f * d_.Q, xs[f], d_.Q);
+    }
+    iota(stk_.get(), out, nf, kinds);
+  }
+  void iota_comb_kind(const T* const* xs, const T* const* ys, const T* al, T* out, int nf, int kind) {
+    int kinds[kMaxFields][3];
+    for (int f = 0; f < nf; ++f) kinds[f][0] = kinds[f][1] = kinds[f][2] = kind;
+    iota_comb(xs, ys, al, out, nf, kinds);
+  }
+  // pi of nf stacked grid fields into per-field destinations: dst_f = beta_f dst_f + alpha_f pi(grid_f)
+  void pi_acc(const T* grid, int nf, T* const* dst, const T* alpha, const T* beta) {
+    const int n0 = d_.n[0], n1 = d_.n[1], n2 = d_.n[2], k0 = d_.k[0], k1 = d_.k[1], k2 = d_.k[2];
+    if constexpr (std::is_same_v<T, float>) {
+      if (fused_dft_ok(n1, n2, k1, k2)) {
+        const T* srcB = grid;
+        if (!(n0 == 1 && k0 == 1)) {
+          FieldMats<T> W{};
+          for (int f = 0; f < nf; ++f) W.w[f] = mat(0, kProj);
+          dft_left(grid, t1_.get(), W, nf, 1, k0, n0, n1 * n2, d_.P, (int64_t)k0 * n1 * n2, st_);
+          srcB = t1_.get();
+        }
+        PiBAArgs b{};
+        b.in = srcB;
+        b.p1 = mat(1, kProj);
+        b.p2 = mat(2, kProj);
+        for (int f = 0; f < nf; ++f) {
+          b.out[f] = dst[f];
+          b.alpha[f] = alpha[f];
+          b.beta[f] = beta[f];
+        }
+        b.k0 = k0, b.k1 = k1, b.k2 = k2, b.n1 = n1, b.n2 = n2;
+        pi_ba(b, nf, st_);
+        return;
+      }
+    }
+    pi_sep(grid, blC_.get(), nf);
+    for (int f = 0; f < nf; ++f) axpby(dst[f], beta[f], dst[f], alpha[f], blC_.get() + f * d_.Q, d_.Q);
+  }
+  void pi(const T* grid, T* bl, int nf) {
+    T* dst[kMaxFields];
+    T one[kMaxFields], zer[kMaxFields];
+    for (int f = 0; f < nf; ++f) dst[f] = bl + f * d_.Q, one[f] = T(1), zer[f] = T(0);
+    if constexpr (std::is_same_v<T, float>) {
+      if (fused_dft_ok(d_.n[1], d_.n[2], d_.k[1], d_.k[2])) return pi_acc(grid, nf, dst, one, zer);
+    }
+    pi_sep(grid, bl, nf);
+  }
+  // image-transport backward products fused with the expansion of e and the first projection stage:
+  // pi([e divv, e G0, e G1, e G2]) into dst with alpha / beta, e = iota(x). Returns false when not applicable.
+  bool fused_v1_products(const T* x, const T* Gn, T* const* dst, const T* al, const T* be) {
+    if constexpr (std::is_same_v<T, float>) {
+      const int n0 = d_.n[0], n1 = d_.n[1], n2 = d_.n[2], k0 = d_.k[0], k1 = d_.k[1], k2 = d_.k[2];
+      if (n0 > 1 && fused_dft_ok(n1, n2, k1, k2) && back_v1_ok(n0, k0)) {
+        IotaABArgs a{};
+        a.x[0] = x;
+        a.y[0] = nullptr;
+        a.alpha[0] = 0.f;
+        a.w1[0] = mat(1, kPlain);
+        a.w2[0] = mat(2, kPlain);
+        a.out = t2_.get();
+        a.k0 = k0, a.k1 = k1, a.k2 = k2, a.n1 = n1, a.n2 = n2;
+        iota_ab(a, 1, st_);
+        BackV1Args b{};
+        b.t2 = t2_.get();
+        b.divv = divv_.get();
+        b.G = Gn;
+        b.B0 = mat(0, kPlain);
+        b.out = t1_.get();
+        b.n0 = n0, b.k0 = k0, b.C = n1 * n2;
+        b.inv_n0 = 1.f / n0;
+        back_v1(b, st_);
+        PiBAArgs c{};
+        c.in = t1_.get();
+        c.p1 = mat(1, kProj);
+        c.p2 = mat(2, kProj);
+        for (int f = 0; f < 4; ++f) {
+          c.out[f] = dst[f];
+          c.alpha[f] = al[f];
+          c.beta[f] = be[f];
+        }
+        c.k0 = k0, c.k1 = k1, c.k2 = k2, c.n1 = n1, c.n2 = n2;
+        pi_ba(c, 4, st_);
+        return true;
+      }
+    }
+    (void)x, (void)Gn, (void)dst, (void)al, (void)be;
+    return false;
+  }
   void iota_kind(const T* bl, T* out, int nf, int kind) {
     int kinds[kMaxFields][3];
     for (int f = 0; f < nf; ++f) kinds[f][0] = kinds[f][1] = kinds[f][2] = kind;
     iota(bl, out, nf, kinds);
   }
-  // pi of nf stacked grid fields
-  void pi(const T* grid, T* bl, int nf) {
+  // pi of nf stacked grid fields (separable stages)
+  void pi_sep(const T* grid, T* bl, int nf) {
     const int n0 = d_.n[0], n1 = d_.n[1], n2 = d_.n[2], k0 = d_.k[0], k1 = d_.k[1], k2 = d_.k[2];
     FieldMats<T> W{};
     const T* srcB = grid;
@@ -452,8 +579,11 @@ class Solver final : public SolverBase {
     for (int n = 0; n < nt_; ++n) {
       const T* un = ubl_.get() + n * 3 * Q;
       T* un1 = ubl_.get() + (n + 1) * 3 * Q;
-      axpby(tmpbl_.get(), T(1), un, hdt, vbl_.get(), 3 * Q);
-      iota_kind(tmpbl_.get(), S(0), 3, kPref);
+      // P(u_n + dt/2 v) o X_b
+      const T* xs[3] = {un, un + Q, un + 2 * Q};
+      const T* ys[3] = {vbl_.get(), vbl_.get() + Q, vbl_.get() + 2 * Q};
+      const T al[3] = {hdt, hdt, hdt};
+      iota_comb_kind(xs, ys, al, S(0), 3, kPref);
       interp<T>(S(3), S(0), 3, Xb_.get(), d_, st_);
       pi(S(3), blA_.get(), 3);
       axpby(un1, T(1), blA_.get(), hdt, vbl_.get(), 3 * Q);
@@ -472,8 +602,10 @@ class Solver final : public SolverBase {
     const T hdt = T(0.5) * dt_;
     zero(u, 3 * Q, st_);
     for (int n = 0; n < nt_; ++n) {
-      axpby(blB_.get(), T(1), u, hdt, vbl_.get(), 3 * Q);
-      iota_kind(blB_.get(), S(0), 3, kPref);
+      const T* xs[3] = {u, u + Q, u + 2 * Q};
+      const T* ys[3] = {vbl_.get(), vbl_.get() + Q, vbl_.get() + 2 * Q};
+      const T al[3] = {hdt, hdt, hdt};
+      iota_comb_kind(xs, ys, al, S(0), 3, kPref);
       interp<T>(S(3), S(0), 3, Xb_.get(), d_, st_);
       pi(S(3), blA_.get(), 3);
       axpby(u, T(1), blA_.get(), hdt, vbl_.get(), 3 * Q);
@@ -498,12 +630,18 @@ class Solver final : public SolverBase {
     scaled_diff<T>(lam, T(-2.0 / sigma2_), m1_ptr(), I1_.get(), P, st_);
     zero(acc_.get(), 3 * Q, st_);
     for (int n = nt_; n >= 0; --n) {
-      // gradient term w_n pi(iota(pi lambda_n) G_n)
+      // gradient term w_n pi(iota(pi lambda_n) G_n), accumulated into acc
       pi(lam, tmpbl_.get(), 1);
-      iota_kind(tmpbl_.get(), S(0), 1, kPlain);
-      v1_products<T>(S(1), S(0), divv_.get(), G_.get() + n * 3 * P, d_, st_);
-      pi(S(2), blA_.get(), 3);
-      axpby(acc_.get(), T(1), acc_.get(), trap_w(n), blA_.get(), 3 * Q);
+      {
+        const T w = trap_w(n);
+        T* dst[4] = {blA_.get(), acc_.get(), acc_.get() + Q, acc_.get() + 2 * Q};
+        const T al[4] = {T(1), w, w, w}, be[4] = {T(0), T(1), T(1), T(1)};
+        if (!fused_v1_products(tmpbl_.get(), G_.get() + n * 3 * P, dst, al, be)) {
+          iota_kind(tmpbl_.get(), S(0), 1, kPlain);
+          v1_products<T>(S(1), S(0), divv_.get(), G_.get() + n * 3 * P, d_, st_);
+          pi_acc(S(1), 4, dst, al, be);
+        }
+      }
       if (n == 0) break;
       copy(S(5), lam, P);
       mul<T>(S(6), lam, divv_.get(), P, st_);
@@ -524,22 +662,37 @@ class Solver final : public SolverBase {
     for (int n = nt_; n >= 0; --n) {
       T* xn = traj + n * stride;
       iota_kind(xn, S(0), ncomp, kPlain);  // e = iota(x_n)
+      const T w = trap_w(n);
       if (variant_ == LDDMM_BL_IMAGE_TRANSPORT) {
-        v1_products<T>(S(1), S(0), divv_.get(), G_.get() + n * 3 * P, d_, st_);
-        pi(S(1), blA_.get(), 4);  // [fl, e G0, e G1, e G2]
-        axpby(acc, T(1), acc, trap_w(n), blA_.get() + Q, 3 * Q);
+        // [fl, e G0, e G1, e G2]: fl to blA, the Hessian / gradient terms accumulated into acc
+        T* dst[4] = {blA_.get(), acc, acc + Q, acc + 2 * Q};
+        const T al[4] = {T(1), w, w, w}, be[4] = {T(0), T(1), T(1), T(1)};
+        if (!fused_v1_products(xn, G_.get() + n * 3 * P, dst, al, be)) {
+          iota_kind(xn, S(0), 1, kPlain);  // e = iota(x_n)
+          v1_products<T>(S(1), S(0), divv_.get(), G_.get() + n * 3 * P, d_, st_);
+          pi_acc(S(1), 4, dst, al, be);
+        }
       } else {
         v3_products<T>(S(3), S(0), divv_.get(), Du_.get() + n * 9 * P, d_, st_);
-        pi(S(3), blA_.get(), 6);  // [fl (3), (Du)^T e (3)]
-        axpby(acc, T(1), acc, trap_w(n), xn, 3 * Q);
-        axpby(acc, T(1), acc, -trap_w(n), blA_.get() + 3 * Q, 3 * Q);
+        // [fl (3), (Du)^T e (3)]
+        T* dst[6] = {blA_.get(), blA_.get() + Q, blA_.get() + 2 * Q, acc, acc + Q, acc + 2 * Q};
+        const T al[6] = {T(1), T(1), T(1), -w, -w, -w}, be[6] = {T(0), T(0), T(0), T(1), T(1), T(1)};
+        pi_acc(S(3), 6, dst, al, be);
+        axpby(acc, T(1), acc, w, xn, 3 * Q);
       }
       if (n == 0) break;
       const T* fl = blA_.get();
       // cA = P(x + dt/2 fl), cB = P(x + dt fl), stacked
-      axpby(blB_.get(), T(1), xn, hdt, fl, stride);
-      axpby(blB_.get() + stride, T(1), xn, dt_, fl, stride);
-      iota_kind(blB_.get(), S(3), 2 * ncomp, kPref);
+      const T* xs[6];
+      const T* ys[6];
+      T al2[6];
+      for (int c = 0; c < ncomp; ++c) {
+        xs[c] = xs[ncomp + c] = xn + c * Q;
+        ys[c] = ys[ncomp + c] = fl + c * Q;
+        al2[c] = hdt;
+        al2[ncomp + c] = dt_;
+      }
+      iota_comb_kind(xs, ys, al2, S(3), 2 * ncomp, kPref);
       bl_adjoint_step<T>(S(9), S(3), S(3 + ncomp), ncomp, Xf_.get(), divv_.get(), d_, dt_, st_);
       pi(S(9), traj + (n - 1) * stride, ncomp);
     }
@@ -564,11 +717,14 @@ class Solver final : public SolverBase {
       pi(S(0), f, 1);
       zero(dm, Q, st_);
       for (int n = 0; n < nt_; ++n) {
-        axpby(tmpbl_.get(), T(1), dm + n * Q, hdt, f, Q);
-        iota_kind(tmpbl_.get(), S(0), 1, kPref);
+        const T* xs[1] = {dm + n * Q};
+        const T* ys[1] = {f};
+        const T al[1] = {hdt};
+        iota_comb_kind(xs, ys, al, S(0), 1, kPref);
         inc_state_v1<T>(S(1), S(0), Xb_.get(), G_.get() + (n + 1) * 3 * P, dvg_.get(), d_, st_);
-        pi(S(1), blA_.get(), 2);
-        copy(f, blA_.get() + Q, Q);
+        T* dst[2] = {blA_.get(), f};
+        const T one[2] = {T(1), T(1)}, zer[2] = {T(0), T(0)};
+        pi_acc(S(1), 2, dst, one, zer);
         axpby(dm + (n + 1) * Q, T(1), blA_.get(), hdt, f, Q);
       }
       T* dl = incadj_.get();
@@ -581,11 +737,15 @@ class Solver final : public SolverBase {
       pi(S(0), f, 3);
       zero(du, 3 * Q, st_);
       for (int n = 0; n < nt_; ++n) {
-        axpby(tmpbl_.get(), T(1), du + n * 3 * Q, hdt, f, 3 * Q);
-        iota_kind(tmpbl_.get(), S(0), 3, kPref);
+        const T* dun = du + n * 3 * Q;
+        const T* xs[3] = {dun, dun + Q, dun + 2 * Q};
+        const T* ys[3] = {f, f + Q, f + 2 * Q};
+        const T al[3] = {hdt, hdt, hdt};
+        iota_comb_kind(xs, ys, al, S(0), 3, kPref);
         inc_state_v3<T>(S(3), S(0), Xb_.get(), Du_.get() + (n + 1) * 9 * P, dvg_.get(), d_, st_);
-        pi(S(3), blA_.get(), 6);
-        copy(f, blA_.get() + 3 * Q, 3 * Q);
+        T* dst[6] = {blA_.get(), blA_.get() + Q, blA_.get() + 2 * Q, f, f + Q, f + 2 * Q};
+        const T one[6] = {T(1), T(1), T(1), T(1), T(1), T(1)}, zer[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
+        pi_acc(S(3), 6, dst, one, zer);
         axpby(du + (n + 1) * 3 * Q, T(1), blA_.get(), hdt, f, 3 * Q);
       }
       // t = 1 coupling: drho~(1) = pi((2/sigma^2) (g1 . iota(du~(1))) g1)
@@ -612,7 +772,7 @@ class Solver final : public SolverBase {
   DevBuf<double> Lsym_, Linv_, work_;
   std::unique_ptr<double, PinnedFree> host_;
   DevBuf<T> t1_, t2_, I0_, I1_, cI0_;
-  DevBuf<T> vbl_, dvbl_, gbl_, hbl_, tmpbl_, stk_, blA_, blB_, acc_;
+  DevBuf<T> vbl_, dvbl_, gbl_, hbl_, tmpbl_, stk_, blA_, blB_, blC_, acc_;
   DevBuf<T> vg_, divv_, Xb_, Xf_, dvg_, scratch_;
   DevBuf<T> inc_, incadj_;
   DevBuf<T> G_, m_, lam0_;               // image transport
