@@ -142,6 +142,19 @@ lddmm_bl_status lddmm_bl_hess_matvec(lddmm_bl_ctx* ctx, const void* dv_bl, void*
 lddmm_bl_status lddmm_bl_gn_solve(lddmm_bl_ctx* ctx, const lddmm_bl_gn_opts* opts, void* v_bl_inout,
                                   const void* precond_Z_or_null, int32_t r, lddmm_bl_gn_report* report);
 
+/* Batched Gauss-Newton-Krylov: `count` independent registrations (subjects with
+ * their own grid and band, per_subject[i]; FP32 or BF16_DFT precision) run in
+ * lockstep on one stream.  In every PCG iteration the Hessian matvecs of all
+ * subjects are replayed as one HIP graph launch; PCG scalars, Armijo line
+ * searches and stopping tests stay per subject.  I0[i], I1[i], v_bl_inout[i]:
+ * device buffers of subject i (layouts as above); reports: host array of
+ * `count` (may be NULL).  Returns LDDMM_BL_W_LINESEARCH if any subject's line
+ * search failed (that subject's velocity is left at its last accepted value). */
+lddmm_bl_status lddmm_bl_gn_solve_batched(const lddmm_bl_params* per_subject, int32_t count, const void* const* I0,
+                                          const void* const* I1, void* const* v_bl_inout,
+                                          const lddmm_bl_gn_opts* opts, void* hip_stream,
+                                          lddmm_bl_gn_report* reports);
+
 /* Jacobian determinant det(I - D iota(u~(1))) of phi(1) = id - iota(u~(1))
  * (Sections 2.3.2-2.3.3) at the velocity of the last state solve, evaluated
  * in double.  detmap_or_null: device double grid; minmax: host double[2]. */

@@ -5,6 +5,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "prof.h"
 #include "solver.h"
@@ -120,6 +121,36 @@ lddmm_bl_status lddmm_bl_gn_solve(lddmm_bl_ctx* ctx, const lddmm_bl_gn_opts* opt
     if (!opts || !v_bl_inout) throw lddmm::ArgError("null options or velocity");
     return ctx->solver->gn_solve(*opts, v_bl_inout, precond_Z_or_null, r, report);
   });
+}
+
+lddmm_bl_status lddmm_bl_gn_solve_batched(const lddmm_bl_params* per_subject, int32_t count, const void* const* I0,
+                                          const void* const* I1, void* const* v_bl_inout,
+                                          const lddmm_bl_gn_opts* opts, void* hip_stream,
+                                          lddmm_bl_gn_report* reports) {
+  if (!per_subject || count < 1 || count > 4096 || !I0 || !I1 || !v_bl_inout || !opts) return LDDMM_BL_E_ARG;
+  if (!hip_stream) return LDDMM_BL_E_ARG;  // graphs need a non-default stream
+  try {
+    std::vector<std::unique_ptr<lddmm::SolverBase>> owned;
+    std::vector<lddmm::SolverBase*> subs;
+    for (int i = 0; i < count; ++i) {
+      if (per_subject[i].precision == LDDMM_BL_FP64) return LDDMM_BL_E_ARG;
+      owned.push_back(lddmm::make_solver(per_subject[i], static_cast<hipStream_t>(hip_stream)));
+      owned.back()->set_images(I0[i], I1[i]);
+      subs.push_back(owned.back().get());
+    }
+    return static_cast<lddmm_bl_status>(
+        lddmm::gn_solve_batched(subs, *opts, v_bl_inout, reports, static_cast<hipStream_t>(hip_stream)));
+  } catch (const lddmm::ArgError&) {
+    return LDDMM_BL_E_ARG;
+  } catch (const lddmm::StateError&) {
+    return LDDMM_BL_E_STATE;
+  } catch (const lddmm::NonFiniteError&) {
+    return LDDMM_BL_E_NONFINITE;
+  } catch (const std::bad_alloc&) {
+    return LDDMM_BL_E_OOM;
+  } catch (...) {
+    return LDDMM_BL_E_HIP;
+  }
 }
 
 lddmm_bl_status lddmm_bl_jacobian(lddmm_bl_ctx* ctx, void* detmap_or_null, double* minmax) {

@@ -269,7 +269,180 @@ __global__ __launch_bounds__(256) void dft_left_expand(const float* __restrict__
   }
 }
 
+// ---- split-bf16 variants (precision LDDMM_BL_BF16_DFT) --------------------------------
+// Every float operand x is split into bf16 hi = rn(x) and lo = rn(x - hi); a product
+// is formed as hi*hi + hi*lo + lo*hi on the bf16 matrix cores (v_mfma_f32_32x32x16_bf16,
+// 16-deep contraction per instruction) with float accumulation, which keeps about 16
+// significant bits per operand at a third of the instruction count of the float path.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ unsigned short bf16_rn(float x) {
+  const unsigned int b = __float_as_uint(x);
+  return static_cast<unsigned short>((b + 0x7FFFu + ((b >> 16) & 1u)) >> 16);
+}
+
+__device__ __forceinline__ void split8(const float v[8], bf16x8& hi, bf16x8& lo) {
+  u16x8 h, l;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const unsigned short hb = bf16_rn(v[j]);
+    h[j] = hb;
+    l[j] = bf16_rn(v[j] - __uint_as_float(static_cast<unsigned int>(hb) << 16));
+  }
+  hi = __builtin_bit_cast(bf16x8, h);
+  lo = __builtin_bit_cast(bf16x8, l);
+}
+
+__device__ __forceinline__ f32x16 mma3(const bf16x8& ah, const bf16x8& al, const bf16x8& bh, const bf16x8& bl,
+                                       f32x16 acc) {
+  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, acc, 0, 0, 0);
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, acc, 0, 0, 0);
+}
+
+template <int MB>
+__global__ __launch_bounds__(256) void dft_left_contract_bf16(const float* __restrict__ in, float* __restrict__ out,
+                                                              FieldMats<float> mats, int bpf, int M, int L, int C,
+                                                              int64_t sIb, int64_t sOb) {
+  extern __shared__ float smem[];
+  const int ldw = L + 1;
+  float* Ws = smem;
+  float* red = smem;
+  const int b = blockIdx.z;
+  const float* __restrict__ W = mats.w[b / bpf];
+  in += b * sIb;
+  out += b * sOb;
+  const int c0 = blockIdx.x * 32;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int e = tid; e < 32 * MB * L; e += 256) {
+    const int m = e / L, l = e - m * L;
+    Ws[m * ldw + l] = m < M ? W[(int64_t)m * L + l] : 0.f;
+  }
+  __syncthreads();
+  const int seg = ((L + 63) / 64) * 16;  // per-wave range, a multiple of 16
+  const int lb = wave * seg, le = min(L, lb + seg);
+  const int c = c0 + (lane & 31);
+  const bool cok = c < C;
+  const int kh = lane >> 5;
+  f32x16 acc[MB];
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[mb][r] = 0.f;
+  for (int kk = lb; kk < le; kk += 16) {
+    float bv[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int l = kk + 8 * kh + j;
+      bv[j] = (cok && l < le) ? in[(int64_t)l * C + c] : 0.f;
+    }
+    bf16x8 bh, bl;
+    split8(bv, bh, bl);
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb) {
+      float av[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int l = kk + 8 * kh + j;
+        av[j] = l < le ? Ws[(mb * 32 + (lane & 31)) * ldw + l] : 0.f;
+      }
+      bf16x8 ah, al;
+      split8(av, ah, al);
+      acc[mb] = mma3(ah, al, bh, bl, acc[mb]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) red[((wave * MB + mb) * 16 + r) * 64 + lane] = acc[mb][r];
+  __syncthreads();
+  for (int e = tid; e < MB * 16 * 64; e += 256) {
+    const int ln = e & 63, r = (e >> 6) & 15, mb = e >> 10;
+    float sum = 0.f;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) sum += red[((w * MB + mb) * 16 + r) * 64 + ln];
+    const int m = mb * 32 + acc_row(r, ln), cc = c0 + (ln & 31);
+    if (m < M && cc < C) out[(int64_t)m * C + cc] = sum;
+  }
+}
+
+__global__ __launch_bounds__(256) void dft_left_expand_bf16(const float* __restrict__ in, float* __restrict__ out,
+                                                            FieldMats<float> mats, int bpf, int M, int L, int C,
+                                                            int64_t sIb, int64_t sOb) {
+  extern __shared__ float smem[];
+  const int ldw = L + 1;
+  float* Ws = smem;  // [128][L + 1]
+  const int b = blockIdx.z;
+  const float* __restrict__ W = mats.w[b / bpf];
+  in += b * sIb;
+  out += b * sOb;
+  const int c0 = blockIdx.x * 32, m0 = blockIdx.y * 128;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int e = tid; e < 128 * L; e += 256) {
+    const int mm = e / L, l = e - mm * L;
+    Ws[mm * ldw + l] = (m0 + mm) < M ? W[(int64_t)(m0 + mm) * L + l] : 0.f;
+  }
+  __syncthreads();
+  const int mw = m0 + wave * 32;
+  if (mw >= M) return;
+  const int c = c0 + (lane & 31);
+  const bool cok = c < C;
+  const int kh = lane >> 5;
+  f32x16 acc;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+  const float* Wr = Ws + (wave * 32 + (lane & 31)) * ldw;
+  for (int kk = 0; kk < L; kk += 16) {
+    float av[8], bv[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int l = kk + 8 * kh + j;
+      bv[j] = (cok && l < L) ? in[(int64_t)l * C + c] : 0.f;
+      av[j] = l < L ? Wr[l] : 0.f;
+    }
+    bf16x8 ah, al, bh, bl;
+    split8(av, ah, al);
+    split8(bv, bh, bl);
+    acc = mma3(ah, al, bh, bl, acc);
+  }
+  if (cok) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int m = mw + acc_row(r, lane);
+      if (m < M) out[(int64_t)m * C + c] = acc[r];
+    }
+  }
+}
+
 }  // namespace
+
+void dft_left_bf16(const float* in, float* out, const FieldMats<float>& W, int nb, int bpf, int M, int L, int C,
+                   int64_t sIb, int64_t sOb, hipStream_t s) {
+  if (nb <= 0 || M <= 0 || C <= 0) return;
+  const double bytes = 4.0 * ((double)nb * L * C + (double)nb * M * C);
+  const double flops = 2.0 * nb * M * (double)L * C;
+  if (M <= 64 && L > 64 && L <= 192) {
+    const int MB = M > 32 ? 2 : 1;
+    const uint32_t sm = (uint32_t)std::max(32 * MB * (L + 1), 4 * MB * 16 * 64) * sizeof(float);
+    dim3 g(ceil_div(C, 32), 1, nb);
+    if (MB == 2)
+      prof::launch("dft_left_contract_bf16<2>", bytes, flops, dft_left_contract_bf16<2>, g, dim3(256), sm, s, in, out,
+                   W, bpf, M, L, C, sIb, sOb);
+    else
+      prof::launch("dft_left_contract_bf16<1>", bytes, flops, dft_left_contract_bf16<1>, g, dim3(256), sm, s, in, out,
+                   W, bpf, M, L, C, sIb, sOb);
+  } else if (L <= 64) {
+    const uint32_t sm = (uint32_t)128 * (L + 1) * sizeof(float);
+    dim3 g(ceil_div(C, 32), ceil_div(M, 128), nb);
+    prof::launch("dft_left_expand_bf16", bytes, flops, dft_left_expand_bf16, g, dim3(256), sm, s, in, out, W, bpf, M,
+                 L, C, sIb, sOb);
+  } else {
+    return dft_left<float>(in, out, W, nb, bpf, M, L, C, sIb, sOb, s);
+  }
+  LDDMM_LAUNCH_CHECK();
+}
 
 template <typename T>
 void dft_left(const T* in, T* out, const FieldMats<T>& W, int nb, int bpf, int M, int L, int C, int64_t sIb,

@@ -82,6 +82,7 @@ class Solver final : public SolverBase {
     alpha_ = p.alpha;
     s_ = p.s;
     sigma2_ = p.sigma2;
+    bf16_ = std::is_same_v<T, float> && p.precision == LDDMM_BL_BF16_DFT;
     build_matrices();
     allocate();
   }
@@ -331,6 +332,14 @@ class Solver final : public SolverBase {
   }
 
   // ------------------------------------------------ truncated DFT (Section 2.2)
+  // axis contraction for the first-axis stages: float or split-bf16 matrix cores
+  void left(const T* in, T* out, const FieldMats<T>& W, int nb, int bpf, int M, int L, int C, int64_t sIb,
+            int64_t sOb, hipStream_t s) {
+    if constexpr (std::is_same_v<T, float>) {
+      if (bf16_) return dft_left_bf16(in, out, W, nb, bpf, M, L, C, sIb, sOb, s);
+    }
+    dft_left<T>(in, out, W, nb, bpf, M, L, C, sIb, sOb, s);
+  }
   // iota of nf stacked BL fields; kinds[f][axis] picks plain / prefiltered / derivative matrices
   void iota(const T* bl, T* out, int nf, const int kinds[][3]) {
     const int n0 = d_.n[0], n1 = d_.n[1], n2 = d_.n[2], k0 = d_.k[0], k1 = d_.k[1], k2 = d_.k[2];
@@ -347,10 +356,10 @@ class Solver final : public SolverBase {
     const bool skip0 = (n0 == 1 && k0 == 1);
     T* dstB = skip0 ? out : t2_.get();
     for (int f = 0; f < nf; ++f) W.w[f] = mat(1, kinds[f][1]);
-    dft_left(t1_.get(), dstB, W, nf * k0, k0, n1, k1, n2, (int64_t)k1 * n2, (int64_t)n1 * n2, st_);
+    left(t1_.get(), dstB, W, nf * k0, k0, n1, k1, n2, (int64_t)k1 * n2, (int64_t)n1 * n2, st_);
     if (!skip0) {
       for (int f = 0; f < nf; ++f) W.w[f] = mat(0, kinds[f][0]);
-      dft_left(t2_.get(), out, W, nf, 1, n0, k0, n1 * n2, (int64_t)k0 * n1 * n2, d_.P, st_);
+      left(t2_.get(), out, W, nf, 1, n0, k0, n1 * n2, (int64_t)k0 * n1 * n2, d_.P, st_);
     }
   }
   // iota of per-field combinations x_f + alpha_f y_f (y_f may be null)
@@ -373,7 +382,7 @@ class Solver final : public SolverBase {
         if (!skip0) {
           FieldMats<T> W{};
           for (int f = 0; f < nf; ++f) W.w[f] = mat(0, kinds[f][0]);
-          dft_left(t2_.get(), out, W, nf, 1, n0, k0, n1 * n2, (int64_t)k0 * n1 * n2, d_.P, st_);
+          left(t2_.get(), out, W, nf, 1, n0, k0, n1 * n2, (int64_t)k0 * n1 * n2, d_.P, st_);
         }
         return;
       }
@@ -401,7 +410,7 @@ class Solver final : public SolverBase {
         if (!(n0 == 1 && k0 == 1)) {
           FieldMats<T> W{};
           for (int f = 0; f < nf; ++f) W.w[f] = mat(0, kProj);
-          dft_left(grid, t1_.get(), W, nf, 1, k0, n0, n1 * n2, d_.P, (int64_t)k0 * n1 * n2, st_);
+          left(grid, t1_.get(), W, nf, 1, k0, n0, n1 * n2, d_.P, (int64_t)k0 * n1 * n2, st_);
           srcB = t1_.get();
         }
         PiBAArgs b{};
@@ -435,7 +444,7 @@ class Solver final : public SolverBase {
   bool fused_v1_products(const T* x, const T* Gn, T* const* dst, const T* al, const T* be) {
     if constexpr (std::is_same_v<T, float>) {
       const int n0 = d_.n[0], n1 = d_.n[1], n2 = d_.n[2], k0 = d_.k[0], k1 = d_.k[1], k2 = d_.k[2];
-      if (n0 > 1 && fused_dft_ok(n1, n2, k1, k2) && back_v1_ok(n0, k0)) {
+      if (!bf16_ && n0 > 1 && fused_dft_ok(n1, n2, k1, k2) && back_v1_ok(n0, k0)) {
         IotaABArgs a{};
         a.x[0] = x;
         a.y[0] = nullptr;
@@ -483,11 +492,11 @@ class Solver final : public SolverBase {
     const T* srcB = grid;
     if (!(n0 == 1 && k0 == 1)) {
       for (int f = 0; f < nf; ++f) W.w[f] = mat(0, kProj);
-      dft_left(grid, t1_.get(), W, nf, 1, k0, n0, n1 * n2, d_.P, (int64_t)k0 * n1 * n2, st_);
+      left(grid, t1_.get(), W, nf, 1, k0, n0, n1 * n2, d_.P, (int64_t)k0 * n1 * n2, st_);
       srcB = t1_.get();
     }
     for (int f = 0; f < nf; ++f) W.w[f] = mat(1, kProj);
-    dft_left(srcB, t2_.get(), W, nf * k0, k0, k1, n1, n2, (int64_t)n1 * n2, (int64_t)k1 * n2, st_);
+    left(srcB, t2_.get(), W, nf * k0, k0, k1, n1, n2, (int64_t)n1 * n2, (int64_t)k1 * n2, st_);
     for (int f = 0; f < nf; ++f) W.w[f] = mat(2, kProj);
     dft_right(t2_.get(), bl, W, nf, k0 * k1, n2, k2, st_);
   }
@@ -766,6 +775,11 @@ class Solver final : public SolverBase {
   double alpha_ = 0, sigma2_ = 1;
   bool have_images_ = false, state_valid_ = false;
   bool graphs_enabled_ = std::getenv("LDDMM_BL_NO_GRAPH") == nullptr;
+  bool bf16_ = false;  // split-bf16 contractions for the first-axis DFT stages
+
+  template <typename U>
+  friend int gn_solve_batched_impl(std::vector<Solver<U>*>& subs, const lddmm_bl_gn_opts& o,
+                                   void* const* v_user, lddmm_bl_gn_report* reps, hipStream_t st);
   hipGraphExec_t mv_exec_ = nullptr;
   int64_t mat_off_[3][4] = {};
   DevBuf<T> mats_;
@@ -1041,9 +1055,201 @@ int Solver<T>::gn_solve(const lddmm_bl_gn_opts& o, void* v_user, const void* Zu,
   return status;
 }
 
+// ---------------------------------------------------- batched Gauss-Newton-Krylov
+// Several subjects (each with its own grid and band) registered in lockstep on one
+// stream.  The Hessian matvecs of every subject in a PCG iteration are captured
+// once into a single HIP graph and replayed with one launch per iteration; the PCG
+// scalars, line searches and stopping tests stay per subject.  A subject that has
+// converged (or whose PCG has stopped) keeps its results; its slot in the graph is
+// still computed and ignored.
+template <typename T>
+int gn_solve_batched_impl(std::vector<Solver<T>*>& subs, const lddmm_bl_gn_opts& o, void* const* v_user,
+                          lddmm_bl_gn_report* reps, hipStream_t st) {
+  const int B = static_cast<int>(subs.size());
+  const auto t0 = std::chrono::steady_clock::now();
+  struct Sub {
+    DevBuf<T> v, g, x, r, z, vt;
+    double E = 0, ginf = 0, ref = 0, gnorm0 = 0, rz = 0, tol = 0;
+    bool converged = false, failed = false, pcg_done = false;
+    lddmm_bl_gn_report R{};
+  };
+  std::vector<Sub> S(B);
+  const bool fixed = o.fixed_iters != 0;
+  for (int i = 0; i < B; ++i) {
+    Solver<T>& sv = *subs[i];
+    if (!sv.have_images_) throw StateError("set_images must precede the batched solve");
+    const int64_t n = sv.vec_len();
+    S[i].v.alloc(n), S[i].g.alloc(n), S[i].x.alloc(n), S[i].r.alloc(n), S[i].z.alloc(n), S[i].vt.alloc(n);
+    sv.user_to_internal(S[i].v.get(), static_cast<const T*>(v_user[i]));
+    sv.set_velocity_internal(S[i].v.get());
+    double e[3];
+    sv.state_internal(e);
+    S[i].E = S[i].R.E0 = e[0];
+    sv.adjoint_internal(S[i].g.get());
+    S[i].ginf = sv.grad_inf_internal(S[i].g.get());
+    S[i].ref = o.grad_ref_inf > 0 ? o.grad_ref_inf : S[i].ginf;
+    S[i].gnorm0 = std::sqrt(sv.dot_internal(S[i].g.get(), S[i].g.get()));
+  }
+  // one graph with every subject's Hessian matvec (p in dvbl_, H p in hbl_); eager while profiling
+  hipGraphExec_t exec = nullptr;
+  const bool use_graph = !prof::enabled();
+  if (use_graph) {
+    hipGraph_t graph = nullptr;
+    LDDMM_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    try {
+      for (int i = 0; i < B; ++i) subs[i]->run_matvec(subs[i]->dvbl_.get(), subs[i]->hbl_.get());
+    } catch (...) {
+      (void)hipStreamEndCapture(st, &graph);
+      if (graph) (void)hipGraphDestroy(graph);
+      throw;
+    }
+    LDDMM_HIP(hipStreamEndCapture(st, &graph));
+    const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) throw HipError(std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
+  struct ExecGuard {
+    hipGraphExec_t e;
+    ~ExecGuard() {
+      if (e) (void)hipGraphExecDestroy(e);
+    }
+  } guard{exec};
+  for (int k = 0; k < o.max_gn; ++k) {
+    bool any = false;
+    for (int i = 0; i < B; ++i) {
+      Sub& u = S[i];
+      if (u.failed || u.converged) continue;
+      if (!fixed && u.ginf <= o.grad_rtol * u.ref) {
+        u.converged = true;
+        continue;
+      }
+      any = true;
+    }
+    if (!any) break;
+    // PCG in lockstep
+    for (int i = 0; i < B; ++i) {
+      Sub& u = S[i];
+      Solver<T>& sv = *subs[i];
+      u.pcg_done = u.failed || u.converged;
+      if (u.pcg_done) continue;
+      const double gnorm = std::sqrt(sv.dot_internal(u.g.get(), u.g.get()));
+      const double eta = u.gnorm0 > 0 ? std::min(0.5, std::sqrt(gnorm / u.gnorm0)) : 0.5;
+      u.tol = eta * gnorm;
+      zero(u.x.get(), sv.vec_len(), st);
+      sv.axpby_internal(u.r.get(), T(-1), u.g.get(), T(0), nullptr);
+      sv.precond_internal(u.r.get(), u.z.get());
+      sv.copy_internal(sv.dvbl_.get(), u.z.get());
+      u.rz = sv.dot_internal(u.r.get(), u.z.get());
+    }
+    for (int it = 0; it < o.max_pcg; ++it) {
+      bool iterate = false;
+      for (int i = 0; i < B; ++i) {
+        Sub& u = S[i];
+        if (u.pcg_done) continue;
+        const double rn = std::sqrt(subs[i]->dot_internal(u.r.get(), u.r.get()));
+        if (!fixed && rn <= u.tol) {
+          u.pcg_done = true;
+          continue;
+        }
+        iterate = true;
+      }
+      if (!iterate) break;
+      if (use_graph) {
+        LDDMM_HIP(hipGraphLaunch(exec, st));
+      } else {
+        for (int i = 0; i < B; ++i) subs[i]->run_matvec(subs[i]->dvbl_.get(), subs[i]->hbl_.get());
+      }
+      for (int i = 0; i < B; ++i) {
+        Sub& u = S[i];
+        Solver<T>& sv = *subs[i];
+        if (u.pcg_done) continue;
+        ++u.R.hess_matvecs;
+        ++u.R.pcg_iters_total;
+        T* p = sv.dvbl_.get();
+        const T* Ap = sv.hbl_.get();
+        const double pAp = sv.dot_internal(p, Ap);
+        if (!std::isfinite(pAp)) throw NonFiniteError("non-finite curvature in batched PCG");
+        if (pAp <= 0.0) {
+          --u.R.pcg_iters_total;
+          if (it == 0) sv.copy_internal(u.x.get(), p);
+          u.pcg_done = true;
+          continue;
+        }
+        const double a = u.rz / pAp;
+        sv.axpby_internal(u.x.get(), T(1), u.x.get(), T(a), p);
+        sv.axpby_internal(u.r.get(), T(1), u.r.get(), T(-a), Ap);
+        sv.precond_internal(u.r.get(), u.z.get());
+        const double rz_new = sv.dot_internal(u.r.get(), u.z.get());
+        sv.axpby_internal(p, T(1), u.z.get(), T(rz_new / u.rz), p);
+        u.rz = rz_new;
+      }
+    }
+    // Armijo line search per subject
+    for (int i = 0; i < B; ++i) {
+      Sub& u = S[i];
+      Solver<T>& sv = *subs[i];
+      if (u.failed || u.converged) continue;
+      const double gd = sv.dot_internal(u.g.get(), u.x.get());
+      double eps = 1.0, Et = u.E, e[3];
+      bool accepted = false;
+      for (int bt = 0; bt <= 10; ++bt) {
+        sv.axpby_internal(u.vt.get(), T(1), u.v.get(), T(eps), u.x.get());
+        sv.set_velocity_internal(u.vt.get());
+        sv.state_internal(e);
+        Et = e[0];
+        if (Et <= u.E + 1e-4 * eps * gd) {
+          accepted = true;
+          break;
+        }
+        ++u.R.backtracks;
+        eps *= 0.5;
+      }
+      if (!accepted) {
+        sv.set_velocity_internal(u.v.get());
+        sv.state_internal(e);
+        u.failed = true;
+        continue;
+      }
+      sv.copy_internal(u.v.get(), u.vt.get());
+      u.E = Et;
+      sv.adjoint_internal(u.g.get());
+      u.ginf = sv.grad_inf_internal(u.g.get());
+      u.R.gn_iters = k + 1;
+    }
+  }
+  int status = LDDMM_BL_OK;
+  for (int i = 0; i < B; ++i) {
+    Sub& u = S[i];
+    Solver<T>& sv = *subs[i];
+    sv.internal_to_user(static_cast<T*>(v_user[i]), u.v.get());
+    u.R.E = u.E;
+    u.R.grad_inf_rel = u.ref > 0 ? u.ginf / u.ref : 0.0;
+    u.R.mse_rel = sv.mse_rel();
+    if (u.failed) status = LDDMM_BL_W_LINESEARCH;
+  }
+  LDDMM_HIP(hipStreamSynchronize(st));
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  for (int i = 0; i < B; ++i) {
+    S[i].R.seconds = secs;
+    if (reps) reps[i] = S[i].R;
+  }
+  return status;
+}
+
+int gn_solve_batched(std::vector<SolverBase*>& subs, const lddmm_bl_gn_opts& o, void* const* v_user,
+                     lddmm_bl_gn_report* reps, hipStream_t st) {
+  std::vector<Solver<float>*> f;
+  for (auto* b : subs) {
+    auto* s = dynamic_cast<Solver<float>*>(b);
+    if (!s) throw ArgError("batched solves take float (FP32 or BF16_DFT) subjects");
+    f.push_back(s);
+  }
+  return gn_solve_batched_impl<float>(f, o, v_user, reps, st);
+}
+
 std::unique_ptr<SolverBase> make_solver(const lddmm_bl_params& p, hipStream_t s) {
   if (p.precision == LDDMM_BL_FP64) return std::make_unique<Solver<double>>(p, s);
-  if (p.precision == LDDMM_BL_FP32) return std::make_unique<Solver<float>>(p, s);
+  if (p.precision == LDDMM_BL_FP32 || p.precision == LDDMM_BL_BF16_DFT) return std::make_unique<Solver<float>>(p, s);
   throw ArgError("unsupported precision");
 }
 

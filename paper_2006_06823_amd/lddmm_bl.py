@@ -34,7 +34,7 @@ EXPORTS = [
     "lddmm_bl_create", "lddmm_bl_destroy", "lddmm_bl_last_error", "lddmm_bl_set_images",
     "lddmm_bl_state_solve", "lddmm_bl_adjoint_solve", "lddmm_bl_hess_matvec", "lddmm_bl_gn_solve",
     "lddmm_bl_jacobian", "lddmm_bl_project", "lddmm_bl_include", "lddmm_bl_get_field", "lddmm_bl_dot",
-    "lddmm_bl_profile_enable", "lddmm_bl_profile_read",
+    "lddmm_bl_profile_enable", "lddmm_bl_profile_read", "lddmm_bl_gn_solve_batched",
 ]
 
 
@@ -89,6 +89,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "lddmm_bl_include": [vp, vp, vp, i32],
         "lddmm_bl_get_field": [vp, i32, i32, vp, ctypes.POINTER(i64)],
         "lddmm_bl_dot": [vp, vp, vp, i64, dp],
+        "lddmm_bl_gn_solve_batched": [ctypes.POINTER(Params), i32, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                      ctypes.POINTER(vp), ctypes.POINTER(GNOpts), vp, ctypes.POINTER(GNReport)],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -125,6 +127,44 @@ class Problem:
     s: int = 2
     sigma2: float = 1.0
     precision: int = FP32
+
+
+def make_params(prob: "Problem") -> Params:
+    p = Params()
+    d = len(prob.n)
+    p.dim = d
+    for j in range(3):
+        p.n[j] = int(prob.n[j]) if j < d else 1
+        p.k[j] = int(prob.k[j]) if j < d else 1
+    p.nt, p.variant, p.alpha, p.s, p.sigma2, p.precision = (
+        prob.nt, prob.variant, prob.alpha, prob.s, prob.sigma2, prob.precision)
+    return p
+
+
+def gn_solve_batched(problems, I0s, I1s, vs, max_gn=10, max_pcg=5, grad_rtol=1e-3, grad_ref_inf=0.0,
+                     fixed_iters=False, device=None):
+    """Batched Gauss-Newton-Krylov over subjects of uneven sizes (velocities updated in place).
+
+    Returns (status, [report dict per subject]).  All tensors float32 on one ROCm device.
+    """
+    lib = load_library()
+    B = len(problems)
+    dev = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+    for t in list(I0s) + list(I1s) + list(vs):
+        if t.dtype != torch.float32 or t.device.type != "cuda" or not t.is_contiguous():
+            raise TypeError("batched tensors must be contiguous float32 ROCm tensors")
+    params = (Params * B)(*[make_params(p) for p in problems])
+    arr = lambda ts: (ctypes.c_void_p * B)(*[t.data_ptr() for t in ts])
+    opts = GNOpts(max_gn, max_pcg, grad_rtol, grad_ref_inf, 1 if fixed_iters else 0)
+    reps = (GNReport * B)()
+    stream = torch.cuda.Stream(device=dev)
+    stream.wait_stream(torch.cuda.current_stream(dev))
+    st = lib.lddmm_bl_gn_solve_batched(params, B, arr(I0s), arr(I1s), arr(vs), ctypes.byref(opts),
+                                       ctypes.c_void_p(stream.cuda_stream), reps)
+    if st < 0:
+        raise LddmmError(st, "lddmm_bl_gn_solve_batched failed")
+    torch.cuda.current_stream(dev).wait_stream(stream)
+    return st, [reps[i].as_dict() for i in range(B)]
 
 
 class Context:

@@ -145,3 +145,28 @@ def test_dot_fp64_reduction():
     got = ctx.dot(torch.tensor(a, device="cuda"), torch.tensor(b, device="cuda"))
     ref = float(np.dot(a.astype(np.float64), b.astype(np.float64)))
     assert abs(got - ref) <= 1e-12 * np.sqrt(len(a)) * max(1.0, abs(ref))
+
+
+@pytest.mark.parametrize("variant", [1, 3])
+def test_bf16_dft_error_vs_oracle(variant):
+    """Split-bf16 truncated DFT (first-axis stages on bf16 matrix cores, float accumulation): the errors
+    against the FP64 oracle are stated, not held to the float tolerance; the bound here (5e-4) is what
+    the 16-bit-per-operand split guarantees with margin for 10-step sweeps."""
+    N, K, Nt = (40, 36, 44), (12, 10, 14), 4
+    I0, I1 = images(N, 0)
+    ctx = L.Context(L.Problem(N, K, nt=Nt, variant=variant, precision=L.BF16_DFT))
+    ctx.set_images(dev(I0, ctx), dev(I1, ctx))
+    v = velocity(N, K, Nt, 1)
+    om = oracle_model(variant, N, K, Nt, I0, I1)
+    E, m1 = ctx.state_solve(dev(v, ctx), want_m1=True)
+    om.setup(v)
+    om.state()
+    g, _ = ctx.adjoint_solve()
+    om.adjoint()
+    from paper_2006_06823_amd import synthetic as syn
+    dv = syn.random_bl_coefficients(3, K, 11)
+    h = ctx.hess_matvec(dev(dv, ctx))
+    errs = {"m1": rel_l2(m1, om.m[-1] if variant == 1 else om.m1), "grad": rel_l2(g, om.gradient()),
+            "hess": rel_l2(h, om.hess_matvec(dv))}
+    print("bf16 split-DFT rel-L2 errors", variant, errs)
+    assert max(errs.values()) <= 5e-4
