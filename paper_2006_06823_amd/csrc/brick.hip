@@ -14,16 +14,27 @@
 // SL-RK2 step update of each equation into the same pass.
 #include "kernels.h"
 #include "prof.h"
+#include "tune.h"
 
 namespace lddmm {
 
 namespace {
 
-constexpr int TX0 = 4, TX1 = 8, TX2 = 32, HALO = 2;
-constexpr int B0 = TX0 + 2 * HALO, B1 = TX1 + 2 * HALO, B2 = TX2 + 2 * HALO;
-constexpr int VOL = B0 * B1 * B2;
-constexpr int NTHR = 256;
-constexpr int PPT = TX0 * TX1 * TX2 / NTHR;  // nodes per thread
+constexpr int HALO = 2;
+
+// Output tile of one workgroup; the autotuner picks one of these per grid shape.
+template <int X0, int X1, int X2, int NT>
+struct Tile {
+  static constexpr int TX0 = X0, TX1 = X1, TX2 = X2, NTHR = NT;
+  static constexpr int B0 = TX0 + 2 * HALO, B1 = TX1 + 2 * HALO, B2 = TX2 + 2 * HALO;
+  static constexpr int VOL = B0 * B1 * B2;
+  static constexpr int PPT = TX0 * TX1 * TX2 / NTHR;  // nodes per thread
+};
+using TileA = Tile<4, 8, 32, 256>;
+using TileB = Tile<8, 8, 32, 512>;
+using TileC = Tile<2, 16, 32, 256>;
+using TileD = Tile<4, 4, 64, 256>;
+constexpr int kTiles = 4;
 
 struct Grid3 {
   int n0, n1, n2;
@@ -36,6 +47,7 @@ __device__ __forceinline__ int wrapi(int i, int n) {
 }
 
 // 64-tap evaluation from the LDS brick; s* are brick-relative first-tap indices
+template <int B1, int B2>
 __device__ __forceinline__ float eval_brick(const float* __restrict__ br, int s0, int s1, int s2, const float w0[4],
                                             const float w1[4], const float w2[4]) {
   float acc = 0.f;
@@ -83,8 +95,10 @@ __device__ __noinline__ float eval_global(const float* __restrict__ c, float x0,
 //   emit(p, const State&)        writes the node's results.
 // The B-spline weights of a node are computed once per group and shared by the
 // group's fields.
-template <class Epi>
-__global__ __launch_bounds__(NTHR) void k_brick(Epi epi, const float* __restrict__ coef, Grid3 g) {
+template <class Epi, class TL>
+__global__ __launch_bounds__(TL::NTHR) void k_brick(Epi epi, const float* __restrict__ coef, Grid3 g) {
+  constexpr int TX0 = TL::TX0, TX1 = TL::TX1, TX2 = TL::TX2, NTHR = TL::NTHR, PPT = TL::PPT;
+  constexpr int B0 = TL::B0, B1 = TL::B1, B2 = TL::B2, VOL = TL::VOL;
   constexpr int GS = Epi::GSIZE;
   __shared__ float br[GS * VOL];
   __shared__ int rowoff[B0 * B1];  // wrapped (i0, i1) row offsets of the brick
@@ -139,7 +153,7 @@ __global__ __launch_bounds__(NTHR) void k_brick(Epi epi, const float* __restrict
         bspline_weights(x[j][2] - f2, w2);
 #pragma unroll
         for (int k = 0; k < GS; ++k)
-          epi.accum(st[j], Epi::field(grp, k), eval_brick(br + k * VOL, s0, s1, s2, w0, w1, w2));
+          epi.accum(st[j], Epi::field(grp, k), eval_brick<B1, B2>(br + k * VOL, s0, s1, s2, w0, w1, w2));
       } else {
 #pragma unroll
         for (int k = 0; k < GS; ++k) {
@@ -312,12 +326,35 @@ struct EpiCharacteristics : OneGroup<3> {
   }
 };
 
+template <class Epi, class TL>
+void launch_tile(const std::string& name, double bytes, const Epi& epi, const float* coef, const Grid3& g,
+                 hipStream_t s) {
+  dim3 grid(ceil_div(g.n2, TL::TX2), ceil_div(g.n1, TL::TX1), ceil_div(g.n0, TL::TX0));
+  prof::launch(name, bytes, 0.0, k_brick<Epi, TL>, grid, dim3(TL::NTHR), 0, s, epi, coef, g);
+}
+
+std::string shape_key(const Dims& d) {
+  return "brick:" + std::to_string(d.n[0]) + "x" + std::to_string(d.n[1]) + "x" + std::to_string(d.n[2]);
+}
+
 template <class Epi>
 void launch(const std::string& name, double bytes, const Epi& epi, const float* coef, const Dims& d,
-            hipStream_t s) {
+            hipStream_t s, int tile = -1) {
   const Grid3 g{d.n[0], d.n[1], d.n[2], d.P};
-  dim3 grid(ceil_div(d.n[2], TX2), ceil_div(d.n[1], TX1), ceil_div(d.n[0], TX0));
-  prof::launch(name, bytes, 0.0, k_brick<Epi>, grid, dim3(NTHR), 0, s, epi, coef, g);
+  if (tile < 0) tile = tune::get(shape_key(d), 0);
+  switch (tile) {
+    case 1:
+      launch_tile<Epi, TileB>(name, bytes, epi, coef, g, s);
+      break;
+    case 2:
+      launch_tile<Epi, TileC>(name, bytes, epi, coef, g, s);
+      break;
+    case 3:
+      launch_tile<Epi, TileD>(name, bytes, epi, coef, g, s);
+      break;
+    default:
+      launch_tile<Epi, TileA>(name, bytes, epi, coef, g, s);
+  }
   LDDMM_LAUNCH_CHECK();
 }
 
@@ -326,6 +363,15 @@ std::string nm(const char* base) { return std::string("k_brick<") + base + ">"; 
 }  // namespace
 
 bool brick_ok(const Dims& d) { return d.n[0] > 1; }
+
+void brick_autotune(float* out, const float* coef, const float* disp, const Dims& d, hipStream_t s) {
+  const std::string key = shape_key(d);
+  if (tune::get(key, -1) >= 0) return;
+  EpiInterp<1> e;
+  e.disp = disp, e.P = d.P, e.out = out;
+  const int best = tune::pick(kTiles, [&](int c) { launch("tune", 0.0, e, coef, d, s, c); }, s);
+  tune::set(key, best);
+}
 
 void brick_interp(float* out, const float* coef, int nf, const float* disp, const Dims& d, hipStream_t s) {
   const std::string name_ = nm("k_interp") + std::to_string(nf);

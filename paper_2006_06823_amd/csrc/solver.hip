@@ -85,6 +85,18 @@ class Solver final : public SolverBase {
     bf16_ = std::is_same_v<T, float> && p.precision == LDDMM_BL_BF16_DFT;
     build_matrices();
     allocate();
+    autotune();
+  }
+
+  // Pick the brick tile for this grid shape once per process (timed on zeroed scratch fields).
+  void autotune() {
+    if constexpr (std::is_same_v<T, float>) {
+      if (!brick_ok(d_) || std::getenv("LDDMM_BL_NO_TUNE")) return;
+      zero(S(0), 2 * d_.P, st_);
+      zero(Xb_.get(), 3 * d_.P, st_);
+      brick_autotune(S(1), S(0), Xb_.get(), d_, st_);
+      sync();
+    }
   }
 
   // ---------------------------------------------------------------- API ops
@@ -360,7 +372,15 @@ class Solver final : public SolverBase {
     if (!skip0) {
       for (int f = 0; f < nf; ++f) W.w[f] = mat(0, kinds[f][0]);
       left(t2_.get(), out, W, nf, 1, n0, k0, n1 * n2, (int64_t)k0 * n1 * n2, d_.P, st_);
+    } else {
+      zero_degenerate_derivatives(out, nf, kinds);
     }
+  }
+  // A 2D problem skips the 1 x 1 stage of its degenerate first axis; that stage is the identity
+  // except for a derivative along the axis, which vanishes: such fields are zero.
+  void zero_degenerate_derivatives(T* out, int nf, const int kinds[][3]) {
+    for (int f = 0; f < nf; ++f)
+      if (kinds[f][0] == kDeriv) zero(out + f * d_.P, d_.P, st_);
   }
   // iota of per-field combinations x_f + alpha_f y_f (y_f may be null)
   void iota_comb(const T* const* xs, const T* const* ys, const T* al, T* out, int nf, const int kinds[][3]) {
@@ -383,6 +403,8 @@ class Solver final : public SolverBase {
           FieldMats<T> W{};
           for (int f = 0; f < nf; ++f) W.w[f] = mat(0, kinds[f][0]);
           left(t2_.get(), out, W, nf, 1, n0, k0, n1 * n2, (int64_t)k0 * n1 * n2, d_.P, st_);
+        } else {
+          zero_degenerate_derivatives(out, nf, kinds);
         }
         return;
       }
@@ -428,7 +450,12 @@ class Solver final : public SolverBase {
       }
     }
     pi_sep(grid, blC_.get(), nf);
-    for (int f = 0; f < nf; ++f) axpby(dst[f], beta[f], dst[f], alpha[f], blC_.get() + f * d_.Q, d_.Q);
+    for (int f = 0; f < nf; ++f) {
+      if (beta[f] == T(0))
+        axpby(dst[f], alpha[f], blC_.get() + f * d_.Q, T(0), nullptr, d_.Q);  // never reads dst
+      else
+        axpby(dst[f], beta[f], dst[f], alpha[f], blC_.get() + f * d_.Q, d_.Q);
+    }
   }
   void pi(const T* grid, T* bl, int nf) {
     T* dst[kMaxFields];
@@ -776,6 +803,7 @@ class Solver final : public SolverBase {
   bool have_images_ = false, state_valid_ = false;
   bool graphs_enabled_ = std::getenv("LDDMM_BL_NO_GRAPH") == nullptr;
   bool bf16_ = false;  // split-bf16 contractions for the first-axis DFT stages
+  bool trace_ = std::getenv("LDDMM_BL_TRACE") != nullptr;  // Gauss-Newton scalars to stderr
 
   template <typename U>
   friend int gn_solve_batched_impl(std::vector<Solver<U>*>& subs, const lddmm_bl_gn_opts& o,
@@ -1007,6 +1035,7 @@ int Solver<T>::gn_solve(const lddmm_bl_gn_opts& o, void* v_user, const void* Zu,
         break;
       }
       const double a = rz / pAp;
+      if (trace_) fprintf(stderr, "[lddmm_bl] gn %d pcg %d rz %.17g pAp %.17g a %.17g\n", k, its, rz, pAp, a);
       axpby_internal(x.get(), T(1), x.get(), T(a), p.get());
       axpby_internal(rr.get(), T(1), rr.get(), T(-a), Ap.get());
       precond(rr.get(), z.get());
@@ -1025,6 +1054,7 @@ int Solver<T>::gn_solve(const lddmm_bl_gn_opts& o, void* v_user, const void* Zu,
       set_velocity_internal(vt.get());
       state_internal(e);
       Et = e[0];
+      if (trace_) fprintf(stderr, "[lddmm_bl] gn %d ls eps %.17g E %.17g Et %.17g gd %.17g\n", k, eps, E, Et, gd);
       if (Et <= E + 1e-4 * eps * gd) {
         accepted = true;
         break;

@@ -170,3 +170,20 @@ def test_bf16_dft_error_vs_oracle(variant):
             "hess": rel_l2(h, om.hess_matvec(dv))}
     print("bf16 split-DFT rel-L2 errors", variant, errs)
     assert max(errs.values()) <= 5e-4
+
+
+@pytest.mark.parametrize("dim,N,K,Nt,precision", CASES)
+def test_jacobian_parity(dim, N, K, Nt, precision):
+    """det(I - D iota(u~(1))) in double on the device vs the oracle, element-wise (both variants'
+    contexts; the image-transport one integrates u~ on demand)."""
+    from oracle.gauss_newton import displacement_state, jacobian_det
+    from oracle.problem import Problem as OP
+    for variant in (1, 3):
+        ctx, om, v = make(variant, dim, N, K, Nt, precision, cfl=1.5)
+        ctx.state_solve(dev(v, ctx))
+        (dmin, dmax), det = ctx.jacobian(want_map=True)
+        prob = OP(tuple(N), tuple(K), Nt=Nt)
+        ref = jacobian_det(prob, displacement_state(prob, v))
+        tol_abs = 1e-10 if precision == L.FP64 else 2e-5
+        assert float((det.cpu() - ref).abs().max()) <= tol_abs
+        assert abs(dmin - float(ref.min())) <= tol_abs and abs(dmax - float(ref.max())) <= tol_abs
