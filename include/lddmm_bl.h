@@ -187,6 +187,29 @@ lddmm_bl_status lddmm_bl_get_field(lddmm_bl_ctx* ctx, int32_t which, int32_t ind
  * dot = sum a_i b_i over n elements of the context's element type. */
 lddmm_bl_status lddmm_bl_dot(lddmm_bl_ctx* ctx, const void* a, const void* b, int64_t n, double* dot);
 
+/* Learned warm start and low-rank preconditioner (a small 3D convolutional network
+ * trained on registrations the method itself computes).  `levels` 3^3 convolutions
+ * (padding 1, ReLU; stride 2 except the last) with channels[0..levels-1] on a
+ * 2-channel input of in_size^3 voxels (the image pair, [B][2][S][S][S] float), then
+ * a 1^3 head to out_channels.  The head output [B][out_channels][s][s][s],
+ * s = in_size / 2^(levels-1), is read as band-limited velocity coefficients in the
+ * real-basis layout (3 channels per predicted field).  Kernels: bf16 matrix-core
+ * implicit-GEMM convolutions with float accumulation; float master weights; Adam.
+ * forward keeps the activations for backward; backward accumulates parameter
+ * gradients (zero_grad clears them); get copies parameters (which = 0) or their
+ * gradients (which = 1) to host (nparam floats), set loads parameters from host. */
+typedef struct lddmm_nn_ctx lddmm_nn_ctx;
+lddmm_bl_status lddmm_nn_create(int32_t levels, const int32_t* channels, int32_t in_size, int32_t out_channels,
+                                uint64_t seed, void* hip_stream, lddmm_nn_ctx** out);
+lddmm_bl_status lddmm_nn_info(lddmm_nn_ctx* ctx, int32_t* out_size, int32_t* out_channels, int64_t* nparam);
+lddmm_bl_status lddmm_nn_forward(lddmm_nn_ctx* ctx, const void* in, int32_t B, void* out);
+lddmm_bl_status lddmm_nn_backward(lddmm_nn_ctx* ctx, const void* dout, int32_t B);
+lddmm_bl_status lddmm_nn_zero_grad(lddmm_nn_ctx* ctx);
+lddmm_bl_status lddmm_nn_step(lddmm_nn_ctx* ctx, double lr);
+lddmm_bl_status lddmm_nn_get(lddmm_nn_ctx* ctx, int32_t which, void* host_dst);
+lddmm_bl_status lddmm_nn_set(lddmm_nn_ctx* ctx, const void* host_src);
+lddmm_bl_status lddmm_nn_destroy(lddmm_nn_ctx* ctx);
+
 /* Per-kernel timing for measurement tools (process-wide).  While enabled,
  * every kernel launch of the library is bracketed with HIP events on its
  * stream and its algorithmic bytes and flops are recorded (enabling clears

@@ -1,0 +1,23 @@
+// Small 3D convolutional network of the learned warm start (see nn.hip).
+#pragma once
+
+#include "common.h"
+
+namespace lddmm {
+
+struct ConvLayer {
+  int cin = 0, cout = 0, k = 3, stride = 1, pad = 1, relu = 1;
+  float *w = nullptr, *b = nullptr;    // float masters [cout][cin][k^3], [cout]
+  float *dw = nullptr, *db = nullptr;  // gradients
+  float *mw = nullptr, *vw = nullptr, *mb = nullptr, *vb = nullptr;  // Adam moments
+  int64_t nw() const { return (int64_t)cout * cin * k * k * k; }
+};
+
+void conv_forward(const ConvLayer& L, const float* x, float* y, int B, int Di, hipStream_t s);
+// g: scratch of y's size; dx may be null (first layer)
+void conv_backward(const ConvLayer& L, const float* x, const float* y, const float* dy, float* g, float* dx, int B,
+                   int Di, hipStream_t s);
+void adam_step(float* w, float* m, float* v, const float* g, int64_t n, float lr, int t, hipStream_t s);
+void fill(float* p, int64_t n, float v, hipStream_t s);
+
+}  // namespace lddmm
