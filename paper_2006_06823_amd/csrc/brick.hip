@@ -64,6 +64,27 @@ __device__ __forceinline__ float eval_brick(const float* __restrict__ br, int s0
   return acc;
 }
 
+// two fields stored interleaved (float2): one LDS read per tap serves both
+template <int B1, int B2>
+__device__ __forceinline__ float2 eval_brick2(const float2* __restrict__ br, int s0, int s1, int s2, const float w0[4],
+                                              const float w1[4], const float w2[4]) {
+  float ax = 0.f, ay = 0.f;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    float sx = 0.f, sy = 0.f;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const float2* row = br + ((s0 + a) * B1 + (s1 + b)) * B2 + s2;
+      const float2 r0 = row[0], r1 = row[1], r2 = row[2], r3 = row[3];
+      sx += w1[b] * (w2[0] * r0.x + w2[1] * r1.x + w2[2] * r2.x + w2[3] * r3.x);
+      sy += w1[b] * (w2[0] * r0.y + w2[1] * r1.y + w2[2] * r2.y + w2[3] * r3.y);
+    }
+    ax += w0[a] * sx;
+    ay += w0[a] * sy;
+  }
+  return make_float2(ax, ay);
+}
+
 __device__ __noinline__ float eval_global(const float* __restrict__ c, float x0, float x1, float x2,
                                              const Grid3& g) {
   int i0[4], i1[4], i2[4];
@@ -100,7 +121,7 @@ __global__ __launch_bounds__(TL::NTHR) void k_brick(Epi epi, const float* __rest
   constexpr int TX0 = TL::TX0, TX1 = TL::TX1, TX2 = TL::TX2, NTHR = TL::NTHR, PPT = TL::PPT;
   constexpr int B0 = TL::B0, B1 = TL::B1, B2 = TL::B2, VOL = TL::VOL;
   constexpr int GS = Epi::GSIZE;
-  __shared__ float br[GS * VOL];
+  __shared__ __align__(16) float br[GS * VOL];
   __shared__ int rowoff[B0 * B1];  // wrapped (i0, i1) row offsets of the brick
   __shared__ int colidx[B2];       // wrapped i2 of the brick columns
   const int t0 = blockIdx.z * TX0, t1 = blockIdx.y * TX1, t2 = blockIdx.x * TX2;
@@ -135,8 +156,13 @@ __global__ __launch_bounds__(TL::NTHR) void k_brick(Epi epi, const float* __rest
     for (int e = tid; e < VOL; e += NTHR) {
       const int row = e / B2, b2 = e - row * B2;
       const int off = rowoff[row] + colidx[b2];
+      if constexpr (GS == 2) {  // interleaved pair
+        reinterpret_cast<float2*>(br)[e] =
+            make_float2(coef[Epi::field(grp, 0) * g.P + off], coef[Epi::field(grp, 1) * g.P + off]);
+      } else {
 #pragma unroll
-      for (int k = 0; k < GS; ++k) br[k * VOL + e] = coef[Epi::field(grp, k) * g.P + off];
+        for (int k = 0; k < GS; ++k) br[k * VOL + e] = coef[Epi::field(grp, k) * g.P + off];
+      }
     }
     __syncthreads();
 #pragma unroll
@@ -151,9 +177,15 @@ __global__ __launch_bounds__(TL::NTHR) void k_brick(Epi epi, const float* __rest
         bspline_weights(x[j][0] - f0, w0);
         bspline_weights(x[j][1] - f1, w1);
         bspline_weights(x[j][2] - f2, w2);
+        if constexpr (GS == 2) {
+          const float2 v = eval_brick2<B1, B2>(reinterpret_cast<const float2*>(br), s0, s1, s2, w0, w1, w2);
+          epi.accum(st[j], Epi::field(grp, 0), v.x);
+          epi.accum(st[j], Epi::field(grp, 1), v.y);
+        } else {
 #pragma unroll
-        for (int k = 0; k < GS; ++k)
-          epi.accum(st[j], Epi::field(grp, k), eval_brick<B1, B2>(br + k * VOL, s0, s1, s2, w0, w1, w2));
+          for (int k = 0; k < GS; ++k)
+            epi.accum(st[j], Epi::field(grp, k), eval_brick<B1, B2>(br + k * VOL, s0, s1, s2, w0, w1, w2));
+        }
       } else {
 #pragma unroll
         for (int k = 0; k < GS; ++k) {

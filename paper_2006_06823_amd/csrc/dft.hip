@@ -172,56 +172,63 @@ __global__ __launch_bounds__(64 * WR * WM) void dft_right_kernel(const T* __rest
 template <int MB>
 __global__ __launch_bounds__(256) void dft_left_contract(const float* __restrict__ in, float* __restrict__ out,
                                                          FieldMats<float> mats, int bpf, int M, int L, int C,
-                                                         int64_t sIb, int64_t sOb) {
+                                                         int64_t sIb, int64_t sOb, int separate_red) {
   extern __shared__ float smem[];
   const int ldw = L + 1;
-  float* Ws = smem;   // [32 MB][L + 1]
-  float* red = smem;  // [4][MB][16][64], reuses the W tile after the contraction
+  float* Ws = smem;                                          // [32 MB][L + 1]
+  float* red = separate_red ? smem + 32 * MB * ldw : smem;   // [4][MB][16][64]
   const int b = blockIdx.z;
   const float* __restrict__ W = mats.w[b / bpf];
   in += b * sIb;
   out += b * sOb;
-  const int c0 = blockIdx.x * 32;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int e = tid; e < 32 * MB * L; e += 256) {
-    const int m = e / L, l = e - m * L;
-    Ws[m * ldw + l] = m < M ? W[(int64_t)m * L + l] : 0.f;
-  }
-  __syncthreads();
   // this wave's contraction range (even length, so each k-step pairs two rows)
   const int seg = ((L + 7) / 8) * 2;
   const int lb = wave * seg, le = min(L, lb + seg);
-  const int c = c0 + (lane & 31);
-  const bool cok = c < C;
   const int kh = lane >> 5;
-  f32x16 acc[MB];
-#pragma unroll
-  for (int mb = 0; mb < MB; ++mb)
-#pragma unroll
-    for (int r = 0; r < 16; ++r) acc[mb][r] = 0.f;
-#pragma unroll 8
-  for (int kk = lb; kk < le; kk += 2) {
-    const int l = kk + kh;
-    const float bv = (cok && l < le) ? in[(int64_t)l * C + c] : 0.f;
-#pragma unroll
-    for (int mb = 0; mb < MB; ++mb) {
-      const float av = l < le ? Ws[(mb * 32 + (lane & 31)) * ldw + l] : 0.f;
-      acc[mb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc[mb], 0, 0, 0);
+  const int ncb = (C + 31) / 32;
+  // without a separate reduction buffer the W tile is reloaded per column block
+  for (int cb = blockIdx.x; cb < ncb; cb += gridDim.x) {
+    if (cb == blockIdx.x || !separate_red) {
+      __syncthreads();
+      for (int e = tid; e < 32 * MB * L; e += 256) {
+        const int m = e / L, l = e - m * L;
+        Ws[m * ldw + l] = m < M ? W[(int64_t)m * L + l] : 0.f;
+      }
+      __syncthreads();
     }
-  }
-  __syncthreads();  // every wave is done reading W
+    const int c0 = cb * 32;
+    const int c = c0 + (lane & 31);
+    const bool cok = c < C;
+    f32x16 acc[MB];
 #pragma unroll
-  for (int mb = 0; mb < MB; ++mb)
+    for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-    for (int r = 0; r < 16; ++r) red[((wave * MB + mb) * 16 + r) * 64 + lane] = acc[mb][r];
-  __syncthreads();
-  for (int e = tid; e < MB * 16 * 64; e += 256) {
-    const int ln = e & 63, r = (e >> 6) & 15, mb = e >> 10;
-    float sum = 0.f;
+      for (int r = 0; r < 16; ++r) acc[mb][r] = 0.f;
+#pragma unroll 8
+    for (int kk = lb; kk < le; kk += 2) {
+      const int l = kk + kh;
+      const float bv = (cok && l < le) ? in[(int64_t)l * C + c] : 0.f;
 #pragma unroll
-    for (int w = 0; w < 4; ++w) sum += red[((w * MB + mb) * 16 + r) * 64 + ln];
-    const int m = mb * 32 + acc_row(r, ln), cc = c0 + (ln & 31);
-    if (m < M && cc < C) out[(int64_t)m * C + cc] = sum;
+      for (int mb = 0; mb < MB; ++mb) {
+        const float av = l < le ? Ws[(mb * 32 + (lane & 31)) * ldw + l] : 0.f;
+        acc[mb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc[mb], 0, 0, 0);
+      }
+    }
+    __syncthreads();  // W reads done (aliased case) / previous reduction consumed
+#pragma unroll
+    for (int mb = 0; mb < MB; ++mb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) red[((wave * MB + mb) * 16 + r) * 64 + lane] = acc[mb][r];
+    __syncthreads();
+    for (int e = tid; e < MB * 16 * 64; e += 256) {
+      const int ln = e & 63, r = (e >> 6) & 15, mb = e >> 10;
+      float sum = 0.f;
+#pragma unroll
+      for (int w = 0; w < 4; ++w) sum += red[((w * MB + mb) * 16 + r) * 64 + ln];
+      const int m = mb * 32 + acc_row(r, ln), cc = c0 + (ln & 31);
+      if (m < M && cc < C) out[(int64_t)m * C + cc] = sum;
+    }
   }
 }
 
@@ -237,7 +244,7 @@ __global__ __launch_bounds__(256) void dft_left_expand(const float* __restrict__
   const float* __restrict__ W = mats.w[b / bpf];
   in += b * sIb;
   out += b * sOb;
-  const int c0 = blockIdx.x * 32, m0 = blockIdx.y * 128;
+  const int m0 = blockIdx.y * 128;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int e = tid; e < 128 * L; e += 256) {
     const int mm = e / L, l = e - mm * L;
@@ -246,25 +253,29 @@ __global__ __launch_bounds__(256) void dft_left_expand(const float* __restrict__
   __syncthreads();
   const int mw = m0 + wave * 32;
   if (mw >= M) return;
-  const int c = c0 + (lane & 31);
-  const bool cok = c < C;
   const int kh = lane >> 5;
-  f32x16 acc;
-#pragma unroll
-  for (int r = 0; r < 16; ++r) acc[r] = 0.f;
   const float* Wr = Ws + (wave * 32 + (lane & 31)) * ldw;
-#pragma unroll 8
-  for (int kk = 0; kk < L; kk += 2) {
-    const int l = kk + kh;
-    const float bv = (cok && l < L) ? in[(int64_t)l * C + c] : 0.f;
-    const float av = l < L ? Wr[l] : 0.f;
-    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
-  }
-  if (cok) {
+  const int ncb = (C + 31) / 32;
+  // the W tile stays in LDS while the block walks several column blocks
+  for (int cb = blockIdx.x; cb < ncb; cb += gridDim.x) {
+    const int c = cb * 32 + (lane & 31);
+    const bool cok = c < C;
+    f32x16 acc;
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int m = mw + acc_row(r, lane);
-      if (m < M) out[(int64_t)m * C + c] = acc[r];
+    for (int r = 0; r < 16; ++r) acc[r] = 0.f;
+#pragma unroll 8
+    for (int kk = 0; kk < L; kk += 2) {
+      const int l = kk + kh;
+      const float bv = (cok && l < L) ? in[(int64_t)l * C + c] : 0.f;
+      const float av = l < L ? Wr[l] : 0.f;
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
+    }
+    if (cok) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int m = mw + acc_row(r, lane);
+        if (m < M) out[(int64_t)m * C + c] = acc[r];
+      }
     }
   }
 }
@@ -454,20 +465,26 @@ void dft_left(const T* in, T* out, const FieldMats<T>& W, int nb, int bpf, int M
   if constexpr (std::is_same_v<T, float>) {
     if (M <= 64 && L > 64 && L <= 192) {
       const int MB = M > 32 ? 2 : 1;
-      const uint32_t sm = (uint32_t)std::max(32 * MB * (L + 1), 4 * MB * 16 * 64) * sizeof(float);
-      dim3 g(ceil_div(C, 32), 1, nb);
+      const size_t wsz = (size_t)32 * MB * (L + 1), rsz = (size_t)4 * MB * 16 * 64;
+      const int sep = (wsz + rsz) * sizeof(float) <= 65536 ? 1 : 0;
+      const uint32_t sm = (uint32_t)((sep ? wsz + rsz : std::max(wsz, rsz)) * sizeof(float));
+      const int ncb = ceil_div(C, 32);
+      const int gx = sep ? std::max(1, std::min(ncb, 1024 / std::max(1, nb))) : ncb;
+      dim3 g(gx, 1, nb);
       if (MB == 2)
         prof::launch("dft_left_contract<2>", bytes, flops, dft_left_contract<2>, g, dim3(256), sm, s, in, out, W, bpf,
-                     M, L, C, sIb, sOb);
+                     M, L, C, sIb, sOb, sep);
       else
         prof::launch("dft_left_contract<1>", bytes, flops, dft_left_contract<1>, g, dim3(256), sm, s, in, out, W, bpf,
-                     M, L, C, sIb, sOb);
+                     M, L, C, sIb, sOb, sep);
       LDDMM_LAUNCH_CHECK();
       return;
     }
     if (L <= 64) {
       const uint32_t sm = (uint32_t)128 * (L + 1) * sizeof(float);
-      dim3 g(ceil_div(C, 32), ceil_div(M, 128), nb);
+      const int ncb = ceil_div(C, 32), gy = ceil_div(M, 128);
+      const int gx = std::max(1, std::min(ncb, 1024 / std::max(1, nb * gy)));
+      dim3 g(gx, gy, nb);
       prof::launch("dft_left_expand", bytes, flops, dft_left_expand, g, dim3(256), sm, s, in, out, W, bpf, M, L, C,
                    sIb, sOb);
       LDDMM_LAUNCH_CHECK();

@@ -53,7 +53,7 @@ __global__ __launch_bounds__(256) void k_iota_ab(IotaABArgs a) {
   }
   __syncthreads();
   // stage 1: T[a1][x2] = sum_a2 S[a1][a2] W2[x2][a2]
-  const float* __restrict__ W2 = a.w2[f];
+  const float* __restrict__ W2t = a.w2t[f];  // [k2][n2]
   const int mb1 = (k1 + 31) / 32, nb = (n2 + 31) / 32;
   for (int tile = wave; tile < mb1 * nb; tile += 4) {
     const int mb = tile / nb, cb = tile - mb * nb;
@@ -63,7 +63,7 @@ __global__ __launch_bounds__(256) void k_iota_ab(IotaABArgs a) {
     for (int kk = 0; kk < k2; kk += 2) {
       const int l = kk + kh;
       const float av = (arow < k1 && l < k2) ? S[arow * lds + l] : 0.f;
-      const float bv = (x2 < n2 && l < k2) ? W2[(int64_t)x2 * k2 + l] : 0.f;
+      const float bv = (x2 < n2 && l < k2) ? W2t[(int64_t)l * n2 + x2] : 0.f;
       acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
     }
 #pragma unroll
@@ -74,7 +74,7 @@ __global__ __launch_bounds__(256) void k_iota_ab(IotaABArgs a) {
   }
   __syncthreads();
   // stage 2: out[x1][x2] = sum_a1 W1[x1][a1] T[a1][x2], x1 in [x1b, x1b + 64)
-  const float* __restrict__ W1 = a.w1[f];
+  const float* __restrict__ W1t = a.w1t[f];  // [k1][n1]
   float* out = a.out + ((int64_t)f * k0 + a0) * n1 * n2;
   for (int tile = wave; tile < 2 * nb; tile += 4) {
     const int mb = tile / nb, cb = tile - mb * nb;
@@ -84,7 +84,7 @@ __global__ __launch_bounds__(256) void k_iota_ab(IotaABArgs a) {
     zero16(acc);
     for (int kk = 0; kk < k1; kk += 2) {
       const int l = kk + kh;
-      const float av = (x1 < n1 && l < k1) ? W1[(int64_t)x1 * k1 + l] : 0.f;
+      const float av = (x1 < n1 && l < k1) ? W1t[(int64_t)l * n1 + x1] : 0.f;
       const float bv = (x2 < n2 && l < k1) ? T[l * ldt + x2] : 0.f;
       acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
     }
@@ -108,8 +108,8 @@ __global__ __launch_bounds__(256) void k_pi_ba(PiBAArgs a) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int kh = lane >> 5, li = lane & 31;
   const float* __restrict__ in = a.in + ((int64_t)f * k0 + a0) * n1 * n2;
-  const float* __restrict__ P1 = a.p1;
-  const float* __restrict__ P2 = a.p2;
+  const float* __restrict__ P1t = a.p1t;  // [n1][k1]
+  const float* __restrict__ P2t = a.p2t;  // [n2][k2]
   // stage 1: T[a1][x2] = sum_x1 P1[a1][x1] in[x1][x2]
   const int mb1 = (k1 + 31) / 32, nb = (n2 + 31) / 32;
   for (int tile = wave; tile < mb1 * nb; tile += 4) {
@@ -120,7 +120,7 @@ __global__ __launch_bounds__(256) void k_pi_ba(PiBAArgs a) {
 #pragma unroll 8
     for (int kk = 0; kk < n1; kk += 2) {
       const int l = kk + kh;
-      const float av = (arow < k1 && l < n1) ? P1[(int64_t)arow * n1 + l] : 0.f;
+      const float av = (arow < k1 && l < n1) ? P1t[(int64_t)l * k1 + arow] : 0.f;
       const float bv = (x2 < n2 && l < n1) ? in[(int64_t)l * n2 + x2] : 0.f;
       acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
     }
@@ -144,7 +144,7 @@ __global__ __launch_bounds__(256) void k_pi_ba(PiBAArgs a) {
   for (int kk = lb; kk < le; kk += 2) {
     const int l = kk + kh;
     const float av = (arow < k1 && l < le) ? T[arow * ldt + l] : 0.f;
-    const float bv = (a2 < k2 && l < le) ? P2[(int64_t)a2 * n2 + l] : 0.f;
+    const float bv = (a2 < k2 && l < le) ? P2t[(int64_t)l * k2 + a2] : 0.f;
     acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
   }
 #pragma unroll

@@ -25,15 +25,15 @@ struct IotaABArgs {
   const float* x[kMaxFields];  // per-field band input [k0][k1][k2]
   const float* y[kMaxFields];  // optional second input (null: none); slab = x + alpha y
   float alpha[kMaxFields];
-  const float* w1[kMaxFields];  // [n1][k1]
-  const float* w2[kMaxFields];  // [n2][k2]
+  const float* w1t[kMaxFields];  // axis-1 matrix transposed, [k1][n1]
+  const float* w2t[kMaxFields];  // axis-2 matrix transposed, [k2][n2]
   float* out;                   // [nf][k0][n1][n2]
   int k0, k1, k2, n1, n2;
 };
 struct PiBAArgs {
   const float* in;  // [nf][k0][n1][n2]
-  const float* p1;  // [k1][n1]
-  const float* p2;  // [k2][n2]
+  const float* p1t;  // axis-1 projection transposed, [n1][k1]
+  const float* p2t;  // axis-2 projection transposed, [n2][k2]
   float* out[kMaxFields];  // per-field band output [k0][k1][k2]: out = beta out + alpha r
   float alpha[kMaxFields];
   float beta[kMaxFields];

@@ -34,7 +34,10 @@ namespace {
 
 constexpr double kTwoPi = 6.283185307179586476925286766559;
 
-enum MatKind { kPlain = 0, kPref = 1, kDeriv = 2, kProj = 3 };
+// per-axis matrices: B, S B, dB as [n][k]; B^T / n as [k][n]; the transposes of the first three
+// as [k][n] and B / n as [n][k], so the fused kernels read every operand with coalesced rows
+enum MatKind { kPlain = 0, kPref = 1, kDeriv = 2, kProj = 3, kPlainT = 4, kPrefT = 5, kDerivT = 6, kProjT = 7 };
+constexpr int kNumMats = 8;
 
 inline int slot_freq(int a, int K) {
   if (a == 0) return 0;
@@ -193,12 +196,12 @@ class Solver final : public SolverBase {
   void build_matrices() {
     // per axis: B [n][k], Bs [n][k], Bd [n][k], P [k][n]
     int64_t total = 0;
-    for (int a = 0; a < 3; ++a) total += 4LL * d_.n[a] * d_.k[a];
+    for (int a = 0; a < 3; ++a) total += (int64_t)kNumMats * d_.n[a] * d_.k[a];
     std::vector<T> h(total);
     int64_t o = 0;
     for (int a = 0; a < 3; ++a) {
       const int n = d_.n[a], k = d_.k[a];
-      for (int m = 0; m < 4; ++m) mat_off_[a][m] = o + (int64_t)m * n * k;
+      for (int m = 0; m < kNumMats; ++m) mat_off_[a][m] = o + (int64_t)m * n * k;
       for (int x = 0; x < n; ++x) {
         const double xx = double(x) / n;
         for (int s = 0; s < k; ++s) {
@@ -209,9 +212,13 @@ class Solver final : public SolverBase {
           h[mat_off_[a][kPref] + (int64_t)x * k + s] = static_cast<T>(b * sc);
           h[mat_off_[a][kDeriv] + (int64_t)x * k + s] = static_cast<T>(basis(s, k, xx, true));
           h[mat_off_[a][kProj] + (int64_t)s * n + x] = static_cast<T>(b / n);
+          h[mat_off_[a][kPlainT] + (int64_t)s * n + x] = static_cast<T>(b);
+          h[mat_off_[a][kPrefT] + (int64_t)s * n + x] = static_cast<T>(b * sc);
+          h[mat_off_[a][kDerivT] + (int64_t)s * n + x] = static_cast<T>(basis(s, k, xx, true));
+          h[mat_off_[a][kProjT] + (int64_t)x * k + s] = static_cast<T>(b / n);
         }
       }
-      o += 4LL * n * k;
+      o += (int64_t)kNumMats * n * k;
     }
     mats_.alloc(total);
     LDDMM_HIP(hipMemcpy(mats_.get(), h.data(), total * sizeof(T), hipMemcpyHostToDevice));
@@ -393,8 +400,8 @@ class Solver final : public SolverBase {
           a.x[f] = xs[f];
           a.y[f] = ys ? ys[f] : nullptr;
           a.alpha[f] = al ? al[f] : 0.f;
-          a.w1[f] = mat(1, kinds[f][1]);
-          a.w2[f] = mat(2, kinds[f][2]);
+          a.w1t[f] = mat(1, kinds[f][1] + kPlainT);
+          a.w2t[f] = mat(2, kinds[f][2] + kPlainT);
         }
         a.out = skip0 ? out : t2_.get();
         a.k0 = k0, a.k1 = k1, a.k2 = k2, a.n1 = n1, a.n2 = n2;
@@ -437,8 +444,8 @@ class Solver final : public SolverBase {
         }
         PiBAArgs b{};
         b.in = srcB;
-        b.p1 = mat(1, kProj);
-        b.p2 = mat(2, kProj);
+        b.p1t = mat(1, kProjT);
+        b.p2t = mat(2, kProjT);
         for (int f = 0; f < nf; ++f) {
           b.out[f] = dst[f];
           b.alpha[f] = alpha[f];
@@ -476,8 +483,8 @@ class Solver final : public SolverBase {
         a.x[0] = x;
         a.y[0] = nullptr;
         a.alpha[0] = 0.f;
-        a.w1[0] = mat(1, kPlain);
-        a.w2[0] = mat(2, kPlain);
+        a.w1t[0] = mat(1, kPlainT);
+        a.w2t[0] = mat(2, kPlainT);
         a.out = t2_.get();
         a.k0 = k0, a.k1 = k1, a.k2 = k2, a.n1 = n1, a.n2 = n2;
         iota_ab(a, 1, st_);
@@ -492,8 +499,8 @@ class Solver final : public SolverBase {
         back_v1(b, st_);
         PiBAArgs c{};
         c.in = t1_.get();
-        c.p1 = mat(1, kProj);
-        c.p2 = mat(2, kProj);
+        c.p1t = mat(1, kProjT);
+        c.p2t = mat(2, kProjT);
         for (int f = 0; f < 4; ++f) {
           c.out[f] = dst[f];
           c.alpha[f] = al[f];
@@ -809,7 +816,7 @@ class Solver final : public SolverBase {
   friend int gn_solve_batched_impl(std::vector<Solver<U>*>& subs, const lddmm_bl_gn_opts& o,
                                    void* const* v_user, lddmm_bl_gn_report* reps, hipStream_t st);
   hipGraphExec_t mv_exec_ = nullptr;
-  int64_t mat_off_[3][4] = {};
+  int64_t mat_off_[3][kNumMats] = {};
   DevBuf<T> mats_;
   DevBuf<double> Lsym_, Linv_, work_;
   std::unique_ptr<double, PinnedFree> host_;
