@@ -210,6 +210,22 @@ lddmm_bl_status lddmm_nn_get(lddmm_nn_ctx* ctx, int32_t which, void* host_dst);
 lddmm_bl_status lddmm_nn_set(lddmm_nn_ctx* ctx, const void* host_src);
 lddmm_bl_status lddmm_nn_destroy(lddmm_nn_ctx* ctx);
 
+/* Input and output maps of the warm-start network (all device float, on the network's stream).
+ * pool_pair: box average of an image pair I0, I1 [n0][n1][n2] (each n_j a multiple of in_size) into
+ *   one network input slot [2][in_size^3] (I0 in channel 0).
+ * velocity: network output [B][3][s^3] (grid samples of the three velocity components on the
+ *   coarse s^3 grid of the unit torus) -> band-limited coefficients v_bl [B][3][k0][k1][k2]: the
+ *   projection of Section 2.2 onto the s-point band (frequencies |m| <= s/2 - 1, i.e. real slots
+ *   0 .. s-2 per axis), zero in every other slot.  Requires 3 output channels and even k_j >= s - 1.
+ * loss: mean over the batch of the squared V-norm error sum_a L~(a) (v_pred - v_target)_a^2 with
+ *   L~ = (1 + alpha (2 pi)^2 |m|^2)^s (Section 2.1), accumulated in double; v_target [B][3][K];
+ *   writes d loss / d output to dout_or_null ([B][3][s^3]) when it is not NULL. */
+lddmm_bl_status lddmm_nn_pool_pair(lddmm_nn_ctx* ctx, const void* I0, const void* I1, const int32_t* n,
+                                   void* in_slot);
+lddmm_bl_status lddmm_nn_velocity(lddmm_nn_ctx* ctx, const void* out, int32_t B, const int32_t* k, void* v_bl);
+lddmm_bl_status lddmm_nn_loss(lddmm_nn_ctx* ctx, const void* out, const void* v_target, int32_t B,
+                              const int32_t* k, double alpha, int32_t s, void* dout_or_null, double* loss);
+
 /* Per-kernel timing for measurement tools (process-wide).  While enabled,
  * every kernel launch of the library is bracketed with HIP events on its
  * stream and its algorithmic bytes and flops are recorded (enabling clears

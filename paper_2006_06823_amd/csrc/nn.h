@@ -19,5 +19,12 @@ void conv_backward(const ConvLayer& L, const float* x, const float* y, const flo
                    int Di, hipStream_t s);
 void adam_step(float* w, float* m, float* v, const float* g, int64_t n, float lr, int t, hipStream_t s);
 void fill(float* p, int64_t n, float v, hipStream_t s);
+// box-average an image pair of n[0] x n[1] x n[2] voxels (each divisible by S) into a [2][S^3] input
+void pool_pair(const float* I0, const float* I1, const int n[3], int S, float* out, hipStream_t s);
+// coarse samples [B][3][sz^3] -> band coefficients [B][3][k0][k1][k2] through the projection P [sz][sz]
+void samples_to_bl(const float* samp, const float* P, int B, int sz, const int k[3], float* v, hipStream_t s);
+// ds = scale * (projection block)^T (w * diff), diff [B][3][k0][k1][k2], w [k0 k1 k2] (double)
+void block_grad(const float* diff, const double* w, const float* P, int B, int sz, const int k[3], float scale,
+                float* ds, hipStream_t s);
 
 }  // namespace lddmm

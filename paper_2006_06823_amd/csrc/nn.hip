@@ -228,6 +228,79 @@ __global__ void k_fill(float* p, int64_t n, float v) {
   if (i < n) p[i] = v;
 }
 
+// network input from an image pair: box average of each f0 x f1 x f2 voxel cell, out [2][S^3]
+__global__ void k_pool_pair(const float* __restrict__ I0, const float* __restrict__ I1, int n1, int n2, int f0, int f1,
+                            int f2, int S, float* __restrict__ out) {
+  const int64_t S3 = (int64_t)S * S * S;
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= 2 * S3) return;
+  const int ch = (int)(e / S3);
+  const int64_t o = e - ch * S3;
+  const int oz = (int)(o / (S * S)), oy = (int)((o / S) % S), ox = (int)(o % S);
+  const float* I = ch == 0 ? I0 : I1;
+  float sum = 0.f;
+  for (int a = 0; a < f0; ++a)
+    for (int b = 0; b < f1; ++b) {
+      const float* row = I + ((int64_t)(oz * f0 + a) * n1 + (oy * f1 + b)) * n2 + (int64_t)ox * f2;
+      for (int c = 0; c < f2; ++c) sum += row[c];
+    }
+  out[e] = sum / (float)(f0 * f1 * f2);
+}
+
+// coarse velocity samples [B][3][s^3] -> band-limited coefficients [B][3][K0][K1][K2]:
+// the separable projection P[a][x] onto the s-point band for slots a < s - 1, zero elsewhere
+__global__ void k_samples_to_bl(const float* __restrict__ samp, const float* __restrict__ P, int B, int sz, int k0,
+                                int k1, int k2, float* __restrict__ v) {
+  const int64_t Q = (int64_t)k0 * k1 * k2;
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= (int64_t)B * 3 * Q) return;
+  const int64_t bc = e / Q, q = e - bc * Q;
+  const int a0 = (int)(q / ((int64_t)k1 * k2)), a1 = (int)((q / k2) % k1), a2 = (int)(q % k2);
+  const int nb = sz - 1;
+  float r = 0.f;
+  if (a0 < nb && a1 < nb && a2 < nb) {
+    const float* sp = samp + bc * sz * sz * sz;
+    for (int x0 = 0; x0 < sz; ++x0) {
+      float t1 = 0.f;
+      for (int x1 = 0; x1 < sz; ++x1) {
+        float t2 = 0.f;
+        for (int x2 = 0; x2 < sz; ++x2) t2 += P[a2 * sz + x2] * sp[(x0 * sz + x1) * sz + x2];
+        t1 += P[a1 * sz + x1] * t2;
+      }
+      r += P[a0 * sz + x0] * t1;
+    }
+  }
+  v[e] = r;
+}
+
+// gradient of the weighted squared coefficient error with respect to the samples:
+// ds[b][c][x] = scale * sum_{a in block} P[a0][x0] P[a1][x1] P[a2][x2] w[a] diff[b][c][a]
+__global__ void k_block_grad(const float* __restrict__ diff, const double* __restrict__ w, const float* __restrict__ P,
+                             int B, int sz, int k0, int k1, int k2, float scale, float* __restrict__ ds) {
+  const int s3 = sz * sz * sz;
+  const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (e >= (int64_t)B * 3 * s3) return;
+  const int64_t bc = e / s3;
+  const int x = (int)(e - bc * s3);
+  const int x0 = x / (sz * sz), x1 = (x / sz) % sz, x2 = x % sz;
+  const int nb = sz - 1;
+  const float* dp = diff + bc * k0 * k1 * k2;
+  float r = 0.f;
+  for (int a0 = 0; a0 < nb; ++a0) {
+    float t1 = 0.f;
+    for (int a1 = 0; a1 < nb; ++a1) {
+      float t2 = 0.f;
+      for (int a2 = 0; a2 < nb; ++a2) {
+        const int64_t q = ((int64_t)a0 * k1 + a1) * k2 + a2;
+        t2 += P[a2 * sz + x2] * (float)w[q] * dp[q];
+      }
+      t1 += P[a1 * sz + x1] * t2;
+    }
+    r += P[a0 * sz + x0] * t1;
+  }
+  ds[e] = scale * r;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------------------------------
@@ -282,6 +355,25 @@ void adam_step(float* w, float* m, float* v, const float* g, int64_t n, float lr
 void fill(float* p, int64_t n, float v, hipStream_t s) {
   if (n <= 0) return;
   k_fill<<<ceil_div(n, 256), 256, 0, s>>>(p, n, v);
+  LDDMM_LAUNCH_CHECK();
+}
+
+void pool_pair(const float* I0, const float* I1, const int n[3], int S, float* out, hipStream_t s) {
+  const int64_t tot = 2LL * S * S * S;
+  k_pool_pair<<<ceil_div(tot, 256), 256, 0, s>>>(I0, I1, n[1], n[2], n[0] / S, n[1] / S, n[2] / S, S, out);
+  LDDMM_LAUNCH_CHECK();
+}
+
+void samples_to_bl(const float* samp, const float* P, int B, int sz, const int k[3], float* v, hipStream_t s) {
+  const int64_t tot = (int64_t)B * 3 * k[0] * k[1] * k[2];
+  k_samples_to_bl<<<ceil_div(tot, 256), 256, 0, s>>>(samp, P, B, sz, k[0], k[1], k[2], v);
+  LDDMM_LAUNCH_CHECK();
+}
+
+void block_grad(const float* diff, const double* w, const float* P, int B, int sz, const int k[3], float scale,
+                float* ds, hipStream_t s) {
+  const int64_t tot = (int64_t)B * 3 * sz * sz * sz;
+  k_block_grad<<<ceil_div(tot, 256), 256, 0, s>>>(diff, w, P, B, sz, k[0], k[1], k[2], scale, ds);
   LDDMM_LAUNCH_CHECK();
 }
 

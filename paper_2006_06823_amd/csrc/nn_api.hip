@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "../../include/lddmm_bl.h"
+#include "kernels.h"
 #include "nn.h"
 #include "solver.h"
 
@@ -77,6 +78,11 @@ class Net {
     if (gbuf_) (void)hipFree(gbuf_);
     if (dbuf_[0]) (void)hipFree(dbuf_[0]);
     if (dbuf_[1]) (void)hipFree(dbuf_[1]);
+    if (P_) (void)hipFree(P_);
+    if (diff_) (void)hipFree(diff_);
+    if (Lw_) (void)hipFree(Lw_);
+    if (work_) (void)hipFree(work_);
+    if (host_) (void)hipHostFree(host_);
   }
 
   int out_size() const { return out_size_; }
@@ -129,7 +135,95 @@ class Net {
     LDDMM_HIP(hipMemcpy(arena_, host, sizeof(float) * nparam_, hipMemcpyHostToDevice));
   }
 
+  // image pair (n[0] x n[1] x n[2], each a multiple of the input size) -> one [2][S^3] input slot
+  void pool(const float* I0, const float* I1, const int n[3], float* slot) {
+    const int S = sizes_[0];
+    for (int j = 0; j < 3; ++j)
+      if (n[j] < S || n[j] % S) throw ArgError("image size must be a multiple of the network input size");
+    pool_pair(I0, I1, n, S, slot, st_);
+    LDDMM_HIP(hipStreamSynchronize(st_));
+  }
+
+  // network output [B][3][s^3] -> velocity coefficients [B][3][k0][k1][k2]
+  void velocity(const float* out, int B, const int k[3], float* v) {
+    check_velocity_args(B, k);
+    samples_to_bl(out, proj(), B, out_size_, k, v, st_);
+    LDDMM_HIP(hipStreamSynchronize(st_));
+  }
+
+  // mean squared V-norm error of the predicted velocities against v_target [B][3][K] and its
+  // gradient with respect to the network output
+  double loss(const float* out, const float* vt, int B, const int k[3], double alpha, int s_exp, float* dout) {
+    check_velocity_args(B, k);
+    if (alpha < 0 || s_exp < 0) throw ArgError("bad regularisation parameters");
+    const int64_t Q = (int64_t)k[0] * k[1] * k[2], n = (int64_t)B * 3 * Q;
+    if (n > diff_cap_) {
+      if (diff_) (void)hipFree(diff_);
+      diff_ = nullptr;
+      if (hipMalloc(&diff_, sizeof(float) * n) != hipSuccess) throw std::bad_alloc();
+      diff_cap_ = n;
+    }
+    weights(k, alpha, s_exp);
+    samples_to_bl(out, proj(), B, out_size_, k, diff_, st_);
+    bl_axpby<float>(diff_, 1.f, diff_, -1.f, vt, n, st_);
+    if (!work_) {
+      if (hipMalloc(&work_, sizeof(double) * reduce_work_size()) != hipSuccess) throw std::bad_alloc();
+      if (hipHostMalloc(reinterpret_cast<void**>(&host_), 8 * sizeof(double), hipHostMallocDefault) != hipSuccess)
+        throw std::bad_alloc();
+    }
+    const double l = sym_dot<float>(diff_, diff_, Lw_, 3 * B, Q, work_, host_, st_) / B;
+    if (dout) block_grad(diff_, Lw_, proj(), B, out_size_, k, 2.f / B, dout, st_);
+    LDDMM_HIP(hipStreamSynchronize(st_));
+    return l;
+  }
+
  private:
+  void check_velocity_args(int B, const int k[3]) const {
+    if (B < 1 || layers_.back().cout != 3) throw ArgError("velocity output needs 3 output channels and B >= 1");
+    for (int j = 0; j < 3; ++j)
+      if (k[j] < out_size_ - 1 || k[j] < 2 || k[j] % 2) throw ArgError("band too small for the network output");
+  }
+  // projection onto the out_size-point band: P[a][x] = b_a(x / s) / s in the real basis
+  // (slot 0 the constant, 2m-1 / 2m sqrt2 cos / sqrt2 sin of frequency m, last slot zero)
+  const float* proj() {
+    if (P_) return P_;
+    const int sz = out_size_;
+    std::vector<float> h((size_t)sz * sz, 0.f);
+    const double r2 = std::sqrt(2.0), tp = 2.0 * M_PI;
+    for (int x = 0; x < sz; ++x) {
+      const double xx = (double)x / sz;
+      h[x] = (float)(1.0 / sz);
+      for (int m = 1; 2 * m < sz; ++m) {
+        h[(2 * m - 1) * sz + x] = (float)(r2 * std::cos(tp * m * xx) / sz);
+        h[(2 * m) * sz + x] = (float)(r2 * std::sin(tp * m * xx) / sz);
+      }
+    }
+    if (hipMalloc(&P_, sizeof(float) * h.size()) != hipSuccess) throw std::bad_alloc();
+    LDDMM_HIP(hipMemcpy(P_, h.data(), sizeof(float) * h.size(), hipMemcpyHostToDevice));
+    return P_;
+  }
+  // diagonal of L~ = (1 + alpha (2 pi)^2 |m|^2)^s on the real slots (zero on the pad slots)
+  void weights(const int k[3], double alpha, int s_exp) {
+    if (Lw_ && k[0] == wk_[0] && k[1] == wk_[1] && k[2] == wk_[2] && alpha == walpha_ && s_exp == ws_) return;
+    const int64_t Q = (int64_t)k[0] * k[1] * k[2];
+    std::vector<double> h(Q);
+    auto fr = [](int a, int K) { return a == K - 1 ? -1 : (a + 1) / 2; };
+    const double c = alpha * 4.0 * M_PI * M_PI;
+    for (int a0 = 0; a0 < k[0]; ++a0)
+      for (int a1 = 0; a1 < k[1]; ++a1)
+        for (int a2 = 0; a2 < k[2]; ++a2) {
+          const int f0 = fr(a0, k[0]), f1 = fr(a1, k[1]), f2 = fr(a2, k[2]);
+          double w = 0.0;
+          if (f0 >= 0 && f1 >= 0 && f2 >= 0) w = std::pow(1.0 + c * (f0 * f0 + f1 * f1 + f2 * f2), s_exp);
+          h[((int64_t)a0 * k[1] + a1) * k[2] + a2] = w;
+        }
+    if (Lw_) (void)hipFree(Lw_);
+    Lw_ = nullptr;
+    if (hipMalloc(&Lw_, sizeof(double) * Q) != hipSuccess) throw std::bad_alloc();
+    LDDMM_HIP(hipMemcpy(Lw_, h.data(), sizeof(double) * Q, hipMemcpyHostToDevice));
+    wk_[0] = k[0], wk_[1] = k[1], wk_[2] = k[2], walpha_ = alpha, ws_ = s_exp;
+  }
+
   int64_t act_elems(int l, int B) const {
     const int so = (l + 1 < (int)sizes_.size()) ? sizes_[l + 1] : out_size_;
     return (int64_t)B * layers_[l].cout * so * so * so;
@@ -170,6 +264,14 @@ class Net {
   float* dbuf_[2] = {nullptr, nullptr};
   const float* in_ = nullptr;
   const float* out_ = nullptr;
+  float* P_ = nullptr;
+  float* diff_ = nullptr;
+  int64_t diff_cap_ = 0;
+  double* Lw_ = nullptr;
+  int wk_[3] = {0, 0, 0}, ws_ = -1;
+  double walpha_ = -1.0;
+  double* work_ = nullptr;
+  double* host_ = nullptr;
 };
 
 }  // namespace lddmm
@@ -266,6 +368,33 @@ lddmm_bl_status lddmm_nn_set(lddmm_nn_ctx* c, const void* host_src) {
   return nn_guard(c, [&] {
     if (!host_src) throw lddmm::ArgError("null parameters");
     c->net->set(static_cast<const float*>(host_src));
+  });
+}
+
+lddmm_bl_status lddmm_nn_pool_pair(lddmm_nn_ctx* c, const void* I0, const void* I1, const int32_t* n,
+                                   void* in_slot) {
+  return nn_guard(c, [&] {
+    if (!I0 || !I1 || !n || !in_slot) throw lddmm::ArgError("null pool arguments");
+    const int nn[3] = {n[0], n[1], n[2]};
+    c->net->pool(static_cast<const float*>(I0), static_cast<const float*>(I1), nn, static_cast<float*>(in_slot));
+  });
+}
+
+lddmm_bl_status lddmm_nn_velocity(lddmm_nn_ctx* c, const void* out, int32_t B, const int32_t* k, void* v_bl) {
+  return nn_guard(c, [&] {
+    if (!out || !k || !v_bl) throw lddmm::ArgError("null velocity arguments");
+    const int kk[3] = {k[0], k[1], k[2]};
+    c->net->velocity(static_cast<const float*>(out), B, kk, static_cast<float*>(v_bl));
+  });
+}
+
+lddmm_bl_status lddmm_nn_loss(lddmm_nn_ctx* c, const void* out, const void* v_target, int32_t B, const int32_t* k,
+                              double alpha, int32_t s, void* dout_or_null, double* loss) {
+  return nn_guard(c, [&] {
+    if (!out || !v_target || !k || !loss) throw lddmm::ArgError("null loss arguments");
+    const int kk[3] = {k[0], k[1], k[2]};
+    *loss = c->net->loss(static_cast<const float*>(out), static_cast<const float*>(v_target), B, kk, alpha, s,
+                         static_cast<float*>(dout_or_null));
   });
 }
 

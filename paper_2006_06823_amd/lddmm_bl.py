@@ -35,6 +35,9 @@ EXPORTS = [
     "lddmm_bl_state_solve", "lddmm_bl_adjoint_solve", "lddmm_bl_hess_matvec", "lddmm_bl_gn_solve",
     "lddmm_bl_jacobian", "lddmm_bl_project", "lddmm_bl_include", "lddmm_bl_get_field", "lddmm_bl_dot",
     "lddmm_bl_profile_enable", "lddmm_bl_profile_read", "lddmm_bl_gn_solve_batched",
+    "lddmm_nn_create", "lddmm_nn_info", "lddmm_nn_forward", "lddmm_nn_backward", "lddmm_nn_zero_grad",
+    "lddmm_nn_step", "lddmm_nn_get", "lddmm_nn_set", "lddmm_nn_destroy", "lddmm_nn_pool_pair",
+    "lddmm_nn_velocity", "lddmm_nn_loss",
 ]
 
 
@@ -92,6 +95,21 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "lddmm_bl_gn_solve_batched": [ctypes.POINTER(Params), i32, ctypes.POINTER(vp), ctypes.POINTER(vp),
                                       ctypes.POINTER(vp), ctypes.POINTER(GNOpts), vp, ctypes.POINTER(GNReport)],
     }
+    ip = ctypes.POINTER(i32)
+    sig.update({
+        "lddmm_nn_create": [i32, ip, i32, i32, ctypes.c_uint64, vp, ctypes.POINTER(vp)],
+        "lddmm_nn_info": [vp, ip, ip, ctypes.POINTER(i64)],
+        "lddmm_nn_forward": [vp, vp, i32, vp],
+        "lddmm_nn_backward": [vp, vp, i32],
+        "lddmm_nn_zero_grad": [vp],
+        "lddmm_nn_step": [vp, ctypes.c_double],
+        "lddmm_nn_get": [vp, i32, vp],
+        "lddmm_nn_set": [vp, vp],
+        "lddmm_nn_destroy": [vp],
+        "lddmm_nn_pool_pair": [vp, vp, vp, ip, vp],
+        "lddmm_nn_velocity": [vp, vp, i32, ip, vp],
+        "lddmm_nn_loss": [vp, vp, vp, i32, ip, ctypes.c_double, i32, vp, dp],
+    })
     for name, args in sig.items():
         fn = getattr(lib, name)
         fn.argtypes = args
@@ -337,3 +355,127 @@ def profile_read():
         name, count, ms, nbytes, flops = line.split("\t")
         out[name] = dict(count=int(count), ms=float(ms), bytes=float(nbytes), flops=float(flops))
     return out
+
+
+class WarmStartNet:
+    """The warm-start network (lddmm_nn_* in the C ABI) on one ROCm device.
+
+    levels 3^3 convolutions (stride 2 but the last, ReLU) with the given channels on a
+    [B][2][in_size]^3 float input, then a 1^3 head to 3 channels: grid samples of the three
+    velocity components on a coarse out_size^3 grid.  All tensors are contiguous float32
+    on the device; the library works on its own stream, ordered after the caller's.
+    """
+
+    def __init__(self, channels=(16, 32, 64, 128), in_size=64, seed=0, device=None):
+        self.lib = load_library()
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.stream = torch.cuda.Stream(device=self.device)
+        self.channels = tuple(int(c) for c in channels)
+        self.in_size = int(in_size)
+        ch = (ctypes.c_int32 * len(channels))(*self.channels)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            st = self.lib.lddmm_nn_create(len(channels), ch, self.in_size, 3, seed,
+                                          ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if st != 0:
+            raise LddmmError(st, "lddmm_nn_create failed")
+        self.h = h
+        osz, oc, npar = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+        self._check(self.lib.lddmm_nn_info(self.h, ctypes.byref(osz), ctypes.byref(oc), ctypes.byref(npar)), "info")
+        self.out_size, self.nparam = osz.value, npar.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.lddmm_nn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st, what):
+        if st != 0:
+            raise LddmmError(st, f"lddmm_nn_{what} failed")
+
+    def _order(self):
+        cur = torch.cuda.current_stream(self.device)
+        if cur != self.stream:
+            self.stream.wait_stream(cur)
+
+    def _dev(self, t, shape, name):
+        if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.float32:
+            raise TypeError(f"{name} must be a float32 ROCm tensor")
+        if shape is not None and tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+        if not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+        return t
+
+    def out_shape(self, B):
+        return (B, 3) + (self.out_size,) * 3
+
+    def pool_pair(self, I0, I1, slot):
+        """Box-average an image pair into one input slot [2][in_size]^3 (a view of the batch tensor)."""
+        self._dev(I0, None, "I0")
+        self._dev(I1, tuple(I0.shape), "I1")
+        self._dev(slot, (2,) + (self.in_size,) * 3, "slot")
+        n = (ctypes.c_int32 * 3)(*I0.shape)
+        self._order()
+        self._check(self.lib.lddmm_nn_pool_pair(self.h, _ptr(I0), _ptr(I1), n, _ptr(slot)), "pool_pair")
+
+    def forward(self, x):
+        B = x.shape[0]
+        self._dev(x, (B, 2) + (self.in_size,) * 3, "x")
+        out = torch.empty(self.out_shape(B), dtype=torch.float32, device=self.device)
+        self._order()
+        self._check(self.lib.lddmm_nn_forward(self.h, _ptr(x), B, _ptr(out)), "forward")
+        return out
+
+    def backward(self, dout):
+        self._dev(dout, None, "dout")
+        self._order()
+        self._check(self.lib.lddmm_nn_backward(self.h, _ptr(dout), dout.shape[0]), "backward")
+
+    def zero_grad(self):
+        self._check(self.lib.lddmm_nn_zero_grad(self.h), "zero_grad")
+
+    def step(self, lr):
+        self._check(self.lib.lddmm_nn_step(self.h, float(lr)), "step")
+
+    def velocity(self, out, K):
+        B = out.shape[0]
+        self._dev(out, self.out_shape(B), "out")
+        v = torch.empty((B, 3) + tuple(K), dtype=torch.float32, device=self.device)
+        k = (ctypes.c_int32 * 3)(*K)
+        self._order()
+        self._check(self.lib.lddmm_nn_velocity(self.h, _ptr(out), B, k, _ptr(v)), "velocity")
+        return v
+
+    def loss(self, out, v_target, alpha=0.0025, s=2, want_grad=True):
+        B = out.shape[0]
+        self._dev(out, self.out_shape(B), "out")
+        self._dev(v_target, None, "v_target")
+        if v_target.dim() != 5 or v_target.shape[:2] != (B, 3):
+            raise ValueError("v_target must be [B][3][K0][K1][K2]")
+        dout = torch.empty_like(out) if want_grad else None
+        k = (ctypes.c_int32 * 3)(*v_target.shape[2:])
+        r = ctypes.c_double()
+        self._order()
+        self._check(self.lib.lddmm_nn_loss(self.h, _ptr(out), _ptr(v_target), B, k, alpha, s, _ptr(dout),
+                                           ctypes.byref(r)), "loss")
+        return r.value, dout
+
+    def get(self, which=0):
+        import numpy as np
+        buf = np.empty(self.nparam, dtype=np.float32)
+        self._check(self.lib.lddmm_nn_get(self.h, which, buf.ctypes.data_as(ctypes.c_void_p)), "get")
+        return buf
+
+    def set(self, params):
+        import numpy as np
+        buf = np.ascontiguousarray(params, dtype=np.float32)
+        if buf.size != self.nparam:
+            raise ValueError(f"expected {self.nparam} parameters, got {buf.size}")
+        self._check(self.lib.lddmm_nn_set(self.h, buf.ctypes.data_as(ctypes.c_void_p)), "set")
