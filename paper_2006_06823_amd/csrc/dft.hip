@@ -232,49 +232,71 @@ __global__ __launch_bounds__(256) void dft_left_contract(const float* __restrict
   }
 }
 
-// expand mode (L <= 64): each wave owns one 32-row block of a 128-row block tile and
-// the block's 32 columns, over the whole (short) contraction.
+// expand mode (L <= 64): a block owns a 128-row x 64-column output tile.  The input rows of
+// its 64 columns are staged in LDS with one coalesced burst (float4 when aligned), each wave
+// owns one 32-row block and both 32-column halves; the W tile stays in LDS while the block
+// walks several column tiles.
+constexpr int kExpCols = 64, kExpLdb = kExpCols + 4;
 __global__ __launch_bounds__(256) void dft_left_expand(const float* __restrict__ in, float* __restrict__ out,
                                                        FieldMats<float> mats, int bpf, int M, int L, int C,
-                                                       int64_t sIb, int64_t sOb) {
+                                                       int64_t sIb, int64_t sOb, int vec) {
   extern __shared__ float smem[];
   const int ldw = L + 1;
-  float* Ws = smem;  // [128][L + 1]
+  float* Ws = smem;              // [128][L + 1]
+  float* Bs = smem + 128 * ldw;  // [L][68]
   const int b = blockIdx.z;
   const float* __restrict__ W = mats.w[b / bpf];
   in += b * sIb;
   out += b * sOb;
   const int m0 = blockIdx.y * 128;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 31;
   for (int e = tid; e < 128 * L; e += 256) {
     const int mm = e / L, l = e - mm * L;
     Ws[mm * ldw + l] = (m0 + mm) < M ? W[(int64_t)(m0 + mm) * L + l] : 0.f;
   }
-  __syncthreads();
   const int mw = m0 + wave * 32;
-  if (mw >= M) return;
   const int kh = lane >> 5;
-  const float* Wr = Ws + (wave * 32 + (lane & 31)) * ldw;
-  const int ncb = (C + 31) / 32;
-  // the W tile stays in LDS while the block walks several column blocks
+  const float* Wr = Ws + (wave * 32 + li) * ldw;
+  const int ncb = (C + kExpCols - 1) / kExpCols;
   for (int cb = blockIdx.x; cb < ncb; cb += gridDim.x) {
-    const int c = cb * 32 + (lane & 31);
-    const bool cok = c < C;
-    f32x16 acc;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) acc[r] = 0.f;
-#pragma unroll 8
-    for (int kk = 0; kk < L; kk += 2) {
-      const int l = kk + kh;
-      const float bv = (cok && l < L) ? in[(int64_t)l * C + c] : 0.f;
-      const float av = l < L ? Wr[l] : 0.f;
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
+    const int c0 = cb * kExpCols;
+    __syncthreads();  // W tile loaded; previous tile's reads of Bs done
+    if (vec) {
+      for (int e = tid; e < L * (kExpCols / 4); e += 256) {
+        const int l = e >> 4, j = (e & 15) * 4;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (c0 + j < C) v = *reinterpret_cast<const float4*>(in + (int64_t)l * C + c0 + j);
+        *reinterpret_cast<float4*>(Bs + l * kExpLdb + j) = v;
+      }
+    } else {
+      for (int e = tid; e < L * kExpCols; e += 256) {
+        const int l = e >> 6, j = e & 63;
+        Bs[l * kExpLdb + j] = (c0 + j < C) ? in[(int64_t)l * C + c0 + j] : 0.f;
+      }
     }
-    if (cok) {
+    __syncthreads();
+    if (mw < M) {
+      f32x16 acc0, acc1;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc0[r] = acc1[r] = 0.f;
+#pragma unroll 4
+      for (int kk = 0; kk < L; kk += 2) {
+        const int l = kk + kh;
+        const bool ok = l < L;
+        const float av = ok ? Wr[l] : 0.f;
+        const float b0 = ok ? Bs[l * kExpLdb + li] : 0.f;
+        const float b1 = ok ? Bs[l * kExpLdb + 32 + li] : 0.f;
+        acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(av, b0, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(av, b1, acc1, 0, 0, 0);
+      }
+      const int c = c0 + li;
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int m = mw + acc_row(r, lane);
-        if (m < M) out[(int64_t)m * C + c] = acc[r];
+        if (m < M) {
+          if (c < C) out[(int64_t)m * C + c] = acc0[r];
+          if (c + 32 < C) out[(int64_t)m * C + c + 32] = acc1[r];
+        }
       }
     }
   }
@@ -481,12 +503,13 @@ void dft_left(const T* in, T* out, const FieldMats<T>& W, int nb, int bpf, int M
       return;
     }
     if (L <= 64) {
-      const uint32_t sm = (uint32_t)128 * (L + 1) * sizeof(float);
-      const int ncb = ceil_div(C, 32), gy = ceil_div(M, 128);
-      const int gx = std::max(1, std::min(ncb, 1024 / std::max(1, nb * gy)));
+      const uint32_t sm = (uint32_t)(128 * (L + 1) + L * kExpLdb) * sizeof(float);
+      const int ncb = ceil_div(C, kExpCols), gy = ceil_div(M, 128);
+      const int gx = std::max(1, std::min(ncb, 2048 / std::max(1, nb * gy)));
+      const int vec = (C % 4 == 0) && (sIb % 4 == 0) && (reinterpret_cast<uintptr_t>(in) % 16 == 0);
       dim3 g(gx, gy, nb);
       prof::launch("dft_left_expand", bytes, flops, dft_left_expand, g, dim3(256), sm, s, in, out, W, bpf, M, L, C,
-                   sIb, sOb);
+                   sIb, sOb, vec);
       LDDMM_LAUNCH_CHECK();
       return;
     }

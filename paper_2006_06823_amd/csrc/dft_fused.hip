@@ -28,17 +28,30 @@ __device__ __forceinline__ void zero16(f32x16& a) {
 }
 
 constexpr int kMaxN = 192, kMaxK = 64;
+constexpr int kRows = 32;  // grid rows of axis 1 per block
 
+// LDS floats of k_iota_ab with and without the staged axis-2 matrix
+__host__ __device__ inline int iota_lds(int k1, int k2, int n2, bool stage_w2) {
+  return k1 * (k2 + 1) + k1 * (n2 + 4) + k1 * kRows + (stage_w2 ? k2 * n2 : 0);
+}
+__host__ __device__ inline int pi_lds(int k2, int n2) { return kRows * (n2 + 1) + 4096 + kRows * (k2 + 1); }
+
+// grid (ceil(n1 / 32), k0, nf): each block expands one (field, a0) slab for 32 rows of x1
+template <bool STAGE_W2>
 __global__ __launch_bounds__(256) void k_iota_ab(IotaABArgs a) {
   extern __shared__ float smem[];
-  const int f = blockIdx.z, a0 = blockIdx.y, x1b = blockIdx.x * 64;
+  const int f = blockIdx.z, a0 = blockIdx.y, x1b = blockIdx.x * kRows;
   const int k0 = a.k0, k1 = a.k1, k2 = a.k2, n1 = a.n1, n2 = a.n2;
   const int lds = k2 + 1, ldt = n2 + 4;
-  float* S = smem;             // [a1][a2]
-  float* T = smem + k1 * lds;  // [a1][x2]
+  float* S = smem;               // [a1][a2]
+  float* T = S + k1 * lds;       // [a1][x2]
+  float* W1s = T + k1 * ldt;     // [a1][32 rows of x1]
+  float* W2s = W1s + k1 * kRows;  // [a2][x2] (when staged)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int kh = lane >> 5, li = lane & 31;
-  // prologue: slab = x + alpha y
+  const float* __restrict__ W2t = a.w2t[f];  // [k2][n2]
+  const float* __restrict__ W1t = a.w1t[f];  // [k1][n1]
+  // prologue: slab = x + alpha y, and the matrix operands, all with coalesced loads
   {
     const int64_t off = (int64_t)a0 * k1 * k2;
     const float* x = a.x[f] + off;
@@ -50,20 +63,27 @@ __global__ __launch_bounds__(256) void k_iota_ab(IotaABArgs a) {
       if (y) v += al * y[e];
       S[r * lds + c] = v;
     }
+    for (int e = tid; e < k1 * kRows; e += 256) {
+      const int r = e / kRows, c = e - r * kRows;
+      W1s[e] = (x1b + c < n1) ? W1t[(int64_t)r * n1 + x1b + c] : 0.f;
+    }
+    if (STAGE_W2)
+      for (int e = tid; e < k2 * n2; e += 256) W2s[e] = W2t[e];
   }
   __syncthreads();
+  const float* W2 = STAGE_W2 ? W2s : W2t;
   // stage 1: T[a1][x2] = sum_a2 S[a1][a2] W2[x2][a2]
-  const float* __restrict__ W2t = a.w2t[f];  // [k2][n2]
   const int mb1 = (k1 + 31) / 32, nb = (n2 + 31) / 32;
   for (int tile = wave; tile < mb1 * nb; tile += 4) {
     const int mb = tile / nb, cb = tile - mb * nb;
     f32x16 acc;
     zero16(acc);
     const int arow = mb * 32 + li, x2 = cb * 32 + li;
+#pragma unroll 4
     for (int kk = 0; kk < k2; kk += 2) {
       const int l = kk + kh;
       const float av = (arow < k1 && l < k2) ? S[arow * lds + l] : 0.f;
-      const float bv = (x2 < n2 && l < k2) ? W2t[(int64_t)l * n2 + x2] : 0.f;
+      const float bv = (x2 < n2 && l < k2) ? W2[l * n2 + x2] : 0.f;
       acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
     }
 #pragma unroll
@@ -73,122 +93,156 @@ __global__ __launch_bounds__(256) void k_iota_ab(IotaABArgs a) {
     }
   }
   __syncthreads();
-  // stage 2: out[x1][x2] = sum_a1 W1[x1][a1] T[a1][x2], x1 in [x1b, x1b + 64)
-  const float* __restrict__ W1t = a.w1t[f];  // [k1][n1]
+  // stage 2: out[x1][x2] = sum_a1 W1[x1][a1] T[a1][x2], x1 in [x1b, x1b + 32)
   float* out = a.out + ((int64_t)f * k0 + a0) * n1 * n2;
-  for (int tile = wave; tile < 2 * nb; tile += 4) {
-    const int mb = tile / nb, cb = tile - mb * nb;
-    const int x1 = x1b + mb * 32 + li, x2 = cb * 32 + li;
-    if (x1b + mb * 32 >= n1) continue;
+  for (int cb = wave; cb < nb; cb += 4) {
+    const int x2 = cb * 32 + li;
     f32x16 acc;
     zero16(acc);
+#pragma unroll 4
     for (int kk = 0; kk < k1; kk += 2) {
       const int l = kk + kh;
-      const float av = (x1 < n1 && l < k1) ? W1t[(int64_t)l * n1 + x1] : 0.f;
+      const float av = l < k1 ? W1s[l * kRows + li] : 0.f;
       const float bv = (x2 < n2 && l < k1) ? T[l * ldt + x2] : 0.f;
       acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
     }
     if (x2 < n2) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int xr = x1b + mb * 32 + acc_row(r, lane);
+        const int xr = x1b + acc_row(r, lane);
         if (xr < n1) out[(int64_t)xr * n2 + x2] = acc[r];
       }
     }
   }
 }
 
+// grid (nsplit = ceil(n1 / 32), k0, nf): each block projects 32 rows of x1 of one (field, a0)
+// slab to a partial band block in the workspace; k_pi_fin then sums the partials of every slab
+// in split order (deterministic) and applies the epilogue.  (A last-block-done reduction inside
+// this kernel would need a device-scope release per block, which writes back the XCD's L2.)
 __global__ __launch_bounds__(256) void k_pi_ba(PiBAArgs a) {
   extern __shared__ float smem[];
-  const int f = blockIdx.z, a0 = blockIdx.y;
+  const int sp = blockIdx.x, a0 = blockIdx.y, f = blockIdx.z, nsplit = gridDim.x;
   const int k0 = a.k0, k1 = a.k1, k2 = a.k2, n1 = a.n1, n2 = a.n2;
-  const int ldt = n2 + 4;
-  float* R = smem;         // [4][1024] partial 32x32 blocks of the waves
-  float* T = smem + 4096;  // [a1][x2]
+  const int x1b = sp * kRows;
+  const int ldi = n2 + 1, ldu = k2 + 1;
+  float* In = smem;              // [32][n2 + 1] rows x1b.. of the slab
+  float* R = In + kRows * ldi;   // [4][1024] partial accumulators of the waves
+  float* U = R + 4096;           // [32][k2 + 1]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int kh = lane >> 5, li = lane & 31;
-  const float* __restrict__ in = a.in + ((int64_t)f * k0 + a0) * n1 * n2;
+  const int slab = f * k0 + a0;
+  const float* __restrict__ in = a.in + (int64_t)slab * n1 * n2;
   const float* __restrict__ P1t = a.p1t;  // [n1][k1]
   const float* __restrict__ P2t = a.p2t;  // [n2][k2]
-  // stage 1: T[a1][x2] = sum_x1 P1[a1][x1] in[x1][x2]
-  const int mb1 = (k1 + 31) / 32, nb = (n2 + 31) / 32;
-  for (int tile = wave; tile < mb1 * nb; tile += 4) {
-    const int mb = tile / nb, cb = tile - mb * nb;
-    const int arow = mb * 32 + li, x2 = cb * 32 + li;
+  for (int e = tid; e < kRows * n2; e += 256) {
+    const int r = e / n2, c = e - r * n2;
+    In[r * ldi + c] = (x1b + r < n1) ? in[(int64_t)(x1b + r) * n2 + c] : 0.f;
+  }
+  __syncthreads();
+  // stage A: U[x][a2] = sum_x2 In[x][x2] P2[a2][x2]; cb2 column tiles, 4 / cb2 waves split x2
+  const int cb2 = (k2 + 31) / 32, wpt = 4 / cb2;
+  {
+    const int tile = wave / wpt, part = wave - tile * wpt;
+    const int a2 = tile * 32 + li;
+    const int seg = ((n2 + 2 * wpt - 1) / (2 * wpt)) * 2;
+    const int lb = part * seg, le = min(n2, lb + seg);
     f32x16 acc;
     zero16(acc);
-#pragma unroll 8
-    for (int kk = 0; kk < n1; kk += 2) {
+#pragma unroll 4
+    for (int kk = lb; kk < le; kk += 2) {
       const int l = kk + kh;
-      const float av = (arow < k1 && l < n1) ? P1t[(int64_t)l * k1 + arow] : 0.f;
-      const float bv = (x2 < n2 && l < n1) ? in[(int64_t)l * n2 + x2] : 0.f;
+      const float av = l < le ? In[li * ldi + l] : 0.f;
+      const float bv = (a2 < k2 && l < le) ? P2t[(int64_t)l * k2 + a2] : 0.f;
       acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
     }
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int a1 = mb * 32 + acc_row(r, lane);
-      if (a1 < k1 && x2 < n2) T[a1 * ldt + x2] = acc[r];
-    }
+    for (int r = 0; r < 16; ++r) R[wave * 1024 + r * 64 + lane] = acc[r];
   }
   __syncthreads();
-  // stage 2: r[a1][a2] = sum_x2 T[a1][x2] P2[a2][x2]; ntile (1, 2 or 4) tiles, 4/ntile waves per tile
-  const int mb2 = (k1 + 31) / 32, cb2 = (k2 + 31) / 32, ntile = mb2 * cb2;
-  const int wpt = 4 / ntile;  // waves per tile
-  const int tile = wave / wpt, part = wave - tile * wpt;
-  const int mb = tile / cb2, cb = tile - mb * cb2;
-  const int arow = mb * 32 + li, a2 = cb * 32 + li;
-  const int seg = ((n2 + 2 * wpt - 1) / (2 * wpt)) * 2;
-  const int lb = part * seg, le = min(n2, lb + seg);
-  f32x16 acc;
-  zero16(acc);
-  for (int kk = lb; kk < le; kk += 2) {
-    const int l = kk + kh;
-    const float av = (arow < k1 && l < le) ? T[arow * ldt + l] : 0.f;
-    const float bv = (a2 < k2 && l < le) ? P2t[(int64_t)l * k2 + a2] : 0.f;
-    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
-  }
-#pragma unroll
-  for (int r = 0; r < 16; ++r) R[wave * 1024 + r * 64 + lane] = acc[r];
-  __syncthreads();
-  // epilogue: one thread per output coefficient of this (field, a0) slab
-  float* dst = a.out[f] + (int64_t)a0 * k1 * k2;
-  const float al = a.alpha[f], be = a.beta[f];
-  for (int e = tid; e < k1 * k2; e += 256) {
-    const int r1 = e / k2, r2 = e - r1 * k2;
-    const int tm = r1 >> 5, tc = r2 >> 5, t = tm * cb2 + tc;
-    const int rr = r1 & 31, ln = r2 & 31;
-    // register index and lane of (rr, ln) in the 32x32 accumulator layout
-    const int reg = ((rr >> 3) << 2) + (rr & 3), lanei = ln + 32 * ((rr >> 2) & 1);
+  for (int e = tid; e < kRows * k2; e += 256) {
+    const int x = e / k2, c = e - x * k2;
+    const int t = c >> 5, reg = ((x >> 3) << 2) + (x & 3), lanei = (c & 31) + 32 * ((x >> 2) & 1);
     float sum = 0.f;
     for (int w = 0; w < wpt; ++w) sum += R[(t * wpt + w) * 1024 + reg * 64 + lanei];
-    dst[e] = be == 0.f ? al * sum : be * dst[e] + al * sum;
+    U[x * ldu + c] = sum;
   }
+  __syncthreads();
+  // stage B: partial r[a1][a2] = sum_{x < 32} P1[a1][x1b + x] U[x][a2], one wave per 32x32 tile
+  const int mb2 = (k1 + 31) / 32;
+  float* part = a.part + ((int64_t)slab * nsplit + sp) * k1 * k2;
+  if (wave < mb2 * cb2) {
+    const int mb = wave / cb2, cb = wave - mb * cb2;
+    const int a1 = mb * 32 + li, a2 = cb * 32 + li;
+    f32x16 acc;
+    zero16(acc);
+#pragma unroll 4
+    for (int kk = 0; kk < kRows; kk += 2) {
+      const int l = kk + kh;
+      const float av = (a1 < k1 && x1b + l < n1) ? P1t[(int64_t)(x1b + l) * k1 + a1] : 0.f;
+      const float bv = a2 < k2 ? U[l * ldu + a2] : 0.f;
+      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
+    }
+    if (a2 < k2) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = mb * 32 + acc_row(r, lane);
+        if (row < k1) part[row * k2 + a2] = acc[r];
+      }
+    }
+  }
+}
+
+// out[f][a0][:] = beta out + alpha * sum_q part[f][a0][q][:], one thread per band coefficient
+__global__ __launch_bounds__(256) void k_pi_fin(PiBAArgs a, int nsplit) {
+  const int kk = a.k1 * a.k2;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= kk) return;
+  const int a0 = blockIdx.y, f = blockIdx.z;
+  const int slab = f * a.k0 + a0;
+  const float* p0 = a.part + (int64_t)slab * nsplit * kk + e;
+  float sum = 0.f;
+  for (int q = 0; q < nsplit; ++q) sum += p0[(int64_t)q * kk];
+  float* dst = a.out[f] + (int64_t)a0 * kk + e;
+  const float al = a.alpha[f], be = a.beta[f];
+  *dst = be == 0.f ? al * sum : be * *dst + al * sum;
 }
 
 }  // namespace
 
 bool fused_dft_ok(int n1, int n2, int k1, int k2) {
-  const size_t lds_iota = ((size_t)k1 * (k2 + 1) + (size_t)k1 * (n2 + 4)) * sizeof(float);
-  const size_t lds_pi = (4096 + (size_t)k1 * (n2 + 4)) * sizeof(float);
-  return n1 <= kMaxN && n2 <= kMaxN && k1 <= kMaxK && k2 <= kMaxK && k1 >= 2 && k2 >= 2 && lds_iota <= 65536 &&
-         lds_pi <= 65536;
+  return n1 <= kMaxN && n2 <= kMaxN && k1 <= kMaxK && k2 <= kMaxK && k1 >= 2 && k2 >= 2 &&
+         (size_t)iota_lds(k1, k2, n2, false) * sizeof(float) <= 65536 &&
+         (size_t)pi_lds(k2, n2) * sizeof(float) <= 65536;
 }
+
+int pi_ba_splits(int n1) { return ceil_div(n1, kRows); }
 
 void iota_ab(const IotaABArgs& a, int nf, hipStream_t s) {
   const double bytes = 4.0 * nf * ((double)a.k0 * a.k1 * a.k2 + (double)a.k0 * a.n1 * a.n2);
   const double flops = 2.0 * nf * a.k0 * ((double)a.k1 * a.k2 * a.n2 + (double)a.n1 * a.k1 * a.n2);
-  dim3 g(ceil_div(a.n1, 64), a.k0, nf);
-  const uint32_t sm = (uint32_t)(a.k1 * (a.k2 + 1) + a.k1 * (a.n2 + 4)) * sizeof(float);
-  prof::launch("k_iota_ab", bytes, flops, k_iota_ab, g, dim3(256), sm, s, a);
+  dim3 g(ceil_div(a.n1, kRows), a.k0, nf);
+  const bool stage = (size_t)iota_lds(a.k1, a.k2, a.n2, true) * sizeof(float) <= 65536;
+  const uint32_t sm = (uint32_t)iota_lds(a.k1, a.k2, a.n2, stage) * sizeof(float);
+  if (stage)
+    prof::launch("k_iota_ab", bytes, flops, k_iota_ab<true>, g, dim3(256), sm, s, a);
+  else
+    prof::launch("k_iota_ab", bytes, flops, k_iota_ab<false>, g, dim3(256), sm, s, a);
   LDDMM_LAUNCH_CHECK();
 }
 
 void pi_ba(const PiBAArgs& a, int nf, hipStream_t s) {
   const double bytes = 4.0 * nf * ((double)a.k0 * a.n1 * a.n2 + (double)a.k0 * a.k1 * a.k2);
-  const double flops = 2.0 * nf * a.k0 * ((double)a.k1 * a.n1 * a.n2 + (double)a.k1 * a.n2 * a.k2);
-  dim3 g(1, a.k0, nf);
-  const uint32_t sm = (uint32_t)(4096 + a.k1 * (a.n2 + 4)) * sizeof(float);
+  const double flops = 2.0 * nf * a.k0 * ((double)a.k2 * a.n1 * a.n2 + (double)a.k1 * a.n1 * a.k2);
+  if (!a.part) throw ArgError("pi_ba needs its partial-sum workspace");
+  const int nsplit = pi_ba_splits(a.n1);
+  dim3 g(nsplit, a.k0, nf);
+  const uint32_t sm = (uint32_t)pi_lds(a.k2, a.n2) * sizeof(float);
   prof::launch("k_pi_ba", bytes, flops, k_pi_ba, g, dim3(256), sm, s, a);
+  LDDMM_LAUNCH_CHECK();
+  dim3 gf(ceil_div(a.k1 * a.k2, 256), a.k0, nf);
+  prof::launch("k_pi_fin", 4.0 * nf * a.k0 * a.k1 * a.k2 * (nsplit + 2.0), 0.0, k_pi_fin, gf, dim3(256), 0, s, a,
+               nsplit);
   LDDMM_LAUNCH_CHECK();
 }
 

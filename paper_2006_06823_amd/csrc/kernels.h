@@ -37,9 +37,11 @@ struct PiBAArgs {
   float* out[kMaxFields];  // per-field band output [k0][k1][k2]: out = beta out + alpha r
   float alpha[kMaxFields];
   float beta[kMaxFields];
+  float* part;  // workspace: [nf][k0][pi_ba_splits(n1)][k1][k2] partial projections
   int k0, k1, k2, n1, n2;
 };
 bool fused_dft_ok(int n1, int n2, int k1, int k2);
+int pi_ba_splits(int n1);
 void iota_ab(const IotaABArgs& a, int nf, hipStream_t s);
 void pi_ba(const PiBAArgs& a, int nf, hipStream_t s);
 

@@ -282,6 +282,11 @@ class Solver final : public SolverBase {
       rho_.alloc(nn * 3 * Q);
     }
     work_.alloc(reduce_work_size());
+    if (std::is_same<T, float>::value && d_.n[0] > 0) {
+      // partial projections of the split fused projection
+      const int64_t slabs = (int64_t)kMaxFields * d_.k[0];
+      pipart_.alloc(slabs * pi_ba_splits(d_.n[1]) * d_.k[1] * d_.k[2]);
+    }
     double* hp = nullptr;
     LDDMM_HIP(hipHostMalloc(reinterpret_cast<void**>(&hp), 8 * sizeof(double), hipHostMallocDefault));
     host_.reset(hp);
@@ -445,6 +450,7 @@ class Solver final : public SolverBase {
         PiBAArgs b{};
         b.in = srcB;
         b.p1t = mat(1, kProjT);
+        b.part = pipart_.get();
         b.p2t = mat(2, kProjT);
         for (int f = 0; f < nf; ++f) {
           b.out[f] = dst[f];
@@ -500,6 +506,7 @@ class Solver final : public SolverBase {
         PiBAArgs c{};
         c.in = t1_.get();
         c.p1t = mat(1, kProjT);
+        c.part = pipart_.get();
         c.p2t = mat(2, kProjT);
         for (int f = 0; f < 4; ++f) {
           c.out[f] = dst[f];
@@ -826,6 +833,7 @@ class Solver final : public SolverBase {
   DevBuf<T> inc_, incadj_;
   DevBuf<T> G_, m_, lam0_;               // image transport
   DevBuf<T> ubl_, Du_, m1_, g1_, rho_;   // deformation state
+  DevBuf<float> pipart_;
 
  public:
   // accessors used by the Gauss-Newton driver

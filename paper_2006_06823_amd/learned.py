@@ -20,9 +20,10 @@ its gradient, Adam, and the registrations.  Python only draws the seeded phantom
 (paper_2006_06823_amd.synthetic) and schedules the calls.
 
 Command line (runs on one ROCm device):
-  python -m paper_2006_06823_amd.learned generate --seeds 0:1000 --out data0.npz
-  python -m paper_2006_06823_amd.learned train --data data0.npz data1.npz --eval-seeds 100000:100200 \\
+  python -m paper_2006_06823_amd.learned generate --seeds 10000:11000 --out data0.npz
+  python -m paper_2006_06823_amd.learned train --data data0.npz data1.npz --eval-seeds 20000:20200 \\
          --weights net.npz --report report.json
+(--variant 1 or 3 selects the image-transport or the deformation-state formulation; default 3.)
 """
 from __future__ import annotations
 
@@ -95,7 +96,7 @@ def parse_range(spec: str) -> List[int]:
 class Registrar:
     """One band-limited registration context plus the helpers of the learned path."""
 
-    def __init__(self, shape=SHAPE, band=BAND, nt=NT, alpha=0.0025, s=2, device="cuda:0"):
+    def __init__(self, shape=SHAPE, band=BAND, nt=NT, alpha=0.0025, s=2, device="cuda:0", variant=3):
         import torch
         from . import lddmm_bl as L
         self.torch = torch
@@ -103,7 +104,8 @@ class Registrar:
         self.device = torch.device(device)
         self.alpha, self.s = alpha, s
         self.band = tuple(band)
-        self.ctx = L.Context(L.Problem(n=tuple(shape), k=tuple(band), nt=nt, variant=L.IMAGE_TRANSPORT,
+        self.variant = variant
+        self.ctx = L.Context(L.Problem(n=tuple(shape), k=tuple(band), nt=nt, variant=variant,
                                        alpha=alpha, s=s, precision=L.FP32), device=self.device)
 
     def set_pair(self, I0, I1):
@@ -141,7 +143,7 @@ def target_block(v, block=BLOCK):
     return t
 
 
-def generate(seeds: Sequence[int], opts: SolveOpts, stream: PairStream, log=print) -> Dict[str, np.ndarray]:
+def generate(seeds: Sequence[int], opts: SolveOpts, stream: PairStream, log=print, variant=3) -> Dict[str, np.ndarray]:
     """Plain Gauss-Newton-Krylov on each seeded pair; keeps the converged velocity's low block.
 
     Returns arrays: seeds, blocks [n][3][b][b][b], energy_full / energy_block (squared V-norms
@@ -156,7 +158,7 @@ def generate(seeds: Sequence[int], opts: SolveOpts, stream: PairStream, log=prin
     t0 = time.time()
     for i, (seed, I0, I1) in enumerate(stream.pairs(seeds)):
         if reg is None:
-            reg = Registrar()
+            reg = Registrar(variant=variant)
             torch = reg.torch
             net = WarmStartNet(channels=CHANNELS, in_size=IN_SIZE, seed=0, device=reg.device)
         reg.set_pair(I0, I1)
@@ -319,6 +321,15 @@ def summarize(rows, with_Z=True):
     for nme in names[1:]:
         s[nme]["gn_iter_ratio"] = s["plain"]["gn_iters_mean"] / max(s[nme]["gn_iters_mean"], 1e-9)
         s[nme]["time_ratio"] = s["plain"]["seconds_mean"] / max(s[nme]["seconds_mean"], 1e-9)
+        # over the pairs where both runs reached the tolerance
+        both = [r for r in rows if r["plain"]["grad_inf_rel"] <= 1e-3 and r[nme]["grad_inf_rel"] <= 1e-3]
+        if both:
+            key_t = "seconds_total"
+            s[nme]["both_reached"] = len(both)
+            s[nme]["gn_iter_ratio_both"] = (float(np.mean([r["plain"]["gn_iters"] for r in both]))
+                                           / max(float(np.mean([r[nme]["gn_iters"] for r in both])), 1e-9))
+            s[nme]["time_ratio_both"] = (float(np.mean([r["plain"]["seconds"] for r in both]))
+                                        / max(float(np.mean([r[nme][key_t] for r in both])), 1e-9))
     return s
 
 
@@ -340,9 +351,10 @@ def _main(argv=None):
     g = sub.add_parser("generate")
     g.add_argument("--seeds", required=True)
     g.add_argument("--out", required=True)
-    g.add_argument("--workers", type=int, default=0)
+    g.add_argument("--workers", type=int, default=10)
     g.add_argument("--max-gn", type=int, default=20)
     g.add_argument("--max-pcg", type=int, default=10)
+    g.add_argument("--variant", type=int, default=3, choices=(1, 3))
     t = sub.add_parser("train")
     t.add_argument("--data", nargs="+", required=True)
     t.add_argument("--eval-seeds", default="")
@@ -356,12 +368,13 @@ def _main(argv=None):
     t.add_argument("--max-gn", type=int, default=20)
     t.add_argument("--max-pcg", type=int, default=10)
     t.add_argument("--no-Z", action="store_true")
+    t.add_argument("--variant", type=int, default=3, choices=(1, 3))
     a = ap.parse_args(argv)
     stream = PairStream(a.workers)  # fork the renderers before the GPU is touched
     opts = SolveOpts(a.max_gn, a.max_pcg)
     try:
         if a.cmd == "generate":
-            d = generate(parse_range(a.seeds), opts, stream)
+            d = generate(parse_range(a.seeds), opts, stream, variant=a.variant)
             np.savez(a.out, **d)
             print(json.dumps({"pairs": int(d["seeds"].size), "gn_iters_mean": float(d["gn_iters"].mean()),
                               "seconds_mean": float(d["seconds"].mean()),
@@ -374,7 +387,7 @@ def _main(argv=None):
         blocks = np.concatenate([d["blocks"] for d in data]).astype(np.float32)
         ok = np.concatenate([d["status"] for d in data]) >= 0
         seeds, blocks = seeds[ok], blocks[ok]
-        reg = Registrar()
+        reg = Registrar(variant=a.variant)
         net = WarmStartNet(channels=CHANNELS, in_size=IN_SIZE, seed=1234, device=reg.device)
         t0 = time.time()
         pairs = []
