@@ -31,6 +31,7 @@ FP32_PEAK_TFLOPS = 157.3     # MI355X dense FP32 (matrix and vector)
 
 # variant-1 Hessian matvec kernels that move data (HBM roofline); DFT kernels also report MFMA use
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_dominant_kernel.json")
+WEIGHTS_FILE = os.path.join(ROOT, "paper_2006_06823_amd", "weights", "warmstart_v1_128.npz")
 
 
 def parse():
@@ -43,6 +44,8 @@ def parse():
     ap.add_argument("--band", type=int, nargs=3, default=(32, 32, 32))
     ap.add_argument("--nt", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--learned-pairs", type=int, default=2,
+                    help="held-out pairs registered plain and with the trained warm start (0: skip)")
     return ap.parse_args()
 
 
@@ -139,6 +142,10 @@ def main():
     ctx.adjoint_solve()
     adjoint_ms = (time.perf_counter() - t0) * 1e3
 
+    learned = None
+    if args.learned_pairs > 0 and args.variant == 1 and N == (128, 128, 128) and K == (32, 32, 32):
+        learned = learned_leg(args.learned_pairs)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(variant, N, K, Nt, I0, I1, (vc * (8.0 / vmax)), syn.random_bl_coefficients(3, K, seed=3))
@@ -160,9 +167,33 @@ def main():
                   "dft_mfma_frac_fp32": round(dft_flops / (dft_ms * 1e-3) / 1e12 / FP32_PEAK_TFLOPS, 4)
                   if dft_ms > 0 else None,
                   "state_solve_ms": round(state_ms, 3), "adjoint_solve_ms": round(adjoint_ms, 3),
-                  "objective": E, "kernels": kernels},
+                  "objective": E, "kernels": kernels, "registrations": learned},
     }
     print(json.dumps(line), flush=True)
+
+
+def learned_leg(npairs):
+    """Registrations/s on held-out pairs: plain GN-Krylov vs the trained warm start (if its weights exist)."""
+    if not os.path.exists(WEIGHTS_FILE):
+        return {"skipped": "no trained weights"}
+    from paper_2006_06823_amd import learned as LW
+    seeds = list(range(20000, 20000 + npairs))
+    pairs = [LW.render_pair(sd) for sd in seeds]
+    reg = LW.Registrar(variant=1)
+    net = LW.load_weights(WEIGHTS_FILE, device=reg.device)
+
+    class _List:
+        def pairs(self, sds):
+            for sd, (a, b) in zip(sds, pairs):
+                yield sd, a, b
+    rows = LW.compare(net, reg, seeds, _List(), LW.SolveOpts(), log=lambda *a, **k: None, with_Z=True)
+    summ = LW.summarize(rows, with_Z=True)
+    out = {"pairs": npairs, "seeds": f"{seeds[0]}..{seeds[-1]}", "tolerance": "rel grad 1e-3 of |g(0)|_inf",
+           "caps": "20 GN x 10 PCG"}
+    for k in ("plain", "learned", "learned_Z"):
+        out[k] = {m: round(summ[k][m], 4) for m in ("registrations_per_s", "gn_iters_mean", "hess_matvecs_mean",
+                                                    "seconds_mean", "reached_tol")}
+    return out
 
 
 def cpu_baseline(variant, N, K, Nt, I0, I1, v, dv):
@@ -177,12 +208,14 @@ def cpu_baseline(variant, N, K, Nt, I0, I1, v, dv):
     model = (Variant1 if variant == 1 else Variant3)(OP(N, K, Nt=Nt), I0.astype(np.float64), I1.astype(np.float64))
     model.setup(v)
     model.state()
+    reps = 3
     t0 = time.perf_counter()
-    model.hess_matvec(dv)
-    dt = time.perf_counter() - t0
+    for _ in range(reps):
+        model.hess_matvec(dv)
+    dt = (time.perf_counter() - t0) / reps
     return {"value": round(1.0 / dt, 5), "unit": "matvec/s", "cores": torch.get_num_threads(), "kind": "oracle",
-            "sample": f"one full Hessian matvec of the same workload in the FP64 oracle (torch CPU), "
-                      f"{dt:.1f} s; set-up and state solve excluded"}
+            "sample": f"{reps} full Hessian matvecs of the same workload in the FP64 oracle (torch CPU), "
+                      f"{dt:.1f} s each; set-up and state solve excluded"}
 
 
 if __name__ == "__main__":

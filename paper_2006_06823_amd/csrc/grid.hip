@@ -450,6 +450,104 @@ __global__ void k_prefilter_inner(T* f, int n2, int64_t rows, int rpb) {
   }
 }
 
+// chunk-parallel form for lines of at most kChunkMaxN points: a block stages 32 lines in LDS,
+// 8 threads per line each own one chunk; a chunk starts its causal (anti-causal) recursion from
+// the truncated geometric sum over the horizon points before (after) it, the same truncation
+// as the serial start values, so every chunk runs independently.
+constexpr int kChunkLines = 32, kChunkGroups = 8, kChunkMaxC = 24, kChunkMaxN = kChunkGroups * kChunkMaxC;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_prefilter_chunked(T* f, int n, int64_t gl, int64_t gi, int nlines_max,
+                                                           int64_t tile_stride_a, int tiles_a, int64_t tile_stride_b,
+                                                           int64_t P) {
+  extern __shared__ unsigned char smem_raw[];
+  T* sm = reinterpret_cast<T*>(smem_raw);  // [n][33]: element (line l, point i) at i * 33 + l
+  constexpr int ld = kChunkLines + 1;
+  // block -> (field, outer index b, tile of 32 lines a)
+  const int ta = blockIdx.x % tiles_a;
+  const int64_t tb = blockIdx.x / tiles_a;
+  T* base = f + blockIdx.y * P + tb * tile_stride_b + (int64_t)ta * kChunkLines * tile_stride_a;
+  const int nl = min(kChunkLines, nlines_max - ta * kChunkLines);
+  const int tid = threadIdx.x;
+  const bool line_major = gi == 1;  // points of a line contiguous in memory
+  for (int e = tid; e < n * kChunkLines; e += 256) {
+    int l, i;
+    if (line_major) {
+      l = e / n, i = e - l * n;
+    } else {
+      i = e / kChunkLines, l = e - i * kChunkLines;
+    }
+    if (l < nl) sm[i * ld + l] = base[l * gl + i * gi];
+  }
+  __syncthreads();
+  const double z = Pole<T>::z;
+  const int h = n < Pole<T>::horizon ? n : Pole<T>::horizon;
+  double zn = 1.0;
+  for (int i = 0; i < n; ++i) zn *= z;
+  const double inv = 1.0 / (1.0 - zn);
+  const int l = tid % kChunkLines, g = tid / kChunkLines;
+  const int Lc = (n + kChunkGroups - 1) / kChunkGroups;
+  const int c0 = g * Lc, c1 = min(n, c0 + Lc);
+  double cp[kChunkMaxC];
+  // causal: c+[i] = 6 f[i] + z c+[i-1]
+  {
+    double acc = 0.0, zi = 1.0;
+    for (int k = 0; k < h; ++k) {
+      int j = c0 - k;
+      j = ((j % n) + n) % n;
+      acc += zi * 6.0 * static_cast<double>(sm[j * ld + l]);
+      zi *= z;
+    }
+    double prev = acc * inv;
+#pragma unroll
+    for (int q = 0; q < kChunkMaxC; ++q) {
+      const int i = c0 + q;
+      if (i < c1) {
+        if (q > 0) prev = 6.0 * static_cast<double>(sm[i * ld + l]) + z * prev;
+        cp[q] = prev;
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kChunkMaxC; ++q)
+    if (c0 + q < c1) sm[(c0 + q) * ld + l] = static_cast<T>(cp[q]);
+  __syncthreads();
+  // anti-causal: c[i] = z (c[i+1] - c+[i]), started at the chunk's last point
+  {
+    const int e = c1 - 1;
+    double acc = 0.0, zi = 1.0;
+    for (int k = 0; k < h; ++k) {
+      const int j = (e + k) % n;
+      acc += zi * static_cast<double>(sm[j * ld + l]);
+      zi *= z;
+    }
+    double prev = -z * inv * acc;
+#pragma unroll
+    for (int q = kChunkMaxC - 1; q >= 0; --q) {
+      const int i = c0 + q;
+      if (i < c1) {
+        if (i < e) prev = z * (prev - static_cast<double>(sm[i * ld + l]));
+        cp[q] = prev;
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kChunkMaxC; ++q)
+    if (c0 + q < c1) sm[(c0 + q) * ld + l] = static_cast<T>(cp[q]);
+  __syncthreads();
+  for (int e = tid; e < n * kChunkLines; e += 256) {
+    int ll, i;
+    if (line_major) {
+      ll = e / n, i = e - ll * n;
+    } else {
+      i = e / kChunkLines, ll = e - i * kChunkLines;
+    }
+    if (ll < nl) base[ll * gl + i * gi] = sm[i * ld + ll];
+  }
+}
+
 inline dim3 grid_for(int64_t n) { return dim3(ceil_div(n, kBlock)); }
 
 }  // namespace
@@ -507,27 +605,52 @@ void interp(T* out, const T* coef, int nf, const T* disp, const Dims& d, hipStre
 template <typename T>
 void prefilter(T* f, int nf, const Dims& d, hipStream_t s) {
   const int n0 = d.n[0], n1 = d.n[1], n2 = d.n[2];
-  if (n2 > 1) {
-    const int64_t rows = (int64_t)nf * n0 * n1;
-    int rpb = static_cast<int>(49152 / ((size_t)(n2 + 1) * sizeof(T)));
-    rpb = rpb > 64 ? 64 : rpb;
-    if (rpb < 1) throw ArgError("prefilter: grid line too long");
-    const size_t sm = (size_t)rpb * (n2 + 1) * sizeof(T);
-    prof::launch(std::string("k_prefilter_inner<") + prof::tname<T>() + ">", 2.0 * rows * n2 * sizeof(T), 0.0,
-                 k_prefilter_inner<T>, dim3(ceil_div(rows, rpb)), dim3(64), (uint32_t)sm, s, f, n2, rows, rpb);
+  const std::string nm = std::string("k_prefilter_chunked<") + prof::tname<T>() + ">";
+  // lines of `n` points at element stride gi; 32 consecutive lines (stride gl) per tile, tiles
+  // along the line index a, outer index b
+  auto chunked = [&](int n, int64_t gl, int64_t gi, int nlines_a, int64_t stride_b, int nb) {
+    const int tiles_a = ceil_div(nlines_a, kChunkLines);
+    const uint32_t sm = (uint32_t)((size_t)n * (kChunkLines + 1) * sizeof(T));
+    prof::launch(nm, 2.0 * nf * d.P * sizeof(T), 0.0, k_prefilter_chunked<T>, dim3(tiles_a * nb, nf), dim3(256),
+                 sm, s, f, n, gl, gi, nlines_a, gl, tiles_a, stride_b, d.P);
     LDDMM_LAUNCH_CHECK();
+  };
+  if (n2 > 1) {
+    if (n2 <= kChunkMaxN) {
+      // lines along axis 2: tiles of 32 consecutive rows x1 at fixed x0
+      chunked(n2, (int64_t)n2, 1, n1, (int64_t)n1 * n2, n0);
+    } else {
+      const int64_t rows = (int64_t)nf * n0 * n1;
+      int rpb = static_cast<int>(49152 / ((size_t)(n2 + 1) * sizeof(T)));
+      rpb = rpb > 64 ? 64 : rpb;
+      if (rpb < 1) throw ArgError("prefilter: grid line too long");
+      const size_t sm = (size_t)rpb * (n2 + 1) * sizeof(T);
+      prof::launch(std::string("k_prefilter_inner<") + prof::tname<T>() + ">", 2.0 * rows * n2 * sizeof(T), 0.0,
+                   k_prefilter_inner<T>, dim3(ceil_div(rows, rpb)), dim3(64), (uint32_t)sm, s, f, n2, rows, rpb);
+      LDDMM_LAUNCH_CHECK();
+    }
   }
   if (n1 > 1) {
-    const int64_t lines = (int64_t)n0 * n2;
-    prof::launch(std::string("k_prefilter_outer<") + prof::tname<T>() + ">", 2.0 * nf * d.P * sizeof(T), 0.0,
-                 k_prefilter_outer<T>, grid_for(lines * nf), dim3(kBlock), 0, s, f, n0, n1, n2, 1, lines, d.P, nf);
-    LDDMM_LAUNCH_CHECK();
+    if (n1 <= kChunkMaxN) {
+      // lines along axis 1: tiles of 32 consecutive x2 at fixed x0
+      chunked(n1, 1, (int64_t)n2, n2, (int64_t)n1 * n2, n0);
+    } else {
+      const int64_t lines = (int64_t)n0 * n2;
+      prof::launch(std::string("k_prefilter_outer<") + prof::tname<T>() + ">", 2.0 * nf * d.P * sizeof(T), 0.0,
+                   k_prefilter_outer<T>, grid_for(lines * nf), dim3(kBlock), 0, s, f, n0, n1, n2, 1, lines, d.P, nf);
+      LDDMM_LAUNCH_CHECK();
+    }
   }
   if (n0 > 1) {
-    const int64_t lines = (int64_t)n1 * n2;
-    prof::launch(std::string("k_prefilter_outer<") + prof::tname<T>() + ">", 2.0 * nf * d.P * sizeof(T), 0.0,
-                 k_prefilter_outer<T>, grid_for(lines * nf), dim3(kBlock), 0, s, f, n0, n1, n2, 0, lines, d.P, nf);
-    LDDMM_LAUNCH_CHECK();
+    if (n0 <= kChunkMaxN) {
+      // lines along axis 0: tiles of 32 consecutive x2 at fixed x1
+      chunked(n0, 1, (int64_t)n1 * n2, n2, (int64_t)n2, n1);
+    } else {
+      const int64_t lines = (int64_t)n1 * n2;
+      prof::launch(std::string("k_prefilter_outer<") + prof::tname<T>() + ">", 2.0 * nf * d.P * sizeof(T), 0.0,
+                   k_prefilter_outer<T>, grid_for(lines * nf), dim3(kBlock), 0, s, f, n0, n1, n2, 0, lines, d.P, nf);
+      LDDMM_LAUNCH_CHECK();
+    }
   }
 }
 
