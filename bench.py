@@ -44,6 +44,11 @@ def parse():
     ap.add_argument("--band", type=int, nargs=3, default=(32, 32, 32))
     ap.add_argument("--nt", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batched", type=int, default=0,
+                    help="instead of the matvec benchmark: register this many uneven subjects (96^3..192^3, "
+                         "deformation-state variant, split-bf16 DFT) to one template in one batched GN-Krylov call")
+    ap.add_argument("--batched-gn", type=int, default=2)
+    ap.add_argument("--batched-pcg", type=int, default=5)
     ap.add_argument("--learned-pairs", type=int, default=2,
                     help="held-out pairs registered plain and with the trained warm start (0: skip)")
     return ap.parse_args()
@@ -61,6 +66,10 @@ def main():
 
     from paper_2006_06823_amd import lddmm_bl as L
     from paper_2006_06823_amd import synthetic as syn
+
+    if args.batched > 0:
+        print(json.dumps(batched_leg(args)), flush=True)
+        return
 
     N, K, Nt = tuple(args.size), tuple(args.band), args.nt
     variant = L.IMAGE_TRANSPORT if args.variant == 1 else L.DEFORMATION_STATE
@@ -170,6 +179,51 @@ def main():
                   "objective": E, "kernels": kernels, "registrations": learned},
     }
     print(json.dumps(line), flush=True)
+
+
+def _render_subject(i):
+    from paper_2006_06823_amd import synthetic as syn
+    import numpy as np
+    n = 96 + 16 * int(np.random.default_rng(1000 + i).integers(0, 7))
+    I0, I1 = syn.phantom_pair_3d((n, n, n), 1000 + i, max_disp_vox=8.0, template_seed=999)
+    return n, I0, I1
+
+
+def batched_leg(args):
+    """Uneven subjects (N_i in {96, 112, ..., 192}, K_i = clamp(8 ceil(N_i / 32), 32, 48)) registered to one
+    template in one batched Gauss-Newton-Krylov call with a fixed iteration budget."""
+    import multiprocessing as mp
+    import numpy as np
+    import torch
+    from paper_2006_06823_amd import lddmm_bl as L
+    B = args.batched
+    with mp.get_context("fork").Pool(min(16, B)) as pool:
+        subj = pool.map(_render_subject, range(B))
+    dev = torch.device("cuda", 0)
+    probs, I0s, I1s, vs = [], [], [], []
+    for n, I0, I1 in subj:
+        k = min(48, max(32, 8 * -(-n // 32)))
+        probs.append(L.Problem((n, n, n), (k, k, k), nt=args.nt, variant=L.DEFORMATION_STATE, precision=L.BF16_DFT))
+        I0s.append(torch.from_numpy(I0).to(dev))
+        I1s.append(torch.from_numpy(I1).to(dev))
+        vs.append(torch.zeros((3, k, k, k), dtype=torch.float32, device=dev))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, reps = L.gn_solve_batched(probs, I0s, I1s, vs, max_gn=args.batched_gn, max_pcg=args.batched_pcg,
+                                  fixed_iters=True, device=dev)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    mv = sum(r["hess_matvecs"] for r in reps)
+    vox = sum(n ** 3 for n, _, _ in subj)
+    return {"metric": "batched subject Hessian-matvecs/s", "value": round(mv / wall, 2), "unit": "matvec/s",
+            "n_gpus": 1, "higher_is_better": True, "dtype": "bf16-split DFT, f32 fields, f64 reductions",
+            "data": "synthetic",
+            "config": {"workload": f"{B} subjects 96^3..192^3 to one template, deformation-state, Nt={args.nt}, "
+                                   f"{args.batched_gn} GN x {args.batched_pcg} PCG fixed",
+                       "subject_sizes": [n for n, _, _ in subj]},
+            "extra": {"wall_s": round(wall, 3), "status": st, "matvecs": mv,
+                      "voxel_matvecs_per_s": round(mv / wall * vox / B, 1),
+                      "mse_rel_mean": round(float(np.mean([r["mse_rel"] for r in reps])), 4)}}
 
 
 def learned_leg(npairs):
