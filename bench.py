@@ -244,9 +244,9 @@ def learned_leg(npairs):
     summ = LW.summarize(rows, with_Z=True)
     out = {"pairs": npairs, "seeds": f"{seeds[0]}..{seeds[-1]}", "tolerance": "rel grad 1e-3 of |g(0)|_inf",
            "caps": "20 GN x 10 PCG"}
-    for k in ("plain", "learned", "learned_Z"):
+    for k in ("plain", "learned", "learned_E", "learned_Z"):
         out[k] = {m: round(summ[k][m], 4) for m in ("registrations_per_s", "gn_iters_mean", "hess_matvecs_mean",
-                                                    "seconds_mean", "reached_tol")}
+                                                    "seconds_mean", "reached_tol", "reached_plain_E")}
     return out
 
 

@@ -96,6 +96,8 @@ typedef struct {
   double grad_rtol;       /* stop when ||g||_inf <= grad_rtol * reference */
   double grad_ref_inf;    /* reference ||g||_inf; 0 => ||g||_inf at the initial velocity */
   int32_t fixed_iters;    /* 1 => run every cap to the end (no tolerance exits) */
+  double energy_target;   /* > 0 => also stop once the objective E <= energy_target (0 = off); used to
+                             time how fast a warm-started run reaches a reference run's objective */
 } lddmm_bl_gn_opts;
 
 typedef struct {

@@ -981,7 +981,9 @@ int Solver<T>::gn_solve(const lddmm_bl_gn_opts& o, void* v_user, const void* Zu,
   };
   int k = 0;
   for (k = 0; k < o.max_gn; ++k) {
+    if (trace_) fprintf(stderr, "[lddmm_bl] gn %d E %.17g ginf_rel %.6g\n", k, E, ginf / ref);
     if (!fixed && ginf <= o.grad_rtol * ref) break;
+    if (!fixed && o.energy_target > 0 && E <= o.energy_target) break;
     if (twolevel) {
       // Z^T H Z at the current velocity (r extra matvecs), inverted by Gauss-Jordan in double
       std::vector<double> A(r * r);
@@ -1089,7 +1091,9 @@ int Solver<T>::gn_solve(const lddmm_bl_gn_opts& o, void* v_user, const void* Zu,
     ginf = grad_inf_internal(g.get());
     R.gn_iters = k + 1;
   }
-  if (status == LDDMM_BL_OK && !fixed && k == o.max_gn && ginf > o.grad_rtol * ref) status = LDDMM_BL_W_MAXITER;
+  if (status == LDDMM_BL_OK && !fixed && k == o.max_gn && ginf > o.grad_rtol * ref &&
+      !(o.energy_target > 0 && E <= o.energy_target))
+    status = LDDMM_BL_W_MAXITER;
   internal_to_user(static_cast<T*>(v_user), v.get());
   R.E = E;
   R.grad_inf_rel = ref > 0 ? ginf / ref : 0.0;
@@ -1164,7 +1168,7 @@ int gn_solve_batched_impl(std::vector<Solver<T>*>& subs, const lddmm_bl_gn_opts&
     for (int i = 0; i < B; ++i) {
       Sub& u = S[i];
       if (u.failed || u.converged) continue;
-      if (!fixed && u.ginf <= o.grad_rtol * u.ref) {
+      if (!fixed && (u.ginf <= o.grad_rtol * u.ref || (o.energy_target > 0 && u.E <= o.energy_target))) {
         u.converged = true;
         continue;
       }

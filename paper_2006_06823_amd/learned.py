@@ -127,9 +127,9 @@ class Registrar:
         _, ginf = self.ctx.adjoint_solve()
         return ginf
 
-    def solve(self, v, opts: SolveOpts, gref: float, Z=None):
+    def solve(self, v, opts: SolveOpts, gref: float, Z=None, energy_target=0.0):
         st, rep = self.ctx.gn_solve(v, max_gn=opts.max_gn, max_pcg=opts.max_pcg, grad_rtol=opts.grad_rtol,
-                                    grad_ref_inf=gref, Z=Z)
+                                    grad_ref_inf=gref, Z=Z, energy_target=energy_target)
         rep["status"] = int(st)
         return rep
 
@@ -275,17 +275,20 @@ def compare(net, reg: Registrar, seeds, stream: PairStream, opts: SolveOpts, log
         row["pred_vnorm_rel"] = float(np.sqrt(e_pred / max(efull, 1e-30)))
         row["fallback"] = bool(fallback)
         row["t_predict"] = t_pred
-        variants = [("learned", None)]
+        # learned: same gradient tolerance; learned_E: stops at the plain run's final objective as well;
+        # learned_Z: gradient tolerance with the two-level preconditioner
+        variants = [("learned", None, 0.0), ("learned_E", None, row["plain"]["E"])]
         if with_Z:
-            variants.append(("learned_Z", "Z"))
-        for name, zmode in variants:
+            variants.append(("learned_Z", "Z", 0.0))
+        for name, zmode, etarget in variants:
             v = reg.zero_velocity() if fallback else v0.clone()
             Z = None
             if zmode and not fallback:
                 Z = torch.zeros((3, 3) + reg.band, dtype=torch.float32, device=reg.device)
                 for c in range(3):
                     Z[c, c] = v0[c]
-            rep = reg.solve(v, opts, gref, Z=Z)
+            rep = reg.solve(v, opts, gref, Z=Z, energy_target=etarget)
+            rep["reached_plain_E"] = bool(rep["E"] <= row["plain"]["E"])
             rep["seconds_total"] = rep["seconds"] + t_pred
             rep["vnorm_rel_to_plain"] = float(np.sqrt(
                 net.loss(zero, (v - vstar)[None].contiguous(), reg.alpha, reg.s, want_grad=False)[0]
@@ -296,7 +299,8 @@ def compare(net, reg: Registrar, seeds, stream: PairStream, opts: SolveOpts, log
             msg = f"eval {i + 1}/{len(seeds)} seed {seed}: plain gn {row['plain']['gn_iters']} " \
                   f"mv {row['plain']['hess_matvecs']} {row['plain']['seconds']:.2f}s | learned gn " \
                   f"{row['learned']['gn_iters']} mv {row['learned']['hess_matvecs']} " \
-                  f"{row['learned']['seconds_total']:.2f}s pred_err {row['pred_vnorm_rel']:.3f}"
+                  f"{row['learned']['seconds_total']:.2f}s pred_err {row['pred_vnorm_rel']:.3f} | to plain E gn " \
+                  f"{row['learned_E']['gn_iters']} {row['learned_E']['seconds_total']:.2f}s"
             if with_Z:
                 msg += f" | +Z gn {row['learned_Z']['gn_iters']} {row['learned_Z']['seconds_total']:.2f}s"
             log(msg, flush=True)
@@ -308,7 +312,7 @@ def summarize(rows, with_Z=True):
         return float(np.mean([r[name][key] for r in rows]))
     s = {"pairs": len(rows), "fallbacks": int(sum(r["fallback"] for r in rows)),
          "pred_vnorm_rel_mean": float(np.mean([r["pred_vnorm_rel"] for r in rows]))}
-    names = ["plain", "learned"] + (["learned_Z"] if with_Z else [])
+    names = ["plain", "learned", "learned_E"] + (["learned_Z"] if with_Z else [])
     for nme in names:
         key_t = "seconds" if nme == "plain" else "seconds_total"
         tot_t = float(np.sum([r[nme][key_t] for r in rows]))
@@ -317,6 +321,8 @@ def summarize(rows, with_Z=True):
                   "registrations_per_s": len(rows) / tot_t,
                   "grad_inf_rel_max": float(np.max([r[nme]["grad_inf_rel"] for r in rows])),
                   "reached_tol": int(sum(r[nme]["grad_inf_rel"] <= 1e-3 for r in rows)),
+                  "reached_plain_E": int(sum(r[nme]["E"] <= r["plain"]["E"] for r in rows)),
+                  "E_mean": agg(nme, "E"),
                   "mse_rel_mean": agg(nme, "mse_rel")}
     for nme in names[1:]:
         s[nme]["gn_iter_ratio"] = s["plain"]["gn_iters_mean"] / max(s[nme]["gn_iters_mean"], 1e-9)
@@ -369,6 +375,15 @@ def _main(argv=None):
     t.add_argument("--max-pcg", type=int, default=10)
     t.add_argument("--no-Z", action="store_true")
     t.add_argument("--variant", type=int, default=3, choices=(1, 3))
+    e = sub.add_parser("evaluate")
+    e.add_argument("--weights", required=True)
+    e.add_argument("--eval-seeds", required=True)
+    e.add_argument("--report", required=True)
+    e.add_argument("--workers", type=int, default=0)
+    e.add_argument("--max-gn", type=int, default=20)
+    e.add_argument("--max-pcg", type=int, default=10)
+    e.add_argument("--no-Z", action="store_true")
+    e.add_argument("--variant", type=int, default=3, choices=(1, 3))
     a = ap.parse_args(argv)
     stream = PairStream(a.workers)  # fork the renderers before the GPU is touched
     opts = SolveOpts(a.max_gn, a.max_pcg)
@@ -382,6 +397,15 @@ def _main(argv=None):
             return 0
         import torch
         from .lddmm_bl import WarmStartNet
+        if a.cmd == "evaluate":
+            reg = Registrar(variant=a.variant)
+            net = load_weights(a.weights, device=reg.device)
+            rows = compare(net, reg, parse_range(a.eval_seeds), stream, opts, with_Z=not a.no_Z)
+            report = {"weights": a.weights, "eval": summarize(rows, with_Z=not a.no_Z), "eval_rows": rows}
+            with open(a.report, "w") as f:
+                json.dump(report, f, indent=1)
+            print(json.dumps(report["eval"], indent=1))
+            return 0
         data = [np.load(p, allow_pickle=False) for p in a.data]
         seeds = np.concatenate([d["seeds"] for d in data])
         blocks = np.concatenate([d["blocks"] for d in data]).astype(np.float32)
