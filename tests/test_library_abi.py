@@ -35,3 +35,20 @@ def test_binding_loads_without_gpu():
     lib = L.load_library()
     assert lib.lddmm_bl_last_error(None) == b"null context"
     assert lib.lddmm_bl_destroy(None) == -1
+
+
+def test_committed_warm_start_weights_match_the_architecture():
+    import os
+    import numpy as np
+    from paper_2006_06823_amd import learned as LW
+    path = os.path.join(os.path.dirname(__file__), "..", "paper_2006_06823_amd", "weights", "warmstart_v1_128.npz")
+    z = np.load(path, allow_pickle=False)
+    ch = [int(c) for c in z["channels"]]
+    assert tuple(ch) == LW.CHANNELS and int(z["in_size"]) == LW.IN_SIZE
+    n, cin = 0, 2
+    for c in ch:
+        n += c * cin * 27 + c
+        cin = c
+    n += 3 * cin + 3
+    assert z["params"].shape == (n,) and z["params"].dtype == np.float32
+    assert np.isfinite(z["params"]).all()
