@@ -49,6 +49,9 @@ def parse():
                          "deformation-state variant, split-bf16 DFT) to one template in one batched GN-Krylov call")
     ap.add_argument("--batched-gn", type=int, default=2)
     ap.add_argument("--batched-pcg", type=int, default=5)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MB",
+                    help="instead of the benchmark: 5 plain device copies of MB megabytes (float32), the reference "
+                         "for scaling the HBM byte counters of a profiler run")
     ap.add_argument("--learned-pairs", type=int, default=2,
                     help="held-out pairs registered plain and with the trained warm start (0: skip)")
     return ap.parse_args()
@@ -69,6 +72,16 @@ def main():
 
     if args.batched > 0:
         print(json.dumps(batched_leg(args)), flush=True)
+        return
+    if args.calibrate_copy > 0:
+        n = args.calibrate_copy * (1 << 20) // 4
+        a = torch.rand(n, device="cuda:0")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": 4 * n, "copies": 5}), flush=True)
         return
 
     N, K, Nt = tuple(args.size), tuple(args.band), args.nt
