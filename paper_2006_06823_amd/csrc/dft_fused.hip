@@ -34,7 +34,12 @@ constexpr int kRows = 32;  // grid rows of axis 1 per block
 __host__ __device__ inline int iota_lds(int k1, int k2, int n2, bool stage_w2) {
   return k1 * (k2 + 1) + k1 * (n2 + 4) + k1 * kRows + (stage_w2 ? k2 * n2 : 0);
 }
-__host__ __device__ inline int pi_lds(int k2, int n2) { return kRows * (n2 + 1) + 4096 + kRows * (k2 + 1); }
+// LDS floats of k_pi_ba: the slab rows (aliased by the wave partials after stage A), U, and the
+// staged projection operands (P2 whole, the block's 32 rows of P1) when they fit
+__host__ __device__ inline int pi_lds(int k1, int k2, int n2, bool stage_p) {
+  const int in_r = kRows * (n2 + 1) > 4096 ? kRows * (n2 + 1) : 4096;
+  return in_r + kRows * (k2 + 1) + (stage_p ? n2 * k2 + kRows * k1 : 0);
+}
 
 // grid (ceil(n1 / 32), k0, nf): each block expands one (field, a0) slab for 32 rows of x1
 template <bool STAGE_W2>
@@ -120,26 +125,36 @@ __global__ __launch_bounds__(256) void k_iota_ab(IotaABArgs a) {
 // slab to a partial band block in the workspace; k_pi_fin then sums the partials of every slab
 // in split order (deterministic) and applies the epilogue.  (A last-block-done reduction inside
 // this kernel would need a device-scope release per block, which writes back the XCD's L2.)
+template <bool STAGE_P>
 __global__ __launch_bounds__(256) void k_pi_ba(PiBAArgs a) {
   extern __shared__ float smem[];
   const int sp = blockIdx.x, a0 = blockIdx.y, f = blockIdx.z, nsplit = gridDim.x;
   const int k0 = a.k0, k1 = a.k1, k2 = a.k2, n1 = a.n1, n2 = a.n2;
   const int x1b = sp * kRows;
   const int ldi = n2 + 1, ldu = k2 + 1;
+  const int in_r = kRows * ldi > 4096 ? kRows * ldi : 4096;
   float* In = smem;              // [32][n2 + 1] rows x1b.. of the slab
-  float* R = In + kRows * ldi;   // [4][1024] partial accumulators of the waves
-  float* U = R + 4096;           // [32][k2 + 1]
+  float* R = smem;               // [4][1024] partial accumulators of the waves (after stage A reads In)
+  float* U = smem + in_r;        // [32][k2 + 1]
+  float* P2s = U + kRows * ldu;  // [n2][k2] (staged)
+  float* P1s = P2s + n2 * k2;    // [32 rows of x1][k1] (staged)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int kh = lane >> 5, li = lane & 31;
   const int slab = f * k0 + a0;
   const float* __restrict__ in = a.in + (int64_t)slab * n1 * n2;
-  const float* __restrict__ P1t = a.p1t;  // [n1][k1]
-  const float* __restrict__ P2t = a.p2t;  // [n2][k2]
   for (int e = tid; e < kRows * n2; e += 256) {
     const int r = e / n2, c = e - r * n2;
     In[r * ldi + c] = (x1b + r < n1) ? in[(int64_t)(x1b + r) * n2 + c] : 0.f;
   }
+  if (STAGE_P) {
+    for (int e = tid; e < n2 * k2; e += 256) P2s[e] = a.p2t[e];
+    for (int e = tid; e < kRows * k1; e += 256) {
+      const int r = e / k1;
+      P1s[e] = (x1b + r < n1) ? a.p1t[(int64_t)x1b * k1 + e] : 0.f;
+    }
+  }
   __syncthreads();
+  const float* P2t = STAGE_P ? P2s : a.p2t;  // [n2][k2]
   // stage A: U[x][a2] = sum_x2 In[x][x2] P2[a2][x2]; cb2 column tiles, 4 / cb2 waves split x2
   const int cb2 = (k2 + 31) / 32, wpt = 4 / cb2;
   {
@@ -153,9 +168,10 @@ __global__ __launch_bounds__(256) void k_pi_ba(PiBAArgs a) {
     for (int kk = lb; kk < le; kk += 2) {
       const int l = kk + kh;
       const float av = l < le ? In[li * ldi + l] : 0.f;
-      const float bv = (a2 < k2 && l < le) ? P2t[(int64_t)l * k2 + a2] : 0.f;
+      const float bv = (a2 < k2 && l < le) ? P2t[l * k2 + a2] : 0.f;
       acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
     }
+    __syncthreads();  // every wave is done reading In before R overwrites it
 #pragma unroll
     for (int r = 0; r < 16; ++r) R[wave * 1024 + r * 64 + lane] = acc[r];
   }
@@ -179,7 +195,13 @@ __global__ __launch_bounds__(256) void k_pi_ba(PiBAArgs a) {
 #pragma unroll 4
     for (int kk = 0; kk < kRows; kk += 2) {
       const int l = kk + kh;
-      const float av = (a1 < k1 && x1b + l < n1) ? P1t[(int64_t)(x1b + l) * k1 + a1] : 0.f;
+      float av = 0.f;
+      if (a1 < k1) {
+        if (STAGE_P)
+          av = P1s[l * k1 + a1];
+        else if (x1b + l < n1)
+          av = a.p1t[(int64_t)(x1b + l) * k1 + a1];
+      }
       const float bv = a2 < k2 ? U[l * ldu + a2] : 0.f;
       acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
     }
@@ -213,7 +235,7 @@ __global__ __launch_bounds__(256) void k_pi_fin(PiBAArgs a, int nsplit) {
 bool fused_dft_ok(int n1, int n2, int k1, int k2) {
   return n1 <= kMaxN && n2 <= kMaxN && k1 <= kMaxK && k2 <= kMaxK && k1 >= 2 && k2 >= 2 &&
          (size_t)iota_lds(k1, k2, n2, false) * sizeof(float) <= 65536 &&
-         (size_t)pi_lds(k2, n2) * sizeof(float) <= 65536;
+         (size_t)pi_lds(k1, k2, n2, false) * sizeof(float) <= 65536;
 }
 
 int pi_ba_splits(int n1) { return ceil_div(n1, kRows); }
@@ -237,8 +259,12 @@ void pi_ba(const PiBAArgs& a, int nf, hipStream_t s) {
   if (!a.part) throw ArgError("pi_ba needs its partial-sum workspace");
   const int nsplit = pi_ba_splits(a.n1);
   dim3 g(nsplit, a.k0, nf);
-  const uint32_t sm = (uint32_t)pi_lds(a.k2, a.n2) * sizeof(float);
-  prof::launch("k_pi_ba", bytes, flops, k_pi_ba, g, dim3(256), sm, s, a);
+  const bool stage = (size_t)pi_lds(a.k1, a.k2, a.n2, true) * sizeof(float) <= 65536;
+  const uint32_t sm = (uint32_t)pi_lds(a.k1, a.k2, a.n2, stage) * sizeof(float);
+  if (stage)
+    prof::launch("k_pi_ba", bytes, flops, k_pi_ba<true>, g, dim3(256), sm, s, a);
+  else
+    prof::launch("k_pi_ba", bytes, flops, k_pi_ba<false>, g, dim3(256), sm, s, a);
   LDDMM_LAUNCH_CHECK();
   dim3 gf(ceil_div(a.k1 * a.k2, 256), a.k0, nf);
   prof::launch("k_pi_fin", 4.0 * nf * a.k0 * a.k1 * a.k2 * (nsplit + 2.0), 0.0, k_pi_fin, gf, dim3(256), 0, s, a,
