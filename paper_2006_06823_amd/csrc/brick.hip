@@ -153,15 +153,31 @@ __global__ __launch_bounds__(TL::NTHR) void k_brick(Epi epi, const float* __rest
 #pragma unroll 1
   for (int grp = 0; grp < Epi::GROUPS; ++grp) {
     __syncthreads();
-    for (int e = tid; e < VOL; e += NTHR) {
-      const int row = e / B2, b2 = e - row * B2;
-      const int off = rowoff[row] + colidx[b2];
-      if constexpr (GS == 2) {  // interleaved pair
-        reinterpret_cast<float2*>(br)[e] =
-            make_float2(coef[Epi::field(grp, 0) * g.P + off], coef[Epi::field(grp, 1) * g.P + off]);
-      } else {
+    {
+      // every load of the thread is issued before its first LDS store (one memory latency per brick)
+      constexpr int NIT = (VOL + NTHR - 1) / NTHR;
+      float v[NIT][GS];
 #pragma unroll
-        for (int k = 0; k < GS; ++k) br[k * VOL + e] = coef[Epi::field(grp, k) * g.P + off];
+      for (int it = 0; it < NIT; ++it) {
+        const int e = tid + it * NTHR;
+        if (e < VOL) {
+          const int row = e / B2, b2 = e - row * B2;
+          const int off = rowoff[row] + colidx[b2];
+#pragma unroll
+          for (int k = 0; k < GS; ++k) v[it][k] = coef[Epi::field(grp, k) * g.P + off];
+        }
+      }
+#pragma unroll
+      for (int it = 0; it < NIT; ++it) {
+        const int e = tid + it * NTHR;
+        if (e < VOL) {
+          if constexpr (GS == 2) {  // interleaved pair
+            reinterpret_cast<float2*>(br)[e] = make_float2(v[it][0], v[it][1]);
+          } else {
+#pragma unroll
+            for (int k = 0; k < GS; ++k) br[k * VOL + e] = v[it][k];
+          }
+        }
       }
     }
     __syncthreads();

@@ -10,6 +10,7 @@
 // vector FMA units.  Tiles of W and of the input are staged through LDS.
 #include "kernels.h"
 #include "prof.h"
+#include "stage.h"
 
 #include <algorithm>
 #include <type_traits>
@@ -172,12 +173,11 @@ __global__ __launch_bounds__(64 * WR * WM) void dft_right_kernel(const T* __rest
 template <int MB>
 __global__ __launch_bounds__(256) void dft_left_contract(const float* __restrict__ in, float* __restrict__ out,
                                                          FieldMats<float> mats, int bpf, int M, int L, int C,
-                                                         int64_t sIb, int64_t sOb, int separate_red, int stage_b) {
+                                                         int64_t sIb, int64_t sOb, int separate_red) {
   extern __shared__ float smem[];
   const int ldw = L + 1;
   float* Ws = smem;                                          // [32 MB][L + 1]
   float* red = separate_red ? smem + 32 * MB * ldw : smem;   // [4][MB][16][64]
-  float* Bt = smem + 32 * MB * ldw + 4 * MB * 1024;          // [L][33] column tile (stage_b)
   const int b = blockIdx.z;
   const float* __restrict__ W = mats.w[b / bpf];
   in += b * sIb;
@@ -192,23 +192,12 @@ __global__ __launch_bounds__(256) void dft_left_contract(const float* __restrict
   for (int cb = blockIdx.x; cb < ncb; cb += gridDim.x) {
     if (cb == blockIdx.x || !separate_red) {
       __syncthreads();
-      for (int e = tid; e < 32 * MB * L; e += 256) {
-        const int m = e / L, l = e - m * L;
-        Ws[m * ldw + l] = m < M ? W[(int64_t)m * L + l] : 0.f;
-      }
+      stage_tile<256, 16>(Ws, ldw, W, L, 32 * MB, L, M, L);
       __syncthreads();
     }
     const int c0 = cb * 32;
     const int c = c0 + (lane & 31);
     const bool cok = c < C;
-    if (stage_b) {
-      // the block's 32 input columns in one coalesced burst
-      for (int e = tid; e < L * 32; e += 256) {
-        const int l = e >> 5, j = e & 31;
-        Bt[l * 33 + j] = (c0 + j < C) ? in[(int64_t)l * C + c0 + j] : 0.f;
-      }
-      __syncthreads();
-    }
     f32x16 acc[MB];
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
@@ -217,8 +206,7 @@ __global__ __launch_bounds__(256) void dft_left_contract(const float* __restrict
 #pragma unroll 8
     for (int kk = lb; kk < le; kk += 2) {
       const int l = kk + kh;
-      float bv = 0.f;
-      if (l < le) bv = stage_b ? Bt[l * 33 + (lane & 31)] : (cok ? in[(int64_t)l * C + c] : 0.f);
+      const float bv = (cok && l < le) ? in[(int64_t)l * C + c] : 0.f;
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb) {
         const float av = l < le ? Ws[(mb * 32 + (lane & 31)) * ldw + l] : 0.f;
@@ -260,10 +248,7 @@ __global__ __launch_bounds__(256) void dft_left_expand(const float* __restrict__
   out += b * sOb;
   const int m0 = blockIdx.y * 128;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, li = lane & 31;
-  for (int e = tid; e < 128 * L; e += 256) {
-    const int mm = e / L, l = e - mm * L;
-    Ws[mm * ldw + l] = (m0 + mm) < M ? W[(int64_t)(m0 + mm) * L + l] : 0.f;
-  }
+  stage_tile<256, 16>(Ws, ldw, W + (int64_t)m0 * L, L, 128, L, M - m0, L);
   const int mw = m0 + wave * 32;
   const int kh = lane >> 5;
   const float* Wr = Ws + (wave * 32 + li) * ldw;
@@ -497,19 +482,18 @@ void dft_left(const T* in, T* out, const FieldMats<T>& W, int nb, int bpf, int M
   if constexpr (std::is_same_v<T, float>) {
     if (M <= 64 && L > 64 && L <= 192) {
       const int MB = M > 32 ? 2 : 1;
-      const size_t wsz = (size_t)32 * MB * (L + 1), rsz = (size_t)4 * MB * 16 * 64, bsz = (size_t)L * 33;
+      const size_t wsz = (size_t)32 * MB * (L + 1), rsz = (size_t)4 * MB * 16 * 64;
       const int sep = (wsz + rsz) * sizeof(float) <= 65536 ? 1 : 0;
-      const int stage_b = sep && (wsz + rsz + bsz) * sizeof(float) <= 65536 ? 1 : 0;
-      const uint32_t sm = (uint32_t)((sep ? wsz + rsz + (stage_b ? bsz : 0) : std::max(wsz, rsz)) * sizeof(float));
+      const uint32_t sm = (uint32_t)((sep ? wsz + rsz : std::max(wsz, rsz)) * sizeof(float));
       const int ncb = ceil_div(C, 32);
       const int gx = sep ? std::max(1, std::min(ncb, 1024 / std::max(1, nb))) : ncb;
       dim3 g(gx, 1, nb);
       if (MB == 2)
         prof::launch("dft_left_contract<2>", bytes, flops, dft_left_contract<2>, g, dim3(256), sm, s, in, out, W, bpf,
-                     M, L, C, sIb, sOb, sep, stage_b);
+                     M, L, C, sIb, sOb, sep);
       else
         prof::launch("dft_left_contract<1>", bytes, flops, dft_left_contract<1>, g, dim3(256), sm, s, in, out, W, bpf,
-                     M, L, C, sIb, sOb, sep, stage_b);
+                     M, L, C, sIb, sOb, sep);
       LDDMM_LAUNCH_CHECK();
       return;
     }

@@ -13,6 +13,7 @@
 // intermediate on chip.
 #include "kernels.h"
 #include "prof.h"
+#include "stage.h"
 
 namespace lddmm {
 
@@ -56,24 +57,32 @@ __global__ __launch_bounds__(256) void k_iota_ab(IotaABArgs a) {
   const int kh = lane >> 5, li = lane & 31;
   const float* __restrict__ W2t = a.w2t[f];  // [k2][n2]
   const float* __restrict__ W1t = a.w1t[f];  // [k1][n1]
-  // prologue: slab = x + alpha y, and the matrix operands, all with coalesced loads
+  // prologue: slab = x + alpha y, and the matrix operands, loads batched ahead of the stores
   {
     const int64_t off = (int64_t)a0 * k1 * k2;
     const float* x = a.x[f] + off;
     const float* y = a.y[f] ? a.y[f] + off : nullptr;
     const float al = a.alpha[f];
-    for (int e = tid; e < k1 * k2; e += 256) {
-      const int r = e / k2, c = e - r * k2;
-      float v = x[e];
-      if (y) v += al * y[e];
-      S[r * lds + c] = v;
+    constexpr int U = 8;
+    for (int base = 0; base < k1 * k2; base += 256 * U) {
+      float v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = base + u * 256 + tid;
+        v[u] = 0.f;
+        if (e < k1 * k2) v[u] = y ? x[e] + al * y[e] : x[e];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int e = base + u * 256 + tid;
+        if (e < k1 * k2) {
+          const int r = e / k2, c = e - r * k2;
+          S[r * lds + c] = v[u];
+        }
+      }
     }
-    for (int e = tid; e < k1 * kRows; e += 256) {
-      const int r = e / kRows, c = e - r * kRows;
-      W1s[e] = (x1b + c < n1) ? W1t[(int64_t)r * n1 + x1b + c] : 0.f;
-    }
-    if (STAGE_W2)
-      for (int e = tid; e < k2 * n2; e += 256) W2s[e] = W2t[e];
+    stage_tile<256, 8>(W1s, kRows, W1t + x1b, n1, k1, kRows, k1, n1 - x1b);
+    if (STAGE_W2) stage_tile<256, 16>(W2s, n2, W2t, n2, k2, n2, k2, n2);
   }
   __syncthreads();
   const float* W2 = STAGE_W2 ? W2s : W2t;
@@ -142,16 +151,11 @@ __global__ __launch_bounds__(256) void k_pi_ba(PiBAArgs a) {
   const int kh = lane >> 5, li = lane & 31;
   const int slab = f * k0 + a0;
   const float* __restrict__ in = a.in + (int64_t)slab * n1 * n2;
-  for (int e = tid; e < kRows * n2; e += 256) {
-    const int r = e / n2, c = e - r * n2;
-    In[r * ldi + c] = (x1b + r < n1) ? in[(int64_t)(x1b + r) * n2 + c] : 0.f;
-  }
+  const int vr = n1 - x1b < kRows ? n1 - x1b : kRows;
+  stage_tile<256, 16>(In, ldi, in + (int64_t)x1b * n2, n2, kRows, n2, vr, n2);
   if (STAGE_P) {
-    for (int e = tid; e < n2 * k2; e += 256) P2s[e] = a.p2t[e];
-    for (int e = tid; e < kRows * k1; e += 256) {
-      const int r = e / k1;
-      P1s[e] = (x1b + r < n1) ? a.p1t[(int64_t)x1b * k1 + e] : 0.f;
-    }
+    stage_tile<256, 16>(P2s, k2, a.p2t, k2, n2, k2, n2, k2);
+    stage_tile<256, 4>(P1s, k1, a.p1t + (int64_t)x1b * k1, k1, kRows, k1, vr, k1);
   }
   __syncthreads();
   const float* P2t = STAGE_P ? P2s : a.p2t;  // [n2][k2]

@@ -13,6 +13,7 @@
 // and writes 4 x F/4, instead of writing and re-reading e and the products.
 #include "kernels.h"
 #include "prof.h"
+#include "stage.h"
 
 namespace lddmm {
 
@@ -31,10 +32,7 @@ __global__ __launch_bounds__(256) void k_back_v1(BackV1Args a) {
   float* red = smem + n0 * ldb;  // [4 waves][MBO][16][64]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int kh = lane >> 5, li = lane & 31;
-  for (int e = tid; e < n0 * k0; e += 256) {
-    const int x0 = e / k0, a0 = e - x0 * k0;
-    B0s[x0 * ldb + a0] = a.B0[e];
-  }
+  stage_tile<256, 16>(B0s, ldb, a.B0, k0, n0, k0, n0, k0);
   __syncthreads();
   const int c0 = blockIdx.x * 32, c = c0 + li;
   const bool cok = c < C;
