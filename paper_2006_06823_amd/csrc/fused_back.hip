@@ -44,28 +44,50 @@ __global__ __launch_bounds__(256) void k_back_v1(BackV1Args a) {
     for (int m = 0; m < MBO; ++m)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[f][m][r] = 0.f;
+  // 32-bit element offsets (the grid stays below 2^31 nodes) keep one address register per load
   for (int mb = wave; mb < MB; mb += 4) {
+    // software pipeline: T2 and the first product field are requested before the expansion,
+    // each further field one product ahead of its use
+    float fcur[16], fnext[16];
+    auto load_field = [&](int f, float* dst) {
+      const float* __restrict__ F = f == 0 ? a.divv : a.G + (int64_t)(f - 1) * n0 * C;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int x0 = mb * 32 + acc_row(r, lane);
+        dst[r] = (cok && x0 < n0) ? F[x0 * C + c] : 0.f;
+      }
+    };
+    float tv[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int l = 2 * q + kh;
+      tv[q] = (cok && l < k0) ? a.t2[l * C + c] : 0.f;
+    }
+    load_field(0, fcur);
     // 1. e for rows x0 in [32 mb, 32 mb + 32)
     f32x16 ev;
 #pragma unroll
     for (int r = 0; r < 16; ++r) ev[r] = 0.f;
     const int xr = mb * 32 + li;
-    for (int kk = 0; kk < k0; kk += 2) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int l = 2 * q + kh;
+      const float av = (xr < n0 && l < k0) ? B0s[xr * ldb + l] : 0.f;
+      ev = __builtin_amdgcn_mfma_f32_32x32x2f32(av, tv[q], ev, 0, 0, 0);
+    }
+    for (int kk = 32; kk < k0; kk += 2) {  // k0 > 32 (second output tile)
       const int l = kk + kh;
       const float av = (xr < n0 && l < k0) ? B0s[xr * ldb + l] : 0.f;
-      const float bv = (cok && l < k0) ? a.t2[(int64_t)l * C + c] : 0.f;
+      const float bv = (cok && l < k0) ? a.t2[l * C + c] : 0.f;
       ev = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, ev, 0, 0, 0);
     }
     // 2-3. products and the axis-0 contraction
 #pragma unroll
     for (int f = 0; f < 4; ++f) {
-      const float* __restrict__ F = f == 0 ? a.divv : a.G + (int64_t)(f - 1) * n0 * C;
+      if (f < 3) load_field(f + 1, fnext);
       float p[16];
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int x0 = mb * 32 + acc_row(r, lane);
-        p[r] = (cok && x0 < n0) ? ev[r] * F[(int64_t)x0 * C + c] : 0.f;
-      }
+      for (int r = 0; r < 16; ++r) p[r] = ev[r] * fcur[r];
 #pragma unroll
       for (int m = 0; m < MBO; ++m) {
         const int a0 = m * 32 + li;
@@ -77,6 +99,10 @@ __global__ __launch_bounds__(256) void k_back_v1(BackV1Args a) {
             const float av = (x0 < n0 && a0 < k0) ? B0s[x0 * ldb + a0] : 0.f;
             acc[f][m] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, p[4 * q + i], acc[f][m], 0, 0, 0);
           }
+      }
+      if (f < 3) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) fcur[r] = fnext[r];
       }
     }
   }
