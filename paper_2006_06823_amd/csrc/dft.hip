@@ -177,7 +177,7 @@ __global__ __launch_bounds__(256) void dft_left_contract(const float* __restrict
   extern __shared__ float smem[];
   const int ldw = L + 1;
   float* Ws = smem;                                          // [32 MB][L + 1]
-  float* red = separate_red ? smem + 32 * MB * ldw : smem;   // [4][MB][16][64]
+  float* red = separate_red ? smem + 32 * MB * ldw : smem;   // [4][16][64]
   const int b = blockIdx.z;
   const float* __restrict__ W = mats.w[b / bpf];
   in += b * sIb;
@@ -213,19 +213,20 @@ __global__ __launch_bounds__(256) void dft_left_contract(const float* __restrict
         acc[mb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc[mb], 0, 0, 0);
       }
     }
-    __syncthreads();  // W reads done (aliased case) / previous reduction consumed
+    // reduce the waves' partial sums one 32-row tile at a time through a 16 KB buffer
 #pragma unroll
-    for (int mb = 0; mb < MB; ++mb)
+    for (int mb = 0; mb < MB; ++mb) {
+      __syncthreads();  // W reads done (aliased case) / previous reduction consumed
 #pragma unroll
-      for (int r = 0; r < 16; ++r) red[((wave * MB + mb) * 16 + r) * 64 + lane] = acc[mb][r];
-    __syncthreads();
-    for (int e = tid; e < MB * 16 * 64; e += 256) {
-      const int ln = e & 63, r = (e >> 6) & 15, mb = e >> 10;
-      float sum = 0.f;
-#pragma unroll
-      for (int w = 0; w < 4; ++w) sum += red[((w * MB + mb) * 16 + r) * 64 + ln];
-      const int m = mb * 32 + acc_row(r, ln), cc = c0 + (ln & 31);
-      if (m < M && cc < C) out[(int64_t)m * C + cc] = sum;
+      for (int r = 0; r < 16; ++r) red[(wave * 16 + r) * 64 + lane] = acc[mb][r];
+      __syncthreads();
+      for (int e = tid; e < 16 * 64; e += 256) {
+        const int ln = e & 63, r = e >> 6;
+        const float sum = red[r * 64 + ln] + red[(16 + r) * 64 + ln] + red[(32 + r) * 64 + ln] +
+                          red[(48 + r) * 64 + ln];
+        const int m = mb * 32 + acc_row(r, ln), cc = c0 + (ln & 31);
+        if (m < M && cc < C) out[(int64_t)m * C + cc] = sum;
+      }
     }
   }
 }
@@ -482,7 +483,7 @@ void dft_left(const T* in, T* out, const FieldMats<T>& W, int nb, int bpf, int M
   if constexpr (std::is_same_v<T, float>) {
     if (M <= 64 && L > 64 && L <= 192) {
       const int MB = M > 32 ? 2 : 1;
-      const size_t wsz = (size_t)32 * MB * (L + 1), rsz = (size_t)4 * MB * 16 * 64;
+      const size_t wsz = (size_t)32 * MB * (L + 1), rsz = (size_t)4 * 16 * 64;
       const int sep = (wsz + rsz) * sizeof(float) <= 65536 ? 1 : 0;
       const uint32_t sm = (uint32_t)((sep ? wsz + rsz : std::max(wsz, rsz)) * sizeof(float));
       const int ncb = ceil_div(C, 32);

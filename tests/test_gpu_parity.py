@@ -41,7 +41,15 @@ def make(variant, dim, N, K, Nt, precision, seed=0, cfl=0.8):
     return ctx, om, v
 
 
-@pytest.mark.parametrize("dim,N,K,Nt,precision", CASES)
+# first-axis shapes of every DFT kernel path: expansion (K0 <= 64), contraction with one and two
+# 32-row output tiles (64 < N0 <= 192, K0 <= 32 / K0 > 32), ragged tails on every axis
+DFT_CASES = CASES + [
+    (3, (80, 36, 44), (40, 12, 14), 4, L.FP32),
+    (3, (100, 20, 70), (24, 12, 30), 4, L.FP32),
+]
+
+
+@pytest.mark.parametrize("dim,N,K,Nt,precision", DFT_CASES)
 def test_truncated_dft_parity(dim, N, K, Nt, precision):
     ctx = L.Context(L.Problem(N, K, nt=Nt, precision=precision))
     rng = np.random.default_rng(5)
