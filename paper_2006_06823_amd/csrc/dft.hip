@@ -170,7 +170,7 @@ __global__ __launch_bounds__(64 * WR * WM) void dft_right_kernel(const T* __rest
 //
 // contract mode (M <= 64, L large): the four waves of a block share 32 columns and
 // split the contraction range; partial 32x32 blocks are summed through LDS.
-template <int MB>
+template <int MB, int NCT>
 __global__ __launch_bounds__(256) void dft_left_contract(const float* __restrict__ in, float* __restrict__ out,
                                                          FieldMats<float> mats, int bpf, int M, int L, int C,
                                                          int64_t sIb, int64_t sOb, int separate_red) {
@@ -187,7 +187,7 @@ __global__ __launch_bounds__(256) void dft_left_contract(const float* __restrict
   const int seg = ((L + 7) / 8) * 2;
   const int lb = wave * seg, le = min(L, lb + seg);
   const int kh = lane >> 5;
-  const int ncb = (C + 31) / 32;
+  const int ncb = (C + 32 * NCT - 1) / (32 * NCT);
   // without a separate reduction buffer the W tile is reloaded per column block
   for (int cb = blockIdx.x; cb < ncb; cb += gridDim.x) {
     if (cb == blockIdx.x || !separate_red) {
@@ -195,39 +195,48 @@ __global__ __launch_bounds__(256) void dft_left_contract(const float* __restrict
       stage_tile<256, 16>(Ws, ldw, W, L, 32 * MB, L, M, L);
       __syncthreads();
     }
-    const int c0 = cb * 32;
-    const int c = c0 + (lane & 31);
-    const bool cok = c < C;
-    f32x16 acc[MB];
+    const int c0 = cb * 32 * NCT;
+    f32x16 acc[MB][NCT];
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) acc[mb][r] = 0.f;
-#pragma unroll 8
+      for (int t = 0; t < NCT; ++t)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) acc[mb][t][r] = 0.f;
+#pragma unroll 4
     for (int kk = lb; kk < le; kk += 2) {
       const int l = kk + kh;
-      const float bv = (cok && l < le) ? in[(int64_t)l * C + c] : 0.f;
+      float bv[NCT];
+#pragma unroll
+      for (int t = 0; t < NCT; ++t) {
+        const int c = c0 + t * 32 + (lane & 31);
+        bv[t] = (c < C && l < le) ? in[(int64_t)l * C + c] : 0.f;
+      }
 #pragma unroll
       for (int mb = 0; mb < MB; ++mb) {
         const float av = l < le ? Ws[(mb * 32 + (lane & 31)) * ldw + l] : 0.f;
-        acc[mb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc[mb], 0, 0, 0);
+#pragma unroll
+        for (int t = 0; t < NCT; ++t)
+          acc[mb][t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv[t], acc[mb][t], 0, 0, 0);
       }
     }
-    // reduce the waves' partial sums one 32-row tile at a time through a 16 KB buffer
+    // reduce the waves' partial sums one 32 x 32 tile at a time through a 16 KB buffer
 #pragma unroll
-    for (int mb = 0; mb < MB; ++mb) {
-      __syncthreads();  // W reads done (aliased case) / previous reduction consumed
+    for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) red[(wave * 16 + r) * 64 + lane] = acc[mb][r];
-      __syncthreads();
-      for (int e = tid; e < 16 * 64; e += 256) {
-        const int ln = e & 63, r = e >> 6;
-        const float sum = red[r * 64 + ln] + red[(16 + r) * 64 + ln] + red[(32 + r) * 64 + ln] +
-                          red[(48 + r) * 64 + ln];
-        const int m = mb * 32 + acc_row(r, ln), cc = c0 + (ln & 31);
-        if (m < M && cc < C) out[(int64_t)m * C + cc] = sum;
+      for (int t = 0; t < NCT; ++t) {
+        __syncthreads();  // W reads done (aliased case) / previous reduction consumed
+#pragma unroll
+        for (int r = 0; r < 16; ++r) red[(wave * 16 + r) * 64 + lane] = acc[mb][t][r];
+        __syncthreads();
+        for (int e = tid; e < 16 * 64; e += 256) {
+          const int ln = e & 63, r = e >> 6;
+          const float sum = red[r * 64 + ln] + red[(16 + r) * 64 + ln] + red[(32 + r) * 64 + ln] +
+                            red[(48 + r) * 64 + ln];
+          const int m = mb * 32 + acc_row(r, ln), cc = c0 + t * 32 + (ln & 31);
+          if (m < M && cc < C) out[(int64_t)m * C + cc] = sum;
+        }
       }
-    }
   }
 }
 
@@ -486,15 +495,15 @@ void dft_left(const T* in, T* out, const FieldMats<T>& W, int nb, int bpf, int M
       const size_t wsz = (size_t)32 * MB * (L + 1), rsz = (size_t)4 * 16 * 64;
       const int sep = (wsz + rsz) * sizeof(float) <= 65536 ? 1 : 0;
       const uint32_t sm = (uint32_t)((sep ? wsz + rsz : std::max(wsz, rsz)) * sizeof(float));
-      const int ncb = ceil_div(C, 32);
+      const int ncb = ceil_div(C, 64);
       const int gx = sep ? std::max(1, std::min(ncb, 1024 / std::max(1, nb))) : ncb;
       dim3 g(gx, 1, nb);
       if (MB == 2)
-        prof::launch("dft_left_contract<2>", bytes, flops, dft_left_contract<2>, g, dim3(256), sm, s, in, out, W, bpf,
-                     M, L, C, sIb, sOb, sep);
+        prof::launch("dft_left_contract<2>", bytes, flops, dft_left_contract<2, 2>, g, dim3(256), sm, s, in, out, W,
+                     bpf, M, L, C, sIb, sOb, sep);
       else
-        prof::launch("dft_left_contract<1>", bytes, flops, dft_left_contract<1>, g, dim3(256), sm, s, in, out, W, bpf,
-                     M, L, C, sIb, sOb, sep);
+        prof::launch("dft_left_contract<1>", bytes, flops, dft_left_contract<1, 2>, g, dim3(256), sm, s, in, out, W,
+                     bpf, M, L, C, sIb, sOb, sep);
       LDDMM_LAUNCH_CHECK();
       return;
     }
