@@ -137,10 +137,12 @@ def main():
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
+        # measured HBM bytes of the dominant kernel over its algorithmic bytes (rocprofv3 FETCH_SIZE /
+        # WRITE_SIZE, scaled by a plain copy of known size), applied to this run's launch mix
         try:
             tr = json.load(open(TRAFFIC_FILE))
             if tr.get("kernel") == dom_name and tr.get("workload") == list(N) + list(K):
-                traffic = tr.get("bytes_per_launch")
+                traffic = round(tr["traffic_over_algorithmic"] * bytes_per_launch)
         except Exception:
             traffic = None
     roofline = {
