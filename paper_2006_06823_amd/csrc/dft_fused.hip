@@ -234,129 +234,6 @@ __global__ __launch_bounds__(256) void k_pi_fin(PiBAArgs a, int nsplit) {
   *dst = be == 0.f ? al * sum : be * *dst + al * sum;
 }
 
-// grid (ceil(C / 64), ceil(n0 / 128), nf): 128 rows of x0 x 64 band columns per block, each wave
-// one 32-row block and both 32-column halves; the combination x + alpha y is formed while staging
-__global__ __launch_bounds__(256) void k_band_exp0(BandExp0Args a) {
-  extern __shared__ float smem[];
-  const int f = blockIdx.z, m0 = blockIdx.y * 128, c0 = blockIdx.x * 64;
-  const int n0 = a.n0, k0 = a.k0, C = a.C;
-  const int ldw = k0 + 1, ldb = 68;
-  float* Ws = smem;              // [128][k0 + 1]
-  float* Bs = smem + 128 * ldw;  // [k0][68]
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int kh = lane >> 5, li = lane & 31;
-  stage_tile<256, 16>(Ws, ldw, a.w0[f] + (int64_t)m0 * k0, k0, 128, k0, n0 - m0, k0);
-  {
-    const float* x = a.x[f];
-    const float* y = a.y[f];
-    const float al = a.alpha[f];
-    constexpr int U = 8;
-    for (int base = 0; base < k0 * 64; base += 256 * U) {
-      float v[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int e = base + u * 256 + tid;
-        const int l = e >> 6, c = c0 + (e & 63);
-        v[u] = 0.f;
-        if (e < k0 * 64 && c < C) v[u] = y ? x[l * C + c] + al * y[l * C + c] : x[l * C + c];
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int e = base + u * 256 + tid;
-        if (e < k0 * 64) Bs[(e >> 6) * ldb + (e & 63)] = v[u];
-      }
-    }
-  }
-  __syncthreads();
-  const int mw = m0 + wave * 32;
-  if (mw >= n0) return;
-  f32x16 acc0, acc1;
-  zero16(acc0);
-  zero16(acc1);
-  const float* Wr = Ws + (wave * 32 + li) * ldw;
-  for (int kk = 0; kk < k0; kk += 2) {
-    const int l = kk + kh;
-    const bool ok = l < k0;
-    const float av = ok ? Wr[l] : 0.f;
-    const float b0 = ok ? Bs[l * ldb + li] : 0.f;
-    const float b1 = ok ? Bs[l * ldb + 32 + li] : 0.f;
-    acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(av, b0, acc0, 0, 0, 0);
-    acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(av, b1, acc1, 0, 0, 0);
-  }
-  float* out = a.out + (int64_t)f * n0 * C;
-  const int c = c0 + li;
-#pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int m = mw + acc_row(r, lane);
-    if (m < n0) {
-      if (c < C) out[(int64_t)m * C + c] = acc0[r];
-      if (c + 32 < C) out[(int64_t)m * C + c + 32] = acc1[r];
-    }
-  }
-}
-
-// grid (ceil(C / 64), 1, nf): 64 band rows (a0) x 64 columns per block, wave w owns row tile w / 2 and
-// column tile w % 2; the contraction over x0 runs in 64-row chunks staged in LDS, the split partials
-// summed in split order while staging
-__global__ __launch_bounds__(256) void k_pi_fin0(PiFin0Args a) {
-  __shared__ float As[64 * 65];  // [a0][x0 chunk]
-  __shared__ float Bs[64 * 68];  // [x0 chunk][c]
-  const int f = blockIdx.z, c0 = blockIdx.x * 64;
-  const int n0 = a.n0, k0 = a.k0, C = a.C, ns = a.nsplit;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int kh = lane >> 5, li = lane & 31;
-  const int rt = wave >> 1, ct = wave & 1;
-  const float* part = a.part + (int64_t)f * n0 * ns * C;
-  f32x16 acc;
-  zero16(acc);
-  for (int xc = 0; xc < n0; xc += 64) {
-    __syncthreads();
-    stage_tile<256, 16>(As, 65, a.p0 + xc, n0, 64, 64, k0, n0 - xc);
-    {
-      constexpr int U = 16;
-      float v[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int e = u * 256 + tid;  // 64 x 64 = 4096 = 16 x 256
-        const int x = e >> 6, c = c0 + (e & 63);
-        float sum = 0.f;
-        if (xc + x < n0 && c < C) {
-          const float* p = part + ((int64_t)(xc + x) * ns) * C + c;
-          for (int q = 0; q < ns; ++q) sum += p[(int64_t)q * C];
-        }
-        v[u] = sum;
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int e = u * 256 + tid;
-        Bs[(e >> 6) * 68 + (e & 63)] = v[u];
-      }
-    }
-    __syncthreads();
-    if (rt * 32 < k0) {
-      for (int kk = 0; kk < 64; kk += 2) {
-        const int l = kk + kh;
-        const float av = As[(rt * 32 + li) * 65 + l];
-        const float bv = Bs[l * 68 + ct * 32 + li];
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
-      }
-    }
-  }
-  if (rt * 32 >= k0) return;
-  const int c = c0 + ct * 32 + li;
-  if (c >= C) return;
-  float* dst = a.out[f];
-  const float al = a.alpha[f], be = a.beta[f];
-#pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int a0 = rt * 32 + acc_row(r, lane);
-    if (a0 < k0) {
-      float* d = dst + (int64_t)a0 * C + c;
-      *d = be == 0.f ? al * acc[r] : be * *d + al * acc[r];
-    }
-  }
-}
-
 }  // namespace
 
 bool fused_dft_ok(int n1, int n2, int k1, int k2) {
@@ -380,7 +257,7 @@ void iota_ab(const IotaABArgs& a, int nf, hipStream_t s) {
   LDDMM_LAUNCH_CHECK();
 }
 
-void pi_ba(const PiBAArgs& a, int nf, hipStream_t s, bool finish) {
+void pi_ba(const PiBAArgs& a, int nf, hipStream_t s) {
   const double bytes = 4.0 * nf * ((double)a.k0 * a.n1 * a.n2 + (double)a.k0 * a.k1 * a.k2);
   const double flops = 2.0 * nf * a.k0 * ((double)a.k2 * a.n1 * a.n2 + (double)a.k1 * a.n1 * a.k2);
   if (!a.part) throw ArgError("pi_ba needs its partial-sum workspace");
@@ -393,29 +270,9 @@ void pi_ba(const PiBAArgs& a, int nf, hipStream_t s, bool finish) {
   else
     prof::launch("k_pi_ba", bytes, flops, k_pi_ba<false>, g, dim3(256), sm, s, a);
   LDDMM_LAUNCH_CHECK();
-  if (!finish) return;
   dim3 gf(ceil_div(a.k1 * a.k2, 256), a.k0, nf);
   prof::launch("k_pi_fin", 4.0 * nf * a.k0 * a.k1 * a.k2 * (nsplit + 2.0), 0.0, k_pi_fin, gf, dim3(256), 0, s, a,
                nsplit);
-  LDDMM_LAUNCH_CHECK();
-}
-
-void band_exp0(const BandExp0Args& a, int nf, hipStream_t s) {
-  if (a.k0 > 64 || a.k0 < 1) throw ArgError("band_exp0: k0 must be 1..64");
-  const double bytes = 4.0 * nf * ((double)a.k0 * a.C * (a.y[0] ? 2.0 : 1.0) + (double)a.n0 * a.C);
-  const double flops = 2.0 * nf * (double)a.n0 * a.k0 * a.C;
-  dim3 g(ceil_div(a.C, 64), ceil_div(a.n0, 128), nf);
-  const uint32_t sm = (uint32_t)(128 * (a.k0 + 1) + a.k0 * 68) * sizeof(float);
-  prof::launch("k_band_exp0", bytes, flops, k_band_exp0, g, dim3(256), sm, s, a);
-  LDDMM_LAUNCH_CHECK();
-}
-
-void pi_fin0(const PiFin0Args& a, int nf, hipStream_t s) {
-  if (a.k0 > 64 || a.k0 < 1) throw ArgError("pi_fin0: k0 must be 1..64");
-  const double bytes = 4.0 * nf * ((double)a.n0 * a.nsplit * a.C + 2.0 * a.k0 * a.C);
-  const double flops = 2.0 * nf * (double)a.k0 * a.n0 * a.C;
-  dim3 g(ceil_div(a.C, 64), 1, nf);
-  prof::launch("k_pi_fin0", bytes, flops, k_pi_fin0, g, dim3(256), 0, s, a);
   LDDMM_LAUNCH_CHECK();
 }
 

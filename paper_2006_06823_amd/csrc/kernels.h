@@ -43,30 +43,7 @@ struct PiBAArgs {
 bool fused_dft_ok(int n1, int n2, int k1, int k2);
 int pi_ba_splits(int n1);
 void iota_ab(const IotaABArgs& a, int nf, hipStream_t s);
-// finish = false leaves the per-split partials in a.part for pi_fin0
-void pi_ba(const PiBAArgs& a, int nf, hipStream_t s, bool finish = true);
-// first-axis expansion on the band: out[f][x0][c] = sum_a0 W0_f[x0][a0] (x_f + alpha_f y_f)[a0][c],
-// c over the C = K1 K2 columns of a band array (k0 <= 64)
-struct BandExp0Args {
-  const float* x[kMaxFields];
-  const float* y[kMaxFields];  // optional
-  float alpha[kMaxFields];
-  const float* w0[kMaxFields];  // [n0][k0]
-  float* out;                   // [nf][n0][C]
-  int n0, k0, C;
-};
-void band_exp0(const BandExp0Args& a, int nf, hipStream_t s);
-// first-axis projection of the split partials left by pi_ba over n0 slabs:
-// out_f[a0][c] = beta_f out_f + alpha_f sum_x0 P0[a0][x0] sum_q part[f][x0][q][c]
-struct PiFin0Args {
-  const float* part;  // [nf][n0][nsplit][C]
-  const float* p0;    // [k0][n0]
-  float* out[kMaxFields];
-  float alpha[kMaxFields];
-  float beta[kMaxFields];
-  int n0, k0, C, nsplit;
-};
-void pi_fin0(const PiFin0Args& a, int nf, hipStream_t s);
+void pi_ba(const PiBAArgs& a, int nf, hipStream_t s);
 
 // fused image-transport backward grid pass (fused_back.hip), float
 struct BackV1Args {

@@ -283,11 +283,9 @@ class Solver final : public SolverBase {
     }
     work_.alloc(reduce_work_size());
     if (std::is_same<T, float>::value && d_.n[0] > 0) {
-      // partial projections of the split fused projection (over K0 or N0 slabs) and the
-      // band-side first-axis expansions
-      const int64_t slabs = (int64_t)kMaxFields * std::max(d_.k[0], d_.n[0]);
+      // partial projections of the split fused projection
+      const int64_t slabs = (int64_t)kMaxFields * d_.k[0];
       pipart_.alloc(slabs * pi_ba_splits(d_.n[1]) * d_.k[1] * d_.k[2]);
-      bexp_.alloc((int64_t)kMaxFields * d_.n[0] * d_.k[1] * d_.k[2]);
     }
     double* hp = nullptr;
     LDDMM_HIP(hipHostMalloc(reinterpret_cast<void**>(&hp), 8 * sizeof(double), hipHostMallocDefault));
@@ -401,33 +399,6 @@ class Solver final : public SolverBase {
     const int n0 = d_.n[0], n1 = d_.n[1], n2 = d_.n[2], k0 = d_.k[0], k1 = d_.k[1], k2 = d_.k[2];
     const bool skip0 = (n0 == 1 && k0 == 1);
     if constexpr (std::is_same_v<T, float>) {
-      if (!skip0 && !bf16_ && k0 <= 64 && fused_dft_ok(n1, n2, k1, k2)) {
-        // first axis on the band (small), then the fused inner axes over the N0 slabs: each grid
-        // field is written once and the fused kernel runs on N0 instead of K0 slabs
-        const int C = k1 * k2;
-        BandExp0Args e{};
-        for (int f = 0; f < nf; ++f) {
-          e.x[f] = xs[f];
-          e.y[f] = ys ? ys[f] : nullptr;
-          e.alpha[f] = al ? al[f] : 0.f;
-          e.w0[f] = mat(0, kinds[f][0]);
-        }
-        e.out = bexp_.get();
-        e.n0 = n0, e.k0 = k0, e.C = C;
-        band_exp0(e, nf, st_);
-        IotaABArgs a{};
-        for (int f = 0; f < nf; ++f) {
-          a.x[f] = bexp_.get() + (int64_t)f * n0 * C;
-          a.y[f] = nullptr;
-          a.alpha[f] = 0.f;
-          a.w1t[f] = mat(1, kinds[f][1] + kPlainT);
-          a.w2t[f] = mat(2, kinds[f][2] + kPlainT);
-        }
-        a.out = out;
-        a.k0 = n0, a.k1 = k1, a.k2 = k2, a.n1 = n1, a.n2 = n2;
-        iota_ab(a, nf, st_);
-        return;
-      }
       if (fused_dft_ok(n1, n2, k1, k2)) {
         IotaABArgs a{};
         for (int f = 0; f < nf; ++f) {
@@ -468,28 +439,6 @@ class Solver final : public SolverBase {
   void pi_acc(const T* grid, int nf, T* const* dst, const T* alpha, const T* beta) {
     const int n0 = d_.n[0], n1 = d_.n[1], n2 = d_.n[2], k0 = d_.k[0], k1 = d_.k[1], k2 = d_.k[2];
     if constexpr (std::is_same_v<T, float>) {
-      if (!(n0 == 1 && k0 == 1) && !bf16_ && k0 <= 64 && fused_dft_ok(n1, n2, k1, k2)) {
-        // fused inner axes over the N0 slabs straight from the grid (each grid field read once),
-        // then the first axis on the small partial band arrays
-        PiBAArgs b{};
-        b.in = grid;
-        b.p1t = mat(1, kProjT);
-        b.p2t = mat(2, kProjT);
-        b.part = pipart_.get();
-        b.k0 = n0, b.k1 = k1, b.k2 = k2, b.n1 = n1, b.n2 = n2;
-        pi_ba(b, nf, st_, false);
-        PiFin0Args c{};
-        c.part = pipart_.get();
-        c.p0 = mat(0, kProj);
-        for (int f = 0; f < nf; ++f) {
-          c.out[f] = dst[f];
-          c.alpha[f] = alpha[f];
-          c.beta[f] = beta[f];
-        }
-        c.n0 = n0, c.k0 = k0, c.C = k1 * k2, c.nsplit = pi_ba_splits(n1);
-        pi_fin0(c, nf, st_);
-        return;
-      }
       if (fused_dft_ok(n1, n2, k1, k2)) {
         const T* srcB = grid;
         if (!(n0 == 1 && k0 == 1)) {
@@ -884,7 +833,7 @@ class Solver final : public SolverBase {
   DevBuf<T> inc_, incadj_;
   DevBuf<T> G_, m_, lam0_;               // image transport
   DevBuf<T> ubl_, Du_, m1_, g1_, rho_;   // deformation state
-  DevBuf<float> pipart_, bexp_;
+  DevBuf<float> pipart_;
 
  public:
   // accessors used by the Gauss-Newton driver
