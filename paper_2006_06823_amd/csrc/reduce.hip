@@ -17,8 +17,9 @@ enum class Op { Sum, Max, Min };
 template <Op op>
 __device__ __forceinline__ double combine(double a, double b) {
   if constexpr (op == Op::Sum) return a + b;
-  if constexpr (op == Op::Max) return a > b ? a : b;
-  return a < b ? a : b;
+  // NaN-propagating: a NaN operand wins, so a non-finite input shows in max / min
+  if constexpr (op == Op::Max) return (a > b || a != a) ? a : b;
+  return (a < b || a != a) ? a : b;
 }
 
 template <Op op>

@@ -563,6 +563,10 @@ class Solver final : public SolverBase {
   // ---------------------------------------------- per-velocity set-up (Section 3.1)
   void setup_velocity() {
     const int64_t Q = d_.Q, P = d_.P;
+    // a non-finite coefficient would turn into non-finite departure points; reject it before any
+    // interpolation runs
+    if (!std::isfinite(maxabs<T>(vbl_.get(), 3 * Q, work_.get(), host_.get(), st_)))
+      throw NonFiniteError("velocity has non-finite coefficients");
     // velocity samples and the B-spline coefficients of the velocity in one 6-field transform
     copy(stk_.get(), vbl_.get(), 3 * Q);
     copy(stk_.get() + 3 * Q, vbl_.get(), 3 * Q);

@@ -1,0 +1,131 @@
+"""Error behaviour of the C ABI (status codes of include/lddmm_bl.h), on a GPU.
+
+Every rejected call is rejected on the host before a kernel sees the bad argument; a non-finite
+velocity is caught by a device reduction before any interpolation runs.  After an error the
+context stays usable.
+"""
+import ctypes
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2006_06823_amd import lddmm_bl as L
+
+pytestmark = pytest.mark.gpu
+
+E_ARG, E_NONFINITE, E_STATE = -1, -4, -5
+
+
+def _create(**kw):
+    lib = L.load_library()
+    p = L.make_params(L.Problem((24, 20, 28), (8, 8, 8), nt=4))
+    for k, v in kw.items():
+        if k in ("n", "k"):
+            for j in range(3):
+                getattr(p, k)[j] = v[j]
+        else:
+            setattr(p, k, v)
+    h = ctypes.c_void_p()
+    st = lib.lddmm_bl_create(ctypes.byref(p), None, ctypes.byref(h))
+    if st == 0:
+        lib.lddmm_bl_destroy(h)
+    return st
+
+
+@pytest.mark.parametrize("bad", [
+    dict(dim=4), dict(nt=0), dict(variant=2), dict(alpha=0.0), dict(s=0), dict(sigma2=-1.0),
+    dict(k=(7, 8, 8)), dict(n=(20, 20, 28), k=(16, 8, 8)), dict(k=(0, 8, 8)), dict(precision=7),
+])
+def test_invalid_parameters_rejected(bad):
+    assert _create(**bad) == E_ARG
+
+
+def test_valid_parameters_accepted():
+    assert _create() == 0
+
+
+def _ctx(variant=1):
+    N, K = (24, 20, 28), (8, 8, 8)
+    ctx = L.Context(L.Problem(N, K, nt=4, variant=variant))
+    rng = np.random.default_rng(0)
+    I0 = torch.tensor(rng.random(N), dtype=torch.float32, device="cuda")
+    I1 = torch.tensor(rng.random(N), dtype=torch.float32, device="cuda")
+    ctx.set_images(I0, I1)
+    return ctx, N, K
+
+
+@pytest.mark.parametrize("variant", [1, 3])
+def test_state_errors_and_recovery(variant):
+    ctx, N, K = _ctx(variant)
+    with pytest.raises(L.LddmmError) as e:
+        ctx.adjoint_solve()
+    assert e.value.status == E_STATE
+    dv = torch.zeros((3,) + K, dtype=torch.float32, device="cuda")
+    with pytest.raises(L.LddmmError) as e:
+        ctx.hess_matvec(dv)
+    assert e.value.status == E_STATE
+    v = torch.zeros((3,) + K, dtype=torch.float32, device="cuda")
+    v[1, 2, 3, 4] = float("nan")
+    with pytest.raises(L.LddmmError) as e:
+        ctx.state_solve(v)
+    assert e.value.status == E_NONFINITE
+    v[1, 2, 3, 4] = float("inf")
+    with pytest.raises(L.LddmmError) as e:
+        ctx.state_solve(v)
+    assert e.value.status == E_NONFINITE
+    # a failed state solve leaves no state behind
+    with pytest.raises(L.LddmmError) as e:
+        ctx.hess_matvec(dv)
+    assert e.value.status == E_STATE
+    # the context still works
+    v.zero_()
+    E, _ = ctx.state_solve(v)
+    assert all(math.isfinite(x) for x in E)
+    g, ginf = ctx.adjoint_solve()
+    assert math.isfinite(ginf) and torch.isfinite(g).all()
+
+
+def test_argument_errors():
+    ctx, N, K = _ctx()
+    ctx.state_solve(torch.zeros((3,) + K, dtype=torch.float32, device="cuda"))
+    with pytest.raises(L.LddmmError) as e:
+        ctx.get_field(L.FIELD_STATE, 99)
+    assert e.value.status == E_ARG
+    with pytest.raises(L.LddmmError) as e:
+        ctx.get_field(42, 0)
+    assert e.value.status == E_ARG
+    with pytest.raises(L.LddmmError) as e:
+        ctx.project(torch.zeros((13,) + N, dtype=torch.float32, device="cuda"), 13)
+    assert e.value.status == E_ARG
+    v = torch.zeros((3,) + K, dtype=torch.float32, device="cuda")
+    st = ctx.lib.lddmm_bl_gn_solve(ctx.h, ctypes.byref(L.GNOpts(1, 0, 1e-3, 0.0, 0, 0.0)), L._ptr(v), None, 0, None)
+    assert st == E_ARG
+    Z = torch.zeros((17, 3) + K, dtype=torch.float32, device="cuda")
+    st = ctx.lib.lddmm_bl_gn_solve(ctx.h, ctypes.byref(L.GNOpts(1, 1, 1e-3, 0.0, 0, 0.0)), L._ptr(v), L._ptr(Z), 17,
+                                   None)
+    assert st == E_ARG
+    # null pointers
+    assert ctx.lib.lddmm_bl_state_solve(ctx.h, None, None, None) == E_ARG
+    assert ctx.lib.lddmm_bl_state_solve(None, L._ptr(v), None, None) == E_ARG
+
+
+def test_network_argument_errors():
+    lib = L.load_library()
+    h = ctypes.c_void_p()
+    ch = (ctypes.c_int32 * 2)(4, 8)
+    assert lib.lddmm_nn_create(0, ch, 16, 3, 0, None, ctypes.byref(h)) == E_ARG
+    assert lib.lddmm_nn_create(2, ch, 2, 3, 0, None, ctypes.byref(h)) == E_ARG
+    net = L.WarmStartNet(channels=(4, 8), in_size=16, device="cuda:0")
+    out = torch.zeros(net.out_shape(1), dtype=torch.float32, device="cuda")
+    with pytest.raises(L.LddmmError) as e:
+        net.velocity(out, (4, 4, 4))  # band smaller than the predicted block
+    assert e.value.status == E_ARG
+    with pytest.raises(L.LddmmError) as e:
+        net.backward(out)  # no forward pass yet
+    assert e.value.status == E_STATE
+    I = torch.zeros((30, 32, 32), dtype=torch.float32, device="cuda")
+    with pytest.raises(L.LddmmError) as e:
+        net.pool_pair(I, I, torch.zeros((2, 16, 16, 16), dtype=torch.float32, device="cuda"))
+    assert e.value.status == E_ARG

@@ -59,3 +59,27 @@ def test_variant3_c3_size_zero_velocity_closed_forms():
     xg = sp.include(torch.tensor(x), N)
     h_ref = sp.apply_L(torch.tensor(x), 3, 0.0025, 2) + 2.0 * sp.project(g1 * (g1 * xg).sum(0), K)
     assert rel_l2(h, h_ref) <= 1e-5
+
+
+@pytest.mark.parametrize("variant", [1, 3])
+def test_c3_size_constant_velocity_exact_shift(variant):
+    """A constant velocity transports the image by an exact shift (Section 3.1: the characteristic of a
+    constant field is x - dt v).  With a shift of whole voxels per step every interpolation hits grid
+    nodes, where the cubic B-spline reproduces the samples, so m(1) = I0 rolled by the total shift; the
+    data term follows in closed form.  Checked at the deformation-state benchmark size for both variants."""
+    N, K, Nt = (160, 192, 160), (40, 48, 40), 10
+    I0, I1 = syn.phantom_pair_3d(N, seed=2, max_disp_vox=8.0)
+    ctx = L.Context(L.Problem(N, K, nt=Nt, variant=variant, precision=L.FP32))
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda")
+    ctx.set_images(t(I0), t(I1))
+    shift = (10, -20, 30)  # voxels per unit time: (1, -2, 3) voxels per step
+    v = np.zeros((3,) + K)
+    for j in range(3):
+        v[j, 0, 0, 0] = shift[j] / N[j]  # slot 0 holds the constant function 1
+    E, m1 = ctx.state_solve(t(v), want_m1=True)
+    ref = np.roll(I0.astype(np.float64), shift, axis=(0, 1, 2))
+    assert rel_l2(m1, torch.tensor(ref)) <= 1e-5
+    data = float(((ref - I1.astype(np.float64)) ** 2).mean())
+    assert abs(E[2] - data) <= 1e-5 * data
+    reg = 0.5 * sum(float(v[j, 0, 0, 0]) ** 2 for j in range(3))  # L~ = 1 on the constant slot
+    assert abs(E[1] - reg) <= 1e-6 * reg
