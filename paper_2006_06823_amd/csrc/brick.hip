@@ -34,7 +34,11 @@ using TileA = Tile<4, 8, 32, 256>;
 using TileB = Tile<8, 8, 32, 512>;
 using TileC = Tile<2, 16, 32, 256>;
 using TileD = Tile<4, 4, 64, 256>;
-constexpr int kTiles = 4;
+// 1024-thread tiles for the 160 KB LDS of a gfx950 workgroup: a 16 x 8 x 32 tile re-reads 2.1x its
+// coefficient volume through the halo instead of 2.5x (8 x 8 x 32), and two workgroups fill a CU
+using TileE = Tile<16, 8, 32, 1024>;
+using TileF = Tile<8, 16, 32, 1024>;
+constexpr int kTiles = 6;
 
 struct Grid3 {
   int n0, n1, n2;
@@ -390,6 +394,8 @@ void launch(const std::string& name, double bytes, const Epi& epi, const float* 
             hipStream_t s, int tile = -1) {
   const Grid3 g{d.n[0], d.n[1], d.n[2], d.P};
   if (tile < 0) tile = tune::get(shape_key(d), 0);
+  // epilogues with more than three fields would spill at 1024 threads: they keep the 512-thread tile
+  if (tile >= 4 && Epi::NF > 3) tile = 1;
   switch (tile) {
     case 1:
       launch_tile<Epi, TileB>(name, bytes, epi, coef, g, s);
@@ -399,6 +405,12 @@ void launch(const std::string& name, double bytes, const Epi& epi, const float* 
       break;
     case 3:
       launch_tile<Epi, TileD>(name, bytes, epi, coef, g, s);
+      break;
+    case 4:
+      launch_tile<Epi, TileE>(name, bytes, epi, coef, g, s);
+      break;
+    case 5:
+      launch_tile<Epi, TileF>(name, bytes, epi, coef, g, s);
       break;
     default:
       launch_tile<Epi, TileA>(name, bytes, epi, coef, g, s);
@@ -415,9 +427,15 @@ bool brick_ok(const Dims& d) { return d.n[0] > 1; }
 void brick_autotune(float* out, const float* coef, const float* disp, const Dims& d, hipStream_t s) {
   const std::string key = shape_key(d);
   if (tune::get(key, -1) >= 0) return;
-  EpiInterp<1> e;
-  e.disp = disp, e.P = d.P, e.out = out;
-  const int best = tune::pick(kTiles, [&](int c) { launch("tune", 0.0, e, coef, d, s, c); }, s);
+  // one- and two-field stagings time together (the sweeps use both; out holds 2 fields, coef 2 fields)
+  EpiInterp<1> e1;
+  e1.disp = disp, e1.P = d.P, e1.out = out;
+  EpiInterp<2> e2;
+  e2.disp = disp, e2.P = d.P, e2.out = out;
+  const int best = tune::pick(kTiles, [&](int c) {
+    launch("tune", 0.0, e1, coef, d, s, c);
+    launch("tune", 0.0, e2, coef, d, s, c);
+  }, s);
   tune::set(key, best);
 }
 
