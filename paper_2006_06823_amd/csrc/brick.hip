@@ -316,11 +316,13 @@ struct EpiIncStateV1 : DispPos, OneGroup<1> {
   float* __restrict__ out;
   const float* __restrict__ G;
   const float* __restrict__ dv;
+  float hdt;
   __device__ __forceinline__ void init(int64_t, State&) const {}
   __device__ __forceinline__ void accum(State& s, int, float v) const { s.o = v; }
   __device__ __forceinline__ void emit(int64_t p, const State& s) const {
-    out[p] = s.o;
-    out[P + p] = -(G[p] * dv[p] + G[P + p] * dv[P + p] + G[2 * P + p] * dv[2 * P + p]);
+    const float src = -(G[p] * dv[p] + G[P + p] * dv[P + p] + G[2 * P + p] * dv[2 * P + p]);
+    out[p] = s.o + hdt * src;
+    out[P + p] = src;
   }
 };
 
@@ -481,12 +483,12 @@ void brick_adjoint_grid_step(float* out, const float* c12, const float* disp, co
   launch(name_, bytes_, e, c12, d, s);
 }
 
-void brick_inc_state_v1(float* out, const float* c, const float* disp, const float* G, const float* dv,
+void brick_inc_state_v1(float* out, const float* c, const float* disp, const float* G, const float* dv, float hdt,
                         const Dims& d, hipStream_t s) {
   const std::string name_ = nm("k_inc_state_v1");
   const double bytes_ = 12.0 * d.P * 4;
   EpiIncStateV1 e;
-  e.disp = disp, e.P = d.P, e.out = out, e.G = G, e.dv = dv;
+  e.disp = disp, e.P = d.P, e.out = out, e.G = G, e.dv = dv, e.hdt = hdt;
   launch(name_, bytes_, e, c, d, s);
 }
 

@@ -179,15 +179,16 @@ __global__ void k_bl_adjoint_step(T* __restrict__ out, const T* __restrict__ cA,
 
 template <typename T>
 __global__ void k_inc_state_v1(T* __restrict__ out, const T* __restrict__ c, const T* __restrict__ disp,
-                               const T* __restrict__ G, const T* __restrict__ dv, int n0, int n1, int n2) {
+                               const T* __restrict__ G, const T* __restrict__ dv, T hdt, int n0, int n1, int n2) {
   const int64_t P = (int64_t)n0 * n1 * n2;
   const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (p >= P) return;
   const GridIdx g = unflatten(p, n1, n2);
   Taps<T> t;
   t.set(g.i0 + disp[p], g.i1 + disp[P + p], g.i2 + disp[2 * P + p], n0, n1, n2);
-  out[p] = t.eval(c, n1, n2);
-  out[P + p] = -(G[p] * dv[p] + G[P + p] * dv[P + p] + G[2 * P + p] * dv[2 * P + p]);
+  const T src = -(G[p] * dv[p] + G[P + p] * dv[P + p] + G[2 * P + p] * dv[2 * P + p]);
+  out[p] = t.eval(c, n1, n2) + hdt * src;
+  out[P + p] = src;
 }
 
 template <typename T>
@@ -680,11 +681,11 @@ void bl_adjoint_step(T* out, const T* cA, const T* cB, int nf, const T* disp, co
 }
 
 template <typename T>
-void inc_state_v1(T* out, const T* c, const T* disp, const T* G, const T* dv, const Dims& d, hipStream_t s) {
+void inc_state_v1(T* out, const T* c, const T* disp, const T* G, const T* dv, T hdt, const Dims& d, hipStream_t s) {
   if constexpr (std::is_same_v<T, float>) {
-    if (brick_ok(d)) return brick_inc_state_v1(out, c, disp, G, dv, d, s);
+    if (brick_ok(d)) return brick_inc_state_v1(out, c, disp, G, dv, hdt, d, s);
   }
-  prof::launch("k_inc_state_v1<" + std::string(prof::tname<T>()) + ">", 12.0 * d.P * sizeof(T), 0.0, k_inc_state_v1<T>, grid_for(d.P), dim3(kBlock), 0, s, out, c, disp, G, dv, d.n[0], d.n[1], d.n[2]);
+  prof::launch("k_inc_state_v1<" + std::string(prof::tname<T>()) + ">", 12.0 * d.P * sizeof(T), 0.0, k_inc_state_v1<T>, grid_for(d.P), dim3(kBlock), 0, s, out, c, disp, G, dv, hdt, d.n[0], d.n[1], d.n[2]);
   LDDMM_LAUNCH_CHECK();
 }
 
@@ -783,7 +784,7 @@ void zero(T* p, int64_t n, hipStream_t s) {
                                      hipStream_t);                                                      \
   template void bl_adjoint_step<T>(T*, const T*, const T*, int, const T*, const T*, const Dims&, T,     \
                                    hipStream_t);                                                        \
-  template void inc_state_v1<T>(T*, const T*, const T*, const T*, const T*, const Dims&, hipStream_t);  \
+  template void inc_state_v1<T>(T*, const T*, const T*, const T*, const T*, T, const Dims&, hipStream_t);  \
   template void inc_state_v3<T>(T*, const T*, const T*, const T*, const T*, const Dims&, hipStream_t);  \
   template void v3_source<T>(T*, const T*, const T*, const Dims&, hipStream_t);                         \
   template void v1_source<T>(T*, const T*, const T*, const Dims&, hipStream_t);                         \

@@ -93,7 +93,8 @@ void bl_adjoint_step(T* out, const T* cA, const T* cB, int nf, const T* disp, co
                      T dt, hipStream_t s);
 // variant-1 incremental state step: out0 = c o X, out1 = -G . dv
 template <typename T>
-void inc_state_v1(T* out, const T* c, const T* disp, const T* G, const T* dv, const Dims& d, hipStream_t s);
+// out[0] = c o X + hdt s, out[1] = s with s = -G . dv (the step's trapezoid sum and its source)
+void inc_state_v1(T* out, const T* c, const T* disp, const T* G, const T* dv, T hdt, const Dims& d, hipStream_t s);
 // variant-3 incremental state step: out[0..2] = c_f o X, out[3..5] = dv - Du dv
 template <typename T>
 void inc_state_v3(T* out, const T* c, const T* disp, const T* Du, const T* dv, const Dims& d,
@@ -143,7 +144,7 @@ void brick_bl_adjoint_step(float* out, const float* cAB, int nc, const float* di
                            const Dims& d, float dt, hipStream_t s);
 void brick_adjoint_grid_step(float* out, const float* c12, const float* disp, const float* divv, const Dims& d,
                              float dt, hipStream_t s);
-void brick_inc_state_v1(float* out, const float* c, const float* disp, const float* G, const float* dv,
+void brick_inc_state_v1(float* out, const float* c, const float* disp, const float* G, const float* dv, float hdt,
                         const Dims& d, hipStream_t s);
 void brick_inc_state_v3(float* out, const float* c, const float* disp, const float* Du, const float* dv,
                         const Dims& d, hipStream_t s);

@@ -715,7 +715,6 @@ class Solver final : public SolverBase {
     zero(acc, 3 * Q, st_);
     for (int n = nt_; n >= 0; --n) {
       T* xn = traj + n * stride;
-      iota_kind(xn, S(0), ncomp, kPlain);  // e = iota(x_n)
       const T w = trap_w(n);
       if (variant_ == LDDMM_BL_IMAGE_TRANSPORT) {
         // [fl, e G0, e G1, e G2]: fl to blA, the Hessian / gradient terms accumulated into acc
@@ -727,6 +726,7 @@ class Solver final : public SolverBase {
           pi_acc(S(1), 4, dst, al, be);
         }
       } else {
+        iota_kind(xn, S(0), ncomp, kPlain);  // e = iota(x_n)
         v3_products<T>(S(3), S(0), divv_.get(), Du_.get() + n * 9 * P, d_, st_);
         // [fl (3), (Du)^T e (3)]
         T* dst[6] = {blA_.get(), blA_.get() + Q, blA_.get() + 2 * Q, acc, acc + Q, acc + 2 * Q};
@@ -775,11 +775,11 @@ class Solver final : public SolverBase {
         const T* ys[1] = {f};
         const T al[1] = {hdt};
         iota_comb_kind(xs, ys, al, S(0), 1, kPref);
-        inc_state_v1<T>(S(1), S(0), Xb_.get(), G_.get() + (n + 1) * 3 * P, dvg_.get(), d_, st_);
-        T* dst[2] = {blA_.get(), f};
+        // [c o X + dt/2 s_{n+1}, s_{n+1}] projected straight into dm_{n+1} and f
+        inc_state_v1<T>(S(1), S(0), Xb_.get(), G_.get() + (n + 1) * 3 * P, dvg_.get(), hdt, d_, st_);
+        T* dst[2] = {dm + (n + 1) * Q, f};
         const T one[2] = {T(1), T(1)}, zer[2] = {T(0), T(0)};
         pi_acc(S(1), 2, dst, one, zer);
-        axpby(dm + (n + 1) * Q, T(1), blA_.get(), hdt, f, Q);
       }
       T* dl = incadj_.get();
       axpby(dl + (int64_t)nt_ * Q, T(-2.0 / sigma2_), dm + (int64_t)nt_ * Q, T(0), nullptr, Q);
