@@ -335,6 +335,7 @@ struct EpiIncStateV3 : DispPos, OneGroup<3> {
   float* __restrict__ out;
   const float* __restrict__ Du;
   const float* __restrict__ dv;
+  float hdt;
   __device__ __forceinline__ void init(int64_t, State&) const {}
   __device__ __forceinline__ void accum(State& s, int f, float v) const {
 #pragma unroll
@@ -344,10 +345,11 @@ struct EpiIncStateV3 : DispPos, OneGroup<3> {
     const float w0 = dv[p], w1 = dv[P + p], w2 = dv[2 * P + p];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      out[i * P + p] = s.o[i];
       const float* D = Du + (int64_t)(3 * i) * P;
       const float wi = i == 0 ? w0 : (i == 1 ? w1 : w2);
-      out[(3 + i) * P + p] = wi - (D[p] * w0 + D[P + p] * w1 + D[2 * P + p] * w2);
+      const float src = wi - (D[p] * w0 + D[P + p] * w1 + D[2 * P + p] * w2);
+      out[i * P + p] = s.o[i] + hdt * src;
+      out[(3 + i) * P + p] = src;
     }
   }
 };
@@ -492,12 +494,12 @@ void brick_inc_state_v1(float* out, const float* c, const float* disp, const flo
   launch(name_, bytes_, e, c, d, s);
 }
 
-void brick_inc_state_v3(float* out, const float* c, const float* disp, const float* Du, const float* dv,
+void brick_inc_state_v3(float* out, const float* c, const float* disp, const float* Du, const float* dv, float hdt,
                         const Dims& d, hipStream_t s) {
   const std::string name_ = nm("k_inc_state_v3");
   const double bytes_ = 24.0 * d.P * 4;
   EpiIncStateV3 e;
-  e.disp = disp, e.P = d.P, e.out = out, e.Du = Du, e.dv = dv;
+  e.disp = disp, e.P = d.P, e.out = out, e.Du = Du, e.dv = dv, e.hdt = hdt;
   launch(name_, bytes_, e, c, d, s);
 }
 

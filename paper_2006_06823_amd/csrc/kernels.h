@@ -95,10 +95,9 @@ void bl_adjoint_step(T* out, const T* cA, const T* cB, int nf, const T* disp, co
 template <typename T>
 // out[0] = c o X + hdt s, out[1] = s with s = -G . dv (the step's trapezoid sum and its source)
 void inc_state_v1(T* out, const T* c, const T* disp, const T* G, const T* dv, T hdt, const Dims& d, hipStream_t s);
-// variant-3 incremental state step: out[0..2] = c_f o X, out[3..5] = dv - Du dv
+// variant-3 incremental state step: out[0..2] = c_f o X + hdt s_f, out[3..5] = s = dv - Du dv
 template <typename T>
-void inc_state_v3(T* out, const T* c, const T* disp, const T* Du, const T* dv, const Dims& d,
-                  hipStream_t s);
+void inc_state_v3(T* out, const T* c, const T* disp, const T* Du, const T* dv, T hdt, const Dims& d, hipStream_t s);
 // variant-3 state source at node n: out = dv - Du dv  (3 comps)
 template <typename T>
 void v3_source(T* out, const T* Du, const T* dv, const Dims& d, hipStream_t s);
@@ -146,7 +145,7 @@ void brick_adjoint_grid_step(float* out, const float* c12, const float* disp, co
                              float dt, hipStream_t s);
 void brick_inc_state_v1(float* out, const float* c, const float* disp, const float* G, const float* dv, float hdt,
                         const Dims& d, hipStream_t s);
-void brick_inc_state_v3(float* out, const float* c, const float* disp, const float* Du, const float* dv,
+void brick_inc_state_v3(float* out, const float* c, const float* disp, const float* Du, const float* dv, float hdt,
                         const Dims& d, hipStream_t s);
 void brick_characteristics(float* disp, const float* v, const float* cv, const Dims& d, float dt, int dir,
                            hipStream_t s);

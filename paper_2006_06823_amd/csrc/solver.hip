@@ -796,11 +796,12 @@ class Solver final : public SolverBase {
         const T* ys[3] = {f, f + Q, f + 2 * Q};
         const T al[3] = {hdt, hdt, hdt};
         iota_comb_kind(xs, ys, al, S(0), 3, kPref);
-        inc_state_v3<T>(S(3), S(0), Xb_.get(), Du_.get() + (n + 1) * 9 * P, dvg_.get(), d_, st_);
-        T* dst[6] = {blA_.get(), blA_.get() + Q, blA_.get() + 2 * Q, f, f + Q, f + 2 * Q};
+        // [c o X + dt/2 s_{n+1} (3), s_{n+1} (3)] projected straight into du_{n+1} and f
+        inc_state_v3<T>(S(3), S(0), Xb_.get(), Du_.get() + (n + 1) * 9 * P, dvg_.get(), hdt, d_, st_);
+        T* dun1 = du + (n + 1) * 3 * Q;
+        T* dst[6] = {dun1, dun1 + Q, dun1 + 2 * Q, f, f + Q, f + 2 * Q};
         const T one[6] = {T(1), T(1), T(1), T(1), T(1), T(1)}, zer[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
         pi_acc(S(3), 6, dst, one, zer);
-        axpby(du + (n + 1) * 3 * Q, T(1), blA_.get(), hdt, f, 3 * Q);
       }
       // t = 1 coupling: drho~(1) = pi((2/sigma^2) (g1 . iota(du~(1))) g1)
       iota_kind(du + (int64_t)nt_ * 3 * Q, S(0), 3, kPlain);
