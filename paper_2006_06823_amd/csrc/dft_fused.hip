@@ -31,9 +31,9 @@ __device__ __forceinline__ void zero16(f32x16& a) {
 constexpr int kMaxN = 192, kMaxK = 64;
 constexpr int kRows = 32;  // grid rows of axis 1 per block
 
-// LDS floats of k_iota_ab with and without the staged axis-2 matrix
-__host__ __device__ inline int iota_lds(int k1, int k2, int n2, bool stage_w2) {
-  return k1 * (k2 + 1) + k1 * (n2 + 4) + k1 * kRows + (stage_w2 ? k2 * n2 : 0);
+// LDS floats of k_iota_ab for an xc-column block, with and without the staged axis-2 matrix
+__host__ __device__ inline int iota_lds(int k1, int k2, int xc, bool stage_w2) {
+  return k1 * (k2 + 1) + k1 * (xc + 4) + k1 * kRows + (stage_w2 ? k2 * xc : 0);
 }
 // LDS floats of k_pi_ba: the slab rows (aliased by the wave partials after stage A), U, and the
 // staged projection operands (P2 whole, the block's 32 rows of P1) when they fit
@@ -42,17 +42,21 @@ __host__ __device__ inline int pi_lds(int k1, int k2, int n2, bool stage_p) {
   return in_r + kRows * (k2 + 1) + (stage_p ? n2 * k2 + kRows * k1 : 0);
 }
 
-// grid (ceil(n1 / 32), k0, nf): each block expands one (field, a0) slab for 32 rows of x1
+// grid (ceil(n1 / 32) * ceil(n2 / xc), k0, nf): each block expands one (field, a0) slab for 32 rows
+// of x1 and xc columns of x2 (xc = all of n2 unless the slabs alone give too few blocks)
 template <bool STAGE_W2>
-__global__ __launch_bounds__(256) void k_iota_ab(IotaABArgs a) {
+__global__ __launch_bounds__(256) void k_iota_ab(IotaABArgs a, int xc) {
   extern __shared__ float smem[];
-  const int f = blockIdx.z, a0 = blockIdx.y, x1b = blockIdx.x * kRows;
+  const int f = blockIdx.z, a0 = blockIdx.y;
   const int k0 = a.k0, k1 = a.k1, k2 = a.k2, n1 = a.n1, n2 = a.n2;
-  const int lds = k2 + 1, ldt = n2 + 4;
+  const int nxb = (n1 + kRows - 1) / kRows;
+  const int x1b = (blockIdx.x % nxb) * kRows, x2b = (blockIdx.x / nxb) * xc;
+  const int ncol = min(xc, n2 - x2b);
+  const int lds = k2 + 1, ldt = xc + 4;
   float* S = smem;               // [a1][a2]
-  float* T = S + k1 * lds;       // [a1][x2]
+  float* T = S + k1 * lds;       // [a1][x2 - x2b]
   float* W1s = T + k1 * ldt;     // [a1][32 rows of x1]
-  float* W2s = W1s + k1 * kRows;  // [a2][x2] (when staged)
+  float* W2s = W1s + k1 * kRows;  // [a2][x2 - x2b] (when staged)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int kh = lane >> 5, li = lane & 31;
   const float* __restrict__ W2t = a.w2t[f];  // [k2][n2]
@@ -82,49 +86,50 @@ __global__ __launch_bounds__(256) void k_iota_ab(IotaABArgs a) {
       }
     }
     stage_tile<256, 8>(W1s, kRows, W1t + x1b, n1, k1, kRows, k1, n1 - x1b);
-    if (STAGE_W2) stage_tile<256, 16>(W2s, n2, W2t, n2, k2, n2, k2, n2);
+    if (STAGE_W2) stage_tile<256, 16>(W2s, xc, W2t + x2b, n2, k2, xc, k2, ncol);
   }
   __syncthreads();
-  const float* W2 = STAGE_W2 ? W2s : W2t;
-  // stage 1: T[a1][x2] = sum_a2 S[a1][a2] W2[x2][a2]
-  const int mb1 = (k1 + 31) / 32, nb = (n2 + 31) / 32;
+  const float* W2 = STAGE_W2 ? W2s : W2t + x2b;
+  const int ld2 = STAGE_W2 ? xc : n2;
+  // stage 1: T[a1][x2] = sum_a2 S[a1][a2] W2[x2][a2] over this block's columns
+  const int mb1 = (k1 + 31) / 32, nb = (ncol + 31) / 32;
   for (int tile = wave; tile < mb1 * nb; tile += 4) {
     const int mb = tile / nb, cb = tile - mb * nb;
     f32x16 acc;
     zero16(acc);
-    const int arow = mb * 32 + li, x2 = cb * 32 + li;
+    const int arow = mb * 32 + li, xl = cb * 32 + li;
 #pragma unroll 4
     for (int kk = 0; kk < k2; kk += 2) {
       const int l = kk + kh;
       const float av = (arow < k1 && l < k2) ? S[arow * lds + l] : 0.f;
-      const float bv = (x2 < n2 && l < k2) ? W2[l * n2 + x2] : 0.f;
+      const float bv = (xl < ncol && l < k2) ? W2[l * ld2 + xl] : 0.f;
       acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
     }
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const int a1 = mb * 32 + acc_row(r, lane);
-      if (a1 < k1 && x2 < n2) T[a1 * ldt + x2] = acc[r];
+      if (a1 < k1 && xl < ncol) T[a1 * ldt + xl] = acc[r];
     }
   }
   __syncthreads();
   // stage 2: out[x1][x2] = sum_a1 W1[x1][a1] T[a1][x2], x1 in [x1b, x1b + 32)
   float* out = a.out + ((int64_t)f * k0 + a0) * n1 * n2;
   for (int cb = wave; cb < nb; cb += 4) {
-    const int x2 = cb * 32 + li;
+    const int xl = cb * 32 + li;
     f32x16 acc;
     zero16(acc);
 #pragma unroll 4
     for (int kk = 0; kk < k1; kk += 2) {
       const int l = kk + kh;
       const float av = l < k1 ? W1s[l * kRows + li] : 0.f;
-      const float bv = (x2 < n2 && l < k1) ? T[l * ldt + x2] : 0.f;
+      const float bv = (xl < ncol && l < k1) ? T[l * ldt + xl] : 0.f;
       acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
     }
-    if (x2 < n2) {
+    if (xl < ncol) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int xr = x1b + acc_row(r, lane);
-        if (xr < n1) out[(int64_t)xr * n2 + x2] = acc[r];
+        if (xr < n1) out[(int64_t)xr * n2 + x2b + xl] = acc[r];
       }
     }
   }
@@ -238,7 +243,7 @@ __global__ __launch_bounds__(256) void k_pi_fin(PiBAArgs a, int nsplit) {
 
 bool fused_dft_ok(int n1, int n2, int k1, int k2) {
   return n1 <= kMaxN && n2 <= kMaxN && k1 <= kMaxK && k2 <= kMaxK && k1 >= 2 && k2 >= 2 &&
-         (size_t)iota_lds(k1, k2, n2, false) * sizeof(float) <= 65536 &&
+         (size_t)iota_lds(k1, k2, ceil_div(n2, 32) * 32, false) * sizeof(float) <= 65536 &&
          (size_t)pi_lds(k1, k2, n2, false) * sizeof(float) <= 65536;
 }
 
@@ -247,13 +252,17 @@ int pi_ba_splits(int n1) { return ceil_div(n1, kRows); }
 void iota_ab(const IotaABArgs& a, int nf, hipStream_t s) {
   const double bytes = 4.0 * nf * ((double)a.k0 * a.k1 * a.k2 + (double)a.k0 * a.n1 * a.n2);
   const double flops = 2.0 * nf * a.k0 * ((double)a.k1 * a.k2 * a.n2 + (double)a.n1 * a.k1 * a.n2);
-  dim3 g(ceil_div(a.n1, kRows), a.k0, nf);
-  const bool stage = (size_t)iota_lds(a.k1, a.k2, a.n2, true) * sizeof(float) <= 65536;
-  const uint32_t sm = (uint32_t)iota_lds(a.k1, a.k2, a.n2, stage) * sizeof(float);
+  // whole rows while the slabs give a block per CU; otherwise 64-column blocks
+  const int nxb = ceil_div(a.n1, kRows);
+  const int full = ceil_div(a.n2, 32) * 32;
+  const int xc = (int64_t)nxb * a.k0 * nf >= 256 || full <= 64 ? full : 64;
+  dim3 g(nxb * ceil_div(a.n2, xc), a.k0, nf);
+  const bool stage = (size_t)iota_lds(a.k1, a.k2, xc, true) * sizeof(float) <= 65536;
+  const uint32_t sm = (uint32_t)iota_lds(a.k1, a.k2, xc, stage) * sizeof(float);
   if (stage)
-    prof::launch("k_iota_ab", bytes, flops, k_iota_ab<true>, g, dim3(256), sm, s, a);
+    prof::launch("k_iota_ab", bytes, flops, k_iota_ab<true>, g, dim3(256), sm, s, a, xc);
   else
-    prof::launch("k_iota_ab", bytes, flops, k_iota_ab<false>, g, dim3(256), sm, s, a);
+    prof::launch("k_iota_ab", bytes, flops, k_iota_ab<false>, g, dim3(256), sm, s, a, xc);
   LDDMM_LAUNCH_CHECK();
 }
 
