@@ -224,88 +224,6 @@ __global__ __launch_bounds__(256) void k_pi_ba(PiBAArgs a) {
   }
 }
 
-// grid (1, k0, nf): one block projects a whole (field, a0) slab when the slab, both projection
-// matrices and the intermediate fit the 160 KB workgroup LDS of gfx950 (no partials, no finish
-// kernel).  Stage A: U[x1][a2] = sum_x2 slab[x1][x2] P2[a2][x2], the waves on 32-row tiles of x1;
-// stage B: r[a1][a2] = sum_x1 P1[a1][x1] U[x1][a2], x1 split across the waves and reduced in LDS;
-// epilogue out = beta out + alpha r.
-__host__ __device__ inline int pi1_lds(int n1, int n2, int k1, int k2) {
-  return n1 * (n2 + 1) + n2 * k2 + n1 * k1 + n1 * (k2 + 1) + 4096;
-}
-
-__global__ __launch_bounds__(256) void k_pi_ba1(PiBAArgs a) {
-  extern __shared__ float smem[];
-  const int a0 = blockIdx.y, f = blockIdx.z;
-  const int k0 = a.k0, k1 = a.k1, k2 = a.k2, n1 = a.n1, n2 = a.n2;
-  const int ldi = n2 + 1, ldu = k2 + 1;
-  float* In = smem;              // [n1][n2 + 1]
-  float* P2s = In + n1 * ldi;    // [n2][k2]
-  float* P1s = P2s + n2 * k2;    // [n1][k1]
-  float* U = P1s + n1 * k1;      // [n1][k2 + 1]
-  float* R = U + n1 * ldu;       // [4][1024]
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int kh = lane >> 5, li = lane & 31;
-  const int slab = f * k0 + a0;
-  stage_tile<256, 16>(In, ldi, a.in + (int64_t)slab * n1 * n2, n2, n1, n2, n1, n2);
-  stage_tile<256, 16>(P2s, k2, a.p2t, k2, n2, k2, n2, k2);
-  stage_tile<256, 16>(P1s, k1, a.p1t, k1, n1, k1, n1, k1);
-  __syncthreads();
-  // stage A
-  const int mbA = (n1 + 31) / 32, cb2 = (k2 + 31) / 32;
-  for (int tile = wave; tile < mbA * cb2; tile += 4) {
-    const int mb = tile / cb2, cb = tile - mb * cb2;
-    const int row = mb * 32 + li, a2 = cb * 32 + li;
-    f32x16 acc;
-    zero16(acc);
-#pragma unroll 4
-    for (int kk = 0; kk < n2; kk += 2) {
-      const int l = kk + kh;
-      const float av = (row < n1 && l < n2) ? In[row * ldi + l] : 0.f;
-      const float bv = (a2 < k2 && l < n2) ? P2s[l * k2 + a2] : 0.f;
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
-    }
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      const int x1 = mb * 32 + acc_row(r, lane);
-      if (x1 < n1 && a2 < k2) U[x1 * ldu + a2] = acc[r];
-    }
-  }
-  __syncthreads();
-  // stage B: ntile (1, 2 or 4) output tiles, 4 / ntile waves per tile splitting x1
-  const int mb2 = (k1 + 31) / 32, ntile = mb2 * cb2;
-  const int wpt = 4 / ntile;
-  const int tile = wave / wpt, part = wave - tile * wpt;
-  const int mb = tile / cb2, cb = tile - mb * cb2;
-  const int a1 = mb * 32 + li, a2 = cb * 32 + li;
-  const int seg = ((n1 + 2 * wpt - 1) / (2 * wpt)) * 2;
-  const int lb = part * seg, le = min(n1, lb + seg);
-  f32x16 acc;
-  zero16(acc);
-#pragma unroll 4
-  for (int kk = lb; kk < le; kk += 2) {
-    const int l = kk + kh;
-    const float av = (a1 < k1 && l < le) ? P1s[l * k1 + a1] : 0.f;
-    const float bv = (a2 < k2 && l < le) ? U[l * ldu + a2] : 0.f;
-    acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
-  }
-#pragma unroll
-  for (int r = 0; r < 16; ++r) R[wave * 1024 + r * 64 + lane] = acc[r];
-  __syncthreads();
-  // epilogue: one thread per output coefficient of this slab
-  float* dst = a.out[f] + (int64_t)a0 * k1 * k2;
-  const float al = a.alpha[f], be = a.beta[f];
-  for (int e = tid; e < k1 * k2; e += 256) {
-    const int r1 = e / k2, r2 = e - r1 * k2;
-    const int t = (r1 >> 5) * cb2 + (r2 >> 5);
-    const int rr = r1 & 31, ln = r2 & 31;
-    // register index and lane of (rr, ln) in the 32 x 32 accumulator layout
-    const int reg = ((rr >> 3) << 2) + (rr & 3), lanei = ln + 32 * ((rr >> 2) & 1);
-    float sum = 0.f;
-    for (int w = 0; w < wpt; ++w) sum += R[(t * wpt + w) * 1024 + reg * 64 + lanei];
-    dst[e] = be == 0.f ? al * sum : be * dst[e] + al * sum;
-  }
-}
-
 // out[f][a0][:] = beta out + alpha * sum_q part[f][a0][q][:], one thread per band coefficient
 __global__ __launch_bounds__(256) void k_pi_fin(PiBAArgs a, int nsplit) {
   const int kk = a.k1 * a.k2;
@@ -351,25 +269,6 @@ void iota_ab(const IotaABArgs& a, int nf, hipStream_t s) {
 void pi_ba(const PiBAArgs& a, int nf, hipStream_t s) {
   const double bytes = 4.0 * nf * ((double)a.k0 * a.n1 * a.n2 + (double)a.k0 * a.k1 * a.k2);
   const double flops = 2.0 * nf * a.k0 * ((double)a.k2 * a.n1 * a.n2 + (double)a.k1 * a.n1 * a.k2);
-  // one block per slab when everything fits the workgroup LDS (queried once per process)
-  static const int max_lds = [] {
-    int v = 65536, dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess ||
-        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
-      v = 65536;
-    if (hipFuncSetAttribute(reinterpret_cast<const void*>(k_pi_ba1), hipFuncAttributeMaxDynamicSharedMemorySize, v) !=
-        hipSuccess)
-      v = 65536;
-    (void)hipGetLastError();
-    return v;
-  }();
-  const size_t lds1 = (size_t)pi1_lds(a.n1, a.n2, a.k1, a.k2) * sizeof(float);
-  if (lds1 <= (size_t)max_lds) {
-    dim3 g1(1, a.k0, nf);
-    prof::launch("k_pi_ba1", bytes, flops, k_pi_ba1, g1, dim3(256), (uint32_t)lds1, s, a);
-    LDDMM_LAUNCH_CHECK();
-    return;
-  }
   if (!a.part) throw ArgError("pi_ba needs its partial-sum workspace");
   const int nsplit = pi_ba_splits(a.n1);
   dim3 g(nsplit, a.k0, nf);
