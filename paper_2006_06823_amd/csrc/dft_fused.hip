@@ -85,17 +85,8 @@ __global__ __launch_bounds__(256) void k_iota_ab(IotaABArgs a, int xc) {
         }
       }
     }
-    if (STAGE_W2 && k1 * kRows <= 256 * 8 && k2 * xc <= 256 * 16) {
-      TileRegs<256, 8> r1;
-      TileRegs<256, 16> r2;
-      r1.load(W1t + x1b, n1, k1, kRows, k1, n1 - x1b);
-      r2.load(W2t + x2b, n2, k2, xc, k2, ncol);
-      r1.store(W1s, kRows, k1, kRows);
-      r2.store(W2s, xc, k2, xc);
-    } else {
-      stage_tile<256, 8>(W1s, kRows, W1t + x1b, n1, k1, kRows, k1, n1 - x1b);
-      if (STAGE_W2) stage_tile<256, 16>(W2s, xc, W2t + x2b, n2, k2, xc, k2, ncol);
-    }
+    stage_tile<256, 8>(W1s, kRows, W1t + x1b, n1, k1, kRows, k1, n1 - x1b);
+    if (STAGE_W2) stage_tile<256, 16>(W2s, xc, W2t + x2b, n2, k2, xc, k2, ncol);
   }
   __syncthreads();
   const float* W2 = STAGE_W2 ? W2s : W2t + x2b;
@@ -166,22 +157,10 @@ __global__ __launch_bounds__(256) void k_pi_ba(PiBAArgs a) {
   const int slab = f * k0 + a0;
   const float* __restrict__ in = a.in + (int64_t)slab * n1 * n2;
   const int vr = n1 - x1b < kRows ? n1 - x1b : kRows;
-  if (STAGE_P && kRows * n2 <= 256 * 16 && n2 * k2 <= 256 * 16 && kRows * k1 <= 256 * 8) {
-    // all three tiles in flight before the first store
-    TileRegs<256, 16> rin, rp2;
-    TileRegs<256, 8> rp1;
-    rin.load(in + (int64_t)x1b * n2, n2, kRows, n2, vr, n2);
-    rp2.load(a.p2t, k2, n2, k2, n2, k2);
-    rp1.load(a.p1t + (int64_t)x1b * k1, k1, kRows, k1, vr, k1);
-    rin.store(In, ldi, kRows, n2);
-    rp2.store(P2s, k2, n2, k2);
-    rp1.store(P1s, k1, kRows, k1);
-  } else {
-    stage_tile<256, 16>(In, ldi, in + (int64_t)x1b * n2, n2, kRows, n2, vr, n2);
-    if (STAGE_P) {
-      stage_tile<256, 16>(P2s, k2, a.p2t, k2, n2, k2, n2, k2);
-      stage_tile<256, 4>(P1s, k1, a.p1t + (int64_t)x1b * k1, k1, kRows, k1, vr, k1);
-    }
+  stage_tile<256, 16>(In, ldi, in + (int64_t)x1b * n2, n2, kRows, n2, vr, n2);
+  if (STAGE_P) {
+    stage_tile<256, 16>(P2s, k2, a.p2t, k2, n2, k2, n2, k2);
+    stage_tile<256, 4>(P1s, k1, a.p1t + (int64_t)x1b * k1, k1, kRows, k1, vr, k1);
   }
   __syncthreads();
   const float* P2t = STAGE_P ? P2s : a.p2t;  // [n2][k2]

@@ -39,38 +39,3 @@ __device__ __forceinline__ void stage_tile(float* __restrict__ lds, int lstride,
 }
 
 }  // namespace lddmm
-
-namespace lddmm {
-
-// Two-phase form of stage_tile for tiles of at most NTHR * U elements: load into registers,
-// then store, so the loads of several tiles can all be in flight before the first store.
-template <int NTHR, int U>
-struct TileRegs {
-  float v[U];
-  __device__ __forceinline__ void load(const float* __restrict__ g, int64_t gstride, int rows, int cols, int vrows,
-                                       int vcols) {
-    const int tid = threadIdx.x, tot = rows * cols;
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int e = u * NTHR + tid;
-      v[u] = 0.f;
-      if (e < tot) {
-        const int r = e / cols, c = e - r * cols;
-        if (r < vrows && c < vcols) v[u] = g[(int64_t)r * gstride + c];
-      }
-    }
-  }
-  __device__ __forceinline__ void store(float* __restrict__ lds, int lstride, int rows, int cols) const {
-    const int tid = threadIdx.x, tot = rows * cols;
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int e = u * NTHR + tid;
-      if (e < tot) {
-        const int r = e / cols, c = e - r * cols;
-        lds[r * lstride + c] = v[u];
-      }
-    }
-  }
-};
-
-}  // namespace lddmm
