@@ -60,8 +60,8 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported (the build targets a single "
-              f"MI355X; see DESIGN.md for how the path would shard).", file=sys.stderr)
+        print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported (the library runs one "
+              f"registration context per GPU; independent registrations would shard one per GPU).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -39,17 +39,5 @@ inline void launch(const std::string& name, double bytes, double flops, F kernel
   }
 }
 
-class Scope {
- public:
-  Scope(hipStream_t s, const std::string& name, double bytes, double flops);
-  ~Scope();
-  Scope(const Scope&) = delete;
-  Scope& operator=(const Scope&) = delete;
-
- private:
-  hipStream_t s_;
-  int slot_ = -1;
-};
-
 }  // namespace prof
 }  // namespace lddmm

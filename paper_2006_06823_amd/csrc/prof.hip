@@ -53,22 +53,6 @@ void set_enabled(bool on) {
   g_on = on;
 }
 
-Scope::Scope(hipStream_t s, const std::string& name, double bytes, double flops) : s_(s) {
-  if (!g_on) return;
-  std::lock_guard<std::mutex> lk(g_mu);
-  Record r{name, bytes, flops, take_event(), take_event()};
-  if (!r.start || !r.stop) return;
-  if (hipEventRecord(r.start, s) != hipSuccess) return;
-  g_rec.push_back(r);
-  slot_ = static_cast<int>(g_rec.size()) - 1;
-}
-
-Scope::~Scope() {
-  if (slot_ < 0) return;
-  std::lock_guard<std::mutex> lk(g_mu);
-  (void)hipEventRecord(g_rec[slot_].stop, s_);
-}
-
 std::string collect() {
   std::lock_guard<std::mutex> lk(g_mu);
   struct Agg {
