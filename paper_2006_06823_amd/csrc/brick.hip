@@ -23,11 +23,15 @@ namespace {
 constexpr int HALO = 2;
 
 // Output tile of one workgroup; the autotuner picks one of these per grid shape.
-template <int X0, int X1, int X2, int NT>
+// LD2 >= B2 is the LDS row stride of the brick: a stride that is not 4 mod 32 changes which lanes
+// share a bank when neighbouring departure points fall in different brick rows
+template <int X0, int X1, int X2, int NT, int PAD2 = 0>
 struct Tile {
   static constexpr int TX0 = X0, TX1 = X1, TX2 = X2, NTHR = NT;
   static constexpr int B0 = TX0 + 2 * HALO, B1 = TX1 + 2 * HALO, B2 = TX2 + 2 * HALO;
-  static constexpr int VOL = B0 * B1 * B2;
+  static constexpr int LD2 = B2 + PAD2;
+  static constexpr int NPT = B0 * B1 * B2;   // staged points
+  static constexpr int VOL = B0 * B1 * LD2;  // LDS floats per field
   static constexpr int PPT = TX0 * TX1 * TX2 / NTHR;  // nodes per thread
 };
 using TileA = Tile<4, 8, 32, 256>;
@@ -38,7 +42,9 @@ using TileD = Tile<4, 4, 64, 256>;
 // coefficient volume through the halo instead of 2.5x (8 x 8 x 32), and two workgroups fill a CU
 using TileE = Tile<16, 8, 32, 1024>;
 using TileF = Tile<8, 16, 32, 1024>;
-constexpr int kTiles = 6;
+using TileG = Tile<8, 8, 32, 512, 1>;   // row stride 37
+using TileH = Tile<8, 8, 32, 512, 28>;  // row stride 64
+constexpr int kTiles = 8;
 
 struct Grid3 {
   int n0, n1, n2;
@@ -123,7 +129,7 @@ __device__ __noinline__ float eval_global(const float* __restrict__ c, float x0,
 template <class Epi, class TL>
 __global__ __launch_bounds__(TL::NTHR) void k_brick(Epi epi, const float* __restrict__ coef, Grid3 g) {
   constexpr int TX0 = TL::TX0, TX1 = TL::TX1, TX2 = TL::TX2, NTHR = TL::NTHR, PPT = TL::PPT;
-  constexpr int B0 = TL::B0, B1 = TL::B1, B2 = TL::B2, VOL = TL::VOL;
+  constexpr int B0 = TL::B0, B1 = TL::B1, B2 = TL::B2, LD2 = TL::LD2, VOL = TL::VOL, NPT = TL::NPT;
   constexpr int GS = Epi::GSIZE;
   __shared__ __align__(16) float br[GS * VOL];
   __shared__ int rowoff[B0 * B1];  // wrapped (i0, i1) row offsets of the brick
@@ -159,12 +165,12 @@ __global__ __launch_bounds__(TL::NTHR) void k_brick(Epi epi, const float* __rest
     __syncthreads();
     {
       // every load of the thread is issued before its first LDS store (one memory latency per brick)
-      constexpr int NIT = (VOL + NTHR - 1) / NTHR;
+      constexpr int NIT = (NPT + NTHR - 1) / NTHR;
       float v[NIT][GS];
 #pragma unroll
       for (int it = 0; it < NIT; ++it) {
         const int e = tid + it * NTHR;
-        if (e < VOL) {
+        if (e < NPT) {
           const int row = e / B2, b2 = e - row * B2;
           const int off = rowoff[row] + colidx[b2];
 #pragma unroll
@@ -174,12 +180,14 @@ __global__ __launch_bounds__(TL::NTHR) void k_brick(Epi epi, const float* __rest
 #pragma unroll
       for (int it = 0; it < NIT; ++it) {
         const int e = tid + it * NTHR;
-        if (e < VOL) {
+        if (e < NPT) {
+          const int row = e / B2, b2 = e - row * B2;
+          const int q = row * LD2 + b2;
           if constexpr (GS == 2) {  // interleaved pair
-            reinterpret_cast<float2*>(br)[e] = make_float2(v[it][0], v[it][1]);
+            reinterpret_cast<float2*>(br)[q] = make_float2(v[it][0], v[it][1]);
           } else {
 #pragma unroll
-            for (int k = 0; k < GS; ++k) br[k * VOL + e] = v[it][k];
+            for (int k = 0; k < GS; ++k) br[k * VOL + q] = v[it][k];
           }
         }
       }
@@ -198,13 +206,13 @@ __global__ __launch_bounds__(TL::NTHR) void k_brick(Epi epi, const float* __rest
         bspline_weights(x[j][1] - f1, w1);
         bspline_weights(x[j][2] - f2, w2);
         if constexpr (GS == 2) {
-          const float2 v = eval_brick2<B1, B2>(reinterpret_cast<const float2*>(br), s0, s1, s2, w0, w1, w2);
+          const float2 v = eval_brick2<B1, LD2>(reinterpret_cast<const float2*>(br), s0, s1, s2, w0, w1, w2);
           epi.accum(st[j], Epi::field(grp, 0), v.x);
           epi.accum(st[j], Epi::field(grp, 1), v.y);
         } else {
 #pragma unroll
           for (int k = 0; k < GS; ++k)
-            epi.accum(st[j], Epi::field(grp, k), eval_brick<B1, B2>(br + k * VOL, s0, s1, s2, w0, w1, w2));
+            epi.accum(st[j], Epi::field(grp, k), eval_brick<B1, LD2>(br + k * VOL, s0, s1, s2, w0, w1, w2));
         }
       } else {
 #pragma unroll
@@ -399,7 +407,7 @@ void launch(const std::string& name, double bytes, const Epi& epi, const float* 
   const Grid3 g{d.n[0], d.n[1], d.n[2], d.P};
   if (tile < 0) tile = tune::get(shape_key(d), 0);
   // epilogues with more than three fields would spill at 1024 threads: they keep the 512-thread tile
-  if (tile >= 4 && Epi::NF > 3) tile = 1;
+  if ((tile == 4 || tile == 5) && Epi::NF > 3) tile = 1;
   switch (tile) {
     case 1:
       launch_tile<Epi, TileB>(name, bytes, epi, coef, g, s);
@@ -416,6 +424,12 @@ void launch(const std::string& name, double bytes, const Epi& epi, const float* 
     case 5:
       launch_tile<Epi, TileF>(name, bytes, epi, coef, g, s);
       break;
+    case 6:
+      launch_tile<Epi, TileG>(name, bytes, epi, coef, g, s);
+      break;
+    case 7:
+      launch_tile<Epi, TileH>(name, bytes, epi, coef, g, s);
+      break;
     default:
       launch_tile<Epi, TileA>(name, bytes, epi, coef, g, s);
   }
@@ -424,13 +438,27 @@ void launch(const std::string& name, double bytes, const Epi& epi, const float* 
 
 std::string nm(const char* base) { return std::string("k_brick<") + base + ">"; }
 
+// smooth sub-voxel departure displacements (amplitude 0.8 voxel) for timing the tiles under the
+// LDS access pattern of real steps
+__global__ void k_tune_disp(float* disp, int n0, int n1, int n2) {
+  const int64_t P = (int64_t)n0 * n1 * n2;
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  const int i2 = (int)(p % n2), i1 = (int)((p / n2) % n1), i0 = (int)(p / ((int64_t)n1 * n2));
+  const float ph = 6.2831853f * ((float)i0 / n0 + 2.f * i1 / n1 + 3.f * i2 / n2);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) disp[c * P + p] = 0.8f * sinf(ph + 1.7f * c);
+}
+
 }  // namespace
 
 bool brick_ok(const Dims& d) { return d.n[0] > 1; }
 
-void brick_autotune(float* out, const float* coef, const float* disp, const Dims& d, hipStream_t s) {
+void brick_autotune(float* out, const float* coef, float* disp, const Dims& d, hipStream_t s) {
   const std::string key = shape_key(d);
   if (tune::get(key, -1) >= 0) return;
+  k_tune_disp<<<ceil_div(d.P, 256), 256, 0, s>>>(disp, d.n[0], d.n[1], d.n[2]);
+  LDDMM_LAUNCH_CHECK();
   // one- and two-field stagings time together (the sweeps use both; out holds 2 fields, coef 2 fields)
   EpiInterp<1> e1;
   e1.disp = disp, e1.P = d.P, e1.out = out;

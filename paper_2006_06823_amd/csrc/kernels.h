@@ -136,8 +136,9 @@ void copy_dev(T* dst, const T* src, int64_t n, hipStream_t s);
 
 // ---- LDS-brick interpolation, float 3D grids (brick.hip) ---------------------
 bool brick_ok(const Dims& d);
-// times every brick tile shape on this grid (one interpolation into `out`) and caches the fastest
-void brick_autotune(float* out, const float* coef, const float* disp, const Dims& d, hipStream_t s);
+// times every brick tile shape on this grid (one- and two-field interpolations into `out` at a smooth
+// synthetic sub-voxel displacement written to the scratch `disp`) and caches the fastest
+void brick_autotune(float* out, const float* coef, float* disp, const Dims& d, hipStream_t s);
 void brick_interp(float* out, const float* coef, int nf, const float* disp, const Dims& d, hipStream_t s);
 void brick_bl_adjoint_step(float* out, const float* cAB, int nc, const float* disp, const float* divv,
                            const Dims& d, float dt, hipStream_t s);
