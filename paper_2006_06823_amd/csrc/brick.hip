@@ -44,7 +44,10 @@ using TileE = Tile<16, 8, 32, 1024>;
 using TileF = Tile<8, 16, 32, 1024>;
 using TileG = Tile<8, 8, 32, 512, 1>;   // row stride 37
 using TileH = Tile<8, 8, 32, 512, 28>;  // row stride 64
-constexpr int kTiles = 8;
+using TileI = Tile<8, 8, 32, 512, 12>;  // row stride 48
+using TileJ = Tile<8, 8, 32, 512, 4>;   // row stride 40
+using TileK = Tile<4, 4, 64, 256, 28>;  // row stride 96
+constexpr int kTiles = 11;
 
 struct Grid3 {
   int n0, n1, n2;
@@ -429,6 +432,15 @@ void launch(const std::string& name, double bytes, const Epi& epi, const float* 
       break;
     case 7:
       launch_tile<Epi, TileH>(name, bytes, epi, coef, g, s);
+      break;
+    case 8:
+      launch_tile<Epi, TileI>(name, bytes, epi, coef, g, s);
+      break;
+    case 9:
+      launch_tile<Epi, TileJ>(name, bytes, epi, coef, g, s);
+      break;
+    case 10:
+      launch_tile<Epi, TileK>(name, bytes, epi, coef, g, s);
       break;
     default:
       launch_tile<Epi, TileA>(name, bytes, epi, coef, g, s);
