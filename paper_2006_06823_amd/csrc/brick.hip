@@ -97,8 +97,11 @@ __device__ __forceinline__ float2 eval_brick2(const float2* __restrict__ br, int
   return make_float2(ax, ay);
 }
 
-__device__ __noinline__ float eval_global(const float* __restrict__ c, float x0, float x1, float x2,
-                                             const Grid3& g) {
+// (the grid sizes go by value: a reference would put the caller's Grid3 on the stack, a 24-byte
+// scratch store per lane on every launch whether or not the gather runs)
+__device__ __noinline__ float eval_global(const float* __restrict__ c, float x0, float x1, float x2, int n0, int n1,
+                                          int n2) {
+  const Grid3 g{n0, n1, n2, 0};
   int i0[4], i1[4], i2[4];
   float w0[4], w1[4], w2[4];
   bspline_weights(tap_indices(x0, g.n0, i0), w0);
@@ -220,7 +223,7 @@ __global__ __launch_bounds__(TL::NTHR) void k_brick(Epi epi, const float* __rest
 #pragma unroll
         for (int k = 0; k < GS; ++k) {
           const int f = Epi::field(grp, k);
-          epi.accum(st[j], f, eval_global(coef + f * g.P, x[j][0], x[j][1], x[j][2], g));
+          epi.accum(st[j], f, eval_global(coef + f * g.P, x[j][0], x[j][1], x[j][2], g.n0, g.n1, g.n2));
         }
       }
     }
@@ -420,11 +423,11 @@ void launch(const std::string& name, double bytes, const Epi& epi, const float* 
     case 3:
       launch_tile<Epi, TileD>(name, bytes, epi, coef, g, s);
       break;
-    case 4:
-      launch_tile<Epi, TileE>(name, bytes, epi, coef, g, s);
+    case 4:  // (not instantiated for the epilogues that keep the 512-thread tile)
+      if constexpr (Epi::NF <= 3) launch_tile<Epi, TileE>(name, bytes, epi, coef, g, s);
       break;
     case 5:
-      launch_tile<Epi, TileF>(name, bytes, epi, coef, g, s);
+      if constexpr (Epi::NF <= 3) launch_tile<Epi, TileF>(name, bytes, epi, coef, g, s);
       break;
     case 6:
       launch_tile<Epi, TileG>(name, bytes, epi, coef, g, s);

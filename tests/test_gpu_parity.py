@@ -144,6 +144,29 @@ def test_hess_matvec_parity(variant, dim, N, K, Nt, precision):
         assert rel_l2(got, dl[n]) <= tol(precision)
 
 
+# image-transport Hessian on grids with a long first axis (first-axis contractions of one and two
+# 32-slot tiles, odd and ragged second and third axes); a CFL of 1.9 voxels sends part of the
+# departure points out of the staged interpolation bricks to the global gather
+LONG_AXIS_CASES = [((96, 21, 36), (24, 12, 14), 4, 0.8), ((100, 18, 40), (40, 10, 12), 3, 1.9)]
+
+
+@pytest.mark.parametrize("N,K,Nt,cfl", LONG_AXIS_CASES)
+def test_hess_matvec_parity_long_first_axis(N, K, Nt, cfl):
+    ctx, om, v = make(1, 3, N, K, Nt, L.FP32, seed=6, cfl=cfl)
+    ctx.state_solve(dev(v, ctx))
+    om.setup(v)
+    om.state()
+    from paper_2006_06823_amd import synthetic as syn
+    dv = syn.random_bl_coefficients(3, K, 13)
+    h = ctx.hess_matvec(dev(dv, ctx))
+    assert rel_l2(h, om.hess_matvec(dv)) <= 1e-5
+    dm, dl = om.last_inc
+    for n in (1, Nt):
+        assert rel_l2(ctx.get_field(L.FIELD_INC_STATE, n).reshape(dm[n].shape), dm[n]) <= 1e-5
+    for n in (0, Nt - 1):
+        assert rel_l2(ctx.get_field(L.FIELD_INC_ADJOINT, n).reshape(dl[n].shape), dl[n]) <= 1e-5
+
+
 def test_dot_fp64_reduction():
     """Device FP64 reductions over FP32 data equal the sum computed in double on the host (1e-12)."""
     ctx = L.Context(L.Problem((32, 32, 32), (8, 8, 8), precision=L.FP32))
