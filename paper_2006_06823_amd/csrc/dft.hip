@@ -170,6 +170,7 @@ __global__ __launch_bounds__(64 * WR * WM) void dft_right_kernel(const T* __rest
 //
 // contract mode (M <= 64, L large): the four waves of a block share 32 columns and
 // split the contraction range; partial 32x32 blocks are summed through LDS.
+constexpr int kPre = 16;  // k-steps of a wave's range whose input loads are issued up front
 template <int MB, int NCT>
 __global__ __launch_bounds__(256) void dft_left_contract(const float* __restrict__ in, float* __restrict__ out,
                                                          FieldMats<float> mats, int bpf, int M, int L, int C,
@@ -190,12 +191,33 @@ __global__ __launch_bounds__(256) void dft_left_contract(const float* __restrict
   const int ncb = (C + 32 * NCT - 1) / (32 * NCT);
   // without a separate reduction buffer the W tile is reloaded per column block
   for (int cb = blockIdx.x; cb < ncb; cb += gridDim.x) {
+    const int c0 = cb * 32 * NCT;
+    // a wave range of up to 2 kPre rows: all of its input loads are issued before the W tile is
+    // staged, so the block waits one memory latency instead of one per unrolled group of steps
+    // (one 32-row output tile only: with two the registers would halve the occupancy)
+    constexpr bool kPrefetch = MB == 1;
+    const bool pre = kPrefetch && seg <= 2 * kPre;
+    float bq[kPrefetch ? kPre : 1][NCT];
+    if constexpr (kPrefetch) {
+      if (pre) {
+        // 32-bit offsets from the uniform base (one address register per load, not two)
+        const int lrow = lb + kh;
+#pragma unroll
+        for (int i = 0; i < kPre; ++i) {
+          const int l = lrow + 2 * i;
+#pragma unroll
+          for (int t = 0; t < NCT; ++t) {
+            const int c = c0 + t * 32 + (lane & 31);
+            bq[i][t] = (c < C && l < le) ? in[l * C + c] : 0.f;
+          }
+        }
+      }
+    }
     if (cb == blockIdx.x || !separate_red) {
       __syncthreads();
       stage_tile<256, 16>(Ws, ldw, W, L, 32 * MB, L, M, L);
       __syncthreads();
     }
-    const int c0 = cb * 32 * NCT;
     f32x16 acc[MB][NCT];
 #pragma unroll
     for (int mb = 0; mb < MB; ++mb)
@@ -203,21 +225,37 @@ __global__ __launch_bounds__(256) void dft_left_contract(const float* __restrict
       for (int t = 0; t < NCT; ++t)
 #pragma unroll
         for (int r = 0; r < 16; ++r) acc[mb][t][r] = 0.f;
-#pragma unroll 4
-    for (int kk = lb; kk < le; kk += 2) {
-      const int l = kk + kh;
-      float bv[NCT];
+    if (pre) {
+      if constexpr (kPrefetch) {
 #pragma unroll
-      for (int t = 0; t < NCT; ++t) {
-        const int c = c0 + t * 32 + (lane & 31);
-        bv[t] = (c < C && l < le) ? in[(int64_t)l * C + c] : 0.f;
+        for (int i = 0; i < kPre; ++i) {
+          const int l = lb + 2 * i + kh;
+#pragma unroll
+          for (int mb = 0; mb < MB; ++mb) {
+            const float av = l < le ? Ws[(mb * 32 + (lane & 31)) * ldw + l] : 0.f;
+#pragma unroll
+            for (int t = 0; t < NCT; ++t)
+              acc[mb][t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bq[i][t], acc[mb][t], 0, 0, 0);
+          }
+        }
       }
+    } else {
+#pragma unroll 4
+      for (int kk = lb; kk < le; kk += 2) {
+        const int l = kk + kh;
+        float bv[NCT];
 #pragma unroll
-      for (int mb = 0; mb < MB; ++mb) {
-        const float av = l < le ? Ws[(mb * 32 + (lane & 31)) * ldw + l] : 0.f;
+        for (int t = 0; t < NCT; ++t) {
+          const int c = c0 + t * 32 + (lane & 31);
+          bv[t] = (c < C && l < le) ? in[(int64_t)l * C + c] : 0.f;
+        }
 #pragma unroll
-        for (int t = 0; t < NCT; ++t)
-          acc[mb][t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv[t], acc[mb][t], 0, 0, 0);
+        for (int mb = 0; mb < MB; ++mb) {
+          const float av = l < le ? Ws[(mb * 32 + (lane & 31)) * ldw + l] : 0.f;
+#pragma unroll
+          for (int t = 0; t < NCT; ++t)
+            acc[mb][t] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv[t], acc[mb][t], 0, 0, 0);
+        }
       }
     }
     // reduce the waves' partial sums one 32 x 32 tile at a time through a 16 KB buffer

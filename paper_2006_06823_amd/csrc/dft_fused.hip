@@ -68,21 +68,21 @@ __global__ __launch_bounds__(256) void k_iota_ab(IotaABArgs a, int xc) {
     const float* y = a.y[f] ? a.y[f] + off : nullptr;
     const float al = a.alpha[f];
     constexpr int U = 8;
-    for (int base = 0; base < k1 * k2; base += 256 * U) {
+    TileWalk w(256, tid, k2, k2, lds);
+    while (w.r < k1) {
+      const TileWalk w0 = w;
       float v[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int e = base + u * 256 + tid;
         v[u] = 0.f;
-        if (e < k1 * k2) v[u] = y ? x[e] + al * y[e] : x[e];
+        if (w.r < k1) v[u] = y ? x[w.o1] + al * y[w.o1] : x[w.o1];
+        w.next();
       }
+      w = w0;
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const int e = base + u * 256 + tid;
-        if (e < k1 * k2) {
-          const int r = e / k2, c = e - r * k2;
-          S[r * lds + c] = v[u];
-        }
+        if (w.r < k1) S[w.o2] = v[u];
+        w.next();
       }
     }
     stage_tile<256, 8>(W1s, kRows, W1t + x1b, n1, k1, kRows, k1, n1 - x1b);
@@ -185,12 +185,12 @@ __global__ __launch_bounds__(256) void k_pi_ba(PiBAArgs a) {
     for (int r = 0; r < 16; ++r) R[wave * 1024 + r * 64 + lane] = acc[r];
   }
   __syncthreads();
-  for (int e = tid; e < kRows * k2; e += 256) {
-    const int x = e / k2, c = e - x * k2;
+  for (TileWalk e(256, tid, k2, k2, ldu); e.r < kRows; e.next()) {
+    const int x = e.r, c = e.c;
     const int t = c >> 5, reg = ((x >> 3) << 2) + (x & 3), lanei = (c & 31) + 32 * ((x >> 2) & 1);
     float sum = 0.f;
     for (int w = 0; w < wpt; ++w) sum += R[(t * wpt + w) * 1024 + reg * 64 + lanei];
-    U[x * ldu + c] = sum;
+    U[e.o2] = sum;
   }
   __syncthreads();
   // stage B: partial r[a1][a2] = sum_{x < 32} P1[a1][x1b + x] U[x][a2], one wave per 32x32 tile
