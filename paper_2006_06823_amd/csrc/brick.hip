@@ -139,7 +139,15 @@ __global__ __launch_bounds__(TL::NTHR) void k_brick(Epi epi, const float* __rest
   __shared__ __align__(16) float br[GS * VOL];
   __shared__ int rowoff[B0 * B1];  // wrapped (i0, i1) row offsets of the brick
   __shared__ int colidx[B2];       // wrapped i2 of the brick columns
-  const int t0 = blockIdx.z * TX0, t1 = blockIdx.y * TX1, t2 = blockIdx.x * TX2;
+  // Workgroups are dealt to the 8 XCDs round-robin in launch order, so grid neighbours would sit in
+  // different L2s and every halo would be fetched again from the fabric.  When the block count is a
+  // multiple of 8 the launch index is remapped so that each XCD owns one contiguous run of tiles
+  // (whole rows and slabs of the volume), whose shared halos then hit in its own L2.
+  const int gx = gridDim.x, gy = gridDim.y, nb = gx * gy * gridDim.z;
+  int bid = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+  if ((nb & 7) == 0) bid = (bid & 7) * (nb >> 3) + (bid >> 3);
+  const int bx = bid % gx, byz = bid / gx, by = byz % gy, bz = byz / gy;
+  const int t0 = bz * TX0, t1 = by * TX1, t2 = bx * TX2;
   const int o0 = t0 - HALO, o1 = t1 - HALO, o2 = t2 - HALO;
   const int tid = threadIdx.x;
   for (int e = tid; e < B0 * B1; e += NTHR) {
