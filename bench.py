@@ -30,7 +30,7 @@ HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
 FP32_PEAK_TFLOPS = 157.3     # MI355X dense FP32 (matrix and vector)
 
 # variant-1 Hessian matvec kernels that move data (HBM roofline); DFT kernels also report MFMA use
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_dominant_kernel.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_matvec_kernels_128.json")
 WEIGHTS_FILE = os.path.join(ROOT, "paper_2006_06823_amd", "weights", "warmstart_v1_128.npz")
 
 
@@ -141,8 +141,9 @@ def main():
         # WRITE_SIZE, scaled by a plain copy of known size), applied to this run's launch mix
         try:
             tr = json.load(open(TRAFFIC_FILE))
-            if tr.get("kernel") == dom_name and tr.get("workload") == list(N) + list(K):
-                traffic = round(tr["traffic_over_algorithmic"] * bytes_per_launch)
+            ratio = tr.get("kernels", {}).get(dom_name, {}).get("traffic_over_algorithmic")
+            if ratio is not None and tr.get("workload") == list(N) + list(K):
+                traffic = round(ratio * bytes_per_launch)
         except Exception:
             traffic = None
     roofline = {

@@ -418,7 +418,7 @@ template <class Epi>
 void launch(const std::string& name, double bytes, const Epi& epi, const float* coef, const Dims& d,
             hipStream_t s, int tile = -1) {
   const Grid3 g{d.n[0], d.n[1], d.n[2], d.P};
-  if (tile < 0) tile = tune::get(shape_key(d), 0);
+  if (tile < 0) tile = tune::get(shape_key(d) + ":gs" + std::to_string(Epi::GSIZE), 0);
   // epilogues with more than three fields would spill at 1024 threads: they keep the 512-thread tile
   if ((tile == 4 || tile == 5) && Epi::NF > 3) tile = 1;
   switch (tile) {
@@ -467,21 +467,22 @@ __global__ void k_tune_disp(float* disp, int n0, int n1, int n2) {
 
 bool brick_ok(const Dims& d) { return d.n[0] > 1; }
 
+// One tile per grid shape and staging width (fields staged together: 1, 2 interleaved, or 3), timed
+// on the interpolation epilogue of that width; out holds 3 fields, coef 3 fields.
 void brick_autotune(float* out, const float* coef, float* disp, const Dims& d, hipStream_t s) {
-  const std::string key = shape_key(d);
-  if (tune::get(key, -1) >= 0) return;
+  const std::string key = shape_key(d) + ":gs";
+  if (tune::get(key + "1", -1) >= 0 && tune::get(key + "2", -1) >= 0 && tune::get(key + "3", -1) >= 0) return;
   k_tune_disp<<<ceil_div(d.P, 256), 256, 0, s>>>(disp, d.n[0], d.n[1], d.n[2]);
   LDDMM_LAUNCH_CHECK();
-  // one- and two-field stagings time together (the sweeps use both; out holds 2 fields, coef 2 fields)
   EpiInterp<1> e1;
   e1.disp = disp, e1.P = d.P, e1.out = out;
   EpiInterp<2> e2;
   e2.disp = disp, e2.P = d.P, e2.out = out;
-  const int best = tune::pick(kTiles, [&](int c) {
-    launch("tune", 0.0, e1, coef, d, s, c);
-    launch("tune", 0.0, e2, coef, d, s, c);
-  }, s);
-  tune::set(key, best);
+  EpiInterp<3> e3;
+  e3.disp = disp, e3.P = d.P, e3.out = out;
+  tune::set(key + "1", tune::pick(kTiles, [&](int c) { launch("tune", 0.0, e1, coef, d, s, c); }, s));
+  tune::set(key + "2", tune::pick(kTiles, [&](int c) { launch("tune", 0.0, e2, coef, d, s, c); }, s));
+  tune::set(key + "3", tune::pick(kTiles, [&](int c) { launch("tune", 0.0, e3, coef, d, s, c); }, s));
 }
 
 void brick_interp(float* out, const float* coef, int nf, const float* disp, const Dims& d, hipStream_t s) {

@@ -95,9 +95,9 @@ class Solver final : public SolverBase {
   void autotune() {
     if constexpr (std::is_same_v<T, float>) {
       if (!brick_ok(d_) || std::getenv("LDDMM_BL_NO_TUNE")) return;
-      zero(S(0), 2 * d_.P, st_);
+      zero(S(0), 3 * d_.P, st_);
       zero(Xb_.get(), 3 * d_.P, st_);
-      brick_autotune(S(1), S(0), Xb_.get(), d_, st_);
+      brick_autotune(S(3), S(0), Xb_.get(), d_, st_);
       sync();
     }
   }

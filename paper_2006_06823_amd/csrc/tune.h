@@ -1,6 +1,6 @@
 // Project autotuner: picks a kernel variant (tile shape, contraction kernel) per
 // problem shape by timing every candidate on the real shapes, and caches the
-// choice process-wide under a key such as "brick:128x128x128".
+// choice process-wide under a key such as "brick:128x128x128:gs2".
 #pragma once
 
 #include <hip/hip_runtime.h>
