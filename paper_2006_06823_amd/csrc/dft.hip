@@ -170,7 +170,9 @@ __global__ __launch_bounds__(64 * WR * WM) void dft_right_kernel(const T* __rest
 //
 // contract mode (M <= 64, L large): the four waves of a block share 32 columns and
 // split the contraction range; partial 32x32 blocks are summed through LDS.
-constexpr int kPre = 16;  // k-steps of a wave's range whose input loads are issued up front
+// k-steps of a wave's range whose input loads are issued up front (covers N0 <= 128 / 192)
+template <int MB>
+constexpr int pre_steps() { return MB == 1 ? 16 : 24; }
 template <int MB, int NCT>
 __global__ __launch_bounds__(256) void dft_left_contract(const float* __restrict__ in, float* __restrict__ out,
                                                          FieldMats<float> mats, int bpf, int M, int L, int C,
@@ -195,7 +197,8 @@ __global__ __launch_bounds__(256) void dft_left_contract(const float* __restrict
     // a wave range of up to 2 kPre rows: all of its input loads are issued before the W tile is
     // staged, so the block waits one memory latency instead of one per unrolled group of steps
     // (one 32-row output tile only: with two the registers would halve the occupancy)
-    constexpr bool kPrefetch = MB == 1;
+    constexpr int kPre = pre_steps<MB>();
+    constexpr bool kPrefetch = true;
     const bool pre = kPrefetch && seg <= 2 * kPre;
     float bq[kPrefetch ? kPre : 1][NCT];
     if constexpr (kPrefetch) {
