@@ -173,23 +173,29 @@ __global__ __launch_bounds__(TL::NTHR) void k_brick(Epi epi, const float* __rest
       x[j][0] = x[j][1] = x[j][2] = 0.f;
     }
   }
+  // every load of the thread is issued before its first LDS store (one memory latency per brick);
+  // with several field groups the next group's loads are issued before the current group's
+  // evaluation, so their latency hides behind it
+  constexpr int NIT = (NPT + NTHR - 1) / NTHR;
+  float v[NIT][GS];
+  __syncthreads();  // row offsets and columns tabulated
+  auto load_group = [&](int grp) {
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      const int e = tid + it * NTHR;
+      if (e < NPT) {
+        const int row = e / B2, b2 = e - row * B2;
+        const int off = rowoff[row] + colidx[b2];
+#pragma unroll
+        for (int k = 0; k < GS; ++k) v[it][k] = coef[Epi::field(grp, k) * g.P + off];
+      }
+    }
+  };
+  load_group(0);
 #pragma unroll 1
   for (int grp = 0; grp < Epi::GROUPS; ++grp) {
-    __syncthreads();
+    __syncthreads();  // the previous group's evaluation is done with the brick
     {
-      // every load of the thread is issued before its first LDS store (one memory latency per brick)
-      constexpr int NIT = (NPT + NTHR - 1) / NTHR;
-      float v[NIT][GS];
-#pragma unroll
-      for (int it = 0; it < NIT; ++it) {
-        const int e = tid + it * NTHR;
-        if (e < NPT) {
-          const int row = e / B2, b2 = e - row * B2;
-          const int off = rowoff[row] + colidx[b2];
-#pragma unroll
-          for (int k = 0; k < GS; ++k) v[it][k] = coef[Epi::field(grp, k) * g.P + off];
-        }
-      }
 #pragma unroll
       for (int it = 0; it < NIT; ++it) {
         const int e = tid + it * NTHR;
@@ -206,6 +212,7 @@ __global__ __launch_bounds__(TL::NTHR) void k_brick(Epi epi, const float* __rest
       }
     }
     __syncthreads();
+    if (grp + 1 < Epi::GROUPS) load_group(grp + 1);
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
       if (!live[j]) continue;
