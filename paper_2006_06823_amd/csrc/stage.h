@@ -34,23 +34,38 @@ struct TileWalk {
 // lstride); elements with r >= vrows or c >= vcols are written as zeros.  Each thread issues U
 // loads before its first LDS store, so a tile of up to NTHR * U elements costs one memory
 // latency instead of one per element the thread moves.
+// Loads are branch-free (an element outside the valid region reads the tile's first element and
+// is replaced by zero), and a batch that lies wholly inside the tile stores without per-element
+// tests, so the compiler emits no divergent branch per element.
 template <int NTHR, int U>
 __device__ __forceinline__ void stage_tile(float* __restrict__ lds, int lstride, const float* __restrict__ g,
                                            int64_t gstride, int rows, int cols, int vrows, int vcols) {
   TileWalk w(NTHR, threadIdx.x, cols, static_cast<int>(gstride), lstride);
-  while (w.r < rows) {
+  const int tot = rows * cols;
+  for (int base = 0; base < tot; base += NTHR * U) {
+    const bool full = base + NTHR * U <= tot;  // uniform across the block
     const TileWalk w0 = w;
     float v[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      v[u] = (w.r < rows && w.r < vrows && w.c < vcols) ? g[w.o1] : 0.f;
+      const bool ok = (full || w.r < rows) && w.r < vrows && w.c < vcols;
+      const float t = g[ok ? w.o1 : 0];
+      v[u] = ok ? t : 0.f;
       w.next();
     }
     w = w0;
+    if (full) {
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      if (w.r < rows) lds[w.o2] = v[u];
-      w.next();
+      for (int u = 0; u < U; ++u) {
+        lds[w.o2] = v[u];
+        w.next();
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (w.r < rows) lds[w.o2] = v[u];
+        w.next();
+      }
     }
   }
 }
