@@ -238,6 +238,20 @@ lddmm_bl_status lddmm_nn_loss(lddmm_nn_ctx* ctx, const void* out, const void* v_
 lddmm_bl_status lddmm_bl_profile_enable(int32_t on);
 int64_t lddmm_bl_profile_read(char* buf, int64_t len);
 
+/* Autotuner cache (process-wide).  The interpolation kernels of a context pick one of
+ * lddmm_bl_tune_candidates("brick") workgroup tiles per grid shape and staging width
+ * (fields staged together: 1, 2 or 3), timing every candidate when the first context of
+ * that shape is created, under the keys "brick:<n0>x<n1>x<n2>:gs<w>".
+ * tune_get returns the cached choice of a key, or -1 if none.  tune_set fixes the choice
+ * of a key before a context of that shape is created (choice in [0, candidates), or -1
+ * to forget it so that the next context times the candidates again); it returns
+ * LDDMM_BL_E_ARG for an unknown key family or a choice out of range.  A key's choice is
+ * read at every launch, so a context created before a tune_set follows it too; calls that
+ * overlap launches on other threads race. */
+int32_t lddmm_bl_tune_candidates(const char* family);
+int32_t lddmm_bl_tune_get(const char* key);
+lddmm_bl_status lddmm_bl_tune_set(const char* key, int32_t choice);
+
 #ifdef __cplusplus
 }
 #endif

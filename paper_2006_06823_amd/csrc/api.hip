@@ -9,6 +9,7 @@
 
 #include "prof.h"
 #include "solver.h"
+#include "tune.h"
 
 struct lddmm_bl_ctx {
   std::unique_ptr<lddmm::SolverBase> solver;
@@ -196,6 +197,31 @@ lddmm_bl_status lddmm_bl_profile_enable(int32_t on) {
   try {
     if (on) lddmm::prof::collect();  // drop stale records
     lddmm::prof::set_enabled(on != 0);
+  } catch (...) {
+    return LDDMM_BL_E_HIP;
+  }
+  return LDDMM_BL_OK;
+}
+
+int32_t lddmm_bl_tune_candidates(const char* family) {
+  if (family && std::strcmp(family, "brick") == 0) return lddmm::brick_tile_count();
+  return 0;
+}
+
+int32_t lddmm_bl_tune_get(const char* key) {
+  if (!key) return -1;
+  try {
+    return lddmm::tune::get(key, -1);
+  } catch (...) {
+    return -1;
+  }
+}
+
+lddmm_bl_status lddmm_bl_tune_set(const char* key, int32_t choice) {
+  if (!key || std::strncmp(key, "brick:", 6) != 0) return LDDMM_BL_E_ARG;
+  if (choice < -1 || choice >= lddmm::brick_tile_count()) return LDDMM_BL_E_ARG;
+  try {
+    lddmm::tune::set(key, choice);
   } catch (...) {
     return LDDMM_BL_E_HIP;
   }

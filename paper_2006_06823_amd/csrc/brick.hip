@@ -425,7 +425,7 @@ template <class Epi>
 void launch(const std::string& name, double bytes, const Epi& epi, const float* coef, const Dims& d,
             hipStream_t s, int tile = -1) {
   const Grid3 g{d.n[0], d.n[1], d.n[2], d.P};
-  if (tile < 0) tile = tune::get(shape_key(d) + ":gs" + std::to_string(Epi::GSIZE), 0);
+  if (tile < 0) tile = std::max(0, tune::get(shape_key(d) + ":gs" + std::to_string(Epi::GSIZE), 0));
   // epilogues with more than three fields would spill at 1024 threads: they keep the 512-thread tile
   if ((tile == 4 || tile == 5) && Epi::NF > 3) tile = 1;
   switch (tile) {
@@ -473,6 +473,8 @@ __global__ void k_tune_disp(float* disp, int n0, int n1, int n2) {
 }  // namespace
 
 bool brick_ok(const Dims& d) { return d.n[0] > 1; }
+
+int brick_tile_count() { return kTiles; }
 
 // One tile per grid shape and staging width (fields staged together: 1, 2 interleaved, or 3), timed
 // on the interpolation epilogue of that width; out holds 3 fields, coef 3 fields.

@@ -35,6 +35,7 @@ EXPORTS = [
     "lddmm_bl_state_solve", "lddmm_bl_adjoint_solve", "lddmm_bl_hess_matvec", "lddmm_bl_gn_solve",
     "lddmm_bl_jacobian", "lddmm_bl_project", "lddmm_bl_include", "lddmm_bl_get_field", "lddmm_bl_dot",
     "lddmm_bl_profile_enable", "lddmm_bl_profile_read", "lddmm_bl_gn_solve_batched",
+    "lddmm_bl_tune_candidates", "lddmm_bl_tune_get", "lddmm_bl_tune_set",
     "lddmm_nn_create", "lddmm_nn_info", "lddmm_nn_forward", "lddmm_nn_backward", "lddmm_nn_zero_grad",
     "lddmm_nn_step", "lddmm_nn_get", "lddmm_nn_set", "lddmm_nn_destroy", "lddmm_nn_pool_pair",
     "lddmm_nn_velocity", "lddmm_nn_loss",
@@ -118,6 +119,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.lddmm_bl_profile_enable.restype = ctypes.c_int
     lib.lddmm_bl_profile_read.argtypes = [ctypes.c_char_p, i64]
     lib.lddmm_bl_profile_read.restype = i64
+    lib.lddmm_bl_tune_candidates.argtypes = [ctypes.c_char_p]
+    lib.lddmm_bl_tune_candidates.restype = i32
+    lib.lddmm_bl_tune_get.argtypes = [ctypes.c_char_p]
+    lib.lddmm_bl_tune_get.restype = i32
+    lib.lddmm_bl_tune_set.argtypes = [ctypes.c_char_p, i32]
+    lib.lddmm_bl_tune_set.restype = ctypes.c_int
     lib.lddmm_bl_last_error.argtypes = [vp]
     lib.lddmm_bl_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -357,6 +364,31 @@ def profile_read():
         name, count, ms, nbytes, flops = line.split("\t")
         out[name] = dict(count=int(count), ms=float(ms), bytes=float(nbytes), flops=float(flops))
     return out
+
+
+def tune_candidates(family: str = "brick") -> int:
+    """Number of kernel variants the autotuner chooses from for a key family."""
+    return int(load_library().lddmm_bl_tune_candidates(family.encode()))
+
+
+def tune_get(key: str) -> int:
+    """Cached autotuner choice of a key such as 'brick:128x128x128:gs2' (-1: none)."""
+    return int(load_library().lddmm_bl_tune_get(key.encode()))
+
+
+def tune_set(key: str, choice: int) -> None:
+    """Fix (or with -1 forget) the autotuner choice of a key."""
+    st = load_library().lddmm_bl_tune_set(key.encode(), int(choice))
+    if st != 0:
+        raise LddmmError(st, f"lddmm_bl_tune_set({key!r}, {choice}) rejected")
+
+
+def brick_tune_keys(n) -> list:
+    """The brick autotuner keys of a grid shape (3D, or 2D held as n0 = 1)."""
+    n = tuple(int(x) for x in n)
+    if len(n) == 2:
+        n = (1,) + n
+    return [f"brick:{n[0]}x{n[1]}x{n[2]}:gs{w}" for w in (1, 2, 3)]
 
 
 class WarmStartNet:

@@ -52,3 +52,21 @@ def test_committed_warm_start_weights_match_the_architecture():
     n += 3 * cin + 3
     assert z["params"].shape == (n,) and z["params"].dtype == np.float32
     assert np.isfinite(z["params"]).all()
+
+
+def test_autotuner_cache_round_trip_and_rejections():
+    """The tuner cache is host state: no GPU is needed to set, read and reject keys."""
+    n = L.tune_candidates("brick")
+    assert n == 8
+    assert L.tune_candidates("nope") == 0
+    key = "brick:7x9x11:gs2"
+    assert L.tune_get(key) == -1
+    L.tune_set(key, n - 1)
+    assert L.tune_get(key) == n - 1
+    L.tune_set(key, -1)
+    assert L.tune_get(key) == -1
+    for bad_key, bad_choice in [("brick:7x9x11:gs2", n), ("brick:7x9x11:gs2", -2), ("dft:7x9x11", 0)]:
+        with pytest.raises(L.LddmmError):
+            L.tune_set(bad_key, bad_choice)
+    assert L.brick_tune_keys((40, 36, 44)) == ["brick:40x36x44:gs1", "brick:40x36x44:gs2", "brick:40x36x44:gs3"]
+    assert L.brick_tune_keys((48, 40))[0] == "brick:1x48x40:gs1"
