@@ -186,6 +186,26 @@ def test_hess_matvec_parity_separable_dft_path(variant):
     assert rel_l2(ctx.hess_matvec(dev(dv, ctx)), om.hess_matvec(dv)) <= 1e-5
 
 
+# degenerate and odd configurations: one time step, a band with a single real mode on one axis
+# (K_j = 2: the constant and the pad slot), odd grid sizes on every axis
+SMALL_CASES = [((12, 10, 14), (4, 2, 4), 1), ((17, 9, 33), (6, 4, 10), 2)]
+
+
+@pytest.mark.parametrize("variant", [1, 3])
+@pytest.mark.parametrize("N,K,Nt", SMALL_CASES)
+def test_small_and_odd_configurations(variant, N, K, Nt):
+    ctx, om, v = make(variant, 3, N, K, Nt, L.FP32, seed=12)
+    ctx.state_solve(dev(v, ctx))
+    om.setup(v)
+    om.state()
+    g, _ = ctx.adjoint_solve()
+    om.adjoint()
+    assert rel_l2(g, om.gradient()) <= 1e-5
+    from paper_2006_06823_amd import synthetic as syn
+    dv = syn.random_bl_coefficients(3, K, 15)
+    assert rel_l2(ctx.hess_matvec(dev(dv, ctx)), om.hess_matvec(dv)) <= 1e-5
+
+
 def test_dot_fp64_reduction():
     """Device FP64 reductions over FP32 data equal the sum computed in double on the host (1e-12)."""
     ctx = L.Context(L.Problem((32, 32, 32), (8, 8, 8), precision=L.FP32))
