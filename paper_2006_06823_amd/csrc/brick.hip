@@ -336,21 +336,24 @@ struct EpiAdjointGrid : DispPos, OneGroup<2> {
 };
 
 // image-transport incremental state: out0 = c o X, out1 = -G . dv
+// (the source is formed in init, before the brick is staged, so that its six loads overlap the
+// staging and the interpolation instead of following them)
 struct EpiIncStateV1 : DispPos, OneGroup<1> {
   static constexpr int NF = 1;
   struct State {
-    float o;
+    float o, src;
   };
   float* __restrict__ out;
   const float* __restrict__ G;
   const float* __restrict__ dv;
   float hdt;
-  __device__ __forceinline__ void init(int64_t, State&) const {}
+  __device__ __forceinline__ void init(int64_t p, State& s) const {
+    s.src = -(G[p] * dv[p] + G[P + p] * dv[P + p] + G[2 * P + p] * dv[2 * P + p]);
+  }
   __device__ __forceinline__ void accum(State& s, int, float v) const { s.o = v; }
   __device__ __forceinline__ void emit(int64_t p, const State& s) const {
-    const float src = -(G[p] * dv[p] + G[P + p] * dv[P + p] + G[2 * P + p] * dv[2 * P + p]);
-    out[p] = s.o + hdt * src;
-    out[P + p] = src;
+    out[p] = s.o + hdt * s.src;
+    out[P + p] = s.src;
   }
 };
 
@@ -358,26 +361,30 @@ struct EpiIncStateV1 : DispPos, OneGroup<1> {
 struct EpiIncStateV3 : DispPos, OneGroup<3> {
   static constexpr int NF = 3;
   struct State {
-    float o[3];
+    float o[3], src[3];
   };
   float* __restrict__ out;
   const float* __restrict__ Du;
   const float* __restrict__ dv;
   float hdt;
-  __device__ __forceinline__ void init(int64_t, State&) const {}
-  __device__ __forceinline__ void accum(State& s, int f, float v) const {
-#pragma unroll
-    for (int i = 0; i < 3; ++i) s.o[i] = (f == i) ? v : s.o[i];
-  }
-  __device__ __forceinline__ void emit(int64_t p, const State& s) const {
+  __device__ __forceinline__ void init(int64_t p, State& s) const {
     const float w0 = dv[p], w1 = dv[P + p], w2 = dv[2 * P + p];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       const float* D = Du + (int64_t)(3 * i) * P;
       const float wi = i == 0 ? w0 : (i == 1 ? w1 : w2);
-      const float src = wi - (D[p] * w0 + D[P + p] * w1 + D[2 * P + p] * w2);
-      out[i * P + p] = s.o[i] + hdt * src;
-      out[(3 + i) * P + p] = src;
+      s.src[i] = wi - (D[p] * w0 + D[P + p] * w1 + D[2 * P + p] * w2);
+    }
+  }
+  __device__ __forceinline__ void accum(State& s, int f, float v) const {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) s.o[i] = (f == i) ? v : s.o[i];
+  }
+  __device__ __forceinline__ void emit(int64_t p, const State& s) const {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      out[i * P + p] = s.o[i] + hdt * s.src[i];
+      out[(3 + i) * P + p] = s.src[i];
     }
   }
 };
