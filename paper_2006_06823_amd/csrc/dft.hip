@@ -394,28 +394,35 @@ __global__ __launch_bounds__(256) void dft_left_contract_bf16(const float* __res
   out += b * sOb;
   const int c0 = blockIdx.x * 32;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int e = tid; e < 32 * MB * L; e += 256) {
-    const int m = e / L, l = e - m * L;
-    Ws[m * ldw + l] = m < M ? W[(int64_t)m * L + l] : 0.f;
-  }
-  __syncthreads();
-  const int seg = ((L + 63) / 64) * 16;  // per-wave range, a multiple of 16
+  const int seg = ((L + 63) / 64) * 16;  // per-wave range, a multiple of 16 (at most 48: L <= 192)
   const int lb = wave * seg, le = min(L, lb + seg);
   const int c = c0 + (lane & 31);
   const bool cok = c < C;
   const int kh = lane >> 5;
+  // the wave's input rows are all requested before the W tile is staged (32-bit offsets from the
+  // uniform base; rows past the range read a valid element and are zeroed)
+  float bq[3][8];
+#pragma unroll
+  for (int it = 0; it < 3; ++it)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int l = lb + 16 * it + 8 * kh + j;
+      const bool ok = cok && l < le;
+      const float t = in[ok ? l * C + c : 0];
+      bq[it][j] = ok ? t : 0.f;
+    }
+  stage_tile<256, 16>(Ws, ldw, W, L, 32 * MB, L, M, L);
+  __syncthreads();
   f32x16 acc[MB];
 #pragma unroll
   for (int mb = 0; mb < MB; ++mb)
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[mb][r] = 0.f;
-  for (int kk = lb; kk < le; kk += 16) {
-    float bv[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int l = kk + 8 * kh + j;
-      bv[j] = (cok && l < le) ? in[(int64_t)l * C + c] : 0.f;
-    }
+  for (int it = 0; it < 3; ++it) {
+    const int kk = lb + 16 * it;
+    if (kk >= le) break;
+    float* bv = bq[it];
     bf16x8 bh, bl;
     split8(bv, bh, bl);
 #pragma unroll
@@ -459,26 +466,37 @@ __global__ __launch_bounds__(256) void dft_left_expand_bf16(const float* __restr
   out += b * sOb;
   const int c0 = blockIdx.x * 32, m0 = blockIdx.y * 128;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int e = tid; e < 128 * L; e += 256) {
-    const int mm = e / L, l = e - mm * L;
-    Ws[mm * ldw + l] = (m0 + mm) < M ? W[(int64_t)(m0 + mm) * L + l] : 0.f;
-  }
-  __syncthreads();
-  const int mw = m0 + wave * 32;
-  if (mw >= M) return;
   const int c = c0 + (lane & 31);
   const bool cok = c < C;
   const int kh = lane >> 5;
+  // every input row (L <= 64) requested before the W tile is staged
+  float bq[4][8];
+#pragma unroll
+  for (int it = 0; it < 4; ++it)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int l = 16 * it + 8 * kh + j;
+      const bool ok = cok && l < L;
+      const float t = in[ok ? l * C + c : 0];
+      bq[it][j] = ok ? t : 0.f;
+    }
+  stage_tile<256, 16>(Ws, ldw, W + (int64_t)m0 * L, L, 128, L, M - m0, L);
+  __syncthreads();
+  const int mw = m0 + wave * 32;
+  if (mw >= M) return;
   f32x16 acc;
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc[r] = 0.f;
   const float* Wr = Ws + (wave * 32 + (lane & 31)) * ldw;
-  for (int kk = 0; kk < L; kk += 16) {
-    float av[8], bv[8];
+#pragma unroll
+  for (int it = 0; it < 4; ++it) {
+    const int kk = 16 * it;
+    if (kk >= L) break;
+    float av[8];
+    float* bv = bq[it];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int l = kk + 8 * kh + j;
-      bv[j] = (cok && l < L) ? in[(int64_t)l * C + c] : 0.f;
       av[j] = l < L ? Wr[l] : 0.f;
     }
     bf16x8 ah, al, bh, bl;
