@@ -52,7 +52,7 @@ def parse():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MB",
                     help="instead of the benchmark: 5 plain device copies of MB megabytes (float32), the reference "
                          "for scaling the HBM byte counters of a profiler run")
-    ap.add_argument("--learned-pairs", type=int, default=2,
+    ap.add_argument("--learned-pairs", type=int, default=8,
                     help="held-out pairs registered plain and with the trained warm start (0: skip)")
     return ap.parse_args()
 
@@ -262,7 +262,8 @@ def learned_leg(npairs):
            "caps": "20 GN x 10 PCG"}
     for k in ("plain", "learned", "learned_E", "learned_Z"):
         out[k] = {m: round(summ[k][m], 4) for m in ("registrations_per_s", "gn_iters_mean", "hess_matvecs_mean",
-                                                    "seconds_mean", "reached_tol", "reached_plain_E")}
+                                                    "seconds_mean", "reached_tol", "reached_plain_E",
+                                                    "gn_iter_ratio", "time_ratio") if m in summ[k]}
     return out
 
 

@@ -140,7 +140,9 @@ lddmm_bl_status lddmm_bl_hess_matvec(lddmm_bl_ctx* ctx, const void* dv_bl, void*
  * v_bl_inout (device BL [d][K..]), which receives the result.  PCG uses
  * L~^{-1}; when precond_Z_or_null is a device array of r BL directions
  * [r][d][K..], the two-level preconditioner L~^{-1} + Z (Z^T H Z)^{-1} Z^T is
- * used instead.  report (host) may be NULL. */
+ * used instead.  report (host) may be NULL.  When the context holds a state
+ * solve at exactly the starting velocity (a state_solve with the same values,
+ * no set_images since), that state is reused instead of being solved again. */
 lddmm_bl_status lddmm_bl_gn_solve(lddmm_bl_ctx* ctx, const lddmm_bl_gn_opts* opts, void* v_bl_inout,
                                   const void* precond_Z_or_null, int32_t r, lddmm_bl_gn_report* report);
 

@@ -602,7 +602,14 @@ class Solver final : public SolverBase {
     else
       state_v3();
     finish_objective(e);
+    std::memcpy(last_e_, e, sizeof(last_e_));
     state_valid_ = true;
+  }
+  // true when the held state was solved at exactly the internal velocity v (tmp: scratch of v's size)
+  bool state_is_at(const T* v, T* tmp) {
+    if (!state_valid_) return false;
+    axpby(tmp, T(1), v, T(-1), vbl_.get(), 3 * d_.Q);
+    return maxabs<T>(tmp, 3 * d_.Q, work_.get(), host_.get(), st_) == 0.0;
   }
 
   // ------------------------------------ image transport: state (Table 1 row 1)
@@ -820,6 +827,7 @@ class Solver final : public SolverBase {
   T dt_ = T(1);
   double alpha_ = 0, sigma2_ = 1;
   bool have_images_ = false, state_valid_ = false;
+  double last_e_[3] = {0, 0, 0};  // objective terms of the held state
   bool graphs_enabled_ = std::getenv("LDDMM_BL_NO_GRAPH") == nullptr;
   bool bf16_ = false;  // split-bf16 contractions for the first-axis DFT stages
   bool trace_ = std::getenv("LDDMM_BL_TRACE") != nullptr;  // Gauss-Newton scalars to stderr
@@ -956,9 +964,13 @@ int Solver<T>::gn_solve(const lddmm_bl_gn_opts& o, void* v_user, const void* Zu,
   int status = LDDMM_BL_OK;
   lddmm_bl_gn_report R{};
   user_to_internal(v.get(), static_cast<T*>(v_user));
-  set_velocity_internal(v.get());
   double e[3];
-  state_internal(e);
+  if (state_is_at(v.get(), x.get())) {
+    std::memcpy(e, last_e_, sizeof(e));  // a state solve at this velocity is already held
+  } else {
+    set_velocity_internal(v.get());
+    state_internal(e);
+  }
   double E = e[0];
   R.E0 = E;
   adjoint_internal(g.get());

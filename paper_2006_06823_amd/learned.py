@@ -286,6 +286,9 @@ def compare(net, reg: Registrar, seeds, stream: PairStream, opts: SolveOpts, log
             variants.append(("learned_Z", "Z", 0.0))
         for name, zmode, etarget in variants:
             v = reg.zero_velocity() if fallback else v0.clone()
+            # each run starts as a deployment would: right after the fallback test, whose state solve at
+            # v (already counted in t_pred) the Gauss-Newton solve then reuses instead of repeating
+            reg.energy(v)
             Z = None
             if zmode and not fallback:
                 Z = torch.zeros((3, 3) + reg.band, dtype=torch.float32, device=reg.device)

@@ -65,3 +65,31 @@ def test_gn_3d_fp32_small_matches_oracle():
     vo, ro = gauss_newton(om, np.zeros((3,) + K), max_gn=3, max_pcg=3, fixed_iters=True)
     assert rep["backtracks"] == ro.backtracks
     assert rel_l2(v, vo) <= 1e-3
+
+
+@pytest.mark.parametrize("variant", [1, 3])
+def test_gn_reuses_a_held_state_at_the_same_velocity(variant):
+    """A state solve at the starting velocity just before gn_solve is reused by it (the solve skips its
+    own first state solve); the result is bitwise the one of a fresh context.  A state held at another
+    velocity, or invalidated by new images, is not reused."""
+    N, K, Nt = (24, 20, 28), (8, 6, 10), 3
+    I0, I1 = syn.phantom_pair_3d(N, 3, max_disp_vox=1.5)
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda")
+    v0 = t(0.02 * syn.random_bl_coefficients(3, K, 4))
+
+    def solve(prep):
+        ctx = L.Context(L.Problem(N, K, nt=Nt, variant=variant, precision=L.FP32))
+        ctx.set_images(t(I0), t(I1))
+        prep(ctx)
+        v = v0.clone()
+        st, rep = ctx.gn_solve(v, max_gn=3, max_pcg=3, fixed_iters=True)
+        return v, rep
+
+    ref_v, ref = solve(lambda ctx: None)
+    held_v, held = solve(lambda ctx: ctx.state_solve(v0.clone()))
+    other_v, other = solve(lambda ctx: ctx.state_solve(torch.zeros_like(v0)))
+    renewed_v, renewed = solve(lambda ctx: (ctx.state_solve(v0.clone()), ctx.set_images(t(I1), t(I0)),
+                                            ctx.set_images(t(I0), t(I1))))
+    for v, rep in ((held_v, held), (other_v, other), (renewed_v, renewed)):
+        assert torch.equal(v, ref_v)
+        assert rep["E0"] == ref["E0"] and rep["E"] == ref["E"] and rep["gn_iters"] == ref["gn_iters"]
