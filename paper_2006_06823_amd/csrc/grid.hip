@@ -7,6 +7,7 @@
 // [c][n0][n1][n2], n2 contiguous, so neighbouring lanes touch neighbouring nodes.
 #include "kernels.h"
 #include "prof.h"
+#include "stage.h"
 
 #include <type_traits>
 
@@ -460,7 +461,7 @@ constexpr int kChunkLines = 32, kChunkGroups = 8, kChunkMaxC = 24, kChunkMaxN = 
 template <typename T>
 __global__ __launch_bounds__(256) void k_prefilter_chunked(T* f, int n, int64_t gl, int64_t gi, int nlines_max,
                                                            int64_t tile_stride_a, int tiles_a, int64_t tile_stride_b,
-                                                           int64_t P) {
+                                                           int64_t P, double inv) {
   extern __shared__ unsigned char smem_raw[];
   T* sm = reinterpret_cast<T*>(smem_raw);  // [n][33]: element (line l, point i) at i * 33 + l
   constexpr int ld = kChunkLines + 1;
@@ -471,21 +472,37 @@ __global__ __launch_bounds__(256) void k_prefilter_chunked(T* f, int n, int64_t 
   const int nl = min(kChunkLines, nlines_max - ta * kChunkLines);
   const int tid = threadIdx.x;
   const bool line_major = gi == 1;  // points of a line contiguous in memory
-  for (int e = tid; e < n * kChunkLines; e += 256) {
-    int l, i;
-    if (line_major) {
-      l = e / n, i = e - l * n;
-    } else {
-      i = e / kChunkLines, l = e - i * kChunkLines;
+  // the tile is walked line by line (points contiguous) or point by point (lines contiguous), its
+  // loads batched ahead of the LDS stores and its indices advanced without integer division; the
+  // element offsets stay below 2^31 (a tile spans at most 32 lines of 192 points of one field)
+  const int rows = line_major ? kChunkLines : n, cols = line_major ? n : kChunkLines;
+  const int gstride = static_cast<int>(line_major ? gl : gi);
+  {
+    constexpr int U = 8;
+    TileWalk w(256, tid, cols, gstride, 0);
+    while (w.r < rows) {
+      const TileWalk w0 = w;
+      T v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int l = line_major ? w.r : w.c;
+        const bool ok = w.r < rows && l < nl;
+        const T t = base[ok ? w.o1 : 0];
+        v[u] = ok ? t : T(0);
+        w.next();
+      }
+      w = w0;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int l = line_major ? w.r : w.c, i = line_major ? w.c : w.r;
+        if (w.r < rows) sm[i * ld + l] = v[u];
+        w.next();
+      }
     }
-    if (l < nl) sm[i * ld + l] = base[l * gl + i * gi];
   }
   __syncthreads();
-  const double z = Pole<T>::z;
+  const double z = Pole<T>::z;  // inv = 1 / (1 - z^n), from the host
   const int h = n < Pole<T>::horizon ? n : Pole<T>::horizon;
-  double zn = 1.0;
-  for (int i = 0; i < n; ++i) zn *= z;
-  const double inv = 1.0 / (1.0 - zn);
   const int l = tid % kChunkLines, g = tid / kChunkLines;
   const int Lc = (n + kChunkGroups - 1) / kChunkGroups;
   const int c0 = g * Lc, c1 = min(n, c0 + Lc);
@@ -494,8 +511,8 @@ __global__ __launch_bounds__(256) void k_prefilter_chunked(T* f, int n, int64_t 
   {
     double acc = 0.0, zi = 1.0;
     for (int k = 0; k < h; ++k) {
-      int j = c0 - k;
-      j = ((j % n) + n) % n;
+      int j = c0 - k;  // periodic: k < h <= n, one wrap at most
+      if (j < 0) j += n;
       acc += zi * 6.0 * static_cast<double>(sm[j * ld + l]);
       zi *= z;
     }
@@ -519,7 +536,7 @@ __global__ __launch_bounds__(256) void k_prefilter_chunked(T* f, int n, int64_t 
     const int e = c1 - 1;
     double acc = 0.0, zi = 1.0;
     for (int k = 0; k < h; ++k) {
-      const int j = (e + k) % n;
+      const int j = e + k < n ? e + k : e + k - n;
       acc += zi * static_cast<double>(sm[j * ld + l]);
       zi *= z;
     }
@@ -538,14 +555,9 @@ __global__ __launch_bounds__(256) void k_prefilter_chunked(T* f, int n, int64_t 
   for (int q = 0; q < kChunkMaxC; ++q)
     if (c0 + q < c1) sm[(c0 + q) * ld + l] = static_cast<T>(cp[q]);
   __syncthreads();
-  for (int e = tid; e < n * kChunkLines; e += 256) {
-    int ll, i;
-    if (line_major) {
-      ll = e / n, i = e - ll * n;
-    } else {
-      i = e / kChunkLines, ll = e - i * kChunkLines;
-    }
-    if (ll < nl) base[ll * gl + i * gi] = sm[i * ld + ll];
+  for (TileWalk w(256, tid, cols, gstride, 0); w.r < rows; w.next()) {
+    const int ll = line_major ? w.r : w.c, i = line_major ? w.c : w.r;
+    if (ll < nl) base[w.o1] = sm[i * ld + ll];
   }
 }
 
@@ -612,8 +624,10 @@ void prefilter(T* f, int nf, const Dims& d, hipStream_t s) {
   auto chunked = [&](int n, int64_t gl, int64_t gi, int nlines_a, int64_t stride_b, int nb) {
     const int tiles_a = ceil_div(nlines_a, kChunkLines);
     const uint32_t sm = (uint32_t)((size_t)n * (kChunkLines + 1) * sizeof(T));
+    double zn = 1.0;
+    for (int i = 0; i < n; ++i) zn *= Pole<T>::z;
     prof::launch(nm, 2.0 * nf * d.P * sizeof(T), 0.0, k_prefilter_chunked<T>, dim3(tiles_a * nb, nf), dim3(256),
-                 sm, s, f, n, gl, gi, nlines_a, gl, tiles_a, stride_b, d.P);
+                 sm, s, f, n, gl, gi, nlines_a, gl, tiles_a, stride_b, d.P, 1.0 / (1.0 - zn));
     LDDMM_LAUNCH_CHECK();
   };
   if (n2 > 1) {
