@@ -1156,15 +1156,53 @@ int gn_solve_batched_impl(std::vector<Solver<T>*>& subs, const lddmm_bl_gn_opts&
     S[i].ref = o.grad_ref_inf > 0 ? o.grad_ref_inf : S[i].ginf;
     S[i].gnorm0 = std::sqrt(sv.dot_internal(S[i].g.get(), S[i].g.get()));
   }
-  // one graph with every subject's Hessian matvec (p in dvbl_, H p in hbl_); eager while profiling
+  // one graph with every subject's Hessian matvec (p in dvbl_, H p in hbl_); eager while profiling.
+  // The subjects are independent, so their matvecs are captured as parallel branches: subject i on
+  // branch stream i mod nb, forked from and joined back into st; the GPU then overlaps the short,
+  // latency-bound kernels of different subjects instead of running B chains back to back.
   hipGraphExec_t exec = nullptr;
   const bool use_graph = !prof::enabled();
   if (use_graph) {
+    const int nb = std::min(B, 8);
+    struct Branches {
+      std::vector<hipStream_t> s;
+      std::vector<hipEvent_t> ev;  // [0] fork, [1 + j] join of branch j
+      ~Branches() {
+        for (hipStream_t x : s) (void)hipStreamDestroy(x);
+        for (hipEvent_t x : ev) (void)hipEventDestroy(x);
+      }
+    } br;
+    for (int j = 0; j < nb; ++j) {
+      hipStream_t x;
+      LDDMM_HIP(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+      br.s.push_back(x);
+    }
+    for (int j = 0; j <= nb; ++j) {
+      hipEvent_t x;
+      LDDMM_HIP(hipEventCreateWithFlags(&x, hipEventDisableTiming));
+      br.ev.push_back(x);
+    }
+    std::vector<hipStream_t> own(B);
+    for (int i = 0; i < B; ++i) own[i] = subs[i]->st_;
+    auto restore = [&] {
+      for (int i = 0; i < B; ++i) subs[i]->st_ = own[i];
+    };
     hipGraph_t graph = nullptr;
     LDDMM_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     try {
-      for (int i = 0; i < B; ++i) subs[i]->run_matvec(subs[i]->dvbl_.get(), subs[i]->hbl_.get());
+      LDDMM_HIP(hipEventRecord(br.ev[0], st));
+      for (int j = 0; j < nb; ++j) LDDMM_HIP(hipStreamWaitEvent(br.s[j], br.ev[0], 0));
+      for (int i = 0; i < B; ++i) {
+        subs[i]->st_ = br.s[i % nb];
+        subs[i]->run_matvec(subs[i]->dvbl_.get(), subs[i]->hbl_.get());
+      }
+      restore();
+      for (int j = 0; j < nb; ++j) {
+        LDDMM_HIP(hipEventRecord(br.ev[1 + j], br.s[j]));
+        LDDMM_HIP(hipStreamWaitEvent(st, br.ev[1 + j], 0));
+      }
     } catch (...) {
+      restore();
       (void)hipStreamEndCapture(st, &graph);
       if (graph) (void)hipGraphDestroy(graph);
       throw;
