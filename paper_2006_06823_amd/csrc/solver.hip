@@ -1156,39 +1156,37 @@ int gn_solve_batched_impl(std::vector<Solver<T>*>& subs, const lddmm_bl_gn_opts&
     S[i].ref = o.grad_ref_inf > 0 ? o.grad_ref_inf : S[i].ginf;
     S[i].gnorm0 = std::sqrt(sv.dot_internal(S[i].g.get(), S[i].g.get()));
   }
-  // one graph with every subject's Hessian matvec (p in dvbl_, H p in hbl_); eager while profiling.
-  // The subjects are independent, so their matvecs are captured as parallel branches: subject i on
-  // branch stream i mod nb, forked from and joined back into st; the GPU then overlaps the short,
-  // latency-bound kernels of different subjects instead of running B chains back to back.
-  hipGraphExec_t exec = nullptr;
-  const bool use_graph = !prof::enabled();
-  if (use_graph) {
-    const int nb = std::min(B, 8);
-    struct Branches {
-      std::vector<hipStream_t> s;
-      std::vector<hipEvent_t> ev;  // [0] fork, [1 + j] join of branch j
-      ~Branches() {
-        for (hipStream_t x : s) (void)hipStreamDestroy(x);
-        for (hipEvent_t x : ev) (void)hipEventDestroy(x);
-      }
-    } br;
-    for (int j = 0; j < nb; ++j) {
-      hipStream_t x;
-      LDDMM_HIP(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
-      br.s.push_back(x);
+  // Every subject's Hessian matvec (p in dvbl_, H p in hbl_) per PCG iteration.  The subjects are
+  // independent, so their matvecs run as parallel branches: subject i on branch stream i mod nb,
+  // forked from and joined back into st; the GPU then overlaps the short, latency-bound kernels of
+  // different subjects instead of running B chains back to back.  The branches are captured once
+  // into a graph, or launched eagerly (while profiling, or with LDDMM_BL_NO_GRAPH set).
+  const bool use_graph = !prof::enabled() && std::getenv("LDDMM_BL_NO_GRAPH") == nullptr;
+  const int nb = std::min(B, 8);
+  struct Branches {
+    std::vector<hipStream_t> s;
+    std::vector<hipEvent_t> ev;  // [0] fork, [1 + j] join of branch j
+    ~Branches() {
+      for (hipStream_t x : s) (void)hipStreamDestroy(x);
+      for (hipEvent_t x : ev) (void)hipEventDestroy(x);
     }
-    for (int j = 0; j <= nb; ++j) {
-      hipEvent_t x;
-      LDDMM_HIP(hipEventCreateWithFlags(&x, hipEventDisableTiming));
-      br.ev.push_back(x);
-    }
-    std::vector<hipStream_t> own(B);
-    for (int i = 0; i < B; ++i) own[i] = subs[i]->st_;
-    auto restore = [&] {
-      for (int i = 0; i < B; ++i) subs[i]->st_ = own[i];
-    };
-    hipGraph_t graph = nullptr;
-    LDDMM_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  } br;
+  for (int j = 0; j < nb; ++j) {
+    hipStream_t x;
+    LDDMM_HIP(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+    br.s.push_back(x);
+  }
+  for (int j = 0; j <= nb; ++j) {
+    hipEvent_t x;
+    LDDMM_HIP(hipEventCreateWithFlags(&x, hipEventDisableTiming));
+    br.ev.push_back(x);
+  }
+  std::vector<hipStream_t> own(B);
+  for (int i = 0; i < B; ++i) own[i] = subs[i]->st_;
+  auto restore = [&] {
+    for (int i = 0; i < B; ++i) subs[i]->st_ = own[i];
+  };
+  auto matvecs = [&] {
     try {
       LDDMM_HIP(hipEventRecord(br.ev[0], st));
       for (int j = 0; j < nb; ++j) LDDMM_HIP(hipStreamWaitEvent(br.s[j], br.ev[0], 0));
@@ -1203,6 +1201,16 @@ int gn_solve_batched_impl(std::vector<Solver<T>*>& subs, const lddmm_bl_gn_opts&
       }
     } catch (...) {
       restore();
+      throw;
+    }
+  };
+  hipGraphExec_t exec = nullptr;
+  if (use_graph) {
+    hipGraph_t graph = nullptr;
+    LDDMM_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    try {
+      matvecs();
+    } catch (...) {
       (void)hipStreamEndCapture(st, &graph);
       if (graph) (void)hipGraphDestroy(graph);
       throw;
@@ -1258,11 +1266,10 @@ int gn_solve_batched_impl(std::vector<Solver<T>*>& subs, const lddmm_bl_gn_opts&
         iterate = true;
       }
       if (!iterate) break;
-      if (use_graph) {
+      if (use_graph)
         LDDMM_HIP(hipGraphLaunch(exec, st));
-      } else {
-        for (int i = 0; i < B; ++i) subs[i]->run_matvec(subs[i]->dvbl_.get(), subs[i]->hbl_.get());
-      }
+      else
+        matvecs();
       for (int i = 0; i < B; ++i) {
         Sub& u = S[i];
         Solver<T>& sv = *subs[i];
