@@ -166,5 +166,15 @@ template <typename T>
 double sym_dot(const T* x, const T* y, const double* sym, int ncomp, int64_t Q, double* work,
                double* host_pinned, hipStream_t s);
 void minmax_f64(const double* a, int64_t n, double* work, double* host_pinned2, hipStream_t s);
+// Asynchronous forms: the result stays in result slot `slot` (0..7) of `work` until fetch_async
+// copies slots 0 .. count-1 into pinned host memory on the stream; the values are valid once the
+// stream has been synchronised.
+enum class RedKind { Dot, SqDiff, MaxAbs };
+template <typename T>
+void reduce_launch(RedKind kind, const T* a, const T* b, int64_t n, double* work, int slot, hipStream_t s);
+template <typename T>
+void sym_dot_launch(const T* x, const T* y, const double* sym, int ncomp, int64_t Q, double* work, int slot,
+                    hipStream_t s);
+void fetch_async(double* work, double* host_pinned, int count, hipStream_t s);
 
 }  // namespace lddmm

@@ -133,6 +133,39 @@ void minmax_f64(const double* a, int64_t n, double* work, double* host2, hipStre
   fetch(work, host2, 2, s);
 }
 
+template <typename T>
+void reduce_launch(RedKind kind, const T* a, const T* b, int64_t n, double* work, int slot, hipStream_t s) {
+  if (slot < 0 || slot >= 8) throw ArgError("reduce_launch: result slot out of range");
+  switch (kind) {
+    case RedKind::Dot:
+      launch<T, Kind::Dot>(a, b, nullptr, 1, n, work, s, slot);
+      break;
+    case RedKind::SqDiff:
+      launch<T, Kind::SqDiff>(a, b, nullptr, 1, n, work, s, slot);
+      break;
+    case RedKind::MaxAbs:
+      launch<T, Kind::MaxAbs>(a, nullptr, nullptr, 1, n, work, s, slot);
+      break;
+  }
+}
+
+template <typename T>
+void sym_dot_launch(const T* x, const T* y, const double* sym, int ncomp, int64_t Q, double* work, int slot,
+                    hipStream_t s) {
+  if (slot < 0 || slot >= 8) throw ArgError("sym_dot_launch: result slot out of range");
+  launch<T, Kind::SymDot>(x, y, sym, Q, Q * ncomp, work, s, slot);
+}
+
+void fetch_async(double* work, double* host, int count, hipStream_t s) {
+  LDDMM_HIP(hipMemcpyAsync(host, work + kRBlocks, count * sizeof(double), hipMemcpyDeviceToHost, s));
+}
+
+template void reduce_launch<float>(RedKind, const float*, const float*, int64_t, double*, int, hipStream_t);
+template void reduce_launch<double>(RedKind, const double*, const double*, int64_t, double*, int, hipStream_t);
+template void sym_dot_launch<float>(const float*, const float*, const double*, int, int64_t, double*, int,
+                                    hipStream_t);
+template void sym_dot_launch<double>(const double*, const double*, const double*, int, int64_t, double*, int,
+                                     hipStream_t);
 template double dot<float>(const float*, const float*, int64_t, double*, double*, hipStream_t);
 template double dot<double>(const double*, const double*, int64_t, double*, double*, hipStream_t);
 template double sqdiff<float>(const float*, const float*, int64_t, double*, double*, hipStream_t);

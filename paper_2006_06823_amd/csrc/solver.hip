@@ -23,6 +23,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <type_traits>
 
 #include "prof.h"
@@ -562,11 +563,14 @@ class Solver final : public SolverBase {
 
   // ---------------------------------------------- per-velocity set-up (Section 3.1)
   void setup_velocity() {
-    const int64_t Q = d_.Q, P = d_.P;
     // a non-finite coefficient would turn into non-finite departure points; reject it before any
     // interpolation runs
-    if (!std::isfinite(maxabs<T>(vbl_.get(), 3 * Q, work_.get(), host_.get(), st_)))
+    if (!std::isfinite(maxabs<T>(vbl_.get(), 3 * d_.Q, work_.get(), host_.get(), st_)))
       throw NonFiniteError("velocity has non-finite coefficients");
+    setup_velocity_body();
+  }
+  void setup_velocity_body() {
+    const int64_t Q = d_.Q, P = d_.P;
     // velocity samples and the B-spline coefficients of the velocity in one 6-field transform
     copy(stk_.get(), vbl_.get(), 3 * Q);
     copy(stk_.get() + 3 * Q, vbl_.get(), 3 * Q);
@@ -605,6 +609,48 @@ class Solver final : public SolverBase {
     std::memcpy(last_e_, e, sizeof(last_e_));
     state_valid_ = true;
   }
+  // ---- split forms for the batched solver: launched without a host synchronisation and finished
+  // once the stream has been synchronised (pinned result slots: 0 velocity check, 1 data term,
+  // 2 regulariser, 3 gradient sup-norm, 4 squared gradient norm); the same arithmetic as
+  // setup_velocity / finish_objective / grad_inf / dot_internal
+  void check_launch(const T* v) {
+    reduce_launch<T>(RedKind::MaxAbs, v, nullptr, 3 * d_.Q, work_.get(), 0, st_);
+    fetch_async(work_.get(), host_.get(), 1, st_);
+  }
+  bool check_ok() const { return std::isfinite(host_.get()[0]); }
+  void state_launch(const T* v) {  // v has passed check_launch / check_ok
+    state_valid_ = false;
+    copy(vbl_.get(), v, 3 * d_.Q);
+    setup_velocity_body();
+    if (variant_ == LDDMM_BL_IMAGE_TRANSPORT)
+      state_v1();
+    else
+      state_v3();
+    reduce_launch<T>(RedKind::SqDiff, m1_ptr(), I1_.get(), d_.P, work_.get(), 1, st_);
+    sym_dot_launch<T>(vbl_.get(), vbl_.get(), Lsym_.get(), 3, d_.Q, work_.get(), 2, st_);
+    fetch_async(work_.get(), host_.get(), 3, st_);
+  }
+  void state_finish(double e[3]) {
+    const double* h = host_.get();
+    const double data = h[1] / d_.P / sigma2_;
+    const double reg = 0.5 * h[2];
+    e[0] = reg + data;
+    e[1] = reg;
+    e[2] = data;
+    if (!std::isfinite(e[0])) throw NonFiniteError("objective is not finite");
+    std::memcpy(last_e_, e, sizeof(last_e_));
+    state_valid_ = true;
+  }
+  void adjoint_launch(T* g) {
+    run_adjoint(g);
+    iota_kind(g, S(0), 3, kPlain);
+    reduce_launch<T>(RedKind::MaxAbs, S(0), nullptr, 3 * d_.P, work_.get(), 3, st_);
+    reduce_launch<T>(RedKind::Dot, g, g, 3 * d_.Q, work_.get(), 4, st_);
+    fetch_async(work_.get(), host_.get(), 5, st_);
+  }
+  double launched_ginf() const { return host_.get()[3]; }
+  double launched_gnorm2() const { return host_.get()[4]; }
+
   // true when the held state was solved at exactly the internal velocity v (tmp: scratch of v's size)
   bool state_is_at(const T* v, T* tmp) {
     if (!state_valid_) return false;
@@ -1144,24 +1190,16 @@ int gn_solve_batched_impl(std::vector<Solver<T>*>& subs, const lddmm_bl_gn_opts&
   for (int i = 0; i < B; ++i) {
     Solver<T>& sv = *subs[i];
     if (!sv.have_images_) throw StateError("set_images must precede the batched solve");
+    if (sv.st_ != st) throw ArgError("the batched subjects must share the batch's stream");
     const int64_t n = sv.vec_len();
     S[i].v.alloc(n), S[i].g.alloc(n), S[i].x.alloc(n), S[i].r.alloc(n), S[i].z.alloc(n), S[i].vt.alloc(n);
     sv.user_to_internal(S[i].v.get(), static_cast<const T*>(v_user[i]));
-    sv.set_velocity_internal(S[i].v.get());
-    double e[3];
-    sv.state_internal(e);
-    S[i].E = S[i].R.E0 = e[0];
-    sv.adjoint_internal(S[i].g.get());
-    S[i].ginf = sv.grad_inf_internal(S[i].g.get());
-    S[i].ref = o.grad_ref_inf > 0 ? o.grad_ref_inf : S[i].ginf;
-    S[i].gnorm0 = std::sqrt(sv.dot_internal(S[i].g.get(), S[i].g.get()));
   }
-  // Every subject's Hessian matvec (p in dvbl_, H p in hbl_) per PCG iteration.  The subjects are
-  // independent, so their matvecs run as parallel branches: subject i on branch stream i mod nb,
-  // forked from and joined back into st; the GPU then overlaps the short, latency-bound kernels of
-  // different subjects instead of running B chains back to back.  The branches are captured once
-  // into a graph, or launched eagerly (while profiling, or with LDDMM_BL_NO_GRAPH set).
-  const bool use_graph = !prof::enabled() && std::getenv("LDDMM_BL_NO_GRAPH") == nullptr;
+  // The subjects are independent, so their solves and matvecs run as parallel branches: subject i
+  // on branch stream i mod nb, forked from and joined back into st; the GPU then overlaps the
+  // short, latency-bound kernels of different subjects instead of running B chains back to back.
+  // Scalars (objectives, gradient norms) come back through pinned memory after one synchronisation
+  // per phase instead of one per subject and reduction.
   const int nb = std::min(B, 8);
   struct Branches {
     std::vector<hipStream_t> s;
@@ -1186,13 +1224,15 @@ int gn_solve_batched_impl(std::vector<Solver<T>*>& subs, const lddmm_bl_gn_opts&
   auto restore = [&] {
     for (int i = 0; i < B; ++i) subs[i]->st_ = own[i];
   };
-  auto matvecs = [&] {
+  // runs fn(i) for the listed subjects on the branches
+  auto on_branches = [&](const std::vector<int>& who, const std::function<void(int)>& fn) {
     try {
       LDDMM_HIP(hipEventRecord(br.ev[0], st));
       for (int j = 0; j < nb; ++j) LDDMM_HIP(hipStreamWaitEvent(br.s[j], br.ev[0], 0));
-      for (int i = 0; i < B; ++i) {
-        subs[i]->st_ = br.s[i % nb];
-        subs[i]->run_matvec(subs[i]->dvbl_.get(), subs[i]->hbl_.get());
+      int k = 0;
+      for (int i : who) {
+        subs[i]->st_ = br.s[k++ % nb];
+        fn(i);
       }
       restore();
       for (int j = 0; j < nb; ++j) {
@@ -1204,6 +1244,32 @@ int gn_solve_batched_impl(std::vector<Solver<T>*>& subs, const lddmm_bl_gn_opts&
       throw;
     }
   };
+  auto sync_st = [&] { LDDMM_HIP(hipStreamSynchronize(st)); };
+  std::vector<int> all(B);
+  for (int i = 0; i < B; ++i) all[i] = i;
+  // velocity checks (a non-finite velocity never reaches an interpolation), then every subject's
+  // state and adjoint solve
+  for (int i = 0; i < B; ++i) subs[i]->check_launch(S[i].v.get());
+  sync_st();
+  for (int i = 0; i < B; ++i)
+    if (!subs[i]->check_ok()) throw NonFiniteError("velocity has non-finite coefficients");
+  on_branches(all, [&](int i) {
+    subs[i]->state_launch(S[i].v.get());
+    subs[i]->adjoint_launch(S[i].g.get());
+  });
+  sync_st();
+  for (int i = 0; i < B; ++i) {
+    double e[3];
+    subs[i]->state_finish(e);
+    S[i].E = S[i].R.E0 = e[0];
+    S[i].ginf = subs[i]->launched_ginf();
+    S[i].ref = o.grad_ref_inf > 0 ? o.grad_ref_inf : S[i].ginf;
+    S[i].gnorm0 = std::sqrt(subs[i]->launched_gnorm2());
+  }
+  // Every subject's Hessian matvec (p in dvbl_, H p in hbl_) per PCG iteration, captured once into a
+  // graph, or launched eagerly (while profiling, or with LDDMM_BL_NO_GRAPH set)
+  const bool use_graph = !prof::enabled() && std::getenv("LDDMM_BL_NO_GRAPH") == nullptr;
+  auto matvecs = [&] { on_branches(all, [&](int i) { subs[i]->run_matvec(subs[i]->dvbl_.get(), subs[i]->hbl_.get()); }); };
   hipGraphExec_t exec = nullptr;
   if (use_graph) {
     hipGraph_t graph = nullptr;
@@ -1295,37 +1361,53 @@ int gn_solve_batched_impl(std::vector<Solver<T>*>& subs, const lddmm_bl_gn_opts&
         u.rz = rz_new;
       }
     }
-    // Armijo line search per subject
+    // Armijo line search, every subject's trial state of a backtracking round in parallel
+    std::vector<int> pending, accepted;
+    std::vector<double> gd(B, 0.0), eps(B, 1.0);
     for (int i = 0; i < B; ++i) {
-      Sub& u = S[i];
-      Solver<T>& sv = *subs[i];
-      if (u.failed || u.converged) continue;
-      const double gd = sv.dot_internal(u.g.get(), u.x.get());
-      double eps = 1.0, Et = u.E, e[3];
-      bool accepted = false;
-      for (int bt = 0; bt <= 10; ++bt) {
-        sv.axpby_internal(u.vt.get(), T(1), u.v.get(), T(eps), u.x.get());
-        sv.set_velocity_internal(u.vt.get());
-        sv.state_internal(e);
-        Et = e[0];
-        if (Et <= u.E + 1e-4 * eps * gd) {
-          accepted = true;
-          break;
+      if (S[i].failed || S[i].converged) continue;
+      gd[i] = subs[i]->dot_internal(S[i].g.get(), S[i].x.get());
+      pending.push_back(i);
+    }
+    for (int bt = 0; bt <= 10 && !pending.empty(); ++bt) {
+      for (int i : pending) {
+        subs[i]->axpby_internal(S[i].vt.get(), T(1), S[i].v.get(), T(eps[i]), S[i].x.get());
+        subs[i]->check_launch(S[i].vt.get());
+      }
+      sync_st();
+      for (int i : pending)
+        if (!subs[i]->check_ok()) throw NonFiniteError("velocity has non-finite coefficients");
+      on_branches(pending, [&](int i) { subs[i]->state_launch(S[i].vt.get()); });
+      sync_st();
+      std::vector<int> next;
+      for (int i : pending) {
+        double e[3];
+        subs[i]->state_finish(e);
+        if (e[0] <= S[i].E + 1e-4 * eps[i] * gd[i]) {
+          subs[i]->copy_internal(S[i].v.get(), S[i].vt.get());
+          S[i].E = e[0];
+          accepted.push_back(i);
+        } else {
+          ++S[i].R.backtracks;
+          eps[i] *= 0.5;
+          next.push_back(i);
         }
-        ++u.R.backtracks;
-        eps *= 0.5;
       }
-      if (!accepted) {
-        sv.set_velocity_internal(u.v.get());
-        sv.state_internal(e);
-        u.failed = true;
-        continue;
-      }
-      sv.copy_internal(u.v.get(), u.vt.get());
-      u.E = Et;
-      sv.adjoint_internal(u.g.get());
-      u.ginf = sv.grad_inf_internal(u.g.get());
-      u.R.gn_iters = k + 1;
+      pending.swap(next);
+    }
+    // no acceptable step: back to the last velocity's state
+    for (int i : pending) {
+      double e[3];
+      subs[i]->set_velocity_internal(S[i].v.get());
+      subs[i]->state_internal(e);
+      S[i].failed = true;
+    }
+    // new gradients of the subjects that moved
+    on_branches(accepted, [&](int i) { subs[i]->adjoint_launch(S[i].g.get()); });
+    sync_st();
+    for (int i : accepted) {
+      S[i].ginf = subs[i]->launched_ginf();
+      S[i].R.gn_iters = k + 1;
     }
   }
   int status = LDDMM_BL_OK;
