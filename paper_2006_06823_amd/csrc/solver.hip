@@ -1187,6 +1187,12 @@ int gn_solve_batched_impl(std::vector<Solver<T>*>& subs, const lddmm_bl_gn_opts&
   };
   std::vector<Sub> S(B);
   const bool fixed = o.fixed_iters != 0;
+  const bool trace = std::getenv("LDDMM_BL_TRACE") != nullptr;
+  auto mark = [&](const char* what) {  // phase timings to stderr with LDDMM_BL_TRACE
+    if (trace)
+      fprintf(stderr, "[lddmm_bl] batched %s at %.3f s\n", what,
+              std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+  };
   for (int i = 0; i < B; ++i) {
     Solver<T>& sv = *subs[i];
     if (!sv.have_images_) throw StateError("set_images must precede the batched solve");
@@ -1266,6 +1272,7 @@ int gn_solve_batched_impl(std::vector<Solver<T>*>& subs, const lddmm_bl_gn_opts&
     S[i].ref = o.grad_ref_inf > 0 ? o.grad_ref_inf : S[i].ginf;
     S[i].gnorm0 = std::sqrt(subs[i]->launched_gnorm2());
   }
+  mark("initial solves done");
   // Every subject's Hessian matvec (p in dvbl_, H p in hbl_) per PCG iteration, captured once into a
   // graph, or launched eagerly (while profiling, or with LDDMM_BL_NO_GRAPH set)
   const bool use_graph = !prof::enabled() && std::getenv("LDDMM_BL_NO_GRAPH") == nullptr;
@@ -1286,6 +1293,7 @@ int gn_solve_batched_impl(std::vector<Solver<T>*>& subs, const lddmm_bl_gn_opts&
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess) throw HipError(std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
   }
+  mark("matvec graph ready");
   struct ExecGuard {
     hipGraphExec_t e;
     ~ExecGuard() {
@@ -1361,6 +1369,7 @@ int gn_solve_batched_impl(std::vector<Solver<T>*>& subs, const lddmm_bl_gn_opts&
         u.rz = rz_new;
       }
     }
+    mark("PCG done");
     // Armijo line search, every subject's trial state of a backtracking round in parallel
     std::vector<int> pending, accepted;
     std::vector<double> gd(B, 0.0), eps(B, 1.0);
@@ -1409,6 +1418,7 @@ int gn_solve_batched_impl(std::vector<Solver<T>*>& subs, const lddmm_bl_gn_opts&
       S[i].ginf = subs[i]->launched_ginf();
       S[i].R.gn_iters = k + 1;
     }
+    mark("line search and gradients done");
   }
   int status = LDDMM_BL_OK;
   for (int i = 0; i < B; ++i) {
