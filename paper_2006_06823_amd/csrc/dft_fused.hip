@@ -98,12 +98,32 @@ __global__ __launch_bounds__(256) void k_iota_ab(IotaABArgs a, int xc) {
     f32x16 acc;
     zero16(acc);
     const int arow = mb * 32 + li, xl = cb * 32 + li;
+    if constexpr (STAGE_W2) {
 #pragma unroll 4
-    for (int kk = 0; kk < k2; kk += 2) {
-      const int l = kk + kh;
-      const float av = (arow < k1 && l < k2) ? S[arow * lds + l] : 0.f;
-      const float bv = (xl < ncol && l < k2) ? W2[l * ld2 + xl] : 0.f;
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
+      for (int kk = 0; kk < k2; kk += 2) {
+        const int l = kk + kh;
+        const float av = (arow < k1 && l < k2) ? S[arow * lds + l] : 0.f;
+        const float bv = (xl < ncol && l < k2) ? W2[l * ld2 + xl] : 0.f;
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
+      }
+    } else {
+      // W2 read from global memory: every k-step's operand requested before the first product
+      // (k2 <= 64: at most 32 steps; 32-bit offsets, out-of-range entries read a valid element)
+      float bq[kMaxK / 2];
+#pragma unroll
+      for (int j = 0; j < kMaxK / 2; ++j) {
+        const int l = 2 * j + kh;
+        const bool ok = xl < ncol && l < k2;
+        const float t = W2[ok ? l * ld2 + xl : 0];
+        bq[j] = ok ? t : 0.f;
+      }
+#pragma unroll
+      for (int j = 0; j < kMaxK / 2; ++j) {
+        if (2 * j >= k2) break;
+        const int l = 2 * j + kh;
+        const float av = (arow < k1 && l < k2) ? S[arow * lds + l] : 0.f;
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bq[j], acc, 0, 0, 0);
+      }
     }
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
