@@ -193,12 +193,35 @@ __global__ __launch_bounds__(256) void k_pi_ba(PiBAArgs a) {
     const int lb = part * seg, le = min(n2, lb + seg);
     f32x16 acc;
     zero16(acc);
+    if constexpr (STAGE_P) {
 #pragma unroll 4
-    for (int kk = lb; kk < le; kk += 2) {
-      const int l = kk + kh;
-      const float av = l < le ? In[li * ldi + l] : 0.f;
-      const float bv = (a2 < k2 && l < le) ? P2t[l * k2 + a2] : 0.f;
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
+      for (int kk = lb; kk < le; kk += 2) {
+        const int l = kk + kh;
+        const float av = l < le ? In[li * ldi + l] : 0.f;
+        const float bv = (a2 < k2 && l < le) ? P2t[l * k2 + a2] : 0.f;
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
+      }
+    } else {
+      // P2 from global memory: the operands of up to kPreP k-steps requested at a time, before
+      // their products (32-bit offsets; out-of-range entries read a valid element and are zeroed)
+      constexpr int kPreP = 16;
+      for (int kb = lb; kb < le; kb += 2 * kPreP) {
+        float bq[kPreP];
+#pragma unroll
+        for (int j = 0; j < kPreP; ++j) {
+          const int l = kb + 2 * j + kh;
+          const bool ok = a2 < k2 && l < le;
+          const float t = P2t[ok ? l * k2 + a2 : 0];
+          bq[j] = ok ? t : 0.f;
+        }
+#pragma unroll
+        for (int j = 0; j < kPreP; ++j) {
+          const int l = kb + 2 * j + kh;
+          if (kb + 2 * j >= le) break;
+          const float av = l < le ? In[li * ldi + l] : 0.f;
+          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bq[j], acc, 0, 0, 0);
+        }
+      }
     }
     __syncthreads();  // every wave is done reading In before R overwrites it
 #pragma unroll
@@ -221,18 +244,30 @@ __global__ __launch_bounds__(256) void k_pi_ba(PiBAArgs a) {
     const int a1 = mb * 32 + li, a2 = cb * 32 + li;
     f32x16 acc;
     zero16(acc);
+    if constexpr (STAGE_P) {
 #pragma unroll 4
-    for (int kk = 0; kk < kRows; kk += 2) {
-      const int l = kk + kh;
-      float av = 0.f;
-      if (a1 < k1) {
-        if (STAGE_P)
-          av = P1s[l * k1 + a1];
-        else if (x1b + l < n1)
-          av = a.p1t[(int64_t)(x1b + l) * k1 + a1];
+      for (int kk = 0; kk < kRows; kk += 2) {
+        const int l = kk + kh;
+        const float av = a1 < k1 ? P1s[l * k1 + a1] : 0.f;
+        const float bv = a2 < k2 ? U[l * ldu + a2] : 0.f;
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
       }
-      const float bv = a2 < k2 ? U[l * ldu + a2] : 0.f;
-      acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
+    } else {
+      // P1 rows from global memory, all 16 k-steps' operands requested before the first product
+      float aq[kRows / 2];
+#pragma unroll
+      for (int j = 0; j < kRows / 2; ++j) {
+        const int l = 2 * j + kh;
+        const bool ok = a1 < k1 && x1b + l < n1;
+        const float t = a.p1t[ok ? (x1b + l) * k1 + a1 : 0];
+        aq[j] = ok ? t : 0.f;
+      }
+#pragma unroll
+      for (int j = 0; j < kRows / 2; ++j) {
+        const int l = 2 * j + kh;
+        const float bv = a2 < k2 ? U[l * ldu + a2] : 0.f;
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(aq[j], bv, acc, 0, 0, 0);
+      }
     }
     if (a2 < k2) {
 #pragma unroll

@@ -48,6 +48,9 @@ DFT_CASES = CASES + [
     (3, (100, 20, 70), (24, 12, 30), 4, L.FP32),
     # an inner axis longer than the fused inner-axis kernels take (192): the separable float path
     (3, (20, 24, 200), (8, 10, 36), 2, L.FP32),
+    # inner-axis matrices too large to stage in 64 KB of LDS: the fused kernels read them from global
+    # memory (the projection for every field count, the expansion for 7 fields)
+    (3, (40, 72, 192), (16, 48, 48), 2, L.FP32),
 ]
 
 
