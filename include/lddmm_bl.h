@@ -148,9 +148,11 @@ lddmm_bl_status lddmm_bl_gn_solve(lddmm_bl_ctx* ctx, const lddmm_bl_gn_opts* opt
 
 /* Batched Gauss-Newton-Krylov: `count` independent registrations (subjects with
  * their own grid and band, per_subject[i]; FP32 or BF16_DFT precision) run in
- * lockstep on one stream.  In every PCG iteration the Hessian matvecs of all
- * subjects are replayed as one HIP graph launch; PCG scalars, Armijo line
- * searches and stopping tests stay per subject.  I0[i], I1[i], v_bl_inout[i]:
+ * lockstep, ordered on hip_stream.  The subjects' solves, line-search trials and
+ * Hessian matvecs run as parallel branches on up to 8 internal streams forked from
+ * and joined back into hip_stream (the matvecs of a PCG iteration as one HIP graph
+ * launch); PCG scalars, Armijo decisions and stopping tests stay per subject, and
+ * every subject computes exactly what its own gn_solve would.  I0[i], I1[i], v_bl_inout[i]:
  * device buffers of subject i (layouts as above); reports: host array of
  * `count` (may be NULL).  Returns LDDMM_BL_W_LINESEARCH if any subject's line
  * search failed (that subject's velocity is left at its last accepted value). */
