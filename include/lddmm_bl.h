@@ -151,8 +151,8 @@ lddmm_bl_status lddmm_bl_gn_solve(lddmm_bl_ctx* ctx, const lddmm_bl_gn_opts* opt
  * lockstep, ordered on hip_stream.  The subjects' solves, line-search trials and
  * Hessian matvecs run as parallel branches on up to 8 internal streams forked from
  * and joined back into hip_stream (the matvecs of a PCG iteration as one HIP graph
- * launch); PCG scalars, Armijo decisions and stopping tests stay per subject, and
- * every subject computes exactly what its own gn_solve would.  I0[i], I1[i], v_bl_inout[i]:
+ * launch); PCG scalars, Armijo decisions and stopping tests stay per subject, each
+ * subject running the steps of its own gn_solve.  I0[i], I1[i], v_bl_inout[i]:
  * device buffers of subject i (layouts as above); reports: host array of
  * `count` (may be NULL).  Returns LDDMM_BL_W_LINESEARCH if any subject's line
  * search failed (that subject's velocity is left at its last accepted value). */

@@ -40,3 +40,28 @@ def test_batched_equals_individual(variant):
         assert rel_l2(vs[i], v) <= 1e-6
         assert abs(reps[i]["E"] - rep["E"]) <= 1e-6 * abs(rep["E"])
         assert reps[i]["E"] < reps[i]["E0"]
+
+
+def test_batched_eager_branches_equal_graph(monkeypatch):
+    """More subjects than branch streams (10 over 8): the matvecs launched eagerly on the branches
+    (LDDMM_BL_NO_GRAPH) and replayed from the captured graph give bitwise the same registrations."""
+    shapes = [((24 + 4 * (i % 3), 24, 28), (8, 8, 8)) for i in range(10)]
+
+    def run():
+        probs, I0s, I1s, vs = [], [], [], []
+        for i, (N, K) in enumerate(shapes):
+            probs.append(L.Problem(N, K, nt=3, variant=L.DEFORMATION_STATE, precision=L.FP32))
+            a, b = _subject(i, N, K)
+            I0s.append(a)
+            I1s.append(b)
+            vs.append(torch.zeros((3,) + K, dtype=torch.float32, device="cuda"))
+        st, reps = L.gn_solve_batched(probs, I0s, I1s, vs, max_gn=2, max_pcg=2, fixed_iters=True)
+        return vs, reps
+
+    vg, rg = run()
+    monkeypatch.setenv("LDDMM_BL_NO_GRAPH", "1")
+    ve, re_ = run()
+    for a, b, x, y in zip(vg, ve, rg, re_):
+        assert torch.equal(a, b)
+        assert (x["E"], x["gn_iters"], x["backtracks"]) == (y["E"], y["gn_iters"], y["backtracks"])
+        assert x["E"] < x["E0"]
