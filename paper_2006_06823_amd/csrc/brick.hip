@@ -287,11 +287,12 @@ struct EpiInterp : DispPos, OneGroup<NFv> {
 };
 
 // band-limited adjoint Heun step: out_f = cA_f o X + dt/2 divv (cB_f o X)
-template <int NC>
+// FS: fields between cA_i and cB_i (NC, or 3 for one component of a three-component pair of stacks)
+template <int NC, int FS = NC>
 struct EpiBLAdjoint : DispPos {
   // fields [cA_0..cA_{NC-1}, cB_0..cB_{NC-1}], staged as the pairs (cA_i, cB_i)
   static constexpr int NF = 2 * NC, GROUPS = NC, GSIZE = 2;
-  __device__ static int field(int g, int k) { return g + k * NC; }
+  __device__ static int field(int g, int k) { return g + k * FS; }
   struct State {
     float hd, o[NC];
   };
@@ -305,7 +306,7 @@ struct EpiBLAdjoint : DispPos {
   }
   __device__ __forceinline__ void accum(State& s, int f, float v) const {
     const float w = f < NC ? v : s.hd * v;
-    const int i0 = f < NC ? f : f - NC;
+    const int i0 = f < NC ? f : f - FS;
 #pragma unroll
     for (int i = 0; i < NC; ++i) s.o[i] += (i0 == i) ? w : 0.f;
   }
@@ -526,9 +527,14 @@ void brick_bl_adjoint_step(float* out, const float* cAB, int nc, const float* di
     e.disp = disp, e.P = d.P, e.out = out, e.divv = divv, e.dt = dt;
     launch(name_, bytes_, e, cAB, d, s);
   } else if (nc == 3) {
-    EpiBLAdjoint<3> e;
-    e.disp = disp, e.P = d.P, e.out = out, e.divv = divv, e.dt = dt;
-    launch(name_, bytes_, e, cAB, d, s);
+    // one launch per component on its pair (cA_i, cB_i): a single staged pair per workgroup keeps the
+    // registers (and the occupancy) of the one-component kernel
+    const double bytes_i = 7.0 * d.P * 4;
+    for (int i = 0; i < 3; ++i) {
+      EpiBLAdjoint<1, 3> e;
+      e.disp = disp, e.P = d.P, e.out = out + i * d.P, e.divv = divv, e.dt = dt;
+      launch(name_, bytes_i, e, cAB + i * d.P, d, s);
+    }
   } else {
     throw ArgError("brick_bl_adjoint_step: nc must be 1 or 3");
   }
