@@ -555,7 +555,11 @@ void dft_left(const T* in, T* out, const FieldMats<T>& W, int nb, int bpf, int M
       const int sep = (wsz + rsz) * sizeof(float) <= 65536 ? 1 : 0;
       const uint32_t sm = (uint32_t)((sep ? wsz + rsz : std::max(wsz, rsz)) * sizeof(float));
       const int ncb = ceil_div(C, 64);
-      const int gx = sep ? std::max(1, std::min(ncb, 1024 / std::max(1, nb))) : ncb;
+      // the two-tile kernel's registers leave room for 2 blocks per CU: at most 512 blocks keeps the
+      // grid resident in one round, each block walking several column tiles with its W tile
+      // (1024 ran a second round: 160x192x160 contraction 2.10 -> 1.86 ms per matvec)
+      const int cap = MB == 2 ? 512 : 1024;
+      const int gx = sep ? std::max(1, std::min(ncb, cap / std::max(1, nb))) : ncb;
       dim3 g(gx, 1, nb);
       if (MB == 2)
         prof::launch("dft_left_contract<2>", bytes, flops, dft_left_contract<2, 2>, g, dim3(256), sm, s, in, out, W,
@@ -569,7 +573,10 @@ void dft_left(const T* in, T* out, const FieldMats<T>& W, int nb, int bpf, int M
     if (L <= 64) {
       const uint32_t sm = (uint32_t)(128 * (L + 1) + L * kExpLdb) * sizeof(float);
       const int ncb = ceil_div(C, kExpCols), gy = ceil_div(M, 128);
-      const int gx = std::max(1, std::min(ncb, 2048 / std::max(1, nb * gy)));
+      // at most 1024 blocks (4 per CU): the whole grid is resident at once and each block walks
+      // several column tiles with its W tile staged once (2048 left a second, partial round:
+      // 160x192x160 expansion 1.45 -> 1.22 ms per matvec)
+      const int gx = std::max(1, std::min(ncb, 1024 / std::max(1, nb * gy)));
       const int vec = (C % 4 == 0) && (sIb % 4 == 0) && (reinterpret_cast<uintptr_t>(in) % 16 == 0);
       dim3 g(gx, gy, nb);
       prof::launch("dft_left_expand", bytes, flops, dft_left_expand, g, dim3(256), sm, s, in, out, W, bpf, M, L, C,
