@@ -155,14 +155,14 @@ __global__ __launch_bounds__(256) void k_iota_ab(IotaABArgs a, int xc) {
   }
 }
 
-// grid (nsplit = ceil(n1 / 32), k0, nf): each block projects 32 rows of x1 of one (field, a0)
-// slab to a partial band block in the workspace; k_pi_fin then sums the partials of every slab
+// grid (nsplit = ceil(n1 / 32), <= k0, nf): each block projects 32 rows of x1 of the (field, a0)
+// slabs it walks to partial band blocks in the workspace; k_pi_fin then sums the partials of every slab
 // in split order (deterministic) and applies the epilogue.  (A last-block-done reduction inside
 // this kernel would need a device-scope release per block, which writes back the XCD's L2.)
-template <bool STAGE_P>
+template <bool STAGE_P, bool WALK>
 __global__ __launch_bounds__(256) void k_pi_ba(PiBAArgs a) {
   extern __shared__ float smem[];
-  const int sp = blockIdx.x, a0 = blockIdx.y, f = blockIdx.z, nsplit = gridDim.x;
+  const int sp = blockIdx.x, f = blockIdx.z, nsplit = gridDim.x;
   const int k0 = a.k0, k1 = a.k1, k2 = a.k2, n1 = a.n1, n2 = a.n2;
   const int x1b = sp * kRows;
   const int ldi = n2 + 1, ldu = k2 + 1;
@@ -174,109 +174,116 @@ __global__ __launch_bounds__(256) void k_pi_ba(PiBAArgs a) {
   float* P1s = P2s + n2 * k2;    // [32 rows of x1][k1] (staged)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int kh = lane >> 5, li = lane & 31;
-  const int slab = f * k0 + a0;
-  const float* __restrict__ in = a.in + (int64_t)slab * n1 * n2;
   const int vr = n1 - x1b < kRows ? n1 - x1b : kRows;
-  stage_tile<256, 16>(In, ldi, in + (int64_t)x1b * n2, n2, kRows, n2, vr, n2);
-  if (STAGE_P) {
-    stage_tile<256, 16>(P2s, k2, a.p2t, k2, n2, k2, n2, k2);
-    stage_tile<256, 4>(P1s, k1, a.p1t + (int64_t)x1b * k1, k1, kRows, k1, vr, k1);
-  }
-  __syncthreads();
   const float* P2t = STAGE_P ? P2s : a.p2t;  // [n2][k2]
-  // stage A: U[x][a2] = sum_x2 In[x][x2] P2[a2][x2]; cb2 column tiles, 4 / cb2 waves split x2
   const int cb2 = (k2 + 31) / 32, wpt = 4 / cb2;
-  {
-    const int tile = wave / wpt, part = wave - tile * wpt;
-    const int a2 = tile * 32 + li;
-    const int seg = ((n2 + 2 * wpt - 1) / (2 * wpt)) * 2;
-    const int lb = part * seg, le = min(n2, lb + seg);
-    f32x16 acc;
-    zero16(acc);
-    if constexpr (STAGE_P) {
-#pragma unroll 4
-      for (int kk = lb; kk < le; kk += 2) {
-        const int l = kk + kh;
-        const float av = l < le ? In[li * ldi + l] : 0.f;
-        const float bv = (a2 < k2 && l < le) ? P2t[l * k2 + a2] : 0.f;
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
-      }
-    } else {
-      // P2 from global memory: the operands of up to kPreP k-steps requested at a time, before
-      // their products (32-bit offsets; out-of-range entries read a valid element and are zeroed)
-      constexpr int kPreP = 16;
-      for (int kb = lb; kb < le; kb += 2 * kPreP) {
-        float bq[kPreP];
-#pragma unroll
-        for (int j = 0; j < kPreP; ++j) {
-          const int l = kb + 2 * j + kh;
-          const bool ok = a2 < k2 && l < le;
-          const float t = P2t[ok ? l * k2 + a2 : 0];
-          bq[j] = ok ? t : 0.f;
-        }
-#pragma unroll
-        for (int j = 0; j < kPreP; ++j) {
-          const int l = kb + 2 * j + kh;
-          if (kb + 2 * j >= le) break;
-          const float av = l < le ? In[li * ldi + l] : 0.f;
-          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bq[j], acc, 0, 0, 0);
-        }
-      }
-    }
-    __syncthreads();  // every wave is done reading In before R overwrites it
-#pragma unroll
-    for (int r = 0; r < 16; ++r) R[wave * 1024 + r * 64 + lane] = acc[r];
-  }
-  __syncthreads();
-  for (TileWalk e(256, tid, k2, k2, ldu); e.r < kRows; e.next()) {
-    const int x = e.r, c = e.c;
-    const int t = c >> 5, reg = ((x >> 3) << 2) + (x & 3), lanei = (c & 31) + 32 * ((x >> 2) & 1);
-    float sum = 0.f;
-    for (int w = 0; w < wpt; ++w) sum += R[(t * wpt + w) * 1024 + reg * 64 + lanei];
-    U[e.o2] = sum;
-  }
-  __syncthreads();
-  // stage B: partial r[a1][a2] = sum_{x < 32} P1[a1][x1b + x] U[x][a2], one wave per 32x32 tile
   const int mb2 = (k1 + 31) / 32;
-  float* part = a.part + ((int64_t)slab * nsplit + sp) * k1 * k2;
-  if (wave < mb2 * cb2) {
-    const int mb = wave / cb2, cb = wave - mb * cb2;
-    const int a1 = mb * 32 + li, a2 = cb * 32 + li;
-    f32x16 acc;
-    zero16(acc);
-    if constexpr (STAGE_P) {
+  // WALK: the block walks the slabs a0 = blockIdx.y + j gridDim.y with the operands staged once;
+  // otherwise it takes the one slab a0 = blockIdx.y (a separate instance: the loop costs registers)
+  const int nwalk = WALK ? (k0 - (int)blockIdx.y + (int)gridDim.y - 1) / (int)gridDim.y : 1;
+  for (int j = 0; j < nwalk; ++j) {
+    const int a0 = blockIdx.y + j * gridDim.y;
+    const int slab = f * k0 + a0;
+    const float* __restrict__ in = a.in + (int64_t)slab * n1 * n2;
+    if (WALK && j > 0) __syncthreads();  // the previous slab's reads of U are done
+    stage_tile<256, 16>(In, ldi, in + (int64_t)x1b * n2, n2, kRows, n2, vr, n2);
+    if (STAGE_P && j == 0) {
+      stage_tile<256, 16>(P2s, k2, a.p2t, k2, n2, k2, n2, k2);
+      stage_tile<256, 4>(P1s, k1, a.p1t + (int64_t)x1b * k1, k1, kRows, k1, vr, k1);
+    }
+    __syncthreads();
+    // stage A: U[x][a2] = sum_x2 In[x][x2] P2[a2][x2]; cb2 column tiles, 4 / cb2 waves split x2
+    {
+      const int tile = wave / wpt, part = wave - tile * wpt;
+      const int a2 = tile * 32 + li;
+      const int seg = ((n2 + 2 * wpt - 1) / (2 * wpt)) * 2;
+      const int lb = part * seg, le = min(n2, lb + seg);
+      f32x16 acc;
+      zero16(acc);
+      if constexpr (STAGE_P) {
 #pragma unroll 4
-      for (int kk = 0; kk < kRows; kk += 2) {
-        const int l = kk + kh;
-        const float av = a1 < k1 ? P1s[l * k1 + a1] : 0.f;
-        const float bv = a2 < k2 ? U[l * ldu + a2] : 0.f;
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
-      }
-    } else {
-      // P1 rows from global memory, all 16 k-steps' operands requested before the first product
-      float aq[kRows / 2];
+        for (int kk = lb; kk < le; kk += 2) {
+          const int l = kk + kh;
+          const float av = l < le ? In[li * ldi + l] : 0.f;
+          const float bv = (a2 < k2 && l < le) ? P2t[l * k2 + a2] : 0.f;
+          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
+        }
+      } else {
+        // P2 from global memory: the operands of up to kPreP k-steps requested at a time, before
+        // their products (32-bit offsets; out-of-range entries read a valid element and are zeroed)
+        constexpr int kPreP = 16;
+        for (int kb = lb; kb < le; kb += 2 * kPreP) {
+          float bq[kPreP];
 #pragma unroll
-      for (int j = 0; j < kRows / 2; ++j) {
-        const int l = 2 * j + kh;
-        const bool ok = a1 < k1 && x1b + l < n1;
-        const float t = a.p1t[ok ? (x1b + l) * k1 + a1 : 0];
-        aq[j] = ok ? t : 0.f;
-      }
+          for (int j = 0; j < kPreP; ++j) {
+            const int l = kb + 2 * j + kh;
+            const bool ok = a2 < k2 && l < le;
+            const float t = P2t[ok ? l * k2 + a2 : 0];
+            bq[j] = ok ? t : 0.f;
+          }
 #pragma unroll
-      for (int j = 0; j < kRows / 2; ++j) {
-        const int l = 2 * j + kh;
-        const float bv = a2 < k2 ? U[l * ldu + a2] : 0.f;
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(aq[j], bv, acc, 0, 0, 0);
+          for (int j = 0; j < kPreP; ++j) {
+            const int l = kb + 2 * j + kh;
+            if (kb + 2 * j >= le) break;
+            const float av = l < le ? In[li * ldi + l] : 0.f;
+            acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bq[j], acc, 0, 0, 0);
+          }
+        }
+      }
+      __syncthreads();  // every wave is done reading In before R overwrites it
+#pragma unroll
+      for (int r = 0; r < 16; ++r) R[wave * 1024 + r * 64 + lane] = acc[r];
+    }
+    __syncthreads();
+    for (TileWalk e(256, tid, k2, k2, ldu); e.r < kRows; e.next()) {
+      const int x = e.r, c = e.c;
+      const int t = c >> 5, reg = ((x >> 3) << 2) + (x & 3), lanei = (c & 31) + 32 * ((x >> 2) & 1);
+      float sum = 0.f;
+      for (int w = 0; w < wpt; ++w) sum += R[(t * wpt + w) * 1024 + reg * 64 + lanei];
+      U[e.o2] = sum;
+    }
+    __syncthreads();
+    // stage B: partial r[a1][a2] = sum_{x < 32} P1[a1][x1b + x] U[x][a2], one wave per 32x32 tile
+    float* part = a.part + ((int64_t)slab * nsplit + sp) * k1 * k2;
+    if (wave < mb2 * cb2) {
+      const int mb = wave / cb2, cb = wave - mb * cb2;
+      const int a1 = mb * 32 + li, a2 = cb * 32 + li;
+      f32x16 acc;
+      zero16(acc);
+      if constexpr (STAGE_P) {
+#pragma unroll 4
+        for (int kk = 0; kk < kRows; kk += 2) {
+          const int l = kk + kh;
+          const float av = a1 < k1 ? P1s[l * k1 + a1] : 0.f;
+          const float bv = a2 < k2 ? U[l * ldu + a2] : 0.f;
+          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
+        }
+      } else {
+        // P1 rows from global memory, all 16 k-steps' operands requested before the first product
+        float aq[kRows / 2];
+#pragma unroll
+        for (int j = 0; j < kRows / 2; ++j) {
+          const int l = 2 * j + kh;
+          const bool ok = a1 < k1 && x1b + l < n1;
+          const float t = a.p1t[ok ? (x1b + l) * k1 + a1 : 0];
+          aq[j] = ok ? t : 0.f;
+        }
+#pragma unroll
+        for (int j = 0; j < kRows / 2; ++j) {
+          const int l = 2 * j + kh;
+          const float bv = a2 < k2 ? U[l * ldu + a2] : 0.f;
+          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(aq[j], bv, acc, 0, 0, 0);
+        }
+      }
+      if (a2 < k2) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int row = mb * 32 + acc_row(r, lane);
+          if (row < k1) part[row * k2 + a2] = acc[r];
+        }
       }
     }
-    if (a2 < k2) {
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int row = mb * 32 + acc_row(r, lane);
-        if (row < k1) part[row * k2 + a2] = acc[r];
-      }
-    }
-  }
+  }  // slabs
 }
 
 // out[f][a0][:] = beta out + alpha * sum_q part[f][a0][q][:], one thread per band coefficient
@@ -326,13 +333,21 @@ void pi_ba(const PiBAArgs& a, int nf, hipStream_t s) {
   const double flops = 2.0 * nf * a.k0 * ((double)a.k2 * a.n1 * a.n2 + (double)a.k1 * a.n1 * a.k2);
   if (!a.part) throw ArgError("pi_ba needs its partial-sum workspace");
   const int nsplit = pi_ba_splits(a.n1);
-  dim3 g(nsplit, a.k0, nf);
   const bool stage = (size_t)pi_lds(a.k1, a.k2, a.n2, true) * sizeof(float) <= 65536;
   const uint32_t sm = (uint32_t)pi_lds(a.k1, a.k2, a.n2, stage) * sizeof(float);
-  if (stage)
-    prof::launch("k_pi_ba", bytes, flops, k_pi_ba<true>, g, dim3(256), sm, s, a);
+  // staged operands: no more workgroups than the CUs hold at once (160 KB of LDS each; the
+  // registers allow 4), every one walking the same number of slabs, since a second, partial
+  // round would stage the operands again
+  const int per_cu = std::max(1, std::min(4, (int)(163840 / sm)));
+  const int slots = std::max(1, 256 * per_cu / (nsplit * nf));
+  const int walk = stage ? ceil_div(a.k0, std::min(a.k0, slots)) : 1;
+  dim3 g(nsplit, ceil_div(a.k0, walk), nf);
+  if (walk > 1)
+    prof::launch("k_pi_ba", bytes, flops, k_pi_ba<true, true>, g, dim3(256), sm, s, a);
+  else if (stage)
+    prof::launch("k_pi_ba", bytes, flops, k_pi_ba<true, false>, g, dim3(256), sm, s, a);
   else
-    prof::launch("k_pi_ba", bytes, flops, k_pi_ba<false>, g, dim3(256), sm, s, a);
+    prof::launch("k_pi_ba", bytes, flops, k_pi_ba<false, false>, g, dim3(256), sm, s, a);
   LDDMM_LAUNCH_CHECK();
   dim3 gf(ceil_div(a.k1 * a.k2, 256), a.k0, nf);
   prof::launch("k_pi_fin", 4.0 * nf * a.k0 * a.k1 * a.k2 * (nsplit + 2.0), 0.0, k_pi_fin, gf, dim3(256), 0, s, a,
