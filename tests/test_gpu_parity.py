@@ -51,6 +51,9 @@ DFT_CASES = CASES + [
     # inner-axis matrices too large to stage in 64 KB of LDS: the fused kernels read them from global
     # memory (the projection for every field count, the expansion for 7 fields)
     (3, (40, 72, 192), (16, 48, 48), 2, L.FP32),
+    # more row splits x fields x first-axis slabs than one round of workgroups holds: with 3 and 7
+    # fields the projection's workgroups walk 2 and 3 slabs each (the last ones fewer)
+    (3, (128, 192, 64), (64, 16, 16), 2, L.FP32),
 ]
 
 
