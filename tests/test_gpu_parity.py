@@ -248,6 +248,28 @@ def test_bf16_dft_error_vs_oracle(variant):
     assert max(errs.values()) <= 5e-4
 
 
+def test_bf16_dft_parity_walking_expansion():
+    """Split-bf16 first-axis stages of pi / iota on a grid with more column tiles than one round of
+    workgroups holds: with 3 and 7 fields every expansion workgroup walks several tiles (1 field:
+    one tile each). Held to the split-bf16 bound of the test above."""
+    N, K = (80, 128, 128), (24, 16, 16)
+    ctx = L.Context(L.Problem(N, K, nt=2, precision=L.BF16_DFT))
+    rng = np.random.default_rng(8)
+    for nf in (1, 3, 7):
+        f = rng.standard_normal((nf,) + N)
+        got = ctx.project(dev(f, ctx), nf) if nf > 1 else ctx.project(dev(f[0], ctx), 1)
+        ref = sp.project(torch.tensor(f), K)
+        assert rel_l2(got.reshape(ref.shape), ref) <= 5e-4
+        c = rng.standard_normal((nf,) + K)
+        for j, k in enumerate(K):
+            sl = [slice(None)] * 4
+            sl[j + 1] = k - 1
+            c[tuple(sl)] = 0.0
+        got = ctx.include(dev(c, ctx), nf) if nf > 1 else ctx.include(dev(c[0], ctx), 1)
+        ref = sp.include(torch.tensor(c), N)
+        assert rel_l2(got.reshape(ref.shape), ref) <= 5e-4
+
+
 @pytest.mark.parametrize("dim,N,K,Nt,precision", CASES)
 def test_jacobian_parity(dim, N, K, Nt, precision):
     """det(I - D iota(u~(1))) in double on the device vs the oracle, element-wise (both variants'
