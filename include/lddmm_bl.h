@@ -39,8 +39,10 @@
  * synchronise that stream.  No exception or abort crosses the ABI.
  *
  * Errors: negative status = error (the result is not valid), positive =
- * warning with a valid result.  lddmm_bl_last_error() gives the text of the
- * last error of a context.
+ * warning with a valid result.  lddmm_bl_last_error(ctx) gives the text of the
+ * last error of a context; lddmm_bl_last_error(NULL) the text of the last error
+ * of a call on this thread that has no context (lddmm_bl_create, the batched
+ * solve, the network calls).
  */
 #ifndef LDDMM_BL_H
 #define LDDMM_BL_H
@@ -63,7 +65,8 @@ typedef enum {
   LDDMM_BL_E_STATE = -5,      /* call order: e.g. adjoint before a state solve at this velocity */
   LDDMM_BL_W_MAXITER = 1,     /* iteration cap reached before the gradient tolerance */
   LDDMM_BL_W_LINESEARCH = 2,  /* Armijo backtracking failed; velocity left unchanged */
-  LDDMM_BL_W_NEGCURV = 3      /* PCG met non-positive curvature and was truncated */
+  LDDMM_BL_W_NEGCURV = 3      /* reserved: gn_solve records a PCG truncated by non-positive curvature
+                                 per iteration in its report (log_negcurv), not in its status */
 } lddmm_bl_status;
 
 typedef enum {
@@ -100,12 +103,22 @@ typedef struct {
                              time how fast a warm-started run reaches a reference run's objective */
 } lddmm_bl_gn_opts;
 
+#define LDDMM_BL_LOG_MAX 64 /* Gauss-Newton iterations whose decisions the report records */
 typedef struct {
   int32_t gn_iters, pcg_iters_total, backtracks, hess_matvecs;
   double E0, E;           /* energy at the start and at the end */
   double mse_rel;         /* ||m(1) - I1||^2 / ||I0 - I1||^2 (Section 5.1.1) */
   double grad_inf_rel;    /* final ||g||_inf / reference */
+  double det_min, det_max; /* extrema of det(I - D iota(u~(1))) of the final map (Section 5.1.1, Tables 3-4) */
   double seconds;         /* wall time of the call */
+  /* Decisions of Gauss-Newton iteration i < min(gn_iters + 1, LDDMM_BL_LOG_MAX), the discrete
+   * branches two implementations can take differently: PCG iterations taken, the PCG exit
+   * (0 tolerance or cap, 1 non-positive curvature), and the Armijo backtracks before the
+   * accepted step (-1: no step accepted, the solve stopped there). */
+  int32_t log_count;
+  int32_t log_pcg[LDDMM_BL_LOG_MAX];
+  int32_t log_negcurv[LDDMM_BL_LOG_MAX];
+  int32_t log_backtracks[LDDMM_BL_LOG_MAX];
 } lddmm_bl_gn_report;
 
 /* Create a context for one registration problem.  hip_stream: a hipStream_t
@@ -142,7 +155,10 @@ lddmm_bl_status lddmm_bl_hess_matvec(lddmm_bl_ctx* ctx, const void* dv_bl, void*
  * [r][d][K..], the two-level preconditioner L~^{-1} + Z (Z^T H Z)^{-1} Z^T is
  * used instead.  report (host) may be NULL.  When the context holds a state
  * solve at exactly the starting velocity (a state_solve with the same values,
- * no set_images since), that state is reused instead of being solved again. */
+ * no set_images since), that state is reused instead of being solved again.
+ * Status: W_LINESEARCH when an Armijo search accepted no step (the velocity is
+ * the last accepted one), else W_MAXITER when the GN cap ended a run with
+ * tolerance exits before the tolerance was met, else OK. */
 lddmm_bl_status lddmm_bl_gn_solve(lddmm_bl_ctx* ctx, const lddmm_bl_gn_opts* opts, void* v_bl_inout,
                                   const void* precond_Z_or_null, int32_t r, lddmm_bl_gn_report* report);
 
@@ -155,7 +171,10 @@ lddmm_bl_status lddmm_bl_gn_solve(lddmm_bl_ctx* ctx, const lddmm_bl_gn_opts* opt
  * subject running the steps of its own gn_solve.  I0[i], I1[i], v_bl_inout[i]:
  * device buffers of subject i (layouts as above); reports: host array of
  * `count` (may be NULL).  Returns LDDMM_BL_W_LINESEARCH if any subject's line
- * search failed (that subject's velocity is left at its last accepted value). */
+ * search failed (that subject's velocity is left at its last accepted value).
+ * hip_stream must not be NULL (E_ARG): the matvec graph is captured on it.
+ * The Gauss-Newton status of each subject follows the rules of lddmm_bl_gn_solve
+ * through its report; the returned status is the worst of them. */
 lddmm_bl_status lddmm_bl_gn_solve_batched(const lddmm_bl_params* per_subject, int32_t count, const void* const* I0,
                                           const void* const* I1, void* const* v_bl_inout,
                                           const lddmm_bl_gn_opts* opts, void* hip_stream,
@@ -194,18 +213,25 @@ lddmm_bl_status lddmm_bl_get_field(lddmm_bl_ctx* ctx, int32_t which, int32_t ind
 lddmm_bl_status lddmm_bl_dot(lddmm_bl_ctx* ctx, const void* a, const void* b, int64_t n, double* dot);
 
 /* Learned warm start and low-rank preconditioner (a small 3D convolutional network
- * trained on registrations the method itself computes).  `levels` 3^3 convolutions
- * (padding 1, ReLU; stride 2 except the last) with channels[0..levels-1] on a
- * 2-channel input of in_size^3 voxels (the image pair, [B][2][S][S][S] float), then
- * a 1^3 head to out_channels.  The head output [B][out_channels][s][s][s],
- * s = in_size / 2^(levels-1), is read as band-limited velocity coefficients in the
- * real-basis layout (3 channels per predicted field).  Kernels: bf16 matrix-core
- * implicit-GEMM convolutions with float accumulation; float master weights; Adam.
+ * trained on registrations the method itself computes; an addition feeding the initial
+ * guess and the PCG preconditioner of eqs. BLNewton / BLKKT, Section 2.2).  `levels` 3^3
+ * convolutions (padding 1, ReLU; stride 2 except the last) with channels[0..levels-1] on
+ * a 2-channel input of in_size^3 voxels (the image pair, [B][2][S][S][S] float), then a
+ * 1^3 head to 3 (1 + rank_r) channels, rank_r in 0..16: the predicted velocity (channels
+ * 0..2) and rank_r low-rank preconditioner directions (3 channels each).  The head output
+ * [B][3 (1 + rank_r)][s][s][s], s = in_size / 2^(levels-1), holds grid samples on the
+ * coarse s^3 grid of the unit torus.  Kernels: bf16 matrix-core implicit-GEMM
+ * convolutions with float accumulation; float master weights; Adam.
  * forward keeps the activations for backward; backward accumulates parameter
  * gradients (zero_grad clears them); get copies parameters (which = 0) or their
- * gradients (which = 1) to host (nparam floats), set loads parameters from host. */
+ * gradients (which = 1) to host (nparam floats), set loads parameters from host.
+ * save writes the architecture and the float master parameters to a file (an 8-byte
+ * tag, int32 levels, channels, in_size, rank_r, int64 nparam, then the parameters);
+ * load reads such a file into a network of the same architecture (E_ARG on a
+ * mismatch or an unreadable file).  Errors of these calls are reported through
+ * lddmm_bl_last_error(NULL). */
 typedef struct lddmm_nn_ctx lddmm_nn_ctx;
-lddmm_bl_status lddmm_nn_create(int32_t levels, const int32_t* channels, int32_t in_size, int32_t out_channels,
+lddmm_bl_status lddmm_nn_create(int32_t levels, const int32_t* channels, int32_t in_size, int32_t rank_r,
                                 uint64_t seed, void* hip_stream, lddmm_nn_ctx** out);
 lddmm_bl_status lddmm_nn_info(lddmm_nn_ctx* ctx, int32_t* out_size, int32_t* out_channels, int64_t* nparam);
 lddmm_bl_status lddmm_nn_forward(lddmm_nn_ctx* ctx, const void* in, int32_t B, void* out);
@@ -214,18 +240,21 @@ lddmm_bl_status lddmm_nn_zero_grad(lddmm_nn_ctx* ctx);
 lddmm_bl_status lddmm_nn_step(lddmm_nn_ctx* ctx, double lr);
 lddmm_bl_status lddmm_nn_get(lddmm_nn_ctx* ctx, int32_t which, void* host_dst);
 lddmm_bl_status lddmm_nn_set(lddmm_nn_ctx* ctx, const void* host_src);
+lddmm_bl_status lddmm_nn_save(const lddmm_nn_ctx* ctx, const char* path);
+lddmm_bl_status lddmm_nn_load(lddmm_nn_ctx* ctx, const char* path);
 lddmm_bl_status lddmm_nn_destroy(lddmm_nn_ctx* ctx);
 
 /* Input and output maps of the warm-start network (all device float, on the network's stream).
  * pool_pair: box average of an image pair I0, I1 [n0][n1][n2] (each n_j a multiple of in_size) into
  *   one network input slot [2][in_size^3] (I0 in channel 0).
- * velocity: network output [B][3][s^3] (grid samples of the three velocity components on the
- *   coarse s^3 grid of the unit torus) -> band-limited coefficients v_bl [B][3][k0][k1][k2]: the
- *   projection of Section 2.2 onto the s-point band (frequencies |m| <= s/2 - 1, i.e. real slots
- *   0 .. s-2 per axis), zero in every other slot.  Requires 3 output channels and even k_j >= s - 1.
- * loss: mean over the batch of the squared V-norm error sum_a L~(a) (v_pred - v_target)_a^2 with
- *   L~ = (1 + alpha (2 pi)^2 |m|^2)^s (Section 2.1), accumulated in double; v_target [B][3][K];
- *   writes d loss / d output to dout_or_null ([B][3][s^3]) when it is not NULL. */
+ * velocity: network output [B][3 (1 + r)][s^3] -> band-limited coefficients
+ *   v_bl [B][1 + r][3][k0][k1][k2] (the velocity, then the r directions): the projection of
+ *   Section 2.2 onto the s-point band (frequencies |m| <= s/2 - 1, i.e. real slots 0 .. s-2 per
+ *   axis), zero in every other slot.  Requires even k_j >= s - 1.
+ * loss: mean over the batch of the squared V-norm error sum_a L~(a) (v_pred - v_target)_a^2 of the
+ *   velocity channels, L~ = (1 + alpha (2 pi)^2 |m|^2)^s (Section 2.1), accumulated in double;
+ *   v_target [B][3][K]; writes d loss / d output to dout_or_null ([B][3 (1 + r)][s^3], zero on
+ *   the direction channels) when it is not NULL. */
 lddmm_bl_status lddmm_nn_pool_pair(lddmm_nn_ctx* ctx, const void* I0, const void* I1, const int32_t* n,
                                    void* in_slot);
 lddmm_bl_status lddmm_nn_velocity(lddmm_nn_ctx* ctx, const void* out, int32_t B, const int32_t* k, void* v_bl);

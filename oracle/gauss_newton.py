@@ -84,6 +84,13 @@ class GNReport:
     status: int = 0
     history: List[dict] = field(default_factory=list)
 
+    @property
+    def decisions(self):
+        """Per GN iteration: (PCG iterations, 1 if PCG stopped on non-positive curvature, Armijo backtracks
+        before the accepted step or -1 when none was accepted): the discrete branches of the driver."""
+        return [(h["pcg"], 1 if h["flag"] == 3 else 0, h["backtracks"] if h["accepted"] else -1)
+                for h in self.history]
+
 
 def gauss_newton(model, v0, max_gn=10, max_pcg=5, grad_rtol=1e-3, grad_ref_inf=0.0,
                  fixed_iters=False, precond=None):
@@ -111,6 +118,7 @@ def gauss_newton(model, v0, max_gn=10, max_pcg=5, grad_rtol=1e-3, grad_ref_inf=0
         gd = float(sp.l2(g, dv))
         eps = 1.0
         accepted = False
+        bt0 = rep.backtracks
         for bt in range(11):
             vt = v + eps * dv
             model.setup(vt)
@@ -122,7 +130,7 @@ def gauss_newton(model, v0, max_gn=10, max_pcg=5, grad_rtol=1e-3, grad_ref_inf=0
             rep.backtracks += 1
             eps *= 0.5
         rep.history.append(dict(iter=k, E=E, grad_inf=ginf, pcg=its, flag=flag, eps=eps if accepted else 0.0,
-                                accepted=accepted))
+                                accepted=accepted, backtracks=rep.backtracks - bt0))
         if not accepted:
             model.setup(v)
             model.state()

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblddmm_bl.so")
-SOURCES = ["dft.hip", "dft_fused.hip", "fused_back.hip", "dft_bf16.hip", "grid.hip", "brick.hip", "reduce.hip", "prof.hip", "tune.hip", "solver.hip", "api.hip", "nn.hip", "nn_api.hip"]
+SOURCES = ["dft.hip", "dft_fused.hip", "fused_back.hip", "grid.hip", "brick.hip", "reduce.hip", "prof.hip", "tune.hip", "solver.hip", "api.hip", "nn.hip", "nn_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -43,12 +43,15 @@ def _compile(src: str) -> str:
 def build_library(verbose: bool = True) -> str:
     """Compile every source and link the shared library; returns its path."""
     os.makedirs(BUILD, exist_ok=True)
-    srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    missing = [s for s in SOURCES if not os.path.exists(os.path.join(CSRC, s))]
+    if missing:
+        raise RuntimeError(f"listed sources are missing: {missing}")
+    srcs = list(SOURCES)
     jobs = min(len(srcs), int(os.environ.get("MAX_JOBS", "8")))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-Wl,--no-undefined", *objs, "-o", tmp]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"link failed:\n{res.stderr}")

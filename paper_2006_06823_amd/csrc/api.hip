@@ -16,6 +16,12 @@ struct lddmm_bl_ctx {
   std::string err;
 };
 
+namespace lddmm {
+// text of the last error of a call without a context, per thread (lddmm_bl_last_error(NULL))
+thread_local std::string g_last_error;
+void set_global_error(const char* what) { g_last_error = what ? what : ""; }
+}  // namespace lddmm
+
 namespace {
 
 template <typename F>
@@ -55,13 +61,20 @@ lddmm_bl_status lddmm_bl_create(const lddmm_bl_params* params, void* hip_stream,
   if (!ctx) return LDDMM_BL_E_OOM;
   try {
     ctx->solver = lddmm::make_solver(*params, static_cast<hipStream_t>(hip_stream));
-  } catch (const lddmm::ArgError&) {
+  } catch (const lddmm::ArgError& e) {
+    lddmm::set_global_error(e.what());
     delete ctx;
     return LDDMM_BL_E_ARG;
   } catch (const std::bad_alloc&) {
+    lddmm::set_global_error("device allocation failed");
     delete ctx;
     return LDDMM_BL_E_OOM;
+  } catch (const std::exception& e) {
+    lddmm::set_global_error(e.what());
+    delete ctx;
+    return LDDMM_BL_E_HIP;
   } catch (...) {
+    lddmm::set_global_error("unknown error");
     delete ctx;
     return LDDMM_BL_E_HIP;
   }
@@ -80,7 +93,7 @@ lddmm_bl_status lddmm_bl_destroy(lddmm_bl_ctx* ctx) {
 }
 
 const char* lddmm_bl_last_error(const lddmm_bl_ctx* ctx) {
-  if (!ctx) return "null context";
+  if (!ctx) return lddmm::g_last_error.c_str();
   return ctx->err.c_str();
 }
 
@@ -128,28 +141,42 @@ lddmm_bl_status lddmm_bl_gn_solve_batched(const lddmm_bl_params* per_subject, in
                                           const void* const* I1, void* const* v_bl_inout,
                                           const lddmm_bl_gn_opts* opts, void* hip_stream,
                                           lddmm_bl_gn_report* reports) {
-  if (!per_subject || count < 1 || count > 4096 || !I0 || !I1 || !v_bl_inout || !opts) return LDDMM_BL_E_ARG;
-  if (!hip_stream) return LDDMM_BL_E_ARG;  // graphs need a non-default stream
+  if (!per_subject || count < 1 || count > 4096 || !I0 || !I1 || !v_bl_inout || !opts) {
+    lddmm::set_global_error("batched solve: null argument or count outside 1..4096");
+    return LDDMM_BL_E_ARG;
+  }
+  if (!hip_stream) {  // graphs need a non-default stream
+    lddmm::set_global_error("batched solve: the stream must not be NULL");
+    return LDDMM_BL_E_ARG;
+  }
   try {
     std::vector<std::unique_ptr<lddmm::SolverBase>> owned;
     std::vector<lddmm::SolverBase*> subs;
     for (int i = 0; i < count; ++i) {
-      if (per_subject[i].precision == LDDMM_BL_FP64) return LDDMM_BL_E_ARG;
+      if (per_subject[i].precision == LDDMM_BL_FP64) throw lddmm::ArgError("batched subjects must be float");
       owned.push_back(lddmm::make_solver(per_subject[i], static_cast<hipStream_t>(hip_stream)));
       owned.back()->set_images(I0[i], I1[i]);
       subs.push_back(owned.back().get());
     }
     return static_cast<lddmm_bl_status>(
         lddmm::gn_solve_batched(subs, *opts, v_bl_inout, reports, static_cast<hipStream_t>(hip_stream)));
-  } catch (const lddmm::ArgError&) {
+  } catch (const lddmm::ArgError& e) {
+    lddmm::set_global_error(e.what());
     return LDDMM_BL_E_ARG;
-  } catch (const lddmm::StateError&) {
+  } catch (const lddmm::StateError& e) {
+    lddmm::set_global_error(e.what());
     return LDDMM_BL_E_STATE;
-  } catch (const lddmm::NonFiniteError&) {
+  } catch (const lddmm::NonFiniteError& e) {
+    lddmm::set_global_error(e.what());
     return LDDMM_BL_E_NONFINITE;
   } catch (const std::bad_alloc&) {
+    lddmm::set_global_error("device allocation failed");
     return LDDMM_BL_E_OOM;
+  } catch (const std::exception& e) {
+    lddmm::set_global_error(e.what());
+    return LDDMM_BL_E_HIP;
   } catch (...) {
+    lddmm::set_global_error("unknown error");
     return LDDMM_BL_E_HIP;
   }
 }

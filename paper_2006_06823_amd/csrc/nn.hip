@@ -249,17 +249,18 @@ __global__ void k_pool_pair(const float* __restrict__ I0, const float* __restric
 
 // coarse velocity samples [B][3][s^3] -> band-limited coefficients [B][3][K0][K1][K2]:
 // the separable projection P[a][x] onto the s-point band for slots a < s - 1, zero elsewhere
-__global__ void k_samples_to_bl(const float* __restrict__ samp, const float* __restrict__ P, int B, int sz, int k0,
-                                int k1, int k2, float* __restrict__ v) {
+__global__ void k_samples_to_bl(const float* __restrict__ samp, const float* __restrict__ P, int B, int gs, int sz,
+                                int k0, int k1, int k2, float* __restrict__ v) {
   const int64_t Q = (int64_t)k0 * k1 * k2;
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (e >= (int64_t)B * 3 * Q) return;
   const int64_t bc = e / Q, q = e - bc * Q;
+  const int64_t sc = (bc / 3) * gs * 3 + bc % 3;  // sample channel: group b at stride gs
   const int a0 = (int)(q / ((int64_t)k1 * k2)), a1 = (int)((q / k2) % k1), a2 = (int)(q % k2);
   const int nb = sz - 1;
   float r = 0.f;
   if (a0 < nb && a1 < nb && a2 < nb) {
-    const float* sp = samp + bc * sz * sz * sz;
+    const float* sp = samp + sc * sz * sz * sz;
     for (int x0 = 0; x0 < sz; ++x0) {
       float t1 = 0.f;
       for (int x1 = 0; x1 < sz; ++x1) {
@@ -276,12 +277,13 @@ __global__ void k_samples_to_bl(const float* __restrict__ samp, const float* __r
 // gradient of the weighted squared coefficient error with respect to the samples:
 // ds[b][c][x] = scale * sum_{a in block} P[a0][x0] P[a1][x1] P[a2][x2] w[a] diff[b][c][a]
 __global__ void k_block_grad(const float* __restrict__ diff, const double* __restrict__ w, const float* __restrict__ P,
-                             int B, int sz, int k0, int k1, int k2, float scale, float* __restrict__ ds) {
+                             int B, int gs, int sz, int k0, int k1, int k2, float scale, float* __restrict__ ds) {
   const int s3 = sz * sz * sz;
   const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (e >= (int64_t)B * 3 * s3) return;
   const int64_t bc = e / s3;
   const int x = (int)(e - bc * s3);
+  const int64_t sc = (bc / 3) * gs * 3 + bc % 3;  // output channel: group b at stride gs
   const int x0 = x / (sz * sz), x1 = (x / sz) % sz, x2 = x % sz;
   const int nb = sz - 1;
   const float* dp = diff + bc * k0 * k1 * k2;
@@ -298,7 +300,7 @@ __global__ void k_block_grad(const float* __restrict__ diff, const double* __res
     }
     r += P[a0 * sz + x0] * t1;
   }
-  ds[e] = scale * r;
+  ds[sc * s3 + x] = scale * r;
 }
 
 }  // namespace
@@ -364,16 +366,17 @@ void pool_pair(const float* I0, const float* I1, const int n[3], int S, float* o
   LDDMM_LAUNCH_CHECK();
 }
 
-void samples_to_bl(const float* samp, const float* P, int B, int sz, const int k[3], float* v, hipStream_t s) {
+void samples_to_bl(const float* samp, const float* P, int B, int gs, int sz, const int k[3], float* v,
+                   hipStream_t s) {
   const int64_t tot = (int64_t)B * 3 * k[0] * k[1] * k[2];
-  k_samples_to_bl<<<ceil_div(tot, 256), 256, 0, s>>>(samp, P, B, sz, k[0], k[1], k[2], v);
+  k_samples_to_bl<<<ceil_div(tot, 256), 256, 0, s>>>(samp, P, B, gs, sz, k[0], k[1], k[2], v);
   LDDMM_LAUNCH_CHECK();
 }
 
-void block_grad(const float* diff, const double* w, const float* P, int B, int sz, const int k[3], float scale,
-                float* ds, hipStream_t s) {
+void block_grad(const float* diff, const double* w, const float* P, int B, int gs, int sz, const int k[3],
+                float scale, float* ds, hipStream_t s) {
   const int64_t tot = (int64_t)B * 3 * sz * sz * sz;
-  k_block_grad<<<ceil_div(tot, 256), 256, 0, s>>>(diff, w, P, B, sz, k[0], k[1], k[2], scale, ds);
+  k_block_grad<<<ceil_div(tot, 256), 256, 0, s>>>(diff, w, P, B, gs, sz, k[0], k[1], k[2], scale, ds);
   LDDMM_LAUNCH_CHECK();
 }
 

@@ -6,6 +6,7 @@
 // activation.  The head's output, of (in_size / 2^(levels-1))^3 voxels per channel,
 // is read as band-limited velocity coefficients in the real-basis layout.
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -22,8 +23,12 @@ namespace lddmm {
 
 class Net {
  public:
-  Net(int levels, const int* channels, int in_size, int out_channels, uint64_t seed, hipStream_t s) : st_(s) {
-    if (levels < 1 || levels > 6 || in_size < 4 || out_channels < 1) throw ArgError("bad network shape");
+  Net(int levels, const int* channels, int in_size, int rank_r, uint64_t seed, hipStream_t s) : st_(s) {
+    if (levels < 1 || levels > 6 || in_size < 4 || rank_r < 0 || rank_r > 16) throw ArgError("bad network shape");
+    const int out_channels = 3 * (1 + rank_r);
+    rank_ = rank_r;
+    for (int l = 0; l < levels; ++l) channels_.push_back(channels[l]);
+    in_size_ = in_size;
     int cin = 2, size = in_size;
     for (int l = 0; l < levels; ++l) {
       ConvLayer L;
@@ -89,6 +94,43 @@ class Net {
   int out_channels() const { return layers_.back().cout; }
   int64_t nparam() const { return nparam_; }
 
+  // Parameter file: the 8-byte tag, levels, channels[levels], in_size, rank_r (int32 each), the
+  // parameter count (int64) and the float master parameters in layer order (weights, then biases).
+  static constexpr char kTag[8] = {'L', 'D', 'D', 'M', 'M', 'N', 'N', '1'};
+  void save(const char* path) {
+    std::vector<float> h(nparam_);
+    get(h.data(), 0);
+    std::FILE* f = std::fopen(path, "wb");
+    if (!f) throw ArgError(std::string("cannot open for writing: ") + path);
+    std::vector<int32_t> hdr{(int32_t)channels_.size()};
+    for (int c : channels_) hdr.push_back(c);
+    hdr.push_back(in_size_);
+    hdr.push_back(rank_);
+    const int64_t n = nparam_;
+    bool ok = std::fwrite(kTag, 1, 8, f) == 8 && std::fwrite(hdr.data(), 4, hdr.size(), f) == hdr.size() &&
+              std::fwrite(&n, 8, 1, f) == 1 && std::fwrite(h.data(), 4, h.size(), f) == h.size();
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok) throw ArgError(std::string("cannot write ") + path);
+  }
+  void load(const char* path) {
+    std::FILE* f = std::fopen(path, "rb");
+    if (!f) throw ArgError(std::string("cannot open: ") + path);
+    char tag[8];
+    int32_t levels = 0;
+    bool ok = std::fread(tag, 1, 8, f) == 8 && std::memcmp(tag, kTag, 8) == 0 && std::fread(&levels, 4, 1, f) == 1 &&
+              levels == (int32_t)channels_.size();
+    std::vector<int32_t> hdr(ok ? levels + 2 : 0);
+    int64_t n = -1;
+    ok = ok && std::fread(hdr.data(), 4, hdr.size(), f) == hdr.size() && std::fread(&n, 8, 1, f) == 1;
+    for (int l = 0; ok && l < levels; ++l) ok = hdr[l] == channels_[l];
+    ok = ok && hdr[levels] == in_size_ && hdr[levels + 1] == rank_ && n == nparam_;
+    std::vector<float> h(ok ? nparam_ : 0);
+    ok = ok && std::fread(h.data(), 4, h.size(), f) == h.size();
+    std::fclose(f);
+    if (!ok) throw ArgError(std::string("parameter file does not match this network: ") + path);
+    set(h.data());
+  }
+
   void forward(const float* in, int B, float* out) {
     ensure(B);
     const float* x = in;
@@ -144,10 +186,10 @@ class Net {
     LDDMM_HIP(hipStreamSynchronize(st_));
   }
 
-  // network output [B][3][s^3] -> velocity coefficients [B][3][k0][k1][k2]
+  // network output [B][3(1+r)][s^3] -> coefficients [B][1+r][3][k0][k1][k2] (velocity, then directions)
   void velocity(const float* out, int B, const int k[3], float* v) {
     check_velocity_args(B, k);
-    samples_to_bl(out, proj(), B, out_size_, k, v, st_);
+    samples_to_bl(out, proj(), B * (1 + rank_), 1, out_size_, k, v, st_);
     LDDMM_HIP(hipStreamSynchronize(st_));
   }
 
@@ -164,7 +206,8 @@ class Net {
       diff_cap_ = n;
     }
     weights(k, alpha, s_exp);
-    samples_to_bl(out, proj(), B, out_size_, k, diff_, st_);
+    const int gs = 1 + rank_;  // the velocity channels are the first 3 of each sample's 3 (1 + r)
+    samples_to_bl(out, proj(), B, gs, out_size_, k, diff_, st_);
     bl_axpby<float>(diff_, 1.f, diff_, -1.f, vt, n, st_);
     if (!work_) {
       if (hipMalloc(&work_, sizeof(double) * reduce_work_size()) != hipSuccess) throw std::bad_alloc();
@@ -172,14 +215,18 @@ class Net {
         throw std::bad_alloc();
     }
     const double l = sym_dot<float>(diff_, diff_, Lw_, 3 * B, Q, work_, host_, st_) / B;
-    if (dout) block_grad(diff_, Lw_, proj(), B, out_size_, k, 2.f / B, dout, st_);
+    if (dout) {
+      // the loss does not depend on the direction channels
+      if (rank_ > 0) fill(dout, (int64_t)B * out_channels() * out_size_ * out_size_ * out_size_, 0.f, st_);
+      block_grad(diff_, Lw_, proj(), B, gs, out_size_, k, 2.f / B, dout, st_);
+    }
     LDDMM_HIP(hipStreamSynchronize(st_));
     return l;
   }
 
  private:
   void check_velocity_args(int B, const int k[3]) const {
-    if (B < 1 || layers_.back().cout != 3) throw ArgError("velocity output needs 3 output channels and B >= 1");
+    if (B < 1) throw ArgError("batch must be >= 1");
     for (int j = 0; j < 3; ++j)
       if (k[j] < out_size_ - 1 || k[j] < 2 || k[j] % 2) throw ArgError("band too small for the network output");
   }
@@ -254,6 +301,8 @@ class Net {
   }
 
   hipStream_t st_;
+  int rank_ = 0, in_size_ = 0;
+  std::vector<int> channels_;
   std::vector<ConvLayer> layers_;
   std::vector<int> sizes_;  // input size of each layer
   int out_size_ = 0, capB_ = 0, lastB_ = 0, t_ = 0;
@@ -283,17 +332,27 @@ struct lddmm_nn_ctx {
 namespace {
 template <typename F>
 lddmm_bl_status nn_guard(lddmm_nn_ctx* c, F&& f) {
-  if (!c || !c->net) return LDDMM_BL_E_ARG;
+  if (!c || !c->net) {
+    lddmm::set_global_error("null network context");
+    return LDDMM_BL_E_ARG;
+  }
   try {
     f();
     return LDDMM_BL_OK;
-  } catch (const lddmm::ArgError&) {
+  } catch (const lddmm::ArgError& e) {
+    lddmm::set_global_error(e.what());
     return LDDMM_BL_E_ARG;
-  } catch (const lddmm::StateError&) {
+  } catch (const lddmm::StateError& e) {
+    lddmm::set_global_error(e.what());
     return LDDMM_BL_E_STATE;
   } catch (const std::bad_alloc&) {
+    lddmm::set_global_error("device allocation failed");
     return LDDMM_BL_E_OOM;
+  } catch (const std::exception& e) {
+    lddmm::set_global_error(e.what());
+    return LDDMM_BL_E_HIP;
   } catch (...) {
+    lddmm::set_global_error("unknown error");
     return LDDMM_BL_E_HIP;
   }
 }
@@ -301,24 +360,44 @@ lddmm_bl_status nn_guard(lddmm_nn_ctx* c, F&& f) {
 
 extern "C" {
 
-lddmm_bl_status lddmm_nn_create(int32_t levels, const int32_t* channels, int32_t in_size, int32_t out_channels,
+lddmm_bl_status lddmm_nn_create(int32_t levels, const int32_t* channels, int32_t in_size, int32_t rank_r,
                                 uint64_t seed, void* hip_stream, lddmm_nn_ctx** out) {
   if (!channels || !out) return LDDMM_BL_E_ARG;
   *out = nullptr;
   auto* c = new (std::nothrow) lddmm_nn_ctx();
   if (!c) return LDDMM_BL_E_OOM;
   try {
-    c->net = std::make_unique<lddmm::Net>(levels, channels, in_size, out_channels, seed,
+    c->net = std::make_unique<lddmm::Net>(levels, channels, in_size, rank_r, seed,
                                           static_cast<hipStream_t>(hip_stream));
-  } catch (const lddmm::ArgError&) {
+  } catch (const lddmm::ArgError& e) {
+    lddmm::set_global_error(e.what());
     delete c;
     return LDDMM_BL_E_ARG;
+  } catch (const std::exception& e) {
+    lddmm::set_global_error(e.what());
+    delete c;
+    return LDDMM_BL_E_OOM;
   } catch (...) {
+    lddmm::set_global_error("unknown error");
     delete c;
     return LDDMM_BL_E_OOM;
   }
   *out = c;
   return LDDMM_BL_OK;
+}
+
+lddmm_bl_status lddmm_nn_save(const lddmm_nn_ctx* c, const char* path) {
+  return nn_guard(const_cast<lddmm_nn_ctx*>(c), [&] {
+    if (!path) throw lddmm::ArgError("null path");
+    c->net->save(path);
+  });
+}
+
+lddmm_bl_status lddmm_nn_load(lddmm_nn_ctx* c, const char* path) {
+  return nn_guard(c, [&] {
+    if (!path) throw lddmm::ArgError("null path");
+    c->net->load(path);
+  });
 }
 
 lddmm_bl_status lddmm_nn_destroy(lddmm_nn_ctx* c) {

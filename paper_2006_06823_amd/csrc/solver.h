@@ -64,6 +64,9 @@ std::unique_ptr<SolverBase> make_solver(const lddmm_bl_params& p, hipStream_t s)
 int gn_solve_batched(std::vector<SolverBase*>& subs, const lddmm_bl_gn_opts& o, void* const* v_user,
                      lddmm_bl_gn_report* reps, hipStream_t st);
 
+// Records the text of the last error of a call without a context (this thread).
+void set_global_error(const char* what);
+
 // Thrown when a call needs a state solve at the current velocity first.
 class StateError : public std::runtime_error {
  public:

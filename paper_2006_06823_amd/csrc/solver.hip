@@ -152,6 +152,13 @@ class Solver final : public SolverBase {
 
   void jacobian(double* detmap, double* minmax) override {
     require_state();
+    double mm[2];
+    jacobian_into(detmap, mm);
+    if (minmax) minmax[0] = mm[0], minmax[1] = mm[1];
+    sync();
+  }
+  // det(I - D iota(u~(1))) into `detmap` (or the context's own buffer when null) and its extrema
+  void jacobian_into(double* detmap, double mm[2]) {
     // u~(1): the deformation state (variant 3 holds it; variant 1 integrates it here)
     const T* u1;
     if (variant_ == LDDMM_BL_DEFORMATION_STATE) {
@@ -162,15 +169,15 @@ class Solver final : public SolverBase {
     }
     stack_deriv9(u1, stk_.get());
     iota9_deriv(stk_.get(), S9());
-    DevBuf<double> det(d_.P);
-    jacobian_det(det.get(), S9(), dim_, d_.P, st_);
-    minmax_f64(det.get(), d_.P, work_.get(), host_.get(), st_);
-    if (minmax) {
-      minmax[0] = host_.get()[0];
-      minmax[1] = host_.get()[1];
+    double* det = detmap;
+    if (!det) {
+      if (!det_.get()) det_.alloc(d_.P);
+      det = det_.get();
     }
-    if (detmap) LDDMM_HIP(hipMemcpyAsync(detmap, det.get(), d_.P * sizeof(double), hipMemcpyDeviceToDevice, st_));
-    sync();
+    jacobian_det(det, S9(), dim_, d_.P, st_);
+    minmax_f64(det, d_.P, work_.get(), host_.get(), st_);
+    mm[0] = host_.get()[0];
+    mm[1] = host_.get()[1];
   }
 
   void project(const void* grid, void* bl, int ncomp) override {
@@ -893,6 +900,7 @@ class Solver final : public SolverBase {
   DevBuf<T> G_, m_, lam0_;               // image transport
   DevBuf<T> ubl_, Du_, m1_, g1_, rho_;   // deformation state
   DevBuf<float> pipart_;
+  DevBuf<double> det_;  // Jacobian map when the caller keeps none
 
  public:
   // accessors used by the Gauss-Newton driver
@@ -1042,11 +1050,21 @@ int Solver<T>::gn_solve(const lddmm_bl_gn_opts& o, void* v_user, const void* Zu,
       for (int j = 0; j < r; ++j) y[i] += ZHZinv[i * r + j] * c[j];
     for (int i = 0; i < r; ++i) axpby_internal(zout, T(1), zout, T(y[i]), Z.get() + i * n);
   };
+  auto log_iter = [&](int it, int pcg, int neg, int bt) {
+    if (it >= LDDMM_BL_LOG_MAX) return;
+    R.log_pcg[it] = pcg;
+    R.log_negcurv[it] = neg;
+    R.log_backtracks[it] = bt;
+    R.log_count = it + 1;
+  };
+  bool ls_failed = false;
+  auto converged = [&] {
+    return ginf <= o.grad_rtol * ref || (o.energy_target > 0 && E <= o.energy_target);
+  };
   int k = 0;
   for (k = 0; k < o.max_gn; ++k) {
     if (trace_) fprintf(stderr, "[lddmm_bl] gn %d E %.17g ginf_rel %.6g\n", k, E, ginf / ref);
-    if (!fixed && ginf <= o.grad_rtol * ref) break;
-    if (!fixed && o.energy_target > 0 && E <= o.energy_target) break;
+    if (!fixed && converged()) break;
     if (twolevel) {
       // Z^T H Z at the current velocity (r extra matvecs), inverted by Gauss-Jordan in double
       std::vector<double> A(r * r);
@@ -1101,7 +1119,7 @@ int Solver<T>::gn_solve(const lddmm_bl_gn_opts& o, void* v_user, const void* Zu,
     precond(rr.get(), z.get());
     copy_internal(p.get(), z.get());
     double rz = dot_internal(rr.get(), z.get());
-    int its = 0;
+    int its = 0, negcurv = 0;
     for (its = 0; its < o.max_pcg; ++its) {
       const double rn = std::sqrt(dot_internal(rr.get(), rr.get()));
       if (!fixed && rn <= tol) break;
@@ -1110,7 +1128,7 @@ int Solver<T>::gn_solve(const lddmm_bl_gn_opts& o, void* v_user, const void* Zu,
       const double pAp = dot_internal(p.get(), Ap.get());
       if (!std::isfinite(pAp)) throw NonFiniteError("non-finite curvature in PCG");
       if (pAp <= 0.0) {
-        status = LDDMM_BL_W_NEGCURV;
+        negcurv = 1;  // truncated CG: the direction so far (or the first search direction)
         if (its == 0) copy_internal(x.get(), p.get());
         break;
       }
@@ -1128,6 +1146,7 @@ int Solver<T>::gn_solve(const lddmm_bl_gn_opts& o, void* v_user, const void* Zu,
     const double gd = dot_internal(g.get(), x.get());
     double eps = 1.0;
     bool accepted = false;
+    const int bt_before = R.backtracks;
     double Et = E;
     for (int bt = 0; bt <= 10; ++bt) {
       axpby_internal(vt.get(), T(1), v.get(), T(eps), x.get());
@@ -1142,10 +1161,11 @@ int Solver<T>::gn_solve(const lddmm_bl_gn_opts& o, void* v_user, const void* Zu,
       ++R.backtracks;
       eps *= 0.5;
     }
+    log_iter(k, its, negcurv, accepted ? R.backtracks - bt_before : -1);
     if (!accepted) {
       set_velocity_internal(v.get());
       state_internal(e);
-      status = LDDMM_BL_W_LINESEARCH;
+      ls_failed = true;
       break;
     }
     copy_internal(v.get(), vt.get());
@@ -1154,13 +1174,22 @@ int Solver<T>::gn_solve(const lddmm_bl_gn_opts& o, void* v_user, const void* Zu,
     ginf = grad_inf_internal(g.get());
     R.gn_iters = k + 1;
   }
-  if (status == LDDMM_BL_OK && !fixed && k == o.max_gn && ginf > o.grad_rtol * ref &&
-      !(o.energy_target > 0 && E <= o.energy_target))
+  // final status from the line search, convergence and the cap (truncated PCG solves are
+  // recorded per iteration in the log, not in the status)
+  if (ls_failed)
+    status = LDDMM_BL_W_LINESEARCH;
+  else if (!fixed && !converged())
     status = LDDMM_BL_W_MAXITER;
   internal_to_user(static_cast<T*>(v_user), v.get());
   R.E = E;
   R.grad_inf_rel = ref > 0 ? ginf / ref : 0.0;
   R.mse_rel = mse_rel();
+  {
+    double mm[2];
+    jacobian_into(nullptr, mm);
+    R.det_min = mm[0];
+    R.det_max = mm[1];
+  }
   synchronize();
   R.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (rep) *rep = R;
@@ -1183,7 +1212,15 @@ int gn_solve_batched_impl(std::vector<Solver<T>*>& subs, const lddmm_bl_gn_opts&
     DevBuf<T> v, g, x, r, z, vt;
     double E = 0, ginf = 0, ref = 0, gnorm0 = 0, rz = 0, tol = 0;
     bool converged = false, failed = false, pcg_done = false;
+    int its = 0, negcurv = 0, bt = 0;  // this GN iteration's PCG iterations, truncation, backtracks
     lddmm_bl_gn_report R{};
+    void log(int k, int backtracks) {
+      if (k >= LDDMM_BL_LOG_MAX) return;
+      R.log_pcg[k] = its;
+      R.log_negcurv[k] = negcurv;
+      R.log_backtracks[k] = backtracks;
+      R.log_count = k + 1;
+    }
   };
   std::vector<Sub> S(B);
   const bool fixed = o.fixed_iters != 0;
@@ -1318,6 +1355,7 @@ int gn_solve_batched_impl(std::vector<Solver<T>*>& subs, const lddmm_bl_gn_opts&
       Solver<T>& sv = *subs[i];
       u.pcg_done = u.failed || u.converged;
       if (u.pcg_done) continue;
+      u.its = u.negcurv = u.bt = 0;
       const double gnorm = std::sqrt(sv.dot_internal(u.g.get(), u.g.get()));
       const double eta = u.gnorm0 > 0 ? std::min(0.5, std::sqrt(gnorm / u.gnorm0)) : 0.5;
       u.tol = eta * gnorm;
@@ -1349,17 +1387,18 @@ int gn_solve_batched_impl(std::vector<Solver<T>*>& subs, const lddmm_bl_gn_opts&
         Solver<T>& sv = *subs[i];
         if (u.pcg_done) continue;
         ++u.R.hess_matvecs;
-        ++u.R.pcg_iters_total;
         T* p = sv.dvbl_.get();
         const T* Ap = sv.hbl_.get();
         const double pAp = sv.dot_internal(p, Ap);
         if (!std::isfinite(pAp)) throw NonFiniteError("non-finite curvature in batched PCG");
         if (pAp <= 0.0) {
-          --u.R.pcg_iters_total;
           if (it == 0) sv.copy_internal(u.x.get(), p);
+          u.negcurv = 1;
           u.pcg_done = true;
           continue;
         }
+        ++u.R.pcg_iters_total;
+        ++u.its;
         const double a = u.rz / pAp;
         sv.axpby_internal(u.x.get(), T(1), u.x.get(), T(a), p);
         sv.axpby_internal(u.r.get(), T(1), u.r.get(), T(-a), Ap);
@@ -1395,9 +1434,11 @@ int gn_solve_batched_impl(std::vector<Solver<T>*>& subs, const lddmm_bl_gn_opts&
         if (e[0] <= S[i].E + 1e-4 * eps[i] * gd[i]) {
           subs[i]->copy_internal(S[i].v.get(), S[i].vt.get());
           S[i].E = e[0];
+          S[i].log(k, S[i].bt);
           accepted.push_back(i);
         } else {
           ++S[i].R.backtracks;
+          ++S[i].bt;
           eps[i] *= 0.5;
           next.push_back(i);
         }
@@ -1410,6 +1451,7 @@ int gn_solve_batched_impl(std::vector<Solver<T>*>& subs, const lddmm_bl_gn_opts&
       subs[i]->set_velocity_internal(S[i].v.get());
       subs[i]->state_internal(e);
       S[i].failed = true;
+      S[i].log(k, -1);
     }
     // new gradients of the subjects that moved
     on_branches(accepted, [&](int i) { subs[i]->adjoint_launch(S[i].g.get()); });
@@ -1420,6 +1462,7 @@ int gn_solve_batched_impl(std::vector<Solver<T>*>& subs, const lddmm_bl_gn_opts&
     }
     mark("line search and gradients done");
   }
+  // per-subject status as in gn_solve; the batch returns the worst (line search, then cap)
   int status = LDDMM_BL_OK;
   for (int i = 0; i < B; ++i) {
     Sub& u = S[i];
@@ -1428,7 +1471,15 @@ int gn_solve_batched_impl(std::vector<Solver<T>*>& subs, const lddmm_bl_gn_opts&
     u.R.E = u.E;
     u.R.grad_inf_rel = u.ref > 0 ? u.ginf / u.ref : 0.0;
     u.R.mse_rel = sv.mse_rel();
-    if (u.failed) status = LDDMM_BL_W_LINESEARCH;
+    double mm[2];
+    sv.jacobian_into(nullptr, mm);
+    u.R.det_min = mm[0];
+    u.R.det_max = mm[1];
+    const bool conv = u.ginf <= o.grad_rtol * u.ref || (o.energy_target > 0 && u.E <= o.energy_target);
+    if (u.failed)
+      status = LDDMM_BL_W_LINESEARCH;
+    else if (!fixed && !conv && status == LDDMM_BL_OK)
+      status = LDDMM_BL_W_MAXITER;
   }
   LDDMM_HIP(hipStreamSynchronize(st));
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

@@ -37,7 +37,8 @@ EXPORTS = [
     "lddmm_bl_profile_enable", "lddmm_bl_profile_read", "lddmm_bl_gn_solve_batched",
     "lddmm_bl_tune_candidates", "lddmm_bl_tune_get", "lddmm_bl_tune_set",
     "lddmm_nn_create", "lddmm_nn_info", "lddmm_nn_forward", "lddmm_nn_backward", "lddmm_nn_zero_grad",
-    "lddmm_nn_step", "lddmm_nn_get", "lddmm_nn_set", "lddmm_nn_destroy", "lddmm_nn_pool_pair",
+    "lddmm_nn_step", "lddmm_nn_get", "lddmm_nn_set", "lddmm_nn_save", "lddmm_nn_load", "lddmm_nn_destroy",
+    "lddmm_nn_pool_pair",
     "lddmm_nn_velocity", "lddmm_nn_loss",
 ]
 
@@ -57,15 +58,25 @@ class GNOpts(ctypes.Structure):
     ]
 
 
+LOG_MAX = 64
+
+
 class GNReport(ctypes.Structure):
     _fields_ = [
         ("gn_iters", ctypes.c_int32), ("pcg_iters_total", ctypes.c_int32), ("backtracks", ctypes.c_int32),
         ("hess_matvecs", ctypes.c_int32), ("E0", ctypes.c_double), ("E", ctypes.c_double),
-        ("mse_rel", ctypes.c_double), ("grad_inf_rel", ctypes.c_double), ("seconds", ctypes.c_double),
+        ("mse_rel", ctypes.c_double), ("grad_inf_rel", ctypes.c_double), ("det_min", ctypes.c_double),
+        ("det_max", ctypes.c_double), ("seconds", ctypes.c_double), ("log_count", ctypes.c_int32),
+        ("log_pcg", ctypes.c_int32 * LOG_MAX), ("log_negcurv", ctypes.c_int32 * LOG_MAX),
+        ("log_backtracks", ctypes.c_int32 * LOG_MAX),
     ]
 
     def as_dict(self):
-        return {name: getattr(self, name) for name, _ in self._fields_}
+        """Report fields; the per-iteration decision log as a list of (pcg, negcurv, backtracks)."""
+        d = {name: getattr(self, name) for name, _ in self._fields_ if not name.startswith("log_")}
+        n = self.log_count
+        d["decisions"] = [(self.log_pcg[i], self.log_negcurv[i], self.log_backtracks[i]) for i in range(n)]
+        return d
 
 
 _lib = None
@@ -106,6 +117,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "lddmm_nn_step": [vp, ctypes.c_double],
         "lddmm_nn_get": [vp, i32, vp],
         "lddmm_nn_set": [vp, vp],
+        "lddmm_nn_save": [vp, ctypes.c_char_p],
+        "lddmm_nn_load": [vp, ctypes.c_char_p],
         "lddmm_nn_destroy": [vp],
         "lddmm_nn_pool_pair": [vp, vp, vp, ip, vp],
         "lddmm_nn_velocity": [vp, vp, i32, ip, vp],
@@ -187,7 +200,7 @@ def gn_solve_batched(problems, I0s, I1s, vs, max_gn=10, max_pcg=5, grad_rtol=1e-
     st = lib.lddmm_bl_gn_solve_batched(params, B, arr(I0s), arr(I1s), arr(vs), ctypes.byref(opts),
                                        ctypes.c_void_p(stream.cuda_stream), reps)
     if st < 0:
-        raise LddmmError(st, "lddmm_bl_gn_solve_batched failed")
+        raise LddmmError(st, lib.lddmm_bl_last_error(None).decode())
     torch.cuda.current_stream(dev).wait_stream(stream)
     return st, [reps[i].as_dict() for i in range(B)]
 
@@ -216,7 +229,7 @@ class Context:
         with torch.cuda.device(self.device):
             st = self.lib.lddmm_bl_create(ctypes.byref(p), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
         if st != 0:
-            raise LddmmError(st, "lddmm_bl_create failed")
+            raise LddmmError(st, "lddmm_bl_create: " + self.lib.lddmm_bl_last_error(None).decode())
         self.h = h
 
     # -- helpers -----------------------------------------------------------
@@ -395,24 +408,26 @@ class WarmStartNet:
     """The warm-start network (lddmm_nn_* in the C ABI) on one ROCm device.
 
     levels 3^3 convolutions (stride 2 but the last, ReLU) with the given channels on a
-    [B][2][in_size]^3 float input, then a 1^3 head to 3 channels: grid samples of the three
-    velocity components on a coarse out_size^3 grid.  All tensors are contiguous float32
-    on the device; the library works on its own stream, ordered after the caller's.
+    [B][2][in_size]^3 float input, then a 1^3 head to 3 (1 + rank_r) channels: grid samples of
+    the three velocity components (and of rank_r preconditioner directions) on a coarse
+    out_size^3 grid.  All tensors are contiguous float32 on the device; the library works on
+    its own stream, ordered after the caller's.
     """
 
-    def __init__(self, channels=(16, 32, 64, 128), in_size=64, seed=0, device=None):
+    def __init__(self, channels=(16, 32, 64, 128), in_size=64, seed=0, device=None, rank_r=0):
         self.lib = load_library()
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.stream = torch.cuda.Stream(device=self.device)
         self.channels = tuple(int(c) for c in channels)
         self.in_size = int(in_size)
+        self.rank_r = int(rank_r)
         ch = (ctypes.c_int32 * len(channels))(*self.channels)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
-            st = self.lib.lddmm_nn_create(len(channels), ch, self.in_size, 3, seed,
+            st = self.lib.lddmm_nn_create(len(channels), ch, self.in_size, self.rank_r, seed,
                                           ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
         if st != 0:
-            raise LddmmError(st, "lddmm_nn_create failed")
+            raise LddmmError(st, "lddmm_nn_create: " + self.lib.lddmm_bl_last_error(None).decode())
         self.h = h
         osz, oc, npar = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
         self._check(self.lib.lddmm_nn_info(self.h, ctypes.byref(osz), ctypes.byref(oc), ctypes.byref(npar)), "info")
@@ -431,7 +446,7 @@ class WarmStartNet:
 
     def _check(self, st, what):
         if st != 0:
-            raise LddmmError(st, f"lddmm_nn_{what} failed")
+            raise LddmmError(st, f"lddmm_nn_{what}: " + self.lib.lddmm_bl_last_error(None).decode())
 
     def _order(self):
         cur = torch.cuda.current_stream(self.device)
@@ -448,7 +463,7 @@ class WarmStartNet:
         return t
 
     def out_shape(self, B):
-        return (B, 3) + (self.out_size,) * 3
+        return (B, 3 * (1 + self.rank_r)) + (self.out_size,) * 3
 
     def pool_pair(self, I0, I1, slot):
         """Box-average an image pair into one input slot [2][in_size]^3 (a view of the batch tensor)."""
@@ -479,13 +494,22 @@ class WarmStartNet:
         self._check(self.lib.lddmm_nn_step(self.h, float(lr)), "step")
 
     def velocity(self, out, K):
+        """Band-limited coefficients of the outputs: [B][3][K] (rank_r = 0) or [B][1 + r][3][K]."""
         B = out.shape[0]
         self._dev(out, self.out_shape(B), "out")
-        v = torch.empty((B, 3) + tuple(K), dtype=torch.float32, device=self.device)
+        v = torch.empty((B, 1 + self.rank_r, 3) + tuple(K), dtype=torch.float32, device=self.device)
         k = (ctypes.c_int32 * 3)(*K)
         self._order()
         self._check(self.lib.lddmm_nn_velocity(self.h, _ptr(out), B, k, _ptr(v)), "velocity")
-        return v
+        return v[:, 0] if self.rank_r == 0 else v
+
+    def save(self, path):
+        """Write the architecture and master parameters (lddmm_nn_save)."""
+        self._check(self.lib.lddmm_nn_save(self.h, os.fsencode(path)), "save")
+
+    def load(self, path):
+        """Read parameters written by save into this network (same architecture)."""
+        self._check(self.lib.lddmm_nn_load(self.h, os.fsencode(path)), "load")
 
     def loss(self, out, v_target, alpha=0.0025, s=2, want_grad=True):
         B = out.shape[0]

@@ -15,6 +15,22 @@ def rel_l2(a, b):
     return float((a - b).norm() / b.norm().clamp_min(1e-300))
 
 
+def max_rel(a, b):
+    """Element-wise bound: max |a - b| / max |b|."""
+    a = torch.as_tensor(a).double().cpu().reshape(-1)
+    b = torch.as_tensor(b).double().cpu().reshape(-1)
+    return float((a - b).abs().max() / b.abs().max().clamp_min(1e-300))
+
+
+def close(a, b, label=""):
+    """The larger of the rel-L2 error and the element-wise max |a - b| / max |b|; both are printed so
+    that a run states the measured errors (a wrong tile or tail can hide under a small rel-L2 but not
+    under the element-wise bound)."""
+    r, m = rel_l2(a, b), max_rel(a, b)
+    print(f"[parity] {label} rel_l2 {r:.3e} max_rel {m:.3e}", flush=True)
+    return max(r, m)
+
+
 def images(N, seed):
     """Source/target pair: 2D Gaussian blobs or 3D brain-like phantom (float64 arrays)."""
     if len(N) == 2:

@@ -1,17 +1,19 @@
 """Gauss-Newton-Krylov on the GPU against the oracle's driver: the 2D configuration (64^2, band 16^2,
 Nt = 10, FP64, 10 GN x 5 PCG with fixed iteration counts), both variants.
 
-Parity target: final velocity rel-L2 <= 1e-3.  Near convergence an Armijo test compares energy
-differences at the rounding level, where the FFT-based oracle and the contraction-based GPU path may
-take different accept/reject decisions (both correct); so the strict check (identical iteration and
-backtracking counts, velocity within 1e-8) runs the first 6 Gauss-Newton iterations, and the full
-10 x 5 run is held to the 1e-3 target.
+Both drivers log their discrete decisions per GN iteration (PCG iterations, truncation on non-positive
+curvature, Armijo backtracks; Section 2.2 eqs. BLNewton / BLKKT with the Armijo reading).  Near
+convergence an Armijo test compares energy differences at the rounding level, where the FFT-based
+oracle and the contraction-based GPU path may take different accept/reject decisions (both correct).
+The test therefore compares the decision sequences of the full run and reports the first iteration where
+they differ; up to that iteration both drivers are re-run and must agree strictly (identical decisions,
+velocity within 1e-8); the full run's final velocity is held to the 1e-3 target.
 """
 import numpy as np
 import pytest
 import torch
 
-from gpu_common import oracle_model, rel_l2
+from gpu_common import close, oracle_model, rel_l2
 from oracle.gauss_newton import gauss_newton
 from paper_2006_06823_amd import lddmm_bl as L
 from paper_2006_06823_amd import synthetic as syn
@@ -32,24 +34,43 @@ def _run_2d(variant, max_gn):
     return ctx, v, rep, vo, ro
 
 
-@pytest.mark.parametrize("variant", [1, 3])
-def test_gn_2d_fp64_first_iterations_identical(variant):
-    ctx, v, rep, vo, ro = _run_2d(variant, 6)
-    assert rep["gn_iters"] == ro.gn_iters == 6
-    assert rep["pcg_iters_total"] == ro.pcg_iters_total
-    assert rep["backtracks"] == ro.backtracks
-    assert rel_l2(v, vo) <= 1e-8
-    assert abs(rep["E"] - ro.E) <= 1e-8 * abs(ro.E)
+def _first_difference(a, b):
+    for i, (x, y) in enumerate(zip(a, b)):
+        if tuple(x) != tuple(y):
+            return i
+    return None if len(a) == len(b) else min(len(a), len(b))
 
 
 @pytest.mark.parametrize("variant", [1, 3])
-def test_gn_2d_fp64_full_configuration(variant):
+def test_gn_2d_fp64_decision_sequences(variant):
     ctx, v, rep, vo, ro = _run_2d(variant, 10)
-    assert rel_l2(v, vo) <= 1e-3
+    gpu, ora = rep["decisions"], ro.decisions
+    j = _first_difference(gpu, ora)
+    print(f"[gn] variant {variant} gpu decisions {gpu}", flush=True)
+    print(f"[gn] variant {variant} oracle decisions {ora}", flush=True)
+    print(f"[gn] variant {variant} first differing GN iteration: {j}", flush=True)
+    assert close(v, vo, "final velocity") <= 1e-3
     assert abs(rep["E"] - ro.E) <= 1e-6 * abs(ro.E)
     assert rep["E"] < rep["E0"] and rep["mse_rel"] < 0.5
+    assert 0.0 < rep["det_min"] <= 1.0 <= rep["det_max"]
+    if j is None:
+        assert close(v, vo, "velocity, identical decisions") <= 1e-8
+        return
+    # the drivers may part only where Armijo compares energies at the rounding level, after the early
+    # iterations whose decrease is far above it
+    assert j >= 4, f"decision sequences differ already at GN iteration {j}"
+    ctx2, v2, rep2, vo2, ro2 = _run_2d(variant, j)
+    assert rep2["decisions"] == ro2.decisions == ora[:j]
+    assert close(v2, vo2, f"velocity after {j} GN iterations") <= 1e-8
+    assert abs(rep2["E"] - ro2.E) <= 1e-8 * abs(ro2.E)
+
+
+@pytest.mark.parametrize("variant", [1, 3])
+def test_gn_2d_fp64_report_extrema_match_the_jacobian_call(variant):
+    ctx, v, rep, vo, ro = _run_2d(variant, 3)
     (dmin, dmax), _ = ctx.jacobian()
-    assert 0.0 < dmin <= 1.0 <= dmax
+    assert rep["det_min"] == dmin and rep["det_max"] == dmax
+    assert rep["decisions"] == ro.decisions
 
 
 def test_gn_3d_fp32_small_matches_oracle():
@@ -64,7 +85,7 @@ def test_gn_3d_fp32_small_matches_oracle():
     om = oracle_model(3, N, K, Nt, I0.astype(np.float64), I1.astype(np.float64))
     vo, ro = gauss_newton(om, np.zeros((3,) + K), max_gn=3, max_pcg=3, fixed_iters=True)
     assert rep["backtracks"] == ro.backtracks
-    assert rel_l2(v, vo) <= 1e-3
+    assert close(v, vo) <= 1e-3
 
 
 @pytest.mark.parametrize("variant", [1, 3])

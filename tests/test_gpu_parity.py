@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 import torch
 
-from gpu_common import images, oracle_model, rel_l2, velocity
+from gpu_common import close, images, oracle_model, rel_l2, velocity
 from oracle import spectral as sp
 from paper_2006_06823_amd import lddmm_bl as L
 
@@ -65,7 +65,7 @@ def test_truncated_dft_parity(dim, N, K, Nt, precision):
         f = rng.standard_normal((nf,) + tuple(N))
         got = ctx.project(dev(f, ctx).reshape((nf,) + tuple(N)) if nf > 1 else dev(f[0], ctx), nf)
         ref = sp.project(torch.tensor(f), K)
-        assert rel_l2(got.reshape(ref.shape), ref) <= tol(precision, "dft")
+        assert close(got.reshape(ref.shape), ref) <= tol(precision, "dft")
         c = np.stack([np.random.default_rng(s).standard_normal(K) for s in range(nf)])
         for j, k in enumerate(K):
             sl = [slice(None)] * (dim + 1)
@@ -73,7 +73,7 @@ def test_truncated_dft_parity(dim, N, K, Nt, precision):
             c[tuple(sl)] = 0.0
         got = ctx.include(dev(c, ctx) if nf > 1 else dev(c[0], ctx), nf)
         ref = sp.include(torch.tensor(c), N)
-        assert rel_l2(got.reshape(ref.shape), ref) <= tol(precision, "dft")
+        assert close(got.reshape(ref.shape), ref) <= tol(precision, "dft")
 
 
 @pytest.mark.parametrize("variant", [1, 3])
@@ -85,19 +85,19 @@ def test_state_adjoint_gradient_parity(variant, dim, N, K, Nt, precision):
     om.state()
     Eo = [float(x) for x in om.objective()]
     # characteristics and divergence
-    assert rel_l2(ctx.get_field(L.FIELD_DEP_BACKWARD).reshape(om.Xb.shape), om.Xb) <= tol(precision)
-    assert rel_l2(ctx.get_field(L.FIELD_DEP_FORWARD).reshape(om.Xf.shape), om.Xf) <= tol(precision)
-    assert rel_l2(ctx.get_field(L.FIELD_DIV_V).reshape(om.divv.shape), om.divv) <= tol(precision)
+    assert close(ctx.get_field(L.FIELD_DEP_BACKWARD).reshape(om.Xb.shape), om.Xb) <= tol(precision)
+    assert close(ctx.get_field(L.FIELD_DEP_FORWARD).reshape(om.Xf.shape), om.Xf) <= tol(precision)
+    assert close(ctx.get_field(L.FIELD_DIV_V).reshape(om.divv.shape), om.divv) <= tol(precision)
     # state trajectory
     if variant == 1:
         for n in range(Nt + 1):
-            assert rel_l2(ctx.get_field(L.FIELD_STATE, n).reshape(om.m[n].shape), om.m[n]) <= tol(precision)
+            assert close(ctx.get_field(L.FIELD_STATE, n).reshape(om.m[n].shape), om.m[n]) <= tol(precision)
         m1o = om.m[-1]
     else:
         for n in range(1, Nt + 1):
-            assert rel_l2(ctx.get_field(L.FIELD_STATE, n).reshape(om.u[n].shape), om.u[n]) <= tol(precision)
+            assert close(ctx.get_field(L.FIELD_STATE, n).reshape(om.u[n].shape), om.u[n]) <= tol(precision)
         m1o = om.m1
-    assert rel_l2(m1, m1o) <= tol(precision)
+    assert close(m1, m1o) <= tol(precision)
     for a, b in zip(E, Eo):
         assert abs(a - b) <= tol(precision) * abs(b) * 10
     # adjoint and gradient
@@ -105,10 +105,10 @@ def test_state_adjoint_gradient_parity(variant, dim, N, K, Nt, precision):
     om.adjoint()
     go = om.gradient()
     if variant == 1:
-        assert rel_l2(ctx.get_field(L.FIELD_ADJOINT0).reshape(om.lam[0].shape), om.lam[0]) <= tol(precision)
+        assert close(ctx.get_field(L.FIELD_ADJOINT0).reshape(om.lam[0].shape), om.lam[0]) <= tol(precision)
     else:
-        assert rel_l2(ctx.get_field(L.FIELD_ADJOINT0).reshape(om.rho[0].shape), om.rho[0]) <= tol(precision)
-    assert rel_l2(g, go) <= tol(precision)
+        assert close(ctx.get_field(L.FIELD_ADJOINT0).reshape(om.rho[0].shape), om.rho[0]) <= tol(precision)
+    assert close(g, go) <= tol(precision)
     ginf_o = float(sp.include(go, N).abs().max())
     assert abs(ginf - ginf_o) <= tol(precision) * ginf_o * 10
 
@@ -122,13 +122,13 @@ def test_large_displacement_parity(variant):
     ctx.state_solve(dev(v, ctx))
     om.setup(v)
     om.state()
-    assert rel_l2(ctx.get_field(L.FIELD_DEP_BACKWARD).reshape(om.Xb.shape), om.Xb) <= 1e-5
+    assert close(ctx.get_field(L.FIELD_DEP_BACKWARD).reshape(om.Xb.shape), om.Xb) <= 1e-5
     g, _ = ctx.adjoint_solve()
     om.adjoint()
-    assert rel_l2(g, om.gradient()) <= 1e-5
+    assert close(g, om.gradient()) <= 1e-5
     from paper_2006_06823_amd import synthetic as syn
     dv = syn.random_bl_coefficients(3, K, 12)
-    assert rel_l2(ctx.hess_matvec(dev(dv, ctx)), om.hess_matvec(dv)) <= 1e-5
+    assert close(ctx.hess_matvec(dev(dv, ctx)), om.hess_matvec(dv)) <= 1e-5
 
 
 @pytest.mark.parametrize("variant", [1, 3])
@@ -142,14 +142,14 @@ def test_hess_matvec_parity(variant, dim, N, K, Nt, precision):
     dv = syn.random_bl_coefficients(dim, K, 11)
     h = ctx.hess_matvec(dev(dv, ctx))
     ho = om.hess_matvec(dv)
-    assert rel_l2(h, ho) <= tol(precision)
+    assert close(h, ho) <= tol(precision)
     dm, dl = om.last_inc
     for n in (1, Nt // 2, Nt):
         got = ctx.get_field(L.FIELD_INC_STATE, n).reshape(dm[n].shape)
-        assert rel_l2(got, dm[n]) <= tol(precision)
+        assert close(got, dm[n]) <= tol(precision)
     for n in (0, Nt // 2, Nt):
         got = ctx.get_field(L.FIELD_INC_ADJOINT, n).reshape(dl[n].shape)
-        assert rel_l2(got, dl[n]) <= tol(precision)
+        assert close(got, dl[n]) <= tol(precision)
 
 
 # image-transport Hessian on grids with a long first axis (first-axis contractions of one and two
@@ -167,12 +167,12 @@ def test_hess_matvec_parity_long_first_axis(N, K, Nt, cfl):
     from paper_2006_06823_amd import synthetic as syn
     dv = syn.random_bl_coefficients(3, K, 13)
     h = ctx.hess_matvec(dev(dv, ctx))
-    assert rel_l2(h, om.hess_matvec(dv)) <= 1e-5
+    assert close(h, om.hess_matvec(dv)) <= 1e-5
     dm, dl = om.last_inc
     for n in (1, Nt):
-        assert rel_l2(ctx.get_field(L.FIELD_INC_STATE, n).reshape(dm[n].shape), dm[n]) <= 1e-5
+        assert close(ctx.get_field(L.FIELD_INC_STATE, n).reshape(dm[n].shape), dm[n]) <= 1e-5
     for n in (0, Nt - 1):
-        assert rel_l2(ctx.get_field(L.FIELD_INC_ADJOINT, n).reshape(dl[n].shape), dl[n]) <= 1e-5
+        assert close(ctx.get_field(L.FIELD_INC_ADJOINT, n).reshape(dl[n].shape), dl[n]) <= 1e-5
 
 
 @pytest.mark.parametrize("variant", [1, 3])
@@ -186,10 +186,10 @@ def test_hess_matvec_parity_separable_dft_path(variant):
     om.state()
     g, _ = ctx.adjoint_solve()
     om.adjoint()
-    assert rel_l2(g, om.gradient()) <= 1e-5
+    assert close(g, om.gradient()) <= 1e-5
     from paper_2006_06823_amd import synthetic as syn
     dv = syn.random_bl_coefficients(3, K, 14)
-    assert rel_l2(ctx.hess_matvec(dev(dv, ctx)), om.hess_matvec(dv)) <= 1e-5
+    assert close(ctx.hess_matvec(dev(dv, ctx)), om.hess_matvec(dv)) <= 1e-5
 
 
 # degenerate and odd configurations: one time step, a band with a single real mode on one axis
@@ -206,10 +206,10 @@ def test_small_and_odd_configurations(variant, N, K, Nt):
     om.state()
     g, _ = ctx.adjoint_solve()
     om.adjoint()
-    assert rel_l2(g, om.gradient()) <= 1e-5
+    assert close(g, om.gradient()) <= 1e-5
     from paper_2006_06823_amd import synthetic as syn
     dv = syn.random_bl_coefficients(3, K, 15)
-    assert rel_l2(ctx.hess_matvec(dev(dv, ctx)), om.hess_matvec(dv)) <= 1e-5
+    assert close(ctx.hess_matvec(dev(dv, ctx)), om.hess_matvec(dv)) <= 1e-5
 
 
 def test_dot_fp64_reduction():
@@ -259,7 +259,7 @@ def test_bf16_dft_parity_walking_expansion():
         f = rng.standard_normal((nf,) + N)
         got = ctx.project(dev(f, ctx), nf) if nf > 1 else ctx.project(dev(f[0], ctx), 1)
         ref = sp.project(torch.tensor(f), K)
-        assert rel_l2(got.reshape(ref.shape), ref) <= 5e-4
+        assert close(got.reshape(ref.shape), ref) <= 5e-4
         c = rng.standard_normal((nf,) + K)
         for j, k in enumerate(K):
             sl = [slice(None)] * 4
@@ -267,7 +267,7 @@ def test_bf16_dft_parity_walking_expansion():
             c[tuple(sl)] = 0.0
         got = ctx.include(dev(c, ctx), nf) if nf > 1 else ctx.include(dev(c[0], ctx), 1)
         ref = sp.include(torch.tensor(c), N)
-        assert rel_l2(got.reshape(ref.shape), ref) <= 5e-4
+        assert close(got.reshape(ref.shape), ref) <= 5e-4
 
 
 @pytest.mark.parametrize("dim,N,K,Nt,precision", CASES)

@@ -33,8 +33,31 @@ def test_binding_loads_without_gpu():
     if not os.path.exists(L.LIB_PATH):
         pytest.skip("library not built")
     lib = L.load_library()
-    assert lib.lddmm_bl_last_error(None) == b"null context"
     assert lib.lddmm_bl_destroy(None) == -1
+    # a context-free call records its error text per thread (argument checks run before any HIP call)
+    p = L.Params()
+    p.dim = 5
+    h = ctypes.c_void_p()
+    assert lib.lddmm_bl_create(ctypes.byref(p), None, ctypes.byref(h)) == -1
+    assert b"dim" in lib.lddmm_bl_last_error(None)
+    opts = L.GNOpts(1, 1, 1e-3, 0.0, 0, 0.0)
+    assert lib.lddmm_bl_gn_solve_batched(None, 0, None, None, None, ctypes.byref(opts), None, None) == -1
+    assert b"count" in lib.lddmm_bl_last_error(None)
+
+
+def test_report_layout_matches_the_header():
+    """The decision log and Jacobian extrema sit where the header puts them (ctypes mirror)."""
+    text = open(HEADER).read()
+    assert "#define LDDMM_BL_LOG_MAX 64" in text and L.LOG_MAX == 64
+    names = [n for n, _ in L.GNReport._fields_]
+    assert names[:11] == ["gn_iters", "pcg_iters_total", "backtracks", "hess_matvecs", "E0", "E", "mse_rel",
+                          "grad_inf_rel", "det_min", "det_max", "seconds"]
+    assert names[11:] == ["log_count", "log_pcg", "log_negcurv", "log_backtracks"]
+    r = L.GNReport()
+    r.log_count = 2
+    r.log_pcg[0], r.log_negcurv[0], r.log_backtracks[0] = 5, 0, 1
+    r.log_pcg[1], r.log_negcurv[1], r.log_backtracks[1] = 3, 1, -1
+    assert r.as_dict()["decisions"] == [(5, 0, 1), (3, 1, -1)]
 
 
 def test_committed_warm_start_weights_match_the_architecture():
