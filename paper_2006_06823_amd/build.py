@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblddmm_bl.so")
-SOURCES = ["dft.hip", "dft_fused.hip", "fused_back.hip", "grid.hip", "brick.hip", "reduce.hip", "prof.hip", "tune.hip", "solver.hip", "api.hip", "nn.hip", "nn_api.hip"]
+SOURCES = ["dft.hip", "dft_fused.hip", "dft_planes.hip", "grid.hip", "brick.hip", "reduce.hip", "prof.hip", "tune.hip", "solver.hip", "api.hip", "nn.hip", "nn_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

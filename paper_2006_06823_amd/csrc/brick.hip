@@ -13,6 +13,8 @@
 // values of a node together with its other pointwise operands, fusing the
 // SL-RK2 step update of each equation into the same pass.
 #include "kernels.h"
+
+#include <type_traits>
 #include "prof.h"
 #include "tune.h"
 
@@ -121,6 +123,12 @@ __device__ __noinline__ float eval_global(const float* __restrict__ c, float x0,
   return acc;
 }
 
+// Epilogues that also take the interpolant at the node itself (NODE = true, accum_node).
+template <class E, class = void>
+struct HasNode : std::false_type {};
+template <class E>
+struct HasNode<E, std::void_t<decltype(E::NODE)>> : std::bool_constant<E::NODE> {};
+
 // Generic brick kernel.  Epi provides:
 //   NF, GROUPS, GSIZE and field(g, k): the NF coefficient fields (stacked with
 //       stride P in `coef`) are staged GSIZE at a time, GROUPS times;
@@ -216,6 +224,17 @@ __global__ __launch_bounds__(TL::NTHR) void k_brick(Epi epi, const float* __rest
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
       if (!live[j]) continue;
+      if constexpr (HasNode<Epi>::value) {
+        // the interpolant at the node itself: taps node-1 .. node+2, always inside the brick
+        const int q = tid + NTHR * j;
+        const int l2 = q % TX2, l1 = (q / TX2) % TX1, l0 = q / (TX1 * TX2);
+        float wn[4];
+        bspline_weights(0.f, wn);
+#pragma unroll
+        for (int k = 0; k < GS; ++k)
+          epi.accum_node(st[j], Epi::field(grp, k),
+                         eval_brick<B1, LD2>(br + k * VOL, l0 + HALO - 1, l1 + HALO - 1, l2 + HALO - 1, wn, wn, wn));
+      }
       const float f0 = floorf(x[j][0]), f1 = floorf(x[j][1]), f2 = floorf(x[j][2]);
       const int s0 = static_cast<int>(f0) - 1 - o0, s1 = static_cast<int>(f1) - 1 - o1,
                 s2 = static_cast<int>(f2) - 1 - o2;
@@ -286,6 +305,32 @@ struct EpiInterp : DispPos, OneGroup<NFv> {
   }
 };
 
+// out_f = P(c_f) o X - P(c_f)(x): the interpolant's change along the characteristic (projected, it is
+// the step's increment of a band-limited field, whose own projection the caller adds back exactly)
+template <int NFv>
+struct EpiInterpDiff : DispPos, OneGroup<NFv> {
+  static constexpr int NF = NFv;
+  static constexpr bool NODE = true;
+  static_assert(NFv != 2, "two fields are staged interleaved");
+  struct State {
+    float o[NF], n[NF];
+  };
+  float* __restrict__ out;
+  __device__ __forceinline__ void init(int64_t, State&) const {}
+  __device__ __forceinline__ void accum(State& s, int f, float v) const {
+#pragma unroll
+    for (int i = 0; i < NF; ++i) s.o[i] = (f == i) ? v : s.o[i];
+  }
+  __device__ __forceinline__ void accum_node(State& s, int f, float v) const {
+#pragma unroll
+    for (int i = 0; i < NF; ++i) s.n[i] = (f == i) ? v : s.n[i];
+  }
+  __device__ __forceinline__ void emit(int64_t p, const State& s) const {
+#pragma unroll
+    for (int f = 0; f < NF; ++f) out[f * P + p] = s.o[f] - s.n[f];
+  }
+};
+
 // band-limited adjoint Heun step: out_f = cA_f o X + dt/2 divv (cB_f o X)
 // FS: fields between cA_i and cB_i (NC, or 3 for one component of a three-component pair of stacks)
 template <int NC, int FS = NC>
@@ -334,60 +379,6 @@ struct EpiAdjointGrid : DispPos, OneGroup<2> {
   }
   __device__ __forceinline__ void accum(State& s, int f, float v) const { s.o += (f == 0 ? s.ca : s.cb) * v; }
   __device__ __forceinline__ void emit(int64_t p, const State& s) const { out[p] = s.o; }
-};
-
-// image-transport incremental state: out0 = c o X, out1 = -G . dv
-// (the source is formed in init, before the brick is staged, so that its six loads overlap the
-// staging and the interpolation instead of following them)
-struct EpiIncStateV1 : DispPos, OneGroup<1> {
-  static constexpr int NF = 1;
-  struct State {
-    float o, src;
-  };
-  float* __restrict__ out;
-  const float* __restrict__ G;
-  const float* __restrict__ dv;
-  float hdt;
-  __device__ __forceinline__ void init(int64_t p, State& s) const {
-    s.src = -(G[p] * dv[p] + G[P + p] * dv[P + p] + G[2 * P + p] * dv[2 * P + p]);
-  }
-  __device__ __forceinline__ void accum(State& s, int, float v) const { s.o = v; }
-  __device__ __forceinline__ void emit(int64_t p, const State& s) const {
-    out[p] = s.o + hdt * s.src;
-    out[P + p] = s.src;
-  }
-};
-
-// deformation-state incremental state: out[0..2] = c_f o X, out[3..5] = dv - Du dv
-struct EpiIncStateV3 : DispPos, OneGroup<3> {
-  static constexpr int NF = 3;
-  struct State {
-    float o[3], src[3];
-  };
-  float* __restrict__ out;
-  const float* __restrict__ Du;
-  const float* __restrict__ dv;
-  float hdt;
-  __device__ __forceinline__ void init(int64_t p, State& s) const {
-    const float w0 = dv[p], w1 = dv[P + p], w2 = dv[2 * P + p];
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      const float* D = Du + (int64_t)(3 * i) * P;
-      const float wi = i == 0 ? w0 : (i == 1 ? w1 : w2);
-      s.src[i] = wi - (D[p] * w0 + D[P + p] * w1 + D[2 * P + p] * w2);
-    }
-  }
-  __device__ __forceinline__ void accum(State& s, int f, float v) const {
-#pragma unroll
-    for (int i = 0; i < 3; ++i) s.o[i] = (f == i) ? v : s.o[i];
-  }
-  __device__ __forceinline__ void emit(int64_t p, const State& s) const {
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      out[i * P + p] = s.o[i] + hdt * s.src[i];
-      out[(3 + i) * P + p] = s.src[i];
-    }
-  }
 };
 
 // characteristics: X* = x + sdt v, X - x = sdt/2 (v + v o X*) (grid units)
@@ -518,6 +509,22 @@ void brick_interp(float* out, const float* coef, int nf, const float* disp, cons
   }
 }
 
+void brick_interp_diff(float* out, const float* coef, int nf, const float* disp, const Dims& d, hipStream_t s) {
+  const std::string name_ = nm("k_interp_diff") + std::to_string(nf);
+  const double bytes_ = (3.0 + 2.0 * nf) * d.P * 4;
+  if (nf == 1) {
+    EpiInterpDiff<1> e;
+    e.disp = disp, e.P = d.P, e.out = out;
+    launch(name_, bytes_, e, coef, d, s);
+  } else if (nf == 3) {
+    EpiInterpDiff<3> e;
+    e.disp = disp, e.P = d.P, e.out = out;
+    launch(name_, bytes_, e, coef, d, s);
+  } else {
+    throw ArgError("brick_interp_diff: nf must be 1 or 3");
+  }
+}
+
 void brick_bl_adjoint_step(float* out, const float* cAB, int nc, const float* disp, const float* divv,
                            const Dims& d, float dt, hipStream_t s) {
   const std::string name_ = nm("k_bl_adjoint_step") + std::to_string(nc);
@@ -547,24 +554,6 @@ void brick_adjoint_grid_step(float* out, const float* c12, const float* disp, co
   EpiAdjointGrid e;
   e.disp = disp, e.P = d.P, e.out = out, e.divv = divv, e.dt = dt;
   launch(name_, bytes_, e, c12, d, s);
-}
-
-void brick_inc_state_v1(float* out, const float* c, const float* disp, const float* G, const float* dv, float hdt,
-                        const Dims& d, hipStream_t s) {
-  const std::string name_ = nm("k_inc_state_v1");
-  const double bytes_ = 12.0 * d.P * 4;
-  EpiIncStateV1 e;
-  e.disp = disp, e.P = d.P, e.out = out, e.G = G, e.dv = dv, e.hdt = hdt;
-  launch(name_, bytes_, e, c, d, s);
-}
-
-void brick_inc_state_v3(float* out, const float* c, const float* disp, const float* Du, const float* dv, float hdt,
-                        const Dims& d, hipStream_t s) {
-  const std::string name_ = nm("k_inc_state_v3");
-  const double bytes_ = 24.0 * d.P * 4;
-  EpiIncStateV3 e;
-  e.disp = disp, e.P = d.P, e.out = out, e.Du = Du, e.dv = dv, e.hdt = hdt;
-  launch(name_, bytes_, e, c, d, s);
 }
 
 void brick_characteristics(float* disp, const float* v, const float* cv, const Dims& d, float dt, int dir,

@@ -179,20 +179,6 @@ __global__ void k_bl_adjoint_step(T* __restrict__ out, const T* __restrict__ cA,
 }
 
 template <typename T>
-__global__ void k_inc_state_v1(T* __restrict__ out, const T* __restrict__ c, const T* __restrict__ disp,
-                               const T* __restrict__ G, const T* __restrict__ dv, T hdt, int n0, int n1, int n2) {
-  const int64_t P = (int64_t)n0 * n1 * n2;
-  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (p >= P) return;
-  const GridIdx g = unflatten(p, n1, n2);
-  Taps<T> t;
-  t.set(g.i0 + disp[p], g.i1 + disp[P + p], g.i2 + disp[2 * P + p], n0, n1, n2);
-  const T src = -(G[p] * dv[p] + G[P + p] * dv[P + p] + G[2 * P + p] * dv[2 * P + p]);
-  out[p] = t.eval(c, n1, n2) + hdt * src;
-  out[P + p] = src;
-}
-
-template <typename T>
 __device__ __forceinline__ void v3_src_point(T o[3], const T* __restrict__ Du, const T* __restrict__ dv,
                                              int64_t p, int64_t P) {
   const T w0 = dv[p], w1 = dv[P + p], w2 = dv[2 * P + p];
@@ -201,24 +187,6 @@ __device__ __forceinline__ void v3_src_point(T o[3], const T* __restrict__ Du, c
     const T* D = Du + (int64_t)(3 * i) * P;  // d_j u_i at D[j * P]
     o[i] = (i == 0 ? w0 : (i == 1 ? w1 : w2)) - (D[p] * w0 + D[P + p] * w1 + D[2 * P + p] * w2);
   }
-}
-
-template <typename T>
-__global__ void k_inc_state_v3(T* __restrict__ out, const T* __restrict__ c, const T* __restrict__ disp,
-                               const T* __restrict__ Du, const T* __restrict__ dv, T hdt, int n0, int n1, int n2) {
-  const int64_t P = (int64_t)n0 * n1 * n2;
-  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (p >= P) return;
-  const GridIdx g = unflatten(p, n1, n2);
-  Taps<T> t;
-  t.set(g.i0 + disp[p], g.i1 + disp[P + p], g.i2 + disp[2 * P + p], n0, n1, n2);
-  T o[3];
-  v3_src_point(o, Du, dv, p, P);
-#pragma unroll
-  for (int f = 0; f < 3; ++f) out[f * P + p] = t.eval(c + f * P, n1, n2) + hdt * o[f];
-  out[3 * P + p] = o[0];
-  out[4 * P + p] = o[1];
-  out[5 * P + p] = o[2];
 }
 
 template <typename T>
@@ -695,24 +663,6 @@ void bl_adjoint_step(T* out, const T* cA, const T* cB, int nf, const T* disp, co
 }
 
 template <typename T>
-void inc_state_v1(T* out, const T* c, const T* disp, const T* G, const T* dv, T hdt, const Dims& d, hipStream_t s) {
-  if constexpr (std::is_same_v<T, float>) {
-    if (brick_ok(d)) return brick_inc_state_v1(out, c, disp, G, dv, hdt, d, s);
-  }
-  prof::launch("k_inc_state_v1<" + std::string(prof::tname<T>()) + ">", 12.0 * d.P * sizeof(T), 0.0, k_inc_state_v1<T>, grid_for(d.P), dim3(kBlock), 0, s, out, c, disp, G, dv, hdt, d.n[0], d.n[1], d.n[2]);
-  LDDMM_LAUNCH_CHECK();
-}
-
-template <typename T>
-void inc_state_v3(T* out, const T* c, const T* disp, const T* Du, const T* dv, T hdt, const Dims& d, hipStream_t s) {
-  if constexpr (std::is_same_v<T, float>) {
-    if (brick_ok(d)) return brick_inc_state_v3(out, c, disp, Du, dv, hdt, d, s);
-  }
-  prof::launch("k_inc_state_v3<" + std::string(prof::tname<T>()) + ">", 24.0 * d.P * sizeof(T), 0.0, k_inc_state_v3<T>, grid_for(d.P), dim3(kBlock), 0, s, out, c, disp, Du, dv, hdt, d.n[0], d.n[1], d.n[2]);
-  LDDMM_LAUNCH_CHECK();
-}
-
-template <typename T>
 void v3_source(T* out, const T* Du, const T* dv, const Dims& d, hipStream_t s) {
   prof::launch("k_v3_source<" + std::string(prof::tname<T>()) + ">", 15.0 * d.P * sizeof(T), 0.0, k_v3_source<T>, grid_for(d.P), dim3(kBlock), 0, s, out, Du, dv, d.P);
   LDDMM_LAUNCH_CHECK();
@@ -798,8 +748,6 @@ void zero(T* p, int64_t n, hipStream_t s) {
                                      hipStream_t);                                                      \
   template void bl_adjoint_step<T>(T*, const T*, const T*, int, const T*, const T*, const Dims&, T,     \
                                    hipStream_t);                                                        \
-  template void inc_state_v1<T>(T*, const T*, const T*, const T*, const T*, T, const Dims&, hipStream_t);  \
-  template void inc_state_v3<T>(T*, const T*, const T*, const T*, const T*, T, const Dims&, hipStream_t);  \
   template void v3_source<T>(T*, const T*, const T*, const Dims&, hipStream_t);                         \
   template void v1_source<T>(T*, const T*, const T*, const Dims&, hipStream_t);                         \
   template void v1_products<T>(T*, const T*, const T*, const T*, const Dims&, hipStream_t);             \

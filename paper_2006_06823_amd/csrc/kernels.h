@@ -45,18 +45,83 @@ int pi_ba_splits(int n1);
 void iota_ab(const IotaABArgs& a, int nf, hipStream_t s);
 void pi_ba(const PiBAArgs& a, int nf, hipStream_t s);
 
-// fused image-transport backward grid pass (fused_back.hip), float
-struct BackV1Args {
-  const float* t2;    // [k0][C] inner-axis slab of iota(dl~), C = n1 n2
-  const float* divv;  // [n0][C]
-  const float* G;     // [3][n0][C]
-  const float* B0;    // [n0][k0] axis-0 basis
-  float* out;         // [4][k0][C] axis-0 projections of e divv, e G_0, e G_1, e G_2
-  int n0, k0, C;
-  float inv_n0;
+// plane-wise truncated DFT (dft_planes.hip), float.  Plane-band arrays are [x0][a1][a2] with
+// C = K1 K2 columns per grid plane.
+// expansion of planes: out[f][x0][x1][x2] = sum_{a1,a2} w1t_f[a1][x1] T_f[x0][a1][a2] w2t_f[a2][x2]
+struct PlaneExpandArgs {
+  const float* T[kMaxFields];    // [n0][k1][k2] per field
+  const float* w1t[kMaxFields];  // [k1][n1]
+  const float* w2t[kMaxFields];  // [k2][n2]
+  float* out;                    // [nf][n0][n1][n2]
+  int nf, n0, n1, n2, k1, k2;
+  int g, ntask;  // x2 tiles per wave and wave tasks (set by the launcher)
 };
-bool back_v1_ok(int n0, int k0);
-void back_v1(const BackV1Args& a, hipStream_t s);
+// reduction of planes: part[f][x0][a1][a2] = sum_{x1,x2} p1t[x1][a1] v_f(x0, x1, x2) p2t[x2][a2], with the
+// grid value v_f of the mode: a plain field, or a pointwise product of fields of the product grid
+enum { kRedPlain = 0, kRedV1Products = 1, kRedV3Products = 2, kRedV1Source = 3, kRedV3Source = 4 };
+struct PlaneReduceArgs {
+  const float* in;    // plain: [nf][P]
+  const float* e;     // products: e (1 or 3 fields); sources: dv (3 fields)
+  const float* divv;  // products: div v
+  const float* G;     // v1 products: G_n [3]; v3 products: D u_n [9]; sources: all nodes [nn][3] / [nn][9]
+  const float* p1t;   // [n1][k1]
+  const float* p2t;   // [n2][k2]
+  float* part;        // [nf][n0][k1][k2]
+  int mode, nf, n0, n1, n2, k1, k2;
+  int64_t P;          // grid points per field
+};
+// first-axis stages (see dft_planes.hip): F finishes nin projections, P forms nout plane-band arrays
+struct Axis0Out {
+  const float* w0t;  // [k0][n0t] first-axis expansion matrix of the target grid
+  float* T;         // [n0t][C]
+  int n0t;
+  int s1, s2;       // finished fields of F used as sources (-1: none)
+  const float* g1;  // band arrays used as sources (null: none)
+  const float* g2;
+  float c1, c2;     // source = c1 (s1 + g1) + c2 (s2 + g2)
+};
+struct Axis0Args {
+  const float* part[kMaxFields];  // [n0][C]
+  const float* p0t;               // [n0][k0]
+  float* out[kMaxFields];         // [k0][C]: out = beta out + alpha r + gamma z
+  float* out2[kMaxFields];        // optional second copy of out
+  const float* z[kMaxFields];
+  float alpha[kMaxFields], beta[kMaxFields], gamma[kMaxFields];
+  Axis0Out o[kMaxFields];
+  int nin, nout, n0, k0, C;
+  const float* zeros;  // >= k0 C zeros, read in place of absent sources
+};
+// kernel view of Axis0Args: one descriptor row per workgroup row (built by plane_axis0)
+struct Axis0Kernel {
+  static constexpr int kRows = 2 * kMaxFields;
+  struct Field {
+    const float* part;
+    float* out;
+    float* out2;
+    const float* z;
+    float alpha, beta, gamma;
+  };
+  struct Out {
+    const float* w0t;
+    float* T;
+    const float* g1;
+    const float* g2;
+    float c1, c2, cf;
+    int n0t;
+  };
+  struct Row {
+    int f, np;
+    Out p[2];
+  };
+  const float* p0t;
+  int n0, k0, C;
+  Field fld[kMaxFields];
+  Row row[kRows];
+};
+bool planes_ok(const Dims& d);
+void plane_expand(const PlaneExpandArgs& a, hipStream_t s);
+void plane_reduce(const PlaneReduceArgs& a, hipStream_t s);
+void plane_axis0(const Axis0Args& a, hipStream_t s);
 
 // ---- band-limited coefficient kernels (grid.hip) ----------------------------
 // out = a x + b y (n elements; y may be null when b == 0)
@@ -91,13 +156,6 @@ void adjoint_grid_step(T* out, const T* c1, const T* c2, const T* disp, const T*
 template <typename T>
 void bl_adjoint_step(T* out, const T* cA, const T* cB, int nf, const T* disp, const T* divv, const Dims& d,
                      T dt, hipStream_t s);
-// variant-1 incremental state step: out0 = c o X, out1 = -G . dv
-template <typename T>
-// out[0] = c o X + hdt s, out[1] = s with s = -G . dv (the step's trapezoid sum and its source)
-void inc_state_v1(T* out, const T* c, const T* disp, const T* G, const T* dv, T hdt, const Dims& d, hipStream_t s);
-// variant-3 incremental state step: out[0..2] = c_f o X + hdt s_f, out[3..5] = s = dv - Du dv
-template <typename T>
-void inc_state_v3(T* out, const T* c, const T* disp, const T* Du, const T* dv, T hdt, const Dims& d, hipStream_t s);
 // variant-3 state source at node n: out = dv - Du dv  (3 comps)
 template <typename T>
 void v3_source(T* out, const T* Du, const T* dv, const Dims& d, hipStream_t s);
@@ -141,14 +199,12 @@ int brick_tile_count();  // workgroup tile candidates of the brick kernels
 // synthetic sub-voxel displacement written to the scratch `disp`) and caches the fastest
 void brick_autotune(float* out, const float* coef, float* disp, const Dims& d, hipStream_t s);
 void brick_interp(float* out, const float* coef, int nf, const float* disp, const Dims& d, hipStream_t s);
+// out_f = P(c_f) o X - P(c_f) at the nodes (nf 1 or 3)
+void brick_interp_diff(float* out, const float* coef, int nf, const float* disp, const Dims& d, hipStream_t s);
 void brick_bl_adjoint_step(float* out, const float* cAB, int nc, const float* disp, const float* divv,
                            const Dims& d, float dt, hipStream_t s);
 void brick_adjoint_grid_step(float* out, const float* c12, const float* disp, const float* divv, const Dims& d,
                              float dt, hipStream_t s);
-void brick_inc_state_v1(float* out, const float* c, const float* disp, const float* G, const float* dv, float hdt,
-                        const Dims& d, hipStream_t s);
-void brick_inc_state_v3(float* out, const float* c, const float* disp, const float* Du, const float* dv, float hdt,
-                        const Dims& d, hipStream_t s);
 void brick_characteristics(float* disp, const float* v, const float* cv, const Dims& d, float dt, int dir,
                            hipStream_t s);
 

@@ -8,40 +8,9 @@
 
 #include "../../include/lddmm_bl.h"
 #include "kernels.h"
+#include "plan.h"
 
 namespace lddmm {
-
-// Device allocation owned by the solver.
-template <typename T>
-class DevBuf {
- public:
-  DevBuf() = default;
-  explicit DevBuf(int64_t n) { alloc(n); }
-  ~DevBuf() { release(); }
-  DevBuf(const DevBuf&) = delete;
-  DevBuf& operator=(const DevBuf&) = delete;
-  void alloc(int64_t n) {
-    release();
-    if (n <= 0) return;
-    if (hipMalloc(reinterpret_cast<void**>(&p_), static_cast<size_t>(n) * sizeof(T)) != hipSuccess) {
-      p_ = nullptr;
-      (void)hipGetLastError();
-      throw std::bad_alloc();
-    }
-    n_ = n;
-  }
-  void release() {
-    if (p_) (void)hipFree(p_);
-    p_ = nullptr;
-    n_ = 0;
-  }
-  T* get() const { return p_; }
-  int64_t size() const { return n_; }
-
- private:
-  T* p_ = nullptr;
-  int64_t n_ = 0;
-};
 
 // Type-erased interface used by the C ABI.
 class SolverBase {

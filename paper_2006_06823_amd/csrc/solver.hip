@@ -19,6 +19,16 @@
 //  - time integrals of the gradient and Hessian terms: trapezoid rule;
 //  - deformation-state gradient term (Du)^T rho, Gauss-Newton Hessian term
 //    (Du)^T drho, final conditions with g1 = (grad P(I0)) o phi(1).
+//
+// Work placement.  Every truncated product of two band-limited fields (the
+// sources f = x * div~ v~, the gradient and Hessian terms x * grad~ m~_n and
+// (D~u~_n)^T x, the incremental source -grad~ m~_n . dv~ and dv~ - D~u~_n dv~) is
+// formed on the product grid of the second plan, where it is exact and costs a
+// small fraction of the image grid.  On the image grid remain the semi-Lagrangian
+// interpolations, the image-transport state and adjoint, and the final warp.  In
+// the incremental state the source does not depend on the unknown, so by
+// linearity pi[c o X + dt/2 s_{n+1}] = pi[c o X] + dt/2 f~_{n+1}: every f~_n is
+// formed before the sweep and each step projects one interpolated field.
 #include <chrono>
 #include <cmath>
 #include <cstdlib>
@@ -30,33 +40,6 @@
 #include "solver.h"
 
 namespace lddmm {
-
-namespace {
-
-constexpr double kTwoPi = 6.283185307179586476925286766559;
-
-// per-axis matrices: B, S B, dB as [n][k]; B^T / n as [k][n]; the transposes of the first three
-// as [k][n] and B / n as [n][k], so the fused kernels read every operand with coalesced rows
-enum MatKind { kPlain = 0, kPref = 1, kDeriv = 2, kProj = 3, kPlainT = 4, kPrefT = 5, kDerivT = 6, kProjT = 7 };
-constexpr int kNumMats = 8;
-
-inline int slot_freq(int a, int K) {
-  if (a == 0) return 0;
-  if (K % 2 == 0 && a == K - 1) return -1;  // pad
-  return (a + 1) / 2;
-}
-
-// value (or derivative) of the real basis function of slot a at x in [0,1)
-inline double basis(int a, int K, double x, bool deriv) {
-  const int k = slot_freq(a, K);
-  if (k < 0) return 0.0;
-  if (k == 0) return deriv ? 0.0 : 1.0;
-  const double th = kTwoPi * k * x, r2 = std::sqrt(2.0);
-  if (a & 1) return deriv ? -kTwoPi * k * r2 * std::sin(th) : r2 * std::cos(th);
-  return deriv ? kTwoPi * k * r2 * std::cos(th) : r2 * std::sin(th);
-}
-
-}  // namespace
 
 template <typename T>
 class Solver final : public SolverBase {
@@ -80,6 +63,9 @@ class Solver final : public SolverBase {
     }
     d_.P = (int64_t)d_.n[0] * d_.n[1] * d_.n[2];
     d_.Q = (int64_t)d_.k[0] * d_.k[1] * d_.k[2];
+    ds_ = d_;
+    for (int a = 0; a < 3; ++a) ds_.n[a] = product_grid_size(d_.n[a], d_.k[a]);
+    ds_.P = (int64_t)ds_.n[0] * ds_.n[1] * ds_.n[2];
     nt_ = p.nt;
     dt_ = T(1.0 / p.nt);
     variant_ = p.variant;
@@ -87,7 +73,9 @@ class Solver final : public SolverBase {
     s_ = p.s;
     sigma2_ = p.sigma2;
     bf16_ = std::is_same_v<T, float> && p.precision == LDDMM_BL_BF16_DFT;
-    build_matrices();
+    full_.init(d_, bf16_, &st_);
+    sm_.init(ds_, bf16_, &st_);
+    build_symbols();
     allocate();
     autotune();
   }
@@ -134,12 +122,7 @@ class Solver final : public SolverBase {
   void hess_matvec(const void* dv, void* hdv) override {
     require_state();
     to_internal(dvbl_.get(), static_cast<const T*>(dv), 3);
-    if (use_graphs()) {
-      if (!mv_exec_) capture_matvec();
-      LDDMM_HIP(hipGraphLaunch(mv_exec_, st_));
-    } else {
-      run_matvec(dvbl_.get(), hbl_.get());
-    }
+    matvec_graph();
     from_internal(static_cast<T*>(hdv), hbl_.get(), 3);
     sync();
   }
@@ -167,8 +150,7 @@ class Solver final : public SolverBase {
       displacement_only(tmpbl_.get());
       u1 = tmpbl_.get();
     }
-    stack_deriv9(u1, stk_.get());
-    iota9_deriv(stk_.get(), S9());
+    full_.iota_grad(u1, S9(), 3);
     double* det = detmap;
     if (!det) {
       if (!det_.get()) det_.alloc(d_.P);
@@ -182,14 +164,14 @@ class Solver final : public SolverBase {
 
   void project(const void* grid, void* bl, int ncomp) override {
     check_ncomp(ncomp);
-    pi(static_cast<const T*>(grid), static_cast<T*>(bl), ncomp);
+    full_.pi(static_cast<const T*>(grid), static_cast<T*>(bl), ncomp);
     sync();
   }
 
   void include(const void* bl, void* grid, int ncomp) override {
     check_ncomp(ncomp);
     int kinds[kMaxFields][3] = {};
-    iota(static_cast<const T*>(bl), static_cast<T*>(grid), ncomp, kinds);
+    full_.iota(static_cast<const T*>(bl), static_cast<T*>(grid), ncomp, kinds);
     sync();
   }
 
@@ -201,35 +183,7 @@ class Solver final : public SolverBase {
 
  private:
   // ------------------------------------------------------------ set-up
-  void build_matrices() {
-    // per axis: B [n][k], Bs [n][k], Bd [n][k], P [k][n]
-    int64_t total = 0;
-    for (int a = 0; a < 3; ++a) total += (int64_t)kNumMats * d_.n[a] * d_.k[a];
-    std::vector<T> h(total);
-    int64_t o = 0;
-    for (int a = 0; a < 3; ++a) {
-      const int n = d_.n[a], k = d_.k[a];
-      for (int m = 0; m < kNumMats; ++m) mat_off_[a][m] = o + (int64_t)m * n * k;
-      for (int x = 0; x < n; ++x) {
-        const double xx = double(x) / n;
-        for (int s = 0; s < k; ++s) {
-          const double b = basis(s, k, xx, false);
-          const int f = slot_freq(s, k);
-          const double sc = f < 0 ? 0.0 : 3.0 / (2.0 + std::cos(kTwoPi * f / n));
-          h[mat_off_[a][kPlain] + (int64_t)x * k + s] = static_cast<T>(b);
-          h[mat_off_[a][kPref] + (int64_t)x * k + s] = static_cast<T>(b * sc);
-          h[mat_off_[a][kDeriv] + (int64_t)x * k + s] = static_cast<T>(basis(s, k, xx, true));
-          h[mat_off_[a][kProj] + (int64_t)s * n + x] = static_cast<T>(b / n);
-          h[mat_off_[a][kPlainT] + (int64_t)s * n + x] = static_cast<T>(b);
-          h[mat_off_[a][kPrefT] + (int64_t)s * n + x] = static_cast<T>(b * sc);
-          h[mat_off_[a][kDerivT] + (int64_t)s * n + x] = static_cast<T>(basis(s, k, xx, true));
-          h[mat_off_[a][kProjT] + (int64_t)x * k + s] = static_cast<T>(b / n);
-        }
-      }
-      o += (int64_t)kNumMats * n * k;
-    }
-    mats_.alloc(total);
-    LDDMM_HIP(hipMemcpy(mats_.get(), h.data(), total * sizeof(T), hipMemcpyHostToDevice));
+  void build_symbols() {
     // L~ symbol and its inverse; zero on pad slots
     std::vector<double> L(d_.Q), Li(d_.Q);
     for (int a0 = 0; a0 < d_.k[0]; ++a0)
@@ -252,11 +206,7 @@ class Solver final : public SolverBase {
   }
 
   void allocate() {
-    const int64_t P = d_.P, Q = d_.Q, nn = nt_ + 1;
-    const int64_t t_sz = (int64_t)kMaxFields * std::max<int64_t>((int64_t)d_.k[0] * d_.n[1] * d_.n[2],
-                                                                 (int64_t)d_.k[0] * d_.k[1] * d_.n[2]);
-    t1_.alloc(t_sz);
-    t2_.alloc(t_sz);
+    const int64_t P = d_.P, Q = d_.Q, Ps = ds_.P, nn = nt_ + 1;
     I0_.alloc(P);
     I1_.alloc(P);
     cI0_.alloc(P);
@@ -265,36 +215,36 @@ class Solver final : public SolverBase {
     gbl_.alloc(3 * Q);
     hbl_.alloc(3 * Q);
     tmpbl_.alloc(3 * Q);
-    stk_.alloc(kMaxFields * Q);
     blA_.alloc(kMaxFields * Q);
-    blB_.alloc(kMaxFields * Q);
-    blC_.alloc(kMaxFields * Q);
     acc_.alloc(3 * Q);
     vg_.alloc(3 * P);
     divv_.alloc(P);
     Xb_.alloc(3 * P);
     Xf_.alloc(3 * P);
-    dvg_.alloc(3 * P);
     scratch_.alloc(13 * P);  // 9P-field transforms + 4P staging
     inc_.alloc(nn * 3 * Q);
     incadj_.alloc(nn * 3 * Q);
+    fsrc_.alloc(nn * 3 * Q);
+    // product grid: div v, the state's gradient fields, the expanded operand and the products
+    divvs_.alloc(Ps);
+    dvs_.alloc(3 * Ps);
+    es_.alloc(3 * Ps);
+    prods_.alloc(std::max<int64_t>(kMaxFields, 3 * nn) * Ps);
     if (variant_ == LDDMM_BL_IMAGE_TRANSPORT) {
-      G_.alloc(nn * 3 * P);
       m_.alloc(nn * P);
+      mt_.alloc(nn * Q);
+      Gs_.alloc(nn * 3 * Ps);
       lam0_.alloc(P);
     } else {
       ubl_.alloc(nn * 3 * Q);
-      Du_.alloc(nn * 9 * P);
+      Dus_.alloc(nn * 9 * Ps);
       m1_.alloc(P);
       g1_.alloc(3 * P);
       rho_.alloc(nn * 3 * Q);
     }
     work_.alloc(reduce_work_size());
-    if (std::is_same<T, float>::value && d_.n[0] > 0) {
-      // partial projections of the split fused projection
-      const int64_t slabs = (int64_t)kMaxFields * d_.k[0];
-      pipart_.alloc(slabs * pi_ba_splits(d_.n[1]) * d_.k[1] * d_.k[2]);
-    }
+    // the incremental sources of every node are reduced in one launch (no allocation inside a capture)
+    if (sm_.planes()) sm_.reserve_parts(std::max<int>(kMaxFields, 3 * (int)nn));
     double* hp = nullptr;
     LDDMM_HIP(hipHostMalloc(reinterpret_cast<void**>(&hp), 8 * sizeof(double), hipHostMallocDefault));
     host_.reset(hp);
@@ -306,9 +256,9 @@ class Solver final : public SolverBase {
 
   // ------------------------------------------------------ graph capture
   // The Hessian matvec has no host synchronisation inside: its whole launch
-  // sequence (about 300 kernels for Nt = 10) is captured once into a HIP graph
-  // over the context's fixed buffers and replayed.  Needs a non-default stream;
-  // not used while per-kernel profiling is on.
+  // sequence (about 130 kernels for Nt = 10) is captured once into a HIP graph
+  // over the context's fixed buffers (input dvbl_, output hbl_) and replayed.
+  // Needs a non-default stream; not used while per-kernel profiling is on.
   bool use_graphs() const { return st_ != nullptr && graphs_enabled_ && !prof::enabled(); }
   void capture_matvec() {
     hipGraph_t g = nullptr;
@@ -328,9 +278,17 @@ class Solver final : public SolverBase {
       throw HipError(std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
     }
   }
+  // H dvbl_ -> hbl_ (replay of the captured graph, or eager launches)
+  void matvec_graph() {
+    if (use_graphs()) {
+      if (!mv_exec_) capture_matvec();
+      LDDMM_HIP(hipGraphLaunch(mv_exec_, st_));
+    } else {
+      run_matvec(dvbl_.get(), hbl_.get());
+    }
+  }
 
   // --------------------------------------------------------- small helpers
-  const T* mat(int axis, int kind) const { return mats_.get() + mat_off_[axis][kind]; }
   void copy(T* dst, const T* src, int64_t n) { copy_dev<T>(dst, src, n, st_); }
   void sync() { LDDMM_HIP(hipStreamSynchronize(st_)); }
   void check_ncomp(int ncomp) const {
@@ -341,6 +299,7 @@ class Solver final : public SolverBase {
   }
   T* S(int i) { return scratch_.get() + (int64_t)i * d_.P; }
   T* S9() { return scratch_.get(); }
+  T* Ps(int i) { return prods_.get() + (int64_t)i * ds_.P; }
   const T* m1_ptr() const {
     return variant_ == LDDMM_BL_IMAGE_TRANSPORT ? m_.get() + (int64_t)nt_ * d_.P : m1_.get();
   }
@@ -362,210 +321,41 @@ class Solver final : public SolverBase {
     else
       copy(dst, src + Q, 2 * Q);
   }
-
-  // ------------------------------------------------ truncated DFT (Section 2.2)
-  // axis contraction for the first-axis stages: float or split-bf16 matrix cores
-  void left(const T* in, T* out, const FieldMats<T>& W, int nb, int bpf, int M, int L, int C, int64_t sIb,
-            int64_t sOb, hipStream_t s) {
-    if constexpr (std::is_same_v<T, float>) {
-      if (bf16_) return dft_left_bf16(in, out, W, nb, bpf, M, L, C, sIb, sOb, s);
-    }
-    dft_left<T>(in, out, W, nb, bpf, M, L, C, sIb, sOb, s);
-  }
-  // iota of nf stacked BL fields; kinds[f][axis] picks plain / prefiltered / derivative matrices
-  void iota(const T* bl, T* out, int nf, const int kinds[][3]) {
-    const int n0 = d_.n[0], n1 = d_.n[1], n2 = d_.n[2], k0 = d_.k[0], k1 = d_.k[1], k2 = d_.k[2];
-    if constexpr (std::is_same_v<T, float>) {
-      if (fused_dft_ok(n1, n2, k1, k2)) {
-        const T* xs[kMaxFields];
-        for (int f = 0; f < nf; ++f) xs[f] = bl + f * d_.Q;
-        return iota_comb(xs, nullptr, nullptr, out, nf, kinds);
-      }
-    }
-    FieldMats<T> W{};
-    for (int f = 0; f < nf; ++f) W.w[f] = mat(2, kinds[f][2]);
-    dft_right(bl, t1_.get(), W, nf, k0 * k1, k2, n2, st_);
-    const bool skip0 = (n0 == 1 && k0 == 1);
-    T* dstB = skip0 ? out : t2_.get();
-    for (int f = 0; f < nf; ++f) W.w[f] = mat(1, kinds[f][1]);
-    left(t1_.get(), dstB, W, nf * k0, k0, n1, k1, n2, (int64_t)k1 * n2, (int64_t)n1 * n2, st_);
-    if (!skip0) {
-      for (int f = 0; f < nf; ++f) W.w[f] = mat(0, kinds[f][0]);
-      left(t2_.get(), out, W, nf, 1, n0, k0, n1 * n2, (int64_t)k0 * n1 * n2, d_.P, st_);
-    } else {
-      zero_degenerate_derivatives(out, nf, kinds);
-    }
-  }
-  // A 2D problem skips the 1 x 1 stage of its degenerate first axis; that stage is the identity
-  // except for a derivative along the axis, which vanishes: such fields are zero.
-  void zero_degenerate_derivatives(T* out, int nf, const int kinds[][3]) {
-    for (int f = 0; f < nf; ++f)
-      if (kinds[f][0] == kDeriv) zero(out + f * d_.P, d_.P, st_);
-  }
-  // iota of per-field combinations x_f + alpha_f y_f (y_f may be null)
-  void iota_comb(const T* const* xs, const T* const* ys, const T* al, T* out, int nf, const int kinds[][3]) {
-    const int n0 = d_.n[0], n1 = d_.n[1], n2 = d_.n[2], k0 = d_.k[0], k1 = d_.k[1], k2 = d_.k[2];
-    const bool skip0 = (n0 == 1 && k0 == 1);
-    if constexpr (std::is_same_v<T, float>) {
-      if (fused_dft_ok(n1, n2, k1, k2)) {
-        IotaABArgs a{};
-        for (int f = 0; f < nf; ++f) {
-          a.x[f] = xs[f];
-          a.y[f] = ys ? ys[f] : nullptr;
-          a.alpha[f] = al ? al[f] : 0.f;
-          a.w1t[f] = mat(1, kinds[f][1] + kPlainT);
-          a.w2t[f] = mat(2, kinds[f][2] + kPlainT);
-        }
-        a.out = skip0 ? out : t2_.get();
-        a.k0 = k0, a.k1 = k1, a.k2 = k2, a.n1 = n1, a.n2 = n2;
-        iota_ab(a, nf, st_);
-        if (!skip0) {
-          FieldMats<T> W{};
-          for (int f = 0; f < nf; ++f) W.w[f] = mat(0, kinds[f][0]);
-          left(t2_.get(), out, W, nf, 1, n0, k0, n1 * n2, (int64_t)k0 * n1 * n2, d_.P, st_);
-        } else {
-          zero_degenerate_derivatives(out, nf, kinds);
-        }
-        return;
-      }
-    }
-    // generic path: stack the combinations, then the separable stages
-    for (int f = 0; f < nf; ++f) {
-      if (ys && ys[f])
-        axpby(stk_.get() + f * d_.Q, T(1), xs[f], al[f], ys[f], d_.Q);
-      else
-        copy(stk_.get() + f * d_.Q, xs[f], d_.Q);
-    }
-    iota(stk_.get(), out, nf, kinds);
-  }
-  void iota_comb_kind(const T* const* xs, const T* const* ys, const T* al, T* out, int nf, int kind) {
-    int kinds[kMaxFields][3];
-    for (int f = 0; f < nf; ++f) kinds[f][0] = kinds[f][1] = kinds[f][2] = kind;
-    iota_comb(xs, ys, al, out, nf, kinds);
-  }
-  // pi of nf stacked grid fields into per-field destinations: dst_f = beta_f dst_f + alpha_f pi(grid_f)
-  void pi_acc(const T* grid, int nf, T* const* dst, const T* alpha, const T* beta) {
-    const int n0 = d_.n[0], n1 = d_.n[1], n2 = d_.n[2], k0 = d_.k[0], k1 = d_.k[1], k2 = d_.k[2];
-    if constexpr (std::is_same_v<T, float>) {
-      if (fused_dft_ok(n1, n2, k1, k2)) {
-        const T* srcB = grid;
-        if (!(n0 == 1 && k0 == 1)) {
-          FieldMats<T> W{};
-          for (int f = 0; f < nf; ++f) W.w[f] = mat(0, kProj);
-          left(grid, t1_.get(), W, nf, 1, k0, n0, n1 * n2, d_.P, (int64_t)k0 * n1 * n2, st_);
-          srcB = t1_.get();
-        }
-        PiBAArgs b{};
-        b.in = srcB;
-        b.p1t = mat(1, kProjT);
-        b.part = pipart_.get();
-        b.p2t = mat(2, kProjT);
-        for (int f = 0; f < nf; ++f) {
-          b.out[f] = dst[f];
-          b.alpha[f] = alpha[f];
-          b.beta[f] = beta[f];
-        }
-        b.k0 = k0, b.k1 = k1, b.k2 = k2, b.n1 = n1, b.n2 = n2;
-        pi_ba(b, nf, st_);
-        return;
-      }
-    }
-    pi_sep(grid, blC_.get(), nf);
-    for (int f = 0; f < nf; ++f) {
-      if (beta[f] == T(0))
-        axpby(dst[f], alpha[f], blC_.get() + f * d_.Q, T(0), nullptr, d_.Q);  // never reads dst
-      else
-        axpby(dst[f], beta[f], dst[f], alpha[f], blC_.get() + f * d_.Q, d_.Q);
-    }
-  }
-  void pi(const T* grid, T* bl, int nf) {
-    T* dst[kMaxFields];
-    T one[kMaxFields], zer[kMaxFields];
-    for (int f = 0; f < nf; ++f) dst[f] = bl + f * d_.Q, one[f] = T(1), zer[f] = T(0);
-    if constexpr (std::is_same_v<T, float>) {
-      if (fused_dft_ok(d_.n[1], d_.n[2], d_.k[1], d_.k[2])) return pi_acc(grid, nf, dst, one, zer);
-    }
-    pi_sep(grid, bl, nf);
-  }
-  // image-transport backward products fused with the expansion of e and the first projection stage:
-  // pi([e divv, e G0, e G1, e G2]) into dst with alpha / beta, e = iota(x). Returns false when not applicable.
-  bool fused_v1_products(const T* x, const T* Gn, T* const* dst, const T* al, const T* be) {
-    if constexpr (std::is_same_v<T, float>) {
-      const int n0 = d_.n[0], n1 = d_.n[1], n2 = d_.n[2], k0 = d_.k[0], k1 = d_.k[1], k2 = d_.k[2];
-      if (!bf16_ && n0 > 1 && fused_dft_ok(n1, n2, k1, k2) && back_v1_ok(n0, k0)) {
-        IotaABArgs a{};
-        a.x[0] = x;
-        a.y[0] = nullptr;
-        a.alpha[0] = 0.f;
-        a.w1t[0] = mat(1, kPlainT);
-        a.w2t[0] = mat(2, kPlainT);
-        a.out = t2_.get();
-        a.k0 = k0, a.k1 = k1, a.k2 = k2, a.n1 = n1, a.n2 = n2;
-        iota_ab(a, 1, st_);
-        BackV1Args b{};
-        b.t2 = t2_.get();
-        b.divv = divv_.get();
-        b.G = Gn;
-        b.B0 = mat(0, kPlain);
-        b.out = t1_.get();
-        b.n0 = n0, b.k0 = k0, b.C = n1 * n2;
-        b.inv_n0 = 1.f / n0;
-        back_v1(b, st_);
-        PiBAArgs c{};
-        c.in = t1_.get();
-        c.p1t = mat(1, kProjT);
-        c.part = pipart_.get();
-        c.p2t = mat(2, kProjT);
-        for (int f = 0; f < 4; ++f) {
-          c.out[f] = dst[f];
-          c.alpha[f] = al[f];
-          c.beta[f] = be[f];
-        }
-        c.k0 = k0, c.k1 = k1, c.k2 = k2, c.n1 = n1, c.n2 = n2;
-        pi_ba(c, 4, st_);
-        return true;
-      }
-    }
-    (void)x, (void)Gn, (void)dst, (void)al, (void)be;
-    return false;
-  }
-  void iota_kind(const T* bl, T* out, int nf, int kind) {
-    int kinds[kMaxFields][3];
-    for (int f = 0; f < nf; ++f) kinds[f][0] = kinds[f][1] = kinds[f][2] = kind;
-    iota(bl, out, nf, kinds);
-  }
-  // pi of nf stacked grid fields (separable stages)
-  void pi_sep(const T* grid, T* bl, int nf) {
-    const int n0 = d_.n[0], n1 = d_.n[1], n2 = d_.n[2], k0 = d_.k[0], k1 = d_.k[1], k2 = d_.k[2];
-    FieldMats<T> W{};
-    const T* srcB = grid;
-    if (!(n0 == 1 && k0 == 1)) {
-      for (int f = 0; f < nf; ++f) W.w[f] = mat(0, kProj);
-      left(grid, t1_.get(), W, nf, 1, k0, n0, n1 * n2, d_.P, (int64_t)k0 * n1 * n2, st_);
-      srcB = t1_.get();
-    }
-    for (int f = 0; f < nf; ++f) W.w[f] = mat(1, kProj);
-    left(srcB, t2_.get(), W, nf * k0, k0, k1, n1, n2, (int64_t)n1 * n2, (int64_t)k1 * n2, st_);
-    for (int f = 0; f < nf; ++f) W.w[f] = mat(2, kProj);
-    dft_right(t2_.get(), bl, W, nf, k0 * k1, n2, k2, st_);
-  }
-  // 9 derivative fields d_j u_i from a BL vector u (stacked as [u0,u0,u0,u1,u1,u1,u2,u2,u2])
-  void stack_deriv9(const T* u, T* stk) {
-    for (int i = 0; i < 3; ++i)
-      for (int j = 0; j < 3; ++j) copy(stk + (int64_t)(3 * i + j) * d_.Q, u + (int64_t)i * d_.Q, d_.Q);
-  }
-  void iota9_deriv(const T* stk, T* out) {
-    int kinds[kMaxFields][3] = {};
-    for (int i = 0; i < 3; ++i)
-      for (int j = 0; j < 3; ++j)
-        for (int a = 0; a < 3; ++a) kinds[3 * i + j][a] = (a == j) ? kDeriv : kPlain;
-    iota(stk, out, 9, kinds);
-  }
   void axpby(T* out, T a, const T* x, T b, const T* y, int64_t n) { bl_axpby<T>(out, a, x, b, y, n, st_); }
 
   double grad_inf(const T* g) {
-    iota_kind(g, S(0), 3, kPlain);
+    full_.iota_kind(g, S(0), 3, kPlain);
     return maxabs<T>(S(0), 3 * d_.P, work_.get(), host_.get(), st_);
+  }
+
+  // ------------------------------------ truncated products on the product grid
+  // x (ncomp band fields) against the state at node n:
+  //   image transport (ncomp 1): pi'([e div v, e G_0, e G_1, e G_2]), G = grad~ m~_n
+  //   deformation state (ncomp 3): pi'([e_i div v (3), (D~u~_n)^T e (3)])
+  // with e = iota'(x), into dst with dst_f = beta_f dst_f + alpha_f (.)
+  void products(const T* x, int n, T* const* dst, const T* al, const T* be) {
+    if constexpr (std::is_same_v<T, float>) {
+      if (sm_.planes()) {
+        const bool v1 = variant_ == LDDMM_BL_IMAGE_TRANSPORT;
+        const int nc = v1 ? 1 : 3, np = v1 ? 4 : 6;
+        sm_.iota_kind(x, es_.get(), nc, kPlain);
+        sm_.reduce(v1 ? kRedV1Products : kRedV3Products, np, nullptr, es_.get(), divvs_.get(),
+                   v1 ? Gs_.get() + (int64_t)n * 3 * ds_.P : Dus_.get() + (int64_t)n * 9 * ds_.P);
+        Axis0Args a = sm_.axis0_args(np);
+        for (int f = 0; f < np; ++f) a.out[f] = dst[f], a.alpha[f] = al[f], a.beta[f] = be[f];
+        plane_axis0(a, st_);
+        return;
+      }
+    }
+    if (variant_ == LDDMM_BL_IMAGE_TRANSPORT) {
+      sm_.iota_kind(x, es_.get(), 1, kPlain);
+      v1_products<T>(Ps(0), es_.get(), divvs_.get(), Gs_.get() + (int64_t)n * 3 * ds_.P, ds_, st_);
+      sm_.pi_acc(Ps(0), 4, dst, al, be);
+    } else {
+      sm_.iota_kind(x, es_.get(), 3, kPlain);
+      v3_products<T>(Ps(0), es_.get(), divvs_.get(), Dus_.get() + (int64_t)n * 9 * ds_.P, ds_, st_);
+      sm_.pi_acc(Ps(0), 6, dst, al, be);
+    }
   }
 
   // ---------------------------------------------- per-velocity set-up (Section 3.1)
@@ -577,19 +367,20 @@ class Solver final : public SolverBase {
     setup_velocity_body();
   }
   void setup_velocity_body() {
-    const int64_t Q = d_.Q, P = d_.P;
+    const int64_t P = d_.P;
     // velocity samples and the B-spline coefficients of the velocity in one 6-field transform
-    copy(stk_.get(), vbl_.get(), 3 * Q);
-    copy(stk_.get() + 3 * Q, vbl_.get(), 3 * Q);
+    const T* xs[6];
     int kinds[kMaxFields][3] = {};
+    for (int f = 0; f < 6; ++f) xs[f] = vbl_.get() + (f % 3) * d_.Q;
     for (int f = 3; f < 6; ++f) kinds[f][0] = kinds[f][1] = kinds[f][2] = kPref;
-    iota(stk_.get(), S(0), 6, kinds);
+    full_.iota_comb(xs, nullptr, nullptr, S(0), 6, kinds);
     copy(vg_.get(), S(0), 3 * P);
     const T* cv = S(3);
     characteristics<T>(Xb_.get(), vg_.get(), cv, d_, dt_, -1, st_);
     characteristics<T>(Xf_.get(), vg_.get(), cv, d_, dt_, +1, st_);
     bl_div<T>(tmpbl_.get(), vbl_.get(), d_, st_);
-    iota_kind(tmpbl_.get(), divv_.get(), 1, kPlain);
+    full_.iota_kind(tmpbl_.get(), divv_.get(), 1, kPlain);
+    sm_.iota_kind(tmpbl_.get(), divvs_.get(), 1, kPlain);
   }
 
   double regulariser() {
@@ -650,7 +441,7 @@ class Solver final : public SolverBase {
   }
   void adjoint_launch(T* g) {
     run_adjoint(g);
-    iota_kind(g, S(0), 3, kPlain);
+    full_.iota_kind(g, S(0), 3, kPlain);
     reduce_launch<T>(RedKind::MaxAbs, S(0), nullptr, 3 * d_.P, work_.get(), 3, st_);
     reduce_launch<T>(RedKind::Dot, g, g, 3 * d_.Q, work_.get(), 4, st_);
     fetch_async(work_.get(), host_.get(), 5, st_);
@@ -671,58 +462,64 @@ class Solver final : public SolverBase {
     copy(m_.get(), I0_.get(), P);
     for (int n = 0; n <= nt_; ++n) {
       T* mn = m_.get() + n * P;
-      // G_n = iota(grad~ pi(m_n)): derivative folded into the axis matrices
-      pi(mn, tmpbl_.get(), 1);
-      for (int j = 0; j < 3; ++j) copy(stk_.get() + j * Q, tmpbl_.get(), Q);
-      int kinds[kMaxFields][3] = {};
-      for (int j = 0; j < 3; ++j) kinds[j][j] = kDeriv;
-      iota(stk_.get(), G_.get() + n * 3 * P, 3, kinds);
+      full_.pi(mn, mt_.get() + n * Q, 1);  // m~_n
       if (n < nt_) {
         copy(S(0), mn, P);
         prefilter(S(0), 1, d_, st_);
         interp<T>(mn + P, S(0), 1, Xb_.get(), d_, st_);
       }
     }
+    // G_n = iota'(grad~ m~_n) on the product grid, four nodes per transform
+    for (int n = 0; n <= nt_; n += 4)
+      sm_.iota_grad(mt_.get() + n * Q, Gs_.get() + (int64_t)n * 3 * ds_.P, std::min(4, nt_ + 1 - n));
   }
 
   // ------------------------------ deformation state: state (Table 1 row 3)
   void state_v3() {
-    const int64_t P = d_.P, Q = d_.Q;
-    const T hdt = T(0.5) * dt_;
+    const int64_t Q = d_.Q;
     zero(ubl_.get(), 3 * Q, st_);
-    for (int n = 0; n < nt_; ++n) {
-      const T* un = ubl_.get() + n * 3 * Q;
-      T* un1 = ubl_.get() + (n + 1) * 3 * Q;
-      // P(u_n + dt/2 v) o X_b
-      const T* xs[3] = {un, un + Q, un + 2 * Q};
-      const T* ys[3] = {vbl_.get(), vbl_.get() + Q, vbl_.get() + 2 * Q};
-      const T al[3] = {hdt, hdt, hdt};
-      iota_comb_kind(xs, ys, al, S(0), 3, kPref);
-      interp<T>(S(3), S(0), 3, Xb_.get(), d_, st_);
-      pi(S(3), blA_.get(), 3);
-      axpby(un1, T(1), blA_.get(), hdt, vbl_.get(), 3 * Q);
-    }
-    for (int n = 0; n <= nt_; ++n) {
-      stack_deriv9(ubl_.get() + n * 3 * Q, stk_.get());
-      iota9_deriv(stk_.get(), Du_.get() + n * 9 * P);
-    }
-    iota_kind(ubl_.get() + (int64_t)nt_ * 3 * Q, S(0), 3, kPlain);
+    for (int n = 0; n < nt_; ++n) u_step(ubl_.get() + n * 3 * Q, ubl_.get() + (n + 1) * 3 * Q);
+    // D u_n = iota'(D~ u~_n) on the product grid
+    for (int n = 0; n <= nt_; ++n) sm_.iota_grad(ubl_.get() + n * 3 * Q, Dus_.get() + (int64_t)n * 9 * ds_.P, 3);
+    full_.iota_kind(ubl_.get() + (int64_t)nt_ * 3 * Q, S(0), 3, kPlain);
     final_warp<T>(m1_.get(), g1_.get(), cI0_.get(), S(0), d_, st_);
+  }
+  // one deformation-state step: u_next = pi[P(u + dt/2 v) o X_b] + dt/2 v
+  void u_step(const T* un, T* un1) {
+    const int64_t Q = d_.Q;
+    const T hdt = T(0.5) * dt_;
+    const T* xs[3] = {un, un + Q, un + 2 * Q};
+    const T* ys[3] = {vbl_.get(), vbl_.get() + Q, vbl_.get() + 2 * Q};
+    const T al[3] = {hdt, hdt, hdt};
+    full_.iota_comb_kind(xs, ys, al, S(0), 3, kPref);
+    if constexpr (std::is_same_v<T, float>) {
+      if (brick_ok(d_)) {
+        // increment form: the B-spline interpolant of c = u + dt/2 v equals iota(c) at the nodes and
+        // pi iota(c) = c, so u_next = u + dt v + pi[P(c) o X_b - P(c)]; the projection then carries one
+        // step's change instead of the whole displacement (an FP32 rounding error that does not grow
+        // with the displacement already accumulated)
+        brick_interp_diff(S(3), S(0), 3, Xb_.get(), d_, st_);
+        axpby(un1, T(1), un, dt_, vbl_.get(), 3 * Q);
+        T* dst[3] = {un1, un1 + Q, un1 + 2 * Q};
+        const T one[3] = {T(1), T(1), T(1)};
+        full_.pi_acc(S(3), 3, dst, one, one);
+        return;
+      }
+    }
+    interp<T>(S(3), S(0), 3, Xb_.get(), d_, st_);
+    copy(un1, vbl_.get(), 3 * Q);
+    T* dst[3] = {un1, un1 + Q, un1 + 2 * Q};
+    const T one[3] = {T(1), T(1), T(1)}, hd[3] = {hdt, hdt, hdt};
+    full_.pi_acc(S(3), 3, dst, one, hd);
   }
 
   // u~(1) only, for the Jacobian of the image-transport variant
   void displacement_only(T* u) {
     const int64_t Q = d_.Q;
-    const T hdt = T(0.5) * dt_;
     zero(u, 3 * Q, st_);
     for (int n = 0; n < nt_; ++n) {
-      const T* xs[3] = {u, u + Q, u + 2 * Q};
-      const T* ys[3] = {vbl_.get(), vbl_.get() + Q, vbl_.get() + 2 * Q};
-      const T al[3] = {hdt, hdt, hdt};
-      iota_comb_kind(xs, ys, al, S(0), 3, kPref);
-      interp<T>(S(3), S(0), 3, Xb_.get(), d_, st_);
-      pi(S(3), blA_.get(), 3);
-      axpby(u, T(1), blA_.get(), hdt, vbl_.get(), 3 * Q);
+      u_step(u, blA_.get());
+      copy(u, blA_.get(), 3 * Q);
     }
   }
 
@@ -744,17 +541,14 @@ class Solver final : public SolverBase {
     scaled_diff<T>(lam, T(-2.0 / sigma2_), m1_ptr(), I1_.get(), P, st_);
     zero(acc_.get(), 3 * Q, st_);
     for (int n = nt_; n >= 0; --n) {
-      // gradient term w_n pi(iota(pi lambda_n) G_n), accumulated into acc
-      pi(lam, tmpbl_.get(), 1);
+      // gradient term w_n pi(iota(pi lambda_n) G_n), accumulated into acc (the first product, the
+      // band-limited source, is not used by the grid adjoint)
+      full_.pi(lam, tmpbl_.get(), 1);
       {
         const T w = trap_w(n);
         T* dst[4] = {blA_.get(), acc_.get(), acc_.get() + Q, acc_.get() + 2 * Q};
         const T al[4] = {T(1), w, w, w}, be[4] = {T(0), T(1), T(1), T(1)};
-        if (!fused_v1_products(tmpbl_.get(), G_.get() + n * 3 * P, dst, al, be)) {
-          iota_kind(tmpbl_.get(), S(0), 1, kPlain);
-          v1_products<T>(S(1), S(0), divv_.get(), G_.get() + n * 3 * P, d_, st_);
-          pi_acc(S(1), 4, dst, al, be);
-        }
+        products(tmpbl_.get(), n, dst, al, be);
       }
       if (n == 0) break;
       copy(S(5), lam, P);
@@ -769,7 +563,10 @@ class Solver final : public SolverBase {
   // band-limited backward sweep with source (.) star div~ v~ (rows 4, 6, 8), ncomp 1 or 3,
   // accumulating the Hessian / gradient term: variant 1 pi(e G_n), variant 3 -pi((Du_n)^T e)
   void bl_backward(T* traj, int ncomp, T* acc) {
-    const int64_t P = d_.P, Q = d_.Q;
+    if constexpr (std::is_same_v<T, float>) {
+      if (full_.planes() && sm_.planes()) return bl_backward_planes(traj, ncomp, acc);
+    }
+    const int64_t Q = d_.Q;
     const int64_t stride = (int64_t)ncomp * Q;
     const T hdt = T(0.5) * dt_;
     zero(acc, 3 * Q, st_);
@@ -780,18 +577,12 @@ class Solver final : public SolverBase {
         // [fl, e G0, e G1, e G2]: fl to blA, the Hessian / gradient terms accumulated into acc
         T* dst[4] = {blA_.get(), acc, acc + Q, acc + 2 * Q};
         const T al[4] = {T(1), w, w, w}, be[4] = {T(0), T(1), T(1), T(1)};
-        if (!fused_v1_products(xn, G_.get() + n * 3 * P, dst, al, be)) {
-          iota_kind(xn, S(0), 1, kPlain);  // e = iota(x_n)
-          v1_products<T>(S(1), S(0), divv_.get(), G_.get() + n * 3 * P, d_, st_);
-          pi_acc(S(1), 4, dst, al, be);
-        }
+        products(xn, n, dst, al, be);
       } else {
-        iota_kind(xn, S(0), ncomp, kPlain);  // e = iota(x_n)
-        v3_products<T>(S(3), S(0), divv_.get(), Du_.get() + n * 9 * P, d_, st_);
         // [fl (3), (Du)^T e (3)]
         T* dst[6] = {blA_.get(), blA_.get() + Q, blA_.get() + 2 * Q, acc, acc + Q, acc + 2 * Q};
         const T al[6] = {T(1), T(1), T(1), -w, -w, -w}, be[6] = {T(0), T(0), T(0), T(1), T(1), T(1)};
-        pi_acc(S(3), 6, dst, al, be);
+        products(xn, n, dst, al, be);
         axpby(acc, T(1), acc, w, xn, 3 * Q);
       }
       if (n == 0) break;
@@ -806,76 +597,203 @@ class Solver final : public SolverBase {
         al2[c] = hdt;
         al2[ncomp + c] = dt_;
       }
-      iota_comb_kind(xs, ys, al2, S(3), 2 * ncomp, kPref);
+      full_.iota_comb_kind(xs, ys, al2, S(3), 2 * ncomp, kPref);
       bl_adjoint_step<T>(S(9), S(3), S(3 + ncomp), ncomp, Xf_.get(), divv_.get(), d_, dt_, st_);
-      pi(S(9), traj + (n - 1) * stride, ncomp);
+      full_.pi(S(9), traj + (n - 1) * stride, ncomp);
     }
   }
 
   void adjoint_v3() {
     const int64_t Q = d_.Q;
     residual_times_grad<T>(S(0), T(-2.0 / sigma2_), m1_.get(), I1_.get(), g1_.get(), d_, st_);
-    pi(S(0), rho_.get() + (int64_t)nt_ * 3 * Q, 3);
+    full_.pi(S(0), rho_.get() + (int64_t)nt_ * 3 * Q, 3);
     bl_backward(rho_.get(), 3, acc_.get());
   }
 
   // ----------------------------------- Hessian matvec (rows 5-8, Section 2.3)
   void run_matvec(const T* dv, T* h) {
-    const int64_t P = d_.P, Q = d_.Q;
+    if constexpr (std::is_same_v<T, float>) {
+      if (full_.planes() && sm_.planes()) return run_matvec_planes(dv, h);
+    }
+    const int64_t Q = d_.Q, Psm = ds_.P;
     const T hdt = T(0.5) * dt_;
-    iota_kind(dv, dvg_.get(), 3, kPlain);
-    if (variant_ == LDDMM_BL_IMAGE_TRANSPORT) {
-      T* dm = inc_.get();  // [nt+1][Q]
-      T* f = blB_.get();   // source projection at node n
-      v1_source<T>(S(0), G_.get(), dvg_.get(), d_, st_);
-      pi(S(0), f, 1);
-      zero(dm, Q, st_);
-      for (int n = 0; n < nt_; ++n) {
-        const T* xs[1] = {dm + n * Q};
-        const T* ys[1] = {f};
-        const T al[1] = {hdt};
-        iota_comb_kind(xs, ys, al, S(0), 1, kPref);
-        // [c o X + dt/2 s_{n+1}, s_{n+1}] projected straight into dm_{n+1} and f
-        inc_state_v1<T>(S(1), S(0), Xb_.get(), G_.get() + (n + 1) * 3 * P, dvg_.get(), hdt, d_, st_);
-        T* dst[2] = {dm + (n + 1) * Q, f};
-        const T one[2] = {T(1), T(1)}, zer[2] = {T(0), T(0)};
-        pi_acc(S(1), 2, dst, one, zer);
+    const int nc = variant_ == LDDMM_BL_IMAGE_TRANSPORT ? 1 : 3;
+    const int nn = nt_ + 1;
+    // incremental sources f~_n = pi'(s_n) for every node, scaled by dt/2, on the product grid:
+    // image transport s_n = -G_n . dv, deformation state s_n = dv - (D u_n) dv
+    sm_.iota_kind(dv, dvs_.get(), 3, kPlain);
+    for (int n = 0; n < nn; ++n) {
+      if (nc == 1)
+        v1_source<T>(Ps(n), Gs_.get() + (int64_t)n * 3 * Psm, dvs_.get(), ds_, st_);
+      else
+        v3_source<T>(Ps(3 * n), Dus_.get() + (int64_t)n * 9 * Psm, dvs_.get(), ds_, st_);
+    }
+    for (int f0 = 0; f0 < nn * nc; f0 += kMaxFields) {
+      const int nf = std::min<int>(kMaxFields, nn * nc - f0);
+      T* dst[kMaxFields];
+      T al[kMaxFields], be[kMaxFields];
+      for (int f = 0; f < nf; ++f) dst[f] = fsrc_.get() + (int64_t)(f0 + f) * Q, al[f] = hdt, be[f] = T(0);
+      sm_.pi_acc(Ps(f0), nf, dst, al, be);
+    }
+    // incremental state: dm_0 = 0, dm_{n+1} = pi[P(dm_n + dt/2 f_n) o X_b] + dt/2 f_{n+1}
+    T* dm = inc_.get();  // [nt+1][nc][Q]
+    zero(dm, nc * Q, st_);
+    copy(dm + nc * Q, fsrc_.get() + nc * Q, (int64_t)nt_ * nc * Q);
+    for (int n = 0; n < nt_; ++n) {
+      const T* xs[3];
+      const T* ys[3];
+      T al[3], one[3];
+      T* dst[3];
+      for (int c = 0; c < nc; ++c) {
+        xs[c] = dm + (n * nc + c) * Q;
+        ys[c] = fsrc_.get() + (n * nc + c) * Q;
+        dst[c] = dm + ((n + 1) * nc + c) * Q;
+        al[c] = one[c] = T(1);
       }
+      full_.iota_comb_kind(xs, ys, al, S(0), nc, kPref);
+      interp<T>(S(3), S(0), nc, Xb_.get(), d_, st_);
+      full_.pi_acc(S(3), nc, dst, one, one);
+    }
+    if (nc == 1) {
       T* dl = incadj_.get();
       axpby(dl + (int64_t)nt_ * Q, T(-2.0 / sigma2_), dm + (int64_t)nt_ * Q, T(0), nullptr, Q);
       bl_backward(dl, 1, acc_.get());
     } else {
-      T* du = inc_.get();  // [nt+1][3][Q]
-      T* f = blB_.get();
-      v3_source<T>(S(0), Du_.get(), dvg_.get(), d_, st_);
-      pi(S(0), f, 3);
-      zero(du, 3 * Q, st_);
-      for (int n = 0; n < nt_; ++n) {
-        const T* dun = du + n * 3 * Q;
-        const T* xs[3] = {dun, dun + Q, dun + 2 * Q};
-        const T* ys[3] = {f, f + Q, f + 2 * Q};
-        const T al[3] = {hdt, hdt, hdt};
-        iota_comb_kind(xs, ys, al, S(0), 3, kPref);
-        // [c o X + dt/2 s_{n+1} (3), s_{n+1} (3)] projected straight into du_{n+1} and f
-        inc_state_v3<T>(S(3), S(0), Xb_.get(), Du_.get() + (n + 1) * 9 * P, dvg_.get(), hdt, d_, st_);
-        T* dun1 = du + (n + 1) * 3 * Q;
-        T* dst[6] = {dun1, dun1 + Q, dun1 + 2 * Q, f, f + Q, f + 2 * Q};
-        const T one[6] = {T(1), T(1), T(1), T(1), T(1), T(1)}, zer[6] = {T(0), T(0), T(0), T(0), T(0), T(0)};
-        pi_acc(S(3), 6, dst, one, zer);
-      }
       // t = 1 coupling: drho~(1) = pi((2/sigma^2) (g1 . iota(du~(1))) g1)
-      iota_kind(du + (int64_t)nt_ * 3 * Q, S(0), 3, kPlain);
+      full_.iota_kind(dm + (int64_t)nt_ * 3 * Q, S(0), 3, kPlain);
       coupling_v3<T>(S(3), T(2.0 / sigma2_), g1_.get(), S(0), d_, st_);
       T* dr = incadj_.get();
-      pi(S(3), dr + (int64_t)nt_ * 3 * Q, 3);
+      full_.pi(S(3), dr + (int64_t)nt_ * 3 * Q, 3);
       bl_backward(dr, 3, acc_.get());
     }
     bl_scale_sym<T>(h, dv, Lsym_.get(), 3, Q, acc_.get(), st_);
   }
 
+  // ------------------------- plane-wise forms of the sweeps (float; dft_planes.hip)
+  // Launch sequence per step: incremental state expand -> interpolate -> reduce -> axis0 (the axis-0
+  // stage finishes dm_{n+1} and forms the next step's plane-band input); backward: the product-grid
+  // expansion, product reduction and axis0 (source fl, Hessian terms, and the plane-band inputs of
+  // P(x + dt/2 fl), P(x + dt fl)), then expand -> interpolate -> reduce -> axis0 (x_{n-1} and its
+  // product-grid plane-band input).
+  void run_matvec_planes(const float* dv, float* h) {
+    const int64_t Q = d_.Q, Psm = ds_.P;
+    const float hdt = 0.5f * dt_;
+    const int nc = variant_ == LDDMM_BL_IMAGE_TRANSPORT ? 1 : 3;
+    const int nn = nt_ + 1;
+    int kpref[kMaxFields][3];
+    for (int f = 0; f < kMaxFields; ++f) kpref[f][0] = kpref[f][1] = kpref[f][2] = kPref;
+    float* dm = inc_.get();  // [nt+1][nc][Q]
+    // f~_n dt/2 for every node (into fsrc, and into dm_n for n >= 1), and the plane-band input of
+    // the first step's interpolant P(dm_0 + dt/2 f~_0) = P(dt/2 f~_0)
+    sm_.iota_kind(dv, dvs_.get(), 3, kPlain);
+    sm_.reduce(nc == 1 ? kRedV1Source : kRedV3Source, nn * nc, nullptr, dvs_.get(), nullptr,
+               nc == 1 ? Gs_.get() : Dus_.get());
+    for (int f0 = 0; f0 < nn * nc; f0 += kMaxFields) {
+      const int m = std::min(kMaxFields, nn * nc - f0);
+      Axis0Args a = sm_.axis0_args(m, f0);
+      for (int f = 0; f < m; ++f) {
+        a.out[f] = fsrc_.get() + (int64_t)(f0 + f) * Q;
+        a.out2[f] = (f0 + f >= nc) ? dm + (int64_t)(f0 + f) * Q : nullptr;
+        a.alpha[f] = hdt;
+      }
+      if (f0 == 0) {
+        a.nout = nc;
+        for (int c = 0; c < nc; ++c) a.o[c] = full_.target(c, kPref, c, nullptr, 1.f);
+      }
+      plane_axis0(a, st_);
+    }
+    (void)Psm;
+    zero(dm, nc * Q, st_);
+    // incremental state: dm_{n+1} = pi[P(dm_n + dt/2 f_n) o X_b] + dt/2 f_{n+1}
+    for (int n = 0; n < nt_; ++n) {
+      full_.expand(nc, kpref, S(0));
+      interp<float>(S(3), S(0), nc, Xb_.get(), d_, st_);
+      full_.reduce(kRedPlain, nc, S(3));
+      Axis0Args a = full_.axis0_args(nc);
+      for (int c = 0; c < nc; ++c) {
+        a.out[c] = dm + (int64_t)((n + 1) * nc + c) * Q;
+        a.alpha[c] = a.beta[c] = 1.f;
+      }
+      if (n + 1 < nt_) {
+        a.nout = nc;
+        for (int c = 0; c < nc; ++c)
+          a.o[c] = full_.target(c, kPref, c, nullptr, 1.f, -1, fsrc_.get() + (int64_t)((n + 1) * nc + c) * Q, 1.f);
+      }
+      plane_axis0(a, st_);
+    }
+    if (nc == 1) {
+      float* dl = incadj_.get();
+      axpby(dl + (int64_t)nt_ * Q, -2.0f / float(sigma2_), dm + (int64_t)nt_ * Q, 0.f, nullptr, Q);
+      bl_backward_planes(dl, 1, acc_.get());
+    } else {
+      // t = 1 coupling: drho~(1) = pi((2/sigma^2) (g1 . iota(du~(1))) g1)
+      full_.iota_kind(dm + (int64_t)nt_ * 3 * Q, S(0), 3, kPlain);
+      coupling_v3<float>(S(3), 2.0f / float(sigma2_), g1_.get(), S(0), d_, st_);
+      float* dr = incadj_.get();
+      full_.pi(S(3), dr + (int64_t)nt_ * 3 * Q, 3);
+      bl_backward_planes(dr, 3, acc_.get());
+    }
+    bl_scale_sym<float>(h, dv, Lsym_.get(), 3, Q, acc_.get(), st_);
+  }
+
+  void bl_backward_planes(float* traj, int nc, float* acc) {
+    const int64_t Q = d_.Q;
+    const int64_t stride = (int64_t)nc * Q;
+    const float hdt = 0.5f * dt_;
+    const bool v1 = variant_ == LDDMM_BL_IMAGE_TRANSPORT;
+    const int np = v1 ? 4 : 6;
+    int kpref[kMaxFields][3];
+    for (int f = 0; f < kMaxFields; ++f) kpref[f][0] = kpref[f][1] = kpref[f][2] = kPref;
+    zero(acc, 3 * Q, st_);
+    {  // product-grid plane-band input of x_Nt
+      Axis0Args a = sm_.axis0_args(0);
+      a.nout = nc;
+      for (int c = 0; c < nc; ++c) a.o[c] = sm_.target(c, kPlain, -1, traj + nt_ * stride + c * Q, 1.f);
+      plane_axis0(a, st_);
+    }
+    for (int n = nt_; n >= 0; --n) {
+      float* xn = traj + n * stride;
+      const float w = trap_w(n);
+      // products on the product grid: fl = x * div~ v~ and the Hessian / gradient terms
+      sm_.expand_kind(nc, kPlain, es_.get());
+      sm_.reduce(v1 ? kRedV1Products : kRedV3Products, np, nullptr, es_.get(), divvs_.get(),
+                 v1 ? Gs_.get() + (int64_t)n * 3 * ds_.P : Dus_.get() + (int64_t)n * 9 * ds_.P);
+      Axis0Args a = sm_.axis0_args(np);
+      for (int c = 0; c < nc; ++c) a.out[c] = blA_.get() + c * Q, a.alpha[c] = 1.f;
+      for (int j = 0; j < 3; ++j) {
+        a.out[nc + j] = acc + j * Q;
+        a.alpha[nc + j] = v1 ? w : -w;
+        a.beta[nc + j] = 1.f;
+        if (!v1) a.z[nc + j] = xn + j * Q, a.gamma[nc + j] = w;  // + w x_n
+      }
+      if (n > 0) {  // plane-band inputs of cA = P(x + dt/2 fl), cB = P(x + dt fl)
+        a.nout = 2 * nc;
+        for (int c = 0; c < nc; ++c) {
+          a.o[c] = full_.target(c, kPref, -1, xn + c * Q, 1.f, c, nullptr, hdt);
+          a.o[nc + c] = full_.target(nc + c, kPref, -1, xn + c * Q, 1.f, c, nullptr, dt_);
+        }
+      }
+      plane_axis0(a, st_);
+      if (n == 0) break;
+      full_.expand(2 * nc, kpref, S(3));
+      bl_adjoint_step<float>(S(9), S(3), S(3 + nc), nc, Xf_.get(), divv_.get(), d_, dt_, st_);
+      full_.reduce(kRedPlain, nc, S(9));
+      Axis0Args b = full_.axis0_args(nc);
+      b.nout = nc;
+      for (int c = 0; c < nc; ++c) {
+        b.out[c] = traj + (n - 1) * stride + c * Q;
+        b.alpha[c] = 1.f;
+        b.o[c] = sm_.target(c, kPlain, c, nullptr, 1.f);
+      }
+      plane_axis0(b, st_);
+    }
+  }
+
   // ------------------------------------------------------------------ state
   hipStream_t st_;
-  Dims d_{};
+  Dims d_{};   // image grid
+  Dims ds_{};  // product grid (same band)
+  Plan<T> full_, sm_;
   int dim_ = 3, nt_ = 1, variant_ = 1, s_ = 2;
   T dt_ = T(1);
   double alpha_ = 0, sigma2_ = 1;
@@ -889,17 +807,15 @@ class Solver final : public SolverBase {
   friend int gn_solve_batched_impl(std::vector<Solver<U>*>& subs, const lddmm_bl_gn_opts& o,
                                    void* const* v_user, lddmm_bl_gn_report* reps, hipStream_t st);
   hipGraphExec_t mv_exec_ = nullptr;
-  int64_t mat_off_[3][kNumMats] = {};
-  DevBuf<T> mats_;
   DevBuf<double> Lsym_, Linv_, work_;
   std::unique_ptr<double, PinnedFree> host_;
-  DevBuf<T> t1_, t2_, I0_, I1_, cI0_;
-  DevBuf<T> vbl_, dvbl_, gbl_, hbl_, tmpbl_, stk_, blA_, blB_, blC_, acc_;
-  DevBuf<T> vg_, divv_, Xb_, Xf_, dvg_, scratch_;
-  DevBuf<T> inc_, incadj_;
-  DevBuf<T> G_, m_, lam0_;               // image transport
-  DevBuf<T> ubl_, Du_, m1_, g1_, rho_;   // deformation state
-  DevBuf<float> pipart_;
+  DevBuf<T> I0_, I1_, cI0_;
+  DevBuf<T> vbl_, dvbl_, gbl_, hbl_, tmpbl_, blA_, acc_;
+  DevBuf<T> vg_, divv_, Xb_, Xf_, scratch_;
+  DevBuf<T> inc_, incadj_, fsrc_;
+  DevBuf<T> divvs_, dvs_, es_, prods_;          // product grid
+  DevBuf<T> m_, mt_, Gs_, lam0_;                // image transport
+  DevBuf<T> ubl_, Dus_, m1_, g1_, rho_;         // deformation state
   DevBuf<double> det_;  // Jacobian map when the caller keeps none
 
  public:

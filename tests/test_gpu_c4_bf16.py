@@ -3,13 +3,12 @@
 Four subjects of the batch (N = 96, 144, 176, 192 with bands 32, 40, 48, 48; deformation-state variant,
 Nt = 10, velocities of 0.8 voxel per step) are checked at a fixed velocity: u~(1), m(1), the gradient and
 one Hessian matvec of a split-bf16 context and of an FP32 context against the oracle's values stored by
-tests/golden/make_fullsize_golden.py (seeded samples of coefficients and nodes).  The printed errors are
-the ones the split-bf16 contractions cost; the bound is derived from the split: the hi + lo bf16 pair
-carries 16 mantissa bits of each float operand, a relative operand error of at most 2^-17 = 7.6e-6 per
-product, and the products of a contraction of length L (<= 192) add errors that grow at most like
-sqrt(L) for independent roundings, about 1e-4; Nt = 10 steps of projection and inclusion add little
-(each step's projection is a contraction).  Then the batched Gauss-Newton-Krylov solve of the four
-subjects (one HIP graph per PCG iteration over all of them) equals the subjects solved one at a time."""
+tests/golden/make_fullsize_golden.py (seeded samples of coefficients and nodes).  The split carries 16
+mantissa bits of each operand (hi + lo bf16), a relative operand error of at most 2^-17 = 7.6e-6 per
+product; the contraction sums of length <= 192 average these errors, and the measured errors sit at
+0.9-2.6e-6 rel-L2 and <= 1e-5 element-wise, so the split-bf16 path is held to the FP32 bound (rel-L2
+<= 1e-5, element-wise <= 1e-4).  Then the batched Gauss-Newton-Krylov solve of the four subjects (one
+HIP graph per PCG iteration over all of them) equals the subjects solved one at a time."""
 import os
 import sys
 
@@ -26,7 +25,7 @@ import make_fullsize_golden as G  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
-BF16_BOUND = 1e-4  # split-bf16, see the module docstring
+BF16_BOUND = 1e-5  # split-bf16, see the module docstring
 FP32_BOUND = 1e-5
 
 
