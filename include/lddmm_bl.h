@@ -191,6 +191,18 @@ lddmm_bl_status lddmm_bl_jacobian(lddmm_bl_ctx* ctx, void* detmap_or_null, doubl
 lddmm_bl_status lddmm_bl_project(lddmm_bl_ctx* ctx, const void* grid, void* bl, int32_t ncomp);
 lddmm_bl_status lddmm_bl_include(lddmm_bl_ctx* ctx, const void* bl, void* grid, int32_t ncomp);
 
+/* The projection of lddmm_bl_project for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the same arguments, layouts and
+ * result, with the reduction's workspace in a static 16 MiB device array of the library instead of
+ * the context's buffers.  It calls no hipMalloc / hipFree and does not wait: the kernels are enqueued
+ * on the context's stream and the call returns (the result is ready when the stream reaches it).
+ * The context's device must be current; the first call on a device looks up that device's copy of the
+ * array.  Limits: FP32 contexts on the plane-wise path (not FP64, not split-bf16: LDDMM_BL_E_ARG),
+ * ncomp * N0 * K1 * K2 * 4 bytes <= 16 MiB (LDDMM_BL_E_ARG otherwise, with the sizes in the error
+ * text).  Every call on one GPU shares that GPU's array: calls that overlap on one GPU (two streams,
+ * two threads) race and must be ordered by the caller. */
+lddmm_bl_status lddmm_bl_project_noalloc(lddmm_bl_ctx* ctx, const void* grid, void* bl, int32_t ncomp);
+
 /* Internal fields of the last solves, for inspection and parity checks.
  * Copies field `which` at time node `index` into dst (device) and returns the
  * number of elements through count (host).  With dst = NULL only the count is

@@ -2,6 +2,8 @@
 // Every call catches its own exceptions and turns them into status codes; the
 // text of the last error is kept per context.
 #include <algorithm>
+#include <array>
+#include <mutex>
 #include <cstring>
 #include <new>
 #include <string>
@@ -22,7 +24,31 @@ thread_local std::string g_last_error;
 void set_global_error(const char* what) { g_last_error = what ? what : ""; }
 }  // namespace lddmm
 
+// Workspace of lddmm_bl_project_noalloc: the plane-band partial projections of its reduction (16 MiB).
+// Each GPU the library runs on holds its own copy until the process ends; host code uses the device
+// address hipGetSymbolAddress returns for the current device, never the array's name.
+constexpr int64_t kNoAllocFloats = int64_t(4) << 20;
+static __device__ __align__(256) float scratch[kNoAllocFloats];
+
 namespace {
+
+std::mutex g_scratch_mu;
+std::array<float*, 64> g_scratch_ptr{};  // per device, set on the first call with that device current
+
+float* scratch_for_current_device() {
+  int dev = 0;
+  LDDMM_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= static_cast<int>(g_scratch_ptr.size())) throw lddmm::ArgError("device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      throw lddmm::HipError(std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = static_cast<float*>(p);
+  }
+  return g_scratch_ptr[dev];
+}
 
 template <typename F>
 lddmm_bl_status guarded(lddmm_bl_ctx* ctx, F&& f) {
@@ -192,6 +218,15 @@ lddmm_bl_status lddmm_bl_project(lddmm_bl_ctx* ctx, const void* grid, void* bl, 
   return guarded(ctx, [&] {
     if (!grid || !bl) throw lddmm::ArgError("null buffer");
     ctx->solver->project(grid, bl, ncomp);
+    return 0;
+  });
+}
+
+lddmm_bl_status lddmm_bl_project_noalloc(lddmm_bl_ctx* ctx, const void* grid, void* bl, int32_t ncomp) {
+  return guarded(ctx, [&] {
+    if (!grid || !bl) throw lddmm::ArgError("null buffer");
+    float* ws = scratch_for_current_device();
+    ctx->solver->project_ws(grid, bl, ncomp, ws, kNoAllocFloats);
     return 0;
   });
 }

@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <string>
 #include <type_traits>
 #include <vector>
 
@@ -154,6 +155,32 @@ class Plan {
     a.mode = mode, a.nf = nf, a.n0 = d_.n[0], a.n1 = d_.n[1], a.n2 = d_.n[2], a.k1 = d_.k[1], a.k2 = d_.k[2];
     a.P = d_.P;
     plane_reduce(a, s());
+  }
+  // pi of nf stacked grid fields into bl with the reductions' plane-band partials in a caller-given
+  // workspace of cap floats (float plane-wise path only)
+  void pi_ws(const float* grid, float* bl, int nf, float* ws, int64_t cap) {
+    if (!planes_) throw ArgError("this context's projection does not run the plane-wise FP32 path");
+    const int64_t need = (int64_t)nf * d_.n[0] * C();
+    if (need > cap)
+      throw ArgError("projection workspace of " + std::to_string(need * 4) + " bytes exceeds the " +
+                     std::to_string(cap * 4) + "-byte static scratch");
+    PlaneReduceArgs r{};
+    r.in = grid;
+    r.p1t = mat(1, kProjT), r.p2t = mat(2, kProjT);
+    r.part = ws;
+    r.mode = kRedPlain, r.nf = nf, r.n0 = d_.n[0], r.n1 = d_.n[1], r.n2 = d_.n[2], r.k1 = d_.k[1], r.k2 = d_.k[2];
+    r.P = d_.P;
+    plane_reduce(r, s());
+    for (int f0 = 0; f0 < nf; f0 += kMaxFields) {
+      const int m = std::min(kMaxFields, nf - f0);
+      Axis0Args a = axis0_args(m);
+      for (int f = 0; f < m; ++f) {
+        a.part[f] = ws + (int64_t)(f0 + f) * d_.n[0] * C();
+        a.out[f] = bl + (int64_t)(f0 + f) * d_.Q;
+        a.alpha[f] = 1.f;
+      }
+      plane_axis0(a, s());
+    }
   }
   // first-axis launch with this plan's projection shape (F inputs from part(f0 ..))
   Axis0Args axis0_args(int nin, int f0 = 0) {

@@ -24,6 +24,8 @@ class SolverBase {
   virtual void jacobian(double* detmap, double* minmax) = 0;
   virtual void project(const void* grid, void* bl, int ncomp) = 0;
   virtual void include(const void* bl, void* grid, int ncomp) = 0;
+  // project with the reduction workspace in ws (cap floats of device memory); enqueued, no host wait
+  virtual void project_ws(const void* grid, void* bl, int ncomp, float* ws, int64_t cap) = 0;
   virtual int64_t get_field(int which, int index, void* dst) = 0;
   virtual double dot(const void* a, const void* b, int64_t n) = 0;
   std::string err;

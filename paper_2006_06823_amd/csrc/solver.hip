@@ -168,6 +168,16 @@ class Solver final : public SolverBase {
     sync();
   }
 
+  void project_ws(const void* grid, void* bl, int ncomp, float* ws, int64_t cap) override {
+    check_ncomp(ncomp);
+    if constexpr (std::is_same_v<T, float>) {
+      full_.pi_ws(static_cast<const float*>(grid), static_cast<float*>(bl), ncomp, ws, cap);
+    } else {
+      (void)grid, (void)bl, (void)ws, (void)cap;
+      throw ArgError("the projection without allocation takes FP32 contexts");
+    }
+  }
+
   void include(const void* bl, void* grid, int ncomp) override {
     check_ncomp(ncomp);
     int kinds[kMaxFields][3] = {};

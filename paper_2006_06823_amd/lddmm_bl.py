@@ -33,7 +33,7 @@ STATUS = {
 EXPORTS = [
     "lddmm_bl_create", "lddmm_bl_destroy", "lddmm_bl_last_error", "lddmm_bl_set_images",
     "lddmm_bl_state_solve", "lddmm_bl_adjoint_solve", "lddmm_bl_hess_matvec", "lddmm_bl_gn_solve",
-    "lddmm_bl_jacobian", "lddmm_bl_project", "lddmm_bl_include", "lddmm_bl_get_field", "lddmm_bl_dot",
+    "lddmm_bl_jacobian", "lddmm_bl_project", "lddmm_bl_project_noalloc", "lddmm_bl_include", "lddmm_bl_get_field", "lddmm_bl_dot",
     "lddmm_bl_profile_enable", "lddmm_bl_profile_read", "lddmm_bl_gn_solve_batched",
     "lddmm_bl_tune_candidates", "lddmm_bl_tune_get", "lddmm_bl_tune_set",
     "lddmm_nn_create", "lddmm_nn_info", "lddmm_nn_forward", "lddmm_nn_backward", "lddmm_nn_zero_grad",
@@ -101,6 +101,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "lddmm_bl_gn_solve": [vp, ctypes.POINTER(GNOpts), vp, vp, i32, ctypes.POINTER(GNReport)],
         "lddmm_bl_jacobian": [vp, vp, dp],
         "lddmm_bl_project": [vp, vp, vp, i32],
+        "lddmm_bl_project_noalloc": [vp, vp, vp, i32],
         "lddmm_bl_include": [vp, vp, vp, i32],
         "lddmm_bl_get_field": [vp, i32, i32, vp, ctypes.POINTER(i64)],
         "lddmm_bl_dot": [vp, vp, vp, i64, dp],
@@ -336,6 +337,15 @@ class Context:
         out = self.empty_bl(ncomp if ncomp > 1 else None)
         self._order()
         self._check(self.lib.lddmm_bl_project(self.h, _ptr(grid), _ptr(out), ncomp))
+        return out
+
+    def project_noalloc(self, grid: torch.Tensor, out: torch.Tensor, ncomp: int = 1) -> torch.Tensor:
+        """pi into a caller-given output, with the library's static workspace (no device allocation
+        in the call); enqueued on the context's stream."""
+        self._arg(grid, self._grid_shape(ncomp if ncomp > 1 else None), "grid")
+        self._arg(out, self._bl_shape(ncomp if ncomp > 1 else None), "out")
+        self._order()
+        self._check(self.lib.lddmm_bl_project_noalloc(self.h, _ptr(grid), _ptr(out), ncomp))
         return out
 
     def include(self, bl: torch.Tensor, ncomp: int = 1) -> torch.Tensor:
