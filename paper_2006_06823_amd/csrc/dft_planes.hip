@@ -324,9 +324,10 @@ __global__ __launch_bounds__(256) void k_axis0(Axis0Kernel a) {
       const int a0 = p * 32 + acc_row(r, l), cc = cb + (l & 31);
       const bool ok = a0 < k0 && cc < C;
       const unsigned o = ok ? (unsigned)(a0 * C + cc) : 0u;
-      // (out is read only when beta != 0: an output buffer need not hold finite values before)
-      const float vb = F.beta != 0.f ? F.beta * F.out[o] : 0.f;
-      const float v = vb + F.gamma * F.z[o];
+      // (in is read only when beta != 0: an output buffer need not hold finite values before)
+      float v = F.beta != 0.f ? F.beta * F.in[o] : 0.f;
+      v += F.gamma * F.z[o];
+      if (F.ysym) v += static_cast<float>(F.ysym[o]) * F.y[o];
       prev[m] = ok ? v : 0.f;
     }
     const Rsrc rpart = rsrc(F.part, (int64_t)n0 * C), rp0 = rsrc(a.p0t, (int64_t)n0 * k0);
@@ -364,7 +365,7 @@ __global__ __launch_bounds__(256) void k_axis0(Axis0Kernel a) {
         const unsigned o = (unsigned)(a0 * C + cc);
         const float v = F.alpha * sum + prev[m];
         F.out[o] = v;
-        if (F.out2) F.out2[o] = v;
+        if (F.out2) F.out2[o] = F.s2 * v;
         fin[a0 * 32 + (l & 31)] = v;
       }
     }
@@ -488,9 +489,12 @@ void plane_axis0(const Axis0Args& a, hipStream_t s) {
   k.p0t = a.p0t, k.n0 = a.n0, k.k0 = a.k0, k.C = a.C;
   for (int f = 0; f < a.nin; ++f) {
     Axis0Kernel::Field& F = k.fld[f];
-    F.part = a.part[f], F.out = a.out[f], F.out2 = a.out2[f];
+    F.part = a.part[f], F.out = a.out[f], F.in = a.in[f] ? a.in[f] : a.out[f], F.out2 = a.out2[f];
     F.z = a.z[f] ? a.z[f] : a.zeros;
+    F.y = a.y[f], F.ysym = a.y[f] ? a.ysym[f] : nullptr;
+    if (F.y && !F.ysym) throw ArgError("plane_axis0: a symbol-weighted term needs its symbol");
     F.alpha = a.alpha[f], F.beta = a.beta[f], F.gamma = a.z[f] ? a.gamma[f] : 0.f;
+    F.s2 = a.s2[f] != 0.f ? a.s2[f] : 1.f;
   }
   int nrow = a.nin;
   for (int f = 0; f < a.nin; ++f) k.row[f].f = f, k.row[f].np = 0;

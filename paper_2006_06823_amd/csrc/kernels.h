@@ -83,10 +83,13 @@ struct Axis0Out {
 struct Axis0Args {
   const float* part[kMaxFields];  // [n0][C]
   const float* p0t;               // [n0][k0]
-  float* out[kMaxFields];         // [k0][C]: out = beta out + alpha r + gamma z
-  float* out2[kMaxFields];        // optional second copy of out
-  const float* z[kMaxFields];
-  float alpha[kMaxFields], beta[kMaxFields], gamma[kMaxFields];
+  float* out[kMaxFields];         // [k0][C]: out = alpha r + beta in + gamma z + ysym y
+  const float* in[kMaxFields];    // optional (default: out)
+  float* out2[kMaxFields];        // optional copy of out, scaled by s2 (0: 1)
+  const float* z[kMaxFields];     // optional
+  const float* y[kMaxFields];     // optional, weighted by the per-coefficient symbol ysym
+  const double* ysym[kMaxFields];
+  float alpha[kMaxFields], beta[kMaxFields], gamma[kMaxFields], s2[kMaxFields];
   Axis0Out o[kMaxFields];
   int nin, nout, n0, k0, C;
   const float* zeros;  // >= k0 C zeros, read in place of absent sources
@@ -97,9 +100,12 @@ struct Axis0Kernel {
   struct Field {
     const float* part;
     float* out;
+    const float* in;
     float* out2;
     const float* z;
-    float alpha, beta, gamma;
+    const float* y;
+    const double* ysym;
+    float alpha, beta, gamma, s2;
   };
   struct Out {
     const float* w0t;

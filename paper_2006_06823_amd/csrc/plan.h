@@ -186,6 +186,7 @@ class Plan {
   Axis0Args axis0_args(int nin, int f0 = 0) {
     Axis0Args a{};
     a.nin = nin;
+    for (int f = 0; f < kMaxFields; ++f) a.s2[f] = 1.f;
     for (int f = 0; f < nin; ++f) a.part[f] = part(f0 + f);
     a.p0t = mat(0, kProjT);
     a.n0 = d_.n[0], a.k0 = d_.k[0], a.C = static_cast<int>(C());

@@ -234,6 +234,8 @@ class Solver final : public SolverBase {
     scratch_.alloc(13 * P);  // 9P-field transforms + 4P staging
     inc_.alloc(nn * 3 * Q);
     incadj_.alloc(nn * 3 * Q);
+    // node 0 of the incremental state is 0 in every matvec; the plane-wise sweep never writes it
+    LDDMM_HIP(hipMemset(inc_.get(), 0, inc_.size() * sizeof(T)));
     fsrc_.alloc(nn * 3 * Q);
     // product grid: div v, the state's gradient fields, the expanded operand and the products
     divvs_.alloc(Ps);
@@ -537,10 +539,18 @@ class Solver final : public SolverBase {
 
   // ------------------------------------------ adjoint + gradient (rows 2 / 4)
   void run_adjoint(T* g) {
-    if (variant_ == LDDMM_BL_IMAGE_TRANSPORT)
+    if (variant_ == LDDMM_BL_IMAGE_TRANSPORT) {
       adjoint_v1();
-    else
+    } else {
+      if constexpr (std::is_same_v<T, float>) {
+        if (full_.planes() && sm_.planes()) {
+          residual_times_grad<T>(S(0), T(-2.0 / sigma2_), m1_.get(), I1_.get(), g1_.get(), d_, st_);
+          full_.pi(S(0), rho_.get() + (int64_t)nt_ * 3 * d_.Q, 3);
+          return bl_backward_planes(rho_.get(), 3, acc_.get(), false, g, vbl_.get());  // g = L~ v + acc
+        }
+      }
       adjoint_v3();
+    }
     bl_scale_sym<T>(g, vbl_.get(), Lsym_.get(), 3, d_.Q, acc_.get(), st_);
   }
 
@@ -713,8 +723,9 @@ class Solver final : public SolverBase {
       plane_axis0(a, st_);
     }
     (void)Psm;
-    zero(dm, nc * Q, st_);
-    // incremental state: dm_{n+1} = pi[P(dm_n + dt/2 f_n) o X_b] + dt/2 f_{n+1}
+    // incremental state: dm_{n+1} = pi[P(dm_n + dt/2 f_n) o X_b] + dt/2 f_{n+1} (dm_0 = 0, kept)
+    float* dl = incadj_.get();
+    const float cpl = -2.0f / float(sigma2_);  // image transport: dl~(1) = -(2/sigma^2) dm~(1)
     for (int n = 0; n < nt_; ++n) {
       full_.expand(nc, kpref, S(0));
       interp<float>(S(3), S(0), nc, Xb_.get(), d_, st_);
@@ -728,25 +739,31 @@ class Solver final : public SolverBase {
         a.nout = nc;
         for (int c = 0; c < nc; ++c)
           a.o[c] = full_.target(c, kPref, c, nullptr, 1.f, -1, fsrc_.get() + (int64_t)((n + 1) * nc + c) * Q, 1.f);
+      } else if (nc == 1) {
+        // the t = 1 coupling and the product-grid plane-band input of the backward sweep's first step
+        a.out2[0] = dl + (int64_t)nt_ * Q;
+        a.s2[0] = cpl;
+        a.nout = 1;
+        a.o[0] = sm_.target(0, kPlain, 0, nullptr, cpl);
       }
       plane_axis0(a, st_);
     }
     if (nc == 1) {
-      float* dl = incadj_.get();
-      axpby(dl + (int64_t)nt_ * Q, -2.0f / float(sigma2_), dm + (int64_t)nt_ * Q, 0.f, nullptr, Q);
-      bl_backward_planes(dl, 1, acc_.get());
+      bl_backward_planes(dl, 1, acc_.get(), true, h, dv);
     } else {
       // t = 1 coupling: drho~(1) = pi((2/sigma^2) (g1 . iota(du~(1))) g1)
       full_.iota_kind(dm + (int64_t)nt_ * 3 * Q, S(0), 3, kPlain);
       coupling_v3<float>(S(3), 2.0f / float(sigma2_), g1_.get(), S(0), d_, st_);
       float* dr = incadj_.get();
       full_.pi(S(3), dr + (int64_t)nt_ * 3 * Q, 3);
-      bl_backward_planes(dr, 3, acc_.get());
+      bl_backward_planes(dr, 3, acc_.get(), false, h, dv);
     }
-    bl_scale_sym<float>(h, dv, Lsym_.get(), 3, Q, acc_.get(), st_);
   }
 
-  void bl_backward_planes(float* traj, int nc, float* acc) {
+  // With h_out, the last step writes h_out = L~ x_sym + (the accumulated term) instead of acc; with
+  // t_formed, the product-grid plane-band input of the first step was formed by the caller.
+  void bl_backward_planes(float* traj, int nc, float* acc, bool t_formed = false, float* h_out = nullptr,
+                          const float* x_sym = nullptr) {
     const int64_t Q = d_.Q;
     const int64_t stride = (int64_t)nc * Q;
     const float hdt = 0.5f * dt_;
@@ -754,8 +771,7 @@ class Solver final : public SolverBase {
     const int np = v1 ? 4 : 6;
     int kpref[kMaxFields][3];
     for (int f = 0; f < kMaxFields; ++f) kpref[f][0] = kpref[f][1] = kpref[f][2] = kPref;
-    zero(acc, 3 * Q, st_);
-    {  // product-grid plane-band input of x_Nt
+    if (!t_formed) {  // product-grid plane-band input of x_Nt
       Axis0Args a = sm_.axis0_args(0);
       a.nout = nc;
       for (int c = 0; c < nc; ++c) a.o[c] = sm_.target(c, kPlain, -1, traj + nt_ * stride + c * Q, 1.f);
@@ -773,8 +789,14 @@ class Solver final : public SolverBase {
       for (int j = 0; j < 3; ++j) {
         a.out[nc + j] = acc + j * Q;
         a.alpha[nc + j] = v1 ? w : -w;
-        a.beta[nc + j] = 1.f;
+        a.beta[nc + j] = n == nt_ ? 0.f : 1.f;  // the first step starts the accumulation
         if (!v1) a.z[nc + j] = xn + j * Q, a.gamma[nc + j] = w;  // + w x_n
+        if (n == 0 && h_out) {  // last step: h = L~ x_sym + acc
+          a.in[nc + j] = acc + j * Q;
+          a.out[nc + j] = h_out + j * Q;
+          a.y[nc + j] = x_sym + j * Q;
+          a.ysym[nc + j] = Lsym_.get();
+        }
       }
       if (n > 0) {  // plane-band inputs of cA = P(x + dt/2 fl), cB = P(x + dt fl)
         a.nout = 2 * nc;
