@@ -71,68 +71,83 @@ __device__ __forceinline__ float bload_if(Rsrc r, unsigned idx, bool ok) {
 __device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
 // ------------------------------------------------------------------ expansion
-// One wave task: plane (f, x0), x1 block b (32 rows), a group of up to two x2 tiles (32 columns each).
-// Stage 1: V[a2][x1] = sum_a1 T[a1][a2] W1t[a1][x1] (T read along a2, W1t along x1), JB k-steps;
-// stage 2 per x2 tile: out[x1][x2] = sum_a2 V[a2][x1] W2t[a2][x2], V's registers as the A operand.
-// Ragged lanes need no test: a lane past n1 or n2 reads finite neighbouring entries and its results
-// are not stored, and rows a2 >= k2 of V meet rows of W2t past its end, which read as zeros (the
-// plane-band buffers are zero-initialised, so every entry a tile can reach is finite).
+// One workgroup (4 waves) per (field f, plane x0, x1 block b of 32 rows).  Stage 1,
+// V[a2][x1] = sum_a1 T[a1][a2] W1t[a1][x1] (T read along a2, W1t along x1), is split over the waves by
+// k-steps and summed in LDS in wave order; stage 2, out[x1][x2] = sum_a2 V[a2][x1] W2t[a2][x2] with V's
+// registers as the A operand, takes the x2 tiles wave, wave + 4, ...  Ragged lanes need no test: a
+// lane past n1 or n2 reads finite neighbouring entries and its results are not stored, and rows
+// a2 >= k2 of V meet rows of W2t past its end, which read as zeros (every plane-band entry a tile can
+// reach is written or zero-initialised, so finite).
 template <int JB, int KT2, bool EXACT>
 __global__ __launch_bounds__(256) void k_expand(PlaneExpandArgs a) {
+  __shared__ float red[4 * KT2 * 1024];
+  constexpr int JW = (JB + 3) / 4;  // stage-1 k-steps per wave
   const int lane = threadIdx.x & 63, i = lane & 31, kh = lane >> 5;
   const int wave = uniform(threadIdx.x >> 6);
   const int n1 = a.n1, n2 = a.n2, k1 = a.k1, k2 = a.k2, J1 = EXACT ? JB : k1 >> 1;
-  const int T2 = (n2 + 31) >> 5, B1 = (n1 + 31) >> 5, G = (T2 + a.g - 1) / a.g, tpp = B1 * G;
-  const int task = blockIdx.x * 4 + wave;
-  if (task >= a.ntask) return;
-  const int plane = task / tpp, t = task - plane * tpp;
-  const int f = plane / a.n0, x0 = plane - f * a.n0;
-  const int b = t % B1, grp = t / B1;
-  const int t2b = grp * a.g, nt = min(a.g, T2 - t2b);
+  const int T2 = (n2 + 31) >> 5;
+  const int b = blockIdx.x, x0 = blockIdx.y, f = blockIdx.z;
   const Rsrc rT = rsrc(a.T[f] + x0 * (k1 * k2), (int64_t)(a.n0 - x0) * k1 * k2);
   const Rsrc r1 = rsrc(a.w1t[f], (int64_t)k1 * n1);  // [k1][n1]
   const Rsrc r2 = rsrc(a.w2t[f], (int64_t)k2 * n2);  // [k2][n2]
   float* __restrict__ out = a.out + (size_t)(f * a.n0 + x0) * (size_t)(n1 * n2);
   const int x1 = b * 32 + i;
-  // stage-2 operands of the (at most two) x2 tiles, requested first
-  float wc[2][KT2][16];
+  // stage-2 operands of the wave's first x2 tile, requested first
+  float wc[KT2][16];
 #pragma unroll
-  for (int u = 0; u < 2; ++u)
+  for (int q = 0; q < KT2; ++q)
 #pragma unroll
-    for (int q = 0; q < KT2; ++q)
+    for (int r = 0; r < 16; ++r)
+      wc[q][r] = bload_if(r2, (unsigned)((q * 32 + acc_row(r, lane)) * n2 + wave * 32 + i), wave < T2);
+  // stage 1, this wave's k-steps j = wave JW .. wave JW + JW - 1 (a1 = kh J1 + j)
+  float wb[JW];
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int x2 = (t2b + u) * 32 + i;
-        const int a2 = q * 32 + acc_row(r, lane);
-        wc[u][q][r] = bload_if(r2, (unsigned)(a2 * n2 + x2), u < nt);
-      }
-  // stage 1: k-step j takes a1 = kh J1 + j
-  float wb[JB];
-#pragma unroll
-  for (int j = 0; j < JB; ++j) wb[j] = bload_if(r1, (unsigned)((kh * J1 + j) * n1 + x1), EXACT || j < J1);
+  for (int u = 0; u < JW; ++u) {
+    const int j = wave * JW + u;
+    wb[u] = bload_if(r1, (unsigned)((kh * J1 + j) * n1 + x1), (EXACT && JW * 4 == JB) || j < J1);
+  }
   f32x16 V[KT2];
 #pragma unroll
   for (int q = 0; q < KT2; ++q) {
     zero16(V[q]);
     const int a2 = q * 32 + i;
-    float ta[JB];
+    float ta[JW];
 #pragma unroll
-    for (int j = 0; j < JB; ++j) ta[j] = bload_if(rT, (unsigned)((kh * J1 + j) * k2 + a2), EXACT || j < J1);
+    for (int u = 0; u < JW; ++u) {
+      const int j = wave * JW + u;
+      ta[u] = bload_if(rT, (unsigned)((kh * J1 + j) * k2 + a2), (EXACT && JW * 4 == JB) || j < J1);
+    }
 #pragma unroll
-    for (int j = 0; j < JB; ++j) V[q] = mfma(ta[j], wb[j], V[q]);
+    for (int u = 0; u < JW; ++u) V[q] = mfma(ta[u], wb[u], V[q]);
   }
+#pragma unroll
+  for (int q = 0; q < KT2; ++q)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) red[((wave * KT2 + q) * 16 + r) * 64 + lane] = V[q][r];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < KT2; ++q)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int e = (q * 16 + r) * 64 + lane;
+      V[q][r] = red[e] + red[KT2 * 1024 + e] + red[2 * KT2 * 1024 + e] + red[3 * KT2 * 1024 + e];
+    }
   // stage 2: k-step r of tile q contracts a2 = q 32 + acc_row(r); output rows x1, columns x2
   const bool fullrows = b * 32 + 32 <= n1;
+  for (int t2 = wave; t2 < T2; t2 += 4) {
+    const int x2b = t2 * 32, x2 = x2b + i;
+    if (t2 != wave) {
 #pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    if (u >= nt) break;
-    const int x2b = (t2b + u) * 32, x2 = x2b + i;
+      for (int q = 0; q < KT2; ++q)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) wc[q][r] = bload(r2, (unsigned)((q * 32 + acc_row(r, lane)) * n2 + x2));
+    }
     f32x16 acc;
     zero16(acc);
 #pragma unroll
     for (int q = 0; q < KT2; ++q)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) acc = mfma(V[q][r], wc[u][q][r], acc);
+      for (int r = 0; r < 16; ++r) acc = mfma(V[q][r], wc[q][r], acc);
     if (fullrows && x2b + 32 <= n2) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) out[(unsigned)((b * 32 + acc_row(r, lane)) * n2 + x2)] = acc[r];
@@ -195,7 +210,7 @@ struct RedIn {
 // no test: rows x1 >= n1 meet rows of P1t past its end and columns x2 >= n2 rows of P2t past its end,
 // which read as zeros, against finite grid entries.  The waves' partial R are summed in LDS in wave
 // order (deterministic) and stored.
-template <int MODE, int KT1, int KT2, int WAVES>
+template <int MODE, int KT1, int KT2, int WAVES, int CH>
 __global__ __launch_bounds__(64 * WAVES) void k_reduce(PlaneReduceArgs a) {
   extern __shared__ float red[];  // [WAVES][KT1 KT2][16][64]
   const int lane = threadIdx.x & 63, i = lane & 31, kh = lane >> 5;
@@ -203,7 +218,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_reduce(PlaneReduceArgs a) {
   const int plane = blockIdx.x;
   const int f = plane / a.n0, x0 = plane - f * a.n0;
   const int n1 = a.n1, n2 = a.n2, k1 = a.k1, k2 = a.k2;
-  const int T2 = (n2 + 31) >> 5, S1 = (n1 + 63) >> 6;
+  const int T2 = (n2 + 31) >> 5, S1 = (n1 + CH - 1) / CH;
   const RedIn<MODE> src(a);
   const Rsrc rp1 = rsrc(a.p1t, (int64_t)n1 * k1), rp2 = rsrc(a.p2t, (int64_t)n2 * k2);
   f32x16 R[KT1][KT2];
@@ -212,21 +227,23 @@ __global__ __launch_bounds__(64 * WAVES) void k_reduce(PlaneReduceArgs a) {
 #pragma unroll
     for (int q = 0; q < KT2; ++q) zero16(R[p][q]);
   const unsigned pbase = (unsigned)(x0 * n1 * n2);
-  constexpr int JC = MODE == kRedPlain ? 16 : 8;
+  constexpr int JA = CH / 2;  // stage-A k-steps of a task
+  constexpr int JC = MODE == kRedPlain ? (JA < 16 ? JA : 16) : 8;
+  constexpr int NH = JA / JC > 1 ? 2 : 1;  // accumulators (shorter rounding chains)
   for (int task = wave; task < T2 * S1; task += WAVES) {
     const int t = task % T2, s = task / T2;
     const int x2 = t * 32 + i;
-    f32x16 W[2][KT1];
+    f32x16 W[NH][KT1];
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
+    for (int h = 0; h < NH; ++h)
 #pragma unroll
       for (int p = 0; p < KT1; ++p) zero16(W[h][p]);
 #pragma unroll
-    for (int jc = 0; jc < 32; jc += JC) {
+    for (int jc = 0; jc < JA; jc += JC) {
       float xa[JC];
 #pragma unroll
       for (int j = 0; j < JC; ++j) {
-        const int x1 = s * 64 + kh * 32 + jc + j;
+        const int x1 = s * CH + kh * JA + jc + j;
         xa[j] = src(f, pbase + (unsigned)(x1 * n2 + x2));
       }
 #pragma unroll
@@ -235,10 +252,10 @@ __global__ __launch_bounds__(64 * WAVES) void k_reduce(PlaneReduceArgs a) {
         float pb[JC];
 #pragma unroll
         for (int j = 0; j < JC; ++j) {
-          const int x1 = s * 64 + kh * 32 + jc + j;
+          const int x1 = s * CH + kh * JA + jc + j;
           pb[j] = bload_if(rp1, (unsigned)(x1 * k1 + a1), a1 < k1);
         }
-        const int h = (jc / JC) & 1;
+        const int h = (jc / JC) % NH;
 #pragma unroll
         for (int j = 0; j < JC; ++j) W[h][p] = mfma(xa[j], pb[j], W[h][p]);
       }
@@ -253,7 +270,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_reduce(PlaneReduceArgs a) {
 #pragma unroll
       for (int p = 0; p < KT1; ++p)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) R[p][q] = mfma(W[0][p][r] + W[1][p][r], pc[r], R[p][q]);
+        for (int r = 0; r < 16; ++r) R[p][q] = mfma(NH == 2 ? W[0][p][r] + W[NH - 1][p][r] : W[0][p][r], pc[r], R[p][q]);
     }
   }
   // sum of the waves' partials in wave order
@@ -285,7 +302,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_reduce(PlaneReduceArgs a) {
 // finished.  Every operand that does not depend on F is requested at the start; absent band sources
 // point at zeros.  As in the other stages, ragged lanes read finite neighbours and are not stored, and
 // rows past the end of an operand read as zeros.
-template <int KT0, int JB, bool EXACT>
+template <int KT0, int JB, bool EXACT, int CPW>
 __global__ __launch_bounds__(256) void k_axis0(Axis0Kernel a) {
   __shared__ float red[4 * KT0 * 1024];
   __shared__ float fin[64 * 32];  // the finished field of this workgroup, [a0][32 columns]
@@ -334,20 +351,40 @@ __global__ __launch_bounds__(256) void k_axis0(Axis0Kernel a) {
     f32x16 acc[KT0];
 #pragma unroll
     for (int p = 0; p < KT0; ++p) zero16(acc[p]);
-    // x0 in chunks of 8 (4 k-steps, lane halves 4 apart) dealt to the waves in turn
+    // x0 in chunks of 8 (4 k-steps, lane halves 4 apart) dealt to the waves in turn; with CPW > 0 the
+    // wave's CPW chunks are requested at once (chunks past n0 read zeros)
     const int nch = (n0 + 7) >> 3;
-    for (int ch = wave; ch < nch; ch += 4) {
-      float bv[4];
+    if constexpr (CPW > 0) {
+      float bv[CPW][4], av[CPW][KT0][4];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bv[j] = bload(rpart, (unsigned)((ch * 8 + kh * 4 + j) * C + c));
+      for (int u = 0; u < CPW; ++u)
 #pragma unroll
-      for (int p = 0; p < KT0; ++p) {
-        const int a0 = p * 32 + i;
-        float av[4];
+        for (int j = 0; j < 4; ++j) {
+          const int x0 = (wave + 4 * u) * 8 + kh * 4 + j;
+          bv[u][j] = bload(rpart, (unsigned)(x0 * C + c));
 #pragma unroll
-        for (int j = 0; j < 4; ++j) av[j] = bload(rp0, (unsigned)((ch * 8 + kh * 4 + j) * k0 + a0));
+          for (int p = 0; p < KT0; ++p) av[u][p][j] = bload(rp0, (unsigned)(x0 * k0 + p * 32 + i));
+        }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[p] = mfma(av[j], bv[j], acc[p]);
+      for (int u = 0; u < CPW; ++u)
+#pragma unroll
+        for (int p = 0; p < KT0; ++p)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[p] = mfma(av[u][p][j], bv[u][j], acc[p]);
+    } else {
+      for (int ch = wave; ch < nch; ch += 4) {
+        float bv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bv[j] = bload(rpart, (unsigned)((ch * 8 + kh * 4 + j) * C + c));
+#pragma unroll
+        for (int p = 0; p < KT0; ++p) {
+          const int a0 = p * 32 + i;
+          float av[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) av[j] = bload(rp0, (unsigned)((ch * 8 + kh * 4 + j) * k0 + a0));
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[p] = mfma(av[j], bv[j], acc[p]);
+        }
       }
     }
 #pragma unroll
@@ -422,17 +459,12 @@ bool planes_ok(const Dims& d) {
 
 static int jb_of(int j) { return j <= 8 ? 8 : j <= 16 ? 16 : j <= 24 ? 24 : 32; }
 
-void plane_expand(const PlaneExpandArgs& a0, hipStream_t s) {
-  PlaneExpandArgs a = a0;
-  const int T2 = ceil_div(a.n2, 32), B1 = ceil_div(a.n1, 32);
-  // x2 tiles per wave (stage 1 is shared by them): two while that keeps a wave per SIMD (1024) busy
-  a.g = (T2 >= 2 && (int64_t)a.nf * a.n0 * B1 * ceil_div(T2, 2) >= 1024) ? 2 : 1;
-  const int64_t tasks = (int64_t)a.nf * a.n0 * B1 * ceil_div(T2, a.g);
-  if (tasks >= (int64_t(1) << 31) - 4) throw ArgError("plane_expand: too many tasks");
-  a.ntask = static_cast<int>(tasks);
+void plane_expand(const PlaneExpandArgs& a, hipStream_t s) {
+  const int B1 = ceil_div(a.n1, 32);
+  if (a.n0 > 65535 || a.nf > 65535) throw ArgError("plane_expand: grid too large");
   const double bytes = 4.0 * a.nf * ((double)a.n0 * a.k1 * a.k2 + (double)a.n0 * a.n1 * a.n2);
   const double flops = 2.0 * a.nf * a.n0 * ((double)a.k1 * a.k2 * a.n1 + (double)a.n1 * a.k2 * a.n2);
-  dim3 g(static_cast<unsigned>((tasks + 3) / 4));
+  dim3 g(B1, a.n0, a.nf);
   const int j1 = a.k1 / 2, jb = jb_of(j1);
   auto go = [&](auto kern) { prof::launch("k_expand", bytes, flops, kern, g, dim3(256), 0, s, a); };
   if (a.k2 <= 32) {
@@ -454,14 +486,16 @@ static void reduce_mode(const PlaneReduceArgs& a, hipStream_t s, double bytes, d
   const int kt1 = a.k1 > 32 ? 2 : 1, kt2 = a.k2 > 32 ? 2 : 1;
   dim3 g(static_cast<unsigned>(a.nf * a.n0));
   const char* nm = MODE == kRedPlain ? "k_reduce" : "k_reduce_products";
+  // tasks of 64 rows (16-wave workgroups with 32-row tasks measured slower); fewer waves for the
+  // larger bands (LDS of the partial sums)
   if (kt1 == 1 && kt2 == 1)
-    prof::launch(nm, bytes, flops, k_reduce<MODE, 1, 1, 8>, g, dim3(512), 8 * 1024 * 4, s, a);
+    prof::launch(nm, bytes, flops, k_reduce<MODE, 1, 1, 8, 64>, g, dim3(512), 8 * 1024 * 4, s, a);
   else if (kt1 == 1)
-    prof::launch(nm, bytes, flops, k_reduce<MODE, 1, 2, 8>, g, dim3(512), 8 * 2048 * 4, s, a);
+    prof::launch(nm, bytes, flops, k_reduce<MODE, 1, 2, 8, 64>, g, dim3(512), 8 * 2048 * 4, s, a);
   else if (kt2 == 1)
-    prof::launch(nm, bytes, flops, k_reduce<MODE, 2, 1, 8>, g, dim3(512), 8 * 2048 * 4, s, a);
+    prof::launch(nm, bytes, flops, k_reduce<MODE, 2, 1, 8, 64>, g, dim3(512), 8 * 2048 * 4, s, a);
   else
-    prof::launch(nm, bytes, flops, k_reduce<MODE, 2, 2, 4>, g, dim3(256), 4 * 4096 * 4, s, a);
+    prof::launch(nm, bytes, flops, k_reduce<MODE, 2, 2, 4, 64>, g, dim3(256), 4 * 4096 * 4, s, a);
   LDDMM_LAUNCH_CHECK();
 }
 
@@ -530,16 +564,23 @@ void plane_axis0(const Axis0Args& a, hipStream_t s) {
   dim3 g(ceil_div(a.C, 32), nrow);
   const int j0 = (a.k0 + 1) / 2, jb = jb_of(j0);
   const bool ex = a.k0 % 2 == 0;
+  const int cpw = ceil_div(ceil_div(a.n0, 8), 4);  // x0 chunks per wave
   const std::string nm = "k_axis0[" + std::to_string(a.nin) + "F" + std::to_string(a.nout) + "P]";
   auto go = [&](auto kern) { prof::launch(nm, bytes, flops, kern, g, dim3(256), 0, s, k); };
-  if (ex && j0 == 16) go(k_axis0<1, 16, true>);
-  else if (ex && j0 == 20) go(k_axis0<2, 20, true>);
-  else if (ex && j0 == 24) go(k_axis0<2, 24, true>);
-  else if (ex && j0 == 32) go(k_axis0<2, 32, true>);
+  if (ex && j0 == 16 && cpw <= 2) go(k_axis0<1, 16, true, 2>);
+  else if (ex && j0 == 16 && cpw <= 4) go(k_axis0<1, 16, true, 4>);
+  else if (ex && j0 == 16) go(k_axis0<1, 16, true, 0>);
+  else if (ex && j0 == 20 && cpw <= 2) go(k_axis0<2, 20, true, 2>);
+  else if (ex && j0 == 20 && cpw <= 6) go(k_axis0<2, 20, true, 6>);
+  else if (ex && j0 == 20) go(k_axis0<2, 20, true, 0>);
+  else if (ex && j0 == 24 && cpw <= 2) go(k_axis0<2, 24, true, 2>);
+  else if (ex && j0 == 24 && cpw <= 6) go(k_axis0<2, 24, true, 6>);
+  else if (ex && j0 == 24) go(k_axis0<2, 24, true, 0>);
+  else if (ex && j0 == 32) go(k_axis0<2, 32, true, 0>);
   else if (a.k0 <= 32) {
-    if (jb == 8) go(k_axis0<1, 8, false>); else go(k_axis0<1, 16, false>);
+    if (jb == 8) go(k_axis0<1, 8, false, 0>); else go(k_axis0<1, 16, false, 0>);
   } else {
-    if (jb == 24) go(k_axis0<2, 24, false>); else go(k_axis0<2, 32, false>);
+    if (jb == 24) go(k_axis0<2, 24, false, 0>); else go(k_axis0<2, 32, false, 0>);
   }
   LDDMM_LAUNCH_CHECK();
 }

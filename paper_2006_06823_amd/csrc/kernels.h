@@ -54,7 +54,6 @@ struct PlaneExpandArgs {
   const float* w2t[kMaxFields];  // [k2][n2]
   float* out;                    // [nf][n0][n1][n2]
   int nf, n0, n1, n2, k1, k2;
-  int g, ntask;  // x2 tiles per wave and wave tasks (set by the launcher)
 };
 // reduction of planes: part[f][x0][a1][a2] = sum_{x1,x2} p1t[x1][a1] v_f(x0, x1, x2) p2t[x2][a2], with the
 // grid value v_f of the mode: a plain field, or a pointwise product of fields of the product grid
