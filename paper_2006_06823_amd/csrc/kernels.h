@@ -215,7 +215,19 @@ void brick_characteristics(float* disp, const float* v, const float* cv, const D
 
 // ---- FP64 reductions (reduce.hip) -------------------------------------------
 // partial results go to `work` (device, >= reduce_work_size doubles); result to host
+constexpr int kRedSlots = 32;  // device result slots of the asynchronous forms
 int64_t reduce_work_size();
+double* reduce_slots(double* work);
+// PCG vector updates reading their scalars from the result slots (no host round trip):
+// x += a p, r -= a Ap with a = slot[irz] / slot[ipap], skipped unless slot[ipap] > 0
+template <typename T>
+void pcg_step(T* x, T* r, const T* p, const T* Ap, double* work, int irz, int ipap, int64_t n, hipStream_t s);
+// p = z + (slot[irzn] / slot[irz]) p, skipped unless slot[ipap] > 0
+template <typename T>
+void pcg_dir(T* p, const T* z, double* work, int irz, int irzn, int ipap, int64_t n, hipStream_t s);
+// z += sum_i (Minv c)_i Z_i with c_i = slot[ic + i] (device Minv r x r, Z r x n)
+template <typename T>
+void lowrank_add(T* z, const T* Z, const double* Minv, double* work, int ic, int r, int64_t n, hipStream_t s);
 template <typename T>
 double dot(const T* a, const T* b, int64_t n, double* work, double* host_pinned, hipStream_t s);
 template <typename T>
@@ -227,7 +239,7 @@ template <typename T>
 double sym_dot(const T* x, const T* y, const double* sym, int ncomp, int64_t Q, double* work,
                double* host_pinned, hipStream_t s);
 void minmax_f64(const double* a, int64_t n, double* work, double* host_pinned2, hipStream_t s);
-// Asynchronous forms: the result stays in result slot `slot` (0..7) of `work` until fetch_async
+// Asynchronous forms: the result stays in result slot `slot` (0..kRedSlots-1) of `work` until fetch_async
 // copies slots 0 .. count-1 into pinned host memory on the stream; the values are valid once the
 // stream has been synchronised.
 enum class RedKind { Dot, SqDiff, MaxAbs };

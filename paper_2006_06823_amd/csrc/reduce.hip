@@ -100,7 +100,9 @@ double fetch(double* work, double* host, int count, hipStream_t s) {
 
 }  // namespace
 
-int64_t reduce_work_size() { return kRBlocks + 8; }
+int64_t reduce_work_size() { return kRBlocks + kRedSlots; }
+
+double* reduce_slots(double* work) { return work + kRBlocks; }
 
 template <typename T>
 double dot(const T* a, const T* b, int64_t n, double* work, double* host, hipStream_t s) {
@@ -135,7 +137,7 @@ void minmax_f64(const double* a, int64_t n, double* work, double* host2, hipStre
 
 template <typename T>
 void reduce_launch(RedKind kind, const T* a, const T* b, int64_t n, double* work, int slot, hipStream_t s) {
-  if (slot < 0 || slot >= 8) throw ArgError("reduce_launch: result slot out of range");
+  if (slot < 0 || slot >= kRedSlots) throw ArgError("reduce_launch: result slot out of range");
   switch (kind) {
     case RedKind::Dot:
       launch<T, Kind::Dot>(a, b, nullptr, 1, n, work, s, slot);
@@ -152,13 +154,72 @@ void reduce_launch(RedKind kind, const T* a, const T* b, int64_t n, double* work
 template <typename T>
 void sym_dot_launch(const T* x, const T* y, const double* sym, int ncomp, int64_t Q, double* work, int slot,
                     hipStream_t s) {
-  if (slot < 0 || slot >= 8) throw ArgError("sym_dot_launch: result slot out of range");
+  if (slot < 0 || slot >= kRedSlots) throw ArgError("sym_dot_launch: result slot out of range");
   launch<T, Kind::SymDot>(x, y, sym, Q, Q * ncomp, work, s, slot);
 }
 
 void fetch_async(double* work, double* host, int count, hipStream_t s) {
   LDDMM_HIP(hipMemcpyAsync(host, work + kRBlocks, count * sizeof(double), hipMemcpyDeviceToHost, s));
 }
+
+// ---- PCG steps with their scalars on the device (result slots sc = reduce_slots(work))
+namespace {
+// x += a p, r -= a Ap with a = rz / pAp, applied only when pAp > 0 (a non-positive curvature leaves
+// every vector as it was, for the caller's truncation)
+template <typename T>
+__global__ void k_pcg_step(T* x, T* r, const T* p, const T* Ap, const double* sc, int irz, int ipap, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const double pap = sc[ipap];
+  if (i >= n || !(pap > 0.0)) return;
+  const T a = static_cast<T>(sc[irz] / pap);
+  x[i] = T(1) * x[i] + a * p[i];
+  r[i] = T(1) * r[i] + (-a) * Ap[i];
+}
+// p = z + (rz_new / rz) p, only when pAp > 0
+template <typename T>
+__global__ void k_pcg_dir(T* p, const T* z, const double* sc, int irz, int irzn, int ipap, int64_t n) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n || !(sc[ipap] > 0.0)) return;
+  const T b = static_cast<T>(sc[irzn] / sc[irz]);
+  p[i] = T(1) * z[i] + b * p[i];
+}
+// z += sum_i y_i Z_i with y = Minv c, c_i = sc[ic + i] (r <= 16 directions of length n, Minv r x r)
+template <typename T>
+__global__ void k_lowrank_add(T* z, const T* Z, const double* Minv, const double* sc, int ic, int r, int64_t n) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  double acc = 0.0;
+  for (int i = 0; i < r; ++i) {
+    double yi = 0.0;
+    for (int j = 0; j < r; ++j) yi += Minv[i * r + j] * sc[ic + j];
+    acc += yi * static_cast<double>(Z[(int64_t)i * n + k]);
+  }
+  z[k] = z[k] + static_cast<T>(acc);
+}
+}  // namespace
+
+template <typename T>
+void pcg_step(T* x, T* r, const T* p, const T* Ap, double* work, int irz, int ipap, int64_t n, hipStream_t s) {
+  k_pcg_step<T><<<ceil_div(n, 256), 256, 0, s>>>(x, r, p, Ap, work + kRBlocks, irz, ipap, n);
+  LDDMM_LAUNCH_CHECK();
+}
+template <typename T>
+void pcg_dir(T* p, const T* z, double* work, int irz, int irzn, int ipap, int64_t n, hipStream_t s) {
+  k_pcg_dir<T><<<ceil_div(n, 256), 256, 0, s>>>(p, z, work + kRBlocks, irz, irzn, ipap, n);
+  LDDMM_LAUNCH_CHECK();
+}
+template <typename T>
+void lowrank_add(T* z, const T* Z, const double* Minv, double* work, int ic, int r, int64_t n, hipStream_t s) {
+  k_lowrank_add<T><<<ceil_div(n, 256), 256, 0, s>>>(z, Z, Minv, work + kRBlocks, ic, r, n);
+  LDDMM_LAUNCH_CHECK();
+}
+template void pcg_step<float>(float*, float*, const float*, const float*, double*, int, int, int64_t, hipStream_t);
+template void pcg_step<double>(double*, double*, const double*, const double*, double*, int, int, int64_t,
+                               hipStream_t);
+template void pcg_dir<float>(float*, const float*, double*, int, int, int, int64_t, hipStream_t);
+template void pcg_dir<double>(double*, const double*, double*, int, int, int, int64_t, hipStream_t);
+template void lowrank_add<float>(float*, const float*, const double*, double*, int, int, int64_t, hipStream_t);
+template void lowrank_add<double>(double*, const double*, const double*, double*, int, int, int64_t, hipStream_t);
 
 template void reduce_launch<float>(RedKind, const float*, const float*, int64_t, double*, int, hipStream_t);
 template void reduce_launch<double>(RedKind, const double*, const double*, int64_t, double*, int, hipStream_t);

@@ -856,7 +856,12 @@ class Solver final : public SolverBase {
   void set_velocity_internal(const T* v) { copy(vbl_.get(), v, 3 * d_.Q); }
   void state_internal(double e[3]) { run_state(e); }
   void adjoint_internal(T* g) { run_adjoint(g); }
-  void matvec_internal(const T* x, T* y) { run_matvec(x, y); }
+  // H x into y through the captured graph (its fixed buffers dvbl_ -> hbl_)
+  void matvec_internal(const T* x, T* y) {
+    if (x != dvbl_.get()) copy(dvbl_.get(), x, 3 * d_.Q);
+    matvec_graph();
+    if (y != hbl_.get()) copy(y, hbl_.get(), 3 * d_.Q);
+  }
   void precond_internal(const T* r, T* z) { bl_scale_sym<T>(z, r, Linv_.get(), 3, d_.Q, nullptr, st_); }
   double dot_internal(const T* a, const T* b) {
     return lddmm::dot<T>(a, b, 3 * d_.Q, work_.get(), host_.get(), st_);
@@ -961,7 +966,7 @@ int Solver<T>::gn_solve(const lddmm_bl_gn_opts& o, void* v_user, const void* Zu,
   if (Zu && (r < 1 || r > 16)) throw ArgError("preconditioner rank must be 1..16");
   const auto t0 = std::chrono::steady_clock::now();
   const int64_t n = vec_len();
-  DevBuf<T> v(n), g(n), x(n), rr(n), z(n), p(n), Ap(n), vt(n), Z, HZ;
+  DevBuf<T> v(n), g(n), x(n), rr(n), z(n), vt(n), Z, HZ;
   std::vector<double> ZHZinv;
   int status = LDDMM_BL_OK;
   lddmm_bl_gn_report R{};
@@ -989,14 +994,18 @@ int Solver<T>::gn_solve(const lddmm_bl_gn_opts& o, void* v_user, const void* Zu,
       user_to_internal(Z.get() + i * n, static_cast<const T*>(Zu) + (int64_t)i * (n / 3) * dim_);
     ZHZinv.assign(r * r, 0.0);
   }
+  // device result slots of the PCG: p.Hp, r.r, r.z (ping-pong), Z^T r
+  enum { kPAP = 0, kRN2 = 1, kRZ0 = 2, kZC = 8 };
+  DevBuf<double> Minv;
+  if (twolevel) Minv.alloc(r * r);
+  double* const wk = work_.get();
+  const double* const hs = host_.get();
+  // M^-1 r = L~^-1 r (+ Z (Z^T H Z)^-1 Z^T r), every scalar on the device
   auto precond = [&](const T* rin, T* zout) {
     precond_internal(rin, zout);
     if (!twolevel) return;
-    std::vector<double> c(r), y(r, 0.0);
-    for (int i = 0; i < r; ++i) c[i] = dot_internal(Z.get() + i * n, rin);
-    for (int i = 0; i < r; ++i)
-      for (int j = 0; j < r; ++j) y[i] += ZHZinv[i * r + j] * c[j];
-    for (int i = 0; i < r; ++i) axpby_internal(zout, T(1), zout, T(y[i]), Z.get() + i * n);
+    for (int i = 0; i < r; ++i) reduce_launch<T>(RedKind::Dot, Z.get() + i * n, rin, n, wk, kZC + i, stream());
+    lowrank_add<T>(zout, Z.get(), Minv.get(), wk, kZC, r, n, stream());
   };
   auto log_iter = [&](int it, int pcg, int neg, int bt) {
     if (it >= LDDMM_BL_LOG_MAX) return;
@@ -1057,37 +1066,49 @@ int Solver<T>::gn_solve(const lddmm_bl_gn_opts& o, void* v_user, const void* Zu,
         ZHZinv = Inv;
       else
         std::fill(ZHZinv.begin(), ZHZinv.end(), 0.0);
+      LDDMM_HIP(hipMemcpyAsync(Minv.get(), ZHZinv.data(), r * r * sizeof(double), hipMemcpyHostToDevice, stream()));
+      synchronize();
     }
     const double gnorm = std::sqrt(dot_internal(g.get(), g.get()));
     const double eta = gnorm0 > 0 ? std::min(0.5, std::sqrt(gnorm / gnorm0)) : 0.5;
     const double tol = eta * gnorm;
-    // PCG
+    // PCG from x = 0.  p and H p are the matvec graph's own buffers; the step lengths stay on the device
+    // and one host round trip per iteration reads p.Hp and r.r
+    T* const pv = dvbl_.get();
+    T* const Apv = hbl_.get();
     zero(x.get(), n, stream());
     axpby_internal(rr.get(), T(-1), g.get(), T(0), nullptr);
     precond(rr.get(), z.get());
-    copy_internal(p.get(), z.get());
-    double rz = dot_internal(rr.get(), z.get());
+    copy_internal(pv, z.get());
+    int irz = kRZ0, irzn = kRZ0 + 1;
+    reduce_launch<T>(RedKind::Dot, rr.get(), z.get(), n, wk, irz, stream());
+    reduce_launch<T>(RedKind::Dot, rr.get(), rr.get(), n, wk, kRN2, stream());
+    fetch_async(wk, host_.get(), 2, stream());
+    synchronize();
+    double rn = std::sqrt(hs[kRN2]);
     int its = 0, negcurv = 0;
     for (its = 0; its < o.max_pcg; ++its) {
-      const double rn = std::sqrt(dot_internal(rr.get(), rr.get()));
       if (!fixed && rn <= tol) break;
-      matvec_internal(p.get(), Ap.get());
+      matvec_graph();  // H p
       ++R.hess_matvecs;
-      const double pAp = dot_internal(p.get(), Ap.get());
+      reduce_launch<T>(RedKind::Dot, pv, Apv, n, wk, kPAP, stream());
+      pcg_step<T>(x.get(), rr.get(), pv, Apv, wk, irz, kPAP, n, stream());
+      precond(rr.get(), z.get());
+      reduce_launch<T>(RedKind::Dot, rr.get(), z.get(), n, wk, irzn, stream());
+      reduce_launch<T>(RedKind::Dot, rr.get(), rr.get(), n, wk, kRN2, stream());
+      pcg_dir<T>(pv, z.get(), wk, irz, irzn, kPAP, n, stream());
+      fetch_async(wk, host_.get(), trace_ ? 4 : 2, stream());
+      synchronize();
+      const double pAp = hs[kPAP];
       if (!std::isfinite(pAp)) throw NonFiniteError("non-finite curvature in PCG");
       if (pAp <= 0.0) {
-        negcurv = 1;  // truncated CG: the direction so far (or the first search direction)
-        if (its == 0) copy_internal(x.get(), p.get());
+        negcurv = 1;  // truncated CG: the direction so far (or the first search direction, p unchanged)
+        if (its == 0) copy_internal(x.get(), pv);
         break;
       }
-      const double a = rz / pAp;
-      if (trace_) fprintf(stderr, "[lddmm_bl] gn %d pcg %d rz %.17g pAp %.17g a %.17g\n", k, its, rz, pAp, a);
-      axpby_internal(x.get(), T(1), x.get(), T(a), p.get());
-      axpby_internal(rr.get(), T(1), rr.get(), T(-a), Ap.get());
-      precond(rr.get(), z.get());
-      const double rz_new = dot_internal(rr.get(), z.get());
-      axpby_internal(p.get(), T(1), z.get(), T(rz_new / rz), p.get());
-      rz = rz_new;
+      if (trace_) fprintf(stderr, "[lddmm_bl] gn %d pcg %d rz %.17g pAp %.17g a %.17g\n", k, its, hs[irz], pAp, hs[irz] / pAp);
+      rn = std::sqrt(hs[kRN2]);
+      std::swap(irz, irzn);
     }
     R.pcg_iters_total += its;
     // Armijo line search on the objective

@@ -114,3 +114,31 @@ def test_gn_reuses_a_held_state_at_the_same_velocity(variant):
     for v, rep in ((held_v, held), (other_v, other), (renewed_v, renewed)):
         assert torch.equal(v, ref_v)
         assert rep["E0"] == ref["E0"] and rep["E"] == ref["E"] and rep["gn_iters"] == ref["gn_iters"]
+
+
+@pytest.mark.parametrize("variant,twolevel", [(1, False), (3, False), (3, True)])
+def test_gn_graph_replay_equals_eager_launches(variant, twolevel, monkeypatch):
+    """gn_solve runs its Hessian matvecs as replays of one captured HIP graph and keeps the PCG step
+    lengths on the device (one host round trip per PCG iteration); with LDDMM_BL_NO_GRAPH set the same
+    kernels are launched one by one.  Both give bitwise the same velocity, report and decisions, with the
+    plain and with the two-level preconditioner (random directions Z, r = 2)."""
+    N, K, Nt = (32, 28, 24), (8, 8, 6), 4
+    I0, I1 = syn.phantom_pair_3d(N, 6, max_disp_vox=2.0)
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda")
+    Z = t(0.01 * np.stack([syn.random_bl_coefficients(3, K, 40 + i) for i in range(2)])) if twolevel else None
+
+    def solve():
+        ctx = L.Context(L.Problem(N, K, nt=Nt, variant=variant, precision=L.FP32))
+        ctx.set_images(t(I0), t(I1))
+        v = torch.zeros((3,) + K, dtype=torch.float32, device="cuda")
+        st, rep = ctx.gn_solve(v, max_gn=3, max_pcg=4, fixed_iters=True, Z=Z)
+        ctx.close()
+        return v, rep
+
+    v_graph, r_graph = solve()
+    monkeypatch.setenv("LDDMM_BL_NO_GRAPH", "1")
+    v_eager, r_eager = solve()
+    print(f"[gn] graph vs eager decisions {r_graph['decisions']} / {r_eager['decisions']}", flush=True)
+    assert torch.equal(v_graph, v_eager)
+    assert r_graph["E"] == r_eager["E"] and r_graph["decisions"] == r_eager["decisions"]
+    assert r_graph["hess_matvecs"] == r_eager["hess_matvecs"] > 0
