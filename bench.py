@@ -34,6 +34,157 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_matvec_kernels_128.json")
 WEIGHTS_FILE = os.path.join(ROOT, "paper_2006_06823_amd", "weights", "warmstart_v1_128.npz")
 
 
+# library profile names of the DFT-stage kernels (MFMA figures in "extra")
+DFT_KERNELS = ("k_expand", "k_reduce", "k_axis0", "dft_", "k_iota", "k_pi")
+
+# library profile name (trailing field count and row-set suffix dropped) -> (pattern of the compiled kernel
+# name as a profiler lists it, spaces removed; the source files its code comes from)
+KERNEL_SOURCES = {
+    "k_brick<k_bl_adjoint_step>": (r"k_brick<[\w:()]*EpiBLAdjoint<", ("brick.hip", "common.h")),
+    "k_brick<k_interp>": (r"k_brick<[\w:()]*EpiInterp<", ("brick.hip", "common.h")),
+    "k_brick<k_interp_diff>": (r"k_brick<[\w:()]*EpiInterpDiff<", ("brick.hip", "common.h")),
+    "k_expand": (r"k_expand<", ("dft_planes.hip",)),
+    "k_reduce": (r"k_reduce<0,", ("dft_planes.hip",)),
+    "k_reduce_products": (r"k_reduce<[1-4],", ("dft_planes.hip",)),
+}
+
+
+def _base_name(name):
+    import re
+    return re.sub(r"(\[.*\])?\d*$", "", name)
+
+
+def _source_digest(files):
+    import hashlib
+    h = hashlib.sha1()
+    for f in files:
+        with open(os.path.join(ROOT, "paper_2006_06823_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(kernel, N, K, variant, alg_bytes):
+    """HBM bytes per launch of `kernel`: the stored ratio of measured (profiler FETCH_SIZE + WRITE_SIZE, scaled
+    by a plain copy of known size) over algorithmic bytes, times this run's algorithmic bytes per launch.  None
+    when no ratio was stored for this kernel and workload, or when the kernel's source changed since."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None, "no stored counter ratio"
+    tr = json.load(open(TRAFFIC_FILE))
+    ent = tr.get("kernels", {}).get(kernel)
+    if tr.get("workload") != list(N) + list(K) + [variant] or ent is None:
+        return None, "no stored counter ratio for this kernel and workload"
+    src = KERNEL_SOURCES.get(_base_name(kernel))
+    if src is None or _source_digest(src[1]) != ent.get("source_digest"):
+        return None, "kernel source changed since the counters were taken"
+    return (round(ent["traffic_over_algorithmic"] * alg_bytes),
+            f"stored ratio {ent['traffic_over_algorithmic']} (profiles/{os.path.basename(TRAFFIC_FILE)}) "
+            f"x this run's algorithmic bytes per launch")
+
+
+def write_traffic(d):
+    """Post-process four counter runs (no GPU): `d`/fetch and `d`/write hold FETCH_SIZE and WRITE_SIZE runs of
+    `bench.py --steps 2 --warmup 1 --no-cpu-baseline --learned-pairs 0`, `d`/cal_fetch and `d`/cal_write the
+    same counters over `bench.py --calibrate-copy 256`, `d`/bench.json the JSON line of an unprofiled run of
+    the same workload (it names the dominant kernel and its algorithmic bytes per launch; under the counters
+    the kernels run serialised and another kernel may lead).  Writes the stored ratio of the dominant kernel
+    (the profiler's most frequent launch shape of it) and prints a markdown table of every dispatch group."""
+    import collections
+    import csv
+    import re
+
+    def load(sub):
+        rows = list(csv.DictReader(open(os.path.join(d, sub, "run_counter_collection.csv"))))
+        per = collections.defaultdict(float)
+        meta = {}
+        for r in rows:
+            key = int(r["Dispatch_Id"])
+            per[key] += float(r["Counter_Value"])
+            meta[key] = (r["Kernel_Name"].replace(" ", ""), int(r["Grid_Size"]))
+        return per, meta
+
+    bench = json.loads(open(os.path.join(d, "bench.json")).read().strip().splitlines()[-1])
+    scale = {}
+    for c in ("fetch", "write"):
+        per, meta = load("cal_" + c)
+        vals = [per[k] for k in per if "copyBuffer" in meta[k][0]]
+        n_kib = 256 * 1024
+        scale[c] = n_kib / (sum(vals) / len(vals))
+    groups = collections.defaultdict(lambda: [0, 0.0, 0.0])
+    fetch, fmeta = load("fetch")
+    write, wmeta = load("write")
+    for c, per, meta in (("fetch", fetch, fmeta), ("write", write, wmeta)):
+        for k, v in per.items():
+            g = groups[meta[k]]
+            if c == "fetch":
+                g[0] += 1
+                g[1] += v * scale[c]
+            else:
+                g[2] += v * scale[c]
+    rf = bench["roofline"]
+    dom = rf["kernel"]
+    pat, files = KERNEL_SOURCES[_base_name(dom)]
+    cand = {key: g for key, g in groups.items() if re.search(pat, key[0]) and g[0] > 0}
+    if not cand:
+        raise SystemExit(f"no dispatch of {dom} in the counter runs")
+    key = max(cand, key=lambda k: cand[k][0])       # the most frequent (name, grid): the matvec's launches
+    n, rd, wr = cand[key]
+    ratio = round((rd + wr) / n * 1024.0 / rf["algorithmic_bytes_per_launch"], 4)
+    cfg = bench["config"]
+    out = {"workload": list(cfg["grid"]) + list(cfg["band"]) + [cfg["variant"]],
+           "fetch_scale": round(scale["fetch"], 5), "write_scale": round(scale["write"], 5),
+           "kernels": {dom: {"traffic_over_algorithmic": ratio, "dispatches": n, "source_digest": _source_digest(files),
+                             "read_KiB": round(rd / n, 1), "write_KiB": round(wr / n, 1),
+                             "algorithmic_KiB": round(rf["algorithmic_bytes_per_launch"] / 1024.0, 1)}}}
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(f"FETCH_SIZE x {scale['fetch']:.5f}, WRITE_SIZE x {scale['write']:.5f} (plain 256 MiB copy)\n")
+    print("| kernel | grid | dispatches | read KiB | write KiB |\n|---|---|---|---|---|")
+    for (name, grid), (n_, rd_, wr_) in sorted(groups.items(), key=lambda kv: -(kv[1][1] + kv[1][2])):
+        if n_ == 0:
+            continue
+        short = re.sub(r"\(.*", "", name.replace("void", "").replace("lddmm::", "").replace("(anonymousnamespace)::", ""))
+        print(f"| {short[:60]} | {grid} | {n_} | {rd_ / n_:.1f} | {wr_ / n_:.1f} |")
+    print(f"\n{dom}: {key[0][:60]} grid {key[1]}, {n} dispatches, measured/algorithmic = {ratio}")
+    if os.path.isdir(os.path.join(d, "sq")):
+        sq_table(d)
+
+
+def sq_table(d):
+    """Per-kernel averages of the SQ counter runs `d`/sq (SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_ANY
+    SQ_WAIT_INST_ANY SQ_ACTIVE_INST_ANY) and `d`/mfma (SQ_VALU_MFMA_BUSY_CYCLES SQ_BUSY_CU_CYCLES SQ_WAVES)."""
+    import collections
+    import csv
+    import re
+
+    def load(sub):
+        agg = collections.defaultdict(lambda: collections.defaultdict(float))
+        cnt = collections.defaultdict(set)
+        for r in csv.DictReader(open(os.path.join(d, sub, "run_counter_collection.csv"))):
+            name = re.sub(r"\(.*", "", r["Kernel_Name"].replace("void ", "").replace("lddmm::", "")
+                          .replace("(anonymous namespace)::", ""))
+            name = re.sub(r",\s*Tile<.*", ">", name)
+            agg[name][r["Counter_Name"]] += float(r["Counter_Value"])
+            cnt[name].add(r["Dispatch_Id"])
+        return agg, cnt
+
+    sq, n_sq = load("sq")
+    mf, _ = load("mfma") if os.path.isdir(os.path.join(d, "mfma")) else ({}, {})
+    print("\n| kernel | dispatches | waves / dispatch | wave lifetime (cycles) | waiting | issuing | MFMA busy |")
+    print("|---|---|---|---|---|---|---|")
+    order = sorted(sq, key=lambda k: -sq[k].get("SQ_WAVE_CYCLES", 0))
+    for k in order[:16]:
+        a, n = sq[k], len(n_sq[k])
+        w = a.get("SQ_WAVES", 0)
+        if w == 0:
+            continue
+        life = a.get("SQ_WAVE_CYCLES", 0)
+        mb = None
+        if k in mf and mf[k].get("SQ_BUSY_CU_CYCLES", 0) > 0:
+            mb = mf[k].get("SQ_VALU_MFMA_BUSY_CYCLES", 0) / (4.0 * mf[k]["SQ_BUSY_CU_CYCLES"])
+        print(f"| {k[:58]} | {n} | {w / n:.0f} | {4 * life / w:.0f} | {a.get('SQ_WAIT_ANY', 0) / life:.0%} | "
+              f"{a.get('SQ_ACTIVE_INST_ANY', 0) / life:.0%} | {'' if mb is None else f'{mb:.1%}'} |")
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -52,6 +203,9 @@ def parse():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MB",
                     help="instead of the benchmark: 5 plain device copies of MB megabytes (float32), the reference "
                          "for scaling the HBM byte counters of a profiler run")
+    ap.add_argument("--write-traffic", default=None, metavar="DIR",
+                    help="instead of the benchmark (no GPU): turn four counter runs under DIR into the stored "
+                         "HBM-traffic ratio of the dominant kernel and print their table")
     ap.add_argument("--learned-pairs", type=int, default=8,
                     help="held-out pairs registered plain and with the trained warm start (0: skip)")
     return ap.parse_args()
@@ -59,6 +213,9 @@ def parse():
 
 def main():
     args = parse()
+    if args.write_traffic:
+        write_traffic(args.write_traffic)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: --gpus {args.gpus} is not supported (the library runs one "
               f"registration context per GPU; independent registrations would shard one per GPU).", file=sys.stderr)
@@ -135,24 +292,14 @@ def main():
     avg_ms = dom["ms"] / dom["count"]
     bytes_per_launch = dom["bytes"] / dom["count"]
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        # measured HBM bytes of the dominant kernel over its algorithmic bytes (rocprofv3 FETCH_SIZE /
-        # WRITE_SIZE, scaled by a plain copy of known size), applied to this run's launch mix
-        try:
-            tr = json.load(open(TRAFFIC_FILE))
-            ratio = tr.get("kernels", {}).get(dom_name, {}).get("traffic_over_algorithmic")
-            if ratio is not None and tr.get("workload") == list(N) + list(K):
-                traffic = round(ratio * bytes_per_launch)
-        except Exception:
-            traffic = None
+    traffic, traffic_note = stored_traffic(dom_name, N, K, args.variant, bytes_per_launch)
     roofline = {
         "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_source": traffic_note,
         "kernel": dom_name, "launches_per_step": dom["count"] / args.steps,
         "avg_launch_us": round(avg_ms * 1e3, 2), "algorithmic_bytes_per_launch": bytes_per_launch,
     }
-    dft = [s for n, s in stats.items() if n.startswith("dft_")]
+    dft = [s for n, s in stats.items() if n.startswith(DFT_KERNELS)]
     dft_flops = sum(s["flops"] for s in dft)
     dft_ms = sum(s["ms"] for s in dft)
     kernels = {n: {"launches_per_step": s["count"] / args.steps, "ms_per_step": round(s["ms"] / args.steps, 4),
@@ -267,8 +414,19 @@ def learned_leg(npairs):
     return out
 
 
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(variant, N, K, Nt, I0, I1, v, dv):
-    """The FP64 CPU oracle on the host cores: one full Hessian matvec at the same workload."""
+    """The FP64 CPU oracle on the host cores: full Hessian matvecs at the same workload, with torch's default
+    thread count (the reported value) and with one thread, plus one matvec of the other variant."""
     import numpy as np
     import torch
 
@@ -276,17 +434,31 @@ def cpu_baseline(variant, N, K, Nt, I0, I1, v, dv):
     from oracle.variant1 import Variant1
     from oracle.variant3 import Variant3
 
-    model = (Variant1 if variant == 1 else Variant3)(OP(N, K, Nt=Nt), I0.astype(np.float64), I1.astype(np.float64))
-    model.setup(v)
-    model.state()
-    reps = 3
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        model.hess_matvec(dv)
-    dt = (time.perf_counter() - t0) / reps
-    return {"value": round(1.0 / dt, 5), "unit": "matvec/s", "cores": torch.get_num_threads(), "kind": "oracle",
-            "sample": f"{reps} full Hessian matvecs of the same workload in the FP64 oracle (torch CPU), "
-                      f"{dt:.1f} s each; set-up and state solve excluded"}
+    def timed(var, reps):
+        model = (Variant1 if var == 1 else Variant3)(OP(N, K, Nt=Nt), I0.astype(np.float64), I1.astype(np.float64))
+        model.setup(v)
+        model.state()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            model.hess_matvec(dv)
+        return (time.perf_counter() - t0) / reps
+
+    threads = torch.get_num_threads()
+    dt = timed(variant, 2)
+    other = timed(3 if variant == 1 else 1, 1)
+    torch.set_num_threads(1)
+    try:
+        dt1 = timed(variant, 1)
+    finally:
+        torch.set_num_threads(threads)
+    return {"value": round(1.0 / dt, 5), "unit": "matvec/s", "cores": threads, "kind": "oracle",
+            "sample": f"2 full Hessian matvecs of the same workload in the FP64 oracle (torch CPU, {threads} "
+                      f"threads), {dt:.1f} s each; set-up and state solve excluded",
+            "cpu_model": _cpu_model(),
+            "single_thread": {"value": round(1.0 / dt1, 5), "cores": 1, "sample": f"1 matvec, {dt1:.1f} s"},
+            "other_variant": {"variant": 3 if variant == 1 else 1, "value": round(1.0 / other, 5), "cores": threads,
+                              "sample": f"1 matvec of the {'deformation-state' if variant == 1 else 'image-transport'}"
+                                        f" variant at the same sizes, {other:.1f} s"}}
 
 
 if __name__ == "__main__":
