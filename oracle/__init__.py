@@ -22,6 +22,7 @@ Modules
   semilag      characteristics and the Heun (RK2) steps along them
   problem      problem description (grid, band, time steps, alpha, s, sigma^2)
   variant1     original BL PDE-LDDMM (image transport)
+  variant2     BL PDE-LDDMM based on the state equation (maps phi, psi, J)
   variant3     BL PDE-LDDMM based on the deformation state equation
   gauss_newton PCG, Armijo line search, Gauss-Newton driver, metrics, Jacobian
   dto          discretise-then-optimise objective for finite-difference pins
