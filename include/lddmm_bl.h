@@ -7,8 +7,11 @@
  *   - the truncated Fourier maps pi (grid -> band) and iota (band -> grid) of
  *     Section 2.2, done as separable dense contractions on the matrix cores;
  *   - the SL-RK2 solves of Table 1 (Section 3.3) for the state, adjoint,
- *     incremental state and incremental adjoint of two variants:
+ *     incremental state and incremental adjoint of three variants:
  *       LDDMM_BL_IMAGE_TRANSPORT   original BL PDE-LDDMM (Section 2.3.1),
+ *       LDDMM_BL_STATE_EQUATION    BL PDE-LDDMM based on the state equation
+ *                                  (Section 2.3.2): m and lambda from the maps
+ *                                  phi, psi and the Jacobian J of eq. BLDefState,
  *       LDDMM_BL_DEFORMATION_STATE BL PDE-LDDMM based on the deformation state
  *                                  equation (Section 2.3.3);
  *   - the gradient, the Gauss-Newton Hessian-vector product and the
@@ -71,6 +74,13 @@ typedef enum {
 
 typedef enum {
   LDDMM_BL_IMAGE_TRANSPORT = 1,   /* original BL PDE-LDDMM, Section 2.3.1 */
+  LDDMM_BL_STATE_EQUATION = 2,    /* state equation with the maps phi, psi, J (eq. BLDefState), Section 2.3.2.
+                                     Gradient L~v~ + int lambda~ star grad~ m~ with m(t) = I0 o phi(t),
+                                     lambda(t) = J(t) lambda(1) o psi(t); Gauss-Newton Hessian with
+                                     dlambda(t) = J(t) dlambda(1) o psi(t), dlambda(1) = -(2/sigma^2) dm(1),
+                                     dm(1) = -grad P(I0) o phi(1) . iota(du~(1)) (eq. BLIncDefState).  The
+                                     nu~ equation is read with right-hand side -v~.  Holds (Nt+1) x 8 grid
+                                     fields for m, psi, J and lambda at every node. */
   LDDMM_BL_DEFORMATION_STATE = 3  /* deformation state equation, Section 2.3.3 */
 } lddmm_bl_variant;
 
@@ -212,11 +222,18 @@ typedef enum {
   LDDMM_BL_FIELD_DEP_BACKWARD = 1, /* departure displacement X - x for forward-in-time equations, grid units [d][N..] */
   LDDMM_BL_FIELD_DEP_FORWARD = 2,  /* departure displacement for backward-in-time equations [d][N..] */
   LDDMM_BL_FIELD_DIV_V = 3,        /* iota(div~ v~) [N..] */
-  LDDMM_BL_FIELD_STATE = 4,        /* image-transport: m at node index [N..]; deformation-state: u~ at node index [d][K..] */
+  LDDMM_BL_FIELD_STATE = 4,        /* image-transport: m at node index [N..]; state-equation and deformation-state:
+                                      u~ at node index [d][K..] */
   LDDMM_BL_FIELD_M1 = 5,           /* m(1) [N..] */
-  LDDMM_BL_FIELD_ADJOINT0 = 6,     /* image-transport: lambda(0) [N..]; deformation-state: rho~(0) [d][K..] */
+  LDDMM_BL_FIELD_ADJOINT0 = 6,     /* image-transport and state-equation: lambda(0) [N..]; deformation-state:
+                                      rho~(0) [d][K..] */
   LDDMM_BL_FIELD_INC_STATE = 7,    /* dm~ [K..] or du~ [d][K..] at node index, from the last matvec */
-  LDDMM_BL_FIELD_INC_ADJOINT = 8   /* dlambda~ [K..] or drho~ [d][K..] at node index, from the last matvec */
+  LDDMM_BL_FIELD_INC_ADJOINT = 8,  /* dlambda~ [K..] (image-transport; state-equation: pi(dlambda(t_n))) or
+                                      drho~ [d][K..] at node index, from the last matvec */
+  LDDMM_BL_FIELD_INVERSE_STATE = 9,  /* state-equation: nu~ at node index [d][K..] (psi = id - iota(nu~)) */
+  LDDMM_BL_FIELD_JACOBIAN_STATE = 10, /* state-equation: J~ = 1 - U~ at node index [K..] */
+  LDDMM_BL_FIELD_IMAGE = 11,       /* image-transport and state-equation: m(t_n) at node index [N..] */
+  LDDMM_BL_FIELD_ADJOINT_GRID = 12 /* state-equation: lambda(t_n) at node index [N..], from the last adjoint solve */
 } lddmm_bl_field;
 lddmm_bl_status lddmm_bl_get_field(lddmm_bl_ctx* ctx, int32_t which, int32_t index, void* dst, int64_t* count);
 

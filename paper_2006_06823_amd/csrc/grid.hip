@@ -234,6 +234,26 @@ __global__ void k_v3_products(T* __restrict__ out, const T* __restrict__ e, cons
     out[(3 + j) * P + p] = r0 * Du[(0 + j) * P + p] + r1 * Du[(3 + j) * P + p] + r2 * Du[(6 + j) * P + p];
 }
 
+// Transformation of a grid field through per-node maps (state-equation variant, Section 2.3.2):
+// out_n(x) = a w_n(x) P(c)(x - u_n(x)), n = blockIdx.y, with u_n a displacement in unit-torus units
+// ([n][3][P]) and w_n an optional weight field ([n][P]).  One gather of the 64 taps per node: the
+// displacements here are whole deformations, not one step's, so no brick around the node holds them.
+template <typename T>
+__global__ void k_pull_back(T* __restrict__ out, const T* __restrict__ c, const T* __restrict__ u,
+                            const T* __restrict__ w, T a, int n0, int n1, int n2) {
+  const int64_t P = (int64_t)n0 * n1 * n2;
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  const int64_t node = blockIdx.y;
+  const T* un = u + node * 3 * P;
+  const GridIdx g = unflatten(p, n1, n2);
+  Taps<T> t;
+  t.set(g.i0 - un[p] * n0, g.i1 - un[P + p] * n1, g.i2 - un[2 * P + p] * n2, n0, n1, n2);
+  T r = a * t.eval(c, n1, n2);
+  if (w) r *= w[node * P + p];
+  out[node * P + p] = r;
+}
+
 template <typename T>
 __global__ void k_final_warp(T* __restrict__ m1, T* __restrict__ g1, const T* __restrict__ cI0,
                              const T* __restrict__ u, int n0, int n1, int n2) {
@@ -693,6 +713,16 @@ void final_warp(T* m1, T* g1, const T* cI0, const T* u, const Dims& d, hipStream
 }
 
 template <typename T>
+void pull_back(T* out, const T* c, const T* u, const T* w, T a, int nodes, const Dims& d, hipStream_t s) {
+  if (nodes < 1 || nodes > 65535) throw ArgError("pull_back: node count out of range");
+  const dim3 g(static_cast<unsigned>((d.P + kBlock - 1) / kBlock), static_cast<unsigned>(nodes));
+  prof::launch("k_pull_back<" + std::string(prof::tname<T>()) + ">",
+               double(nodes) * (w ? 5.0 : 4.0) * d.P * sizeof(T) + d.P * sizeof(T), 0.0, k_pull_back<T>, g,
+               dim3(kBlock), 0, s, out, c, u, w, a, d.n[0], d.n[1], d.n[2]);
+  LDDMM_LAUNCH_CHECK();
+}
+
+template <typename T>
 void scaled_diff(T* out, T a, const T* x, const T* y, int64_t n, hipStream_t s) {
   prof::launch(std::string("k_scaled_diff<") + prof::tname<T>() + ">", 3.0 * n * sizeof(T), 0.0, k_scaled_diff<T>, grid_for(n), dim3(kBlock), 0, s, out, a, x, y, n);
   LDDMM_LAUNCH_CHECK();
@@ -753,6 +783,7 @@ void zero(T* p, int64_t n, hipStream_t s) {
   template void v1_products<T>(T*, const T*, const T*, const T*, const Dims&, hipStream_t);             \
   template void v3_products<T>(T*, const T*, const T*, const T*, const Dims&, hipStream_t);             \
   template void final_warp<T>(T*, T*, const T*, const T*, const Dims&, hipStream_t);                    \
+  template void pull_back<T>(T*, const T*, const T*, const T*, T, int, const Dims&, hipStream_t);        \
   template void scaled_diff<T>(T*, T, const T*, const T*, int64_t, hipStream_t);                        \
   template void residual_times_grad<T>(T*, T, const T*, const T*, const T*, const Dims&, hipStream_t);  \
   template void coupling_v3<T>(T*, T, const T*, const T*, const Dims&, hipStream_t);                    \

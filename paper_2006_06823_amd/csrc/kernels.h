@@ -176,6 +176,9 @@ void v3_products(T* out, const T* e, const T* divv, const T* Du, const Dims& d, 
 // variant-3 final warp: m1 = P(I0) o (x - u n), g1 = grad P(I0) o (.) in unit-torus units
 template <typename T>
 void final_warp(T* m1, T* g1, const T* cI0, const T* u, const Dims& d, hipStream_t s);
+// out_n = a w_n P(c)(x - u_n) for nodes n < nodes: u [nodes][3][P] (unit-torus units), w [nodes][P] or null
+template <typename T>
+void pull_back(T* out, const T* c, const T* u, const T* w, T a, int nodes, const Dims& d, hipStream_t s);
 // out = a * (x - y)
 template <typename T>
 void scaled_diff(T* out, T a, const T* x, const T* y, int64_t n, hipStream_t s);

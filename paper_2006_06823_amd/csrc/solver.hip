@@ -1,7 +1,8 @@
 // Band-limited PDE-LDDMM with SL-RK2 integration: the sweeps of Table 1 for the
-// image-transport variant (Section 2.3.1) and the deformation-state variant
-// (Section 2.3.3), their gradient and Gauss-Newton Hessian-vector product, and
-// the Gauss-Newton-Krylov driver (Section 2.2, eqs. BLNewton / BLKKT).
+// image-transport variant (Section 2.3.1), the state-equation variant (Section
+// 2.3.2) and the deformation-state variant (Section 2.3.3), their gradient and
+// Gauss-Newton Hessian-vector product, and the Gauss-Newton-Krylov driver
+// (Section 2.2, eqs. BLNewton / BLKKT).
 //
 // Readings of the paper used throughout (it leaves them open):
 //  - unit periodic torus, grid-mean L^2 product, real orthonormal band basis with
@@ -18,7 +19,14 @@
 //    folded into the inclusion matrices;
 //  - time integrals of the gradient and Hessian terms: trapezoid rule;
 //  - deformation-state gradient term (Du)^T rho, Gauss-Newton Hessian term
-//    (Du)^T drho, final conditions with g1 = (grad P(I0)) o phi(1).
+//    (Du)^T drho, final conditions with g1 = (grad P(I0)) o phi(1);
+//  - state-equation variant: the nu~ equation's right-hand side is -v~; the
+//    Jacobian J~ = 1 - U~ is integrated in the equivalent form -D~_t J~ =
+//    J~ star div~ v~ from J~(1) = 1 (the same SL-RK2 arithmetic as the printed U~
+//    equation, since the interpolant of a constant is that constant and
+//    pi(iota(div~ v~)) = div~ v~); the Gauss-Newton incremental adjoint is
+//    dlambda(t) = J(t) dlambda(1) o psi(t), dlambda(1) = -(2/sigma^2) dm(1),
+//    dm(1) = -g1 . iota(du~(1)).
 //
 // Work placement.  Every truncated product of two band-limited fields (the
 // sources f = x * div~ v~, the gradient and Hessian terms x * grad~ m~_n and
@@ -48,7 +56,8 @@ class Solver final : public SolverBase {
     dim_ = p.dim;
     if (dim_ != 2 && dim_ != 3) throw ArgError("dim must be 2 or 3");
     if (p.nt < 1) throw ArgError("nt must be >= 1");
-    if (p.variant != LDDMM_BL_IMAGE_TRANSPORT && p.variant != LDDMM_BL_DEFORMATION_STATE)
+    if (p.variant != LDDMM_BL_IMAGE_TRANSPORT && p.variant != LDDMM_BL_STATE_EQUATION &&
+        p.variant != LDDMM_BL_DEFORMATION_STATE)
       throw ArgError("unknown variant");
     if (!(p.alpha > 0) || p.s < 1 || !(p.sigma2 > 0)) throw ArgError("alpha, s, sigma2 must be positive");
     const int off = 3 - dim_;
@@ -144,7 +153,7 @@ class Solver final : public SolverBase {
   void jacobian_into(double* detmap, double mm[2]) {
     // u~(1): the deformation state (variant 3 holds it; variant 1 integrates it here)
     const T* u1;
-    if (variant_ == LDDMM_BL_DEFORMATION_STATE) {
+    if (variant_ != LDDMM_BL_IMAGE_TRANSPORT) {
       u1 = ubl_.get() + (int64_t)nt_ * 3 * d_.Q;
     } else {
       displacement_only(tmpbl_.get());
@@ -242,17 +251,32 @@ class Solver final : public SolverBase {
     dvs_.alloc(3 * Ps);
     es_.alloc(3 * Ps);
     prods_.alloc(std::max<int64_t>(kMaxFields, 3 * nn) * Ps);
-    if (variant_ == LDDMM_BL_IMAGE_TRANSPORT) {
+    if (variant_ != LDDMM_BL_DEFORMATION_STATE) {
       m_.alloc(nn * P);
       mt_.alloc(nn * Q);
       Gs_.alloc(nn * 3 * Ps);
-      lam0_.alloc(P);
-    } else {
+    }
+    if (variant_ == LDDMM_BL_IMAGE_TRANSPORT) lam0_.alloc(P);
+    if (variant_ != LDDMM_BL_IMAGE_TRANSPORT) {
       ubl_.alloc(nn * 3 * Q);
       Dus_.alloc(nn * 9 * Ps);
       m1_.alloc(P);
       g1_.alloc(3 * P);
-      rho_.alloc(nn * 3 * Q);
+    }
+    if (variant_ == LDDMM_BL_DEFORMATION_STATE) rho_.alloc(nn * 3 * Q);
+    if (variant_ == LDDMM_BL_STATE_EQUATION) {
+      // inverse map, its Jacobian, their grid samples at every node, and the pulled-back adjoint
+      nubl_.alloc(nn * 3 * Q);
+      Jbl_.alloc(nn * Q);
+      psi_.alloc(nn * 3 * P);
+      Jg_.alloc(nn * P);
+      lamg_.alloc(nn * P);
+      lamt_.alloc(nn * Q);
+      // J~(1) = 1: the constant slot of the band
+      std::vector<T> e0(Q, T(0));
+      e0[0] = T(1);
+      one_.alloc(Q);
+      LDDMM_HIP(hipMemcpy(one_.get(), e0.data(), Q * sizeof(T), hipMemcpyHostToDevice));
     }
     work_.alloc(reduce_work_size());
     // the incremental sources of every node are reduced in one launch (no allocation inside a capture)
@@ -315,6 +339,15 @@ class Solver final : public SolverBase {
   const T* m1_ptr() const {
     return variant_ == LDDMM_BL_IMAGE_TRANSPORT ? m_.get() + (int64_t)nt_ * d_.P : m1_.get();
   }
+  // projection / inclusion of any number of stacked fields (kMaxFields per transform)
+  void pi_many(const T* grid, T* bl, int nf) {
+    for (int f0 = 0; f0 < nf; f0 += kMaxFields)
+      full_.pi(grid + (int64_t)f0 * d_.P, bl + (int64_t)f0 * d_.Q, std::min(kMaxFields, nf - f0));
+  }
+  void iota_many(const T* bl, T* grid, int nf) {
+    for (int f0 = 0; f0 < nf; f0 += kMaxFields)
+      full_.iota_kind(bl + (int64_t)f0 * d_.Q, grid + (int64_t)f0 * d_.P, std::min(kMaxFields, nf - f0), kPlain);
+  }
 
   // user [dim][..] <-> internal [3][..] for ncomp-vector arrays of length Q
   void to_internal(T* dst, const T* src, int ncomp) {
@@ -345,10 +378,11 @@ class Solver final : public SolverBase {
   //   image transport (ncomp 1): pi'([e div v, e G_0, e G_1, e G_2]), G = grad~ m~_n
   //   deformation state (ncomp 3): pi'([e_i div v (3), (D~u~_n)^T e (3)])
   // with e = iota'(x), into dst with dst_f = beta_f dst_f + alpha_f (.)
-  void products(const T* x, int n, T* const* dst, const T* al, const T* be) {
+  // (one-component x: the image-transport form, with the state-equation variant's G_n as well)
+  void products(const T* x, int nc, int n, T* const* dst, const T* al, const T* be) {
     if constexpr (std::is_same_v<T, float>) {
       if (sm_.planes()) {
-        const bool v1 = variant_ == LDDMM_BL_IMAGE_TRANSPORT;
+        const bool v1 = nc == 1;
         const int nc = v1 ? 1 : 3, np = v1 ? 4 : 6;
         sm_.iota_kind(x, es_.get(), nc, kPlain);
         sm_.reduce(v1 ? kRedV1Products : kRedV3Products, np, nullptr, es_.get(), divvs_.get(),
@@ -359,7 +393,7 @@ class Solver final : public SolverBase {
         return;
       }
     }
-    if (variant_ == LDDMM_BL_IMAGE_TRANSPORT) {
+    if (nc == 1) {
       sm_.iota_kind(x, es_.get(), 1, kPlain);
       v1_products<T>(Ps(0), es_.get(), divvs_.get(), Gs_.get() + (int64_t)n * 3 * ds_.P, ds_, st_);
       sm_.pi_acc(Ps(0), 4, dst, al, be);
@@ -411,10 +445,7 @@ class Solver final : public SolverBase {
   void run_state(double e[3]) {
     state_valid_ = false;
     setup_velocity();
-    if (variant_ == LDDMM_BL_IMAGE_TRANSPORT)
-      state_v1();
-    else
-      state_v3();
+    state_body();
     finish_objective(e);
     std::memcpy(last_e_, e, sizeof(last_e_));
     state_valid_ = true;
@@ -432,10 +463,7 @@ class Solver final : public SolverBase {
     state_valid_ = false;
     copy(vbl_.get(), v, 3 * d_.Q);
     setup_velocity_body();
-    if (variant_ == LDDMM_BL_IMAGE_TRANSPORT)
-      state_v1();
-    else
-      state_v3();
+    state_body();
     reduce_launch<T>(RedKind::SqDiff, m1_ptr(), I1_.get(), d_.P, work_.get(), 1, st_);
     sym_dot_launch<T>(vbl_.get(), vbl_.get(), Lsym_.get(), 3, d_.Q, work_.get(), 2, st_);
     fetch_async(work_.get(), host_.get(), 3, st_);
@@ -468,6 +496,15 @@ class Solver final : public SolverBase {
     return maxabs<T>(tmp, 3 * d_.Q, work_.get(), host_.get(), st_) == 0.0;
   }
 
+  void state_body() {
+    if (variant_ == LDDMM_BL_IMAGE_TRANSPORT)
+      state_v1();
+    else if (variant_ == LDDMM_BL_STATE_EQUATION)
+      state_v2();
+    else
+      state_v3();
+  }
+
   // ------------------------------------ image transport: state (Table 1 row 1)
   void state_v1() {
     const int64_t P = d_.P, Q = d_.Q;
@@ -496,10 +533,73 @@ class Solver final : public SolverBase {
     full_.iota_kind(ubl_.get() + (int64_t)nt_ * 3 * Q, S(0), 3, kPlain);
     final_warp<T>(m1_.get(), g1_.get(), cI0_.get(), S(0), d_, st_);
   }
-  // one deformation-state step: u_next = pi[P(u + dt/2 v) o X_b] + dt/2 v
-  void u_step(const T* un, T* un1) {
+  // ------------------------------- state-equation variant (Section 2.3.2)
+  // phi(t) = id - iota(u~(t)), psi(t) = id - iota(nu~(t)), J(t) = 1 - iota(U~(t)) = iota(J~(t));
+  // m(t_n) = I0 o phi(t_n); every node's m~_n, G_n (image-transport form), D u_n (incremental sources),
+  // and the grid samples of psi_n and J_n are kept for the adjoint and the matvecs.
+  void state_v2() {
+    const int64_t P = d_.P, Q = d_.Q;
+    const int nn = nt_ + 1;
+    zero(ubl_.get(), 3 * Q, st_);
+    for (int n = 0; n < nt_; ++n) u_step(ubl_.get() + n * 3 * Q, ubl_.get() + (n + 1) * 3 * Q);
+    for (int n = 0; n <= nt_; ++n) sm_.iota_grad(ubl_.get() + n * 3 * Q, Dus_.get() + (int64_t)n * 9 * ds_.P, 3);
+    // m(t_n) at every node (psi_ holds the samples of u~_n until the inverse map replaces them)
+    iota_many(ubl_.get(), psi_.get(), 3 * nn);
+    pull_back<T>(m_.get(), cI0_.get(), psi_.get(), nullptr, T(1), nn, d_, st_);
+    final_warp<T>(m1_.get(), g1_.get(), cI0_.get(), psi_.get() + (int64_t)nt_ * 3 * P, d_, st_);
+    pi_many(m_.get(), mt_.get(), nn);
+    for (int n = 0; n <= nt_; n += 4)
+      sm_.iota_grad(mt_.get() + n * Q, Gs_.get() + (int64_t)n * 3 * ds_.P, std::min(4, nt_ + 1 - n));
+    // -D~_t nu~ = -v~ from nu~(1) = 0, and -D~_t J~ = J~ star div~ v~ from J~(1) = 1 (the image-transport
+    // products the band-limited sweep also forms land in scratch)
+    zero(nubl_.get() + (int64_t)nt_ * 3 * Q, 3 * Q, st_);
+    for (int n = nt_ - 1; n >= 0; --n) map_step(nubl_.get() + (n + 1) * 3 * Q, nubl_.get() + n * 3 * Q, Xf_.get(), -1);
+    copy(Jbl_.get() + (int64_t)nt_ * Q, one_.get(), Q);
+    bl_backward(Jbl_.get(), 1, tmpbl_.get());
+    iota_many(nubl_.get(), psi_.get(), 3 * nn);
+    iota_many(Jbl_.get(), Jg_.get(), nn);
+  }
+
+  // acc = sum_n w_n pi(iota(f~_n) G_n) with f_n = a J_n P(c) o psi_n (c: prefiltered grid samples at
+  // t = 1) and f~_n = pi(f_n) written to bl [nt+1][Q]: the gradient term (c from lambda(1)) or the
+  // Hessian term (c from dlambda(1)) of the state-equation variant
+  void pull_back_terms(const T* c, T a, T* bl, T* acc) {
+    const int nn = nt_ + 1;
     const int64_t Q = d_.Q;
-    const T hdt = T(0.5) * dt_;
+    pull_back<T>(lamg_.get(), c, psi_.get(), Jg_.get(), a, nn, d_, st_);
+    pi_many(lamg_.get(), bl, nn);
+    zero(acc, 3 * Q, st_);
+    for (int n = 0; n <= nt_; ++n) {
+      const T w = trap_w(n);
+      T* dst[4] = {blA_.get(), acc, acc + Q, acc + 2 * Q};
+      const T al[4] = {T(1), w, w, w}, be[4] = {T(0), T(1), T(1), T(1)};
+      products(bl + n * Q, 1, n, dst, al, be);
+    }
+  }
+
+  // lambda(1) = -(2/sigma^2)(m(1) - I1)
+  void adjoint_v2() {
+    scaled_diff<T>(S(0), T(-2.0 / sigma2_), m1_.get(), I1_.get(), d_.P, st_);
+    prefilter(S(0), 1, d_, st_);
+    pull_back_terms(S(0), T(1), lamt_.get(), acc_.get());
+  }
+
+  // Gauss-Newton incremental adjoint: dlambda(1) = -(2/sigma^2) dm(1), dm(1) = -g1 . iota(du~(1))
+  void matvec_tail_v2(const T* du1) {
+    full_.iota_kind(du1, S(0), 3, kPlain);
+    v1_source<T>(S(3), g1_.get(), S(0), d_, st_);
+    prefilter(S(3), 1, d_, st_);
+    pull_back_terms(S(3), T(-2.0 / sigma2_), incadj_.get(), acc_.get());
+  }
+
+  // one deformation-state step: u_next = pi[P(u + dt/2 v) o X_b] + dt/2 v
+  void u_step(const T* un, T* un1) { map_step(un, un1, Xb_.get(), 1); }
+  // one step of a displacement map along the departure displacements X:
+  // next = pi[P(u + sgn dt/2 v) o X] + sgn dt/2 v (sgn = +1: u~ forward along X_b; sgn = -1: the inverse
+  // map nu~ of the state-equation variant, backward along X_f)
+  void map_step(const T* un, T* un1, const T* X, int sgn) {
+    const int64_t Q = d_.Q;
+    const T hdt = T(0.5) * dt_ * T(sgn), sdt = dt_ * T(sgn);
     const T* xs[3] = {un, un + Q, un + 2 * Q};
     const T* ys[3] = {vbl_.get(), vbl_.get() + Q, vbl_.get() + 2 * Q};
     const T al[3] = {hdt, hdt, hdt};
@@ -510,15 +610,15 @@ class Solver final : public SolverBase {
         // pi iota(c) = c, so u_next = u + dt v + pi[P(c) o X_b - P(c)]; the projection then carries one
         // step's change instead of the whole displacement (an FP32 rounding error that does not grow
         // with the displacement already accumulated)
-        brick_interp_diff(S(3), S(0), 3, Xb_.get(), d_, st_);
-        axpby(un1, T(1), un, dt_, vbl_.get(), 3 * Q);
+        brick_interp_diff(S(3), S(0), 3, X, d_, st_);
+        axpby(un1, T(1), un, sdt, vbl_.get(), 3 * Q);
         T* dst[3] = {un1, un1 + Q, un1 + 2 * Q};
         const T one[3] = {T(1), T(1), T(1)};
         full_.pi_acc(S(3), 3, dst, one, one);
         return;
       }
     }
-    interp<T>(S(3), S(0), 3, Xb_.get(), d_, st_);
+    interp<T>(S(3), S(0), 3, X, d_, st_);
     copy(un1, vbl_.get(), 3 * Q);
     T* dst[3] = {un1, un1 + Q, un1 + 2 * Q};
     const T one[3] = {T(1), T(1), T(1)}, hd[3] = {hdt, hdt, hdt};
@@ -541,6 +641,8 @@ class Solver final : public SolverBase {
   void run_adjoint(T* g) {
     if (variant_ == LDDMM_BL_IMAGE_TRANSPORT) {
       adjoint_v1();
+    } else if (variant_ == LDDMM_BL_STATE_EQUATION) {
+      adjoint_v2();
     } else {
       if constexpr (std::is_same_v<T, float>) {
         if (full_.planes() && sm_.planes()) {
@@ -568,7 +670,7 @@ class Solver final : public SolverBase {
         const T w = trap_w(n);
         T* dst[4] = {blA_.get(), acc_.get(), acc_.get() + Q, acc_.get() + 2 * Q};
         const T al[4] = {T(1), w, w, w}, be[4] = {T(0), T(1), T(1), T(1)};
-        products(tmpbl_.get(), n, dst, al, be);
+        products(tmpbl_.get(), 1, n, dst, al, be);
       }
       if (n == 0) break;
       copy(S(5), lam, P);
@@ -593,16 +695,16 @@ class Solver final : public SolverBase {
     for (int n = nt_; n >= 0; --n) {
       T* xn = traj + n * stride;
       const T w = trap_w(n);
-      if (variant_ == LDDMM_BL_IMAGE_TRANSPORT) {
+      if (ncomp == 1) {
         // [fl, e G0, e G1, e G2]: fl to blA, the Hessian / gradient terms accumulated into acc
         T* dst[4] = {blA_.get(), acc, acc + Q, acc + 2 * Q};
         const T al[4] = {T(1), w, w, w}, be[4] = {T(0), T(1), T(1), T(1)};
-        products(xn, n, dst, al, be);
+        products(xn, 1, n, dst, al, be);
       } else {
         // [fl (3), (Du)^T e (3)]
         T* dst[6] = {blA_.get(), blA_.get() + Q, blA_.get() + 2 * Q, acc, acc + Q, acc + 2 * Q};
         const T al[6] = {T(1), T(1), T(1), -w, -w, -w}, be[6] = {T(0), T(0), T(0), T(1), T(1), T(1)};
-        products(xn, n, dst, al, be);
+        products(xn, 3, n, dst, al, be);
         axpby(acc, T(1), acc, w, xn, 3 * Q);
       }
       if (n == 0) break;
@@ -678,6 +780,8 @@ class Solver final : public SolverBase {
       T* dl = incadj_.get();
       axpby(dl + (int64_t)nt_ * Q, T(-2.0 / sigma2_), dm + (int64_t)nt_ * Q, T(0), nullptr, Q);
       bl_backward(dl, 1, acc_.get());
+    } else if (variant_ == LDDMM_BL_STATE_EQUATION) {
+      matvec_tail_v2(dm + (int64_t)nt_ * 3 * Q);
     } else {
       // t = 1 coupling: drho~(1) = pi((2/sigma^2) (g1 . iota(du~(1))) g1)
       full_.iota_kind(dm + (int64_t)nt_ * 3 * Q, S(0), 3, kPlain);
@@ -750,6 +854,9 @@ class Solver final : public SolverBase {
     }
     if (nc == 1) {
       bl_backward_planes(dl, 1, acc_.get(), true, h, dv);
+    } else if (variant_ == LDDMM_BL_STATE_EQUATION) {
+      matvec_tail_v2(dm + (int64_t)nt_ * 3 * Q);
+      bl_scale_sym<float>(h, dv, Lsym_.get(), 3, Q, acc_.get(), st_);
     } else {
       // t = 1 coupling: drho~(1) = pi((2/sigma^2) (g1 . iota(du~(1))) g1)
       full_.iota_kind(dm + (int64_t)nt_ * 3 * Q, S(0), 3, kPlain);
@@ -767,7 +874,7 @@ class Solver final : public SolverBase {
     const int64_t Q = d_.Q;
     const int64_t stride = (int64_t)nc * Q;
     const float hdt = 0.5f * dt_;
-    const bool v1 = variant_ == LDDMM_BL_IMAGE_TRANSPORT;
+    const bool v1 = nc == 1;  // image-transport form (also the state-equation variant's J~ sweep)
     const int np = v1 ? 4 : 6;
     int kpref[kMaxFields][3];
     for (int f = 0; f < kMaxFields; ++f) kpref[f][0] = kpref[f][1] = kpref[f][2] = kPref;
@@ -847,7 +954,8 @@ class Solver final : public SolverBase {
   DevBuf<T> inc_, incadj_, fsrc_;
   DevBuf<T> divvs_, dvs_, es_, prods_;          // product grid
   DevBuf<T> m_, mt_, Gs_, lam0_;                // image transport
-  DevBuf<T> ubl_, Dus_, m1_, g1_, rho_;         // deformation state
+  DevBuf<T> ubl_, Dus_, m1_, g1_, rho_;         // deformation state (and the state-equation variant)
+  DevBuf<T> nubl_, Jbl_, psi_, Jg_, lamg_, lamt_, one_;  // state-equation variant
   DevBuf<double> det_;  // Jacobian map when the caller keeps none
 
  public:
@@ -899,7 +1007,13 @@ int64_t Solver<T>::get_field(int which, int index, void* dst_v) {
   };
   int64_t count = 0;
   const bool v1 = variant_ == LDDMM_BL_IMAGE_TRANSPORT;
+  const bool v2 = variant_ == LDDMM_BL_STATE_EQUATION;
   if (which != LDDMM_BL_FIELD_INC_STATE && which != LDDMM_BL_FIELD_INC_ADJOINT) require_state();
+  auto grid_node = [&](const T* base) -> int64_t {
+    check_index();
+    if (dst) copy(dst, base + index * P, P);
+    return P;
+  };
   switch (which) {
     case LDDMM_BL_FIELD_VELOCITY:
       count = grid_vec(vg_.get());
@@ -931,6 +1045,9 @@ int64_t Solver<T>::get_field(int which, int index, void* dst_v) {
       if (v1) {
         if (dst) copy(dst, lam0_.get(), P);
         count = P;
+      } else if (v2) {
+        if (dst) copy(dst, lamg_.get(), P);
+        count = P;
       } else {
         count = bl_vec(rho_.get());
       }
@@ -939,7 +1056,7 @@ int64_t Solver<T>::get_field(int which, int index, void* dst_v) {
     case LDDMM_BL_FIELD_INC_ADJOINT: {
       check_index();
       const T* base = which == LDDMM_BL_FIELD_INC_STATE ? inc_.get() : incadj_.get();
-      if (v1) {
+      if (v1 || (v2 && which == LDDMM_BL_FIELD_INC_ADJOINT)) {
         if (dst) copy(dst, base + index * Q, Q);
         count = Q;
       } else {
@@ -947,6 +1064,25 @@ int64_t Solver<T>::get_field(int which, int index, void* dst_v) {
       }
       break;
     }
+    case LDDMM_BL_FIELD_IMAGE:
+      if (!v1 && !v2) throw ArgError("the deformation-state variant keeps m(1) only");
+      count = grid_node(m_.get());
+      break;
+    case LDDMM_BL_FIELD_ADJOINT_GRID:
+      if (!v2) throw ArgError("grid adjoint at every node: state-equation variant only");
+      count = grid_node(lamg_.get());
+      break;
+    case LDDMM_BL_FIELD_INVERSE_STATE:
+      if (!v2) throw ArgError("inverse map: state-equation variant only");
+      check_index();
+      count = bl_vec(nubl_.get() + index * 3 * Q);
+      break;
+    case LDDMM_BL_FIELD_JACOBIAN_STATE:
+      if (!v2) throw ArgError("Jacobian state: state-equation variant only");
+      check_index();
+      if (dst) copy(dst, Jbl_.get() + index * Q, Q);
+      count = Q;
+      break;
     default:
       throw ArgError("unknown field");
   }

@@ -19,11 +19,13 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblddmm_bl.so")
 
 IMAGE_TRANSPORT = 1
+STATE_EQUATION = 2
 DEFORMATION_STATE = 3
 FP64, FP32, BF16_DFT = 0, 1, 2
 
 FIELD_VELOCITY, FIELD_DEP_BACKWARD, FIELD_DEP_FORWARD, FIELD_DIV_V = 0, 1, 2, 3
 FIELD_STATE, FIELD_M1, FIELD_ADJOINT0, FIELD_INC_STATE, FIELD_INC_ADJOINT = 4, 5, 6, 7, 8
+FIELD_INVERSE_STATE, FIELD_JACOBIAN_STATE, FIELD_IMAGE, FIELD_ADJOINT_GRID = 9, 10, 11, 12
 
 STATUS = {
     0: "OK", -1: "E_ARG", -2: "E_OOM", -3: "E_HIP", -4: "E_NONFINITE", -5: "E_STATE",

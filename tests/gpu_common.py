@@ -5,6 +5,7 @@ import torch
 from oracle import spectral as sp
 from oracle.problem import Problem as OProblem
 from oracle.variant1 import Variant1
+from oracle.variant2 import Variant2
 from oracle.variant3 import Variant3
 from paper_2006_06823_amd import synthetic as syn
 
@@ -65,4 +66,4 @@ def velocity(N, K, Nt, seed, cfl_vox=0.8):
 
 def oracle_model(variant, N, K, Nt, I0, I1):
     prob = OProblem(tuple(N), tuple(K), Nt=Nt)
-    return (Variant1 if variant == 1 else Variant3)(prob, I0, I1)
+    return {1: Variant1, 2: Variant2, 3: Variant3}[variant](prob, I0, I1)

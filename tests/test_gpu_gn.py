@@ -1,5 +1,5 @@
 """Gauss-Newton-Krylov on the GPU against the oracle's driver: the 2D configuration (64^2, band 16^2,
-Nt = 10, FP64, 10 GN x 5 PCG with fixed iteration counts), both variants.
+Nt = 10, FP64, 10 GN x 5 PCG with fixed iteration counts), all three variants.
 
 Both drivers log their discrete decisions per GN iteration (PCG iterations, truncation on non-positive
 curvature, Armijo backtracks; Section 2.2 eqs. BLNewton / BLKKT with the Armijo reading).  Near
@@ -41,7 +41,7 @@ def _first_difference(a, b):
     return None if len(a) == len(b) else min(len(a), len(b))
 
 
-@pytest.mark.parametrize("variant", [1, 3])
+@pytest.mark.parametrize("variant", [1, 2, 3])
 def test_gn_2d_fp64_decision_sequences(variant):
     ctx, v, rep, vo, ro = _run_2d(variant, 10)
     gpu, ora = rep["decisions"], ro.decisions
@@ -88,7 +88,7 @@ def test_gn_3d_fp32_small_matches_oracle():
     assert close(v, vo) <= 1e-3
 
 
-@pytest.mark.parametrize("variant", [1, 3])
+@pytest.mark.parametrize("variant", [1, 2, 3])
 def test_gn_reuses_a_held_state_at_the_same_velocity(variant):
     """A state solve at the starting velocity just before gn_solve is reused by it (the solve skips its
     own first state solve); the result is bitwise the one of a fresh context.  A state held at another
@@ -116,7 +116,7 @@ def test_gn_reuses_a_held_state_at_the_same_velocity(variant):
         assert rep["E0"] == ref["E0"] and rep["E"] == ref["E"] and rep["gn_iters"] == ref["gn_iters"]
 
 
-@pytest.mark.parametrize("variant,twolevel", [(1, False), (3, False), (3, True)])
+@pytest.mark.parametrize("variant,twolevel", [(1, False), (2, False), (3, False), (3, True)])
 def test_gn_graph_replay_equals_eager_launches(variant, twolevel, monkeypatch):
     """gn_solve runs its Hessian matvecs as replays of one captured HIP graph and keeps the PCG step
     lengths on the device (one host round trip per PCG iteration); with LDDMM_BL_NO_GRAPH set the same
