@@ -34,6 +34,8 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_matvec_kernels_128.json")
 WEIGHTS_FILE = os.path.join(ROOT, "paper_2006_06823_amd", "weights", "warmstart_v1_128.npz")
 
 
+VARIANT_NAMES = {1: "image-transport", 2: "state-equation", 3: "deformation-state"}
+
 # library profile names of the DFT-stage kernels (MFMA figures in "extra")
 DFT_KERNELS = ("k_expand", "k_reduce", "k_axis0", "dft_", "k_iota", "k_pi")
 
@@ -190,7 +192,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--variant", type=int, default=1, choices=(1, 3))
+    ap.add_argument("--variant", type=int, default=1, choices=(1, 2, 3),
+                    help="1 image transport (default), 2 state equation, 3 deformation state")
     ap.add_argument("--size", type=int, nargs=3, default=(128, 128, 128))
     ap.add_argument("--band", type=int, nargs=3, default=(32, 32, 32))
     ap.add_argument("--nt", type=int, default=10)
@@ -242,7 +245,7 @@ def main():
         return
 
     N, K, Nt = tuple(args.size), tuple(args.band), args.nt
-    variant = L.IMAGE_TRANSPORT if args.variant == 1 else L.DEFORMATION_STATE
+    variant = {1: L.IMAGE_TRANSPORT, 2: L.STATE_EQUATION, 3: L.DEFORMATION_STATE}[args.variant]
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
 
@@ -327,7 +330,7 @@ def main():
         "value": round(value, 2), "unit": "matvec/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"{'image-transport' if args.variant == 1 else 'deformation-state'} BL PDE-LDDMM "
+        "config": {"workload": f"{VARIANT_NAMES[args.variant]} BL PDE-LDDMM "
                                f"Gauss-Newton Hessian matvec, grid {N[0]}x{N[1]}x{N[2]}, band {K[0]}x{K[1]}x{K[2]}x3, "
                                f"Nt={Nt}, SL-RK2, FP32 with FP64 reductions",
                    "grid": list(N), "band": list(K), "nt": Nt, "variant": args.variant,
@@ -432,10 +435,12 @@ def cpu_baseline(variant, N, K, Nt, I0, I1, v, dv):
 
     from oracle.problem import Problem as OP
     from oracle.variant1 import Variant1
+    from oracle.variant2 import Variant2
     from oracle.variant3 import Variant3
 
     def timed(var, reps):
-        model = (Variant1 if var == 1 else Variant3)(OP(N, K, Nt=Nt), I0.astype(np.float64), I1.astype(np.float64))
+        model = {1: Variant1, 2: Variant2, 3: Variant3}[var](OP(N, K, Nt=Nt), I0.astype(np.float64),
+                                                          I1.astype(np.float64))
         model.setup(v)
         model.state()
         t0 = time.perf_counter()
@@ -457,7 +462,7 @@ def cpu_baseline(variant, N, K, Nt, I0, I1, v, dv):
             "cpu_model": _cpu_model(),
             "single_thread": {"value": round(1.0 / dt1, 5), "cores": 1, "sample": f"1 matvec, {dt1:.1f} s"},
             "other_variant": {"variant": 3 if variant == 1 else 1, "value": round(1.0 / other, 5), "cores": threads,
-                              "sample": f"1 matvec of the {'deformation-state' if variant == 1 else 'image-transport'}"
+                              "sample": f"1 matvec of the {VARIANT_NAMES[3 if variant == 1 else 1]}"
                                         f" variant at the same sizes, {other:.1f} s"}}
 
 

@@ -14,6 +14,7 @@
 // SL-RK2 step update of each equation into the same pass.
 #include "kernels.h"
 
+#include <climits>
 #include <type_traits>
 #include "prof.h"
 #include "tune.h"
@@ -469,9 +470,170 @@ __global__ void k_tune_disp(float* disp, int n0, int n1, int n2) {
   for (int c = 0; c < 3; ++c) disp[c * P + p] = 0.8f * sinf(ph + 1.7f * c);
 }
 
+// ---- transformation through whole-deformation maps ------------------------------------
+
+// 64-tap evaluation from a staged box with runtime strides (rows of e2 floats, planes of e1 rows)
+__device__ __forceinline__ float eval_box(const float* __restrict__ br, int s0, int s1, int s2, int e1, int e2,
+                                          const float w0[4], const float w1[4], const float w2[4]) {
+  float acc = 0.f;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    float sa = 0.f;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const float* row = br + ((s0 + a) * e1 + (s1 + b)) * e2 + s2;
+      sa += w1[b] * (w2[0] * row[0] + w2[1] * row[1] + w2[2] * row[2] + w2[3] * row[3]);
+    }
+    acc += w0[a] * sa;
+  }
+  return acc;
+}
+
+// out_n(x) = a w_n(x) P(c)(x - u_n(x)) for node n = blockIdx.y (u_n [3][P] in unit-torus units, w_n
+// optional).  The departure points lie up to a whole deformation away from their nodes, beyond any
+// fixed halo, but they move smoothly: the workgroup takes the bounding box of its tile's 4 x 4 x 4
+// stencils (a min / max over the workgroup), stages the box into LDS when it holds at most CAP floats
+// and evaluates every node from there; a larger box falls back to gathers from global memory.
+template <int TX0, int TX1, int TX2, int NTHR, int CAP>
+__global__ __launch_bounds__(NTHR) void k_pull_back_box(float* __restrict__ out, const float* __restrict__ c,
+                                                        const float* __restrict__ u, const float* __restrict__ w,
+                                                        float a, Grid3 g) {
+  constexpr int PPT = TX0 * TX1 * TX2 / NTHR, NW = NTHR / 64;
+  __shared__ float br[CAP];
+  __shared__ int bmin[3], bmax[3];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int T2 = (g.n2 + TX2 - 1) / TX2, T1 = (g.n1 + TX1 - 1) / TX1;
+  // consecutive tiles of one node on one XCD (its L2 then holds the boxes' overlap)
+  const int nb = gridDim.x;
+  int bid = blockIdx.x;
+  if ((nb & 7) == 0) bid = (bid & 7) * (nb >> 3) + (bid >> 3);
+  const int bx = bid % T2, rest = bid / T2, by = rest % T1, bz = rest / T1;
+  const int64_t P = g.P, node = blockIdx.y;
+  const float* __restrict__ un = u + node * 3 * P;
+  if (tid < 3) bmin[tid] = INT_MAX, bmax[tid] = INT_MIN;
+  float x[PPT][3];
+  int pidx[PPT];
+  bool live[PPT];
+  int lmin[3] = {INT_MAX, INT_MAX, INT_MAX}, lmax[3] = {INT_MIN, INT_MIN, INT_MIN};
+#pragma unroll
+  for (int j = 0; j < PPT; ++j) {
+    const int q = tid + NTHR * j;
+    const int l2 = q % TX2, l1 = (q / TX2) % TX1, l0 = q / (TX1 * TX2);
+    const int i0 = bz * TX0 + l0, i1 = by * TX1 + l1, i2 = bx * TX2 + l2;
+    live[j] = i0 < g.n0 && i1 < g.n1 && i2 < g.n2;
+    pidx[j] = (i0 * g.n1 + i1) * g.n2 + i2;
+    x[j][0] = x[j][1] = x[j][2] = 0.f;
+    if (live[j]) {
+      const int p = pidx[j];
+      x[j][0] = i0 - un[p] * g.n0;
+      x[j][1] = i1 - un[P + p] * g.n1;
+      x[j][2] = i2 - un[2 * P + p] * g.n2;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const int f = static_cast<int>(floorf(x[j][k]));
+        lmin[k] = min(lmin[k], f - 1);
+        lmax[k] = max(lmax[k], f + 2);
+      }
+    }
+  }
+  __syncthreads();  // bounds initialised
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    if (lmin[k] != INT_MAX) {
+      atomicMin(&bmin[k], lmin[k]);
+      atomicMax(&bmax[k], lmax[k]);
+    }
+  }
+  __syncthreads();
+  const int lo0 = bmin[0], lo1 = bmin[1], lo2 = bmin[2];
+  // every tile holds a live node (the grid is ceil-divided), so bmin <= bmax on every axis
+  const int64_t w0b = (int64_t)bmax[0] - lo0 + 1, w1b = (int64_t)bmax[1] - lo1 + 1, w2b = (int64_t)bmax[2] - lo2 + 1;
+  const bool staged = w0b > 0 && w1b > 0 && w2b > 0 && w0b <= g.n0 && w1b <= g.n1 && w2b <= g.n2 && w2b <= 128 &&
+                      w0b * w1b * w2b <= CAP;
+  const int e0 = staged ? (int)w0b : 0, e1 = staged ? (int)w1b : 0, e2 = staged ? (int)w2b : 0;
+  if (staged) {
+    const int m0 = ((lo0 % g.n0) + g.n0) % g.n0, m1 = ((lo1 % g.n1) + g.n1) % g.n1, m2 = ((lo2 % g.n2) + g.n2) % g.n2;
+    // a wave stages rows of e2 columns, two rows per 64 lanes when they are at most 32 columns wide,
+    // RB (pairs of) rows at a time with all their loads requested before its LDS stores
+    constexpr int RB = 4;
+    const int rows = e0 * e1;
+    const bool half = e2 <= 32;
+    const int lrow = half ? (lane >> 5) : 0, lcol = half ? (lane & 31) : lane, rstep = half ? 2 : 1;
+    for (int row0 = wave * RB * rstep; row0 < rows; row0 += NW * RB * rstep) {
+      float vals[RB][2];
+#pragma unroll
+      for (int k = 0; k < RB; ++k) {
+        const int row = row0 + k * rstep + lrow;
+        vals[k][0] = vals[k][1] = 0.f;
+        if (row < rows) {
+          const int b0 = row / e1, b1 = row - b0 * e1;
+          int r0 = m0 + b0, r1 = m1 + b1;
+          if (r0 >= g.n0) r0 -= g.n0;
+          if (r1 >= g.n1) r1 -= g.n1;
+          const float* __restrict__ src = c + ((int64_t)r0 * g.n1 + r1) * g.n2;
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int cc = lcol + 64 * h;
+            if (cc < e2) {
+              int c2 = m2 + cc;
+              if (c2 >= g.n2) c2 -= g.n2;
+              vals[k][h] = src[c2];
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < RB; ++k) {
+        const int row = row0 + k * rstep + lrow;
+        if (row < rows) {
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int cc = lcol + 64 * h;
+            if (cc < e2) br[row * e2 + cc] = vals[k][h];
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 0; j < PPT; ++j) {
+    if (!live[j]) continue;
+    float val;
+    if (staged) {
+      const float f0 = floorf(x[j][0]), f1 = floorf(x[j][1]), f2 = floorf(x[j][2]);
+      float w0[4], w1[4], w2[4];
+      bspline_weights(x[j][0] - f0, w0);
+      bspline_weights(x[j][1] - f1, w1);
+      bspline_weights(x[j][2] - f2, w2);
+      val = eval_box(br, static_cast<int>(f0) - 1 - lo0, static_cast<int>(f1) - 1 - lo1,
+                     static_cast<int>(f2) - 1 - lo2, e1, e2, w0, w1, w2);
+    } else {
+      val = eval_global(c, x[j][0], x[j][1], x[j][2], g.n0, g.n1, g.n2);
+    }
+    const int64_t o = node * P + pidx[j];
+    out[o] = a * (w ? w[o] * val : val);
+  }
+}
+
 }  // namespace
 
 bool brick_ok(const Dims& d) { return d.n[0] > 1; }
+
+void brick_pull_back(float* out, const float* c, const float* u, const float* w, float a, int nodes, const Dims& d,
+                     hipStream_t s) {
+  // 8 x 8 x 16 nodes per workgroup: the boxes of an 8-voxel deformation of 128^3 hold 5 staged values per
+  // node on average and all fit in 8192 floats (32 KB, five workgroups per CU)
+  constexpr int TX0 = 8, TX1 = 8, TX2 = 16, NTHR = 256, CAP = 8192;
+  if (nodes < 1 || nodes > 65535) throw ArgError("brick_pull_back: node count out of range");
+  const Grid3 g{d.n[0], d.n[1], d.n[2], d.P};
+  const int64_t tiles = (int64_t)ceil_div(d.n[0], TX0) * ceil_div(d.n[1], TX1) * ceil_div(d.n[2], TX2);
+  if (tiles > INT_MAX) throw ArgError("brick_pull_back: grid too large");
+  prof::launch("k_pull_back_box", double(nodes) * (w ? 5.0 : 4.0) * d.P * 4 + d.P * 4.0, 0.0,
+               k_pull_back_box<TX0, TX1, TX2, NTHR, CAP>, dim3(static_cast<unsigned>(tiles), nodes), dim3(NTHR), 0,
+               s, out, c, u, w, a, g);
+  LDDMM_LAUNCH_CHECK();
+}
 
 int brick_tile_count() { return kTiles; }
 

@@ -254,6 +254,25 @@ __global__ void k_pull_back(T* __restrict__ out, const T* __restrict__ c, const 
   out[node * P + p] = r;
 }
 
+// out_j = sum_n e_n G_n,j (e [ns][P], G [ns][3][P]): the time integral of the state-equation variant's
+// gradient and Hessian terms on the product grid, its weights folded into e_n
+template <typename T>
+__global__ void k_node_sum(T* __restrict__ out, const T* __restrict__ e, const T* __restrict__ G, int ns, int64_t P) {
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  T a0 = 0, a1 = 0, a2 = 0;
+  for (int n = 0; n < ns; ++n) {
+    const T x = e[n * P + p];
+    const T* g = G + 3 * n * P;
+    a0 += x * g[p];
+    a1 += x * g[P + p];
+    a2 += x * g[2 * P + p];
+  }
+  out[p] = a0;
+  out[P + p] = a1;
+  out[2 * P + p] = a2;
+}
+
 template <typename T>
 __global__ void k_final_warp(T* __restrict__ m1, T* __restrict__ g1, const T* __restrict__ cI0,
                              const T* __restrict__ u, int n0, int n1, int n2) {
@@ -723,6 +742,13 @@ void pull_back(T* out, const T* c, const T* u, const T* w, T a, int nodes, const
 }
 
 template <typename T>
+void node_sum(T* out, const T* e, const T* G, int ns, int64_t P, hipStream_t s) {
+  prof::launch("k_node_sum<" + std::string(prof::tname<T>()) + ">", (4.0 * ns + 3.0) * P * sizeof(T), 0.0,
+               k_node_sum<T>, grid_for(P), dim3(kBlock), 0, s, out, e, G, ns, P);
+  LDDMM_LAUNCH_CHECK();
+}
+
+template <typename T>
 void scaled_diff(T* out, T a, const T* x, const T* y, int64_t n, hipStream_t s) {
   prof::launch(std::string("k_scaled_diff<") + prof::tname<T>() + ">", 3.0 * n * sizeof(T), 0.0, k_scaled_diff<T>, grid_for(n), dim3(kBlock), 0, s, out, a, x, y, n);
   LDDMM_LAUNCH_CHECK();
@@ -784,6 +810,7 @@ void zero(T* p, int64_t n, hipStream_t s) {
   template void v3_products<T>(T*, const T*, const T*, const T*, const Dims&, hipStream_t);             \
   template void final_warp<T>(T*, T*, const T*, const T*, const Dims&, hipStream_t);                    \
   template void pull_back<T>(T*, const T*, const T*, const T*, T, int, const Dims&, hipStream_t);        \
+  template void node_sum<T>(T*, const T*, const T*, int, int64_t, hipStream_t);                          \
   template void scaled_diff<T>(T*, T, const T*, const T*, int64_t, hipStream_t);                        \
   template void residual_times_grad<T>(T*, T, const T*, const T*, const T*, const Dims&, hipStream_t);  \
   template void coupling_v3<T>(T*, T, const T*, const T*, const Dims&, hipStream_t);                    \

@@ -179,6 +179,9 @@ void final_warp(T* m1, T* g1, const T* cI0, const T* u, const Dims& d, hipStream
 // out_n = a w_n P(c)(x - u_n) for nodes n < nodes: u [nodes][3][P] (unit-torus units), w [nodes][P] or null
 template <typename T>
 void pull_back(T* out, const T* c, const T* u, const T* w, T a, int nodes, const Dims& d, hipStream_t s);
+// out [3][P] = sum_n e_n G_n (e [ns][P], G [ns][3][P])
+template <typename T>
+void node_sum(T* out, const T* e, const T* G, int ns, int64_t P, hipStream_t s);
 // out = a * (x - y)
 template <typename T>
 void scaled_diff(T* out, T a, const T* x, const T* y, int64_t n, hipStream_t s);
@@ -209,6 +212,9 @@ void brick_autotune(float* out, const float* coef, float* disp, const Dims& d, h
 void brick_interp(float* out, const float* coef, int nf, const float* disp, const Dims& d, hipStream_t s);
 // out_f = P(c_f) o X - P(c_f) at the nodes (nf 1 or 3)
 void brick_interp_diff(float* out, const float* coef, int nf, const float* disp, const Dims& d, hipStream_t s);
+// pull_back through LDS-staged bounding boxes of each tile's stencils (float, 3D grids)
+void brick_pull_back(float* out, const float* c, const float* u, const float* w, float a, int nodes, const Dims& d,
+                     hipStream_t s);
 void brick_bl_adjoint_step(float* out, const float* cAB, int nc, const float* disp, const float* divv,
                            const Dims& d, float dt, hipStream_t s);
 void brick_adjoint_grid_step(float* out, const float* c12, const float* disp, const float* divv, const Dims& d,

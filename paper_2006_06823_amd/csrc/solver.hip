@@ -249,7 +249,7 @@ class Solver final : public SolverBase {
     // product grid: div v, the state's gradient fields, the expanded operand and the products
     divvs_.alloc(Ps);
     dvs_.alloc(3 * Ps);
-    es_.alloc(3 * Ps);
+    es_.alloc(std::max<int64_t>(3, variant_ == LDDMM_BL_STATE_EQUATION ? std::min(nn, (int64_t)kMaxFields) : 3) * Ps);
     prods_.alloc(std::max<int64_t>(kMaxFields, 3 * nn) * Ps);
     if (variant_ != LDDMM_BL_DEFORMATION_STATE) {
       m_.alloc(nn * P);
@@ -545,7 +545,7 @@ class Solver final : public SolverBase {
     for (int n = 0; n <= nt_; ++n) sm_.iota_grad(ubl_.get() + n * 3 * Q, Dus_.get() + (int64_t)n * 9 * ds_.P, 3);
     // m(t_n) at every node (psi_ holds the samples of u~_n until the inverse map replaces them)
     iota_many(ubl_.get(), psi_.get(), 3 * nn);
-    pull_back<T>(m_.get(), cI0_.get(), psi_.get(), nullptr, T(1), nn, d_, st_);
+    pull_back_any(m_.get(), cI0_.get(), psi_.get(), nullptr, T(1), nn);
     final_warp<T>(m1_.get(), g1_.get(), cI0_.get(), psi_.get() + (int64_t)nt_ * 3 * P, d_, st_);
     pi_many(m_.get(), mt_.get(), nn);
     for (int n = 0; n <= nt_; n += 4)
@@ -560,13 +560,58 @@ class Solver final : public SolverBase {
     iota_many(Jbl_.get(), Jg_.get(), nn);
   }
 
+  void pull_back_any(T* out, const T* c, const T* u, const T* w, T a, int nodes) {
+    if constexpr (std::is_same_v<T, float>) {
+      if (brick_ok(d_)) return brick_pull_back(out, c, u, w, a, nodes, d_, st_);
+    }
+    pull_back<T>(out, c, u, w, a, nodes, d_, st_);
+  }
+
   // acc = sum_n w_n pi(iota(f~_n) G_n) with f_n = a J_n P(c) o psi_n (c: prefiltered grid samples at
   // t = 1) and f~_n = pi(f_n) written to bl [nt+1][Q]: the gradient term (c from lambda(1)) or the
   // Hessian term (c from dlambda(1)) of the state-equation variant
-  void pull_back_terms(const T* c, T a, T* bl, T* acc) {
+  // With h_out (float plane-wise path): h_out = L~ x_sym + acc, acc left unspecified.
+  void pull_back_terms(const T* c, T a, T* bl, T* acc, T* h_out = nullptr, const T* x_sym = nullptr) {
     const int nn = nt_ + 1;
     const int64_t Q = d_.Q;
-    pull_back<T>(lamg_.get(), c, psi_.get(), Jg_.get(), a, nn, d_, st_);
+    pull_back_any(lamg_.get(), c, psi_.get(), Jg_.get(), a, nn);
+    if constexpr (std::is_same_v<T, float>) {
+      if (full_.planes() && sm_.planes() && h_out) {
+        // per chunk of nodes: f~_n and the product-grid plane-band inputs of w_n iota'(f~_n) in one axis-0
+        // stage, their expansion, sum_n w_n e_n G_n in one node-sum reduction, and its axis-0 stage
+        // (accumulating over chunks; the last one writes h_out = L~ x_sym + acc)
+        for (int n0 = 0; n0 < nn; n0 += kMaxFields) {
+          const int m = std::min(kMaxFields, nn - n0);
+          const bool last = n0 + m == nn;
+          full_.reduce(kRedPlain, m, lamg_.get() + (int64_t)n0 * d_.P);
+          Axis0Args b = full_.axis0_args(m);
+          b.nout = m;
+          for (int f = 0; f < m; ++f) {
+            b.out[f] = bl + (int64_t)(n0 + f) * Q;
+            b.alpha[f] = 1.f;
+            b.o[f] = sm_.target(f, kPlain, f, nullptr, trap_w(n0 + f));
+          }
+          plane_axis0(b, st_);
+          sm_.expand_kind(m, kPlain, es_.get());
+          node_sum<float>(Ps(0), es_.get(), Gs_.get() + (int64_t)n0 * 3 * ds_.P, m, ds_.P, st_);
+          sm_.reduce(kRedPlain, 3, Ps(0));
+          Axis0Args r = sm_.axis0_args(3);
+          for (int j = 0; j < 3; ++j) {
+            r.out[j] = acc + j * Q;
+            r.alpha[j] = 1.f;
+            r.beta[j] = n0 == 0 ? 0.f : 1.f;
+            if (last) {
+              r.in[j] = acc + j * Q;
+              r.out[j] = h_out + j * Q;
+              r.y[j] = x_sym + j * Q;
+              r.ysym[j] = Lsym_.get();
+            }
+          }
+          plane_axis0(r, st_);
+        }
+        return;
+      }
+    }
     pi_many(lamg_.get(), bl, nn);
     zero(acc, 3 * Q, st_);
     for (int n = 0; n <= nt_; ++n) {
@@ -578,18 +623,18 @@ class Solver final : public SolverBase {
   }
 
   // lambda(1) = -(2/sigma^2)(m(1) - I1)
-  void adjoint_v2() {
+  void adjoint_v2(T* g) {
     scaled_diff<T>(S(0), T(-2.0 / sigma2_), m1_.get(), I1_.get(), d_.P, st_);
     prefilter(S(0), 1, d_, st_);
-    pull_back_terms(S(0), T(1), lamt_.get(), acc_.get());
+    pull_back_terms(S(0), T(1), lamt_.get(), acc_.get(), g, vbl_.get());
   }
 
   // Gauss-Newton incremental adjoint: dlambda(1) = -(2/sigma^2) dm(1), dm(1) = -g1 . iota(du~(1))
-  void matvec_tail_v2(const T* du1) {
+  void matvec_tail_v2(const T* du1, T* h, const T* dv) {
     full_.iota_kind(du1, S(0), 3, kPlain);
     v1_source<T>(S(3), g1_.get(), S(0), d_, st_);
     prefilter(S(3), 1, d_, st_);
-    pull_back_terms(S(3), T(-2.0 / sigma2_), incadj_.get(), acc_.get());
+    pull_back_terms(S(3), T(-2.0 / sigma2_), incadj_.get(), acc_.get(), h, dv);
   }
 
   // one deformation-state step: u_next = pi[P(u + dt/2 v) o X_b] + dt/2 v
@@ -642,7 +687,10 @@ class Solver final : public SolverBase {
     if (variant_ == LDDMM_BL_IMAGE_TRANSPORT) {
       adjoint_v1();
     } else if (variant_ == LDDMM_BL_STATE_EQUATION) {
-      adjoint_v2();
+      if constexpr (std::is_same_v<T, float>) {
+        if (full_.planes() && sm_.planes()) return adjoint_v2(g);  // g = L~ v + acc
+      }
+      adjoint_v2(nullptr);
     } else {
       if constexpr (std::is_same_v<T, float>) {
         if (full_.planes() && sm_.planes()) {
@@ -781,7 +829,7 @@ class Solver final : public SolverBase {
       axpby(dl + (int64_t)nt_ * Q, T(-2.0 / sigma2_), dm + (int64_t)nt_ * Q, T(0), nullptr, Q);
       bl_backward(dl, 1, acc_.get());
     } else if (variant_ == LDDMM_BL_STATE_EQUATION) {
-      matvec_tail_v2(dm + (int64_t)nt_ * 3 * Q);
+      matvec_tail_v2(dm + (int64_t)nt_ * 3 * Q, nullptr, nullptr);
     } else {
       // t = 1 coupling: drho~(1) = pi((2/sigma^2) (g1 . iota(du~(1))) g1)
       full_.iota_kind(dm + (int64_t)nt_ * 3 * Q, S(0), 3, kPlain);
@@ -855,8 +903,7 @@ class Solver final : public SolverBase {
     if (nc == 1) {
       bl_backward_planes(dl, 1, acc_.get(), true, h, dv);
     } else if (variant_ == LDDMM_BL_STATE_EQUATION) {
-      matvec_tail_v2(dm + (int64_t)nt_ * 3 * Q);
-      bl_scale_sym<float>(h, dv, Lsym_.get(), 3, Q, acc_.get(), st_);
+      matvec_tail_v2(dm + (int64_t)nt_ * 3 * Q, h, dv);  // h = L~ dv + acc
     } else {
       // t = 1 coupling: drho~(1) = pi((2/sigma^2) (g1 . iota(du~(1))) g1)
       full_.iota_kind(dm + (int64_t)nt_ * 3 * Q, S(0), 3, kPlain);
