@@ -194,6 +194,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--variant", type=int, default=1, choices=(1, 2, 3),
                     help="1 image transport (default), 2 state equation, 3 deformation state")
+    ap.add_argument("--rk4", action="store_true",
+                    help="deformation-state variant integrated by the explicit RK4 comparator (Eulerian form) "
+                         "instead of SL-RK2; use with --variant 3 and its nt (25-50)")
     ap.add_argument("--size", type=int, nargs=3, default=(128, 128, 128))
     ap.add_argument("--band", type=int, nargs=3, default=(32, 32, 32))
     ap.add_argument("--nt", type=int, default=10)
@@ -250,7 +253,8 @@ def main():
     torch.cuda.set_device(dev)
 
     I0, I1 = syn.phantom_pair_3d(N, seed=1, max_disp_vox=8.0)
-    ctx = L.Context(L.Problem(N, K, nt=Nt, variant=variant, precision=L.FP32))
+    integ = L.EULER_RK4 if args.rk4 else L.SL_RK2
+    ctx = L.Context(L.Problem(N, K, nt=Nt, variant=variant, precision=L.FP32, integrator=integ))
     g = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device=dev)
     ctx.set_images(g(I0), g(I1))
     # random band-limited velocity scaled to 8 voxels maximum displacement per unit time
@@ -323,7 +327,8 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(variant, N, K, Nt, I0, I1, (vc * (8.0 / vmax)), syn.random_bl_coefficients(3, K, seed=3))
+        cpu = cpu_baseline(variant, N, K, Nt, I0, I1, (vc * (8.0 / vmax)), syn.random_bl_coefficients(3, K, seed=3),
+                           rk4=args.rk4)
 
     line = {
         "metric": "Hessian-matvecs/s at 128^3" if N == (128, 128, 128) else f"Hessian-matvecs/s at {N}",
@@ -332,8 +337,10 @@ def main():
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{VARIANT_NAMES[args.variant]} BL PDE-LDDMM "
                                f"Gauss-Newton Hessian matvec, grid {N[0]}x{N[1]}x{N[2]}, band {K[0]}x{K[1]}x{K[2]}x3, "
-                               f"Nt={Nt}, SL-RK2, FP32 with FP64 reductions",
+                               f"Nt={Nt}, {'explicit RK4 (Eulerian)' if args.rk4 else 'SL-RK2'}, "
+                               f"FP32 with FP64 reductions",
                    "grid": list(N), "band": list(K), "nt": Nt, "variant": args.variant,
+                   "integrator": "rk4" if args.rk4 else "sl-rk2",
                    "alpha": 0.0025, "s": 2, "sigma2": 1.0},
         "roofline": roofline,
         "cpu_baseline": cpu,
@@ -427,20 +434,21 @@ def _cpu_model():
     return None
 
 
-def cpu_baseline(variant, N, K, Nt, I0, I1, v, dv):
+def cpu_baseline(variant, N, K, Nt, I0, I1, v, dv, rk4=False):
     """The FP64 CPU oracle on the host cores: full Hessian matvecs at the same workload, with torch's default
     thread count (the reported value) and with one thread, plus one matvec of the other variant."""
     import numpy as np
     import torch
 
     from oracle.problem import Problem as OP
+    from oracle.eulerian_rk import Variant3RK
     from oracle.variant1 import Variant1
     from oracle.variant2 import Variant2
     from oracle.variant3 import Variant3
 
     def timed(var, reps):
-        model = {1: Variant1, 2: Variant2, 3: Variant3}[var](OP(N, K, Nt=Nt), I0.astype(np.float64),
-                                                          I1.astype(np.float64))
+        cls = Variant3RK if (rk4 and var == 3) else {1: Variant1, 2: Variant2, 3: Variant3}[var]
+        model = cls(OP(N, K, Nt=Nt), I0.astype(np.float64), I1.astype(np.float64))
         model.setup(v)
         model.state()
         t0 = time.perf_counter()

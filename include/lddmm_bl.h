@@ -91,6 +91,16 @@ typedef enum {
                           with float accumulation (hi/lo split operands) */
 } lddmm_bl_precision;
 
+typedef enum {
+  LDDMM_BL_SL_RK2 = 0,    /* semi-Lagrangian Heun steps along the characteristics (Section 3) */
+  LDDMM_BL_EULER_RK4 = 1  /* comparator: the deformation-state equations of Section 2.3.3 in Eulerian form,
+                             d_t u~ = v~ - D~u~ star v~, d_t rho~ = -div~(rho~ star v~) and their incremental
+                             counterparts, integrated by the classical four-stage Runge-Kutta method with exact
+                             truncated products (the RK rows of the paper's evaluation, Section 4.3: it needs
+                             nt = 25-50 for stability).  The incremental state's D~u~ at half steps is the mean of
+                             the two nodes'.  LDDMM_BL_DEFORMATION_STATE only (LDDMM_BL_E_ARG otherwise). */
+} lddmm_bl_integrator;
+
 typedef struct {
   int32_t dim;            /* 2 or 3 */
   int32_t n[3];           /* grid N1..Nd (unused entries ignored) */
@@ -101,6 +111,7 @@ typedef struct {
   int32_t s;
   double sigma2;          /* data weight 1/sigma^2, eq. BLEnergy */
   int32_t precision;      /* lddmm_bl_precision */
+  int32_t integrator;     /* lddmm_bl_integrator (0: SL-RK2) */
 } lddmm_bl_params;
 
 typedef struct {

@@ -273,6 +273,42 @@ __global__ void k_node_sum(T* __restrict__ out, const T* __restrict__ e, const T
   out[2 * P + p] = a2;
 }
 
+// Right-hand sides of the explicit RK comparator (deformation-state equations in Eulerian form) on the
+// product grid, where the truncated products are exact:
+//   adjoint:            out_i = -(sum_j d_j r_i v_j + r_i div v)   (the product rule of -div(r_i v))
+//   incremental state:  out_i = dv_i - sum_j d_j du_i v_j - sum_j (a Du_a + b Du_b)_ij dv_j
+// (D fields [i][j] = d_j x_i, 9 per vector)
+template <typename T>
+__global__ void k_rk_adjoint_rhs(T* __restrict__ out, const T* __restrict__ Dr, const T* __restrict__ r,
+                                 const T* __restrict__ v, const T* __restrict__ divv, int64_t P) {
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  const T v0 = v[p], v1 = v[P + p], v2 = v[2 * P + p], dv = divv[p];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const T* D = Dr + 3 * i * P;
+    out[i * P + p] = -(D[p] * v0 + D[P + p] * v1 + D[2 * P + p] * v2 + r[i * P + p] * dv);
+  }
+}
+
+template <typename T>
+__global__ void k_rk_inc_rhs(T* __restrict__ out, const T* __restrict__ Ddu, const T* __restrict__ Dua,
+                             const T* __restrict__ Dub, T a, T b, const T* __restrict__ v, const T* __restrict__ dv,
+                             int64_t P) {
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  const T v0 = v[p], v1 = v[P + p], v2 = v[2 * P + p];
+  const T w0 = dv[p], w1 = dv[P + p], w2 = dv[2 * P + p];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const T* D = Ddu + 3 * i * P;
+    const T* A = Dua + 3 * i * P;
+    const T* B = Dub + 3 * i * P;
+    const T u0 = a * A[p] + b * B[p], u1 = a * A[P + p] + b * B[P + p], u2 = a * A[2 * P + p] + b * B[2 * P + p];
+    out[i * P + p] = dv[i * P + p] - (D[p] * v0 + D[P + p] * v1 + D[2 * P + p] * v2) - (u0 * w0 + u1 * w1 + u2 * w2);
+  }
+}
+
 template <typename T>
 __global__ void k_final_warp(T* __restrict__ m1, T* __restrict__ g1, const T* __restrict__ cI0,
                              const T* __restrict__ u, int n0, int n1, int n2) {
@@ -749,6 +785,21 @@ void node_sum(T* out, const T* e, const T* G, int ns, int64_t P, hipStream_t s) 
 }
 
 template <typename T>
+void rk_adjoint_rhs(T* out, const T* Dr, const T* r, const T* v, const T* divv, int64_t P, hipStream_t s) {
+  prof::launch("k_rk_adjoint_rhs<" + std::string(prof::tname<T>()) + ">", 20.0 * P * sizeof(T), 0.0,
+               k_rk_adjoint_rhs<T>, grid_for(P), dim3(kBlock), 0, s, out, Dr, r, v, divv, P);
+  LDDMM_LAUNCH_CHECK();
+}
+
+template <typename T>
+void rk_inc_rhs(T* out, const T* Ddu, const T* Dua, const T* Dub, T a, T b, const T* v, const T* dv, int64_t P,
+                hipStream_t s) {
+  prof::launch("k_rk_inc_rhs<" + std::string(prof::tname<T>()) + ">", 39.0 * P * sizeof(T), 0.0, k_rk_inc_rhs<T>,
+               grid_for(P), dim3(kBlock), 0, s, out, Ddu, Dua, Dub, a, b, v, dv, P);
+  LDDMM_LAUNCH_CHECK();
+}
+
+template <typename T>
 void scaled_diff(T* out, T a, const T* x, const T* y, int64_t n, hipStream_t s) {
   prof::launch(std::string("k_scaled_diff<") + prof::tname<T>() + ">", 3.0 * n * sizeof(T), 0.0, k_scaled_diff<T>, grid_for(n), dim3(kBlock), 0, s, out, a, x, y, n);
   LDDMM_LAUNCH_CHECK();
@@ -811,6 +862,9 @@ void zero(T* p, int64_t n, hipStream_t s) {
   template void final_warp<T>(T*, T*, const T*, const T*, const Dims&, hipStream_t);                    \
   template void pull_back<T>(T*, const T*, const T*, const T*, T, int, const Dims&, hipStream_t);        \
   template void node_sum<T>(T*, const T*, const T*, int, int64_t, hipStream_t);                          \
+  template void rk_adjoint_rhs<T>(T*, const T*, const T*, const T*, const T*, int64_t, hipStream_t);      \
+  template void rk_inc_rhs<T>(T*, const T*, const T*, const T*, T, T, const T*, const T*, int64_t,         \
+                              hipStream_t);                                                              \
   template void scaled_diff<T>(T*, T, const T*, const T*, int64_t, hipStream_t);                        \
   template void residual_times_grad<T>(T*, T, const T*, const T*, const T*, const Dims&, hipStream_t);  \
   template void coupling_v3<T>(T*, T, const T*, const T*, const Dims&, hipStream_t);                    \

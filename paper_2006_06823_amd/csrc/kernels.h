@@ -179,6 +179,14 @@ void final_warp(T* m1, T* g1, const T* cI0, const T* u, const Dims& d, hipStream
 // out_n = a w_n P(c)(x - u_n) for nodes n < nodes: u [nodes][3][P] (unit-torus units), w [nodes][P] or null
 template <typename T>
 void pull_back(T* out, const T* c, const T* u, const T* w, T a, int nodes, const Dims& d, hipStream_t s);
+// explicit RK comparator right-hand sides on the product grid (D fields [i][j] = d_j x_i):
+// adjoint out_i = -(sum_j Dr_ij v_j + r_i divv); incremental state
+// out_i = dv_i - sum_j Ddu_ij v_j - sum_j (a Dua + b Dub)_ij dv_j
+template <typename T>
+void rk_adjoint_rhs(T* out, const T* Dr, const T* r, const T* v, const T* divv, int64_t P, hipStream_t s);
+template <typename T>
+void rk_inc_rhs(T* out, const T* Ddu, const T* Dua, const T* Dub, T a, T b, const T* v, const T* dv, int64_t P,
+                hipStream_t s);
 // out [3][P] = sum_n e_n G_n (e [ns][P], G [ns][3][P])
 template <typename T>
 void node_sum(T* out, const T* e, const T* G, int ns, int64_t P, hipStream_t s);

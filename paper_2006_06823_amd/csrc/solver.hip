@@ -60,6 +60,10 @@ class Solver final : public SolverBase {
         p.variant != LDDMM_BL_DEFORMATION_STATE)
       throw ArgError("unknown variant");
     if (!(p.alpha > 0) || p.s < 1 || !(p.sigma2 > 0)) throw ArgError("alpha, s, sigma2 must be positive");
+    if (p.integrator != LDDMM_BL_SL_RK2 && p.integrator != LDDMM_BL_EULER_RK4) throw ArgError("unknown integrator");
+    rk_ = p.integrator == LDDMM_BL_EULER_RK4;
+    if (rk_ && p.variant != LDDMM_BL_DEFORMATION_STATE)
+      throw ArgError("the explicit RK4 comparator integrates the deformation-state variant only");
     const int off = 3 - dim_;
     d_.n[0] = d_.n[1] = d_.n[2] = 1;
     d_.k[0] = d_.k[1] = d_.k[2] = 1;
@@ -264,6 +268,12 @@ class Solver final : public SolverBase {
       g1_.alloc(3 * P);
     }
     if (variant_ == LDDMM_BL_DEFORMATION_STATE) rho_.alloc(nn * 3 * Q);
+    if (rk_) {
+      // the RK comparator's velocity samples, right-hand side and operand transforms on the product grid
+      vs_.alloc(3 * Ps);
+      rkw_.alloc(3 * Ps);
+      rkD_.alloc(12 * Ps);
+    }
     if (variant_ == LDDMM_BL_STATE_EQUATION) {
       // inverse map, its Jacobian, their grid samples at every node, and the pulled-back adjoint
       nubl_.alloc(nn * 3 * Q);
@@ -427,6 +437,7 @@ class Solver final : public SolverBase {
     bl_div<T>(tmpbl_.get(), vbl_.get(), d_, st_);
     full_.iota_kind(tmpbl_.get(), divv_.get(), 1, kPlain);
     sm_.iota_kind(tmpbl_.get(), divvs_.get(), 1, kPlain);
+    if (rk_) sm_.iota_kind(vbl_.get(), vs_.get(), 3, kPlain);
   }
 
   double regulariser() {
@@ -527,7 +538,13 @@ class Solver final : public SolverBase {
   void state_v3() {
     const int64_t Q = d_.Q;
     zero(ubl_.get(), 3 * Q, st_);
-    for (int n = 0; n < nt_; ++n) u_step(ubl_.get() + n * 3 * Q, ubl_.get() + (n + 1) * 3 * Q);
+    for (int n = 0; n < nt_; ++n) {
+      if (rk_)
+        rk4_step(ubl_.get() + n * 3 * Q, ubl_.get() + (n + 1) * 3 * Q, dt_,
+                 [&](const T* x, int, T* o) { rk_rhs_state(x, o); });
+      else
+        u_step(ubl_.get() + n * 3 * Q, ubl_.get() + (n + 1) * 3 * Q);
+    }
     // D u_n = iota'(D~ u~_n) on the product grid
     for (int n = 0; n <= nt_; ++n) sm_.iota_grad(ubl_.get() + n * 3 * Q, Dus_.get() + (int64_t)n * 9 * ds_.P, 3);
     full_.iota_kind(ubl_.get() + (int64_t)nt_ * 3 * Q, S(0), 3, kPlain);
@@ -637,6 +654,100 @@ class Solver final : public SolverBase {
     pull_back_terms(S(3), T(-2.0 / sigma2_), incadj_.get(), acc_.get(), h, dv);
   }
 
+  // ----------------- explicit RK4 comparator (deformation-state equations in Eulerian form)
+  // Band-limited right-hand sides, each formed on the product grid (exact truncated products) and
+  // projected: d_t u~ = v~ - D~u~ star v~; d_t r~ = -div~(r~ star v~) for the adjoint and the incremental
+  // adjoint; d_t du~ = dv~ - D~du~ star v~ - D~u~ star dv~ with D~u~ at the stage's time (a node, or the
+  // mean of the step's two nodes at its half step).
+  void rk_rhs_state(const T* u, T* out) {
+    sm_.iota_grad(u, rkD_.get(), 3);
+    v3_source<T>(rkw_.get(), rkD_.get(), vs_.get(), ds_, st_);
+    sm_.pi(rkw_.get(), out, 3);
+  }
+  void rk_rhs_adjoint(const T* r, T* out) {
+    const int64_t Q = d_.Q;
+    int kinds[kMaxFields][3] = {};
+    const T* xs[kMaxFields];
+    for (int i = 0; i < 3; ++i) {
+      for (int j = 0; j < 3; ++j) {
+        xs[3 * i + j] = r + i * Q;
+        for (int a = 0; a < 3; ++a) kinds[3 * i + j][a] = (a == j) ? kDeriv : kPlain;
+      }
+      xs[9 + i] = r + i * Q;
+    }
+    sm_.iota_comb(xs, nullptr, nullptr, rkD_.get(), 12, kinds);
+    rk_adjoint_rhs<T>(rkw_.get(), rkD_.get(), rkD_.get() + 9 * ds_.P, vs_.get(), divvs_.get(), ds_.P, st_);
+    sm_.pi(rkw_.get(), out, 3);
+  }
+  void rk_rhs_inc(const T* du, int n, T a, T b, T* out) {
+    const T* Da = Dus_.get() + (int64_t)n * 9 * ds_.P;
+    const T* Db = b != T(0) ? Da + 9 * ds_.P : Da;
+    sm_.iota_grad(du, rkD_.get(), 3);
+    rk_inc_rhs<T>(rkw_.get(), rkD_.get(), Da, Db, a, b, vs_.get(), dvs_.get(), ds_.P, st_);
+    sm_.pi(rkw_.get(), out, 3);
+  }
+  // one classical four-stage step y_next = y + h/6 (k1 + 2 k2 + 2 k3 + k4) of y' = rhs(y) for a band
+  // vector (h < 0 steps backward); rhs(stage input, stage 0..3, out); y_next must not alias y
+  template <class F>
+  void rk4_step(const T* y, T* ynext, T h, F&& rhs) {
+    const int64_t n3 = 3 * d_.Q;
+    T* k = blA_.get();
+    T* ys = blA_.get() + n3;
+    const T c[4] = {T(0), h / 2, h / 2, h}, w[4] = {h / 6, h / 3, h / 3, h / 6};
+    copy(ynext, y, n3);
+    for (int st = 0; st < 4; ++st) {
+      const T* in = y;
+      if (st > 0) {
+        axpby(ys, T(1), y, c[st], k, n3);
+        in = ys;
+      }
+      rhs(in, st, k);
+      axpby(ynext, T(1), ynext, w[st], k, n3);
+    }
+  }
+  // backward RK4 sweep of -d_t r~ = div~(r~ star v~) from traj[nt] to traj[0]
+  void rk_backward(T* traj) {
+    const int64_t Q = d_.Q;
+    for (int n = nt_; n > 0; --n)
+      rk4_step(traj + n * 3 * Q, traj + (n - 1) * 3 * Q, -dt_, [&](const T* x, int, T* o) { rk_rhs_adjoint(x, o); });
+  }
+  // acc = sum_n w_n (x_n - pi((D u_n)^T iota(x_n))): the deformation-state gradient / Hessian term
+  void v3_terms(const T* traj, T* acc) {
+    const int64_t Q = d_.Q;
+    zero(acc, 3 * Q, st_);
+    for (int n = 0; n <= nt_; ++n) {
+      const T w = trap_w(n);
+      const T* xn = traj + n * 3 * Q;
+      T* dst[6] = {tmpbl_.get(), tmpbl_.get() + Q, tmpbl_.get() + 2 * Q, acc, acc + Q, acc + 2 * Q};
+      const T al[6] = {T(1), T(1), T(1), -w, -w, -w}, be[6] = {T(0), T(0), T(0), T(1), T(1), T(1)};
+      products(xn, 3, n, dst, al, be);
+      axpby(acc, T(1), acc, w, xn, 3 * Q);
+    }
+  }
+  void run_matvec_rk(const T* dv, T* h) {
+    const int64_t Q = d_.Q;
+    sm_.iota_kind(dv, dvs_.get(), 3, kPlain);
+    T* du = inc_.get();
+    zero(du, 3 * Q, st_);
+    for (int n = 0; n < nt_; ++n)
+      rk4_step(du + n * 3 * Q, du + (n + 1) * 3 * Q, dt_, [&](const T* x, int st, T* o) {
+        if (st == 0)
+          rk_rhs_inc(x, n, T(1), T(0), o);
+        else if (st == 3)
+          rk_rhs_inc(x, n + 1, T(1), T(0), o);
+        else
+          rk_rhs_inc(x, n, T(0.5), T(0.5), o);
+      });
+    // t = 1 coupling as in the SL form
+    full_.iota_kind(du + (int64_t)nt_ * 3 * Q, S(0), 3, kPlain);
+    coupling_v3<T>(S(3), T(2.0 / sigma2_), g1_.get(), S(0), d_, st_);
+    T* dr = incadj_.get();
+    full_.pi(S(3), dr + (int64_t)nt_ * 3 * Q, 3);
+    rk_backward(dr);
+    v3_terms(dr, acc_.get());
+    bl_scale_sym<T>(h, dv, Lsym_.get(), 3, Q, acc_.get(), st_);
+  }
+
   // one deformation-state step: u_next = pi[P(u + dt/2 v) o X_b] + dt/2 v
   void u_step(const T* un, T* un1) { map_step(un, un1, Xb_.get(), 1); }
   // one step of a displacement map along the departure displacements X:
@@ -691,6 +802,11 @@ class Solver final : public SolverBase {
         if (full_.planes() && sm_.planes()) return adjoint_v2(g);  // g = L~ v + acc
       }
       adjoint_v2(nullptr);
+    } else if (rk_) {
+      residual_times_grad<T>(S(0), T(-2.0 / sigma2_), m1_.get(), I1_.get(), g1_.get(), d_, st_);
+      full_.pi(S(0), rho_.get() + (int64_t)nt_ * 3 * d_.Q, 3);
+      rk_backward(rho_.get());
+      v3_terms(rho_.get(), acc_.get());
     } else {
       if constexpr (std::is_same_v<T, float>) {
         if (full_.planes() && sm_.planes()) {
@@ -782,6 +898,7 @@ class Solver final : public SolverBase {
 
   // ----------------------------------- Hessian matvec (rows 5-8, Section 2.3)
   void run_matvec(const T* dv, T* h) {
+    if (rk_) return run_matvec_rk(dv, h);
     if constexpr (std::is_same_v<T, float>) {
       if (full_.planes() && sm_.planes()) return run_matvec_planes(dv, h);
     }
@@ -987,6 +1104,7 @@ class Solver final : public SolverBase {
   double last_e_[3] = {0, 0, 0};  // objective terms of the held state
   bool graphs_enabled_ = std::getenv("LDDMM_BL_NO_GRAPH") == nullptr;
   bool bf16_ = false;  // split-bf16 contractions for the first-axis DFT stages
+  bool rk_ = false;    // explicit RK4 comparator instead of the SL-RK2 sweeps
   bool trace_ = std::getenv("LDDMM_BL_TRACE") != nullptr;  // Gauss-Newton scalars to stderr
 
   template <typename U>
@@ -1003,6 +1121,7 @@ class Solver final : public SolverBase {
   DevBuf<T> m_, mt_, Gs_, lam0_;                // image transport
   DevBuf<T> ubl_, Dus_, m1_, g1_, rho_;         // deformation state (and the state-equation variant)
   DevBuf<T> nubl_, Jbl_, psi_, Jg_, lamg_, lamt_, one_;  // state-equation variant
+  DevBuf<T> vs_, rkw_, rkD_;                    // explicit RK4 comparator (product grid)
   DevBuf<double> det_;  // Jacobian map when the caller keeps none
 
  public:

@@ -22,6 +22,7 @@ IMAGE_TRANSPORT = 1
 STATE_EQUATION = 2
 DEFORMATION_STATE = 3
 FP64, FP32, BF16_DFT = 0, 1, 2
+SL_RK2, EULER_RK4 = 0, 1
 
 FIELD_VELOCITY, FIELD_DEP_BACKWARD, FIELD_DEP_FORWARD, FIELD_DIV_V = 0, 1, 2, 3
 FIELD_STATE, FIELD_M1, FIELD_ADJOINT0, FIELD_INC_STATE, FIELD_INC_ADJOINT = 4, 5, 6, 7, 8
@@ -50,6 +51,7 @@ class Params(ctypes.Structure):
         ("dim", ctypes.c_int32), ("n", ctypes.c_int32 * 3), ("k", ctypes.c_int32 * 3),
         ("nt", ctypes.c_int32), ("variant", ctypes.c_int32), ("alpha", ctypes.c_double),
         ("s", ctypes.c_int32), ("sigma2", ctypes.c_double), ("precision", ctypes.c_int32),
+        ("integrator", ctypes.c_int32),
     ]
 
 
@@ -168,6 +170,7 @@ class Problem:
     s: int = 2
     sigma2: float = 1.0
     precision: int = FP32
+    integrator: int = 0     # SL_RK2; EULER_RK4: the explicit RK comparator (deformation state only)
 
 
 def make_params(prob: "Problem") -> Params:
@@ -179,6 +182,7 @@ def make_params(prob: "Problem") -> Params:
         p.k[j] = int(prob.k[j]) if j < d else 1
     p.nt, p.variant, p.alpha, p.s, p.sigma2, p.precision = (
         prob.nt, prob.variant, prob.alpha, prob.s, prob.sigma2, prob.precision)
+    p.integrator = prob.integrator
     return p
 
 
@@ -221,13 +225,7 @@ class Context:
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         # a dedicated non-default stream: the library captures its Hessian matvec into a HIP graph on it
         self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
-        p = Params()
-        p.dim = self.dim
-        for j in range(3):
-            p.n[j] = self.n[j] if j < self.dim else 1
-            p.k[j] = self.k[j] if j < self.dim else 1
-        p.nt, p.variant, p.alpha, p.s, p.sigma2, p.precision = (
-            prob.nt, prob.variant, prob.alpha, prob.s, prob.sigma2, prob.precision)
+        p = make_params(prob)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             st = self.lib.lddmm_bl_create(ctypes.byref(p), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
