@@ -39,10 +39,12 @@ def grad_inf(g, prob: Problem) -> float:
     return float(sp.include(g, prob.N).abs().max())
 
 
-def pcg(matvec, b, precond, tol: float, maxit: int, fixed: bool = False):
+def pcg(matvec, b, precond, tol: float, maxit: int, fixed: bool = False, flexible: bool = False):
     """Preconditioned CG from 0 for A x = b.  Returns (x, iterations, flag, rnorm).
 
-    flag: 0 converged/cap, 3 non-positive curvature.
+    flag: 0 converged/cap, 3 non-positive curvature.  flexible: the direction update
+    beta = r_new . (z_new - z_old) / r_old . z_old (flexible CG, for a preconditioner that is itself an
+    iteration); it equals the PCG update when the preconditioner is a fixed SPD operator.
     """
     x = torch.zeros_like(b)
     r = b.clone()
@@ -65,9 +67,11 @@ def pcg(matvec, b, precond, tol: float, maxit: int, fixed: bool = False):
         a = rz / pAp
         x = x + a * p
         r = r - a * Ap
+        z_old = z
         z = precond(r)
         rz_new = float(sp.l2(r, z))
-        p = z + (rz_new / rz) * p
+        num = rz_new - float(sp.l2(r, z_old)) if flexible else rz_new
+        p = z + (num / rz) * p
         rz = rz_new
     return x, maxit, flag, math.sqrt(float(sp.l2(r, r)))
 
@@ -94,10 +98,12 @@ class GNReport:
 
 def gauss_newton(model, v0, max_gn=10, max_pcg=5, grad_rtol=1e-3, grad_ref_inf=0.0,
                  fixed_iters=False, precond=None):
-    """Gauss-Newton-Krylov on the BL energy.  model: Variant1 or Variant3 instance."""
+    """Gauss-Newton-Krylov on the BL energy.  model: a variant instance.  precond: r -> M^-1 r; one with a
+    set_velocity(v) method is re-linearised at every GN iteration, one with flexible = True runs flexible CG."""
     p = model.p
     if precond is None:
         precond = lambda r: sp.apply_L(r, p.d, p.alpha, p.s, inverse=True)
+    flexible = bool(getattr(precond, "flexible", False))
     v = sp.as_t(v0).clone()
     model.setup(v)
     model.state()
@@ -113,7 +119,9 @@ def gauss_newton(model, v0, max_gn=10, max_pcg=5, grad_rtol=1e-3, grad_ref_inf=0
             break
         gnorm = math.sqrt(float(sp.l2(g, g)))
         eta = min(0.5, math.sqrt(gnorm / gnorm0)) if gnorm0 > 0 else 0.5
-        dv, its, flag, _ = pcg(model.hess_matvec, -g, precond, eta * gnorm, max_pcg, fixed_iters)
+        if hasattr(precond, "set_velocity"):
+            precond.set_velocity(v)
+        dv, its, flag, _ = pcg(model.hess_matvec, -g, precond, eta * gnorm, max_pcg, fixed_iters, flexible)
         rep.pcg_iters_total += its
         gd = float(sp.l2(g, dv))
         eps = 1.0
