@@ -413,11 +413,11 @@ def learned_leg(npairs):
         def pairs(self, sds):
             for sd, (a, b) in zip(sds, pairs):
                 yield sd, a, b
-    rows = LW.compare(net, reg, seeds, _List(), LW.SolveOpts(), log=lambda *a, **k: None, with_Z=True)
+    rows = LW.compare(net, reg, seeds, _List(), LW.SolveOpts(), log=lambda *a, **k: None, with_Z=True, ml_inner=5)
     summ = LW.summarize(rows, with_Z=True)
     out = {"pairs": npairs, "seeds": f"{seeds[0]}..{seeds[-1]}", "tolerance": "rel grad 1e-3 of |g(0)|_inf",
            "caps": "20 GN x 10 PCG"}
-    for k in ("plain", "learned", "learned_E", "learned_Z"):
+    for k in ("plain", "learned", "learned_E", "learned_Z", "plain_ml"):
         out[k] = {m: round(summ[k][m], 4) for m in ("registrations_per_s", "gn_iters_mean", "hess_matvecs_mean",
                                                     "seconds_mean", "reached_tol", "reached_plain_E",
                                                     "gn_iter_ratio", "time_ratio") if m in summ[k]}

@@ -122,6 +122,13 @@ typedef struct {
   int32_t fixed_iters;    /* 1 => run every cap to the end (no tolerance exits) */
   double energy_target;   /* > 0 => also stop once the objective E <= energy_target (0 = off); used to
                              time how fast a warm-started run reaches a reference run's objective */
+  int32_t ml_inner;       /* > 0 => two-level spectral preconditioner (the multi-level preconditioning the
+                             Discussion names as the next step): M^-1 r = L~^-1 on the slots above the coarse
+                             band Kc = 2 floor(K / 4) and, inside it, ml_inner PCG iterations (from 0, with
+                             L~c^-1) on the Gauss-Newton Hessian of the coarse problem (grid N / 2, images
+                             restricted by 2^d block means, velocity restricted to Kc) linearised at every GN
+                             iteration; the outer iteration is then flexible CG.  Needs even N and a valid
+                             coarse band on every axis; excludes precond_Z (LDDMM_BL_E_ARG). 0 = off. */
 } lddmm_bl_gn_opts;
 
 #define LDDMM_BL_LOG_MAX 64 /* Gauss-Newton iterations whose decisions the report records */

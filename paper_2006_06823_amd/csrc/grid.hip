@@ -310,6 +310,37 @@ __global__ void k_rk_inc_rhs(T* __restrict__ out, const T* __restrict__ Ddu, con
 }
 
 template <typename T>
+__global__ void k_band_copy(T* __restrict__ out, int o0, int o1, int o2, const T* __restrict__ in, int i0, int i1,
+                            int i2, int m0, int m1, int m2, int ncomp, bool keep_rest) {
+  const int64_t Qo = (int64_t)o0 * o1 * o2;
+  const int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (q >= ncomp * Qo) return;
+  const int c = static_cast<int>(q / Qo);
+  const int64_t r = q - c * Qo;
+  const int a2 = static_cast<int>(r % o2), a1 = static_cast<int>((r / o2) % o1), a0 = static_cast<int>(r / ((int64_t)o1 * o2));
+  if (a0 < m0 && a1 < m1 && a2 < m2)
+    out[q] = in[(int64_t)c * i0 * i1 * i2 + ((int64_t)a0 * i1 + a1) * i2 + a2];
+  else if (!keep_rest)
+    out[q] = T(0);
+}
+
+template <typename T>
+__global__ void k_restrict_grid(T* __restrict__ out, const T* __restrict__ in, int n0, int n1, int n2, int f0,
+                                int f1, int f2) {
+  const int c0 = n0 / f0, c1 = n1 / f1, c2 = n2 / f2;
+  const int64_t Pc = (int64_t)c0 * c1 * c2;
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= Pc) return;
+  const GridIdx g = unflatten(p, c1, c2);
+  T acc = 0;
+  for (int a = 0; a < f0; ++a)
+    for (int b = 0; b < f1; ++b)
+      for (int e = 0; e < f2; ++e)
+        acc += in[((int64_t)(g.i0 * f0 + a) * n1 + (g.i1 * f1 + b)) * n2 + (g.i2 * f2 + e)];
+  out[p] = acc / T(f0 * f1 * f2);
+}
+
+template <typename T>
 __global__ void k_final_warp(T* __restrict__ m1, T* __restrict__ g1, const T* __restrict__ cI0,
                              const T* __restrict__ u, int n0, int n1, int n2) {
   const int64_t P = (int64_t)n0 * n1 * n2;
@@ -800,6 +831,32 @@ void rk_inc_rhs(T* out, const T* Ddu, const T* Dua, const T* Dub, T a, T b, cons
 }
 
 template <typename T>
+void band_copy(T* out, const int ko[3], const T* in, const int ki[3], const int m[3], int ncomp, bool keep_rest,
+               hipStream_t s) {
+  const int64_t n = (int64_t)ncomp * ko[0] * ko[1] * ko[2];
+  for (int j = 0; j < 3; ++j)
+    if (m[j] > ko[j] || m[j] > ki[j]) throw ArgError("band_copy: copy extent beyond a band");
+  prof::launch("k_band_copy<" + std::string(prof::tname<T>()) + ">", 2.0 * n * sizeof(T), 0.0, k_band_copy<T>,
+               grid_for(n), dim3(kBlock), 0, s, out, ko[0], ko[1], ko[2], in, ki[0], ki[1], ki[2], m[0], m[1], m[2],
+               ncomp, keep_rest);
+  LDDMM_LAUNCH_CHECK();
+}
+
+template <typename T>
+void restrict_grid(T* out, const T* in, const Dims& fine, hipStream_t s) {
+  int f[3];
+  for (int j = 0; j < 3; ++j) {
+    f[j] = fine.n[j] > 1 ? 2 : 1;
+    if (fine.n[j] % f[j]) throw ArgError("restrict_grid: odd grid size");
+  }
+  const int64_t Pc = fine.P / (f[0] * f[1] * f[2]);
+  prof::launch("k_restrict_grid<" + std::string(prof::tname<T>()) + ">", 1.0 * (fine.P + Pc) * sizeof(T), 0.0,
+               k_restrict_grid<T>, grid_for(Pc), dim3(kBlock), 0, s, out, in, fine.n[0], fine.n[1], fine.n[2], f[0],
+               f[1], f[2]);
+  LDDMM_LAUNCH_CHECK();
+}
+
+template <typename T>
 void scaled_diff(T* out, T a, const T* x, const T* y, int64_t n, hipStream_t s) {
   prof::launch(std::string("k_scaled_diff<") + prof::tname<T>() + ">", 3.0 * n * sizeof(T), 0.0, k_scaled_diff<T>, grid_for(n), dim3(kBlock), 0, s, out, a, x, y, n);
   LDDMM_LAUNCH_CHECK();
@@ -862,6 +919,8 @@ void zero(T* p, int64_t n, hipStream_t s) {
   template void final_warp<T>(T*, T*, const T*, const T*, const Dims&, hipStream_t);                    \
   template void pull_back<T>(T*, const T*, const T*, const T*, T, int, const Dims&, hipStream_t);        \
   template void node_sum<T>(T*, const T*, const T*, int, int64_t, hipStream_t);                          \
+  template void band_copy<T>(T*, const int*, const T*, const int*, const int*, int, bool, hipStream_t);   \
+  template void restrict_grid<T>(T*, const T*, const Dims&, hipStream_t);                                 \
   template void rk_adjoint_rhs<T>(T*, const T*, const T*, const T*, const T*, int64_t, hipStream_t);      \
   template void rk_inc_rhs<T>(T*, const T*, const T*, const T*, T, T, const T*, const T*, int64_t,         \
                               hipStream_t);                                                              \

@@ -239,9 +239,19 @@ double* reduce_slots(double* work);
 // x += a p, r -= a Ap with a = slot[irz] / slot[ipap], skipped unless slot[ipap] > 0
 template <typename T>
 void pcg_step(T* x, T* r, const T* p, const T* Ap, double* work, int irz, int ipap, int64_t n, hipStream_t s);
-// p = z + (slot[irzn] / slot[irz]) p, skipped unless slot[ipap] > 0
+// p = z + beta p, skipped unless slot[ipap] > 0: beta = slot[irzn] / slot[irz], or, with ixz >= 0 (flexible
+// CG; slot[ixz] = r_new . z_old), beta = (slot[irzn] - slot[ixz]) / slot[irz]
 template <typename T>
-void pcg_dir(T* p, const T* z, double* work, int irz, int irzn, int ipap, int64_t n, hipStream_t s);
+void pcg_dir(T* p, const T* z, double* work, int irz, int irzn, int ipap, int64_t n, hipStream_t s, int ixz = -1);
+// band arrays [c][K0][K1][K2]: out = in on the slots a_j < m_j of every axis; the other slots of out are
+// zeroed (keep_rest = false) or kept.  Restriction to a coarse band (out Kc, in K, m = Kc - 1 per axis with
+// more than one slot) and its extension or overwrite of the fine band's low slots (out K, in Kc).
+template <typename T>
+void band_copy(T* out, const int ko[3], const T* in, const int ki[3], const int m[3], int ncomp, bool keep_rest,
+               hipStream_t s);
+// 2^d block means of a grid field (axes with one node are kept): out on the grid n / f, f_j = 2 or 1
+template <typename T>
+void restrict_grid(T* out, const T* in, const Dims& fine, hipStream_t s);
 // z += sum_i (Minv c)_i Z_i with c_i = slot[ic + i] (device Minv r x r, Z r x n)
 template <typename T>
 void lowrank_add(T* z, const T* Z, const double* Minv, double* work, int ic, int r, int64_t n, hipStream_t s);

@@ -175,12 +175,13 @@ __global__ void k_pcg_step(T* x, T* r, const T* p, const T* Ap, const double* sc
   x[i] = T(1) * x[i] + a * p[i];
   r[i] = T(1) * r[i] + (-a) * Ap[i];
 }
-// p = z + (rz_new / rz) p, only when pAp > 0
+// p = z + beta p, only when pAp > 0: beta = rz_new / rz, or with ixz >= 0 (flexible CG, the slot holding
+// r_new . z_old) beta = (rz_new - r_new . z_old) / rz
 template <typename T>
-__global__ void k_pcg_dir(T* p, const T* z, const double* sc, int irz, int irzn, int ipap, int64_t n) {
+__global__ void k_pcg_dir(T* p, const T* z, const double* sc, int irz, int irzn, int ipap, int ixz, int64_t n) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n || !(sc[ipap] > 0.0)) return;
-  const T b = static_cast<T>(sc[irzn] / sc[irz]);
+  const T b = static_cast<T>((sc[irzn] - (ixz >= 0 ? sc[ixz] : 0.0)) / sc[irz]);
   p[i] = T(1) * z[i] + b * p[i];
 }
 // z += sum_i y_i Z_i with y = Minv c, c_i = sc[ic + i] (r <= 16 directions of length n, Minv r x r)
@@ -204,8 +205,8 @@ void pcg_step(T* x, T* r, const T* p, const T* Ap, double* work, int irz, int ip
   LDDMM_LAUNCH_CHECK();
 }
 template <typename T>
-void pcg_dir(T* p, const T* z, double* work, int irz, int irzn, int ipap, int64_t n, hipStream_t s) {
-  k_pcg_dir<T><<<ceil_div(n, 256), 256, 0, s>>>(p, z, work + kRBlocks, irz, irzn, ipap, n);
+void pcg_dir(T* p, const T* z, double* work, int irz, int irzn, int ipap, int64_t n, hipStream_t s, int ixz) {
+  k_pcg_dir<T><<<ceil_div(n, 256), 256, 0, s>>>(p, z, work + kRBlocks, irz, irzn, ipap, ixz, n);
   LDDMM_LAUNCH_CHECK();
 }
 template <typename T>
@@ -216,8 +217,8 @@ void lowrank_add(T* z, const T* Z, const double* Minv, double* work, int ic, int
 template void pcg_step<float>(float*, float*, const float*, const float*, double*, int, int, int64_t, hipStream_t);
 template void pcg_step<double>(double*, double*, const double*, const double*, double*, int, int, int64_t,
                                hipStream_t);
-template void pcg_dir<float>(float*, const float*, double*, int, int, int, int64_t, hipStream_t);
-template void pcg_dir<double>(double*, const double*, double*, int, int, int, int64_t, hipStream_t);
+template void pcg_dir<float>(float*, const float*, double*, int, int, int, int64_t, hipStream_t, int);
+template void pcg_dir<double>(double*, const double*, double*, int, int, int, int64_t, hipStream_t, int);
 template void lowrank_add<float>(float*, const float*, const double*, double*, int, int, int64_t, hipStream_t);
 template void lowrank_add<double>(double*, const double*, const double*, double*, int, int, int64_t, hipStream_t);
 

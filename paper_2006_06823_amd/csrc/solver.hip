@@ -52,7 +52,7 @@ namespace lddmm {
 template <typename T>
 class Solver final : public SolverBase {
  public:
-  Solver(const lddmm_bl_params& p, hipStream_t s) : st_(s) {
+  Solver(const lddmm_bl_params& p, hipStream_t s) : st_(s), params_(p) {
     dim_ = p.dim;
     if (dim_ != 2 && dim_ != 3) throw ArgError("dim must be 2 or 3");
     if (p.nt < 1) throw ArgError("nt must be >= 1");
@@ -112,6 +112,7 @@ class Solver final : public SolverBase {
     prefilter(cI0_.get(), 1, d_, st_);
     have_images_ = true;
     state_valid_ = false;
+    coarse_.reset();  // the coarse level restricts these images
   }
 
   void state_solve(const void* v, void* m1, double* E3) override {
@@ -1111,6 +1112,12 @@ class Solver final : public SolverBase {
   friend int gn_solve_batched_impl(std::vector<Solver<U>*>& subs, const lddmm_bl_gn_opts& o,
                                    void* const* v_user, lddmm_bl_gn_report* reps, hipStream_t st);
   hipGraphExec_t mv_exec_ = nullptr;
+  lddmm_bl_params params_{};
+  // two-level preconditioner: the coarse problem and its band vectors (restricted residual and velocity,
+  // inner solution and inner PCG scratch)
+  std::unique_ptr<Solver<T>> coarse_;
+  DevBuf<T> cb_, cx_, cr_, cz_, cv_;
+  int kf3_[3] = {1, 1, 1}, kc3_[3] = {1, 1, 1}, m3_[3] = {1, 1, 1};
   DevBuf<double> Lsym_, Linv_, work_;
   std::unique_ptr<double, PinnedFree> host_;
   DevBuf<T> I0_, I1_, cI0_;
@@ -1152,6 +1159,70 @@ class Solver final : public SolverBase {
   }
   hipStream_t stream() const { return st_; }
   void synchronize() { sync(); }
+
+  // x = PCG from 0 on H x = b with L~^-1 for a fixed number of iterations, every scalar on the device (no
+  // host synchronisation); r, z: scratch band vectors.  A direction with p.Hp <= 0 leaves x unchanged.
+  void inner_pcg(const T* b, T* x, T* r, T* z, int iters) {
+    const int64_t n = vec_len();
+    double* wk = work_.get();
+    T* const pv = dvbl_.get();
+    T* const Apv = hbl_.get();
+    zero(x, n, st_);
+    copy(r, b, n);
+    precond_internal(r, z);
+    copy(pv, z, n);
+    int irz = 2, irzn = 3;
+    reduce_launch<T>(RedKind::Dot, r, z, n, wk, irz, st_);
+    for (int it = 0; it < iters; ++it) {
+      matvec_graph();
+      reduce_launch<T>(RedKind::Dot, pv, Apv, n, wk, 0, st_);
+      pcg_step<T>(x, r, pv, Apv, wk, irz, 0, n, st_);
+      precond_internal(r, z);
+      reduce_launch<T>(RedKind::Dot, r, z, n, wk, irzn, st_);
+      pcg_dir<T>(pv, z, wk, irz, irzn, 0, n, st_);
+      std::swap(irz, irzn);
+    }
+  }
+  // the coarse level of the two-level preconditioner: grid N / 2, band 2 floor(K / 4), images restricted
+  // by 2^d block means
+  void ensure_coarse() {
+    if (coarse_) return;
+    lddmm_bl_params cp = params_;
+    for (int j = 0; j < dim_; ++j) {
+      if (params_.n[j] % 2) throw ArgError("two-level preconditioner: grid sizes must be even");
+      cp.n[j] = params_.n[j] / 2;
+      cp.k[j] = 2 * (params_.k[j] / 4);
+      if (cp.k[j] < 2) throw ArgError("two-level preconditioner: band too small for a coarse level");
+    }
+    coarse_ = std::make_unique<Solver<T>>(cp, st_);
+    Solver<T>& c = *coarse_;
+    DevBuf<T> a(c.d_.P), b(c.d_.P);
+    restrict_grid<T>(a.get(), I0_.get(), d_, st_);
+    restrict_grid<T>(b.get(), I1_.get(), d_, st_);
+    c.set_images(a.get(), b.get());
+    const int64_t nc = c.vec_len();
+    cb_.alloc(nc), cx_.alloc(nc), cr_.alloc(nc), cz_.alloc(nc), cv_.alloc(nc);
+    for (int j = 0; j < 3; ++j) {
+      kf3_[j] = d_.k[j];
+      kc3_[j] = c.d_.k[j];
+      m3_[j] = d_.k[j] > 1 ? c.d_.k[j] - 1 : 1;
+    }
+    sync();
+  }
+  // re-linearise the coarse level at the restricted velocity R v
+  void coarse_at(const T* v) {
+    band_copy<T>(cv_.get(), kc3_, v, kf3_, m3_, 3, false, st_);
+    coarse_->set_velocity_internal(cv_.get());
+    double e[3];
+    coarse_->state_internal(e);
+  }
+  // M^-1 r = L~^-1 r with the coarse band's slots replaced by the inner solve of C x = R r
+  void two_level_precond(const T* r, T* z, int inner) {
+    band_copy<T>(cb_.get(), kc3_, r, kf3_, m3_, 3, false, st_);
+    coarse_->inner_pcg(cb_.get(), cx_.get(), cr_.get(), cz_.get(), inner);
+    precond_internal(r, z);
+    band_copy<T>(z, kf3_, cx_.get(), kc3_, m3_, 3, true, st_);
+  }
 };
 
 // ---------------------------------------------------------------- field access
@@ -1266,9 +1337,14 @@ int Solver<T>::gn_solve(const lddmm_bl_gn_opts& o, void* v_user, const void* Zu,
   if (!have_images_) throw StateError("set_images must precede gn_solve");
   if (o.max_gn < 0 || o.max_pcg < 1) throw ArgError("max_gn >= 0 and max_pcg >= 1 required");
   if (Zu && (r < 1 || r > 16)) throw ArgError("preconditioner rank must be 1..16");
+  const bool ml = o.ml_inner > 0;
+  if (ml && Zu) throw ArgError("the low-rank and the two-level preconditioners exclude each other");
+  if (o.ml_inner < 0 || o.ml_inner > 1000) throw ArgError("ml_inner must be in 0..1000");
+  if (ml) ensure_coarse();
   const auto t0 = std::chrono::steady_clock::now();
   const int64_t n = vec_len();
-  DevBuf<T> v(n), g(n), x(n), rr(n), z(n), vt(n), Z, HZ;
+  DevBuf<T> v(n), g(n), x(n), rr(n), z(n), vt(n), Z, HZ, zold;
+  if (ml) zold.alloc(n);
   std::vector<double> ZHZinv;
   int status = LDDMM_BL_OK;
   lddmm_bl_gn_report R{};
@@ -1296,14 +1372,15 @@ int Solver<T>::gn_solve(const lddmm_bl_gn_opts& o, void* v_user, const void* Zu,
       user_to_internal(Z.get() + i * n, static_cast<const T*>(Zu) + (int64_t)i * (n / 3) * dim_);
     ZHZinv.assign(r * r, 0.0);
   }
-  // device result slots of the PCG: p.Hp, r.r, r.z (ping-pong), Z^T r
-  enum { kPAP = 0, kRN2 = 1, kRZ0 = 2, kZC = 8 };
+  // device result slots of the PCG: p.Hp, r.r, r.z (ping-pong), r.z_old (flexible CG), Z^T r
+  enum { kPAP = 0, kRN2 = 1, kRZ0 = 2, kRZX = 4, kZC = 8 };
   DevBuf<double> Minv;
   if (twolevel) Minv.alloc(r * r);
   double* const wk = work_.get();
   const double* const hs = host_.get();
   // M^-1 r = L~^-1 r (+ Z (Z^T H Z)^-1 Z^T r), every scalar on the device
   auto precond = [&](const T* rin, T* zout) {
+    if (ml) return two_level_precond(rin, zout, o.ml_inner);
     precond_internal(rin, zout);
     if (!twolevel) return;
     for (int i = 0; i < r; ++i) reduce_launch<T>(RedKind::Dot, Z.get() + i * n, rin, n, wk, kZC + i, stream());
@@ -1371,6 +1448,7 @@ int Solver<T>::gn_solve(const lddmm_bl_gn_opts& o, void* v_user, const void* Zu,
       LDDMM_HIP(hipMemcpyAsync(Minv.get(), ZHZinv.data(), r * r * sizeof(double), hipMemcpyHostToDevice, stream()));
       synchronize();
     }
+    if (ml) coarse_at(v.get());
     const double gnorm = std::sqrt(dot_internal(g.get(), g.get()));
     const double eta = gnorm0 > 0 ? std::min(0.5, std::sqrt(gnorm / gnorm0)) : 0.5;
     const double tol = eta * gnorm;
@@ -1395,10 +1473,12 @@ int Solver<T>::gn_solve(const lddmm_bl_gn_opts& o, void* v_user, const void* Zu,
       ++R.hess_matvecs;
       reduce_launch<T>(RedKind::Dot, pv, Apv, n, wk, kPAP, stream());
       pcg_step<T>(x.get(), rr.get(), pv, Apv, wk, irz, kPAP, n, stream());
+      if (ml) copy_internal(zold.get(), z.get());
       precond(rr.get(), z.get());
       reduce_launch<T>(RedKind::Dot, rr.get(), z.get(), n, wk, irzn, stream());
+      if (ml) reduce_launch<T>(RedKind::Dot, rr.get(), zold.get(), n, wk, kRZX, stream());
       reduce_launch<T>(RedKind::Dot, rr.get(), rr.get(), n, wk, kRN2, stream());
-      pcg_dir<T>(pv, z.get(), wk, irz, irzn, kPAP, n, stream());
+      pcg_dir<T>(pv, z.get(), wk, irz, irzn, kPAP, n, stream(), ml ? kRZX : -1);
       fetch_async(wk, host_.get(), trace_ ? 4 : 2, stream());
       synchronize();
       const double pAp = hs[kPAP];

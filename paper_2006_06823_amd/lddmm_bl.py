@@ -59,6 +59,7 @@ class GNOpts(ctypes.Structure):
     _fields_ = [
         ("max_gn", ctypes.c_int32), ("max_pcg", ctypes.c_int32), ("grad_rtol", ctypes.c_double),
         ("grad_ref_inf", ctypes.c_double), ("fixed_iters", ctypes.c_int32), ("energy_target", ctypes.c_double),
+        ("ml_inner", ctypes.c_int32),
     ]
 
 
@@ -200,7 +201,7 @@ def gn_solve_batched(problems, I0s, I1s, vs, max_gn=10, max_pcg=5, grad_rtol=1e-
             raise TypeError("batched tensors must be contiguous float32 ROCm tensors")
     params = (Params * B)(*[make_params(p) for p in problems])
     arr = lambda ts: (ctypes.c_void_p * B)(*[t.data_ptr() for t in ts])
-    opts = GNOpts(max_gn, max_pcg, grad_rtol, grad_ref_inf, 1 if fixed_iters else 0, 0.0)
+    opts = GNOpts(max_gn, max_pcg, grad_rtol, grad_ref_inf, 1 if fixed_iters else 0, 0.0, 0)
     reps = (GNReport * B)()
     stream = torch.cuda.Stream(device=dev)
     stream.wait_stream(torch.cuda.current_stream(dev))
@@ -309,12 +310,14 @@ class Context:
         return out
 
     def gn_solve(self, v: torch.Tensor, max_gn=10, max_pcg=5, grad_rtol=1e-3, grad_ref_inf=0.0,
-                 fixed_iters=False, Z: Optional[torch.Tensor] = None, energy_target=0.0):
+                 fixed_iters=False, Z: Optional[torch.Tensor] = None, energy_target=0.0, ml_inner=0):
         """Gauss-Newton-Krylov in place on v; returns (status, report dict).
 
-        energy_target > 0 also stops the run once the objective is at or below it."""
+        energy_target > 0 also stops the run once the objective is at or below it; ml_inner > 0 selects the
+        two-level spectral preconditioner with that many inner coarse PCG iterations."""
         self._arg(v, self._bl_shape(self.dim), "v")
-        o = GNOpts(max_gn, max_pcg, grad_rtol, grad_ref_inf, 1 if fixed_iters else 0, float(energy_target))
+        o = GNOpts(max_gn, max_pcg, grad_rtol, grad_ref_inf, 1 if fixed_iters else 0, float(energy_target),
+                   int(ml_inner))
         rep = GNReport()
         r = 0
         if Z is not None:

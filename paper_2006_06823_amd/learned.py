@@ -128,9 +128,9 @@ class Registrar:
         _, ginf = self.ctx.adjoint_solve()
         return ginf, E[0]
 
-    def solve(self, v, opts: SolveOpts, gref: float, Z=None, energy_target=0.0):
+    def solve(self, v, opts: SolveOpts, gref: float, Z=None, energy_target=0.0, ml_inner=0):
         st, rep = self.ctx.gn_solve(v, max_gn=opts.max_gn, max_pcg=opts.max_pcg, grad_rtol=opts.grad_rtol,
-                                    grad_ref_inf=gref, Z=Z, energy_target=energy_target)
+                                    grad_ref_inf=gref, Z=Z, energy_target=energy_target, ml_inner=ml_inner)
         rep["status"] = int(st)
         return rep
 
@@ -246,8 +246,9 @@ def predict(net, reg: Registrar, x1):
     return net.velocity(out, reg.band)[0].contiguous()
 
 
-def compare(net, reg: Registrar, seeds, stream: PairStream, opts: SolveOpts, log=print, with_Z=True):
-    """Plain vs learned warm start (and warm start + two-level preconditioner) on held-out pairs."""
+def compare(net, reg: Registrar, seeds, stream: PairStream, opts: SolveOpts, log=print, with_Z=True, ml_inner=0):
+    """Plain vs learned warm start (and warm start + low-rank preconditioner) on held-out pairs; with
+    ml_inner > 0 also the plain start with the two-level spectral preconditioner ("plain_ml")."""
     torch = reg.torch
     rows = []
     for i, (seed, I0, I1) in enumerate(stream.pairs(seeds)):
@@ -259,6 +260,12 @@ def compare(net, reg: Registrar, seeds, stream: PairStream, opts: SolveOpts, log
         rep = reg.solve(v, opts, gref)
         row["plain"] = rep
         vstar = v.clone()
+        if ml_inner > 0:
+            vm = reg.zero_velocity()
+            rep = reg.solve(vm, opts, gref, ml_inner=ml_inner)
+            rep["seconds_total"] = rep["seconds"]
+            rep["reached_plain_E"] = bool(rep["E"] <= row["plain"]["E"])
+            row["plain_ml"] = rep
         zero = torch.zeros(net.out_shape(1), dtype=torch.float32, device=reg.device)
         efull, _ = net.loss(zero, vstar[None].contiguous(), reg.alpha, reg.s, want_grad=False)
         # learned
@@ -319,7 +326,8 @@ def summarize(rows, with_Z=True):
         return float(np.mean([r[name][key] for r in rows]))
     s = {"pairs": len(rows), "fallbacks": int(sum(r["fallback"] for r in rows)),
          "pred_vnorm_rel_mean": float(np.mean([r["pred_vnorm_rel"] for r in rows]))}
-    names = ["plain", "learned", "learned_E"] + (["learned_Z"] if with_Z else [])
+    names = ["plain", "learned", "learned_E"] + (["learned_Z"] if with_Z else []) + \
+        (["plain_ml"] if rows and "plain_ml" in rows[0] else [])
     for nme in names:
         key_t = "seconds" if nme == "plain" else "seconds_total"
         tot_t = float(np.sum([r[nme][key_t] for r in rows]))
