@@ -35,8 +35,9 @@ def _create(**kw):
 
 
 @pytest.mark.parametrize("bad", [
-    dict(dim=4), dict(nt=0), dict(variant=2), dict(alpha=0.0), dict(s=0), dict(sigma2=-1.0),
+    dict(dim=4), dict(nt=0), dict(variant=4), dict(variant=0), dict(alpha=0.0), dict(s=0), dict(sigma2=-1.0),
     dict(k=(7, 8, 8)), dict(n=(20, 20, 28), k=(16, 8, 8)), dict(k=(0, 8, 8)), dict(precision=7),
+    dict(integrator=2), dict(variant=1, integrator=1), dict(variant=2, integrator=1),
 ])
 def test_invalid_parameters_rejected(bad):
     assert _create(**bad) == E_ARG
@@ -44,6 +45,8 @@ def test_invalid_parameters_rejected(bad):
 
 def test_valid_parameters_accepted():
     assert _create() == 0
+    assert _create(variant=2) == 0
+    assert _create(variant=3, integrator=1) == 0
 
 
 def _ctx(variant=1):
