@@ -39,26 +39,28 @@ def grad_inf(g, prob: Problem) -> float:
     return float(sp.include(g, prob.N).abs().max())
 
 
-def pcg(matvec, b, precond, tol: float, maxit: int, fixed: bool = False, flexible: bool = False):
+def pcg(matvec, b, precond, tol: float, maxit: int, fixed: bool = False, flexible: bool = False, dot=None):
     """Preconditioned CG from 0 for A x = b.  Returns (x, iterations, flag, rnorm).
 
     flag: 0 converged/cap, 3 non-positive curvature.  flexible: the direction update
     beta = r_new . (z_new - z_old) / r_old . z_old (flexible CG, for a preconditioner that is itself an
-    iteration); it equals the PCG update when the preconditioner is a fixed SPD operator.
+    iteration); it equals the PCG update when the preconditioner is a fixed SPD operator.  dot: the inner
+    product (default: the l^2 product of the coefficients).
     """
+    ip = dot if dot is not None else sp.l2
     x = torch.zeros_like(b)
     r = b.clone()
     z = precond(r)
     p = z.clone()
-    rz = float(sp.l2(r, z))
+    rz = float(ip(r, z))
     it = 0
     flag = 0
     for it in range(maxit):
-        rn = math.sqrt(float(sp.l2(r, r)))
+        rn = math.sqrt(float(ip(r, r)))
         if not fixed and rn <= tol:
             return x, it, flag, rn
         Ap = matvec(p)
-        pAp = float(sp.l2(p, Ap))
+        pAp = float(ip(p, Ap))
         if pAp <= 0.0:
             flag = 3
             if it == 0:
@@ -69,11 +71,11 @@ def pcg(matvec, b, precond, tol: float, maxit: int, fixed: bool = False, flexibl
         r = r - a * Ap
         z_old = z
         z = precond(r)
-        rz_new = float(sp.l2(r, z))
-        num = rz_new - float(sp.l2(r, z_old)) if flexible else rz_new
+        rz_new = float(ip(r, z))
+        num = rz_new - float(ip(r, z_old)) if flexible else rz_new
         p = z + (num / rz) * p
         rz = rz_new
-    return x, maxit, flag, math.sqrt(float(sp.l2(r, r)))
+    return x, maxit, flag, math.sqrt(float(ip(r, r)))
 
 
 @dataclass
@@ -104,6 +106,7 @@ def gauss_newton(model, v0, max_gn=10, max_pcg=5, grad_rtol=1e-3, grad_ref_inf=0
     if precond is None:
         precond = lambda r: sp.apply_L(r, p.d, p.alpha, p.s, inverse=True)
     flexible = bool(getattr(precond, "flexible", False))
+    ip = getattr(model, "inner", sp.l2)   # a non-stationary model's node-field inner product
     v = sp.as_t(v0).clone()
     model.setup(v)
     model.state()
@@ -113,17 +116,17 @@ def gauss_newton(model, v0, max_gn=10, max_pcg=5, grad_rtol=1e-3, grad_ref_inf=0
     g = model.gradient()
     ginf = grad_inf(g, p)
     ref = grad_ref_inf if grad_ref_inf > 0 else ginf
-    gnorm0 = math.sqrt(float(sp.l2(g, g)))
+    gnorm0 = math.sqrt(float(ip(g, g)))
     for k in range(max_gn):
         if not fixed_iters and ginf <= grad_rtol * ref:
             break
-        gnorm = math.sqrt(float(sp.l2(g, g)))
+        gnorm = math.sqrt(float(ip(g, g)))
         eta = min(0.5, math.sqrt(gnorm / gnorm0)) if gnorm0 > 0 else 0.5
         if hasattr(precond, "set_velocity"):
             precond.set_velocity(v)
-        dv, its, flag, _ = pcg(model.hess_matvec, -g, precond, eta * gnorm, max_pcg, fixed_iters, flexible)
+        dv, its, flag, _ = pcg(model.hess_matvec, -g, precond, eta * gnorm, max_pcg, fixed_iters, flexible, ip)
         rep.pcg_iters_total += its
-        gd = float(sp.l2(g, dv))
+        gd = float(ip(g, dv))
         eps = 1.0
         accepted = False
         bt0 = rep.backtracks
