@@ -197,6 +197,8 @@ def parse():
     ap.add_argument("--rk4", action="store_true",
                     help="deformation-state variant integrated by the explicit RK4 comparator (Eulerian form) "
                          "instead of SL-RK2; use with --variant 3 and its nt (25-50)")
+    ap.add_argument("--nonstationary", action="store_true",
+                    help="a velocity per time node (variants 1 and 3): the matvec of the (nt + 1)-node parameter")
     ap.add_argument("--size", type=int, nargs=3, default=(128, 128, 128))
     ap.add_argument("--band", type=int, nargs=3, default=(32, 32, 32))
     ap.add_argument("--nt", type=int, default=10)
@@ -254,7 +256,8 @@ def main():
 
     I0, I1 = syn.phantom_pair_3d(N, seed=1, max_disp_vox=8.0)
     integ = L.EULER_RK4 if args.rk4 else L.SL_RK2
-    ctx = L.Context(L.Problem(N, K, nt=Nt, variant=variant, precision=L.FP32, integrator=integ))
+    ctx = L.Context(L.Problem(N, K, nt=Nt, variant=variant, precision=L.FP32, integrator=integ,
+                              nonstationary=args.nonstationary))
     g = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device=dev)
     ctx.set_images(g(I0), g(I1))
     # random band-limited velocity scaled to 8 voxels maximum displacement per unit time
@@ -264,6 +267,9 @@ def main():
     vmax = float((vg * scale).abs().max())
     v = g(vc * (8.0 / vmax))
     dv = g(syn.random_bl_coefficients(3, K, seed=3))
+    if args.nonstationary:   # the same fields at every node: a time-constant velocity in the (nt + 1)-node form
+        v = v.unsqueeze(0).repeat(Nt + 1, 1, 1, 1, 1).contiguous()
+        dv = dv.unsqueeze(0).repeat(Nt + 1, 1, 1, 1, 1).contiguous()
     E, _ = ctx.state_solve(v)
     out = torch.empty_like(dv)
     stream = torch.cuda.current_stream(dev)
@@ -326,7 +332,7 @@ def main():
         learned = learned_leg(args.learned_pairs)
 
     cpu = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not args.nonstationary:
         cpu = cpu_baseline(variant, N, K, Nt, I0, I1, (vc * (8.0 / vmax)), syn.random_bl_coefficients(3, K, seed=3),
                            rk4=args.rk4)
 
@@ -338,9 +344,10 @@ def main():
         "config": {"workload": f"{VARIANT_NAMES[args.variant]} BL PDE-LDDMM "
                                f"Gauss-Newton Hessian matvec, grid {N[0]}x{N[1]}x{N[2]}, band {K[0]}x{K[1]}x{K[2]}x3, "
                                f"Nt={Nt}, {'explicit RK4 (Eulerian)' if args.rk4 else 'SL-RK2'}, "
+                               f"{'non-stationary velocity, ' if args.nonstationary else ''}"
                                f"FP32 with FP64 reductions",
                    "grid": list(N), "band": list(K), "nt": Nt, "variant": args.variant,
-                   "integrator": "rk4" if args.rk4 else "sl-rk2",
+                   "integrator": "rk4" if args.rk4 else "sl-rk2", "nonstationary": bool(args.nonstationary),
                    "alpha": 0.0025, "s": 2, "sigma2": 1.0},
         "roofline": roofline,
         "cpu_baseline": cpu,

@@ -112,6 +112,15 @@ typedef struct {
   double sigma2;          /* data weight 1/sigma^2, eq. BLEnergy */
   int32_t precision;      /* lddmm_bl_precision */
   int32_t integrator;     /* lddmm_bl_integrator (0: SL-RK2) */
+  int32_t nonstationary;  /* 1: a velocity per time node (Section 1.3; the NSt rows of Tables 3-4) for the
+                             image-transport and deformation-state variants with SL-RK2 (LDDMM_BL_E_ARG
+                             otherwise).  Velocity-like arrays (v, gradient, dv, H dv, gn_solve's v) are then
+                             [nt + 1][d][K..]; the regulariser integrates over the nodes by the trapezoid rule;
+                             gradient and Hessian are node fields (the stationary integrands node by node), and
+                             PCG and the Armijo test use the node-field product sum_n w_n <a_n, b_n>.  A step's
+                             characteristics take the arrival node's velocity at the arrival point and the
+                             departure node's at the predicted departure point.  Excludes the batched solve and
+                             the low-rank and two-level preconditioners.  0: stationary. */
 } lddmm_bl_params;
 
 typedef struct {

@@ -180,6 +180,7 @@ lddmm_bl_status lddmm_bl_gn_solve_batched(const lddmm_bl_params* per_subject, in
     std::vector<lddmm::SolverBase*> subs;
     for (int i = 0; i < count; ++i) {
       if (per_subject[i].precision == LDDMM_BL_FP64) throw lddmm::ArgError("batched subjects must be float");
+      if (per_subject[i].nonstationary) throw lddmm::ArgError("batched subjects must have stationary velocities");
       owned.push_back(lddmm::make_solver(per_subject[i], static_cast<hipStream_t>(hip_stream)));
       owned.back()->set_images(I0[i], I1[i]);
       subs.push_back(owned.back().get());

@@ -167,12 +167,13 @@ __global__ __launch_bounds__(256) void k_expand(PlaneExpandArgs a) {
 template <int MODE>
 struct RedIn {
   Rsrc in, e, divv, G;
-  unsigned P;
-  __device__ __forceinline__ RedIn(const PlaneReduceArgs& a) : P((unsigned)a.P) {
+  unsigned P, en;
+  __device__ __forceinline__ RedIn(const PlaneReduceArgs& a) : P((unsigned)a.P), en((unsigned)a.e_node) {
     if constexpr (MODE == kRedPlain) {
       in = rsrc(a.in, (int64_t)a.nf * a.P);
     } else {
-      const int ne = (MODE == kRedV1Products) ? 1 : 3;
+      const int64_t ne = (MODE == kRedV1Products) ? 1 : (MODE == kRedV1Source || MODE == kRedV3Source) && a.e_node
+                         ? (int64_t)(MODE == kRedV1Source ? a.nf : a.nf / 3) * 3 : 3;
       const int ng = MODE == kRedV1Products ? 3 : MODE == kRedV3Products ? 9
                    : MODE == kRedV1Source   ? 3 * a.nf : 3 * a.nf;
       e = rsrc(a.e, (int64_t)ne * a.P);
@@ -191,14 +192,14 @@ struct RedIn {
       const unsigned j = f - 3;
       return bload(e, p) * bload(G, j * P + p) + bload(e, P + p) * bload(G, (3 + j) * P + p) +
              bload(e, 2 * P + p) * bload(G, (6 + j) * P + p);
-    } else if constexpr (MODE == kRedV1Source) {  // node f: -G_f . dv
-      const unsigned g = 3u * f * P;
-      return -(bload(G, g + p) * bload(e, p) + bload(G, g + P + p) * bload(e, P + p) +
-               bload(G, g + 2 * P + p) * bload(e, 2 * P + p));
-    } else {  // kRedV3Source, field f = 3 n + c: dv_c - sum_j d_j u_c dv_j at node n
-      const unsigned n = f / 3, c = f - 3 * n, g = (9 * n + 3 * c) * P;
-      return bload(e, c * P + p) - (bload(G, g + p) * bload(e, p) + bload(G, g + P + p) * bload(e, P + p) +
-                                    bload(G, g + 2 * P + p) * bload(e, 2 * P + p));
+    } else if constexpr (MODE == kRedV1Source) {  // node f: -G_f . dv_f
+      const unsigned g = 3u * f * P, q = f * en + p;
+      return -(bload(G, g + p) * bload(e, q) + bload(G, g + P + p) * bload(e, P + q) +
+               bload(G, g + 2 * P + p) * bload(e, 2 * P + q));
+    } else {  // kRedV3Source, field f = 3 n + c: dv_c - sum_j d_j u_c dv_j at node n (dv of node n)
+      const unsigned n = f / 3, c = f - 3 * n, g = (9 * n + 3 * c) * P, q = n * en + p;
+      return bload(e, c * P + q) - (bload(G, g + p) * bload(e, q) + bload(G, g + P + p) * bload(e, P + q) +
+                                    bload(G, g + 2 * P + p) * bload(e, 2 * P + q));
     }
   }
 };

@@ -68,6 +68,7 @@ struct PlaneReduceArgs {
   float* part;        // [nf][n0][k1][k2]
   int mode, nf, n0, n1, n2, k1, k2;
   int64_t P;          // grid points per field
+  int64_t e_node;     // sources: offset of node n's dv (0: one dv for every node; 3 P: a dv per node)
 };
 // first-axis stages (see dft_planes.hip): F finishes nin projections, P forms nout plane-band arrays
 struct Axis0Out {

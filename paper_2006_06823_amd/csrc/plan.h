@@ -146,10 +146,10 @@ class Plan {
   }
   // reduction of nf grid values (plain fields or products, see PlaneReduceArgs) into part(0..nf)
   void reduce(int mode, int nf, const float* in, const float* e = nullptr, const float* divv = nullptr,
-              const float* G = nullptr) {
+              const float* G = nullptr, int64_t e_node = 0) {
     reserve_parts(nf);
     PlaneReduceArgs a{};
-    a.in = in, a.e = e, a.divv = divv, a.G = G;
+    a.in = in, a.e = e, a.divv = divv, a.G = G, a.e_node = e_node;
     a.p1t = mat(1, kProjT), a.p2t = mat(2, kProjT);
     a.part = part_.get();
     a.mode = mode, a.nf = nf, a.n0 = d_.n[0], a.n1 = d_.n[1], a.n2 = d_.n[2], a.k1 = d_.k[1], a.k2 = d_.k[2];

@@ -64,6 +64,10 @@ class Solver final : public SolverBase {
     rk_ = p.integrator == LDDMM_BL_EULER_RK4;
     if (rk_ && p.variant != LDDMM_BL_DEFORMATION_STATE)
       throw ArgError("the explicit RK4 comparator integrates the deformation-state variant only");
+    if (p.nonstationary != 0 && p.nonstationary != 1) throw ArgError("nonstationary must be 0 or 1");
+    ns_ = p.nonstationary == 1;
+    if (ns_ && (rk_ || p.variant == LDDMM_BL_STATE_EQUATION))
+      throw ArgError("non-stationary velocities: image-transport and deformation-state variants with SL-RK2 only");
     const int off = 3 - dim_;
     d_.n[0] = d_.n[1] = d_.n[2] = 1;
     d_.k[0] = d_.k[1] = d_.k[2] = 1;
@@ -234,17 +238,35 @@ class Solver final : public SolverBase {
     I0_.alloc(P);
     I1_.alloc(P);
     cI0_.alloc(P);
-    vbl_.alloc(3 * Q);
-    dvbl_.alloc(3 * Q);
-    gbl_.alloc(3 * Q);
-    hbl_.alloc(3 * Q);
+    // velocity-like band vectors hold one node (stationary) or nt + 1 nodes (non-stationary); so do the
+    // per-node divergence fields, and the departure displacements one per step
+    const int64_t VQ = (ns_ ? nn : 1) * 3 * Q, nsteps = ns_ ? nt_ : 1, nnodes = ns_ ? nn : 1;
+    vbl_.alloc(VQ);
+    dvbl_.alloc(VQ);
+    gbl_.alloc(VQ);
+    hbl_.alloc(VQ);
     tmpbl_.alloc(3 * Q);
     blA_.alloc(kMaxFields * Q);
-    acc_.alloc(3 * Q);
+    acc_.alloc(VQ);
     vg_.alloc(3 * P);
-    divv_.alloc(P);
-    Xb_.alloc(3 * P);
-    Xf_.alloc(3 * P);
+    divv_.alloc(nnodes * P);
+    Xb_.alloc(nsteps * 3 * P);
+    Xf_.alloc(nsteps * 3 * P);
+    if (ns_) {
+      // node weights of the trapezoid rule per element: the node-field inner product and regulariser
+      std::vector<double> wv(VQ), wl(VQ), Lh(Q);
+      LDDMM_HIP(hipMemcpy(Lh.data(), Lsym_.get(), Q * sizeof(double), hipMemcpyDeviceToHost));
+      for (int64_t i = 0; i < VQ; ++i) {
+        const int64_t n = i / (3 * Q);
+        const double w = (n == 0 || n == nt_) ? 0.5 / nt_ : 1.0 / nt_;
+        wv[i] = w;
+        wl[i] = w * Lh[i % Q];
+      }
+      wvec_.alloc(VQ);
+      wLsym_.alloc(VQ);
+      LDDMM_HIP(hipMemcpy(wvec_.get(), wv.data(), VQ * sizeof(double), hipMemcpyHostToDevice));
+      LDDMM_HIP(hipMemcpy(wLsym_.get(), wl.data(), VQ * sizeof(double), hipMemcpyHostToDevice));
+    }
     scratch_.alloc(13 * P);  // 9P-field transforms + 4P staging
     inc_.alloc(nn * 3 * Q);
     incadj_.alloc(nn * 3 * Q);
@@ -252,8 +274,8 @@ class Solver final : public SolverBase {
     LDDMM_HIP(hipMemset(inc_.get(), 0, inc_.size() * sizeof(T)));
     fsrc_.alloc(nn * 3 * Q);
     // product grid: div v, the state's gradient fields, the expanded operand and the products
-    divvs_.alloc(Ps);
-    dvs_.alloc(3 * Ps);
+    divvs_.alloc(nnodes * Ps);
+    dvs_.alloc(nnodes * 3 * Ps);
     es_.alloc(std::max<int64_t>(3, variant_ == LDDMM_BL_STATE_EQUATION ? std::min(nn, (int64_t)kMaxFields) : 3) * Ps);
     prods_.alloc(std::max<int64_t>(kMaxFields, 3 * nn) * Ps);
     if (variant_ != LDDMM_BL_DEFORMATION_STATE) {
@@ -346,6 +368,22 @@ class Solver final : public SolverBase {
   }
   T* S(int i) { return scratch_.get() + (int64_t)i * d_.P; }
   T* S9() { return scratch_.get(); }
+  // per-node / per-step views (the one stationary array when the velocity is stationary)
+  int64_t VQ() const { return (ns_ ? nt_ + 1 : 1) * 3 * d_.Q; }
+  T* vnode(int n) { return vbl_.get() + (ns_ ? (int64_t)n * 3 * d_.Q : 0); }
+  T* XbN(int n) { return Xb_.get() + (ns_ ? (int64_t)n * 3 * d_.P : 0); }
+  T* XfN(int n) { return Xf_.get() + (ns_ ? (int64_t)n * 3 * d_.P : 0); }
+  T* divvN(int n) { return divv_.get() + (ns_ ? (int64_t)n * d_.P : 0); }
+  T* divvsN(int n) { return divvs_.get() + (ns_ ? (int64_t)n * ds_.P : 0); }
+  T* dvsN(int n) { return dvs_.get() + (ns_ ? (int64_t)n * 3 * ds_.P : 0); }
+  // the dv samples on the product grid (per node when non-stationary)
+  void dv_on_product_grid(const T* dv) {
+    const int nodes = ns_ ? nt_ + 1 : 1;
+    for (int n0 = 0; n0 < nodes; n0 += 4) {
+      const int m = std::min(4, nodes - n0);
+      sm_.iota_kind(dv + (int64_t)n0 * 3 * d_.Q, dvs_.get() + (int64_t)n0 * 3 * ds_.P, 3 * m, kPlain);
+    }
+  }
   T* Ps(int i) { return prods_.get() + (int64_t)i * ds_.P; }
   const T* m1_ptr() const {
     return variant_ == LDDMM_BL_IMAGE_TRANSPORT ? m_.get() + (int64_t)nt_ * d_.P : m1_.get();
@@ -360,28 +398,38 @@ class Solver final : public SolverBase {
       full_.iota_kind(bl + (int64_t)f0 * d_.Q, grid + (int64_t)f0 * d_.P, std::min(kMaxFields, nf - f0), kPlain);
   }
 
-  // user [dim][..] <-> internal [3][..] for ncomp-vector arrays of length Q
+  // user [dim][..] <-> internal [3][..] for velocity-like arrays of length Q per component ([nt + 1][..] of them
+  // when non-stationary)
   void to_internal(T* dst, const T* src, int ncomp) {
     const int64_t Q = d_.Q;
+    const int nodes = (ns_ && ncomp == 3) ? nt_ + 1 : 1;
     if (dim_ == 3) {
-      copy(dst, src, ncomp * Q);
-    } else {
-      zero(dst, Q, st_);
-      copy(dst + Q, src, 2 * Q);
+      copy(dst, src, (int64_t)nodes * ncomp * Q);
+      return;
+    }
+    for (int n = 0; n < nodes; ++n) {
+      zero(dst + n * 3 * Q, Q, st_);
+      copy(dst + n * 3 * Q + Q, src + n * 2 * Q, 2 * Q);
     }
   }
   void from_internal(T* dst, const T* src, int ncomp) {
     const int64_t Q = d_.Q;
-    if (dim_ == 3)
-      copy(dst, src, ncomp * Q);
-    else
-      copy(dst, src + Q, 2 * Q);
+    const int nodes = (ns_ && ncomp == 3) ? nt_ + 1 : 1;
+    if (dim_ == 3) {
+      copy(dst, src, (int64_t)nodes * ncomp * Q);
+      return;
+    }
+    for (int n = 0; n < nodes; ++n) copy(dst + n * 2 * Q, src + n * 3 * Q + Q, 2 * Q);
   }
   void axpby(T* out, T a, const T* x, T b, const T* y, int64_t n) { bl_axpby<T>(out, a, x, b, y, n, st_); }
 
   double grad_inf(const T* g) {
-    full_.iota_kind(g, S(0), 3, kPlain);
-    return maxabs<T>(S(0), 3 * d_.P, work_.get(), host_.get(), st_);
+    double m = 0.0;
+    for (int n = 0; n < (ns_ ? nt_ + 1 : 1); ++n) {
+      full_.iota_kind(g + (int64_t)n * 3 * d_.Q, S(0), 3, kPlain);
+      m = std::max(m, maxabs<T>(S(0), 3 * d_.P, work_.get(), host_.get(), st_));
+    }
+    return m;
   }
 
   // ------------------------------------ truncated products on the product grid
@@ -396,7 +444,7 @@ class Solver final : public SolverBase {
         const bool v1 = nc == 1;
         const int nc = v1 ? 1 : 3, np = v1 ? 4 : 6;
         sm_.iota_kind(x, es_.get(), nc, kPlain);
-        sm_.reduce(v1 ? kRedV1Products : kRedV3Products, np, nullptr, es_.get(), divvs_.get(),
+        sm_.reduce(v1 ? kRedV1Products : kRedV3Products, np, nullptr, es_.get(), divvsN(n),
                    v1 ? Gs_.get() + (int64_t)n * 3 * ds_.P : Dus_.get() + (int64_t)n * 9 * ds_.P);
         Axis0Args a = sm_.axis0_args(np);
         for (int f = 0; f < np; ++f) a.out[f] = dst[f], a.alpha[f] = al[f], a.beta[f] = be[f];
@@ -406,11 +454,11 @@ class Solver final : public SolverBase {
     }
     if (nc == 1) {
       sm_.iota_kind(x, es_.get(), 1, kPlain);
-      v1_products<T>(Ps(0), es_.get(), divvs_.get(), Gs_.get() + (int64_t)n * 3 * ds_.P, ds_, st_);
+      v1_products<T>(Ps(0), es_.get(), divvsN(n), Gs_.get() + (int64_t)n * 3 * ds_.P, ds_, st_);
       sm_.pi_acc(Ps(0), 4, dst, al, be);
     } else {
       sm_.iota_kind(x, es_.get(), 3, kPlain);
-      v3_products<T>(Ps(0), es_.get(), divvs_.get(), Dus_.get() + (int64_t)n * 9 * ds_.P, ds_, st_);
+      v3_products<T>(Ps(0), es_.get(), divvsN(n), Dus_.get() + (int64_t)n * 9 * ds_.P, ds_, st_);
       sm_.pi_acc(Ps(0), 6, dst, al, be);
     }
   }
@@ -419,11 +467,12 @@ class Solver final : public SolverBase {
   void setup_velocity() {
     // a non-finite coefficient would turn into non-finite departure points; reject it before any
     // interpolation runs
-    if (!std::isfinite(maxabs<T>(vbl_.get(), 3 * d_.Q, work_.get(), host_.get(), st_)))
+    if (!std::isfinite(maxabs<T>(vbl_.get(), VQ(), work_.get(), host_.get(), st_)))
       throw NonFiniteError("velocity has non-finite coefficients");
     setup_velocity_body();
   }
   void setup_velocity_body() {
+    if (ns_) return setup_velocity_ns();
     const int64_t P = d_.P;
     // velocity samples and the B-spline coefficients of the velocity in one 6-field transform
     const T* xs[6];
@@ -441,7 +490,32 @@ class Solver final : public SolverBase {
     if (rk_) sm_.iota_kind(vbl_.get(), vs_.get(), 3, kPlain);
   }
 
+  // per step n -> n + 1: X_b from the arrival velocity v_{n+1} and the departure velocity's interpolant
+  // P(v_n); X_f (arrival t_n, departure t_{n+1}) from v_n and P(v_{n+1}); div v at every node
+  void setup_velocity_ns() {
+    const int64_t Q = d_.Q;
+    for (int n = 0; n < nt_; ++n) {
+      const T* xs[12];
+      int kinds[kMaxFields][3];
+      for (int f = 0; f < 12; ++f) {
+        const int which = f / 3, c = f % 3;
+        xs[f] = vnode(n + (which & 1)) + c * Q;  // v_n, v_{n+1}, P v_n, P v_{n+1}
+        kinds[f][0] = kinds[f][1] = kinds[f][2] = which >= 2 ? kPref : kPlain;
+      }
+      full_.iota_comb(xs, nullptr, nullptr, S(0), 12, kinds);
+      characteristics<T>(XbN(n), S(3), S(6), d_, dt_, -1, st_);
+      characteristics<T>(XfN(n), S(0), S(9), d_, dt_, +1, st_);
+    }
+    for (int n = 0; n <= nt_; ++n) {
+      bl_div<T>(tmpbl_.get(), vnode(n), d_, st_);
+      full_.iota_kind(tmpbl_.get(), divvN(n), 1, kPlain);
+      sm_.iota_kind(tmpbl_.get(), divvsN(n), 1, kPlain);
+    }
+  }
+
   double regulariser() {
+    if (ns_)  // sum_n w_n 1/2 <L~ v_n, v_n>
+      return 0.5 * sym_dot<T>(vbl_.get(), vbl_.get(), wLsym_.get(), 1, VQ(), work_.get(), host_.get(), st_);
     return 0.5 * sym_dot<T>(vbl_.get(), vbl_.get(), Lsym_.get(), 3, d_.Q, work_.get(), host_.get(), st_);
   }
 
@@ -504,8 +578,8 @@ class Solver final : public SolverBase {
   // true when the held state was solved at exactly the internal velocity v (tmp: scratch of v's size)
   bool state_is_at(const T* v, T* tmp) {
     if (!state_valid_) return false;
-    axpby(tmp, T(1), v, T(-1), vbl_.get(), 3 * d_.Q);
-    return maxabs<T>(tmp, 3 * d_.Q, work_.get(), host_.get(), st_) == 0.0;
+    axpby(tmp, T(1), v, T(-1), vbl_.get(), VQ());
+    return maxabs<T>(tmp, VQ(), work_.get(), host_.get(), st_) == 0.0;
   }
 
   void state_body() {
@@ -527,7 +601,7 @@ class Solver final : public SolverBase {
       if (n < nt_) {
         copy(S(0), mn, P);
         prefilter(S(0), 1, d_, st_);
-        interp<T>(mn + P, S(0), 1, Xb_.get(), d_, st_);
+        interp<T>(mn + P, S(0), 1, XbN(n), d_, st_);
       }
     }
     // G_n = iota'(grad~ m~_n) on the product grid, four nodes per transform
@@ -544,7 +618,7 @@ class Solver final : public SolverBase {
         rk4_step(ubl_.get() + n * 3 * Q, ubl_.get() + (n + 1) * 3 * Q, dt_,
                  [&](const T* x, int, T* o) { rk_rhs_state(x, o); });
       else
-        u_step(ubl_.get() + n * 3 * Q, ubl_.get() + (n + 1) * 3 * Q);
+        u_step(ubl_.get() + n * 3 * Q, ubl_.get() + (n + 1) * 3 * Q, n);
     }
     // D u_n = iota'(D~ u~_n) on the product grid
     for (int n = 0; n <= nt_; ++n) sm_.iota_grad(ubl_.get() + n * 3 * Q, Dus_.get() + (int64_t)n * 9 * ds_.P, 3);
@@ -559,7 +633,7 @@ class Solver final : public SolverBase {
     const int64_t P = d_.P, Q = d_.Q;
     const int nn = nt_ + 1;
     zero(ubl_.get(), 3 * Q, st_);
-    for (int n = 0; n < nt_; ++n) u_step(ubl_.get() + n * 3 * Q, ubl_.get() + (n + 1) * 3 * Q);
+    for (int n = 0; n < nt_; ++n) u_step(ubl_.get() + n * 3 * Q, ubl_.get() + (n + 1) * 3 * Q, n);
     for (int n = 0; n <= nt_; ++n) sm_.iota_grad(ubl_.get() + n * 3 * Q, Dus_.get() + (int64_t)n * 9 * ds_.P, 3);
     // m(t_n) at every node (psi_ holds the samples of u~_n until the inverse map replaces them)
     iota_many(ubl_.get(), psi_.get(), 3 * nn);
@@ -571,7 +645,8 @@ class Solver final : public SolverBase {
     // -D~_t nu~ = -v~ from nu~(1) = 0, and -D~_t J~ = J~ star div~ v~ from J~(1) = 1 (the image-transport
     // products the band-limited sweep also forms land in scratch)
     zero(nubl_.get() + (int64_t)nt_ * 3 * Q, 3 * Q, st_);
-    for (int n = nt_ - 1; n >= 0; --n) map_step(nubl_.get() + (n + 1) * 3 * Q, nubl_.get() + n * 3 * Q, Xf_.get(), -1);
+    for (int n = nt_ - 1; n >= 0; --n)
+      map_step(nubl_.get() + (n + 1) * 3 * Q, nubl_.get() + n * 3 * Q, Xf_.get(), -1, vbl_.get(), vbl_.get());
     copy(Jbl_.get() + (int64_t)nt_ * Q, one_.get(), Q);
     bl_backward(Jbl_.get(), 1, tmpbl_.get());
     iota_many(nubl_.get(), psi_.get(), 3 * nn);
@@ -749,16 +824,16 @@ class Solver final : public SolverBase {
     bl_scale_sym<T>(h, dv, Lsym_.get(), 3, Q, acc_.get(), st_);
   }
 
-  // one deformation-state step: u_next = pi[P(u + dt/2 v) o X_b] + dt/2 v
-  void u_step(const T* un, T* un1) { map_step(un, un1, Xb_.get(), 1); }
-  // one step of a displacement map along the departure displacements X:
-  // next = pi[P(u + sgn dt/2 v) o X] + sgn dt/2 v (sgn = +1: u~ forward along X_b; sgn = -1: the inverse
-  // map nu~ of the state-equation variant, backward along X_f)
-  void map_step(const T* un, T* un1, const T* X, int sgn) {
+  // deformation-state step n -> n + 1: u_next = pi[P(u + dt/2 v_n) o X_b] + dt/2 v_{n+1}
+  void u_step(const T* un, T* un1, int n) { map_step(un, un1, XbN(n), 1, vnode(n), vnode(n + 1)); }
+  // one step of a displacement map along the departure displacements X, with the velocity vd at the
+  // departure time and va at the arrival time: next = pi[P(u + sgn dt/2 vd) o X] + sgn dt/2 va (sgn = +1: u~
+  // forward along X_b; sgn = -1: the inverse map nu~ of the state-equation variant, backward along X_f)
+  void map_step(const T* un, T* un1, const T* X, int sgn, const T* vd, const T* va) {
     const int64_t Q = d_.Q;
     const T hdt = T(0.5) * dt_ * T(sgn), sdt = dt_ * T(sgn);
     const T* xs[3] = {un, un + Q, un + 2 * Q};
-    const T* ys[3] = {vbl_.get(), vbl_.get() + Q, vbl_.get() + 2 * Q};
+    const T* ys[3] = {vd, vd + Q, vd + 2 * Q};
     const T al[3] = {hdt, hdt, hdt};
     full_.iota_comb_kind(xs, ys, al, S(0), 3, kPref);
     if constexpr (std::is_same_v<T, float>) {
@@ -768,7 +843,12 @@ class Solver final : public SolverBase {
         // step's change instead of the whole displacement (an FP32 rounding error that does not grow
         // with the displacement already accumulated)
         brick_interp_diff(S(3), S(0), 3, X, d_, st_);
-        axpby(un1, T(1), un, sdt, vbl_.get(), 3 * Q);
+        if (vd == va) {
+          axpby(un1, T(1), un, sdt, vd, 3 * Q);
+        } else {
+          axpby(un1, T(1), un, hdt, vd, 3 * Q);
+          axpby(un1, T(1), un1, hdt, va, 3 * Q);
+        }
         T* dst[3] = {un1, un1 + Q, un1 + 2 * Q};
         const T one[3] = {T(1), T(1), T(1)};
         full_.pi_acc(S(3), 3, dst, one, one);
@@ -776,7 +856,7 @@ class Solver final : public SolverBase {
       }
     }
     interp<T>(S(3), S(0), 3, X, d_, st_);
-    copy(un1, vbl_.get(), 3 * Q);
+    copy(un1, va, 3 * Q);
     T* dst[3] = {un1, un1 + Q, un1 + 2 * Q};
     const T one[3] = {T(1), T(1), T(1)}, hd[3] = {hdt, hdt, hdt};
     full_.pi_acc(S(3), 3, dst, one, hd);
@@ -787,12 +867,16 @@ class Solver final : public SolverBase {
     const int64_t Q = d_.Q;
     zero(u, 3 * Q, st_);
     for (int n = 0; n < nt_; ++n) {
-      u_step(u, blA_.get());
+      u_step(u, blA_.get(), n);
       copy(u, blA_.get(), 3 * Q);
     }
   }
 
   T trap_w(int n) const { return (n == 0 || n == nt_) ? T(0.5) * dt_ : dt_; }
+  // weight of node n's gradient / Hessian term and its offset in a velocity-like vector: the trapezoid
+  // weight into one accumulated field (stationary), or 1 into the node's own field (non-stationary)
+  T term_w(int n) const { return ns_ ? T(1) : trap_w(n); }
+  int64_t node_off(int n) const { return ns_ ? (int64_t)n * 3 * d_.Q : 0; }
 
   // ------------------------------------------ adjoint + gradient (rows 2 / 4)
   void run_adjoint(T* g) {
@@ -818,7 +902,7 @@ class Solver final : public SolverBase {
       }
       adjoint_v3();
     }
-    bl_scale_sym<T>(g, vbl_.get(), Lsym_.get(), 3, d_.Q, acc_.get(), st_);
+    bl_scale_sym<T>(g, vbl_.get(), Lsym_.get(), ns_ ? 3 * (nt_ + 1) : 3, d_.Q, acc_.get(), st_);
   }
 
   void adjoint_v1() {
@@ -826,22 +910,23 @@ class Solver final : public SolverBase {
     T* lam = S(9);
     T* lam_next = S(10);
     scaled_diff<T>(lam, T(-2.0 / sigma2_), m1_ptr(), I1_.get(), P, st_);
-    zero(acc_.get(), 3 * Q, st_);
+    zero(acc_.get(), VQ(), st_);
     for (int n = nt_; n >= 0; --n) {
       // gradient term w_n pi(iota(pi lambda_n) G_n), accumulated into acc (the first product, the
-      // band-limited source, is not used by the grid adjoint)
+      // band-limited source, is not used by the grid adjoint); non-stationary: the node's own term
       full_.pi(lam, tmpbl_.get(), 1);
       {
-        const T w = trap_w(n);
-        T* dst[4] = {blA_.get(), acc_.get(), acc_.get() + Q, acc_.get() + 2 * Q};
+        const T w = term_w(n);
+        T* an = acc_.get() + node_off(n);
+        T* dst[4] = {blA_.get(), an, an + Q, an + 2 * Q};
         const T al[4] = {T(1), w, w, w}, be[4] = {T(0), T(1), T(1), T(1)};
         products(tmpbl_.get(), 1, n, dst, al, be);
       }
       if (n == 0) break;
       copy(S(5), lam, P);
-      mul<T>(S(6), lam, divv_.get(), P, st_);
+      mul<T>(S(6), lam, divvN(n), P, st_);
       prefilter(S(5), 2, d_, st_);
-      adjoint_grid_step<T>(lam_next, S(5), S(6), Xf_.get(), divv_.get(), d_, dt_, st_);
+      adjoint_grid_step<T>(lam_next, S(5), S(6), XfN(n - 1), divvN(n - 1), d_, dt_, st_);
       std::swap(lam, lam_next);
     }
     copy(lam0_.get(), lam, P);
@@ -856,21 +941,22 @@ class Solver final : public SolverBase {
     const int64_t Q = d_.Q;
     const int64_t stride = (int64_t)ncomp * Q;
     const T hdt = T(0.5) * dt_;
-    zero(acc, 3 * Q, st_);
+    zero(acc, ns_ ? VQ() : 3 * Q, st_);
     for (int n = nt_; n >= 0; --n) {
       T* xn = traj + n * stride;
-      const T w = trap_w(n);
+      const T w = term_w(n);
+      T* an = acc + node_off(n);
       if (ncomp == 1) {
         // [fl, e G0, e G1, e G2]: fl to blA, the Hessian / gradient terms accumulated into acc
-        T* dst[4] = {blA_.get(), acc, acc + Q, acc + 2 * Q};
+        T* dst[4] = {blA_.get(), an, an + Q, an + 2 * Q};
         const T al[4] = {T(1), w, w, w}, be[4] = {T(0), T(1), T(1), T(1)};
         products(xn, 1, n, dst, al, be);
       } else {
         // [fl (3), (Du)^T e (3)]
-        T* dst[6] = {blA_.get(), blA_.get() + Q, blA_.get() + 2 * Q, acc, acc + Q, acc + 2 * Q};
+        T* dst[6] = {blA_.get(), blA_.get() + Q, blA_.get() + 2 * Q, an, an + Q, an + 2 * Q};
         const T al[6] = {T(1), T(1), T(1), -w, -w, -w}, be[6] = {T(0), T(0), T(0), T(1), T(1), T(1)};
         products(xn, 3, n, dst, al, be);
-        axpby(acc, T(1), acc, w, xn, 3 * Q);
+        axpby(an, T(1), an, w, xn, 3 * Q);
       }
       if (n == 0) break;
       const T* fl = blA_.get();
@@ -885,7 +971,7 @@ class Solver final : public SolverBase {
         al2[ncomp + c] = dt_;
       }
       full_.iota_comb_kind(xs, ys, al2, S(3), 2 * ncomp, kPref);
-      bl_adjoint_step<T>(S(9), S(3), S(3 + ncomp), ncomp, Xf_.get(), divv_.get(), d_, dt_, st_);
+      bl_adjoint_step<T>(S(9), S(3), S(3 + ncomp), ncomp, XfN(n - 1), divvN(n - 1), d_, dt_, st_);
       full_.pi(S(9), traj + (n - 1) * stride, ncomp);
     }
   }
@@ -909,12 +995,12 @@ class Solver final : public SolverBase {
     const int nn = nt_ + 1;
     // incremental sources f~_n = pi'(s_n) for every node, scaled by dt/2, on the product grid:
     // image transport s_n = -G_n . dv, deformation state s_n = dv - (D u_n) dv
-    sm_.iota_kind(dv, dvs_.get(), 3, kPlain);
+    dv_on_product_grid(dv);
     for (int n = 0; n < nn; ++n) {
       if (nc == 1)
-        v1_source<T>(Ps(n), Gs_.get() + (int64_t)n * 3 * Psm, dvs_.get(), ds_, st_);
+        v1_source<T>(Ps(n), Gs_.get() + (int64_t)n * 3 * Psm, dvsN(n), ds_, st_);
       else
-        v3_source<T>(Ps(3 * n), Dus_.get() + (int64_t)n * 9 * Psm, dvs_.get(), ds_, st_);
+        v3_source<T>(Ps(3 * n), Dus_.get() + (int64_t)n * 9 * Psm, dvsN(n), ds_, st_);
     }
     for (int f0 = 0; f0 < nn * nc; f0 += kMaxFields) {
       const int nf = std::min<int>(kMaxFields, nn * nc - f0);
@@ -939,7 +1025,7 @@ class Solver final : public SolverBase {
         al[c] = one[c] = T(1);
       }
       full_.iota_comb_kind(xs, ys, al, S(0), nc, kPref);
-      interp<T>(S(3), S(0), nc, Xb_.get(), d_, st_);
+      interp<T>(S(3), S(0), nc, XbN(n), d_, st_);
       full_.pi_acc(S(3), nc, dst, one, one);
     }
     if (nc == 1) {
@@ -956,7 +1042,7 @@ class Solver final : public SolverBase {
       full_.pi(S(3), dr + (int64_t)nt_ * 3 * Q, 3);
       bl_backward(dr, 3, acc_.get());
     }
-    bl_scale_sym<T>(h, dv, Lsym_.get(), 3, Q, acc_.get(), st_);
+    bl_scale_sym<T>(h, dv, Lsym_.get(), ns_ ? 3 * nn : 3, Q, acc_.get(), st_);
   }
 
   // ------------------------- plane-wise forms of the sweeps (float; dft_planes.hip)
@@ -975,9 +1061,9 @@ class Solver final : public SolverBase {
     float* dm = inc_.get();  // [nt+1][nc][Q]
     // f~_n dt/2 for every node (into fsrc, and into dm_n for n >= 1), and the plane-band input of
     // the first step's interpolant P(dm_0 + dt/2 f~_0) = P(dt/2 f~_0)
-    sm_.iota_kind(dv, dvs_.get(), 3, kPlain);
+    dv_on_product_grid(dv);
     sm_.reduce(nc == 1 ? kRedV1Source : kRedV3Source, nn * nc, nullptr, dvs_.get(), nullptr,
-               nc == 1 ? Gs_.get() : Dus_.get());
+               nc == 1 ? Gs_.get() : Dus_.get(), ns_ ? 3 * Psm : 0);
     for (int f0 = 0; f0 < nn * nc; f0 += kMaxFields) {
       const int m = std::min(kMaxFields, nn * nc - f0);
       Axis0Args a = sm_.axis0_args(m, f0);
@@ -992,13 +1078,12 @@ class Solver final : public SolverBase {
       }
       plane_axis0(a, st_);
     }
-    (void)Psm;
     // incremental state: dm_{n+1} = pi[P(dm_n + dt/2 f_n) o X_b] + dt/2 f_{n+1} (dm_0 = 0, kept)
     float* dl = incadj_.get();
     const float cpl = -2.0f / float(sigma2_);  // image transport: dl~(1) = -(2/sigma^2) dm~(1)
     for (int n = 0; n < nt_; ++n) {
       full_.expand(nc, kpref, S(0));
-      interp<float>(S(3), S(0), nc, Xb_.get(), d_, st_);
+      interp<float>(S(3), S(0), nc, XbN(n), d_, st_);
       full_.reduce(kRedPlain, nc, S(3));
       Axis0Args a = full_.axis0_args(nc);
       for (int c = 0; c < nc; ++c) {
@@ -1051,22 +1136,24 @@ class Solver final : public SolverBase {
     }
     for (int n = nt_; n >= 0; --n) {
       float* xn = traj + n * stride;
-      const float w = trap_w(n);
+      const float w = term_w(n);
+      const int64_t off = node_off(n);
       // products on the product grid: fl = x * div~ v~ and the Hessian / gradient terms
       sm_.expand_kind(nc, kPlain, es_.get());
-      sm_.reduce(v1 ? kRedV1Products : kRedV3Products, np, nullptr, es_.get(), divvs_.get(),
+      sm_.reduce(v1 ? kRedV1Products : kRedV3Products, np, nullptr, es_.get(), divvsN(n),
                  v1 ? Gs_.get() + (int64_t)n * 3 * ds_.P : Dus_.get() + (int64_t)n * 9 * ds_.P);
       Axis0Args a = sm_.axis0_args(np);
       for (int c = 0; c < nc; ++c) a.out[c] = blA_.get() + c * Q, a.alpha[c] = 1.f;
       for (int j = 0; j < 3; ++j) {
-        a.out[nc + j] = acc + j * Q;
+        a.out[nc + j] = acc + off + j * Q;
         a.alpha[nc + j] = v1 ? w : -w;
-        a.beta[nc + j] = n == nt_ ? 0.f : 1.f;  // the first step starts the accumulation
+        // stationary: the first step starts the accumulation; non-stationary: each node its own term
+        a.beta[nc + j] = (ns_ || n == nt_) ? 0.f : 1.f;
         if (!v1) a.z[nc + j] = xn + j * Q, a.gamma[nc + j] = w;  // + w x_n
-        if (n == 0 && h_out) {  // last step: h = L~ x_sym + acc
-          a.in[nc + j] = acc + j * Q;
-          a.out[nc + j] = h_out + j * Q;
-          a.y[nc + j] = x_sym + j * Q;
+        if (h_out && (ns_ || n == 0)) {  // h = L~ x_sym + acc (non-stationary: node by node)
+          if (!ns_) a.in[nc + j] = acc + j * Q;
+          a.out[nc + j] = h_out + off + j * Q;
+          a.y[nc + j] = x_sym + off + j * Q;
           a.ysym[nc + j] = Lsym_.get();
         }
       }
@@ -1080,7 +1167,7 @@ class Solver final : public SolverBase {
       plane_axis0(a, st_);
       if (n == 0) break;
       full_.expand(2 * nc, kpref, S(3));
-      bl_adjoint_step<float>(S(9), S(3), S(3 + nc), nc, Xf_.get(), divv_.get(), d_, dt_, st_);
+      bl_adjoint_step<float>(S(9), S(3), S(3 + nc), nc, XfN(n - 1), divvN(n - 1), d_, dt_, st_);
       full_.reduce(kRedPlain, nc, S(9));
       Axis0Args b = full_.axis0_args(nc);
       b.nout = nc;
@@ -1106,6 +1193,7 @@ class Solver final : public SolverBase {
   bool graphs_enabled_ = std::getenv("LDDMM_BL_NO_GRAPH") == nullptr;
   bool bf16_ = false;  // split-bf16 contractions for the first-axis DFT stages
   bool rk_ = false;    // explicit RK4 comparator instead of the SL-RK2 sweeps
+  bool ns_ = false;    // a velocity per time node
   bool trace_ = std::getenv("LDDMM_BL_TRACE") != nullptr;  // Gauss-Newton scalars to stderr
 
   template <typename U>
@@ -1129,27 +1217,39 @@ class Solver final : public SolverBase {
   DevBuf<T> ubl_, Dus_, m1_, g1_, rho_;         // deformation state (and the state-equation variant)
   DevBuf<T> nubl_, Jbl_, psi_, Jg_, lamg_, lamt_, one_;  // state-equation variant
   DevBuf<T> vs_, rkw_, rkD_;                    // explicit RK4 comparator (product grid)
+  DevBuf<double> wvec_, wLsym_;                 // non-stationary: node weights, node-weighted L~ symbol
   DevBuf<double> det_;  // Jacobian map when the caller keeps none
 
  public:
   // accessors used by the Gauss-Newton driver
-  int64_t vec_len() const { return 3 * d_.Q; }
-  void set_velocity_internal(const T* v) { copy(vbl_.get(), v, 3 * d_.Q); }
+  int64_t vec_len() const { return VQ(); }
+  bool nonstationary() const { return ns_; }
+  void set_velocity_internal(const T* v) { copy(vbl_.get(), v, VQ()); }
   void state_internal(double e[3]) { run_state(e); }
   void adjoint_internal(T* g) { run_adjoint(g); }
   // H x into y through the captured graph (its fixed buffers dvbl_ -> hbl_)
   void matvec_internal(const T* x, T* y) {
-    if (x != dvbl_.get()) copy(dvbl_.get(), x, 3 * d_.Q);
+    if (x != dvbl_.get()) copy(dvbl_.get(), x, VQ());
     matvec_graph();
-    if (y != hbl_.get()) copy(y, hbl_.get(), 3 * d_.Q);
+    if (y != hbl_.get()) copy(y, hbl_.get(), VQ());
   }
-  void precond_internal(const T* r, T* z) { bl_scale_sym<T>(z, r, Linv_.get(), 3, d_.Q, nullptr, st_); }
+  void precond_internal(const T* r, T* z) {
+    bl_scale_sym<T>(z, r, Linv_.get(), ns_ ? 3 * (nt_ + 1) : 3, d_.Q, nullptr, st_);
+  }
+  // the PCG / Armijo inner product (non-stationary: sum_n w_n <a_n, b_n>)
   double dot_internal(const T* a, const T* b) {
+    if (ns_) return sym_dot<T>(a, b, wvec_.get(), 1, VQ(), work_.get(), host_.get(), st_);
     return lddmm::dot<T>(a, b, 3 * d_.Q, work_.get(), host_.get(), st_);
   }
+  void dot_launch(const T* a, const T* b, int slot) {
+    if (ns_)
+      sym_dot_launch<T>(a, b, wvec_.get(), 1, VQ(), work_.get(), slot, st_);
+    else
+      reduce_launch<T>(RedKind::Dot, a, b, 3 * d_.Q, work_.get(), slot, st_);
+  }
   double grad_inf_internal(const T* g) { return grad_inf(g); }
-  void axpby_internal(T* out, T a, const T* x, T b, const T* y) { axpby(out, a, x, b, y, 3 * d_.Q); }
-  void copy_internal(T* dst, const T* src) { copy(dst, src, 3 * d_.Q); }
+  void axpby_internal(T* out, T a, const T* x, T b, const T* y) { axpby(out, a, x, b, y, VQ()); }
+  void copy_internal(T* dst, const T* src) { copy(dst, src, VQ()); }
   void user_to_internal(T* dst, const T* src) { to_internal(dst, src, 3); }
   void internal_to_user(T* dst, const T* src) { from_internal(dst, src, 3); }
   double mse_rel() {
@@ -1253,16 +1353,22 @@ int64_t Solver<T>::get_field(int which, int index, void* dst_v) {
   };
   switch (which) {
     case LDDMM_BL_FIELD_VELOCITY:
-      count = grid_vec(vg_.get());
+      if (ns_) {  // iota(v~_n) at node index
+        check_index();
+        full_.iota_kind(vnode(index), S(0), 3, kPlain);
+        count = grid_vec(S(0));
+      } else {
+        count = grid_vec(vg_.get());
+      }
       break;
     case LDDMM_BL_FIELD_DEP_BACKWARD:
-      count = grid_vec(Xb_.get());
-      break;
     case LDDMM_BL_FIELD_DEP_FORWARD:
-      count = grid_vec(Xf_.get());
+      if (ns_ && (index < 0 || index >= nt_)) throw ArgError("step index out of range");
+      count = grid_vec(which == LDDMM_BL_FIELD_DEP_BACKWARD ? XbN(ns_ ? index : 0) : XfN(ns_ ? index : 0));
       break;
     case LDDMM_BL_FIELD_DIV_V:
-      if (dst) copy(dst, divv_.get(), P);
+      if (ns_) check_index();
+      if (dst) copy(dst, divvN(ns_ ? index : 0), P);
       count = P;
       break;
     case LDDMM_BL_FIELD_STATE:
@@ -1339,6 +1445,7 @@ int Solver<T>::gn_solve(const lddmm_bl_gn_opts& o, void* v_user, const void* Zu,
   if (Zu && (r < 1 || r > 16)) throw ArgError("preconditioner rank must be 1..16");
   const bool ml = o.ml_inner > 0;
   if (ml && Zu) throw ArgError("the low-rank and the two-level preconditioners exclude each other");
+  if (ns_ && (ml || Zu)) throw ArgError("non-stationary velocities take the L~^-1 preconditioner only");
   if (o.ml_inner < 0 || o.ml_inner > 1000) throw ArgError("ml_inner must be in 0..1000");
   if (ml) ensure_coarse();
   const auto t0 = std::chrono::steady_clock::now();
@@ -1461,8 +1568,8 @@ int Solver<T>::gn_solve(const lddmm_bl_gn_opts& o, void* v_user, const void* Zu,
     precond(rr.get(), z.get());
     copy_internal(pv, z.get());
     int irz = kRZ0, irzn = kRZ0 + 1;
-    reduce_launch<T>(RedKind::Dot, rr.get(), z.get(), n, wk, irz, stream());
-    reduce_launch<T>(RedKind::Dot, rr.get(), rr.get(), n, wk, kRN2, stream());
+    dot_launch(rr.get(), z.get(), irz);
+    dot_launch(rr.get(), rr.get(), kRN2);
     fetch_async(wk, host_.get(), 2, stream());
     synchronize();
     double rn = std::sqrt(hs[kRN2]);
@@ -1471,13 +1578,13 @@ int Solver<T>::gn_solve(const lddmm_bl_gn_opts& o, void* v_user, const void* Zu,
       if (!fixed && rn <= tol) break;
       matvec_graph();  // H p
       ++R.hess_matvecs;
-      reduce_launch<T>(RedKind::Dot, pv, Apv, n, wk, kPAP, stream());
+      dot_launch(pv, Apv, kPAP);
       pcg_step<T>(x.get(), rr.get(), pv, Apv, wk, irz, kPAP, n, stream());
       if (ml) copy_internal(zold.get(), z.get());
       precond(rr.get(), z.get());
-      reduce_launch<T>(RedKind::Dot, rr.get(), z.get(), n, wk, irzn, stream());
-      if (ml) reduce_launch<T>(RedKind::Dot, rr.get(), zold.get(), n, wk, kRZX, stream());
-      reduce_launch<T>(RedKind::Dot, rr.get(), rr.get(), n, wk, kRN2, stream());
+      dot_launch(rr.get(), z.get(), irzn);
+      if (ml) dot_launch(rr.get(), zold.get(), kRZX);
+      dot_launch(rr.get(), rr.get(), kRN2);
       pcg_dir<T>(pv, z.get(), wk, irz, irzn, kPAP, n, stream(), ml ? kRZX : -1);
       fetch_async(wk, host_.get(), trace_ ? 4 : 2, stream());
       synchronize();

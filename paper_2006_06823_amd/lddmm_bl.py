@@ -51,7 +51,7 @@ class Params(ctypes.Structure):
         ("dim", ctypes.c_int32), ("n", ctypes.c_int32 * 3), ("k", ctypes.c_int32 * 3),
         ("nt", ctypes.c_int32), ("variant", ctypes.c_int32), ("alpha", ctypes.c_double),
         ("s", ctypes.c_int32), ("sigma2", ctypes.c_double), ("precision", ctypes.c_int32),
-        ("integrator", ctypes.c_int32),
+        ("integrator", ctypes.c_int32), ("nonstationary", ctypes.c_int32),
     ]
 
 
@@ -172,6 +172,7 @@ class Problem:
     sigma2: float = 1.0
     precision: int = FP32
     integrator: int = 0     # SL_RK2; EULER_RK4: the explicit RK comparator (deformation state only)
+    nonstationary: bool = False  # a velocity per time node: v~ of shape (nt + 1, d, *k)
 
 
 def make_params(prob: "Problem") -> Params:
@@ -184,6 +185,7 @@ def make_params(prob: "Problem") -> Params:
     p.nt, p.variant, p.alpha, p.s, p.sigma2, p.precision = (
         prob.nt, prob.variant, prob.alpha, prob.s, prob.sigma2, prob.precision)
     p.integrator = prob.integrator
+    p.nonstationary = 1 if prob.nonstationary else 0
     return p
 
 
@@ -220,6 +222,8 @@ class Context:
         self.lib = load_library()
         self.prob = prob
         self.dim = len(prob.n)
+        self.nt = int(prob.nt)
+        self.nonstationary = bool(prob.nonstationary)
         self.n = tuple(int(x) for x in prob.n)
         self.k = tuple(int(x) for x in prob.k)
         self.dtype = torch.float64 if prob.precision == FP64 else torch.float32
@@ -263,6 +267,11 @@ class Context:
     def _bl_shape(self, ncomp=None):
         return self.k if ncomp is None else (ncomp,) + self.k
 
+    def _vshape(self):
+        """Shape of velocity-like arrays (velocity, gradient, Hessian directions): (dim, *k), or
+        (nt + 1, dim, *k) for a non-stationary problem."""
+        return ((self.nt + 1,) if self.nonstationary else ()) + self._bl_shape(self.dim)
+
     def _arg(self, t: torch.Tensor, shape, name):
         if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
             raise TypeError(f"{name} must be a ROCm device tensor")
@@ -288,7 +297,7 @@ class Context:
         self._check(self.lib.lddmm_bl_set_images(self.h, _ptr(I0), _ptr(I1)))
 
     def state_solve(self, v: torch.Tensor, want_m1: bool = False) -> Tuple[Tuple[float, float, float], Optional[torch.Tensor]]:
-        self._arg(v, self._bl_shape(self.dim), "v")
+        self._arg(v, self._vshape(), "v")
         m1 = self.empty_grid() if want_m1 else None
         E = (ctypes.c_double * 3)()
         self._order()
@@ -296,15 +305,16 @@ class Context:
         return (E[0], E[1], E[2]), m1
 
     def adjoint_solve(self) -> Tuple[torch.Tensor, float]:
-        g = self.empty_bl(self.dim)
+        g = torch.empty(self._vshape(), dtype=self.dtype, device=self.device)
         ginf = ctypes.c_double()
         self._order()
         self._check(self.lib.lddmm_bl_adjoint_solve(self.h, _ptr(g), ctypes.byref(ginf)))
         return g, ginf.value
 
     def hess_matvec(self, dv: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
-        self._arg(dv, self._bl_shape(self.dim), "dv")
-        out = self.empty_bl(self.dim) if out is None else self._arg(out, self._bl_shape(self.dim), "out")
+        self._arg(dv, self._vshape(), "dv")
+        out = torch.empty(self._vshape(), dtype=self.dtype, device=self.device) if out is None else \
+            self._arg(out, self._vshape(), "out")
         self._order()
         self._check(self.lib.lddmm_bl_hess_matvec(self.h, _ptr(dv), _ptr(out)))
         return out
@@ -315,7 +325,7 @@ class Context:
 
         energy_target > 0 also stops the run once the objective is at or below it; ml_inner > 0 selects the
         two-level spectral preconditioner with that many inner coarse PCG iterations."""
-        self._arg(v, self._bl_shape(self.dim), "v")
+        self._arg(v, self._vshape(), "v")
         o = GNOpts(max_gn, max_pcg, grad_rtol, grad_ref_inf, 1 if fixed_iters else 0, float(energy_target),
                    int(ml_inner))
         rep = GNReport()
