@@ -42,6 +42,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <functional>
+#include <map>
 #include <type_traits>
 
 #include "prof.h"
@@ -546,13 +547,17 @@ class Solver final : public SolverBase {
   }
   bool check_ok() const { return std::isfinite(host_.get()[0]); }
   void state_launch(const T* v) {  // v has passed check_launch / check_ok
+    state_compute(v);
+    fetch_async(work_.get(), host_.get(), 3, st_);
+  }
+  // the state solve's launches with its scalars left in the device slots (capturable: no copy to the host)
+  void state_compute(const T* v) {
     state_valid_ = false;
     copy(vbl_.get(), v, 3 * d_.Q);
     setup_velocity_body();
     state_body();
     reduce_launch<T>(RedKind::SqDiff, m1_ptr(), I1_.get(), d_.P, work_.get(), 1, st_);
     sym_dot_launch<T>(vbl_.get(), vbl_.get(), Lsym_.get(), 3, d_.Q, work_.get(), 2, st_);
-    fetch_async(work_.get(), host_.get(), 3, st_);
   }
   void state_finish(double e[3]) {
     const double* h = host_.get();
@@ -566,12 +571,17 @@ class Solver final : public SolverBase {
     state_valid_ = true;
   }
   void adjoint_launch(T* g) {
+    adjoint_compute(g);
+    fetch_async(work_.get(), host_.get(), 5, st_);
+  }
+  void adjoint_compute(T* g) {
     run_adjoint(g);
     full_.iota_kind(g, S(0), 3, kPlain);
     reduce_launch<T>(RedKind::MaxAbs, S(0), nullptr, 3 * d_.P, work_.get(), 3, st_);
     reduce_launch<T>(RedKind::Dot, g, g, 3 * d_.Q, work_.get(), 4, st_);
-    fetch_async(work_.get(), host_.get(), 5, st_);
   }
+  void fetch_slots(int count) { fetch_async(work_.get(), host_.get(), count, st_); }
+  const double* host_slots() const { return host_.get(); }
   double launched_ginf() const { return host_.get()[3]; }
   double launched_gnorm2() const { return host_.get()[4]; }
 
@@ -1656,11 +1666,12 @@ int Solver<T>::gn_solve(const lddmm_bl_gn_opts& o, void* v_user, const void* Zu,
 
 // ---------------------------------------------------- batched Gauss-Newton-Krylov
 // Several subjects (each with its own grid and band) registered in lockstep on one
-// stream.  The Hessian matvecs of every subject in a PCG iteration are captured
-// once into a single HIP graph and replayed with one launch per iteration; the PCG
-// scalars, line searches and stopping tests stay per subject.  A subject that has
-// converged (or whose PCG has stopped) keeps its results; its slot in the graph is
-// still computed and ignored.
+// stream.  The Hessian matvecs of the subjects still iterating in a PCG iteration run as
+// one HIP graph launch (one graph per set of active subjects, captured on first use);
+// the PCG scalars live on the device and come back once per iteration for all
+// subjects together; line searches and stopping tests stay per subject.  A subject
+// that has converged (or whose PCG has stopped) keeps its results and drops out of
+// the launched work.
 template <typename T>
 int gn_solve_batched_impl(std::vector<Solver<T>*>& subs, const lddmm_bl_gn_opts& o, void* const* v_user,
                           lddmm_bl_gn_report* reps, hipStream_t st) {
@@ -1668,7 +1679,7 @@ int gn_solve_batched_impl(std::vector<Solver<T>*>& subs, const lddmm_bl_gn_opts&
   const auto t0 = std::chrono::steady_clock::now();
   struct Sub {
     DevBuf<T> v, g, x, r, z, vt;
-    double E = 0, ginf = 0, ref = 0, gnorm0 = 0, rz = 0, tol = 0;
+    double E = 0, ginf = 0, ref = 0, gnorm0 = 0, tol = 0;
     bool converged = false, failed = false, pcg_done = false;
     int its = 0, negcurv = 0, bt = 0;  // this GN iteration's PCG iterations, truncation, backtracks
     lddmm_bl_gn_report R{};
@@ -1748,6 +1759,44 @@ int gn_solve_batched_impl(std::vector<Solver<T>*>& subs, const lddmm_bl_gn_opts&
   auto sync_st = [&] { LDDMM_HIP(hipStreamSynchronize(st)); };
   std::vector<int> all(B);
   for (int i = 0; i < B; ++i) all[i] = i;
+  // Every phase that runs the same launches for the same subjects again (the Hessian matvecs of a PCG
+  // iteration; the state solves of a line-search round; the adjoint solves of new gradients) is captured
+  // once per (phase, subject set) into a HIP graph over fixed buffers and replayed; a subject that has
+  // converged or stopped drops out of the set, so its work is not computed.  Graphs are not used while
+  // profiling or with LDDMM_BL_NO_GRAPH set (the same launches then run eagerly).
+  const bool use_graph = !prof::enabled() && std::getenv("LDDMM_BL_NO_GRAPH") == nullptr;
+  std::map<std::pair<int, std::vector<int>>, hipGraphExec_t> graphs;
+  struct GraphsGuard {
+    std::map<std::pair<int, std::vector<int>>, hipGraphExec_t>& g;
+    ~GraphsGuard() {
+      for (auto& kv : g) (void)hipGraphExecDestroy(kv.second);
+    }
+  } graphs_guard{graphs};
+  auto run_phase = [&](int phase, const std::vector<int>& who, const std::function<void(int)>& fn) {
+    if (who.empty()) return;
+    if (!use_graph) return on_branches(who, fn);
+    auto key = std::make_pair(phase, who);
+    auto it = graphs.find(key);
+    if (it == graphs.end()) {
+      hipGraph_t graph = nullptr;
+      LDDMM_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      try {
+        on_branches(who, fn);
+      } catch (...) {
+        (void)hipStreamEndCapture(st, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+        throw;
+      }
+      LDDMM_HIP(hipStreamEndCapture(st, &graph));
+      hipGraphExec_t exec = nullptr;
+      const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) throw HipError(std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+      it = graphs.emplace(key, exec).first;
+    }
+    LDDMM_HIP(hipGraphLaunch(it->second, st));
+  };
+  enum { kPhaseMatvec = 0, kPhaseTrial = 1, kPhaseAdjoint = 2 };
   // velocity checks (a non-finite velocity never reaches an interpolation), then every subject's
   // state and adjoint solve
   for (int i = 0; i < B; ++i) subs[i]->check_launch(S[i].v.get());
@@ -1755,9 +1804,10 @@ int gn_solve_batched_impl(std::vector<Solver<T>*>& subs, const lddmm_bl_gn_opts&
   for (int i = 0; i < B; ++i)
     if (!subs[i]->check_ok()) throw NonFiniteError("velocity has non-finite coefficients");
   on_branches(all, [&](int i) {
-    subs[i]->state_launch(S[i].v.get());
-    subs[i]->adjoint_launch(S[i].g.get());
+    subs[i]->state_compute(S[i].v.get());
+    subs[i]->adjoint_compute(S[i].g.get());
   });
+  for (int i = 0; i < B; ++i) subs[i]->fetch_slots(5);
   sync_st();
   for (int i = 0; i < B; ++i) {
     double e[3];
@@ -1768,33 +1818,11 @@ int gn_solve_batched_impl(std::vector<Solver<T>*>& subs, const lddmm_bl_gn_opts&
     S[i].gnorm0 = std::sqrt(subs[i]->launched_gnorm2());
   }
   mark("initial solves done");
-  // Every subject's Hessian matvec (p in dvbl_, H p in hbl_) per PCG iteration, captured once into a
-  // graph, or launched eagerly (while profiling, or with LDDMM_BL_NO_GRAPH set)
-  const bool use_graph = !prof::enabled() && std::getenv("LDDMM_BL_NO_GRAPH") == nullptr;
-  auto matvecs = [&] { on_branches(all, [&](int i) { subs[i]->run_matvec(subs[i]->dvbl_.get(), subs[i]->hbl_.get()); }); };
-  hipGraphExec_t exec = nullptr;
-  if (use_graph) {
-    hipGraph_t graph = nullptr;
-    LDDMM_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    try {
-      matvecs();
-    } catch (...) {
-      (void)hipStreamEndCapture(st, &graph);
-      if (graph) (void)hipGraphDestroy(graph);
-      throw;
-    }
-    LDDMM_HIP(hipStreamEndCapture(st, &graph));
-    const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    if (e != hipSuccess) throw HipError(std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-  }
-  mark("matvec graph ready");
-  struct ExecGuard {
-    hipGraphExec_t e;
-    ~ExecGuard() {
-      if (e) (void)hipGraphExecDestroy(e);
-    }
-  } guard{exec};
+  // PCG scalars stay on the device (slots: 0 p.Hp, 1 r.r, 2 / 3 r.z ping-pong); one host round trip per
+  // PCG iteration brings every subject's p.Hp and r.r back together
+  enum { kPAP = 0, kRN2 = 1, kRZ0 = 2 };
+  std::vector<int> irz(B, kRZ0), irzn(B, kRZ0 + 1);
+  std::vector<double> rn(B, 0.0);
   for (int k = 0; k < o.max_gn; ++k) {
     bool any = false;
     for (int i = 0; i < B; ++i) {
@@ -1821,49 +1849,59 @@ int gn_solve_batched_impl(std::vector<Solver<T>*>& subs, const lddmm_bl_gn_opts&
       sv.axpby_internal(u.r.get(), T(-1), u.g.get(), T(0), nullptr);
       sv.precond_internal(u.r.get(), u.z.get());
       sv.copy_internal(sv.dvbl_.get(), u.z.get());
-      u.rz = sv.dot_internal(u.r.get(), u.z.get());
+      irz[i] = kRZ0, irzn[i] = kRZ0 + 1;
+      sv.dot_launch(u.r.get(), u.z.get(), irz[i]);
+      sv.dot_launch(u.r.get(), u.r.get(), kRN2);
+      sv.fetch_slots(2);
     }
+    sync_st();
+    for (int i = 0; i < B; ++i)
+      if (!S[i].pcg_done) rn[i] = std::sqrt(subs[i]->host_slots()[kRN2]);
     for (int it = 0; it < o.max_pcg; ++it) {
-      bool iterate = false;
+      std::vector<int> active;
       for (int i = 0; i < B; ++i) {
         Sub& u = S[i];
         if (u.pcg_done) continue;
-        const double rn = std::sqrt(subs[i]->dot_internal(u.r.get(), u.r.get()));
-        if (!fixed && rn <= u.tol) {
+        if (!fixed && rn[i] <= u.tol) {
           u.pcg_done = true;
           continue;
         }
-        iterate = true;
+        active.push_back(i);
       }
-      if (!iterate) break;
-      if (use_graph)
-        LDDMM_HIP(hipGraphLaunch(exec, st));
-      else
-        matvecs();
-      for (int i = 0; i < B; ++i) {
+      if (active.empty()) break;
+      run_phase(kPhaseMatvec, active,
+                [&](int i) { subs[i]->run_matvec(subs[i]->dvbl_.get(), subs[i]->hbl_.get()); });
+      for (int i : active) {
         Sub& u = S[i];
         Solver<T>& sv = *subs[i];
-        if (u.pcg_done) continue;
         ++u.R.hess_matvecs;
         T* p = sv.dvbl_.get();
         const T* Ap = sv.hbl_.get();
-        const double pAp = sv.dot_internal(p, Ap);
+        const int64_t n = sv.vec_len();
+        double* wk = sv.work_.get();
+        sv.dot_launch(p, Ap, kPAP);
+        pcg_step<T>(u.x.get(), u.r.get(), p, Ap, wk, irz[i], kPAP, n, st);
+        sv.precond_internal(u.r.get(), u.z.get());
+        sv.dot_launch(u.r.get(), u.z.get(), irzn[i]);
+        sv.dot_launch(u.r.get(), u.r.get(), kRN2);
+        pcg_dir<T>(p, u.z.get(), wk, irz[i], irzn[i], kPAP, n, st);
+        sv.fetch_slots(2);
+      }
+      sync_st();
+      for (int i : active) {
+        Sub& u = S[i];
+        const double pAp = subs[i]->host_slots()[kPAP];
         if (!std::isfinite(pAp)) throw NonFiniteError("non-finite curvature in batched PCG");
-        if (pAp <= 0.0) {
-          if (it == 0) sv.copy_internal(u.x.get(), p);
+        if (pAp <= 0.0) {  // the device updates were skipped; p is unchanged
+          if (it == 0) subs[i]->copy_internal(u.x.get(), subs[i]->dvbl_.get());
           u.negcurv = 1;
           u.pcg_done = true;
           continue;
         }
         ++u.R.pcg_iters_total;
         ++u.its;
-        const double a = u.rz / pAp;
-        sv.axpby_internal(u.x.get(), T(1), u.x.get(), T(a), p);
-        sv.axpby_internal(u.r.get(), T(1), u.r.get(), T(-a), Ap);
-        sv.precond_internal(u.r.get(), u.z.get());
-        const double rz_new = sv.dot_internal(u.r.get(), u.z.get());
-        sv.axpby_internal(p, T(1), u.z.get(), T(rz_new / u.rz), p);
-        u.rz = rz_new;
+        rn[i] = std::sqrt(subs[i]->host_slots()[kRN2]);
+        std::swap(irz[i], irzn[i]);
       }
     }
     mark("PCG done");
@@ -1883,7 +1921,8 @@ int gn_solve_batched_impl(std::vector<Solver<T>*>& subs, const lddmm_bl_gn_opts&
       sync_st();
       for (int i : pending)
         if (!subs[i]->check_ok()) throw NonFiniteError("velocity has non-finite coefficients");
-      on_branches(pending, [&](int i) { subs[i]->state_launch(S[i].vt.get()); });
+      run_phase(kPhaseTrial, pending, [&](int i) { subs[i]->state_compute(S[i].vt.get()); });
+      for (int i : pending) subs[i]->fetch_slots(3);
       sync_st();
       std::vector<int> next;
       for (int i : pending) {
@@ -1912,7 +1951,8 @@ int gn_solve_batched_impl(std::vector<Solver<T>*>& subs, const lddmm_bl_gn_opts&
       S[i].log(k, -1);
     }
     // new gradients of the subjects that moved
-    on_branches(accepted, [&](int i) { subs[i]->adjoint_launch(S[i].g.get()); });
+    run_phase(kPhaseAdjoint, accepted, [&](int i) { subs[i]->adjoint_compute(S[i].g.get()); });
+    for (int i : accepted) subs[i]->fetch_slots(5);
     sync_st();
     for (int i : accepted) {
       S[i].ginf = subs[i]->launched_ginf();
