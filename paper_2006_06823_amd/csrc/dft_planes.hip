@@ -295,6 +295,125 @@ __global__ __launch_bounds__(64 * WAVES) void k_reduce(PlaneReduceArgs a) {
   }
 }
 
+// ------------------------------------------------------------------ product-grid step
+// Expansion and product reduction of one plane in one pass, for the products of a band-limited
+// field e~ (1 or 3 components, plane-band inputs T) with node fields on the product grid:
+//   part[f][x0] = P1 (prod_f(x0, ., .)) P2^T,  prod_f = e div v, e G_j  (MODE kRedV1Products)
+//                                              e_c div v, sum_i e_i G_{3i+j}  (kRedV3Products).
+// One workgroup per (output field f, plane x0); wave w owns the grid tile (x1 tile s, x2 tile t) of
+// 32 x 32 nodes.  It expands the e components f needs on its tile (V = T W1t, then D = V^T W2t, the
+// accumulator of the first read as the A operand of the second), multiplies by the node fields in
+// registers, and contracts the tile with P1 over its rows (the product's registers as the A operand)
+// and with P2 over its columns; the tiles' partials are summed in LDS in wave order.  The expanded
+// field never goes to memory.  Ragged tiles need no test, as in the separate kernels: grid entries past
+// n1 / n2 are finite and meet rows of P1t / P2t past their ends, which read as zeros.
+template <int MODE, int KT1, int KT2, int JB, bool EXACT>
+__global__ __launch_bounds__(512) void k_prod_plane(ProdPlaneArgs a) {
+  extern __shared__ float red[];  // [waves][KT1 KT2][16][64]
+  constexpr int NE = MODE == kRedV1Products ? 1 : 3;
+  const int lane = threadIdx.x & 63, i = lane & 31, kh = lane >> 5;
+  const int wave = uniform(threadIdx.x >> 6), nw = blockDim.x >> 6;
+  const int n1 = a.n1, n2 = a.n2, k1 = a.k1, k2 = a.k2, J1 = EXACT ? JB : k1 >> 1;
+  const int T2 = (n2 + 31) >> 5;
+  const int f = blockIdx.x / a.n0, x0 = blockIdx.x - f * a.n0;
+  const int s = wave / T2, t = wave - s * T2;
+  const int x1 = s * 32 + i, x2 = t * 32 + i;
+  const unsigned P = (unsigned)a.P, pbase = (unsigned)(x0 * n1 * n2);
+  const Rsrc r1 = rsrc(a.w1t, (int64_t)k1 * n1), r2 = rsrc(a.w2t, (int64_t)k2 * n2);
+  const Rsrc rp1 = rsrc(a.p1t, (int64_t)n1 * k1), rp2 = rsrc(a.p2t, (int64_t)n2 * k2);
+  const Rsrc rdiv = rsrc(a.divv, a.P), rG = rsrc(a.G, (int64_t)(MODE == kRedV1Products ? 3 : 9) * a.P);
+  // node offsets of this lane's accumulator rows
+  unsigned pr[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) pr[r] = pbase + (unsigned)((s * 32 + acc_row(r, lane)) * n2 + x2);
+  // the e components this output reads: V1 e; V3 f < 3 e_f, f >= 3 all three
+  const int c0 = (MODE == kRedV3Products && f < 3) ? f : 0;
+  const int ne = (MODE == kRedV3Products && f >= 3) ? 3 : 1;
+  // node-field factors of each e component at this lane's nodes (requested before the expansion)
+  float gf[NE][16];
+#pragma unroll
+  for (int c = 0; c < NE; ++c)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      unsigned q;
+      if constexpr (MODE == kRedV1Products) q = f == 0 ? kOut : (unsigned)(f - 1) * P + pr[r];
+      else q = f < 3 ? kOut : (unsigned)(3 * c + f - 3) * P + pr[r];
+      gf[c][r] = c < ne ? (q == kOut ? bload(rdiv, pr[r]) : bload(rG, q)) : 0.f;
+    }
+  f32x16 Y;
+  zero16(Y);
+#pragma unroll
+  for (int c = 0; c < NE; ++c) {
+    if (c >= ne) break;
+    const Rsrc rT = rsrc(a.T[c0 + c] + x0 * (k1 * k2), (int64_t)(a.n0 - x0) * k1 * k2);
+    // V[a2][x1] = sum_a1 T[a1][a2] W1t[a1][x1]
+    f32x16 V[KT2];
+#pragma unroll
+    for (int q = 0; q < KT2; ++q) {
+      zero16(V[q]);
+      const int a2 = q * 32 + i;
+#pragma unroll
+      for (int j = 0; j < JB; ++j) {
+        const bool ok = EXACT || j < J1;
+        const float ta = bload_if(rT, (unsigned)((kh * J1 + j) * k2 + a2), ok);
+        const float wb = bload_if(r1, (unsigned)((kh * J1 + j) * n1 + x1), ok);
+        V[q] = mfma(ta, wb, V[q]);
+      }
+    }
+    // D[x1][x2] = sum_a2 V[a2][x1] W2t[a2][x2]
+    f32x16 D;
+    zero16(D);
+#pragma unroll
+    for (int q = 0; q < KT2; ++q)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) D = mfma(V[q][r], bload(r2, (unsigned)((q * 32 + acc_row(r, lane)) * n2 + x2)), D);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) Y[r] += D[r] * gf[c][r];
+  }
+  // W[x2][a1] = sum_x1 Y[x1][x2] P1t[x1][a1] over the tile's rows
+  f32x16 W[KT1];
+#pragma unroll
+  for (int p = 0; p < KT1; ++p) {
+    zero16(W[p]);
+    const int a1 = p * 32 + i;
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+      W[p] = mfma(Y[r], bload_if(rp1, (unsigned)((s * 32 + acc_row(r, lane)) * k1 + a1), a1 < k1), W[p]);
+  }
+  // R[a1][a2] = sum_x2 W[x2][a1] P2t[x2][a2] over the tile's columns
+  f32x16 R[KT1][KT2];
+#pragma unroll
+  for (int q = 0; q < KT2; ++q) {
+    const int a2 = q * 32 + i;
+    float pc[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) pc[r] = bload_if(rp2, (unsigned)((t * 32 + acc_row(r, lane)) * k2 + a2), a2 < k2);
+#pragma unroll
+    for (int p = 0; p < KT1; ++p) {
+      zero16(R[p][q]);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) R[p][q] = mfma(W[p][r], pc[r], R[p][q]);
+    }
+  }
+  constexpr int TILES = KT1 * KT2;
+#pragma unroll
+  for (int p = 0; p < KT1; ++p)
+#pragma unroll
+    for (int q = 0; q < KT2; ++q)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) red[((wave * TILES + p * KT2 + q) * 16 + r) * 64 + lane] = R[p][q][r];
+  __syncthreads();
+  float* __restrict__ part = a.part + (size_t)blockIdx.x * (k1 * k2);
+  for (int e = threadIdx.x; e < TILES * 16 * 64; e += blockDim.x) {
+    const int l = e & 63, r = (e >> 6) & 15, tile = e >> 10;
+    const int p = tile / KT2, q = tile - p * KT2;
+    float sum = 0.f;
+    for (int w = 0; w < nw; ++w) sum += red[(w * TILES * 16) * 64 + e];
+    const int a1 = p * 32 + acc_row(r, l), a2 = q * 32 + (l & 31);
+    if (a1 < k1 && a2 < k2) part[a1 * k2 + a2] = sum;
+  }
+}
+
 // ------------------------------------------------------------------ first axis
 // Workgroup (column tile of 32 band columns (a1, a2), row y) with the descriptor row[y] resolved on the
 // host: F of field row.f (if any): r[a0][c] = sum_x0 P0t[x0][a0] part[x0][c] (x0 in chunks of 8 dealt
@@ -512,6 +631,55 @@ void plane_reduce(const PlaneReduceArgs& a, hipStream_t s) {
     case kRedV3Source: return reduce_mode<kRedV3Source>(a, s, bytes, flops);
     default: throw ArgError("plane_reduce: unknown mode");
   }
+}
+
+// one wave per 32 x 32 tile of a plane (at most 8), their partials in at most 64 KB of LDS
+bool prod_plane_ok(const Dims& d) {
+  const int tiles = ceil_div(d.n[1], 32) * ceil_div(d.n[2], 32);
+  const int kt = (d.k[1] > 32 ? 2 : 1) * (d.k[2] > 32 ? 2 : 1);
+  return planes_ok(d) && tiles <= 8 && (size_t)tiles * kt * 4096 <= 64 * 1024;
+}
+
+void plane_prod(const ProdPlaneArgs& a, hipStream_t s) {
+  const int tiles = ceil_div(a.n1, 32) * ceil_div(a.n2, 32);
+  const int kt1 = a.k1 > 32 ? 2 : 1, kt2 = a.k2 > 32 ? 2 : 1;
+  if (tiles > 8 || (size_t)tiles * kt1 * kt2 * 4096 > 64 * 1024) throw ArgError("plane_prod: plane too large");
+  if (a.P >= (int64_t(1) << 31)) throw ArgError("plane_prod: field too large");
+  const int nf = a.mode == kRedV1Products ? 4 : 6;
+  const int ne = a.mode == kRedV1Products ? 1 : 3;
+  const double bytes = 4.0 * a.n0 * (ne * (double)a.k1 * a.k2 + nf * (double)a.k1 * a.k2) +
+                       4.0 * a.P * (a.mode == kRedV1Products ? 4 : 10);
+  const double flops = 2.0 * nf * a.n0 *
+                       ((double)a.k1 * a.k2 * a.n1 + (double)a.n1 * a.k2 * a.n2 + (double)a.n1 * a.n2 * a.k1 +
+                        (double)a.k1 * a.n2 * a.k2);
+  dim3 g(static_cast<unsigned>(nf * a.n0));
+  const dim3 b(64 * tiles);
+  const size_t lds = (size_t)tiles * kt1 * kt2 * 4096;
+  const int j1 = a.k1 / 2;
+  const bool ex = j1 == 16 || j1 == 20 || j1 == 24 || j1 == 32;
+  const int jb = ex ? j1 : jb_of(j1);
+  auto go = [&](auto kern) { prof::launch("k_prod_plane", bytes, flops, kern, g, b, lds, s, a); };
+  // instantiated for the bands of the configurations; other bands take the general form (jb = 32)
+  auto pick = [&](auto mode) {
+    constexpr int M = decltype(mode)::value;
+    if (kt1 == 1 && kt2 == 1) {
+      if (ex && jb == 16) go(k_prod_plane<M, 1, 1, 16, true>);
+      else go(k_prod_plane<M, 1, 1, 16, false>);
+    } else if (kt1 == 2 && kt2 == 1) {
+      if (ex && jb == 24) go(k_prod_plane<M, 2, 1, 24, true>);
+      else go(k_prod_plane<M, 2, 1, 32, false>);
+    } else if (kt1 == 1 && kt2 == 2) {
+      if (ex && jb == 16) go(k_prod_plane<M, 1, 2, 16, true>);
+      else go(k_prod_plane<M, 1, 2, 16, false>);
+    } else {
+      if (ex && jb == 24) go(k_prod_plane<M, 2, 2, 24, true>);
+      else go(k_prod_plane<M, 2, 2, 32, false>);
+    }
+  };
+  if (a.mode == kRedV1Products) pick(std::integral_constant<int, kRedV1Products>{});
+  else if (a.mode == kRedV3Products) pick(std::integral_constant<int, kRedV3Products>{});
+  else throw ArgError("plane_prod: unknown mode");
+  LDDMM_LAUNCH_CHECK();
 }
 
 void plane_axis0(const Axis0Args& a, hipStream_t s) {

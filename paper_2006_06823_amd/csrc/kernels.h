@@ -70,6 +70,20 @@ struct PlaneReduceArgs {
   int64_t P;          // grid points per field
   int64_t e_node;     // sources: offset of node n's dv (0: one dv for every node; 3 P: a dv per node)
 };
+// expansion of e~ (T, 1 or 3 components) and reduction of its products with node fields in one pass
+// per plane (product grid): part[f][x0] as PlaneReduceArgs in the modes kRedV1Products / kRedV3Products
+struct ProdPlaneArgs {
+  const float* T[3];  // [n0][k1][k2] per component of e~
+  const float* w1t;   // [k1][n1]
+  const float* w2t;   // [k2][n2]
+  const float* divv;  // div v
+  const float* G;     // v1: G_n [3]; v3: D u_n [9]
+  const float* p1t;   // [n1][k1]
+  const float* p2t;   // [n2][k2]
+  float* part;        // [nf][n0][k1][k2]
+  int mode, n0, n1, n2, k1, k2;
+  int64_t P;
+};
 // first-axis stages (see dft_planes.hip): F finishes nin projections, P forms nout plane-band arrays
 struct Axis0Out {
   const float* w0t;  // [k0][n0t] first-axis expansion matrix of the target grid
@@ -128,6 +142,8 @@ bool planes_ok(const Dims& d);
 void plane_expand(const PlaneExpandArgs& a, hipStream_t s);
 void plane_reduce(const PlaneReduceArgs& a, hipStream_t s);
 void plane_axis0(const Axis0Args& a, hipStream_t s);
+bool prod_plane_ok(const Dims& d);
+void plane_prod(const ProdPlaneArgs& a, hipStream_t s);
 
 // ---- band-limited coefficient kernels (grid.hip) ----------------------------
 // out = a x + b y (n elements; y may be null when b == 0)

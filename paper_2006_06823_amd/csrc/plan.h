@@ -106,6 +106,7 @@ class Plan {
       const int64_t slabs = (int64_t)kMaxFields * d_.k[0];
       pipart_.alloc(slabs * pi_ba_splits(d_.n[1]) * d_.k[1] * d_.k[2]);
       planes_ = !bf16_ && planes_ok(d_) && std::getenv("LDDMM_BL_NO_PLANES") == nullptr;
+      prod_fused_ = planes_ && prod_plane_ok(d_) && std::getenv("LDDMM_BL_NO_PROD_FUSE") == nullptr;
       if (planes_) {
         Tp_.alloc(2 * kMaxFields * d_.n[0] * C());
         LDDMM_HIP(hipMemset(Tp_.get(), 0, Tp_.size() * sizeof(float)));
@@ -155,6 +156,22 @@ class Plan {
     a.mode = mode, a.nf = nf, a.n0 = d_.n[0], a.n1 = d_.n[1], a.n2 = d_.n[2], a.k1 = d_.k[1], a.k2 = d_.k[2];
     a.P = d_.P;
     plane_reduce(a, s());
+  }
+  // expansion of the e~ components in Tbuf(0 ..) fused with the reduction of their products with node
+  // fields (kRedV1Products: 4 outputs, kRedV3Products: 6) into part(0 ..), when prod_fused()
+  bool prod_fused() const { return prod_fused_; }
+  void prod_reduce(int mode, const float* divv, const float* G) {
+    const int nf = mode == kRedV1Products ? 4 : 6, ne = mode == kRedV1Products ? 1 : 3;
+    reserve_parts(nf);
+    ProdPlaneArgs a{};
+    for (int c = 0; c < ne; ++c) a.T[c] = Tbuf(c);
+    a.w1t = mat(1, kPlainT), a.w2t = mat(2, kPlainT);
+    a.divv = divv, a.G = G;
+    a.p1t = mat(1, kProjT), a.p2t = mat(2, kProjT);
+    a.part = part_.get();
+    a.mode = mode, a.n0 = d_.n[0], a.n1 = d_.n[1], a.n2 = d_.n[2], a.k1 = d_.k[1], a.k2 = d_.k[2];
+    a.P = d_.P;
+    plane_prod(a, s());
   }
   // pi of nf stacked grid fields into bl with the reductions' plane-band partials in a caller-given
   // workspace of cap floats (float plane-wise path only)
@@ -420,7 +437,7 @@ class Plan {
   }
 
   Dims d_{};
-  bool bf16_ = false, planes_ = false;
+  bool bf16_ = false, planes_ = false, prod_fused_ = false;
   const hipStream_t* st_ = nullptr;
   int64_t mat_off_[3][kNumMats] = {};
   DevBuf<T> mats_, t1_, t2_, stk_, blC_;

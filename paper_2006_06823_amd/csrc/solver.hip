@@ -444,9 +444,17 @@ class Solver final : public SolverBase {
       if (sm_.planes()) {
         const bool v1 = nc == 1;
         const int nc = v1 ? 1 : 3, np = v1 ? 4 : 6;
-        sm_.iota_kind(x, es_.get(), nc, kPlain);
-        sm_.reduce(v1 ? kRedV1Products : kRedV3Products, np, nullptr, es_.get(), divvsN(n),
-                   v1 ? Gs_.get() + (int64_t)n * 3 * ds_.P : Dus_.get() + (int64_t)n * 9 * ds_.P);
+        const float* Gn = v1 ? Gs_.get() + (int64_t)n * 3 * ds_.P : Dus_.get() + (int64_t)n * 9 * ds_.P;
+        if (sm_.prod_fused()) {  // plane-band inputs of x, then expansion and reduction in one pass
+          Axis0Args t = sm_.axis0_args(0);
+          t.nout = nc;
+          for (int c = 0; c < nc; ++c) t.o[c] = sm_.target(c, kPlain, -1, x + c * d_.Q, 1.f);
+          plane_axis0(t, st_);
+          sm_.prod_reduce(v1 ? kRedV1Products : kRedV3Products, divvsN(n), Gn);
+        } else {
+          sm_.iota_kind(x, es_.get(), nc, kPlain);
+          sm_.reduce(v1 ? kRedV1Products : kRedV3Products, np, nullptr, es_.get(), divvsN(n), Gn);
+        }
         Axis0Args a = sm_.axis0_args(np);
         for (int f = 0; f < np; ++f) a.out[f] = dst[f], a.alpha[f] = al[f], a.beta[f] = be[f];
         plane_axis0(a, st_);
@@ -1148,10 +1156,15 @@ class Solver final : public SolverBase {
       float* xn = traj + n * stride;
       const float w = term_w(n);
       const int64_t off = node_off(n);
-      // products on the product grid: fl = x * div~ v~ and the Hessian / gradient terms
-      sm_.expand_kind(nc, kPlain, es_.get());
-      sm_.reduce(v1 ? kRedV1Products : kRedV3Products, np, nullptr, es_.get(), divvsN(n),
-                 v1 ? Gs_.get() + (int64_t)n * 3 * ds_.P : Dus_.get() + (int64_t)n * 9 * ds_.P);
+      // products on the product grid: fl = x * div~ v~ and the Hessian / gradient terms (expansion and
+      // reduction fused into one pass per plane where the plane fits)
+      const float* Gn = v1 ? Gs_.get() + (int64_t)n * 3 * ds_.P : Dus_.get() + (int64_t)n * 9 * ds_.P;
+      if (sm_.prod_fused()) {
+        sm_.prod_reduce(v1 ? kRedV1Products : kRedV3Products, divvsN(n), Gn);
+      } else {
+        sm_.expand_kind(nc, kPlain, es_.get());
+        sm_.reduce(v1 ? kRedV1Products : kRedV3Products, np, nullptr, es_.get(), divvsN(n), Gn);
+      }
       Axis0Args a = sm_.axis0_args(np);
       for (int c = 0; c < nc; ++c) a.out[c] = blA_.get() + c * Q, a.alpha[c] = 1.f;
       for (int j = 0; j < 3; ++j) {
