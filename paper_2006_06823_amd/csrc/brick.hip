@@ -61,43 +61,123 @@ __device__ __forceinline__ int wrapi(int i, int n) {
   return i < 0 ? i + n : i;
 }
 
-// 64-tap evaluation from the LDS brick; s* are brick-relative first-tap indices
+// Cubic B-spline weights of a tap offset t in [0, 1): w3 = t^3/6, w0 = (1-t)^3/6, w1 = 2/3 - t^2 (1 - t/2),
+// and w2 from the partition of unity (12 operations instead of the polynomial forms' 15).
+__device__ __forceinline__ void brick_weights(float t, float w[4]) {
+  const float t2 = t * t, u = 1.f - t;
+  w[3] = t2 * (t * (1.f / 6.f));
+  w[0] = (u * u) * (u * (1.f / 6.f));
+  w[1] = fmaf(t2, fmaf(t, 0.5f, -1.f), 2.f / 3.f);
+  w[2] = 1.f - w[0] - w[1] - w[3];
+}
+
+// LDS views of the brick: with the address space explicit, tap addresses stay 32-bit and the rows of a
+// stencil are reached by immediate offsets from one base per node
+typedef const __attribute__((address_space(3))) float lds_float;
+typedef const __attribute__((address_space(3))) unsigned long long lds_pair;  // two interleaved floats
+
+// 64-tap evaluation from the LDS brick at the brick-relative first tap (s0, s1, s2).  The stencil is read
+// in four slabs of 4 x 4 taps (first index a), the next slab's reads issued before the current one is
+// summed; empty asm statements (no instruction) keep the compiler from moving a slab's sums below the
+// next slab's reads.
 template <int B1, int B2>
-__device__ __forceinline__ float eval_brick(const float* __restrict__ br, int s0, int s1, int s2, const float w0[4],
+__device__ __forceinline__ float eval_brick(const float* br, int s0, int s1, int s2, const float w0[4],
                                             const float w1[4], const float w2[4]) {
+  lds_float* p = (lds_float*)br + ((s0 * B1 + s1) * B2 + s2);
+  float v[2][4][4];
+  auto load = [&](int a, float (&d)[4][4]) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) d[b][c] = p[(a * B1 + b) * B2 + c];
+  };
+  load(0, v[0]);
   float acc = 0.f;
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
+    if (a < 3) load(a + 1, v[(a + 1) & 1]);
+    const float(&d)[4][4] = v[a & 1];
     float sa = 0.f;
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const float* row = br + ((s0 + a) * B1 + (s1 + b)) * B2 + s2;
-      sa += w1[b] * (w2[0] * row[0] + w2[1] * row[1] + w2[2] * row[2] + w2[3] * row[3]);
-    }
+    for (int b = 0; b < 4; ++b) sa += w1[b] * (w2[0] * d[b][0] + w2[1] * d[b][1] + w2[2] * d[b][2] + w2[3] * d[b][3]);
     acc += w0[a] * sa;
+    asm volatile("" : "+v"(acc)::"memory");
   }
   return acc;
 }
 
-// two fields stored interleaved (float2): one LDS read per tap serves both
+// two fields stored interleaved (float2): one LDS read per tap serves both, and the products
+// w1[b] w2[c] are formed once for the two
 template <int B1, int B2>
-__device__ __forceinline__ float2 eval_brick2(const float2* __restrict__ br, int s0, int s1, int s2, const float w0[4],
+__device__ __forceinline__ float2 eval_brick2(const float2* br, int s0, int s1, int s2, const float w0[4],
                                               const float w1[4], const float w2[4]) {
+  lds_pair* p = (lds_pair*)br + ((s0 * B1 + s1) * B2 + s2);
+  float w12[4][4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) w12[b][c] = w1[b] * w2[c];
+  float2 v[2][4][4];
+  auto load = [&](int a, float2 (&d)[4][4]) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) d[b][c] = __builtin_bit_cast(float2, p[(a * B1 + b) * B2 + c]);
+  };
+  load(0, v[0]);
   float ax = 0.f, ay = 0.f;
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
+    if (a < 3) load(a + 1, v[(a + 1) & 1]);
+    const float2(&d)[4][4] = v[a & 1];
     float sx = 0.f, sy = 0.f;
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const float2* row = br + ((s0 + a) * B1 + (s1 + b)) * B2 + s2;
-      const float2 r0 = row[0], r1 = row[1], r2 = row[2], r3 = row[3];
-      sx += w1[b] * (w2[0] * r0.x + w2[1] * r1.x + w2[2] * r2.x + w2[3] * r3.x);
-      sy += w1[b] * (w2[0] * r0.y + w2[1] * r1.y + w2[2] * r2.y + w2[3] * r3.y);
-    }
-    ax += w0[a] * sx;
-    ay += w0[a] * sy;
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        sx = fmaf(w12[b][c], d[b][c].x, sx);
+        sy = fmaf(w12[b][c], d[b][c].y, sy);
+      }
+    ax = fmaf(w0[a], sx, ax);
+    ay = fmaf(w0[a], sy, ay);
+    asm volatile("" : "+v"(ax), "+v"(ay)::"memory");
   }
   return make_float2(ax, ay);
+}
+
+// GS fields stored one after the other (stride VOL): each slab's reads of every field are issued
+// together, and the products w1[b] w2[c] are shared by the fields
+template <int GS, int B1, int B2, int VOL>
+__device__ __forceinline__ void eval_brick_n(const float* br, int s0, int s1, int s2, const float w0[4],
+                                             const float w1[4], const float w2[4], float out[GS]) {
+  lds_float* p = (lds_float*)br + ((s0 * B1 + s1) * B2 + s2);
+  float w12[4][4];
+#pragma unroll
+  for (int b = 0; b < 4; ++b)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) w12[b][c] = w1[b] * w2[c];
+#pragma unroll
+  for (int k = 0; k < GS; ++k) out[k] = 0.f;
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    float d[GS][4][4];
+#pragma unroll
+    for (int k = 0; k < GS; ++k)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) d[k][b][c] = p[k * VOL + (a * B1 + b) * B2 + c];
+#pragma unroll
+    for (int k = 0; k < GS; ++k) {
+      float sk = 0.f;
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) sk = fmaf(w12[b][c], d[k][b][c], sk);
+      out[k] = fmaf(w0[a], sk, out[k]);
+      asm volatile("" : "+v"(out[k])::"memory");
+    }
+  }
 }
 
 // (the grid sizes go by value: a reference would put the caller's Grid3 on the stack, a 24-byte
@@ -188,7 +268,29 @@ __global__ __launch_bounds__(TL::NTHR) void k_brick(Epi epi, const float* __rest
   constexpr int NIT = (NPT + NTHR - 1) / NTHR;
   float v[NIT][GS];
   __syncthreads();  // row offsets and columns tabulated
+  // fields below 2^29 nodes are read through raw buffer loads (one resource per field, 32-bit byte
+  // offsets: no 64-bit address arithmetic per staged point)
+  const bool rawbuf = g.P < (int64_t(1) << 29);
   auto load_group = [&](int grp) {
+    if (rawbuf) {
+      __amdgpu_buffer_rsrc_t rs[GS];
+#pragma unroll
+      for (int k = 0; k < GS; ++k)
+        rs[k] = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(coef + Epi::field(grp, k) * g.P), (short)0,
+                                                  (int)(g.P * 4), 0x00020000);
+#pragma unroll
+      for (int it = 0; it < NIT; ++it) {
+        const int e = tid + it * NTHR;
+        if (e < NPT) {
+          const int row = e / B2, b2 = e - row * B2;
+          const unsigned off = (unsigned)(rowoff[row] + colidx[b2]) * 4u;
+#pragma unroll
+          for (int k = 0; k < GS; ++k)
+            v[it][k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs[k], (int)off, 0, 0));
+        }
+      }
+      return;
+    }
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
       const int e = tid + it * NTHR;
@@ -242,13 +344,18 @@ __global__ __launch_bounds__(TL::NTHR) void k_brick(Epi epi, const float* __rest
       const bool inb = s0 >= 0 && s0 + 3 < B0 && s1 >= 0 && s1 + 3 < B1 && s2 >= 0 && s2 + 3 < B2;
       if (inb) {
         float w0[4], w1[4], w2[4];
-        bspline_weights(x[j][0] - f0, w0);
-        bspline_weights(x[j][1] - f1, w1);
-        bspline_weights(x[j][2] - f2, w2);
+        brick_weights(x[j][0] - f0, w0);
+        brick_weights(x[j][1] - f1, w1);
+        brick_weights(x[j][2] - f2, w2);
         if constexpr (GS == 2) {
           const float2 v = eval_brick2<B1, LD2>(reinterpret_cast<const float2*>(br), s0, s1, s2, w0, w1, w2);
           epi.accum(st[j], Epi::field(grp, 0), v.x);
           epi.accum(st[j], Epi::field(grp, 1), v.y);
+        } else if constexpr (GS >= 3) {
+          float o[GS];
+          eval_brick_n<GS, B1, LD2, VOL>(br, s0, s1, s2, w0, w1, w2, o);
+#pragma unroll
+          for (int k = 0; k < GS; ++k) epi.accum(st[j], Epi::field(grp, k), o[k]);
         } else {
 #pragma unroll
           for (int k = 0; k < GS; ++k)
