@@ -395,12 +395,20 @@ def batched_leg(args):
     wall = time.perf_counter() - t0
     mv = sum(r["hess_matvecs"] for r in reps)
     vox = sum(n ** 3 for n, _, _ in subj)
+    # reference bytes of a deformation-state matvec: (27 + 59 Nt) grid fields of 4 N^3 bytes each, the
+    # per-matvec dataflow in which every kernel reads its grid inputs once
+    ref_bytes = sum(r["hess_matvecs"] * (27 + 59 * args.nt) * 4.0 * n ** 3 for r, (n, _, _) in zip(reps, subj))
+    achieved = ref_bytes / wall / 1e9
     return {"metric": "batched subject Hessian-matvecs/s", "value": round(mv / wall, 2), "unit": "matvec/s",
             "n_gpus": 1, "higher_is_better": True, "dtype": "bf16-split DFT, f32 fields, f64 reductions",
             "data": "synthetic",
             "config": {"workload": f"{B} subjects 96^3..192^3 to one template, deformation-state, Nt={args.nt}, "
                                    f"{args.batched_gn} GN x {args.batched_pcg} PCG fixed",
                        "subject_sizes": [n for n, _, _ in subj]},
+            "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
+                         "frac": round(achieved / 8000.0, 4), "traffic": None,
+                         "basis": "reference bytes of every subject's matvecs over the whole batch's wall time, "
+                                  "which also holds the state, adjoint and line-search solves"},
             "extra": {"wall_s": round(wall, 3), "status": st, "matvecs": mv,
                       "voxel_matvecs_per_s": round(mv / wall * vox / B, 1),
                       "mse_rel_mean": round(float(np.mean([r["mse_rel"] for r in reps])), 4)}}

@@ -330,7 +330,11 @@ int64_t lddmm_bl_profile_read(char* buf, int64_t len);
 /* Autotuner cache (process-wide).  The interpolation kernels of a context pick one of
  * lddmm_bl_tune_candidates("brick") workgroup tiles per grid shape and staging width
  * (fields staged together: 1, 2 or 3), timing every candidate when the first context of
- * that shape is created, under the keys "brick:<n0>x<n1>x<n2>:gs<w>".
+ * that shape is created, under the keys "brick:<n0>x<n1>x<n2>:gs<w>".  Contexts whose
+ * truncated DFT does not run the plane-wise path (LDDMM_BL_BF16_DFT) also pick one of
+ * lddmm_bl_tune_candidates("dft") workgroup caps (256, 512, 768, 1024, 1536, 2048) for each
+ * first-axis contraction shape at creation, under keys "dft:<kernel>:M<m>:L<l>:C<c>"; a
+ * shape first met later (or inside graph capture) takes the kernel's default cap.
  * tune_get returns the cached choice of a key, or -1 if none.  tune_set fixes the choice
  * of a key before a context of that shape is created (choice in [0, candidates), or -1
  * to forget it so that the next context times the candidates again); it returns
@@ -340,6 +344,11 @@ int64_t lddmm_bl_profile_read(char* buf, int64_t len);
 int32_t lddmm_bl_tune_candidates(const char* family);
 int32_t lddmm_bl_tune_get(const char* key);
 lddmm_bl_status lddmm_bl_tune_set(const char* key, int32_t choice);
+/* The cache as text, one "key=choice" line per key: lddmm_bl_tune_table(NULL, 0) takes a
+ * snapshot and returns the bytes needed (with the terminating zero, -1 on failure), then
+ * lddmm_bl_tune_table(buf, len) copies it into buf (truncated to len - 1 characters) and
+ * returns the characters copied. */
+int64_t lddmm_bl_tune_table(char* buf, int64_t len);
 
 #ifdef __cplusplus
 }

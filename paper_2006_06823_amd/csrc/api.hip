@@ -268,6 +268,7 @@ lddmm_bl_status lddmm_bl_profile_enable(int32_t on) {
 
 int32_t lddmm_bl_tune_candidates(const char* family) {
   if (family && std::strcmp(family, "brick") == 0) return lddmm::brick_tile_count();
+  if (family && std::strcmp(family, "dft") == 0) return lddmm::dft_cap_count();
   return 0;
 }
 
@@ -281,14 +282,35 @@ int32_t lddmm_bl_tune_get(const char* key) {
 }
 
 lddmm_bl_status lddmm_bl_tune_set(const char* key, int32_t choice) {
-  if (!key || std::strncmp(key, "brick:", 6) != 0) return LDDMM_BL_E_ARG;
-  if (choice < -1 || choice >= lddmm::brick_tile_count()) return LDDMM_BL_E_ARG;
+  if (!key) return LDDMM_BL_E_ARG;
+  int ncand = 0;
+  if (std::strncmp(key, "brick:", 6) == 0) ncand = lddmm::brick_tile_count();
+  else if (std::strncmp(key, "dft:", 4) == 0) ncand = lddmm::dft_cap_count();
+  else return LDDMM_BL_E_ARG;
+  if (choice < -1 || choice >= ncand) return LDDMM_BL_E_ARG;
   try {
     lddmm::tune::set(key, choice);
   } catch (...) {
     return LDDMM_BL_E_HIP;
   }
   return LDDMM_BL_OK;
+}
+
+int64_t lddmm_bl_tune_table(char* buf, int64_t len) {
+  static std::string last;
+  if (buf == nullptr || len <= 0) {
+    try {
+      last.clear();
+      for (const auto& kv : lddmm::tune::table()) last += kv.first + "=" + std::to_string(kv.second) + "\n";
+    } catch (...) {
+      return -1;
+    }
+    return static_cast<int64_t>(last.size()) + 1;
+  }
+  const int64_t n = std::min<int64_t>(len - 1, static_cast<int64_t>(last.size()));
+  std::memcpy(buf, last.data(), static_cast<size_t>(n));
+  buf[n] = 0;
+  return n;
 }
 
 int64_t lddmm_bl_profile_read(char* buf, int64_t len) {

@@ -11,8 +11,10 @@
 #include "kernels.h"
 #include "prof.h"
 #include "stage.h"
+#include "tune.h"
 
 #include <algorithm>
+#include <string>
 #include <type_traits>
 
 namespace lddmm {
@@ -524,7 +526,18 @@ __global__ __launch_bounds__(256) void dft_left_expand_bf16(const float* __restr
   }
 }
 
+// Workgroup caps of the first-axis launches that walk several column tiles per workgroup: the
+// autotuner picks one per kernel, element type and (M, L, C) shape (the total number of workgroups
+// decides how many rounds the grid takes and how often each W tile is staged).
+constexpr int kCaps[] = {256, 512, 768, 1024, 1536, 2048};
+constexpr int kNumCaps = sizeof(kCaps) / sizeof(kCaps[0]);
+std::string cap_key(const char* kern, int M, int L, int C) {
+  return std::string("dft:") + kern + ":M" + std::to_string(M) + ":L" + std::to_string(L) + ":C" + std::to_string(C);
+}
+
 }  // namespace
+
+int dft_cap_count() { return kNumCaps; }
 
 void dft_left_bf16(const float* in, float* out, const FieldMats<float>& W, int nb, int bpf, int M, int L, int C,
                    int64_t sIb, int64_t sOb, hipStream_t s) {
@@ -544,11 +557,14 @@ void dft_left_bf16(const float* in, float* out, const FieldMats<float>& W, int n
   } else if (L <= 64) {
     const uint32_t sm = (uint32_t)128 * (L + 1) * sizeof(float);
     const int ncb = ceil_div(C, 32), gy = ceil_div(M, 128);
-    // at most 768 workgroups (the 3 per CU its registers allow), each walking several column tiles
-    // with its W tile staged once (32 uneven subjects: 85 -> 90 subject-matvecs/s)
-    dim3 g(std::max(1, std::min(ncb, 768 / std::max(1, nb * gy))), gy, nb);
-    prof::launch("dft_left_expand_bf16", bytes, flops, dft_left_expand_bf16, g, dim3(256), sm, s, in, out, W, bpf, M,
-                 L, C, sIb, sOb);
+    // at most cap workgroups, each walking several column tiles with its W tile staged once (default
+    // 768, the 3 per CU its registers allow: 32 uneven subjects 85 -> 90 subject-matvecs/s)
+    auto run = [&](int cap) {
+      dim3 g(std::max(1, std::min(ncb, cap / std::max(1, nb * gy))), gy, nb);
+      prof::launch("dft_left_expand_bf16", bytes, flops, dft_left_expand_bf16, g, dim3(256), sm, s, in, out, W, bpf,
+                   M, L, C, sIb, sOb);
+    };
+    run(tune::choose(cap_key("expand_bf16", M, L, C), kCaps, kNumCaps, 768, run, s));
   } else {
     return dft_left<float>(in, out, W, nb, bpf, M, L, C, sIb, sOb, s);
   }
@@ -572,15 +588,20 @@ void dft_left(const T* in, T* out, const FieldMats<T>& W, int nb, int bpf, int M
       // the two-tile kernel's registers leave room for 2 blocks per CU: at most 512 blocks keeps the
       // grid resident in one round, each block walking several column tiles with its W tile
       // (1024 ran a second round: 160x192x160 contraction 2.10 -> 1.86 ms per matvec)
-      const int cap = MB == 2 ? 512 : 1024;
-      const int gx = sep ? std::max(1, std::min(ncb, cap / std::max(1, nb))) : ncb;
-      dim3 g(gx, 1, nb);
-      if (MB == 2)
-        prof::launch("dft_left_contract<2>", bytes, flops, dft_left_contract<2, 2>, g, dim3(256), sm, s, in, out, W,
-                     bpf, M, L, C, sIb, sOb, sep);
-      else
-        prof::launch("dft_left_contract<1>", bytes, flops, dft_left_contract<1, 2>, g, dim3(256), sm, s, in, out, W,
-                     bpf, M, L, C, sIb, sOb, sep);
+      auto run = [&](int cap) {
+        const int gx = sep ? std::max(1, std::min(ncb, cap / std::max(1, nb))) : ncb;
+        dim3 g(gx, 1, nb);
+        if (MB == 2)
+          prof::launch("dft_left_contract<2>", bytes, flops, dft_left_contract<2, 2>, g, dim3(256), sm, s, in, out,
+                       W, bpf, M, L, C, sIb, sOb, sep);
+        else
+          prof::launch("dft_left_contract<1>", bytes, flops, dft_left_contract<1, 2>, g, dim3(256), sm, s, in, out,
+                       W, bpf, M, L, C, sIb, sOb, sep);
+      };
+      const int dflt = MB == 2 ? 512 : 1024;
+      run(sep ? tune::choose(cap_key(MB == 2 ? "contract2_f32" : "contract1_f32", M, L, C), kCaps, kNumCaps, dflt,
+                             run, s)
+              : dflt);
       LDDMM_LAUNCH_CHECK();
       return;
     }
@@ -590,11 +611,14 @@ void dft_left(const T* in, T* out, const FieldMats<T>& W, int nb, int bpf, int M
       // at most 1024 blocks (4 per CU): the whole grid is resident at once and each block walks
       // several column tiles with its W tile staged once (2048 left a second, partial round:
       // 160x192x160 expansion 1.45 -> 1.22 ms per matvec)
-      const int gx = std::max(1, std::min(ncb, 1024 / std::max(1, nb * gy)));
       const int vec = (C % 4 == 0) && (sIb % 4 == 0) && (reinterpret_cast<uintptr_t>(in) % 16 == 0);
-      dim3 g(gx, gy, nb);
-      prof::launch("dft_left_expand", bytes, flops, dft_left_expand, g, dim3(256), sm, s, in, out, W, bpf, M, L, C,
-                   sIb, sOb, vec);
+      auto run = [&](int cap) {
+        const int gx = std::max(1, std::min(ncb, cap / std::max(1, nb * gy)));
+        dim3 g(gx, gy, nb);
+        prof::launch("dft_left_expand", bytes, flops, dft_left_expand, g, dim3(256), sm, s, in, out, W, bpf, M, L, C,
+                     sIb, sOb, vec);
+      };
+      run(tune::choose(cap_key("expand_f32", M, L, C), kCaps, kNumCaps, 1024, run, s));
       LDDMM_LAUNCH_CHECK();
       return;
     }

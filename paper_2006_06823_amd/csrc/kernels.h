@@ -231,6 +231,7 @@ void copy_dev(T* dst, const T* src, int64_t n, hipStream_t s);
 // ---- LDS-brick interpolation, float 3D grids (brick.hip) ---------------------
 bool brick_ok(const Dims& d);
 int brick_tile_count();  // workgroup tile candidates of the brick kernels
+int dft_cap_count();     // workgroup-cap candidates of the first-axis DFT launches
 // times every brick tile shape on this grid (one- and two-field interpolations into `out` at a smooth
 // synthetic sub-voxel displacement written to the scratch `disp`) and caches the fastest
 void brick_autotune(float* out, const float* coef, float* disp, const Dims& d, hipStream_t s);

@@ -47,6 +47,7 @@
 
 #include "prof.h"
 #include "solver.h"
+#include "tune.h"
 
 namespace lddmm {
 
@@ -98,13 +99,27 @@ class Solver final : public SolverBase {
     autotune();
   }
 
-  // Pick the brick tile for this grid shape once per process (timed on zeroed scratch fields).
+  // Pick the brick tile for this grid shape, and the workgroup caps of the first-axis DFT launches of
+  // plans that do not run the plane-wise path (split-bf16), once per process (timed on zeroed scratch
+  // fields, three components as in the velocity and displacement transforms).
   void autotune() {
     if constexpr (std::is_same_v<T, float>) {
-      if (!brick_ok(d_) || std::getenv("LDDMM_BL_NO_TUNE")) return;
-      zero(S(0), 3 * d_.P, st_);
-      zero(Xb_.get(), 3 * d_.P, st_);
-      brick_autotune(S(3), S(0), Xb_.get(), d_, st_);
+      if (std::getenv("LDDMM_BL_NO_TUNE")) return;
+      if (brick_ok(d_)) {
+        zero(S(0), 3 * d_.P, st_);
+        zero(Xb_.get(), 3 * d_.P, st_);
+        brick_autotune(S(3), S(0), Xb_.get(), d_, st_);
+      }
+      if (!full_.planes() || !sm_.planes()) {
+        tune::Collect scope;
+        zero(S(0), 3 * d_.P, st_);
+        zero(tmpbl_.get(), 3 * d_.Q, st_);
+        full_.iota_kind(tmpbl_.get(), S(0), 3, kPlain);
+        full_.pi(S(0), tmpbl_.get(), 3);
+        zero(Ps(0), 3 * ds_.P, st_);
+        sm_.iota_kind(tmpbl_.get(), Ps(0), 3, kPlain);
+        sm_.pi(Ps(0), tmpbl_.get(), 3);
+      }
       sync();
     }
   }

@@ -53,6 +53,30 @@ int pick(int ncand, const std::function<void(int)>& run, hipStream_t s, int reps
   return best;
 }
 
+namespace {
+thread_local int t_collect = 0;
+}
+
+Collect::Collect() { ++t_collect; }
+Collect::~Collect() { --t_collect; }
+
+bool collecting(hipStream_t s) {
+  if (t_collect == 0) return false;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess) return false;
+  return cs == hipStreamCaptureStatusNone;
+}
+
+int choose(const std::string& key, const int* cand, int n, int dflt, const std::function<void(int)>& run,
+           hipStream_t s) {
+  const int c = get(key, -1);
+  if (c >= 0 && c < n) return cand[c];
+  if (!collecting(s)) return dflt;
+  const int best = pick(n, [&](int i) { run(cand[i]); }, s);
+  set(key, best);
+  return cand[best];
+}
+
 std::vector<std::pair<std::string, int>> table() {
   std::lock_guard<std::mutex> lk(g_mu);
   return {g_choice.begin(), g_choice.end()};

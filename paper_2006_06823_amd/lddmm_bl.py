@@ -38,7 +38,7 @@ EXPORTS = [
     "lddmm_bl_state_solve", "lddmm_bl_adjoint_solve", "lddmm_bl_hess_matvec", "lddmm_bl_gn_solve",
     "lddmm_bl_jacobian", "lddmm_bl_project", "lddmm_bl_project_noalloc", "lddmm_bl_include", "lddmm_bl_get_field", "lddmm_bl_dot",
     "lddmm_bl_profile_enable", "lddmm_bl_profile_read", "lddmm_bl_gn_solve_batched",
-    "lddmm_bl_tune_candidates", "lddmm_bl_tune_get", "lddmm_bl_tune_set",
+    "lddmm_bl_tune_candidates", "lddmm_bl_tune_get", "lddmm_bl_tune_set", "lddmm_bl_tune_table",
     "lddmm_nn_create", "lddmm_nn_info", "lddmm_nn_forward", "lddmm_nn_backward", "lddmm_nn_zero_grad",
     "lddmm_nn_step", "lddmm_nn_get", "lddmm_nn_set", "lddmm_nn_save", "lddmm_nn_load", "lddmm_nn_destroy",
     "lddmm_nn_pool_pair",
@@ -144,6 +144,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.lddmm_bl_tune_get.restype = i32
     lib.lddmm_bl_tune_set.argtypes = [ctypes.c_char_p, i32]
     lib.lddmm_bl_tune_set.restype = ctypes.c_int
+    lib.lddmm_bl_tune_table.argtypes = [ctypes.c_char_p, i64]
+    lib.lddmm_bl_tune_table.restype = i64
     lib.lddmm_bl_last_error.argtypes = [vp]
     lib.lddmm_bl_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -417,6 +419,21 @@ def tune_set(key: str, choice: int) -> None:
     st = load_library().lddmm_bl_tune_set(key.encode(), int(choice))
     if st != 0:
         raise LddmmError(st, f"lddmm_bl_tune_set({key!r}, {choice}) rejected")
+
+
+def tune_table() -> dict:
+    """The autotuner cache: {key: choice}."""
+    lib = load_library()
+    need = lib.lddmm_bl_tune_table(None, 0)
+    if need < 0:
+        raise LddmmError(-1, "lddmm_bl_tune_table failed")
+    buf = ctypes.create_string_buffer(int(need))
+    lib.lddmm_bl_tune_table(buf, need)
+    out = {}
+    for line in buf.value.decode().splitlines():
+        k, v = line.rsplit("=", 1)
+        out[k] = int(v)
+    return out
 
 
 def brick_tune_keys(n) -> list:

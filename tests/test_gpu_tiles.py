@@ -61,3 +61,40 @@ def test_every_brick_tile_matches_oracle(N, K, tile):
     finally:
         for key in L.brick_tune_keys(N):
             L.tune_set(key, -1)
+
+
+def test_dft_workgroup_caps_tuned_and_bitwise_equal():
+    """A split-bf16 context (its DFT does not run the plane-wise path) times the workgroup caps of its
+    first-axis contractions when it is created, under "dft:" keys.  A cap only changes how many column
+    tiles each workgroup walks, so every candidate gives bitwise the same state, gradient and Hessian
+    matvec: the smallest and the largest cap, forced on every such key, against the tuned choice."""
+    N, K = (96, 96, 96), (32, 32, 32)
+    I0, I1 = images(N, 11)
+    v = velocity(N, K, NT, 12)
+    dv = syn.random_bl_coefficients(3, K, 13)
+
+    def run():
+        ctx = L.Context(L.Problem(N, K, nt=NT, variant=3, precision=L.BF16_DFT))
+        dev = lambda x: torch.tensor(np.ascontiguousarray(x), dtype=torch.float32, device=ctx.device)
+        ctx.set_images(dev(I0), dev(I1))
+        E, _ = ctx.state_solve(dev(v))
+        g, _ = ctx.adjoint_solve()
+        return E, g, ctx.hess_matvec(dev(dv))
+
+    E0, g0, h0 = run()
+    keys = [k for k in L.tune_table() if k.startswith("dft:")]
+    print("dft keys:", {k: L.tune_get(k) for k in keys}, flush=True)
+    assert keys and all(0 <= L.tune_get(k) < L.tune_candidates("dft") for k in keys)
+    tuned = {k: L.tune_get(k) for k in keys}
+    try:
+        for choice in (0, L.tune_candidates("dft") - 1):
+            for k in keys:
+                L.tune_set(k, choice)
+            print(f"dft caps forced to candidate {choice}", flush=True)
+            E, g, h = run()
+            assert E == E0
+            assert torch.equal(g, g0)
+            assert torch.equal(h, h0)
+    finally:
+        for k, c in tuned.items():
+            L.tune_set(k, c)

@@ -88,7 +88,16 @@ def test_autotuner_cache_round_trip_and_rejections():
     assert L.tune_get(key) == n - 1
     L.tune_set(key, -1)
     assert L.tune_get(key) == -1
-    for bad_key, bad_choice in [("brick:7x9x11:gs2", n), ("brick:7x9x11:gs2", -2), ("dft:7x9x11", 0)]:
+    nd = L.tune_candidates("dft")
+    assert nd == 6
+    dkey = "dft:expand_bf16:M96:L32:C1024"
+    assert L.tune_get(dkey) == -1
+    L.tune_set(dkey, nd - 1)
+    assert L.tune_get(dkey) == nd - 1
+    assert L.tune_table()[dkey] == nd - 1
+    L.tune_set(dkey, -1)
+    assert L.tune_get(dkey) == -1
+    for bad_key, bad_choice in [("brick:7x9x11:gs2", n), ("brick:7x9x11:gs2", -2), (dkey, nd), ("fft:7x9x11", 0)]:
         with pytest.raises(L.LddmmError):
             L.tune_set(bad_key, bad_choice)
     assert L.brick_tune_keys((40, 36, 44)) == ["brick:40x36x44:gs1", "brick:40x36x44:gs2", "brick:40x36x44:gs3"]
