@@ -101,7 +101,10 @@ def write_traffic(d):
         for r in rows:
             key = int(r["Dispatch_Id"])
             per[key] += float(r["Counter_Value"])
-            meta[key] = (r["Kernel_Name"].replace(" ", ""), int(r["Grid_Size"]))
+            # the brick tile (an autotuner choice, which may differ between the runs) is dropped from the
+            # name: every tile writes the same fields and differs only in its halo re-reads
+            name = re.sub(r",?lddmm::\(anonymousnamespace\)::Tile<[^>]*>", "", r["Kernel_Name"].replace(" ", ""))
+            meta[key] = (name, int(r["Grid_Size"]))
         return per, meta
 
     bench = json.loads(open(os.path.join(d, "bench.json")).read().strip().splitlines()[-1])

@@ -309,7 +309,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_reduce(PlaneReduceArgs a) {
 // n1 / n2 are finite and meet rows of P1t / P2t past their ends, which read as zeros.
 template <int MODE, int KT1, int KT2, int JB, bool EXACT>
 __global__ __launch_bounds__(512) void k_prod_plane(ProdPlaneArgs a) {
-  extern __shared__ float red[];  // [waves][KT1 KT2][16][64]
+  extern __shared__ float red[];  // [ceil(waves / 2)][KT1 KT2][16][64]
   constexpr int NE = MODE == kRedV1Products ? 1 : 3;
   const int lane = threadIdx.x & 63, i = lane & 31, kh = lane >> 5;
   const int wave = uniform(threadIdx.x >> 6), nw = blockDim.x >> 6;
@@ -395,20 +395,32 @@ __global__ __launch_bounds__(512) void k_prod_plane(ProdPlaneArgs a) {
       for (int r = 0; r < 16; ++r) R[p][q] = mfma(W[p][r], pc[r], R[p][q]);
     }
   }
+  // partials summed in LDS in a fixed order: waves w < ns store theirs in slot w, then waves w >= ns add
+  // theirs to slot w - ns, then the slots are summed in order (ns = ceil(nw / 2) slots of LDS)
   constexpr int TILES = KT1 * KT2;
+  const int ns = (nw + 1) >> 1;
+  for (int half = 0; half < 2; ++half) {
+    const bool mine = half == 0 ? wave < ns : wave >= ns;
+    if (mine) {
+      const int slot = half == 0 ? wave : wave - ns;
 #pragma unroll
-  for (int p = 0; p < KT1; ++p)
+      for (int p = 0; p < KT1; ++p)
 #pragma unroll
-    for (int q = 0; q < KT2; ++q)
+        for (int q = 0; q < KT2; ++q)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) red[((wave * TILES + p * KT2 + q) * 16 + r) * 64 + lane] = R[p][q][r];
-  __syncthreads();
+          for (int r = 0; r < 16; ++r) {
+            float& d = red[((slot * TILES + p * KT2 + q) * 16 + r) * 64 + lane];
+            d = half == 0 ? R[p][q][r] : d + R[p][q][r];
+          }
+    }
+    __syncthreads();
+  }
   float* __restrict__ part = a.part + (size_t)blockIdx.x * (k1 * k2);
   for (int e = threadIdx.x; e < TILES * 16 * 64; e += blockDim.x) {
     const int l = e & 63, r = (e >> 6) & 15, tile = e >> 10;
     const int p = tile / KT2, q = tile - p * KT2;
     float sum = 0.f;
-    for (int w = 0; w < nw; ++w) sum += red[(w * TILES * 16) * 64 + e];
+    for (int w = 0; w < ns; ++w) sum += red[(w * TILES * 16) * 64 + e];
     const int a1 = p * 32 + acc_row(r, l), a2 = q * 32 + (l & 31);
     if (a1 < k1 && a2 < k2) part[a1 * k2 + a2] = sum;
   }
@@ -633,17 +645,23 @@ void plane_reduce(const PlaneReduceArgs& a, hipStream_t s) {
   }
 }
 
-// one wave per 32 x 32 tile of a plane (at most 8), their partials in at most 64 KB of LDS
+// one wave per 32 x 32 tile of a plane (at most 8), their partials in ceil(tiles / 2) slots of at
+// most 64 KB of LDS together.  The fused pass is chosen for inner bands of at most 32 (one band tile
+// per axis): with two, every workgroup's repeated expansions (each output field's workgroup expands
+// the e components it reads) cost more than the separate kernels save (160x192x160 / 40x48x40
+// deformation state: 46 us per fused launch against 30 us for the separate reduction).
+static size_t prod_plane_lds(int tiles, int kt) { return (size_t)((tiles + 1) / 2) * kt * 4096; }
 bool prod_plane_ok(const Dims& d) {
   const int tiles = ceil_div(d.n[1], 32) * ceil_div(d.n[2], 32);
   const int kt = (d.k[1] > 32 ? 2 : 1) * (d.k[2] > 32 ? 2 : 1);
-  return planes_ok(d) && tiles <= 8 && (size_t)tiles * kt * 4096 <= 64 * 1024;
+  return planes_ok(d) && tiles <= 8 && kt == 1 && prod_plane_lds(tiles, kt) <= 64 * 1024;
 }
 
 void plane_prod(const ProdPlaneArgs& a, hipStream_t s) {
   const int tiles = ceil_div(a.n1, 32) * ceil_div(a.n2, 32);
   const int kt1 = a.k1 > 32 ? 2 : 1, kt2 = a.k2 > 32 ? 2 : 1;
-  if (tiles > 8 || (size_t)tiles * kt1 * kt2 * 4096 > 64 * 1024) throw ArgError("plane_prod: plane too large");
+  if (tiles > 8 || kt1 * kt2 != 1 || prod_plane_lds(tiles, 1) > 64 * 1024)
+    throw ArgError("plane_prod: plane or band too large");
   if (a.P >= (int64_t(1) << 31)) throw ArgError("plane_prod: field too large");
   const int nf = a.mode == kRedV1Products ? 4 : 6;
   const int ne = a.mode == kRedV1Products ? 1 : 3;
@@ -654,27 +672,15 @@ void plane_prod(const ProdPlaneArgs& a, hipStream_t s) {
                         (double)a.k1 * a.n2 * a.k2);
   dim3 g(static_cast<unsigned>(nf * a.n0));
   const dim3 b(64 * tiles);
-  const size_t lds = (size_t)tiles * kt1 * kt2 * 4096;
+  const size_t lds = prod_plane_lds(tiles, kt1 * kt2);
   const int j1 = a.k1 / 2;
   const bool ex = j1 == 16 || j1 == 20 || j1 == 24 || j1 == 32;
   const int jb = ex ? j1 : jb_of(j1);
   auto go = [&](auto kern) { prof::launch("k_prod_plane", bytes, flops, kern, g, b, lds, s, a); };
-  // instantiated for the bands of the configurations; other bands take the general form (jb = 32)
   auto pick = [&](auto mode) {
     constexpr int M = decltype(mode)::value;
-    if (kt1 == 1 && kt2 == 1) {
-      if (ex && jb == 16) go(k_prod_plane<M, 1, 1, 16, true>);
-      else go(k_prod_plane<M, 1, 1, 16, false>);
-    } else if (kt1 == 2 && kt2 == 1) {
-      if (ex && jb == 24) go(k_prod_plane<M, 2, 1, 24, true>);
-      else go(k_prod_plane<M, 2, 1, 32, false>);
-    } else if (kt1 == 1 && kt2 == 2) {
-      if (ex && jb == 16) go(k_prod_plane<M, 1, 2, 16, true>);
-      else go(k_prod_plane<M, 1, 2, 16, false>);
-    } else {
-      if (ex && jb == 24) go(k_prod_plane<M, 2, 2, 24, true>);
-      else go(k_prod_plane<M, 2, 2, 32, false>);
-    }
+    if (ex && jb == 16) go(k_prod_plane<M, 1, 1, 16, true>);
+    else go(k_prod_plane<M, 1, 1, 16, false>);
   };
   if (a.mode == kRedV1Products) pick(std::integral_constant<int, kRedV1Products>{});
   else if (a.mode == kRedV3Products) pick(std::integral_constant<int, kRedV3Products>{});
