@@ -6,8 +6,9 @@ The warm start and the low-rank preconditioner are the learned additions to
 the Gauss-Newton-Krylov solver (Section 2.3.1 gives the solver they feed: the
 PCG system of the reduced Hessian and its initial guess).  The network is an
 encoder of 3^3 convolutions (zero padding 1, ReLU; stride 2 on every level but
-the last) on the two-channel image pair, followed by a 1^3 head without
-activation.  Its output holds grid samples of the three velocity components on
+the last, or, for a requested output grid, stride 2 while the grid is larger than
+it and 1 afterwards) on the two-channel image pair, followed by a 1^3 head
+without activation.  Its output holds grid samples of the three velocity components on
 a coarse s^3 grid of the unit torus; their band-limited projection onto the K=s
 real basis (the exact s-point DFT without the unpaired Nyquist frequency) gives
 the low-frequency block of the velocity's band-limited coefficients.  The
@@ -97,10 +98,26 @@ def conv3d_backward(x, y, dy, layer: Layer):
     return dx, dw, db
 
 
-def make_layers(params: np.ndarray, channels: Sequence[int], out_channels: int) -> List[Layer]:
+def strides(channels: Sequence[int], in_size: int = 0, out_size: int = 0) -> List[int]:
+    """Stride of each 3^3 level: 2 on every level but the last; with out_size, 2 while the grid
+    (in_size on the first level) is larger than out_size, then 1."""
+    if not out_size:
+        return [2 if i < len(channels) - 1 else 1 for i in range(len(channels))]
+    out, n = [], in_size
+    for _ in channels:
+        st = 2 if n > out_size else 1
+        out.append(st)
+        n = _out_size(n, 3, st, 1)
+    if n != out_size:
+        raise ValueError("output grid not reachable by halving the input grid")
+    return out
+
+
+def make_layers(params: np.ndarray, channels: Sequence[int], out_channels: int, in_size: int = 0,
+                out_size: int = 0) -> List[Layer]:
     """Unpack a flat parameter vector (per layer: weights [Cout][Cin][k^3], then biases)."""
     layers, cin, o = [], 2, 0
-    specs = [(c, 3, 2 if i < len(channels) - 1 else 1, 1, True) for i, c in enumerate(channels)]
+    specs = [(c, 3, st, 1, True) for c, st in zip(channels, strides(channels, in_size, out_size))]
     specs.append((out_channels, 1, 1, 0, False))
     for cout, k, stride, pad, relu in specs:
         nw = cout * cin * k ** 3

@@ -153,3 +153,27 @@ def test_adam_first_step_closed_form():
     np.testing.assert_allclose(p1, p - lr * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=1e-15)
     np.testing.assert_allclose(m, 0.1 * g)
     np.testing.assert_allclose(v, 0.001 * g * g)
+
+
+def test_stride_schedule_for_an_output_grid():
+    """The default schedule (stride 2 but the last level) is the one a requested output grid of
+    in_size / 2^(levels - 1) gives; other output grids stop halving once reached, and one that halving
+    cannot reach is refused.  A network with the 32^3 schedule maps 64^3 inputs to 32^3 samples."""
+    ch = [16, 32, 64, 128]
+    assert convnet.strides(ch) == [2, 2, 2, 1]
+    assert convnet.strides(ch, 64, 8) == [2, 2, 2, 1]
+    assert convnet.strides(ch, 64, 16) == [2, 2, 1, 1]
+    assert convnet.strides(ch, 64, 32) == [2, 1, 1, 1]
+    assert convnet.strides(ch, 64, 64) == [1, 1, 1, 1]
+    with pytest.raises(ValueError):
+        convnet.strides(ch, 64, 24)
+    rng = np.random.default_rng(8)
+    channels, out_c = [3, 4, 2], 3
+    n, cin = 0, 2
+    for c in channels:
+        n += c * cin * 27 + c
+        cin = c
+    n += out_c * cin + out_c
+    layers = convnet.make_layers(rng.standard_normal(n), channels, out_c, in_size=8, out_size=4)
+    assert [L.stride for L in layers] == [2, 1, 1, 1]
+    assert convnet.forward(rng.standard_normal((1, 2, 8, 8, 8)), layers)[-1].shape == (1, 3, 4, 4, 4)
