@@ -282,13 +282,20 @@ lddmm_bl_status lddmm_bl_dot(lddmm_bl_ctx* ctx, const void* a, const void* b, in
  * gradients (zero_grad clears them); get copies parameters (which = 0) or their
  * gradients (which = 1) to host (nparam floats), set loads parameters from host.
  * save writes the architecture and the float master parameters to a file (an 8-byte
- * tag, int32 levels, channels, in_size, rank_r, int64 nparam, then the parameters);
- * load reads such a file into a network of the same architecture (E_ARG on a
- * mismatch or an unreadable file).  Errors of these calls are reported through
- * lddmm_bl_last_error(NULL). */
+ * tag, int32 levels, channels, in_size, rank_r, [out_size,] int64 nparam, then the
+ * parameters; out_size only in files of networks made by lddmm_nn_create_out, under
+ * their own tag); load reads such a file into a network of the same architecture
+ * (E_ARG on a mismatch or an unreadable file).  Errors of these calls are reported
+ * through lddmm_bl_last_error(NULL).
+ * lddmm_nn_create_out makes the same network with the output grid out_size^3 instead
+ * (the levels take stride 2 while the grid is larger than out_size, then stride 1;
+ * out_size = in_size / 2^j for some j < levels, else E_ARG; 0 selects the default
+ * schedule): out_size = 32 predicts every coefficient of a 32^3 band. */
 typedef struct lddmm_nn_ctx lddmm_nn_ctx;
 lddmm_bl_status lddmm_nn_create(int32_t levels, const int32_t* channels, int32_t in_size, int32_t rank_r,
                                 uint64_t seed, void* hip_stream, lddmm_nn_ctx** out);
+lddmm_bl_status lddmm_nn_create_out(int32_t levels, const int32_t* channels, int32_t in_size, int32_t out_size,
+                                    int32_t rank_r, uint64_t seed, void* hip_stream, lddmm_nn_ctx** out);
 lddmm_bl_status lddmm_nn_info(lddmm_nn_ctx* ctx, int32_t* out_size, int32_t* out_channels, int64_t* nparam);
 lddmm_bl_status lddmm_nn_forward(lddmm_nn_ctx* ctx, const void* in, int32_t B, void* out);
 lddmm_bl_status lddmm_nn_backward(lddmm_nn_ctx* ctx, const void* dout, int32_t B);

@@ -4,7 +4,9 @@
 // except the last (stride 1), channels[0..levels-1], on a 2-channel input of
 // in_size^3 voxels (the image pair); then a 1^3 head to out_channels without
 // activation.  The head's output, of (in_size / 2^(levels-1))^3 voxels per channel,
-// is read as band-limited velocity coefficients in the real-basis layout.
+// holds grid samples whose band-limited projection gives velocity coefficients in the
+// real-basis layout.  With a requested output grid, the levels take stride 2 while the
+// grid is larger than it and stride 1 afterwards.
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -23,12 +25,16 @@ namespace lddmm {
 
 class Net {
  public:
-  Net(int levels, const int* channels, int in_size, int rank_r, uint64_t seed, hipStream_t s) : st_(s) {
-    if (levels < 1 || levels > 6 || in_size < 4 || rank_r < 0 || rank_r > 16) throw ArgError("bad network shape");
+  // out_size 0: the default schedule (stride 2 on every level but the last)
+  Net(int levels, const int* channels, int in_size, int rank_r, uint64_t seed, hipStream_t s, int out_size = 0)
+      : st_(s) {
+    if (levels < 1 || levels > 6 || in_size < 4 || rank_r < 0 || rank_r > 16 || out_size < 0 || out_size > in_size)
+      throw ArgError("bad network shape");
     const int out_channels = 3 * (1 + rank_r);
     rank_ = rank_r;
     for (int l = 0; l < levels; ++l) channels_.push_back(channels[l]);
     in_size_ = in_size;
+    req_out_ = out_size;
     int cin = 2, size = in_size;
     for (int l = 0; l < levels; ++l) {
       ConvLayer L;
@@ -36,7 +42,7 @@ class Net {
       L.cout = channels[l];
       L.k = 3;
       L.pad = 1;
-      L.stride = (l < levels - 1) ? 2 : 1;
+      L.stride = out_size > 0 ? (size > out_size ? 2 : 1) : (l < levels - 1) ? 2 : 1;
       L.relu = 1;
       if (L.cout < 1 || L.cout > 1024) throw ArgError("bad channel count");
       layers_.push_back(L);
@@ -44,6 +50,7 @@ class Net {
       size = (size + 2 - 3) / L.stride + 1;
       cin = L.cout;
     }
+    if (out_size > 0 && size != out_size) throw ArgError("output grid not reachable by halving the input grid");
     ConvLayer H;
     H.cin = cin, H.cout = out_channels, H.k = 1, H.pad = 0, H.stride = 1, H.relu = 0;
     layers_.push_back(H);
@@ -96,7 +103,10 @@ class Net {
 
   // Parameter file: the 8-byte tag, levels, channels[levels], in_size, rank_r (int32 each), the
   // parameter count (int64) and the float master parameters in layer order (weights, then biases).
+  // A network with a requested output grid writes the second tag and out_size (int32) after rank_r;
+  // files with the first tag hold networks of the default schedule.
   static constexpr char kTag[8] = {'L', 'D', 'D', 'M', 'M', 'N', 'N', '1'};
+  static constexpr char kTag2[8] = {'L', 'D', 'D', 'M', 'M', 'N', 'N', '2'};
   void save(const char* path) {
     std::vector<float> h(nparam_);
     get(h.data(), 0);
@@ -106,8 +116,10 @@ class Net {
     for (int c : channels_) hdr.push_back(c);
     hdr.push_back(in_size_);
     hdr.push_back(rank_);
+    if (req_out_ > 0) hdr.push_back(req_out_);
     const int64_t n = nparam_;
-    bool ok = std::fwrite(kTag, 1, 8, f) == 8 && std::fwrite(hdr.data(), 4, hdr.size(), f) == hdr.size() &&
+    bool ok = std::fwrite(req_out_ > 0 ? kTag2 : kTag, 1, 8, f) == 8 &&
+              std::fwrite(hdr.data(), 4, hdr.size(), f) == hdr.size() &&
               std::fwrite(&n, 8, 1, f) == 1 && std::fwrite(h.data(), 4, h.size(), f) == h.size();
     ok = (std::fclose(f) == 0) && ok;
     if (!ok) throw ArgError(std::string("cannot write ") + path);
@@ -117,13 +129,17 @@ class Net {
     if (!f) throw ArgError(std::string("cannot open: ") + path);
     char tag[8];
     int32_t levels = 0;
-    bool ok = std::fread(tag, 1, 8, f) == 8 && std::memcmp(tag, kTag, 8) == 0 && std::fread(&levels, 4, 1, f) == 1 &&
-              levels == (int32_t)channels_.size();
-    std::vector<int32_t> hdr(ok ? levels + 2 : 0);
+    bool ok = std::fread(tag, 1, 8, f) == 8;
+    const bool v2 = ok && std::memcmp(tag, kTag2, 8) == 0;
+    ok = ok && (v2 || std::memcmp(tag, kTag, 8) == 0) && std::fread(&levels, 4, 1, f) == 1 &&
+         levels == (int32_t)channels_.size();
+    std::vector<int32_t> hdr(ok ? levels + (v2 ? 3 : 2) : 0);
     int64_t n = -1;
     ok = ok && std::fread(hdr.data(), 4, hdr.size(), f) == hdr.size() && std::fread(&n, 8, 1, f) == 1;
     for (int l = 0; ok && l < levels; ++l) ok = hdr[l] == channels_[l];
-    ok = ok && hdr[levels] == in_size_ && hdr[levels + 1] == rank_ && n == nparam_;
+    // the file's output grid (the default schedule's for the first tag) must be this network's
+    ok = ok && hdr[levels] == in_size_ && hdr[levels + 1] == rank_ && n == nparam_ &&
+         (v2 ? hdr[levels + 2] : (in_size_ >> (levels - 1))) == out_size_;
     std::vector<float> h(ok ? nparam_ : 0);
     ok = ok && std::fread(h.data(), 4, h.size(), f) == h.size();
     std::fclose(f);
@@ -305,7 +321,7 @@ class Net {
   std::vector<int> channels_;
   std::vector<ConvLayer> layers_;
   std::vector<int> sizes_;  // input size of each layer
-  int out_size_ = 0, capB_ = 0, lastB_ = 0, t_ = 0;
+  int out_size_ = 0, req_out_ = 0, capB_ = 0, lastB_ = 0, t_ = 0;
   int64_t nparam_ = 0;
   float* arena_ = nullptr;
   std::vector<float*> acts_;
@@ -362,13 +378,18 @@ extern "C" {
 
 lddmm_bl_status lddmm_nn_create(int32_t levels, const int32_t* channels, int32_t in_size, int32_t rank_r,
                                 uint64_t seed, void* hip_stream, lddmm_nn_ctx** out) {
+  return lddmm_nn_create_out(levels, channels, in_size, 0, rank_r, seed, hip_stream, out);
+}
+
+lddmm_bl_status lddmm_nn_create_out(int32_t levels, const int32_t* channels, int32_t in_size, int32_t out_size,
+                                    int32_t rank_r, uint64_t seed, void* hip_stream, lddmm_nn_ctx** out) {
   if (!channels || !out) return LDDMM_BL_E_ARG;
   *out = nullptr;
   auto* c = new (std::nothrow) lddmm_nn_ctx();
   if (!c) return LDDMM_BL_E_OOM;
   try {
     c->net = std::make_unique<lddmm::Net>(levels, channels, in_size, rank_r, seed,
-                                          static_cast<hipStream_t>(hip_stream));
+                                          static_cast<hipStream_t>(hip_stream), out_size);
   } catch (const lddmm::ArgError& e) {
     lddmm::set_global_error(e.what());
     delete c;

@@ -39,7 +39,7 @@ EXPORTS = [
     "lddmm_bl_jacobian", "lddmm_bl_project", "lddmm_bl_project_noalloc", "lddmm_bl_include", "lddmm_bl_get_field", "lddmm_bl_dot",
     "lddmm_bl_profile_enable", "lddmm_bl_profile_read", "lddmm_bl_gn_solve_batched",
     "lddmm_bl_tune_candidates", "lddmm_bl_tune_get", "lddmm_bl_tune_set", "lddmm_bl_tune_table",
-    "lddmm_nn_create", "lddmm_nn_info", "lddmm_nn_forward", "lddmm_nn_backward", "lddmm_nn_zero_grad",
+    "lddmm_nn_create", "lddmm_nn_create_out", "lddmm_nn_info", "lddmm_nn_forward", "lddmm_nn_backward", "lddmm_nn_zero_grad",
     "lddmm_nn_step", "lddmm_nn_get", "lddmm_nn_set", "lddmm_nn_save", "lddmm_nn_load", "lddmm_nn_destroy",
     "lddmm_nn_pool_pair",
     "lddmm_nn_velocity", "lddmm_nn_loss",
@@ -116,6 +116,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     ip = ctypes.POINTER(i32)
     sig.update({
         "lddmm_nn_create": [i32, ip, i32, i32, ctypes.c_uint64, vp, ctypes.POINTER(vp)],
+        "lddmm_nn_create_out": [i32, ip, i32, i32, i32, ctypes.c_uint64, vp, ctypes.POINTER(vp)],
         "lddmm_nn_info": [vp, ip, ip, ctypes.POINTER(i64)],
         "lddmm_nn_forward": [vp, vp, i32, vp],
         "lddmm_nn_backward": [vp, vp, i32],
@@ -447,27 +448,29 @@ def brick_tune_keys(n) -> list:
 class WarmStartNet:
     """The warm-start network (lddmm_nn_* in the C ABI) on one ROCm device.
 
-    levels 3^3 convolutions (stride 2 but the last, ReLU) with the given channels on a
+    levels 3^3 convolutions (stride 2 but the last, or with out_size > 0 stride 2 while the grid
+    is larger than out_size and 1 afterwards; ReLU) with the given channels on a
     [B][2][in_size]^3 float input, then a 1^3 head to 3 (1 + rank_r) channels: grid samples of
     the three velocity components (and of rank_r preconditioner directions) on a coarse
     out_size^3 grid.  All tensors are contiguous float32 on the device; the library works on
     its own stream, ordered after the caller's.
     """
 
-    def __init__(self, channels=(16, 32, 64, 128), in_size=64, seed=0, device=None, rank_r=0):
+    def __init__(self, channels=(16, 32, 64, 128), in_size=64, seed=0, device=None, rank_r=0, out_size=0):
         self.lib = load_library()
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.stream = torch.cuda.Stream(device=self.device)
         self.channels = tuple(int(c) for c in channels)
         self.in_size = int(in_size)
         self.rank_r = int(rank_r)
+        self.req_out = int(out_size)
         ch = (ctypes.c_int32 * len(channels))(*self.channels)
         h = ctypes.c_void_p()
         with torch.cuda.device(self.device):
-            st = self.lib.lddmm_nn_create(len(channels), ch, self.in_size, self.rank_r, seed,
-                                          ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+            st = self.lib.lddmm_nn_create_out(len(channels), ch, self.in_size, self.req_out, self.rank_r, seed,
+                                              ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
         if st != 0:
-            raise LddmmError(st, "lddmm_nn_create: " + self.lib.lddmm_bl_last_error(None).decode())
+            raise LddmmError(st, "lddmm_nn_create_out: " + self.lib.lddmm_bl_last_error(None).decode())
         self.h = h
         osz, oc, npar = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
         self._check(self.lib.lddmm_nn_info(self.h, ctypes.byref(osz), ctypes.byref(oc), ctypes.byref(npar)), "info")

@@ -3,7 +3,8 @@
 A small 3D convolutional encoder (WarmStartNet, bf16 matrix-core kernels in the HIP
 library) maps the image pair, box-averaged to in_size^3 voxels, to grid samples of the
 velocity on a coarse s^3 grid; their band-limited projection is the low-frequency block
-(|m| <= s/2 - 1 per axis) of the velocity coefficients.  It is trained on registrations
+(|m| <= s/2 - 1 per axis) of the velocity coefficients.  The committed network has four
+levels (16 -> 128 channels) of strides 2, 2, 1, 1 on 64^3 inputs: s = 16, |m| <= 7.  It is trained on registrations
 the method itself computes: image pair -> converged band-limited velocity of plain
 Gauss-Newton-Krylov.  At registration time its prediction v0 is
 
@@ -20,10 +21,12 @@ its gradient, Adam, and the registrations.  Python only draws the seeded phantom
 (paper_2006_06823_amd.synthetic) and schedules the calls.
 
 Command line (runs on one ROCm device):
-  python -m paper_2006_06823_amd.learned generate --seeds 10000:11000 --out data0.npz
-  python -m paper_2006_06823_amd.learned train --data data0.npz data1.npz --eval-seeds 20000:20200 \\
-         --weights net.npz --report report.json
-(--variant 1 or 3 selects the image-transport or the deformation-state formulation; default 3.)
+  python -m paper_2006_06823_amd.learned generate --seeds 10000:11000 --block 32 --out data0.npz
+  python -m paper_2006_06823_amd.learned train --data data0.npz data1.npz --out-size 16 \\
+         --eval-seeds 20000:20200 --weights net.npz --report report.json
+(--variant 1 or 3 selects the image-transport or the deformation-state formulation, default 3;
+--block the band of the stored targets, --out-size the network's output grid, to which the
+targets are cropped.)
 """
 from __future__ import annotations
 
@@ -46,7 +49,7 @@ NT = 10
 IN_SIZE = 64
 CHANNELS = (16, 32, 64, 128)
 MAX_DISP_VOX = 8.0
-BLOCK = 8  # coarse grid of the network output = K of the predicted block
+BLOCK = 8  # coarse grid of the default network output = K of the predicted block
 
 
 @dataclass
@@ -136,16 +139,18 @@ class Registrar:
 
 
 def target_block(v, block=BLOCK):
-    """The low block of a velocity [3][K..] as a K = block band (pad slots zero): [3][b][b][b]."""
-    t = v[:, :block, :block, :block].clone()
-    t[:, block - 1, :, :] = 0
-    t[:, :, block - 1, :] = 0
-    t[:, :, :, block - 1] = 0
+    """The low block of velocities [..][3][K..] as a K = block band (pad slots zero): [..][3][b][b][b]."""
+    t = v[..., :block, :block, :block].clone()
+    t[..., block - 1, :, :] = 0
+    t[..., :, block - 1, :] = 0
+    t[..., :, :, block - 1] = 0
     return t
 
 
-def generate(seeds: Sequence[int], opts: SolveOpts, stream: PairStream, log=print, variant=3) -> Dict[str, np.ndarray]:
-    """Plain Gauss-Newton-Krylov on each seeded pair; keeps the converged velocity's low block.
+def generate(seeds: Sequence[int], opts: SolveOpts, stream: PairStream, log=print, variant=3,
+             block=BLOCK) -> Dict[str, np.ndarray]:
+    """Plain Gauss-Newton-Krylov on each seeded pair; keeps the converged velocity's low block (block = the
+    band of the velocity: every coefficient).
 
     Returns arrays: seeds, blocks [n][3][b][b][b], energy_full / energy_block (squared V-norms
     of v* and of its block), and per-run statistics of the plain solver.
@@ -166,7 +171,7 @@ def generate(seeds: Sequence[int], opts: SolveOpts, stream: PairStream, log=prin
         gref, _ = reg.grad_ref()
         v = reg.zero_velocity()
         rep = reg.solve(v, opts, gref)
-        blk = target_block(v)
+        blk = target_block(v, block)
         zero = torch.zeros(net.out_shape(1), dtype=torch.float32, device=reg.device)
         efull, _ = net.loss(zero, v[None].contiguous(), reg.alpha, reg.s, want_grad=False)
         eblk, _ = net.loss(zero, blk[None].contiguous(), reg.alpha, reg.s, want_grad=False)
@@ -355,13 +360,15 @@ def summarize(rows, with_Z=True):
 
 
 def save_weights(net, path):
-    np.savez(path, params=net.get(0), channels=np.asarray(net.channels), in_size=net.in_size)
+    np.savez(path, params=net.get(0), channels=np.asarray(net.channels), in_size=net.in_size, out_size=net.req_out)
 
 
 def load_weights(path, device="cuda:0"):
     from .lddmm_bl import WarmStartNet
     z = np.load(path, allow_pickle=False)
-    net = WarmStartNet(channels=tuple(int(c) for c in z["channels"]), in_size=int(z["in_size"]), device=device)
+    out_size = int(z["out_size"]) if "out_size" in z.files else 0
+    net = WarmStartNet(channels=tuple(int(c) for c in z["channels"]), in_size=int(z["in_size"]), device=device,
+                       out_size=out_size)
     net.set(z["params"])
     return net
 
@@ -376,6 +383,7 @@ def _main(argv=None):
     g.add_argument("--max-gn", type=int, default=20)
     g.add_argument("--max-pcg", type=int, default=10)
     g.add_argument("--variant", type=int, default=3, choices=(1, 3))
+    g.add_argument("--block", type=int, default=BLOCK, help="band of the stored targets (32: the whole band)")
     t = sub.add_parser("train")
     t.add_argument("--data", nargs="+", required=True)
     t.add_argument("--eval-seeds", default="")
@@ -390,6 +398,8 @@ def _main(argv=None):
     t.add_argument("--max-pcg", type=int, default=10)
     t.add_argument("--no-Z", action="store_true")
     t.add_argument("--variant", type=int, default=3, choices=(1, 3))
+    t.add_argument("--out-size", type=int, default=0,
+                   help="output grid of the network (0: in_size / 2^(levels-1)); the targets are cropped to it")
     e = sub.add_parser("evaluate")
     e.add_argument("--weights", required=True)
     e.add_argument("--eval-seeds", required=True)
@@ -404,7 +414,7 @@ def _main(argv=None):
     opts = SolveOpts(a.max_gn, a.max_pcg)
     try:
         if a.cmd == "generate":
-            d = generate(parse_range(a.seeds), opts, stream, variant=a.variant)
+            d = generate(parse_range(a.seeds), opts, stream, variant=a.variant, block=a.block)
             np.savez(a.out, **d)
             print(json.dumps({"pairs": int(d["seeds"].size), "gn_iters_mean": float(d["gn_iters"].mean()),
                               "seconds_mean": float(d["seconds"].mean()),
@@ -427,7 +437,9 @@ def _main(argv=None):
         ok = np.concatenate([d["status"] for d in data]) >= 0
         seeds, blocks = seeds[ok], blocks[ok]
         reg = Registrar(variant=a.variant)
-        net = WarmStartNet(channels=CHANNELS, in_size=IN_SIZE, seed=1234, device=reg.device)
+        net = WarmStartNet(channels=CHANNELS, in_size=IN_SIZE, seed=1234, device=reg.device, out_size=a.out_size)
+        if blocks.shape[-1] < net.out_size:
+            raise SystemExit(f"targets of band {blocks.shape[-1]} are narrower than the network output {net.out_size}")
         t0 = time.time()
         pairs = []
         X = torch.empty((len(seeds), 2, IN_SIZE, IN_SIZE, IN_SIZE), dtype=torch.float32, device=reg.device)
@@ -435,7 +447,7 @@ def _main(argv=None):
             net.pool_pair(torch.from_numpy(I0).to(reg.device), torch.from_numpy(I1).to(reg.device), X[j])
             if j % 250 == 0:
                 print(f"inputs {j + 1}/{len(seeds)} {time.time() - t0:.0f}s", flush=True)
-        T = torch.from_numpy(blocks).to(reg.device)
+        T = target_block(torch.from_numpy(blocks).to(reg.device), net.out_size).contiguous()
         nval = max(1, int(a.val_frac * len(seeds)))
         Xtr, Ttr, Xva, Tva = X[nval:], T[nval:], X[:nval], T[:nval]
         t1 = time.time()
@@ -443,7 +455,7 @@ def _main(argv=None):
         t_train = time.time() - t1
         save_weights(net, a.weights)
         report = {"train_pairs": int(Xtr.shape[0]), "val_pairs": nval, "epochs": a.epochs, "batch": a.batch,
-                  "lr": a.lr, "train_seconds": t_train, "history": hist}
+                  "lr": a.lr, "out_size": net.out_size, "train_seconds": t_train, "history": hist}
         del X
         if a.eval_seeds:
             rows = compare(net, reg, parse_range(a.eval_seeds), stream, opts, with_Z=not a.no_Z)

@@ -34,32 +34,33 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def _net(channels, in_size, seed=0):
+def _net(channels, in_size, seed=0, out_size=0):
     from paper_2006_06823_amd.lddmm_bl import WarmStartNet
-    return WarmStartNet(channels=channels, in_size=in_size, seed=seed, device="cuda:0")
+    return WarmStartNet(channels=channels, in_size=in_size, seed=seed, device="cuda:0", out_size=out_size)
 
 
 # (channels, in_size, batch): output channels spanning one and several 32-row tiles, ragged voxel tails
-CASES = [((4, 8), 16, 2), ((16, 40, 24), 24, 3)]
+# (the last: an output grid of 8^3 from 16^3 inputs, levels of strides 2, 1, 1)
+CASES = [((4, 8), 16, 2, 0), ((16, 40, 24), 24, 3, 0), ((4, 8, 6), 16, 2, 8)]
 
 
-@pytest.mark.parametrize("channels,in_size,B", CASES)
-def test_forward_matches_reference(channels, in_size, B):
-    net = _net(channels, in_size, seed=1)
+@pytest.mark.parametrize("channels,in_size,B,out_size", CASES)
+def test_forward_matches_reference(channels, in_size, B, out_size):
+    net = _net(channels, in_size, seed=1, out_size=out_size)
     rng = np.random.default_rng(2)
     x = rng.standard_normal((B, 2, in_size, in_size, in_size)).astype(np.float32)
     params = net.get(0)
     out = net.forward(torch.from_numpy(x).cuda()).cpu().numpy()
-    layers = convnet.make_layers(params.astype(np.float64), channels, 3)
+    layers = convnet.make_layers(params.astype(np.float64), channels, 3, in_size=in_size, out_size=out_size)
     ref = convnet.forward(x, layers)[-1]
     assert out.shape == ref.shape == (B, 3) + (net.out_size,) * 3
     assert _rel(out, ref) <= fwd_tol(channels)
 
 
-def _active_biases(params, channels, x):
+def _active_biases(params, channels, x, in_size=0, out_size=0):
     """Conv biases that keep every pre-activation positive on input x (all ReLUs active)."""
     p = params.copy()
-    layers = convnet.make_layers(p, channels, 3)
+    layers = convnet.make_layers(p, channels, 3, in_size=in_size, out_size=out_size)
     h = np.asarray(x, dtype=np.float64)
     o, cin = 0, 2
     for i, c in enumerate(channels):
@@ -81,14 +82,14 @@ def _active_biases(params, channels, x):
 # error of a gradient grows like sqrt(p), about 0.07-0.09 for p ~ 1e-2 on these random
 # networks, so that case is held to 0.15 (an indexing mistake gives errors of order 1).
 @pytest.mark.parametrize("all_active", [True, False])
-@pytest.mark.parametrize("channels,in_size,B", CASES)
-def test_backward_matches_reference(channels, in_size, B, all_active):
-    net = _net(channels, in_size, seed=3)
+@pytest.mark.parametrize("channels,in_size,B,out_size", CASES)
+def test_backward_matches_reference(channels, in_size, B, out_size, all_active):
+    net = _net(channels, in_size, seed=3, out_size=out_size)
     rng = np.random.default_rng(4)
     x = rng.standard_normal((B, 2, in_size, in_size, in_size)).astype(np.float32)
     params = net.get(0).astype(np.float64)
     if all_active:
-        params = _active_biases(params, channels, x)
+        params = _active_biases(params, channels, x, in_size, out_size)
         net.set(params.astype(np.float32))
         params = net.get(0).astype(np.float64)
     tol = grad_tol(channels) if all_active else 0.15
@@ -98,7 +99,7 @@ def test_backward_matches_reference(channels, in_size, B, all_active):
     net.zero_grad()
     net.backward(torch.from_numpy(dout).cuda())
     g = net.get(1).astype(np.float64)
-    layers = convnet.make_layers(params, channels, 3)
+    layers = convnet.make_layers(params, channels, 3, in_size=in_size, out_size=out_size)
     acts = convnet.forward(x, layers)
     if all_active:
         assert all((a > 0).all() for a in acts[1:-1])
@@ -181,3 +182,31 @@ def test_adam_step_matches_reference_and_training_reduces_loss():
         net.step(3e-3)
     # the FP64 reference network trained the same way ends near 0.81 of its first loss
     assert losses[-1] < 0.9 * losses[0], losses[::10]
+
+
+def test_save_load_round_trip(tmp_path):
+    """lddmm_nn_save / lddmm_nn_load: a network of the default schedule and one with a requested
+    output grid each reload into a fresh network of the same architecture with identical parameters
+    and outputs; a file of the other architecture is refused."""
+    rng = np.random.default_rng(12)
+    x = torch.from_numpy(rng.standard_normal((1, 2, 16, 16, 16)).astype(np.float32)).cuda()
+    paths = {}
+    for out_size in (0, 8):
+        a = _net((4, 8, 6), 16, seed=13, out_size=out_size)
+        a.set((a.get(0) + 0.01 * rng.standard_normal(a.nparam)).astype(np.float32))
+        path = tmp_path / f"net{out_size}.bin"
+        a.save(path)
+        b = _net((4, 8, 6), 16, seed=14, out_size=out_size)
+        assert not np.array_equal(a.get(0), b.get(0))
+        b.load(path)
+        assert np.array_equal(a.get(0), b.get(0))
+        assert torch.equal(a.forward(x), b.forward(x))
+        paths[out_size] = path
+    assert _net((4, 8, 6), 16, out_size=0).out_size == 4 and _net((4, 8, 6), 16, out_size=8).out_size == 8
+    from paper_2006_06823_amd.lddmm_bl import LddmmError
+    with pytest.raises(LddmmError):
+        _net((4, 8, 6), 16, out_size=8).load(paths[0])
+    with pytest.raises(LddmmError):
+        _net((4, 8, 6), 16, out_size=0).load(paths[8])
+    with pytest.raises(LddmmError):
+        _net((4, 8, 6), 16, out_size=6)  # not reachable by halving 16
