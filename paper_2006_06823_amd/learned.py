@@ -59,32 +59,91 @@ class SolveOpts:
     grad_rtol: float = 1e-3
 
 
-def render_pair(seed: int, shape=SHAPE, max_disp_vox=MAX_DISP_VOX):
-    """Seeded phantom pair (I0 template, I1 warped target), float32 [N1][N2][N3]."""
-    return synthetic.phantom_pair_3d(shape, seed, max_disp_vox=max_disp_vox)
+# Pairs of the learned path: "smooth" (the analytic low-frequency displacements of synthetic.phantom_pair_3d;
+# the committed network's training and held-out pairs) or "prior" (the target is the template moved by a
+# band-limited velocity drawn from the regulariser's prior, through the deformation-state solve; at 8 voxels
+# these warps carry frequencies up to the band edge, plain Gauss-Newton leaves mse_rel ~0.54 on them, and
+# the network trained on them predicts nothing: its loss stays at the targets' energy).
+PAIRS = "smooth"
+
+
+class PriorWarper:
+    """I1 = m(1) of the deformation-state solve (Section 2.3.3) for the template and a velocity v* drawn from
+    the prior: iid N(0, 1) band coefficients with the envelope 1 / (1 + 0.1 |k|^2) (synthetic.random_bl_
+    coefficients), scaled so that its grid samples move at most max_disp_vox voxels over unit time."""
+
+    def __init__(self, shape=SHAPE, band=BAND, nt=NT, device="cuda:0"):
+        import torch
+        from . import lddmm_bl as L
+        self.torch = torch
+        self.shape, self.band = tuple(shape), tuple(band)
+        self.ctx = L.Context(L.Problem(n=self.shape, k=self.band, nt=nt, variant=3, precision=L.FP32),
+                             device=torch.device(device))
+
+    def velocity(self, seed, max_disp_vox=MAX_DISP_VOX):
+        t = self.torch
+        v = t.tensor(synthetic.random_bl_coefficients(3, self.band, seed + 104729), dtype=t.float32,
+                     device=self.ctx.device)
+        g = self.ctx.include(v, 3)
+        n = t.tensor(self.shape, dtype=t.float32, device=self.ctx.device).reshape(3, 1, 1, 1)
+        return (v * (max_disp_vox / float((g.abs() * n).max()))).contiguous()
+
+    def __call__(self, P, seed, max_disp_vox=MAX_DISP_VOX):
+        t = self.torch
+        I = t.from_numpy(np.ascontiguousarray(P)).to(self.ctx.device)
+        self.ctx.set_images(I, I)
+        _, m1 = self.ctx.state_solve(self.velocity(seed, max_disp_vox), want_m1=True)
+        return m1.cpu().numpy()
+
+
+_warpers = {}
+
+
+def _warper(shape):
+    if tuple(shape) not in _warpers:
+        _warpers[tuple(shape)] = PriorWarper(shape)
+    return _warpers[tuple(shape)]
+
+
+def render_pair(seed: int, shape=SHAPE, max_disp_vox=MAX_DISP_VOX, mode=None):
+    """Seeded phantom pair (I0 template, I1 warped target), float32 [N1][N2][N3]; the "prior" mode runs the
+    warp on the GPU in this process."""
+    mode = mode or PAIRS
+    if mode == "smooth":
+        return synthetic.phantom_pair_3d(shape, seed, max_disp_vox=max_disp_vox)
+    P, n0, n1 = synthetic.phantom_with_noise_3d(shape, seed)
+    return P + n0, _warper(shape)(P, seed, max_disp_vox) + n1
 
 
 def _render_job(args):
-    seed, shape, disp = args
-    I0, I1 = render_pair(seed, shape, disp)
-    return seed, I0, I1
+    seed, shape, disp, mode = args
+    if mode == "smooth":
+        I0, I1 = synthetic.phantom_pair_3d(shape, seed, max_disp_vox=disp)
+        return seed, I0, I1, None
+    P, n0, n1 = synthetic.phantom_with_noise_3d(shape, seed)
+    return seed, P, n0, n1
 
 
 class PairStream:
-    """Renders phantom pairs in worker processes, in seed order.
+    """Renders phantom pairs in worker processes, in seed order (the "prior" targets' warps then run on the
+    GPU in this process).
 
     Create it before the first GPU call of the process: the workers are forked.
     """
 
-    def __init__(self, workers: int = 0):
+    def __init__(self, workers: int = 0, mode=None):
         if workers <= 0:
             workers = max(1, min(16, (os.cpu_count() or 2) - 1))
+        self.mode = mode or PAIRS
         self.pool = mp.get_context("fork").Pool(workers)
 
     def pairs(self, seeds: Sequence[int], shape=SHAPE, max_disp_vox=MAX_DISP_VOX):
-        jobs = [(int(s), tuple(shape), float(max_disp_vox)) for s in seeds]
-        for seed, I0, I1 in self.pool.imap(_render_job, jobs, chunksize=1):
-            yield seed, I0, I1
+        jobs = [(int(s), tuple(shape), float(max_disp_vox), self.mode) for s in seeds]
+        for seed, a, b, c in self.pool.imap(_render_job, jobs, chunksize=1):
+            if self.mode == "smooth":
+                yield seed, a, b
+            else:
+                yield seed, a + b, _warper(shape)(a, seed, max_disp_vox) + c
 
     def close(self):
         self.pool.close()
@@ -383,6 +442,7 @@ def _main(argv=None):
     g.add_argument("--max-gn", type=int, default=20)
     g.add_argument("--max-pcg", type=int, default=10)
     g.add_argument("--variant", type=int, default=3, choices=(1, 3))
+    g.add_argument("--pairs", default=PAIRS, choices=("prior", "smooth"))
     g.add_argument("--block", type=int, default=BLOCK, help="band of the stored targets (32: the whole band)")
     t = sub.add_parser("train")
     t.add_argument("--data", nargs="+", required=True)
@@ -398,6 +458,7 @@ def _main(argv=None):
     t.add_argument("--max-pcg", type=int, default=10)
     t.add_argument("--no-Z", action="store_true")
     t.add_argument("--variant", type=int, default=3, choices=(1, 3))
+    t.add_argument("--pairs", default=PAIRS, choices=("prior", "smooth"))
     t.add_argument("--out-size", type=int, default=0,
                    help="output grid of the network (0: in_size / 2^(levels-1)); the targets are cropped to it")
     e = sub.add_parser("evaluate")
@@ -409,8 +470,9 @@ def _main(argv=None):
     e.add_argument("--max-pcg", type=int, default=10)
     e.add_argument("--no-Z", action="store_true")
     e.add_argument("--variant", type=int, default=3, choices=(1, 3))
+    e.add_argument("--pairs", default=PAIRS, choices=("prior", "smooth"))
     a = ap.parse_args(argv)
-    stream = PairStream(a.workers)  # fork the renderers before the GPU is touched
+    stream = PairStream(a.workers, a.pairs)  # fork the renderers before the GPU is touched
     opts = SolveOpts(a.max_gn, a.max_pcg)
     try:
         if a.cmd == "generate":

@@ -232,6 +232,17 @@ def phantom_pair_3d(shape, seed, max_disp_vox=8.0, noise=0.02, template_seed=Non
     return I0.astype(np.float32), I1.astype(np.float32)
 
 
+def phantom_with_noise_3d(shape, seed, noise=0.02):
+    """The brain-like phantom of phantom_pair_3d, unwarped, and two independent N(0, noise^2) fields: the
+    template of a pair whose target is produced elsewhere, and the noise of each image.  Float32 [N1][N2][N3]."""
+    rng = np.random.default_rng(seed)
+    ph = BrainPhantom3D(rng, shape)
+    P = ph(grid_coords(shape))
+    n0 = noise * rng.standard_normal(shape)
+    n1 = noise * rng.standard_normal(shape)
+    return P.astype(np.float32), n0.astype(np.float32), n1.astype(np.float32)
+
+
 def random_bl_coefficients(ncomp, K, seed, decay=0.1):
     """iid N(0,1) real-basis coefficients [ncomp][K1]..[Kd] with a smooth spectral envelope.
 

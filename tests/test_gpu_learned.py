@@ -210,3 +210,20 @@ def test_save_load_round_trip(tmp_path):
         _net((4, 8, 6), 16, out_size=0).load(paths[8])
     with pytest.raises(LddmmError):
         _net((4, 8, 6), 16, out_size=6)  # not reachable by halving 16
+
+
+def test_prior_warper_scale_and_zero_velocity():
+    """The learned path's targets: a prior-drawn velocity scaled so that its grid samples move at most
+    the requested voxels over unit time, and the deformation-state warp of a zero velocity returning
+    the template."""
+    from paper_2006_06823_amd import learned as LW
+    from paper_2006_06823_amd import synthetic as syn
+    N, K = (32, 32, 32), (8, 8, 8)
+    w = LW.PriorWarper(shape=N, band=K, nt=4)
+    v = w.velocity(3, max_disp_vox=2.0)
+    g = w.ctx.include(v, 3)
+    assert abs(float(g.abs().max()) * 32 - 2.0) <= 1e-5 * 2.0
+    P, _, _ = syn.phantom_with_noise_3d(N, 5)
+    assert _rel(w(P, 3, max_disp_vox=0.0), P) <= 1e-5
+    m1 = w(P, 3, max_disp_vox=2.0)
+    assert 1e-2 < _rel(m1, P) < 0.5
