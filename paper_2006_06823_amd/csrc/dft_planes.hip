@@ -213,7 +213,7 @@ struct RedIn {
 // order (deterministic) and stored.
 template <int MODE, int KT1, int KT2, int WAVES, int CH>
 __global__ __launch_bounds__(64 * WAVES) void k_reduce(PlaneReduceArgs a) {
-  extern __shared__ float red[];  // [WAVES][KT1 KT2][16][64]
+  extern __shared__ float red[];  // [WAVES / 2][KT1 KT2][16][64]
   const int lane = threadIdx.x & 63, i = lane & 31, kh = lane >> 5;
   const int wave = uniform(threadIdx.x >> 6);
   const int plane = blockIdx.x;
@@ -274,22 +274,32 @@ __global__ __launch_bounds__(64 * WAVES) void k_reduce(PlaneReduceArgs a) {
         for (int r = 0; r < 16; ++r) R[p][q] = mfma(NH == 2 ? W[0][p][r] + W[NH - 1][p][r] : W[0][p][r], pc[r], R[p][q]);
     }
   }
-  // sum of the waves' partials in wave order
+  // the waves' partials summed in a fixed order in NS = WAVES / 2 slots of LDS: waves w < NS store theirs
+  // in slot w, waves w >= NS add theirs to slot w - NS, then the slots are summed in order
   constexpr int TILES = KT1 * KT2;
+  constexpr int NS = (WAVES + 1) / 2;
+  for (int half = 0; half < 2; ++half) {
+    if (half == 0 ? wave < NS : wave >= NS) {
+      const int slot = half == 0 ? wave : wave - NS;
 #pragma unroll
-  for (int p = 0; p < KT1; ++p)
+      for (int p = 0; p < KT1; ++p)
 #pragma unroll
-    for (int q = 0; q < KT2; ++q)
+        for (int q = 0; q < KT2; ++q)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) red[((wave * TILES + p * KT2 + q) * 16 + r) * 64 + lane] = R[p][q][r];
-  __syncthreads();
+          for (int r = 0; r < 16; ++r) {
+            float& d = red[((slot * TILES + p * KT2 + q) * 16 + r) * 64 + lane];
+            d = half == 0 ? R[p][q][r] : d + R[p][q][r];
+          }
+    }
+    __syncthreads();
+  }
   float* __restrict__ part = a.part + (size_t)plane * (k1 * k2);
   for (int e = threadIdx.x; e < TILES * 16 * 64; e += 64 * WAVES) {
     const int l = e & 63, r = (e >> 6) & 15, tile = e >> 10;
     const int p = tile / KT2, q = tile - p * KT2;
     float sum = 0.f;
 #pragma unroll
-    for (int w = 0; w < WAVES; ++w) sum += red[(w * TILES * 16) * 64 + e];
+    for (int w = 0; w < NS; ++w) sum += red[(w * TILES * 16) * 64 + e];
     const int a1 = p * 32 + acc_row(r, l), a2 = q * 32 + (l & 31);
     if (a1 < k1 && a2 < k2) part[a1 * k2 + a2] = sum;
   }
@@ -618,16 +628,17 @@ static void reduce_mode(const PlaneReduceArgs& a, hipStream_t s, double bytes, d
   const int kt1 = a.k1 > 32 ? 2 : 1, kt2 = a.k2 > 32 ? 2 : 1;
   dim3 g(static_cast<unsigned>(a.nf * a.n0));
   const char* nm = MODE == kRedPlain ? "k_reduce" : "k_reduce_products";
-  // tasks of 64 rows (16-wave workgroups with 32-row tasks measured slower); fewer waves for the
-  // larger bands (LDS of the partial sums)
+  // tasks of 64 rows (16-wave workgroups with 32-row tasks measured slower); 8 waves (4 for two band tiles
+  // per axis: 8 slowed the product modes of the 40x48x40 band from 29 to 54 us), their partials in half as
+  // many slots of LDS (KT1 KT2 x 4 KB each)
   if (kt1 == 1 && kt2 == 1)
-    prof::launch(nm, bytes, flops, k_reduce<MODE, 1, 1, 8, 64>, g, dim3(512), 8 * 1024 * 4, s, a);
+    prof::launch(nm, bytes, flops, k_reduce<MODE, 1, 1, 8, 64>, g, dim3(512), 4 * 1024 * 4, s, a);
   else if (kt1 == 1)
-    prof::launch(nm, bytes, flops, k_reduce<MODE, 1, 2, 8, 64>, g, dim3(512), 8 * 2048 * 4, s, a);
+    prof::launch(nm, bytes, flops, k_reduce<MODE, 1, 2, 8, 64>, g, dim3(512), 4 * 2048 * 4, s, a);
   else if (kt2 == 1)
-    prof::launch(nm, bytes, flops, k_reduce<MODE, 2, 1, 8, 64>, g, dim3(512), 8 * 2048 * 4, s, a);
+    prof::launch(nm, bytes, flops, k_reduce<MODE, 2, 1, 8, 64>, g, dim3(512), 4 * 2048 * 4, s, a);
   else
-    prof::launch(nm, bytes, flops, k_reduce<MODE, 2, 2, 4, 64>, g, dim3(256), 4 * 4096 * 4, s, a);
+    prof::launch(nm, bytes, flops, k_reduce<MODE, 2, 2, 4, 64>, g, dim3(256), 2 * 4096 * 4, s, a);
   LDDMM_LAUNCH_CHECK();
 }
 
