@@ -155,14 +155,22 @@ class Solver final : public SolverBase {
 
   void hess_matvec(const void* dv, void* hdv) override {
     require_state();
-    to_internal(dvbl_.get(), static_cast<const T*>(dv), 3);
-    matvec_graph();
-    from_internal(static_cast<T*>(hdv), hbl_.get(), 3);
+    const T* x = static_cast<const T*>(dv);
+    T* y = static_cast<T*>(hdv);
+    if (dim_ == 3 && x != y && use_graphs()) {
+      // the caller's layout is the internal one: replay a graph captured on the caller's buffers
+      LDDMM_HIP(hipGraphLaunch(user_matvec_graph(x, y), st_));
+    } else {
+      to_internal(dvbl_.get(), x, 3);
+      matvec_graph();
+      from_internal(y, hbl_.get(), 3);
+    }
     sync();
   }
 
   ~Solver() override {
     if (mv_exec_) (void)hipGraphExecDestroy(mv_exec_);
+    for (auto& u : user_mv_) (void)hipGraphExecDestroy(u.exec);
   }
 
   int gn_solve(const lddmm_bl_gn_opts& o, void* v, const void* Z, int r, lddmm_bl_gn_report* rep) override;
@@ -362,6 +370,39 @@ class Solver final : public SolverBase {
       mv_exec_ = nullptr;
       throw HipError(std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
     }
+  }
+  // Graphs of H x -> y over callers' buffers (the four most recent pointer pairs; the oldest is dropped).
+  // A graph holds only the two addresses: replaying it for the same pair reads and writes whatever the
+  // caller keeps there at the time.
+  struct UserGraph {
+    const T* x;
+    T* y;
+    hipGraphExec_t exec;
+  };
+  std::vector<UserGraph> user_mv_;
+  hipGraphExec_t user_matvec_graph(const T* x, T* y) {
+    for (const auto& u : user_mv_)
+      if (u.x == x && u.y == y) return u.exec;
+    hipGraph_t g = nullptr;
+    LDDMM_HIP(hipStreamBeginCapture(st_, hipStreamCaptureModeThreadLocal));
+    try {
+      run_matvec(x, y);
+    } catch (...) {
+      (void)hipStreamEndCapture(st_, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    LDDMM_HIP(hipStreamEndCapture(st_, &g));
+    hipGraphExec_t exec = nullptr;
+    const hipError_t e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) throw HipError(std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    if (user_mv_.size() == 4) {
+      (void)hipGraphExecDestroy(user_mv_.front().exec);
+      user_mv_.erase(user_mv_.begin());
+    }
+    user_mv_.push_back({x, y, exec});
+    return exec;
   }
   // H dvbl_ -> hbl_ (replay of the captured graph, or eager launches)
   void matvec_graph() {

@@ -313,3 +313,37 @@ def test_fused_product_grid_pass_equals_separate_kernels(variant, monkeypatch):
         assert close(h, om.hess_matvec(dv)) <= 1e-5
     assert close(out[0][0], out[1][0]) <= 1e-6
     assert close(out[0][1], out[1][1]) <= 1e-6
+
+
+def test_hess_matvec_graphs_on_caller_buffers(monkeypatch):
+    """lddmm_bl_hess_matvec replays graphs captured on the caller's buffers (the four most recent pointer
+    pairs): against eager launches (LDDMM_BL_NO_GRAPH) bitwise, for six pairs (the first ones dropped and
+    captured again) and for new contents in a cached pair's input; one buffer as both dv and h is
+    refused."""
+    from paper_2006_06823_amd import synthetic as syn
+    N, K, Nt = (40, 36, 44), (12, 10, 14), 4
+    dvs = [syn.random_bl_coefficients(3, K, 30 + i) for i in range(7)]
+
+    def run():
+        ctx, om, v = make(1, 3, N, K, Nt, L.FP32, seed=3)
+        ctx.state_solve(dev(v, ctx))
+        ins = [dev(d, ctx) for d in dvs[:6]]
+        outs = [torch.empty_like(ins[0]) for _ in range(6)]
+        res = []
+        for _ in range(2):
+            for a, b in zip(ins, outs):
+                ctx.hess_matvec(a, out=b)
+                res.append(b.clone())
+        ins[0].copy_(dev(dvs[6], ctx))
+        res.append(ctx.hess_matvec(ins[0], out=outs[0]).clone())
+        x = dev(dvs[1], ctx)
+        with pytest.raises(L.LddmmError):
+            ctx.hess_matvec(x, out=x)
+        return res
+
+    graph = run()
+    monkeypatch.setenv("LDDMM_BL_NO_GRAPH", "1")
+    eager = run()
+    for a, b in zip(graph, eager):
+        assert torch.equal(a, b)
+    assert torch.equal(graph[0], graph[6]) and not torch.equal(graph[12], graph[0])
