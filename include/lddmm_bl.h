@@ -36,10 +36,13 @@
  *     accumulated in double on the device.
  *
  * Ownership and ordering: the caller owns every buffer it passes; device
- * buffers are borrowed for the duration of the call.  The context owns its
- * workspaces (trajectories, departure points, scratch).  Every call runs in
- * order on the stream given at creation; calls that return host scalars
- * synchronise that stream.  No exception or abort crosses the ABI.
+ * buffers are borrowed until the stream has run the call.  The context owns
+ * its workspaces (trajectories, departure points, scratch).  Every call runs
+ * in order on the stream given at creation and synchronises that stream
+ * before it returns, except lddmm_bl_hess_matvec and
+ * lddmm_bl_project_noalloc, which only enqueue their work: their results are
+ * ready, and their buffers free for other use, once the stream has reached
+ * them.  No exception or abort crosses the ABI.
  *
  * Errors: negative status = error (the result is not valid), positive =
  * warning with a valid result.  lddmm_bl_last_error(ctx) gives the text of the
@@ -183,7 +186,11 @@ lddmm_bl_status lddmm_bl_adjoint_solve(lddmm_bl_ctx* ctx, void* grad_bl, double*
 /* Gauss-Newton Hessian-vector product at the velocity of the last state solve:
  * incremental state (Table 1 row 5 or 7), final coupling, incremental adjoint
  * (row 6 or 8) and the time integral of the Hessian term.  dv_bl, hdv_bl:
- * device BL [d][K..] (may not alias).  E_STATE without a prior state solve. */
+ * device BL [d][K..] (may not alias).  E_STATE without a prior state solve.
+ * Enqueued on the context's stream without waiting for it (see the ordering
+ * rule above), so back-to-back calls keep the GPU busy; in 3D each call
+ * replays a HIP graph captured on the caller's own (dv_bl, hdv_bl) pair (the
+ * four most recent pairs are kept). */
 lddmm_bl_status lddmm_bl_hess_matvec(lddmm_bl_ctx* ctx, const void* dv_bl, void* hdv_bl);
 
 /* Gauss-Newton-Krylov registration (eqs. BLNewton, BLKKT) starting from

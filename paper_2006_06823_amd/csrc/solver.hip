@@ -165,10 +165,11 @@ class Solver final : public SolverBase {
       matvec_graph();
       from_internal(y, hbl_.get(), 3);
     }
-    sync();
+    // enqueued only: the result is ready when the stream reaches it (no host scalar to return)
   }
 
   ~Solver() override {
+    (void)hipStreamSynchronize(st_);  // replays still queued read the graphs and buffers freed below
     if (mv_exec_) (void)hipGraphExecDestroy(mv_exec_);
     for (auto& u : user_mv_) (void)hipGraphExecDestroy(u.exec);
   }
@@ -398,6 +399,7 @@ class Solver final : public SolverBase {
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) throw HipError(std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
     if (user_mv_.size() == 4) {
+      sync();  // the oldest graph may still be queued on the stream
       (void)hipGraphExecDestroy(user_mv_.front().exec);
       user_mv_.erase(user_mv_.begin());
     }

@@ -259,6 +259,12 @@ class Context:
         if cur != self.stream:
             self.stream.wait_stream(cur)
 
+    def _after(self):
+        """Make the caller's current stream wait for work the library only enqueued (no host wait)."""
+        cur = torch.cuda.current_stream(self.device)
+        if cur != self.stream:
+            cur.wait_stream(self.stream)
+
     def _check(self, st, allow_warn=False):
         if st < 0 or (st > 0 and not allow_warn):
             raise LddmmError(st, self.lib.lddmm_bl_last_error(self.h).decode())
@@ -315,11 +321,13 @@ class Context:
         return g, ginf.value
 
     def hess_matvec(self, dv: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """H dv into out, enqueued on the context's stream; the current stream waits for it (no host wait)."""
         self._arg(dv, self._vshape(), "dv")
         out = torch.empty(self._vshape(), dtype=self.dtype, device=self.device) if out is None else \
             self._arg(out, self._vshape(), "out")
         self._order()
         self._check(self.lib.lddmm_bl_hess_matvec(self.h, _ptr(dv), _ptr(out)))
+        self._after()
         return out
 
     def gn_solve(self, v: torch.Tensor, max_gn=10, max_pcg=5, grad_rtol=1e-3, grad_ref_inf=0.0,
@@ -362,6 +370,7 @@ class Context:
         self._arg(out, self._bl_shape(ncomp if ncomp > 1 else None), "out")
         self._order()
         self._check(self.lib.lddmm_bl_project_noalloc(self.h, _ptr(grid), _ptr(out), ncomp))
+        self._after()
         return out
 
     def include(self, bl: torch.Tensor, ncomp: int = 1) -> torch.Tensor:

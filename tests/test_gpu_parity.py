@@ -347,3 +347,34 @@ def test_hess_matvec_graphs_on_caller_buffers(monkeypatch):
     for a, b in zip(graph, eager):
         assert torch.equal(a, b)
     assert torch.equal(graph[0], graph[6]) and not torch.equal(graph[12], graph[0])
+
+
+def test_hess_matvec_enqueued_on_the_stream():
+    """lddmm_bl_hess_matvec only enqueues its work: eight calls on one (dv, h) pair whose input is
+    rewritten by the caller's own stream between them, with no host wait anywhere, give bitwise the
+    results of the same calls each followed by a device synchronisation."""
+    from paper_2006_06823_amd import synthetic as syn
+    N, K, Nt = (40, 36, 44), (12, 10, 14), 4
+    ctx, om, v = make(1, 3, N, K, Nt, L.FP32, seed=5)
+    ctx.state_solve(dev(v, ctx))
+    srcs = [dev(syn.random_bl_coefficients(3, K, 60 + i), ctx) for i in range(8)]
+    a = torch.empty_like(srcs[0])
+    b = torch.empty_like(srcs[0])
+    ref = []
+    for s_ in srcs:
+        a.copy_(s_)
+        ctx.hess_matvec(a, out=b)
+        torch.cuda.synchronize()
+        ref.append(b.clone())
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        got = []
+        for s_ in srcs:
+            a.copy_(s_)
+            ctx.hess_matvec(a, out=b)
+            got.append(b.clone())
+    torch.cuda.synchronize()
+    for x, y in zip(got, ref):
+        assert torch.equal(x, y)
+    assert not torch.equal(ref[0], ref[1])
