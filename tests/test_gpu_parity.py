@@ -76,6 +76,30 @@ def test_truncated_dft_parity(dim, N, K, Nt, precision):
         assert close(got.reshape(ref.shape), ref) <= tol(precision, "dft")
 
 
+@pytest.mark.parametrize("N,K", [((256, 256, 256), (64, 64, 64)), ((250, 252, 254), (62, 60, 64))])
+def test_truncated_dft_parity_largest_grid(N, K):
+    """The largest grid and band of the kernels' envelope (band 64 per axis, two 32-row tiles on every
+    axis, 8 x 8 column tiles per plane) and a ragged one just below it: projection and inclusion of one
+    field and of three against the FP64 oracle's FFT."""
+    ctx = L.Context(L.Problem(N, K, nt=1, precision=L.FP32))
+    rng = np.random.default_rng(9)
+    for nf in (1, 3):
+        print(f"[largest grid] N {N} K {K} fields {nf}", flush=True)
+        f = rng.standard_normal((nf,) + tuple(N)).astype(np.float32)
+        got = ctx.project(dev(f, ctx) if nf > 1 else dev(f[0], ctx), nf)
+        ref = sp.project(torch.tensor(f, dtype=torch.float64), K)
+        assert close(got.reshape(ref.shape), ref, f"project {N}") <= tol(L.FP32, "dft")
+        c = rng.standard_normal((nf,) + tuple(K))
+        for j, k in enumerate(K):
+            sl = [slice(None)] * 4
+            sl[j + 1] = k - 1
+            c[tuple(sl)] = 0.0
+        got = ctx.include(dev(c, ctx) if nf > 1 else dev(c[0], ctx), nf)
+        ref = sp.include(torch.tensor(c), N)
+        assert close(got.reshape(ref.shape), ref, f"include {N}") <= tol(L.FP32, "dft")
+    ctx.close()
+
+
 @pytest.mark.parametrize("variant", [1, 3])
 @pytest.mark.parametrize("dim,N,K,Nt,precision", CASES)
 def test_state_adjoint_gradient_parity(variant, dim, N, K, Nt, precision):
