@@ -631,7 +631,14 @@ static void reduce_mode(const PlaneReduceArgs& a, hipStream_t s, double bytes, d
   // tasks of 64 rows (16-wave workgroups with 32-row tasks measured slower); 8 waves (4 for two band tiles
   // per axis: 8 slowed the product modes of the 40x48x40 band from 29 to 54 us), their partials in half as
   // many slots of LDS (KT1 KT2 x 4 KB each)
-  if (kt1 == 1 && kt2 == 1)
+  // Small planes (the 48 x 48 product grid of a 32-wide band: two 64-row tasks for eight waves) take
+  // 16-row tasks instead, one per wave: each wave's chain of dependent load groups is then one group
+  // long instead of four.
+  const int t2 = ceil_div(a.n2, 32);
+  const bool small = 2 * t2 * ceil_div(a.n1, 64) <= 8 && t2 * ceil_div(a.n1, 16) <= 8;
+  if (kt1 == 1 && kt2 == 1 && small)
+    prof::launch(nm, bytes, flops, k_reduce<MODE, 1, 1, 8, 16>, g, dim3(512), 4 * 1024 * 4, s, a);
+  else if (kt1 == 1 && kt2 == 1)
     prof::launch(nm, bytes, flops, k_reduce<MODE, 1, 1, 8, 64>, g, dim3(512), 4 * 1024 * 4, s, a);
   else if (kt1 == 1)
     prof::launch(nm, bytes, flops, k_reduce<MODE, 1, 2, 8, 64>, g, dim3(512), 4 * 2048 * 4, s, a);
