@@ -76,6 +76,16 @@ __device__ __forceinline__ void brick_weights(float t, float w[4]) {
 typedef const __attribute__((address_space(3))) float lds_float;
 typedef const __attribute__((address_space(3))) unsigned long long lds_pair;  // two interleaved floats
 
+// p + off as a base the compiler cannot see through: the taps of one slab (row offsets b B2 + c <= 3 B2 + 3)
+// are then reached by the LDS reads' immediate offsets from this one register, instead of an address
+// add per pair of taps (the slab offset itself exceeds the 8-bit offsets of the paired reads)
+template <typename P>
+__device__ __forceinline__ P* opaque_base(P* p, int off) {
+  unsigned u = static_cast<unsigned>(reinterpret_cast<uintptr_t>(p + off));
+  asm volatile("" : "+v"(u));
+  return reinterpret_cast<P*>(static_cast<uintptr_t>(u));
+}
+
 // 64-tap evaluation from the LDS brick at the brick-relative first tap (s0, s1, s2).  The stencil is read
 // in four slabs of 4 x 4 taps (first index a), the next slab's reads issued before the current one is
 // summed; empty asm statements (no instruction) keep the compiler from moving a slab's sums below the
@@ -86,10 +96,11 @@ __device__ __forceinline__ float eval_brick(const float* br, int s0, int s1, int
   lds_float* p = (lds_float*)br + ((s0 * B1 + s1) * B2 + s2);
   float v[2][4][4];
   auto load = [&](int a, float (&d)[4][4]) {
+    lds_float* q = opaque_base(p, a * B1 * B2);
 #pragma unroll
     for (int b = 0; b < 4; ++b)
 #pragma unroll
-      for (int c = 0; c < 4; ++c) d[b][c] = p[(a * B1 + b) * B2 + c];
+      for (int c = 0; c < 4; ++c) d[b][c] = q[b * B2 + c];
   };
   load(0, v[0]);
   float acc = 0.f;
@@ -119,10 +130,11 @@ __device__ __forceinline__ float2 eval_brick2(const float2* br, int s0, int s1, 
     for (int c = 0; c < 4; ++c) w12[b][c] = w1[b] * w2[c];
   float2 v[2][4][4];
   auto load = [&](int a, float2 (&d)[4][4]) {
+    lds_pair* q = opaque_base(p, a * B1 * B2);
 #pragma unroll
     for (int b = 0; b < 4; ++b)
 #pragma unroll
-      for (int c = 0; c < 4; ++c) d[b][c] = __builtin_bit_cast(float2, p[(a * B1 + b) * B2 + c]);
+      for (int c = 0; c < 4; ++c) d[b][c] = __builtin_bit_cast(float2, q[b * B2 + c]);
   };
   load(0, v[0]);
   float ax = 0.f, ay = 0.f;
@@ -162,11 +174,13 @@ __device__ __forceinline__ void eval_brick_n(const float* br, int s0, int s1, in
   for (int a = 0; a < 4; ++a) {
     float d[GS][4][4];
 #pragma unroll
-    for (int k = 0; k < GS; ++k)
+    for (int k = 0; k < GS; ++k) {
+      lds_float* q = opaque_base(p, k * VOL + a * B1 * B2);
 #pragma unroll
       for (int b = 0; b < 4; ++b)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) d[k][b][c] = p[k * VOL + (a * B1 + b) * B2 + c];
+        for (int c = 0; c < 4; ++c) d[k][b][c] = q[b * B2 + c];
+    }
 #pragma unroll
     for (int k = 0; k < GS; ++k) {
       float sk = 0.f;
