@@ -219,6 +219,11 @@ def parse():
                          "HBM-traffic ratio of the dominant kernel and print their table")
     ap.add_argument("--learned-pairs", type=int, default=8,
                     help="held-out pairs registered plain and with the trained warm start (0: skip)")
+    ap.add_argument("--tune-save", default=None, metavar="FILE",
+                    help="write the autotuner's choices of this run ({key: choice} JSON) to FILE at the end")
+    ap.add_argument("--tune-load", default=None, metavar="FILE",
+                    help="fix the autotuner's choices from FILE before the run (so that a profiled run, whose "
+                         "timings the profiler perturbs, launches the kernels an unprofiled run chose)")
     return ap.parse_args()
 
 
@@ -238,6 +243,9 @@ def main():
     from paper_2006_06823_amd import lddmm_bl as L
     from paper_2006_06823_amd import synthetic as syn
 
+    if args.tune_load:
+        for key, choice in json.load(open(args.tune_load)).items():
+            L.tune_set(key, int(choice))
     if args.batched > 0:
         print(json.dumps(batched_leg(args)), flush=True)
         return
@@ -368,6 +376,9 @@ def main():
                   "objective": E, "kernels": kernels, "registrations": learned},
     }
     print(json.dumps(line), flush=True)
+    if args.tune_save:
+        with open(args.tune_save, "w") as fh:
+            json.dump(L.tune_table(), fh, indent=1, sort_keys=True)
 
 
 def _render_subject(i):
